@@ -1,0 +1,249 @@
+"""ctypes binding of the FP64 C oracle (liblrauv_oracle.so).
+
+TEST INFRASTRUCTURE ONLY. Parameters arrive as a plain dict of values (the
+same dict a test also hands to the GPU library); nothing here imports the
+product package.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liblrauv_oracle.so")
+_lib = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [
+        ("n_agents", C.c_int32), ("n_targets", C.c_int32), ("ragged", C.c_int32),
+        ("window", C.c_int32), ("episode_len", C.c_int32), ("n_actions", C.c_int32),
+        ("gn_iters", C.c_int32), ("pad_", C.c_int32),
+        ("dt", C.c_double), ("area", C.c_double), ("agent_speed", C.c_double),
+        ("spawn_agent_radius", C.c_double), ("action_dpsi", C.c_double * 8),
+        ("agent_heading_sigma", C.c_double), ("target_heading_sigma", C.c_double),
+        ("target_speed_lo", C.c_double), ("target_speed_hi", C.c_double),
+        ("range_sigma_lo", C.c_double), ("range_sigma_hi", C.c_double),
+        ("det_range", C.c_double), ("comm_range", C.c_double), ("comm_loss_p", C.c_double),
+        ("eps_min", C.c_double), ("eps_max", C.c_double), ("d_safe", C.c_double),
+        ("guard_tau", C.c_double), ("lost_range", C.c_double),
+    ]
+
+
+_TRAJ_FIELDS = [
+    ("init_agent", C.c_double), ("init_target", C.c_double), ("sigma_r", C.c_double),
+    ("init_obs", C.c_double), ("init_mask", C.c_uint8),
+    ("agent", C.c_double), ("target", C.c_double), ("ranges", C.c_double),
+    ("est", C.c_double), ("est_valid", C.c_uint8), ("est_fresh", C.c_uint8),
+    ("sens", C.c_double), ("err", C.c_double), ("reward", C.c_double),
+    ("crash", C.c_uint8), ("done", C.c_uint8), ("obs", C.c_double),
+    ("obs_mask", C.c_uint8), ("actions", C.c_int32), ("env_metrics", C.c_double),
+]
+
+
+class OrcTraj(C.Structure):
+    _fields_ = [(n, C.POINTER(t)) for n, t in _TRAJ_FIELDS]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from .build import build
+            build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER
+        L.orc_philox4x32_10.argtypes = [P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]
+        L.orc_philox_bulk.argtypes = [C.c_int64, P(C.c_uint32), C.c_uint64, P(C.c_uint32)]
+        L.orc_u01.argtypes = [C.c_uint32]
+        L.orc_u01.restype = C.c_double
+        L.orc_normal2.argtypes = [C.c_uint32, C.c_uint32, P(C.c_double), P(C.c_double)]
+        L.orc_choice.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_choice.restype = C.c_uint32
+        L.orc_env_counts.argtypes = [P(OrcParams), C.c_uint64, C.c_int64, P(C.c_int64),
+                                     P(C.c_int32), P(C.c_int32)]
+        L.orc_ls_estimate.argtypes = [C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                      C.c_int, C.c_double, P(C.c_double), P(C.c_double)]
+        L.orc_ls_estimate.restype = C.c_int
+        L.orc_ls_estimate_sens.argtypes = [C.c_int, P(C.c_double), P(C.c_double), P(C.c_double),
+                                           C.c_int, C.c_double, P(C.c_double), P(C.c_double),
+                                           P(C.c_double)]
+        L.orc_ls_estimate_sens.restype = C.c_int
+        L.orc_ls_batch.argtypes = [C.c_int64, C.c_int, P(C.c_double), C.c_int, C.c_double,
+                                   P(C.c_double), P(C.c_uint8), C.c_int]
+        L.orc_tracking_reward.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_tracking_reward.restype = C.c_double
+        L.orc_rollout.argtypes = [P(OrcParams), C.c_uint64, C.c_uint64, C.c_int64, P(C.c_int64),
+                                  P(C.c_int32), P(C.c_int32), C.c_int32, P(C.c_int32),
+                                  P(OrcTraj), C.c_int]
+        L.orc_rollout.restype = C.c_int
+        _register_learned(L)
+        _lib = L
+    return _lib
+
+
+def _register_learned(L):
+    """Declare the learned-part entry points when the library has them."""
+    P = C.POINTER
+    if hasattr(L, "orc_mlp_forward"):
+        L.orc_mlp_forward.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.orc_mlp_backward.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double),
+                                       P(C.c_double), P(C.c_double)]
+        L.orc_mlp_backward.restype = C.c_double
+        L.orc_adam_step.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double),
+                                    P(C.c_double), C.c_int64, C.c_double, C.c_double,
+                                    C.c_double, C.c_double]
+        L.orc_window_features.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_double),
+                                          P(C.c_double)]
+        L.orc_mlp_residual_rms.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_double),
+                                           P(C.c_double)]
+    if hasattr(L, "orc_policy_forward"):
+        L.orc_policy_forward.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_uint8),
+                                         P(C.c_double), P(C.c_double)]
+
+
+def _p(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_params(cfg: dict) -> OrcParams:
+    p = OrcParams()
+    for name, _ in OrcParams._fields_:
+        if name == "pad_":
+            continue
+        if name == "action_dpsi":
+            vals = list(cfg["action_dpsi"]) + [0.0] * (8 - len(cfg["action_dpsi"]))
+            p.action_dpsi = (C.c_double * 8)(*vals)
+            continue
+        setattr(p, name, cfg[name])
+    return p
+
+
+# ---------------------------------------------------------------- RNG pieces
+def philox(ctr: np.ndarray, seed: int) -> np.ndarray:
+    """Philox4x32-10 of counters [n,4] (uint32) with key = (seed lo, seed hi)."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.empty_like(ctr)
+    lib().orc_philox_bulk(ctr.shape[0], _p(ctr, C.c_uint32), C.c_uint64(seed), _p(out, C.c_uint32))
+    return out
+
+
+def philox_key(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def u01(x: int) -> float:
+    return lib().orc_u01(C.c_uint32(x))
+
+
+def normal2(x0: int, x1: int):
+    z0, z1 = C.c_double(), C.c_double()
+    lib().orc_normal2(x0, x1, C.byref(z0), C.byref(z1))
+    return z0.value, z1.value
+
+
+def choice(x: int, n: int) -> int:
+    return int(lib().orc_choice(x, n))
+
+
+def env_counts(cfg: dict, seed: int, env_ids) -> tuple:
+    ids = np.ascontiguousarray(env_ids, dtype=np.int64)
+    na = np.empty(ids.shape[0], np.int32)
+    nt = np.empty(ids.shape[0], np.int32)
+    p = make_params(cfg)
+    lib().orc_env_counts(C.byref(p), seed, ids.shape[0], _p(ids, C.c_int64), _p(na, C.c_int32),
+                         _p(nt, C.c_int32))
+    return na, nt
+
+
+# ---------------------------------------------------------------- estimator
+def ls_estimate(ax, ay, r, gn_iters=0, tau=1e-4, with_sens=False):
+    ax = np.ascontiguousarray(ax, np.float64)
+    ay = np.ascontiguousarray(ay, np.float64)
+    r = np.ascontiguousarray(r, np.float64)
+    px, py, s = C.c_double(), C.c_double(), C.c_double()
+    if with_sens:
+        ok = lib().orc_ls_estimate_sens(len(ax), _p(ax, C.c_double), _p(ay, C.c_double),
+                                        _p(r, C.c_double), gn_iters, tau, C.byref(px),
+                                        C.byref(py), C.byref(s))
+        return (bool(ok), px.value, py.value, s.value)
+    ok = lib().orc_ls_estimate(len(ax), _p(ax, C.c_double), _p(ay, C.c_double),
+                               _p(r, C.c_double), gn_iters, tau, C.byref(px), C.byref(py))
+    return (bool(ok), px.value, py.value)
+
+
+def ls_batch(win: np.ndarray, gn_iters=0, tau=1e-4, n_threads=1):
+    """win [N][W][3] = (ax, ay, r); r NaN marks a missing entry."""
+    win = np.ascontiguousarray(win, np.float64)
+    N, W, _ = win.shape
+    out = np.zeros((N, 2), np.float64)
+    valid = np.zeros(N, np.uint8)
+    lib().orc_ls_batch(N, W, _p(win, C.c_double), gn_iters, tau, _p(out, C.c_double),
+                       _p(valid, C.c_uint8), n_threads)
+    return out, valid
+
+
+def tracking_reward(e: float, eps_min=10.0, eps_max=50.0) -> float:
+    return lib().orc_tracking_reward(e, eps_min, eps_max)
+
+
+# ---------------------------------------------------------------- rollout
+ALL_RECORDS = ("init_agent", "init_target", "sigma_r", "init_obs", "init_mask", "agent",
+               "target", "ranges", "est", "est_valid", "est_fresh", "sens", "err", "reward",
+               "crash", "done", "obs", "obs_mask", "actions", "env_metrics")
+
+
+def rollout(cfg: dict, env_ids, n_agents, n_targets, seed: int, T: int, episode: int = 0,
+            actions=None, records=ALL_RECORDS, n_threads: int = 1) -> dict:
+    """Reset then T steps of the selected envs (global ids `env_ids`)."""
+    ids = np.ascontiguousarray(env_ids, np.int64)
+    na = np.ascontiguousarray(n_agents, np.int32)
+    nt = np.ascontiguousarray(n_targets, np.int32)
+    E = ids.shape[0]
+    A, Tt = int(na.sum()), int(nt.sum())
+    P = int((na.astype(np.int64) * nt).sum())
+    K = int((na.astype(np.int64) * (na + nt)).sum())
+    shapes = {
+        "init_agent": ((A, 3), np.float64), "init_target": ((Tt, 4), np.float64),
+        "sigma_r": ((E,), np.float64), "init_obs": ((K, 6), np.float64),
+        "init_mask": ((K,), np.uint8),
+        "agent": ((T, A, 3), np.float64), "target": ((T, Tt, 4), np.float64),
+        "ranges": ((T, P), np.float64), "est": ((T, P, 2), np.float64),
+        "est_valid": ((T, P), np.uint8), "est_fresh": ((T, P), np.uint8),
+        "sens": ((T, P), np.float64), "err": ((T, Tt), np.float64),
+        "reward": ((T, E), np.float64), "crash": ((T, E), np.uint8),
+        "done": ((T, E), np.uint8), "obs": ((T, K, 6), np.float64),
+        "obs_mask": ((T, K), np.uint8), "actions": ((T, A), np.int32),
+        "env_metrics": ((E, 6), np.float64),
+    }
+    if "init_obs" in records and "init_mask" not in records:
+        records = tuple(records) + ("init_mask",)
+    traj = OrcTraj()
+    out = {}
+    ctmap = dict(_TRAJ_FIELDS)
+    for name in records:
+        shp, dt = shapes[name]
+        arr = np.zeros(shp, dt)
+        out[name] = arr
+        setattr(traj, name, _p(arr, ctmap[name]))
+    act_p = None
+    if actions is not None:
+        actions = np.ascontiguousarray(actions, np.int32).reshape(T, A)
+        act_p = _p(actions, C.c_int32)
+    p = make_params(cfg)
+    rc = lib().orc_rollout(C.byref(p), C.c_uint64(seed), C.c_uint64(episode), E,
+                           _p(ids, C.c_int64), _p(na, C.c_int32), _p(nt, C.c_int32), T, act_p,
+                           C.byref(traj), n_threads)
+    if rc != 0:
+        raise ValueError(f"oracle rollout rejected its arguments (rc={rc})")
+    out["csr"] = {
+        "agent": np.concatenate([[0], np.cumsum(na)]),
+        "target": np.concatenate([[0], np.cumsum(nt)]),
+        "pair": np.concatenate([[0], np.cumsum(na.astype(np.int64) * nt)]),
+        "token": np.concatenate([[0], np.cumsum(na.astype(np.int64) * (na + nt))]),
+    }
+    return out

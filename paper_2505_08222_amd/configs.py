@@ -1,0 +1,65 @@
+"""The five workload configurations of the batched tracking environment.
+
+Each config is a plain dict of parameter values (SI units). The same dict is
+handed to the GPU library and, in the tests, to the FP64 oracle; it holds no
+arithmetic of the method.
+
+Paper constants used as defaults (arXiv 2505.08222):
+  * Eq. (1) thresholds eps_min = 10 m, eps_max = 50 m;
+  * agent heading noise 0.02 rad (Sec. III-A-3);
+  * detection range 450 m and communication range 1500 m (Sec. III-A-2). The
+    batched workloads place targets uniformly in a square of 2-4 km with the
+    agents near the centre, so the detection cut is lifted (det_range = inf)
+    to keep every tracker busy; 450 m is kept as the "lost target" distance.
+"""
+import copy
+import math
+
+ACTIONS_DPSI = [-0.3, -0.15, 0.0, 0.15, 0.3]
+
+BASE = dict(
+    n_agents=1, n_targets=1, ragged=0, window=10, episode_len=200, n_actions=5,
+    gn_iters=0, dt=1.0, area=2000.0, agent_speed=1.0, spawn_agent_radius=200.0,
+    action_dpsi=ACTIONS_DPSI, agent_heading_sigma=0.02, target_heading_sigma=0.1,
+    target_speed_lo=0.5, target_speed_hi=0.5, range_sigma_lo=1.0, range_sigma_hi=1.0,
+    det_range=math.inf, comm_range=1500.0, comm_loss_p=0.0, eps_min=10.0, eps_max=50.0,
+    d_safe=10.0, guard_tau=1e-4, lost_range=450.0,
+)
+
+
+def _cfg(**kw):
+    c = copy.deepcopy(BASE)
+    c.update(kw)
+    return c
+
+
+# c0: plain step, 16 envs, 1 agent x 1 target, 200 steps, 2 km area.
+PLAIN = dict(name="plain", num_envs=16, steps=200, seed=0,
+             env=_cfg(n_agents=1, n_targets=1, episode_len=200, area=2000.0))
+# c1: plain batched step, 4096 envs, 2x2, 500 steps, 4 km area, one graph.
+BATCHED = dict(name="batched", num_envs=4096, steps=500, seed=0,
+               env=_cfg(n_agents=2, n_targets=2, episode_len=500, area=4000.0))
+# c2: ragged batch, 65536 envs, counts uniform 1..5 each, 1000 steps.
+RAGGED = dict(name="ragged", num_envs=65536, steps=1000, seed=0,
+              env=_cfg(n_agents=5, n_targets=5, ragged=1, episode_len=1000, area=4000.0,
+                       target_speed_lo=0.2, target_speed_hi=1.5,
+                       range_sigma_lo=0.5, range_sigma_hi=3.0))
+# c3: learned estimator; windows of 16 from ragged-config rollouts.
+LEARNED = dict(name="learned", num_envs=65536, steps=1000, seed=0, window=16,
+               train_windows=10_000_000, infer_windows=1_000_000, hidden=128,
+               env=_cfg(n_agents=5, n_targets=5, ragged=1, window=16, episode_len=1000,
+                        area=4000.0, target_speed_lo=0.2, target_speed_hi=1.5,
+                        range_sigma_lo=0.5, range_sigma_hi=3.0))
+# c4: full rollout with the attention policy, 16384 envs, 5x5, 1000 steps.
+POLICY = dict(name="policy", num_envs=16384, steps=1000, seed=0, d_model=64, heads=4,
+              layers=2, ffn=256,
+              env=_cfg(n_agents=5, n_targets=5, window=16, episode_len=1000, area=4000.0))
+
+CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY)}
+
+
+def env_config(name: str, **overrides) -> dict:
+    """A copy of a workload's environment parameters with overrides applied."""
+    c = copy.deepcopy(CONFIGS[name]["env"])
+    c.update(overrides)
+    return c
