@@ -1,0 +1,238 @@
+/*
+ * mi_lrauv: MI355X (gfx950) library of the batched range-only tracking
+ * environment of "Scaling Multi-Agent Reinforcement Learning for Underwater
+ * Acoustic Tracking via Autonomous Vehicles" (arXiv 2505.08222).
+ *
+ * C ABI. Plain pointers and sizes only. Pointers named d_* are DEVICE
+ * pointers (HIP global memory on the current device); all others are host.
+ * Every call that takes a hipStream_t (passed as void*) only enqueues work on
+ * that stream, in stream order, and never synchronises, unless stated.
+ *
+ * Ownership: the caller allocates every device buffer (its size comes from
+ * env_query_layout) and keeps it alive while the handle uses it; the library
+ * owns only the host-side handle and any HIP graph it instantiates.
+ *
+ * Errors: every int-returning call returns 0 (MIL_OK) or a negative
+ * mil_status; env_last_error() then describes the last failure of the
+ * calling thread. Device-side anomalies (an action index out of range, a
+ * non-finite state) never trap: they set bits of a status word that
+ * env_status() reads back.
+ *
+ * Layouts: struct-of-arrays, FP32 unless stated. Environments are stored in
+ * PACKED order: sorted by (agents, targets) so that each wavefront holds
+ * environments of one shape (identity order when the counts are fixed).
+ * env_get_order() gives the global id of each packed environment and the
+ * CSR offsets of its agents, targets, (agent,target) pairs and
+ * observation tokens. Entities of one environment are contiguous:
+ *   agents  [A]   A = sum n_agents
+ *   targets [Tt]  Tt = sum n_targets
+ *   pairs   [P]   P = sum n_agents*n_targets, pair (i,j) at i*n_targets + j
+ *   tokens  [K]   K = sum n_agents*(n_agents+n_targets); agent i's tokens are
+ *                 [self, the other agents in index order, the targets in
+ *                 index order] (the TransfMAPPO entity tokens, Sec. III-B).
+ * A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef MI_LRAUV_H
+#define MI_LRAUV_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MIL_MAX_AGENTS 8
+#define MIL_MAX_TARGETS 8
+#define MIL_MAX_WINDOW 16
+#define MIL_MAX_ACTIONS 8
+
+typedef enum mil_status {
+  MIL_OK = 0,
+  MIL_EINVAL = -1, /* a parameter is out of its documented range */
+  MIL_ESHAPE = -2, /* a size does not match the handle or the layout */
+  MIL_EALIGN = -3, /* a device pointer is not 256-byte aligned (workspace) or
+                      not 8-byte aligned (outputs) */
+  MIL_EHIP = -4,   /* a HIP runtime call failed; see env_last_error() */
+  MIL_ESTATE = -5, /* call out of order (e.g. step before bind/reset, or past
+                      the end of the episode) */
+  MIL_ENOMEM = -6  /* host allocation failed */
+} mil_status;
+
+/* Device status bits reported by env_status(). */
+#define MIL_STATUS_BAD_ACTION 0x1u /* an action index was outside 0..n_actions-1;
+                                      that agent kept its heading */
+#define MIL_STATUS_NONFINITE 0x2u  /* a position or heading became non-finite */
+
+/* Environment parameters (SI units). Meaning of each field, with the passage
+ * of the paper it comes from:
+ *  n_agents, n_targets  fixed counts, or the maxima (1..8) when ragged = 1;
+ *                       ragged counts are drawn per env, uniform in 1..max.
+ *  window               W, number of most recent range measurements each
+ *                       (agent,target) tracker keeps (3..16).
+ *  episode_len          steps per episode; done is set on the last one and
+ *                       stepping past it is an error (termination only at the
+ *                       step limit, Sec. III-A-2 "Termination").
+ *  n_actions, action_dpsi  heading change per discrete action (rad); the
+ *                       paper's agents only steer at constant speed (Sec.
+ *                       III-A-2 "Actions Space").
+ *  gn_iters             Gauss-Newton refinements after the linearised
+ *                       least-squares solve (0 = plain LS, Sec. II-A).
+ *  dt, agent_speed      step duration and constant agent speed; agents move
+ *                       p += v dt (cos psi, sin psi) after turning (Sec.
+ *                       III-A-3).
+ *  agent_heading_sigma  std of the Gaussian heading noise added each step
+ *                       (0.02 rad in Sec. III-A-3).
+ *  target_heading_sigma std of the targets' random-walk heading jitter.
+ *  target_speed_lo/hi   per-target constant speed, uniform in [lo, hi].
+ *  range_sigma_lo/hi    per-env range-noise std, uniform in [lo, hi].
+ *  area, spawn_agent_radius  targets spawn uniformly in the square
+ *                       [-area/2, area/2]^2; agents uniformly in the disk of
+ *                       this radius about the centre.
+ *  det_range            true distances beyond this give no range (the
+ *                       paper's 450 m detection limit, Sec. III-A-2); INF
+ *                       disables it.
+ *  comm_range, comm_loss_p  an agent receives another agent's position only
+ *                       within comm_range and when that agent's broadcast is
+ *                       not dropped (probability comm_loss_p).
+ *  eps_min, eps_max     Eq. (1) thresholds (10 m and 50 m in the paper).
+ *  d_safe               crash distance: the reward is -1 when two agents are
+ *                       closer (text after Eq. (2)).
+ *  guard_tau            2x2 solves are refused when det <= tau * trace^2.
+ *  lost_range           a target counts as lost at the end of a rollout when
+ *                       every agent is farther than this. */
+typedef struct mil_env_params {
+  int32_t n_agents, n_targets, ragged, window;
+  int32_t episode_len, n_actions, gn_iters, reserved0;
+  float dt, area, agent_speed, spawn_agent_radius;
+  float action_dpsi[MIL_MAX_ACTIONS];
+  float agent_heading_sigma, target_heading_sigma;
+  float target_speed_lo, target_speed_hi;
+  float range_sigma_lo, range_sigma_hi;
+  float det_range, comm_range, comm_loss_p;
+  float eps_min, eps_max, d_safe, guard_tau, lost_range;
+} mil_env_params;
+
+/* Sizes of a created environment batch. */
+typedef struct mil_env_layout {
+  int64_t num_envs;        /* E */
+  int64_t num_agents;      /* A */
+  int64_t num_targets;     /* Tt */
+  int64_t num_pairs;       /* P */
+  int64_t num_tokens;      /* K */
+  int64_t num_entities;    /* A + Tt (rows of the global state) */
+  int64_t workspace_bytes; /* device workspace to pass to env_bind */
+  int32_t window;          /* W */
+  int32_t num_classes;     /* distinct (agents, targets) shapes */
+} mil_env_layout;
+
+/* Per-step outputs. Any pointer may be NULL (not written). For env_step each
+ * array holds one step; for env_rollout it holds T steps, step-major
+ * ([T][...]). Alignment: 8 bytes for float arrays.
+ *  obs       [K][6] token = (dx, dy, dz, is_self, is_agent, is_target): the
+ *            offset of the entity from the observing agent (other agents
+ *            from what they broadcast, targets from the agent's own tracker)
+ *            and a one-hot type (Sec. III-A-2 "Observation Space", TransfMAPPO
+ *            caption). A missing offset is written as zeros.
+ *  obs_mask  [K] uint8, 1 if the offset is present.
+ *  reward    [E] team reward: mean over targets of Eq. (1) on the best
+ *            tracker's error, or -1 on a crash.
+ *  done      [E] uint8.
+ *  est       [P][2] each tracker's current (possibly held) estimate.
+ *  est_valid [P] uint8, 1 once the tracker has an estimate.
+ *  gstate    [A+Tt][6] global state (x, y, z, speed, heading, is_target); per
+ *            env its agents then its targets; row offset of env e is
+ *            agent_off[e] + target_off[e].
+ *  actions   [A] int32, action applied (-1 when the input was invalid).
+ *  ranges    [P] measured range (NaN when not detected).
+ *  err       [Tt] tracking error e_j of the best tracker (+inf if none). */
+typedef struct mil_env_outputs {
+  float *obs;
+  uint8_t *obs_mask;
+  float *reward;
+  uint8_t *done;
+  float *est;
+  uint8_t *est_valid;
+  float *gstate;
+  int32_t *actions;
+  float *ranges;
+  float *err;
+} mil_env_outputs;
+
+typedef struct mil_env mil_env; /* opaque handle */
+
+/* Create a batch of num_envs environments (host only; no device memory is
+ * touched). seed keys every random draw (Philox4x32-10, key = seed): ragged
+ * counts, spawns, noise and random actions. counts (optional, host [2][E]:
+ * agents then targets) overrides the drawn ragged counts. */
+int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
+               const int32_t *counts, mil_env **out);
+int env_query_layout(const mil_env *h, mil_env_layout *out);
+/* Host arrays: env_ids [E] (global id of each packed env), agent_off,
+ * target_off, pair_off, token_off [E+1]. Any pointer may be NULL. */
+int env_get_order(const mil_env *h, int64_t *env_ids, int64_t *agent_off, int64_t *target_off,
+                  int64_t *pair_off, int64_t *token_off);
+/* Attach the caller's device workspace (>= workspace_bytes, 256-B aligned)
+ * and upload the packed tables. Synchronous on `stream`. */
+int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream);
+/* Start episode `episode` in every env: spawn agents and targets, draw the
+ * per-env range noise, clear trackers and metrics. outs may carry obs /
+ * obs_mask / gstate for the initial observation (other fields ignored). */
+int env_reset(mil_env *h, uint64_t episode, const mil_env_outputs *outs, void *stream);
+/* One step of every env. d_actions [A] int32 (packed agent order) or NULL
+ * for uniformly random actions drawn in the kernel. */
+int env_step(mil_env *h, const int32_t *d_actions, const mil_env_outputs *outs, void *stream);
+/* T steps in one persistent launch; state stays in registers between steps.
+ * d_actions [T][A] or NULL (random). Bit-identical to T calls of env_step. */
+int env_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
+                void *stream);
+/* Capture reset(episode) + rollout(T) + metrics reduction as one HIP graph on
+ * `stream` (capture mode: relaxed) and instantiate it; env_graph_launch
+ * replays it. Outputs and d_metrics are baked into the graph. */
+int env_graph_capture(mil_env *h, uint64_t episode, int32_t T, const mil_env_outputs *outs,
+                      double *d_metrics, void *stream);
+int env_graph_launch(mil_env *h, void *stream);
+/* Reduce the per-env accumulators since the last reset into d_metrics[8]:
+ * reward_sum, err_sum, err_sq_sum, err_count, crash_steps, lost_targets,
+ * env_steps, agent_steps (sums over all envs; lost is evaluated on the
+ * current positions). Deterministic order. */
+int env_metrics(mil_env *h, double *d_metrics, void *stream);
+/* Synchronise `stream`, read the device status word, clear it. */
+int env_status(mil_env *h, uint32_t *host_flags, void *stream);
+/* Copy the current state (packed order): d_agent [A][3] (x, y, heading),
+ * d_target [Tt][4] (x, y, heading, speed). Either may be NULL. */
+int env_get_state(mil_env *h, float *d_agent, float *d_target, void *stream);
+/* Choose the env-to-wavefront mapping: `lanes_per_agent` 1 or 2 (targets of
+ * an agent split over that many lanes) and `waves_per_block` 1, 2 or 4.
+ * Every mapping gives bit-identical results. */
+int env_set_mapping(mil_env *h, int32_t lanes_per_agent, int32_t waves_per_block);
+int env_get_mapping(const mil_env *h, int32_t *lanes_per_agent, int32_t *waves_per_block);
+/* Time every mapping on probe_steps steps writing `outs` (buffers sized for
+ * probe_steps steps; NULL = no outputs), with the state saved before and
+ * restored after each probe, and keep the fastest. If cache_path is not NULL
+ * the choice is looked up in, and appended to, that JSON-lines file, keyed by
+ * device, batch shape and code version. Needs a reset; synchronous. */
+int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
+                 const char *cache_path, void *stream);
+int env_destroy(mil_env *h);
+/* Description of the last error on this thread (never NULL). */
+const char *env_last_error(void);
+
+/* Range-only localisation of N independent windows (Sec. II-A, linearised
+ * least squares about the window centroid, then gn_iters Gauss-Newton steps
+ * on the range residuals). d_win [N][W][3] = (agent x, agent y, range); a NaN
+ * range marks a missing entry. Outputs d_out [N][2], d_valid [N] (0 when fewer
+ * than 3 entries or det <= tau*trace^2). accum: 0 accumulates in FP64, 1 in
+ * FP32 (faster, less accurate on ill-conditioned windows). W in 3..64. */
+int est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float tau, int32_t accum,
+              float *d_out, uint8_t *d_valid, void *stream);
+
+/* Philox4x32-10 (Salmon et al., SC'11) on n counters d_ctr [n][4] with key
+ * (seed lo, seed hi) -> d_out [n][4]; also the library's transforms of those
+ * words: d_u01 [n][4] uniforms ((x>>9)+1/2)/2^23 and d_normal [n][4]
+ * Box-Muller pairs of (w0,w1) and (w2,w3). Output pointers may be NULL. */
+int rng_philox(const uint32_t *d_ctr, int64_t n, uint64_t seed, uint32_t *d_out, float *d_u01,
+               float *d_normal, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,691 @@
+// Host runtime of the C ABI declared in include/mi_lrauv.h: batch packing,
+// workspace layout, kernel dispatch, HIP graph capture and the mapping
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "env_internal.h"
+#include "mi_lrauv.h"
+
+#ifndef MIL_CODE_VERSION
+#define MIL_CODE_VERSION "dev"
+#endif
+
+namespace {
+
+thread_local std::string g_last_error = "no error";
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_CHECK(call)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (call);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      return fail(MIL_EHIP, "%s failed: %s", #call, hipGetErrorString(_e));               \
+  } while (0)
+
+// Host copy of Philox4x32-10 (same definition as the device one, Salmon et
+// al. SC'11) for the per-env counts drawn at creation time.
+void philox_host(const uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = (uint32_t)p1;
+    c2 = n2;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+}  // namespace
+
+struct mil_env {
+  mil_env_params P{};
+  int64_t E = 0;
+  uint64_t seed = 0;
+  int W = 0, max_a = 0, max_t = 0, size_class = 0, wcap = 0;
+  std::vector<int64_t> env_ids;            // packed -> global id
+  std::vector<uint8_t> na, nt;             // packed
+  std::vector<int64_t> aoff, toff, poff, koff;
+  struct Cls {
+    int na, nt;
+    int64_t env0, nenv;
+  };
+  std::vector<Cls> cls;
+  int G = 1, wpb = 1;
+  std::vector<mil::ClassInfo> cinfo;
+  std::vector<uint8_t> wave_class;
+  int num_waves = 0, max_waves = 0;
+  // workspace
+  char *ws = nullptr;
+  int64_t ws_bytes = 0;
+  struct {
+    int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class;
+    int64_t ax, ay, apsi, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
+    int64_t state_begin, state_end, status, snap, total;
+  } off{};
+  mil::DevParams dp{};
+  mil::DevState ds{};
+  int64_t t = -1;  // steps since reset; -1 before the first reset
+  uint32_t episode = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int32_t graph_T = 0;
+};
+
+namespace {
+
+bool valid_params(const mil_env_params *p, std::string &why) {
+  auto bad = [&](const char *m) {
+    why = m;
+    return false;
+  };
+  if (p->n_agents < 1 || p->n_agents > MIL_MAX_AGENTS) return bad("n_agents must be in 1..8");
+  if (p->n_targets < 1 || p->n_targets > MIL_MAX_TARGETS) return bad("n_targets must be in 1..8");
+  if (p->ragged != 0 && p->ragged != 1) return bad("ragged must be 0 or 1");
+  if (p->window < 3 || p->window > MIL_MAX_WINDOW) return bad("window must be in 3..16");
+  if (p->episode_len < 1) return bad("episode_len must be >= 1");
+  if (p->n_actions < 1 || p->n_actions > MIL_MAX_ACTIONS) return bad("n_actions must be in 1..8");
+  if (p->gn_iters < 0 || p->gn_iters > 64) return bad("gn_iters must be in 0..64");
+  if (!(p->dt > 0.f) || !(p->agent_speed >= 0.f)) return bad("dt must be > 0, agent_speed >= 0");
+  if (!(p->area > 0.f) || !(p->spawn_agent_radius >= 0.f)) return bad("bad spawn geometry");
+  if (!(p->target_speed_lo <= p->target_speed_hi) || !(p->range_sigma_lo <= p->range_sigma_hi))
+    return bad("speed / range-sigma ranges need lo <= hi");
+  if (!(p->range_sigma_lo >= 0.f) || !(p->target_speed_lo >= 0.f)) return bad("negative lo bound");
+  if (!(p->eps_min < p->eps_max)) return bad("eps_min must be < eps_max");
+  if (!(p->comm_loss_p >= 0.f && p->comm_loss_p <= 1.f)) return bad("comm_loss_p in [0,1]");
+  if (!(p->guard_tau >= 0.f)) return bad("guard_tau must be >= 0");
+  return true;
+}
+
+void build_waves(mil_env *h) {
+  h->cinfo.clear();
+  h->wave_class.clear();
+  int wave = 0;
+  for (size_t c = 0; c < h->cls.size(); ++c) {
+    const auto &k = h->cls[c];
+    const int epw = 64 / (k.na * h->G);
+    const int64_t nw = (k.nenv + epw - 1) / epw;
+    mil::ClassInfo ci{};
+    ci.env0 = k.env0;
+    ci.nenv = k.nenv;
+    ci.aoff0 = h->aoff[k.env0];
+    ci.toff0 = h->toff[k.env0];
+    ci.poff0 = h->poff[k.env0];
+    ci.koff0 = h->koff[k.env0];
+    ci.na = k.na;
+    ci.nt = k.nt;
+    ci.wave0 = wave;
+    ci.nwaves = (int32_t)nw;
+    h->cinfo.push_back(ci);
+    for (int64_t w = 0; w < nw; ++w) h->wave_class.push_back((uint8_t)c);
+    wave += (int)nw;
+  }
+  h->num_waves = wave;
+}
+
+int upload_mapping(mil_env *h, hipStream_t st) {
+  build_waves(h);
+  if (h->num_waves > h->max_waves) return fail(MIL_EINVAL, "wave table overflow");
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.classes, h->cinfo.data(),
+                           h->cinfo.size() * sizeof(mil::ClassInfo), hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.wave_class, h->wave_class.data(), h->wave_class.size(),
+                           hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return MIL_OK;
+}
+
+void fill_dev_params(mil_env *h) {
+  auto &d = h->dp;
+  const auto &p = h->P;
+  d.window = p.window;
+  d.episode_len = p.episode_len;
+  d.n_actions = p.n_actions;
+  d.gn_iters = p.gn_iters;
+  d.dt = p.dt;
+  d.agent_speed = p.agent_speed;
+  d.area = p.area;
+  d.spawn_r = p.spawn_agent_radius;
+  for (int k = 0; k < 8; ++k) d.dpsi[k] = p.action_dpsi[k];
+  d.sig_a = p.agent_heading_sigma;
+  d.sig_t = p.target_heading_sigma;
+  d.tv_lo = p.target_speed_lo;
+  d.tv_hi = p.target_speed_hi;
+  d.sr_lo = p.range_sigma_lo;
+  d.sr_hi = p.range_sigma_hi;
+  d.det_range = p.det_range;
+  d.comm_range = p.comm_range;
+  d.comm_loss_p = p.comm_loss_p;
+  d.eps_min = p.eps_min;
+  d.eps_max = p.eps_max;
+  d.d_safe = p.d_safe;
+  d.tau = p.guard_tau;
+  d.lost_range = p.lost_range;
+  d.key0 = (uint32_t)h->seed;
+  d.key1 = (uint32_t)(h->seed >> 32);
+}
+
+mil::DevOut dev_out(const mil_env_outputs *o) {
+  mil::DevOut d{};
+  if (!o) return d;
+  d.obs = o->obs;
+  d.obs_mask = o->obs_mask;
+  d.reward = o->reward;
+  d.done = o->done;
+  d.est = o->est;
+  d.est_valid = o->est_valid;
+  d.gstate = o->gstate;
+  d.actions = o->actions;
+  d.ranges = o->ranges;
+  d.err = o->err;
+  return d;
+}
+
+int check_outputs(const mil_env_outputs *o) {
+  if (!o) return MIL_OK;
+  const void *fl[] = {o->obs, o->reward, o->est, o->gstate, o->actions, o->ranges, o->err};
+  for (const void *q : fl)
+    if (q && (((uintptr_t)q) & 7)) return fail(MIL_EALIGN, "output arrays must be 8-byte aligned");
+  return MIL_OK;
+}
+
+int run_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
+                hipStream_t st) {
+  const int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
+                                     h->ds, (int32_t)h->t, T, h->episode, d_actions,
+                                     dev_out(outs), st);
+  if (rc == -2) return fail(MIL_EINVAL, "no kernel for size class %d / window %d", h->size_class,
+                            h->wcap);
+  if (rc != 0) return fail(MIL_EHIP, "rollout launch failed: %s",
+                           hipGetErrorString(hipGetLastError()));
+  return MIL_OK;
+}
+
+std::string device_key(mil_env *h) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  hipDeviceProp_t prop{};
+  hipGetDeviceProperties(&prop, dev);
+  std::ostringstream k;
+  k << prop.gcnArchName << "/" << prop.multiProcessorCount << "|E" << h->E << "|W" << h->W
+    << "|gn" << h->P.gn_iters << "|S" << h->size_class;
+  for (auto &c : h->cls) k << "|" << c.na << "x" << c.nt << ":" << c.nenv;
+  k << "|" << MIL_CODE_VERSION;
+  return k.str();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *env_last_error(void) { return g_last_error.c_str(); }
+
+int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
+               const int32_t *counts, mil_env **out) {
+  if (!params || !out) return fail(MIL_EINVAL, "null argument");
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(params, why)) return fail(MIL_EINVAL, "%s", why.c_str());
+  if (num_envs < 1 || num_envs > (int64_t(1) << 31))
+    return fail(MIL_EINVAL, "num_envs must be in 1..2^31");
+  mil_env *h = new (std::nothrow) mil_env();
+  if (!h) return fail(MIL_ENOMEM, "out of host memory");
+  h->P = *params;
+  h->E = num_envs;
+  h->seed = seed;
+  h->W = params->window;
+  // per-env counts (global id order)
+  std::vector<uint8_t> ga(num_envs), gt(num_envs);
+  for (int64_t e = 0; e < num_envs; ++e) {
+    int a = params->n_agents, b = params->n_targets;
+    if (counts) {
+      a = counts[e];
+      b = counts[num_envs + e];
+      if (a < 1 || a > params->n_agents || b < 1 || b > params->n_targets) {
+        delete h;
+        return fail(MIL_EINVAL, "counts of env %lld outside 1..max", (long long)e);
+      }
+    } else if (params->ragged) {
+      const uint32_t ctr[4] = {0u, (uint32_t)e, 0u, 3u /* config purpose */};
+      uint32_t x[4];
+      philox_host(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), x);
+      a = 1 + (int)(((uint64_t)x[0] * (uint32_t)params->n_agents) >> 32);
+      b = 1 + (int)(((uint64_t)x[1] * (uint32_t)params->n_targets) >> 32);
+    }
+    ga[e] = (uint8_t)a;
+    gt[e] = (uint8_t)b;
+  }
+  // packing: classes by (targets desc, agents desc) -- heavier wavefronts are
+  // dispatched first; inside a class, global id order
+  std::vector<int64_t> order(num_envs);
+  for (int64_t e = 0; e < num_envs; ++e) order[e] = e;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    if (gt[x] != gt[y]) return gt[x] > gt[y];
+    return ga[x] > ga[y];
+  });
+  h->env_ids = order;
+  h->na.resize(num_envs);
+  h->nt.resize(num_envs);
+  h->aoff.assign(num_envs + 1, 0);
+  h->toff.assign(num_envs + 1, 0);
+  h->poff.assign(num_envs + 1, 0);
+  h->koff.assign(num_envs + 1, 0);
+  for (int64_t k = 0; k < num_envs; ++k) {
+    const int a = ga[order[k]], b = gt[order[k]];
+    h->na[k] = (uint8_t)a;
+    h->nt[k] = (uint8_t)b;
+    h->max_a = std::max(h->max_a, a);
+    h->max_t = std::max(h->max_t, b);
+    h->aoff[k + 1] = h->aoff[k] + a;
+    h->toff[k + 1] = h->toff[k] + b;
+    h->poff[k + 1] = h->poff[k] + (int64_t)a * b;
+    h->koff[k + 1] = h->koff[k] + (int64_t)a * (a + b);
+    if (h->cls.empty() || h->cls.back().na != a || h->cls.back().nt != b)
+      h->cls.push_back({a, b, k, 0});
+    h->cls.back().nenv += 1;
+  }
+  const int m = std::max(h->max_a, h->max_t);
+  h->size_class = m <= 2 ? 2 : (m <= 5 ? 5 : 8);
+  h->wcap = (h->W <= 10 && h->size_class < 8) ? 10 : 16;
+  // wave-table capacity: the largest count over the supported mappings
+  for (int G = 1; G <= 2; ++G) {
+    int64_t nw = 0;
+    for (auto &c : h->cls) {
+      const int epw = 64 / (c.na * G);
+      nw += (c.nenv + epw - 1) / epw;
+    }
+    h->max_waves = (int)std::max<int64_t>(h->max_waves, nw);
+  }
+  h->G = 1;
+  h->wpb = 1;
+  build_waves(h);
+  // workspace layout
+  const int64_t E = num_envs, A = h->aoff[E], Tt = h->toff[E], P = h->poff[E];
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  auto &f = h->off;
+  f.env_id = take(E * 4);
+  f.cnt_a = take(E);
+  f.cnt_t = take(E);
+  f.aoff = take((E + 1) * 8);
+  f.toff = take((E + 1) * 8);
+  f.poff = take((E + 1) * 8);
+  f.koff = take((E + 1) * 8);
+  f.classes = take((int64_t)h->cls.size() * sizeof(mil::ClassInfo));
+  f.wave_class = take(h->max_waves);
+  f.status = take(256);
+  f.state_begin = o;
+  f.ax = take(A * 4);
+  f.ay = take(A * 4);
+  f.apsi = take(A * 4);
+  f.tx = take(Tt * 4);
+  f.ty = take(Tt * 4);
+  f.tpsi = take(Tt * 4);
+  f.tv = take(Tt * 4);
+  f.sigma = take(E * 4);
+  f.hx = take((int64_t)h->W * A * 4);
+  f.hy = take((int64_t)h->W * A * 4);
+  f.hr = take((int64_t)h->W * P * 4);
+  f.ex = take(P * 4);
+  f.ey = take(P * 4);
+  f.ev = take(P);
+  f.macc = take(E * 3 * 8);
+  f.miacc = take(E * 2 * 4);
+  f.state_end = o;
+  f.snap = take(f.state_end - f.state_begin);
+  f.total = o;
+  fill_dev_params(h);
+  *out = h;
+  return MIL_OK;
+}
+
+int env_query_layout(const mil_env *h, mil_env_layout *out) {
+  if (!h || !out) return fail(MIL_EINVAL, "null argument");
+  out->num_envs = h->E;
+  out->num_agents = h->aoff[h->E];
+  out->num_targets = h->toff[h->E];
+  out->num_pairs = h->poff[h->E];
+  out->num_tokens = h->koff[h->E];
+  out->num_entities = out->num_agents + out->num_targets;
+  out->workspace_bytes = h->off.total;
+  out->window = h->W;
+  out->num_classes = (int32_t)h->cls.size();
+  return MIL_OK;
+}
+
+int env_get_order(const mil_env *h, int64_t *env_ids, int64_t *agent_off, int64_t *target_off,
+                  int64_t *pair_off, int64_t *token_off) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  const size_t n1 = (size_t)h->E + 1;
+  if (env_ids) std::copy(h->env_ids.begin(), h->env_ids.end(), env_ids);
+  if (agent_off) std::copy(h->aoff.begin(), h->aoff.begin() + n1, agent_off);
+  if (target_off) std::copy(h->toff.begin(), h->toff.begin() + n1, target_off);
+  if (pair_off) std::copy(h->poff.begin(), h->poff.begin() + n1, pair_off);
+  if (token_off) std::copy(h->koff.begin(), h->koff.begin() + n1, token_off);
+  return MIL_OK;
+}
+
+int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
+  if (!h || !d_workspace) return fail(MIL_EINVAL, "null argument");
+  if (((uintptr_t)d_workspace) & 255) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (bytes < h->off.total)
+    return fail(MIL_ESHAPE, "workspace has %lld bytes, %lld needed", (long long)bytes,
+                (long long)h->off.total);
+  hipStream_t st = (hipStream_t)stream;
+  h->ws = (char *)d_workspace;
+  h->ws_bytes = bytes;
+  const int64_t E = h->E;
+  std::vector<uint32_t> ids(E);
+  for (int64_t k = 0; k < E; ++k) ids[k] = (uint32_t)h->env_ids[k];
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.env_id, ids.data(), E * 4, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.cnt_a, h->na.data(), E, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.cnt_t, h->nt.data(), E, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.aoff, h->aoff.data(), (E + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.toff, h->toff.data(), (E + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.poff, h->poff.data(), (E + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.koff, h->koff.data(), (E + 1) * 8, hipMemcpyHostToDevice, st));
+  HIP_CHECK(hipMemsetAsync(h->ws + h->off.status, 0, 256, st));
+  auto &d = h->ds;
+  auto F = [&](int64_t off) { return (float *)(h->ws + off); };
+  d.env_id = (const uint32_t *)(h->ws + h->off.env_id);
+  d.cnt_a = (const uint8_t *)(h->ws + h->off.cnt_a);
+  d.cnt_t = (const uint8_t *)(h->ws + h->off.cnt_t);
+  d.aoff = (const int64_t *)(h->ws + h->off.aoff);
+  d.toff = (const int64_t *)(h->ws + h->off.toff);
+  d.poff = (const int64_t *)(h->ws + h->off.poff);
+  d.koff = (const int64_t *)(h->ws + h->off.koff);
+  d.classes = (const mil::ClassInfo *)(h->ws + h->off.classes);
+  d.wave_class = (const uint8_t *)(h->ws + h->off.wave_class);
+  d.ax = F(h->off.ax);
+  d.ay = F(h->off.ay);
+  d.apsi = F(h->off.apsi);
+  d.tx = F(h->off.tx);
+  d.ty = F(h->off.ty);
+  d.tpsi = F(h->off.tpsi);
+  d.tv = F(h->off.tv);
+  d.sigma = F(h->off.sigma);
+  d.hx = F(h->off.hx);
+  d.hy = F(h->off.hy);
+  d.hr = F(h->off.hr);
+  d.ex = F(h->off.ex);
+  d.ey = F(h->off.ey);
+  d.ev = (uint8_t *)(h->ws + h->off.ev);
+  d.macc = (double *)(h->ws + h->off.macc);
+  d.miacc = (int32_t *)(h->ws + h->off.miacc);
+  d.status = (uint32_t *)(h->ws + h->off.status);
+  d.E = E;
+  d.A = h->aoff[E];
+  d.Tt = h->toff[E];
+  d.P = h->poff[E];
+  d.K = h->koff[E];
+  const int rc = upload_mapping(h, st);
+  if (rc) return rc;
+  h->t = -1;
+  return MIL_OK;
+}
+
+int env_reset(mil_env *h, uint64_t episode, const mil_env_outputs *outs, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
+  if (episode >= (1ull << 28)) return fail(MIL_EINVAL, "episode must be < 2^28");
+  int rc = check_outputs(outs);
+  if (rc) return rc;
+  h->episode = (uint32_t)episode;
+  if (mil::launch_reset(h->dp, h->ds, h->episode, dev_out(outs), stream))
+    return fail(MIL_EHIP, "reset launch failed: %s", hipGetErrorString(hipGetLastError()));
+  h->t = 0;
+  return MIL_OK;
+}
+
+int env_step(mil_env *h, const int32_t *d_actions, const mil_env_outputs *outs, void *stream) {
+  return env_rollout(h, 1, d_actions, outs, stream);
+}
+
+int env_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
+                void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
+  if (T < 0) return fail(MIL_EINVAL, "T must be >= 0");
+  if (h->t + T > h->P.episode_len)
+    return fail(MIL_ESTATE, "%d steps from step %lld pass the episode length %d", T,
+                (long long)h->t, h->P.episode_len);
+  int rc = check_outputs(outs);
+  if (rc) return rc;
+  if (T == 0) return MIL_OK;
+  rc = run_rollout(h, T, d_actions, outs, (hipStream_t)stream);
+  if (rc) return rc;
+  h->t += T;
+  return MIL_OK;
+}
+
+int env_metrics(mil_env *h, double *d_metrics, void *stream) {
+  if (!h || !d_metrics) return fail(MIL_EINVAL, "null argument");
+  if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
+  if (mil::launch_metrics(h->dp, h->ds, (int32_t)h->t, d_metrics, stream))
+    return fail(MIL_EHIP, "metrics launch failed");
+  return MIL_OK;
+}
+
+int env_graph_capture(mil_env *h, uint64_t episode, int32_t T, const mil_env_outputs *outs,
+                      double *d_metrics, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
+  if (T < 1 || T > h->P.episode_len) return fail(MIL_EINVAL, "T must be in 1..episode_len");
+  if (episode >= (1ull << 28)) return fail(MIL_EINVAL, "episode must be < 2^28");
+  int rc = check_outputs(outs);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  if (h->gexec) {
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  if (h->graph) {
+    hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  int lrc = mil::launch_reset(h->dp, h->ds, (uint32_t)episode, dev_out(outs), st);
+  if (!lrc)
+    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds, 0,
+                              T, (uint32_t)episode, nullptr, dev_out(outs), st);
+  if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
+  hipGraph_t g = nullptr;
+  hipError_t ec = hipStreamEndCapture(st, &g);
+  if (lrc || ec != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(MIL_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+  }
+  h->graph = g;
+  HIP_CHECK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  h->graph_T = T;
+  h->episode = (uint32_t)episode;
+  h->t = -1;  // nothing has run yet
+  return MIL_OK;
+}
+
+int env_graph_launch(mil_env *h, void *stream) {
+  if (!h || !h->gexec) return fail(MIL_ESTATE, "no captured graph");
+  HIP_CHECK(hipGraphLaunch(h->gexec, (hipStream_t)stream));
+  h->t = h->graph_T;
+  return MIL_OK;
+}
+
+int env_status(mil_env *h, uint32_t *host_flags, void *stream) {
+  if (!h || !host_flags) return fail(MIL_EINVAL, "null argument");
+  if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_CHECK(hipStreamSynchronize(st));
+  HIP_CHECK(hipMemcpy(host_flags, h->ws + h->off.status, 4, hipMemcpyDeviceToHost));
+  HIP_CHECK(hipMemset(h->ws + h->off.status, 0, 4));
+  return MIL_OK;
+}
+
+int env_get_state(mil_env *h, float *d_agent, float *d_target, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
+  if (mil::launch_get_state(h->ds, d_agent, d_target, stream))
+    return fail(MIL_EHIP, "state copy launch failed");
+  return MIL_OK;
+}
+
+int env_set_mapping(mil_env *h, int32_t lanes_per_agent, int32_t waves_per_block) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (lanes_per_agent != 1 && lanes_per_agent != 2)
+    return fail(MIL_EINVAL, "lanes_per_agent must be 1 or 2");
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+    return fail(MIL_EINVAL, "waves_per_block must be 1, 2 or 4");
+  h->G = lanes_per_agent;
+  h->wpb = waves_per_block;
+  if (h->gexec) {  // a captured graph holds the old launch shape
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  if (h->ws) return upload_mapping(h, nullptr);
+  build_waves(h);
+  return MIL_OK;
+}
+
+int env_get_mapping(const mil_env *h, int32_t *lanes_per_agent, int32_t *waves_per_block) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (lanes_per_agent) *lanes_per_agent = h->G;
+  if (waves_per_block) *waves_per_block = h->wpb;
+  return MIL_OK;
+}
+
+int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
+                 const char *cache_path, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
+  if (probe_steps < 1 || h->t + probe_steps > h->P.episode_len)
+    return fail(MIL_EINVAL, "probe_steps must fit in the rest of the episode");
+  hipStream_t st = (hipStream_t)stream;
+  const std::string key = device_key(h);
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const auto kp = line.find("\"key\": \"" + key + "\"");
+      if (kp == std::string::npos) continue;
+      int G = 0, w = 0;
+      const auto gp = line.find("\"lanes_per_agent\": ");
+      const auto wp = line.find("\"waves_per_block\": ");
+      if (gp != std::string::npos) G = std::atoi(line.c_str() + gp + 19);
+      if (wp != std::string::npos) w = std::atoi(line.c_str() + wp + 19);
+      if (env_set_mapping(h, G, w) == MIL_OK) return MIL_OK;
+    }
+  }
+  const int64_t sbytes = h->off.state_end - h->off.state_begin;
+  char *state = h->ws + h->off.state_begin;
+  char *snap = h->ws + h->off.snap;
+  HIP_CHECK(hipMemcpyAsync(snap, state, sbytes, hipMemcpyDeviceToDevice, st));
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestG = h->G, bestW = h->wpb;
+  std::ostringstream trials;
+  for (int G = 1; G <= 2; ++G) {
+    for (int w : {1, 2, 4}) {
+      int rc = env_set_mapping(h, G, w);
+      if (rc) return rc;
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIP_CHECK(hipEventRecord(e0, st));
+        rc = run_rollout(h, probe_steps, nullptr, outs, st);
+        if (rc) return rc;
+        HIP_CHECK(hipEventRecord(e1, st));
+        HIP_CHECK(hipMemcpyAsync(state, snap, sbytes, hipMemcpyDeviceToDevice, st));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        ms_min = std::min(ms_min, ms);
+      }
+      trials << (trials.tellp() ? ", " : "") << "\"" << G << "x" << w << "\": " << ms_min;
+      if (ms_min < best) {
+        best = ms_min;
+        bestG = G;
+        bestW = w;
+      }
+    }
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  int rc = env_set_mapping(h, bestG, bestW);
+  if (rc) return rc;
+  if (cache_path) {
+    std::ofstream outf(cache_path, std::ios::app);
+    outf << "{\"key\": \"" << key << "\", \"lanes_per_agent\": " << bestG
+         << ", \"waves_per_block\": " << bestW << ", \"probe_steps\": " << probe_steps
+         << ", \"ms\": " << best << ", \"trials_ms\": {" << trials.str() << "}}\n";
+  }
+  return MIL_OK;
+}
+
+int env_destroy(mil_env *h) {
+  if (!h) return MIL_OK;
+  if (h->gexec) hipGraphExecDestroy(h->gexec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  delete h;
+  return MIL_OK;
+}
+
+int est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float tau, int32_t accum,
+              float *d_out, uint8_t *d_valid, void *stream) {
+  if (N < 0) return fail(MIL_EINVAL, "N must be >= 0");
+  if (N == 0) return MIL_OK;
+  if (!d_win || !d_out || !d_valid) return fail(MIL_EINVAL, "null argument");
+  if (W < 3 || W > 64) return fail(MIL_EINVAL, "W must be in 3..64");
+  if (gn_iters < 0 || gn_iters > 64) return fail(MIL_EINVAL, "gn_iters must be in 0..64");
+  if (accum != 0 && accum != 1) return fail(MIL_EINVAL, "accum must be 0 or 1");
+  if (((uintptr_t)d_win) & 3 || ((uintptr_t)d_out) & 7) return fail(MIL_EALIGN, "misaligned");
+  if (mil::launch_est_exact(d_win, N, W, gn_iters, tau, accum, d_out, d_valid, stream))
+    return fail(MIL_EHIP, "est_exact launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return MIL_OK;
+}
+
+int rng_philox(const uint32_t *d_ctr, int64_t n, uint64_t seed, uint32_t *d_out, float *d_u01,
+               float *d_normal, void *stream) {
+  if (n < 0) return fail(MIL_EINVAL, "n must be >= 0");
+  if (n == 0) return MIL_OK;
+  if (!d_ctr) return fail(MIL_EINVAL, "null counters");
+  if (mil::launch_rng(d_ctr, n, (uint32_t)seed, (uint32_t)(seed >> 32), d_out, d_u01, d_normal,
+                      stream))
+    return fail(MIL_EHIP, "rng launch failed");
+  return MIL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Structures shared by the host runtime and the environment kernels.
+#pragma once
+#include <stdint.h>
+
+namespace mil {
+
+// Environment constants as the kernels see them (by value, kernel argument).
+struct DevParams {
+  int32_t window, episode_len, n_actions, gn_iters;
+  float dt, agent_speed, area, spawn_r;
+  float dpsi[8];
+  float sig_a, sig_t;
+  float tv_lo, tv_hi, sr_lo, sr_hi;
+  float det_range, comm_range, comm_loss_p;
+  float eps_min, eps_max, d_safe, tau, lost_range;
+  uint32_t key0, key1;
+};
+
+// One (agents, targets) shape. Environments of a shape are consecutive in
+// packed order, so every per-env offset is an affine function of the env's
+// index inside its class. wave0/nwaves depend on the lane mapping.
+struct ClassInfo {
+  int64_t env0, nenv;
+  int64_t aoff0, toff0, poff0, koff0;
+  int32_t na, nt;
+  int32_t wave0, nwaves;
+};
+
+// Device pointers into the caller's workspace.
+struct DevState {
+  const uint32_t *env_id;  // [E] global id of each packed env
+  const uint8_t *cnt_a;    // [E]
+  const uint8_t *cnt_t;    // [E]
+  const int64_t *aoff, *toff, *poff, *koff;  // [E+1]
+  const ClassInfo *classes;                  // [num_classes]
+  const uint8_t *wave_class;                 // [num_waves]
+  float *ax, *ay, *apsi;                     // [A]
+  float *tx, *ty, *tpsi, *tv;                // [Tt]
+  float *sigma;                              // [E]
+  float *hx, *hy;                            // [W][A], entry 0 = newest
+  float *hr;                                 // [W][P]
+  float *ex, *ey;                            // [P]
+  uint8_t *ev;                               // [P]
+  double *macc;                              // [E][3] reward, err, err^2 sums
+  int32_t *miacc;                            // [E][2] err count, crash steps
+  uint32_t *status;                          // [1]
+  int64_t E, A, Tt, P, K;
+};
+
+// Output pointers (mirrors mil_env_outputs).
+struct DevOut {
+  float *obs;
+  uint8_t *obs_mask;
+  float *reward;
+  uint8_t *done;
+  float *est;
+  uint8_t *est_valid;
+  float *gstate;
+  int32_t *actions;
+  float *ranges;
+  float *err;
+};
+
+// Kernel launchers (env_kernels.hip). All enqueue on `stream`.
+int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const DevOut &o,
+                 void *stream);
+int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_block,
+                   int num_waves, const DevParams &p, const DevState &s, int32_t t0, int32_t T,
+                   uint32_t episode, const int32_t *actions, const DevOut &o, void *stream);
+int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
+                   void *stream);
+int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream);
+
+// est_kernels.hip
+int launch_est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float tau,
+                     int32_t accum, float *d_out, uint8_t *d_valid, void *stream);
+int launch_rng(const uint32_t *d_ctr, int64_t n, uint32_t key0, uint32_t key1, uint32_t *d_out,
+               float *d_u01, float *d_normal, void *stream);
+
+}  // namespace mil

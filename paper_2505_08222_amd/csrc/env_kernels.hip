@@ -1,0 +1,778 @@
+// Environment kernels for gfx950: reset, the persistent multi-step rollout
+// (which is also the one-step kernel, with T = 1), the metrics reduction and
+// a state copy.
+//
+// Mapping. One lane per (agent, lane-of-agent): an environment with n_a
+// agents occupies n_a * G consecutive lanes of one wavefront (G = lanes per
+// agent, 1 or 2; with G = 2 the agent's targets are split between its two
+// lanes by parity). Environments are packed by shape, so every lane of a
+// wavefront has the same (n_a, n_t) and all loops over entities have
+// wave-uniform trip counts. Per-lane state (the agent, the targets the lane
+// owns, its trackers' range histories and estimates) stays in registers for
+// the whole rollout; target positions are broadcast through a per-wavefront
+// LDS slab, agent positions and tracking errors through ds_bpermute.
+//
+// Step semantics (arXiv 2505.08222): kinematic surrogate with heading noise
+// (Sec. III-A-3), noisy ranges after the move, one range-only least-squares
+// tracker per (agent, target) over the last W ranges (Sec. II-A, III-A-2),
+// tracking reward Eq. (1) normalised by the number of targets with the crash
+// penalty (text after Eq. 2), entity-token observation (Sec. III-A-2 and the
+// TransfMAPPO caption), termination at the step limit only.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "env_internal.h"
+#include "ls_device.h"
+#include "rng.h"
+
+namespace mil {
+
+constexpr uint32_t kStatusBadAction = 0x1u;
+constexpr uint32_t kStatusNonFinite = 0x2u;
+
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Eq. (1): 1 below eps_min, exp(-2t/(1-t)) with t = (e-eps_min)/(eps_max-eps_min)
+// up to eps_max, 0 from eps_max on (the limit of the exponential there).
+__device__ __forceinline__ float tracking_reward(float e, float emin, float emax) {
+  if (e < emin) return 1.0f;
+  if (!(e < emax)) return 0.0f;
+  const float t = (e - emin) / (emax - emin);
+  return expf(-2.0f * t / (1.0f - t));
+}
+
+__device__ __forceinline__ void store_token(float *dst, float dx, float dy, float is_self,
+                                            float is_agent, float is_target) {
+  float2 *d = reinterpret_cast<float2 *>(dst);
+  d[0] = make_float2(dx, dy);
+  d[1] = make_float2(0.0f, is_self);
+  d[2] = make_float2(is_agent, is_target);
+}
+
+// Element (g + G*sl) of a per-env array held with compile-time indices.
+template <int G, int N>
+__device__ __forceinline__ float pick(const float (&arr)[N], int g, int sl) {
+  if constexpr (G == 1) {
+    return arr[sl];
+  } else {
+    const int j0 = G * sl;
+    const float a = arr[j0 < N ? j0 : N - 1];
+    const float b = arr[j0 + 1 < N ? j0 + 1 : N - 1];
+    return g ? b : a;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reset: one thread per (env, slot); slots 0..7 agents, 8..15 targets, 16 env.
+// ---------------------------------------------------------------------------
+__global__ void reset_kernel(DevParams p, DevState s, uint32_t episode) {
+  constexpr int kSlots = 17;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = tid / kSlots;
+  const int slot = (int)(tid - e * kSlots);
+  if (e >= s.E) return;
+  const uint32_t id = s.env_id[e];
+  const int na = s.cnt_a[e], nt = s.cnt_t[e];
+  const uint32_t c3 = (episode << 4) | kPurposeReset;
+  if (slot < 8) {
+    const int i = slot;
+    if (i >= na) return;
+    const u32x4 x = philox4x32_10(0u, id, (uint32_t)i, c3, p.key0, p.key1);
+    const float rad = p.spawn_r * sqrtf(u01(x.x));
+    float sn, cs;
+    sincospif(2.0f * u01(x.y), &sn, &cs);
+    const int64_t a = s.aoff[e] + i;
+    s.ax[a] = rad * cs;
+    s.ay[a] = rad * sn;
+    s.apsi[a] = -3.14159265358979f + 6.28318530717959f * u01(x.z);
+    const int64_t pb = s.poff[e] + (int64_t)i * nt;
+    for (int j = 0; j < nt; ++j) s.ev[pb + j] = 0;
+  } else if (slot < 16) {
+    const int j = slot - 8;
+    if (j >= nt) return;
+    const u32x4 x = philox4x32_10(0u, id, kEntTargetBlock + (uint32_t)j, c3, p.key0, p.key1);
+    const int64_t q = s.toff[e] + j;
+    s.tx[q] = -0.5f * p.area + p.area * u01(x.x);
+    s.ty[q] = -0.5f * p.area + p.area * u01(x.y);
+    s.tpsi[q] = -3.14159265358979f + 6.28318530717959f * u01(x.z);
+    s.tv[q] = p.tv_lo + (p.tv_hi - p.tv_lo) * u01(x.w);
+  } else {
+    const u32x4 x = philox4x32_10(0u, id, kEntEnv, c3, p.key0, p.key1);
+    s.sigma[e] = p.sr_lo + (p.sr_hi - p.sr_lo) * u01(x.x);
+    s.macc[3 * e] = 0.0;
+    s.macc[3 * e + 1] = 0.0;
+    s.macc[3 * e + 2] = 0.0;
+    s.miacc[2 * e] = 0;
+    s.miacc[2 * e + 1] = 0;
+  }
+}
+
+// Initial observation and global state after reset: one thread per (env,
+// slot); agents write their tokens (no tracker has an estimate yet, every
+// broadcast is received within the comm range), both write global state.
+__global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
+  constexpr int kSlots = 16;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = tid / kSlots;
+  const int slot = (int)(tid - e * kSlots);
+  if (e >= s.E) return;
+  const int na = s.cnt_a[e], nt = s.cnt_t[e];
+  const int64_t ab = s.aoff[e], tb = s.toff[e];
+  const int64_t gb = ab + tb;
+  if (slot < 8) {
+    const int i = slot;
+    if (i >= na) return;
+    const float ax = s.ax[ab + i], ay = s.ay[ab + i];
+    if (o.gstate) {
+      float *gs = o.gstate + (gb + i) * 6;
+      gs[0] = ax; gs[1] = ay; gs[2] = 0.0f; gs[3] = p.agent_speed; gs[4] = s.apsi[ab + i]; gs[5] = 0.0f;
+    }
+    const int64_t kb = s.koff[e] + (int64_t)i * (na + nt);
+    int m = 0;
+    if (o.obs) store_token(o.obs + (kb + m) * 6, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
+    if (o.obs_mask) o.obs_mask[kb + m] = 1;
+    ++m;
+    for (int k = 0; k < na; ++k) {
+      if (k == i) continue;
+      const float dx = s.ax[ab + k] - ax, dy = s.ay[ab + k] - ay;
+      const bool ok = sqrtf(dx * dx + dy * dy) <= p.comm_range;
+      if (o.obs) store_token(o.obs + (kb + m) * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
+      if (o.obs_mask) o.obs_mask[kb + m] = ok;
+      ++m;
+    }
+    for (int j = 0; j < nt; ++j) {
+      if (o.obs) store_token(o.obs + (kb + m) * 6, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
+      if (o.obs_mask) o.obs_mask[kb + m] = 0;
+      ++m;
+    }
+  } else {
+    const int j = slot - 8;
+    if (j >= nt || !o.gstate) return;
+    float *gs = o.gstate + (gb + na + j) * 6;
+    gs[0] = s.tx[tb + j]; gs[1] = s.ty[tb + j]; gs[2] = 0.0f; gs[3] = s.tv[tb + j];
+    gs[4] = s.tpsi[tb + j]; gs[5] = 1.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rollout: T steps per launch. S = largest supported entity count per env
+// (agents and targets), WC = register window capacity (W <= WC), G = lanes
+// per agent.
+// ---------------------------------------------------------------------------
+template <int S, int WC, int G>
+__global__ void __launch_bounds__(256)
+rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T,
+               uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
+  constexpr int MA = S, MT = S;
+  constexpr int NPL = (MT + G - 1) / G;  // (agent, target) pairs per lane
+  constexpr int NQ = (MT + 3) / 4;       // range-noise draws per agent
+  // per wavefront: the targets of its envs, (x, y, heading, speed)
+  extern __shared__ float4 lds_targets[];
+
+  const int lane = threadIdx.x & 63;
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
+  if (wave >= num_waves) return;
+  const ClassInfo C = s.classes[s.wave_class[wave]];
+  const int na = C.na, nt = C.nt;
+  const int lpe = na * G;
+  const int epw = 64 / lpe;
+  const int el = lane / lpe;
+  const int r = lane - el * lpe;
+  const int i = r / G;
+  const int g = r - i * G;
+  const int64_t ce_raw = (int64_t)(wave - C.wave0) * epw + el;
+  const bool active = (el < epw) && (ce_raw < C.nenv);
+  const int64_t ce = active ? ce_raw : 0;
+  const int64_t e = C.env0 + ce;
+  const int64_t aidx = C.aoff0 + ce * na + i;
+  const int64_t tbase = C.toff0 + ce * nt;
+  const int64_t pbase = C.poff0 + ce * na * nt + (int64_t)i * nt;
+  const int64_t kbase = C.koff0 + ce * na * (na + nt) + (int64_t)i * (na + nt);
+  const int64_t gbase = C.aoff0 + C.toff0 + ce * (na + nt);
+  const int base_lane = el * lpe;
+  const uint32_t env_id = s.env_id[e];
+  const float sig_r = s.sigma[e];
+  const int W = p.window;
+  const uint32_t c3dyn = (episode << 4) | kPurposeDynamics;
+  const uint32_t c3meas = (episode << 4) | kPurposeMeasure;
+  const float vdt = p.agent_speed * p.dt;
+  const int nB = (nt + 1) >> 1;
+  const double tau = (double)p.tau;
+  const float kInf = __int_as_float(0x7f800000);
+  const float kNaN = __int_as_float(0x7fc00000);
+  float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
+
+  // ---- load state: targets of the env into LDS (each lane its own blocks)
+  for (int q = r; q < nB; q += lpe) {
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int j = 2 * q + m;
+      if (j < nt) {
+        const int64_t idx = tbase + j;
+        tl[j] = make_float4(s.tx[idx], s.ty[idx], s.tpsi[idx], s.tv[idx]);
+      }
+    }
+  }
+  float ax = s.ax[aidx], ay = s.ay[aidx], apsi = s.apsi[aidx];
+  float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
+  uint32_t evb = 0;
+#pragma unroll
+  for (int k = 0; k < WC; ++k) {
+    hx[k] = (k < W) ? s.hx[(int64_t)k * s.A + aidx] : 0.0f;
+    hy[k] = (k < W) ? s.hy[(int64_t)k * s.A + aidx] : 0.0f;
+  }
+#pragma unroll
+  for (int sl = 0; sl < NPL; ++sl) {
+    const int j = g + G * sl;
+    const int64_t pidx = pbase + (j < nt ? j : 0);
+#pragma unroll
+    for (int k = 0; k < WC; ++k) hr[sl][k] = (k < W) ? s.hr[(int64_t)k * s.P + pidx] : 0.0f;
+    ex[sl] = s.ex[pidx];
+    ey[sl] = s.ey[pidx];
+    if (j < nt && s.ev[pidx]) evb |= 1u << sl;
+  }
+  double acc_rew = 0.0, acc_err = 0.0, acc_err2 = 0.0;
+  int acc_cnt = 0, acc_crash = 0;
+  if (active && r == 0) {
+    acc_rew = s.macc[3 * e];
+    acc_err = s.macc[3 * e + 1];
+    acc_err2 = s.macc[3 * e + 2];
+    acc_cnt = s.miacc[2 * e];
+    acc_crash = s.miacc[2 * e + 1];
+  }
+  uint32_t status = 0;
+  wave_lds_fence();
+
+  for (int step = 0; step < T; ++step) {
+    const uint32_t t = (uint32_t)(t0 + step);
+
+    // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
+    const u32x4 xa = philox4x32_10(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
+    int act;
+    if (actions) {
+      act = actions[(int64_t)step * s.A + aidx];
+      if (act < 0 || act >= p.n_actions) {
+        act = -1;
+        if (active) status |= kStatusBadAction;
+      }
+    } else {
+      act = (int)choice(xa.x, (uint32_t)p.n_actions);
+    }
+    float za, zb;
+    normal2(xa.y, xa.z, za, zb);
+    float dpsi = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (act == q) dpsi = p.dpsi[q];
+    apsi = (apsi + dpsi) + p.sig_a * za;
+    {
+      float sn, cs;
+      sincosf(apsi, &sn, &cs);
+      ax = ax + vdt * cs;
+      ay = ay + vdt * sn;
+    }
+    const bool comm_ok = !(u01(xa.w) < p.comm_loss_p);
+
+    // ---- targets owned by this lane (blocks of two): heading random walk
+    for (int q = r; q < nB; q += lpe) {
+      const u32x4 xt =
+          philox4x32_10(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
+      float zt[2];
+      normal2(xt.x, xt.y, zt[0], zt[1]);
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int j = 2 * q + m;
+        if (j < nt) {
+          float4 tg = tl[j];
+          tg.z = tg.z + p.sig_t * zt[m];
+          float sn, cs;
+          sincosf(tg.z, &sn, &cs);
+          const float step_len = tg.w * p.dt;
+          tg.x = tg.x + step_len * cs;
+          tg.y = tg.y + step_len * sn;
+          tl[j] = tg;
+        }
+      }
+    }
+    wave_lds_fence();
+    float tpx[MT], tpy[MT];
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      tpx[j] = 0.0f;
+      tpy[j] = 0.0f;
+      if (j < nt) {
+        const float4 v = tl[j];
+        tpx[j] = v.x;
+        tpy[j] = v.y;
+      }
+    }
+    wave_lds_fence();  // every lane has read before next step's owners write
+
+    // ---- noisy ranges after the move; missing beyond the detection range
+    float rnew[NPL];
+#pragma unroll
+    for (int sl = 0; sl < NPL; ++sl) rnew[sl] = kNaN;
+#pragma unroll
+    for (int q4 = 0; q4 < NQ; ++q4) {
+      if (4 * q4 < nt) {
+        const u32x4 xr = philox4x32_10(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4,
+                                       c3meas, p.key0, p.key1);
+        float zr[4];
+        normal2(xr.x, xr.y, zr[0], zr[1]);
+        normal2(xr.z, xr.w, zr[2], zr[3]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int j = 4 * q4 + m;
+          if (j < MT && j < nt && (j % G) == g) {
+            const float dx = ax - tpx[j], dy = ay - tpy[j];
+            const float dist = sqrtf(dx * dx + dy * dy);
+            const float rr = dist + sig_r * zr[m];
+            rnew[j / G] = (dist <= p.det_range) ? rr : kNaN;
+          }
+        }
+      }
+    }
+
+    // ---- range history: entry 0 is the newest
+#pragma unroll
+    for (int k = WC - 1; k > 0; --k) {
+      hx[k] = hx[k - 1];
+      hy[k] = hy[k - 1];
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) hr[sl][k] = hr[sl][k - 1];
+    }
+    hx[0] = ax;
+    hy[0] = ay;
+#pragma unroll
+    for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
+    const int filled = min((int)t + 1, W);
+
+    // ---- trackers (Sec. II-A): linearised LS about the centroid of the
+    // agent's window, FP64. With every entry present and no refinement the
+    // agent's 2x2 matrix S = sum u u^T and G = sum u |u|^2 are shared by its
+    // trackers and each tracker only adds g = G - sum u_k r_k^2 (the r-bar^2
+    // term of the centred form vanishes because sum u_k = 0). Other trackers
+    // take the general path below.
+    uint32_t pending = 0;
+    if (filled >= 3) {
+      double mx = 0.0, my = 0.0;
+#pragma unroll
+      for (int k = 0; k < WC; ++k)
+        if (k < filled) {
+          mx += (double)hx[k];
+          my += (double)hy[k];
+        }
+      const double invn = 1.0 / (double)filled;
+      mx *= invn;
+      my *= invn;
+      bool full[NPL];
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) full[sl] = (g + G * sl) < nt;
+      double sxx = 0.0, sxy = 0.0, syy = 0.0, gx[NPL], gy[NPL];
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) {
+        gx[sl] = 0.0;
+        gy[sl] = 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < WC; ++k) {
+        if (k < filled) {
+          const double ux = (double)hx[k] - mx, uy = (double)hy[k] - my;
+          const double nu = ux * ux + uy * uy;
+          sxx += ux * ux;
+          sxy += ux * uy;
+          syy += uy * uy;
+#pragma unroll
+          for (int sl = 0; sl < NPL; ++sl) {
+            const float rk = hr[sl][k];
+            full[sl] = full[sl] && (rk == rk);
+            const double rr = (double)rk;
+            const double c = nu - rr * rr;
+            gx[sl] += ux * c;
+            gy[sl] += uy * c;
+          }
+        }
+      }
+      const double det = sxx * syy - sxy * sxy, tr = sxx + syy;
+      const bool agent_ok = det > tau * tr * tr;
+      const double hdet = agent_ok ? 0.5 / det : 0.0;
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) {
+        const int j = g + G * sl;
+        if (j < nt) {
+          if (full[sl] && p.gn_iters == 0) {
+            if (agent_ok) {
+              ex[sl] = (float)(mx + hdet * (syy * gx[sl] - sxy * gy[sl]));
+              ey[sl] = (float)(my + hdet * (sxx * gy[sl] - sxy * gx[sl]));
+              evb |= 1u << sl;
+            }
+          } else {
+            pending |= 1u << sl;
+          }
+        }
+      }
+    }
+    // general path: missing entries or Gauss-Newton refinement (one copy of
+    // the solver, the tracker's history selected into a scratch row)
+    while (pending) {
+      const int sl = __builtin_ctz(pending);
+      pending &= pending - 1;
+      float row[WC];
+#pragma unroll
+      for (int k = 0; k < WC; ++k) {
+        float v = hr[0][k];
+#pragma unroll
+        for (int q = 1; q < NPL; ++q) v = (sl == q) ? hr[q][k] : v;
+        row[k] = v;
+      }
+      double px, py;
+      if (ls_masked<WC>(hx, hy, row, filled, p.gn_iters, tau, px, py)) {
+#pragma unroll
+        for (int q = 0; q < NPL; ++q)
+          if (sl == q) {
+            ex[q] = (float)px;
+            ey[q] = (float)py;
+          }
+        evb |= 1u << sl;
+      }
+    }
+
+    // ---- tracking error of this lane's trackers
+    float errp[NPL];
+#pragma unroll
+    for (int sl = 0; sl < NPL; ++sl) {
+      const int j = g + G * sl;
+      errp[sl] = kInf;
+      if (j < nt && ((evb >> sl) & 1u)) {
+        const float dx = ex[sl] - pick<G>(tpx, g, sl), dy = ey[sl] - pick<G>(tpy, g, sl);
+        errp[sl] = sqrtf(dx * dx + dy * dy);
+      }
+    }
+    // ---- team error per target (best tracker), Eq. (1), normalisation
+    float ej[MT];
+    float rsum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < MT; ++j) {
+      float v = kInf;
+      if (j < nt) {
+#pragma unroll
+        for (int k = 0; k < MA; ++k) {
+          if (k < na) v = fminf(v, __shfl(errp[j / G], base_lane + k * G + (j % G)));
+        }
+        rsum += tracking_reward(v, p.eps_min, p.eps_max);
+      }
+      ej[j] = v;
+    }
+    float rew = rsum / (float)nt;
+    // ---- agents' positions and broadcasts; crash penalty
+    float agx[MA], agy[MA];
+    int agc[MA];
+#pragma unroll
+    for (int k = 0; k < MA; ++k) {
+      agx[k] = 0.0f;
+      agy[k] = 0.0f;
+      agc[k] = 0;
+      if (k < na) {
+        const int src = base_lane + k * G;
+        agx[k] = __shfl(ax, src);
+        agy[k] = __shfl(ay, src);
+        agc[k] = __shfl((int)comm_ok, src);
+      }
+    }
+    bool crash = false;
+#pragma unroll
+    for (int k = 0; k < MA; ++k)
+#pragma unroll
+      for (int k2 = k + 1; k2 < MA; ++k2)
+        if (k2 < na) {
+          const float dx = agx[k] - agx[k2], dy = agy[k] - agy[k2];
+          crash = crash || (sqrtf(dx * dx + dy * dy) < p.d_safe);
+        }
+    if (crash) rew = -1.0f;
+    const bool done = (t + 1u == (uint32_t)p.episode_len);
+
+    // ---- outputs
+    if (active) {
+      if (r == 0) {
+        acc_rew += (double)rew;
+        acc_crash += crash ? 1 : 0;
+#pragma unroll
+        for (int j = 0; j < MT; ++j)
+          if (j < nt && ej[j] < kInf) {
+            acc_err += (double)ej[j];
+            acc_err2 += (double)ej[j] * (double)ej[j];
+            acc_cnt += 1;
+          }
+        if (o.reward) o.reward[(int64_t)step * s.E + e] = rew;
+        if (o.done) o.done[(int64_t)step * s.E + e] = done ? 1 : 0;
+        if (o.err) {
+#pragma unroll
+          for (int j = 0; j < MT; ++j)
+            if (j < nt) o.err[(int64_t)step * s.Tt + tbase + j] = ej[j];
+        }
+      }
+      const int64_t kb = (int64_t)step * s.K + kbase;
+      if (o.obs) {
+        float *ob = o.obs + kb * 6;
+        if (g == 0) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
+#pragma unroll
+        for (int m = 1; m < MA; ++m) {
+          if (m < na && (m % G) == g) {
+            const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
+            const float ox = before ? agx[m - 1] : agx[m];
+            const float oy = before ? agy[m - 1] : agy[m];
+            const int oc = before ? agc[m - 1] : agc[m];
+            const float dx = ox - ax, dy = oy - ay;
+            const bool ok = oc && (sqrtf(dx * dx + dy * dy) <= p.comm_range);
+            store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
+            if (o.obs_mask) o.obs_mask[kb + m] = ok ? 1 : 0;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          if (j < nt && (j % G) == g) {
+            const int sl = j / G;
+            const bool ok = (evb >> sl) & 1u;
+            store_token(ob + (na + j) * 6, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, 0.0f,
+                        0.0f, 1.0f);
+            if (o.obs_mask) o.obs_mask[kb + na + j] = ok ? 1 : 0;
+          }
+        }
+        if (o.obs_mask && g == 0) o.obs_mask[kb] = 1;
+      } else if (o.obs_mask) {
+        if (g == 0) o.obs_mask[kb] = 1;
+#pragma unroll
+        for (int m = 1; m < MA; ++m) {
+          if (m < na && (m % G) == g) {
+            const bool before = (m - 1) < i;
+            const float ox = before ? agx[m - 1] : agx[m];
+            const float oy = before ? agy[m - 1] : agy[m];
+            const int oc = before ? agc[m - 1] : agc[m];
+            const float dx = ox - ax, dy = oy - ay;
+            o.obs_mask[kb + m] = (oc && (sqrtf(dx * dx + dy * dy) <= p.comm_range)) ? 1 : 0;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < MT; ++j)
+          if (j < nt && (j % G) == g) o.obs_mask[kb + na + j] = ((evb >> (j / G)) & 1u) ? 1 : 0;
+      }
+      if (g == 0) {
+        if (o.actions) o.actions[(int64_t)step * s.A + aidx] = act;
+        if (o.gstate) {
+          float *gs = o.gstate + ((int64_t)step * (s.A + s.Tt) + gbase + i) * 6;
+          gs[0] = ax; gs[1] = ay; gs[2] = 0.0f; gs[3] = p.agent_speed; gs[4] = apsi; gs[5] = 0.0f;
+        }
+      }
+      if (o.gstate) {
+        for (int q = r; q < nB; q += lpe) {
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const int j = 2 * q + m;
+            if (j < nt) {
+              const float4 tg = tl[j];
+              float *gs = o.gstate + ((int64_t)step * (s.A + s.Tt) + gbase + na + j) * 6;
+              gs[0] = tg.x; gs[1] = tg.y; gs[2] = 0.0f; gs[3] = tg.w; gs[4] = tg.z; gs[5] = 1.0f;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) {
+        const int j = g + G * sl;
+        if (j < nt) {
+          const int64_t pidx = (int64_t)step * s.P + pbase + j;
+          const bool ok = (evb >> sl) & 1u;
+          if (o.est) {
+            o.est[2 * pidx] = ok ? ex[sl] : 0.0f;
+            o.est[2 * pidx + 1] = ok ? ey[sl] : 0.0f;
+          }
+          if (o.est_valid) o.est_valid[pidx] = ok ? 1 : 0;
+          if (o.ranges) o.ranges[pidx] = hr[sl][0];
+        }
+      }
+      if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
+        status |= kStatusNonFinite;
+    }
+  }
+
+  // ---- store state back
+  if (active) {
+    if (g == 0) {
+      s.ax[aidx] = ax;
+      s.ay[aidx] = ay;
+      s.apsi[aidx] = apsi;
+#pragma unroll
+      for (int k = 0; k < WC; ++k) {
+        if (k < W) {
+          s.hx[(int64_t)k * s.A + aidx] = hx[k];
+          s.hy[(int64_t)k * s.A + aidx] = hy[k];
+        }
+      }
+    }
+    for (int q = r; q < nB; q += lpe) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int j = 2 * q + m;
+        if (j < nt) {
+          const float4 tg = tl[j];
+          s.tx[tbase + j] = tg.x;
+          s.ty[tbase + j] = tg.y;
+          s.tpsi[tbase + j] = tg.z;
+        }
+      }
+    }
+#pragma unroll
+    for (int sl = 0; sl < NPL; ++sl) {
+      const int j = g + G * sl;
+      if (j < nt) {
+        const int64_t pidx = pbase + j;
+#pragma unroll
+        for (int k = 0; k < WC; ++k)
+          if (k < W) s.hr[(int64_t)k * s.P + pidx] = hr[sl][k];
+        s.ex[pidx] = ex[sl];
+        s.ey[pidx] = ey[sl];
+        s.ev[pidx] = (evb >> sl) & 1u;
+      }
+    }
+    if (r == 0) {
+      s.macc[3 * e] = acc_rew;
+      s.macc[3 * e + 1] = acc_err;
+      s.macc[3 * e + 2] = acc_err2;
+      s.miacc[2 * e] = acc_cnt;
+      s.miacc[2 * e + 1] = acc_crash;
+    }
+  }
+  if (status) atomicOr(s.status, status);
+}
+
+// ---------------------------------------------------------------------------
+// Metrics: one block; fixed assignment of envs to threads and a fixed tree,
+// so the sums are reproducible run to run.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) metrics_kernel(DevParams p, DevState s, int32_t steps,
+                                                       double *out) {
+  __shared__ double red[1024][6];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t e = threadIdx.x; e < s.E; e += blockDim.x) {
+    v[0] += s.macc[3 * e];
+    v[1] += s.macc[3 * e + 1];
+    v[2] += s.macc[3 * e + 2];
+    v[3] += (double)s.miacc[2 * e];
+    v[4] += (double)s.miacc[2 * e + 1];
+    const int64_t ab = s.aoff[e], tb = s.toff[e];
+    const int na = s.cnt_a[e], nt = s.cnt_t[e];
+    for (int j = 0; j < nt; ++j) {
+      float dmin = __int_as_float(0x7f800000);
+      for (int i = 0; i < na; ++i) {
+        const float dx = s.ax[ab + i] - s.tx[tb + j], dy = s.ay[ab + i] - s.ty[tb + j];
+        dmin = fminf(dmin, sqrtf(dx * dx + dy * dy));
+      }
+      if (dmin > p.lost_range) v[5] += 1.0;
+    }
+  }
+  for (int c = 0; c < 6; ++c) red[threadIdx.x][c] = v[c];
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 6; ++c) red[threadIdx.x][c] += red[threadIdx.x + w][c];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int c = 0; c < 6; ++c) out[c] = red[0][c];
+    out[6] = (double)s.E * (double)steps;
+    out[7] = (double)s.A * (double)steps;
+  }
+}
+
+__global__ void get_state_kernel(DevState s, float *agent, float *target) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (agent && k < s.A) {
+    agent[3 * k] = s.ax[k];
+    agent[3 * k + 1] = s.ay[k];
+    agent[3 * k + 2] = s.apsi[k];
+  }
+  if (target && k < s.Tt) {
+    target[4 * k] = s.tx[k];
+    target[4 * k + 1] = s.ty[k];
+    target[4 * k + 2] = s.tpsi[k];
+    target[4 * k + 3] = s.tv[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const DevOut &o,
+                 void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = s.E * 17;
+  const int bs = 256;
+  hipLaunchKernelGGL(reset_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, p, s,
+                     episode);
+  if (check_launch()) return -1;
+  if (o.obs || o.obs_mask || o.gstate) {
+    const int64_t n2 = s.E * 16;
+    hipLaunchKernelGGL(reset_obs_kernel, dim3((unsigned)((n2 + bs - 1) / bs)), dim3(bs), 0, st,
+                       p, s, o);
+    if (check_launch()) return -1;
+  }
+  return 0;
+}
+
+template <int S, int WC, int G>
+static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
+                            const DevState &s, int32_t t0, int32_t T, uint32_t episode,
+                            const int32_t *actions, const DevOut &o, hipStream_t st) {
+  const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
+  const size_t lds = (size_t)waves_per_block * 64 * S * sizeof(float4);
+  hipLaunchKernelGGL((rollout_kernel<S, WC, G>), dim3(blocks), dim3(64 * waves_per_block), lds,
+                     st, p, s, num_waves, t0, T, episode, actions, o);
+  return check_launch();
+}
+
+int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num_waves,
+                   const DevParams &p, const DevState &s, int32_t t0, int32_t T, uint32_t episode,
+                   const int32_t *actions, const DevOut &o, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (num_waves <= 0 || T <= 0) return 0;
+#define MIL_ROLL(SC, WCV, GV)                                                                 \
+  if (size_class == SC && wcap == WCV && G == GV)                                            \
+    return launch_rollout_t<SC, WCV, GV>(waves_per_block, num_waves, p, s, t0, T, episode,   \
+                                         actions, o, st);
+  MIL_ROLL(2, 10, 1)
+  MIL_ROLL(2, 10, 2)
+  MIL_ROLL(2, 16, 1)
+  MIL_ROLL(2, 16, 2)
+  MIL_ROLL(5, 10, 1)
+  MIL_ROLL(5, 10, 2)
+  MIL_ROLL(5, 16, 1)
+  MIL_ROLL(5, 16, 2)
+  MIL_ROLL(8, 16, 1)
+  MIL_ROLL(8, 16, 2)
+#undef MIL_ROLL
+  return -2;
+}
+
+int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
+                   void *stream) {
+  hipLaunchKernelGGL(metrics_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, p, s, steps,
+                     d_metrics);
+  return check_launch();
+}
+
+int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream) {
+  const int64_t n = s.A > s.Tt ? s.A : s.Tt;
+  const int bs = 256;
+  hipLaunchKernelGGL(get_state_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, s, d_agent, d_target);
+  return check_launch();
+}
+
+}  // namespace mil

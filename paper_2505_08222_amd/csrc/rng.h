@@ -1,0 +1,77 @@
+// Device-side counter-based random numbers for gfx950.
+//
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11): a 128-bit counter, a 64-bit key,
+// each round multiplies words 0 and 2 by two fixed odd constants, mixes the
+// product halves with words 1 and 3 and the key, and bumps the key by two
+// Weyl constants. The key is the user seed, so on a wavefront it is uniform
+// and the key schedule lives in scalar registers.
+//
+// Every draw of the environment is a pure function of
+// (step, global env id, entity code, purpose | episode << 4): results do not
+// depend on which lane or launch computes them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mil {
+
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return u32x4{c0, c1, c2, c3};
+}
+
+// Uniform in (0,1): ((x >> 9) + 1/2) / 2^23, exact in binary32.
+__device__ __forceinline__ float u01(uint32_t x) {
+  return __uint2float_rn(x >> 9) * 0x1p-23f + 0x1p-24f;
+}
+
+// Box-Muller (1958). The angle 2*pi*u1 is evaluated with sincospi on the
+// exactly representable argument 2*u1, avoiding a rounded 2*pi product.
+__device__ __forceinline__ void normal2(uint32_t x0, uint32_t x1, float &z0, float &z1) {
+  const float u0 = u01(x0);
+  const float u1 = u01(x1);
+  const float rad = sqrtf(-2.0f * logf(u0));
+  float s, c;
+  sincospif(2.0f * u1, &s, &c);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
+// Uniform choice in 0..n-1: floor(n * x / 2^32).
+__device__ __forceinline__ uint32_t choice(uint32_t x, uint32_t n) { return __umulhi(x, n); }
+
+// Counter layout of the environment's draws.
+enum : uint32_t {
+  kPurposeDynamics = 0,
+  kPurposeMeasure = 1,
+  kPurposeReset = 2,
+  kPurposeConfig = 3,
+  kPurposePolicy = 4,
+};
+enum : uint32_t {
+  kEntTargetBlock = 16,  // + j/2 for step draws, + j for reset draws
+  kEntRangeRow = 64,     // + 8 * agent + j/4
+  kEntEnv = 127,
+};
+
+}  // namespace mil

@@ -1,0 +1,131 @@
+"""Comparison of GPU rollouts with the FP64 oracle.
+
+Tolerances ("parity"): states, ranges and rewards must agree to
+1e-5 relative with scale s = area/2 for lengths and pi for headings. The
+range-only estimate amplifies any difference of its inputs by the window's
+geometry, so each estimate is checked against
+    1e-5 * s + 4 * sens * delta_in
+where sens (from the oracle) is the estimate's sensitivity to its window
+inputs (m per m) and delta_in the largest input difference measured so far in
+that env; rewards and target tokens inherit that bound (Eq. (1) changes by at
+most 0.05 per metre of tracking error).
+"""
+import numpy as np
+
+REL = 1e-5
+
+
+def gpu_rollout_records(env, T, record, actions=None):
+    out = env.rollout(T, actions=actions, record=record)
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def select(gpu_arr, csr_gpu, packed_idx, width=1):
+    """Rows of the packed envs `packed_idx` from a [T, N*width...] array."""
+    parts = [gpu_arr[:, csr_gpu[k]:csr_gpu[k + 1]] for k in packed_idx]
+    return np.concatenate(parts, axis=1)
+
+
+def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
+    """gpu: dict of numpy [T, ...] arrays in packed order (all envs);
+    orc: oracle rollout of the selected envs (in the order of packed_idx)."""
+    s = cfg["area"] / 2.0
+    o = env.order
+    report = {}
+    na = env.n_agents[packed_idx]
+    nt = env.n_targets[packed_idx]
+    # ---- states (global state rows: agents then targets per env)
+    g_ent_off = o["agent"] + o["target"]
+    gs = select(gpu["gstate"], g_ent_off, packed_idx)  # [T, sum(na+nt), 6]
+    rows_a, rows_t = [], []
+    cur = 0
+    for k in range(len(packed_idx)):
+        rows_a.extend(range(cur, cur + na[k]))
+        rows_t.extend(range(cur + na[k], cur + na[k] + nt[k]))
+        cur += na[k] + nt[k]
+    ga, gt = gs[:, rows_a], gs[:, rows_t]
+    oa, ot = orc["agent"], orc["target"]
+    dpos_a = np.abs(ga[..., :2] - oa[..., :2]).max(-1)  # [T, A]
+    dpos_t = np.abs(gt[..., :2] - ot[..., :2]).max(-1)
+    dpsi = np.abs(ga[..., 4] - oa[..., 2])
+    report["pos_rel"] = max(dpos_a.max(), dpos_t.max()) / s
+    report["psi_rel"] = dpsi.max() / np.pi
+    assert report["pos_rel"] <= REL, f"{label} positions differ: {report['pos_rel']:.3g}"
+    assert report["psi_rel"] <= REL, f"{label} headings differ: {report['psi_rel']:.3g}"
+    report["tpsi_rel"] = np.abs(gt[..., 4] - ot[..., 2]).max() / np.pi
+    assert report["tpsi_rel"] <= REL, f"{label} target headings differ"
+    assert (np.abs(gt[..., 3] - ot[..., 3]) <= 1e-6 * np.abs(ot[..., 3]) + 1e-7).all()
+    # ---- actions (random policy: exact integer draws)
+    if "actions" in gpu:
+        np.testing.assert_array_equal(select(gpu["actions"], o["agent"], packed_idx),
+                                      orc["actions"])
+    # ---- ranges
+    gr = select(gpu["ranges"], o["pair"], packed_idx)
+    orr = orc["ranges"]
+    assert (np.isnan(gr) == np.isnan(orr)).all(), f"{label} range presence differs"
+    fin = ~np.isnan(orr)
+    dr = np.zeros_like(orr)
+    dr[fin] = np.abs(gr[fin] - orr[fin])
+    report["range_rel"] = dr.max() / s
+    assert report["range_rel"] <= REL, f"{label} ranges differ: {report['range_rel']:.3g}"
+    # ---- input difference per env, cumulative over time
+    T = oa.shape[0]
+    E = len(packed_idx)
+    delta = np.zeros((T, E))
+    ca = np.concatenate([[0], np.cumsum(na)])
+    ct = np.concatenate([[0], np.cumsum(nt)])
+    cp = np.concatenate([[0], np.cumsum(na * nt)])
+    for k in range(E):
+        d = np.maximum(dpos_a[:, ca[k]:ca[k + 1]].max(1), dr[:, cp[k]:cp[k + 1]].max(1))
+        delta[:, k] = np.maximum.accumulate(d)
+    # ---- estimates
+    ge = select(gpu["est"], o["pair"], packed_idx)
+    gv = select(gpu["est_valid"], o["pair"], packed_idx)
+    np.testing.assert_array_equal(gv, orc["est_valid"], err_msg=f"{label} estimate validity")
+    pair_env = np.repeat(np.arange(E), na * nt)
+    tol_est = REL * s + 4.0 * orc["sens"] * delta[:, pair_env]
+    tol_est = np.where(np.isfinite(tol_est), tol_est, np.inf)
+    de = np.abs(ge - orc["est"]).max(-1)
+    v = orc["est_valid"].astype(bool)
+    ratio = np.where(v, de / tol_est, 0.0)
+    report["est_max_ratio"] = float(ratio.max()) if ratio.size else 0.0
+    report["est_plain_rel_max"] = float((de[v] / s).max()) if v.any() else 0.0
+    report["est_frac_within_1e-5"] = float((de[v] / s <= REL).mean()) if v.any() else 1.0
+    assert report["est_max_ratio"] <= 1.0, f"{label} estimates differ beyond bound: {report}"
+    # ---- tracking error, rewards, crash, done
+    tol_pair = np.where(v, tol_est, 0.0)
+    tol_e = np.zeros((T, int(ct[-1])))
+    for k in range(E):
+        tp = tol_pair[:, cp[k]:cp[k + 1]].reshape(T, na[k], nt[k]).max(1)
+        tol_e[:, ct[k]:ct[k + 1]] = tp + dpos_t[:, ct[k]:ct[k + 1]]
+    g_err = select(gpu["err"], o["target"], packed_idx)
+    o_err = orc["err"]
+    assert (np.isinf(g_err) == np.isinf(o_err)).all(), f"{label} tracking-error presence"
+    f = np.isfinite(o_err)
+    assert (np.abs(g_err[f] - o_err[f]) <= tol_e[f] + REL * s).all(), f"{label} tracking error"
+    grw = gpu["reward"][:, packed_idx]
+    crash_g = grw == -1.0
+    np.testing.assert_array_equal(crash_g, orc["crash"].astype(bool), err_msg=f"{label} crash")
+    tol_r = np.zeros((T, E))
+    for k in range(E):
+        tol_r[:, k] = 0.05 * tol_e[:, ct[k]:ct[k + 1]].sum(1) / nt[k] + REL
+    dr_ = np.abs(grw - orc["reward"])
+    report["reward_max_abs"] = float(dr_.max())
+    assert (dr_ <= tol_r).all(), f"{label} rewards differ: {report}"
+    np.testing.assert_array_equal(gpu["done"][:, packed_idx], orc["done"])
+    # ---- observations
+    gob = select(gpu["obs"], o["token"], packed_idx)
+    gm = select(gpu["obs_mask"], o["token"], packed_idx)
+    np.testing.assert_array_equal(gm, orc["obs_mask"], err_msg=f"{label} obs mask")
+    np.testing.assert_array_equal(gob[..., 2:], orc["obs"][..., 2:].astype(np.float32))
+    ck = np.concatenate([[0], np.cumsum(na * (na + nt))])
+    for k in range(E):
+        tok = slice(ck[k], ck[k + 1])
+        d = np.abs(gob[:, tok, :2] - orc["obs"][:, tok, :2]).max(-1).reshape(T, na[k], -1)
+        # agent tokens: two positions; target tokens: estimate plus position
+        lim_agent = 2 * REL * s + 2 * dpos_a[:, ca[k]:ca[k + 1]].max(1)
+        assert (d[:, :, :na[k]] <= lim_agent[:, None, None] + 1e-6).all(), f"{label} agent tokens"
+        tp = tol_pair[:, cp[k]:cp[k + 1]].reshape(T, na[k], nt[k])
+        lim_t = tp + REL * s + dpos_a[:, ca[k]:ca[k + 1], None]
+        assert (d[:, :, na[k]:] <= lim_t + 1e-6).all(), f"{label} target tokens"
+    return report
