@@ -232,6 +232,58 @@ int est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float 
 int rng_philox(const uint32_t *d_ctr, int64_t n, uint64_t seed, uint32_t *d_out, float *d_u01,
                float *d_normal, void *stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Learned range-only estimator (stands in for the exact solve of Sec. II-A;
+ * the exact estimator remains its fallback and the judge of its error).
+ * Network: 64 -> 128 -> 128 -> 2, GELU (tanh form) after each hidden layer.
+ * Parameters: one FP32 vector of mlp_num_params() floats, in this order:
+ * W1 [128][64], b1 [128], W2 [128][128], b2 [128], W3 [2][128], b3 [2], each
+ * weight matrix row-major (output, input).
+ * Features of a window [W][3] = (agent x, agent y, range), W <= 21, all
+ * entries present: with abar, rbar the means and theta the direction of the
+ * chord from the oldest to the newest agent position (entry W-1 to entry 0),
+ * u_k = R(-theta)(a_k - abar); x[3k..3k+2] = (u_k / 10 m, (r_k - rbar) / 10 m),
+ * x[3W] = rbar / 1000 m, the rest 0. frame = (abar_x, abar_y, cos theta,
+ * sin theta, rbar). The network predicts y = R(-theta)(p - abar) / rbar, so
+ * p = abar + rbar R(theta) y.
+ * precision: 0 = BF16 operands on MFMA with FP32 accumulation, 1 = FP32
+ * operands (FP32 MFMA; for checks). Workspaces are caller-owned device
+ * buffers of mlp_workspace_bytes(N, precision) bytes, 256-byte aligned.
+ * ------------------------------------------------------------------------- */
+int64_t mlp_num_params(void);
+int64_t mlp_workspace_bytes(int64_t N, int32_t precision);
+/* Glorot-uniform weights (Philox stream keyed by seed), zero biases. */
+int mlp_init(float *d_params, uint64_t seed, void *stream);
+/* d_win [N][W][3] -> d_x [N][64] (16-byte aligned), d_frame [N][5]. */
+int mlp_features(const float *d_win, int64_t N, int32_t W, float *d_x, float *d_frame,
+                 void *stream);
+/* Normalised training target of estimates d_p [N][2]: d_y [N][2]. */
+int mlp_targets(const float *d_frame, const float *d_p, int64_t N, float *d_y, void *stream);
+/* d_y [N][2] = network(d_x). */
+int mlp_forward(int64_t N, const float *d_x, const float *d_params, float *d_y, int32_t precision,
+                void *d_work, int64_t work_bytes, void *stream);
+/* Mean over the N samples of |y - target|^2 into *d_loss (may be NULL) and
+ * its gradient into d_grad [mlp_num_params()]. Sample s reads row
+ * d_index[s] of d_x and d_target (d_index NULL: row s). Deterministic. */
+int mlp_backward(int64_t N, const float *d_x, const int64_t *d_index, const float *d_target,
+                 const float *d_params, float *d_grad, float *d_loss, int32_t precision,
+                 void *d_work, int64_t work_bytes, void *stream);
+/* Adam (Kingma and Ba) with bias correction on P parameters; step >= 1. */
+int mlp_adam_step(int64_t P, float *d_params, const float *d_grad, float *d_m, float *d_v,
+                  float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
+/* Estimates of N windows: the BF16 network, accepted when the RMS over the
+ * window of (|p - a_k| - r_k) is <= k_sigma * d_sigma[n]; otherwise (or with a
+ * missing entry) the exact solve of est_exact (gn_iters, tau). d_flag [N]:
+ * 1 network, 0 exact fallback, 2 neither (exact solve refused). */
+int mlp_infer(const float *d_win, int64_t N, int32_t W, const float *d_params,
+              const float *d_sigma, float k_sigma, int32_t gn_iters, float tau, float *d_out,
+              uint8_t *d_flag, void *d_work, int64_t work_bytes, void *stream);
+/* Every tracker's current window of a bound environment: d_win [P][W][3]
+ * (entry 0 = newest), d_sigma [P] its env's range-noise std, d_truth [P][2]
+ * the true target position (either may be NULL). */
+int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,205 @@
+/*
+ * FP64 oracle of the learned range-only estimator and of the attention
+ * policy. TEST INFRASTRUCTURE ONLY (see lrauv_oracle.h).
+ *
+ * The learned estimator is not in the paper: it stands in for the per-target
+ * range-only estimator of Sec. II-A. Its readings (features, output
+ * parameterisation, loss) are listed in the design doc; this file writes them out
+ * plainly in FP64.
+ *
+ *   features of a window of W entries (a_k, r_k), all present:
+ *     abar = mean a_k, rbar = mean r_k; theta = direction of a_0 - a_{W-1}
+ *     (0 when that chord is shorter than 1e-6 m); u_k = R(-theta)(a_k - abar)
+ *     x[3k] = u_k.x / 10, x[3k+1] = u_k.y / 10, x[3k+2] = (r_k - rbar) / 10,
+ *     x[3W] = rbar / 1000, remaining inputs up to 64 are 0.
+ *   network: z1 = W1 x + b1, h1 = gelu(z1), z2 = W2 h1 + b2, h2 = gelu(z2),
+ *     y = W3 h2 + b3 with gelu the tanh form of Hendrycks and Gimpel,
+ *     W1 [128][64], W2 [128][128], W3 [2][128] stored row-major (out, in),
+ *     parameter vector = W1, b1, W2, b2, W3, b3.
+ *   estimate: p = abar + rbar * R(theta) y.
+ *   loss: mean over samples of |y - y_target|^2.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NIN 64
+#define NH 128
+#define NOUT 2
+#define OFF_W1 0
+#define OFF_B1 (OFF_W1 + NH * NIN)
+#define OFF_W2 (OFF_B1 + NH)
+#define OFF_B2 (OFF_W2 + NH * NH)
+#define OFF_W3 (OFF_B2 + NH)
+#define OFF_B3 (OFF_W3 + NOUT * NH)
+#define NPARAM (OFF_B3 + NOUT)
+
+int64_t orc_mlp_num_params(void) { return NPARAM; }
+
+static double gelu(double x) {
+  const double c = 0.79788456080286535588; /* sqrt(2/pi) */
+  return 0.5 * x * (1.0 + tanh(c * (x + 0.044715 * x * x * x)));
+}
+
+static double gelu_grad(double x) {
+  const double c = 0.79788456080286535588;
+  double u = c * (x + 0.044715 * x * x * x);
+  double th = tanh(u);
+  double du = c * (1.0 + 3.0 * 0.044715 * x * x);
+  return 0.5 * (1.0 + th) + 0.5 * x * (1.0 - th * th) * du;
+}
+
+/* feat [N][64], frame [N][5] = (abar_x, abar_y, cos theta, sin theta, rbar) */
+void orc_window_features(int64_t N, int W, const double *win, double *feat, double *frame) {
+  for (int64_t n = 0; n < N; ++n) {
+    const double *w = win + n * W * 3;
+    double mx = 0.0, my = 0.0, mr = 0.0;
+    for (int k = 0; k < W; ++k) {
+      mx += w[3 * k];
+      my += w[3 * k + 1];
+      mr += w[3 * k + 2];
+    }
+    mx /= W;
+    my /= W;
+    mr /= W;
+    double cx = w[0] - w[3 * (W - 1)], cy = w[1] - w[3 * (W - 1) + 1];
+    double len = hypot(cx, cy);
+    double c = 1.0, s = 0.0;
+    if (len > 1e-6) {
+      c = cx / len;
+      s = cy / len;
+    }
+    double *f = feat + n * NIN;
+    for (int i = 0; i < NIN; ++i) f[i] = 0.0;
+    for (int k = 0; k < W; ++k) {
+      double dx = w[3 * k] - mx, dy = w[3 * k + 1] - my;
+      f[3 * k] = (c * dx + s * dy) / 10.0;
+      f[3 * k + 1] = (-s * dx + c * dy) / 10.0;
+      f[3 * k + 2] = (w[3 * k + 2] - mr) / 10.0;
+    }
+    f[3 * W] = mr / 1000.0;
+    double *fr = frame + n * 5;
+    fr[0] = mx;
+    fr[1] = my;
+    fr[2] = c;
+    fr[3] = s;
+    fr[4] = mr;
+  }
+}
+
+/* Normalised target of an estimate p in a window's frame: R(-theta)(p - abar)/rbar. */
+void orc_mlp_target(int64_t N, const double *frame, const double *p, double *y) {
+  for (int64_t n = 0; n < N; ++n) {
+    const double *fr = frame + n * 5;
+    double dx = p[2 * n] - fr[0], dy = p[2 * n + 1] - fr[1];
+    y[2 * n] = (fr[2] * dx + fr[3] * dy) / fr[4];
+    y[2 * n + 1] = (-fr[3] * dx + fr[2] * dy) / fr[4];
+  }
+}
+
+/* Estimate from a network output: abar + rbar R(theta) y. */
+void orc_mlp_decode(int64_t N, const double *frame, const double *y, double *p) {
+  for (int64_t n = 0; n < N; ++n) {
+    const double *fr = frame + n * 5;
+    double ux = fr[4] * y[2 * n], uy = fr[4] * y[2 * n + 1];
+    p[2 * n] = fr[0] + fr[2] * ux - fr[3] * uy;
+    p[2 * n + 1] = fr[1] + fr[3] * ux + fr[2] * uy;
+  }
+}
+
+static void forward_one(const double *x, const double *th, double *z1, double *h1, double *z2,
+                        double *h2, double *y) {
+  for (int o = 0; o < NH; ++o) {
+    double acc = th[OFF_B1 + o];
+    for (int i = 0; i < NIN; ++i) acc += th[OFF_W1 + o * NIN + i] * x[i];
+    z1[o] = acc;
+    h1[o] = gelu(acc);
+  }
+  for (int o = 0; o < NH; ++o) {
+    double acc = th[OFF_B2 + o];
+    for (int i = 0; i < NH; ++i) acc += th[OFF_W2 + o * NH + i] * h1[i];
+    z2[o] = acc;
+    h2[o] = gelu(acc);
+  }
+  for (int o = 0; o < NOUT; ++o) {
+    double acc = th[OFF_B3 + o];
+    for (int i = 0; i < NH; ++i) acc += th[OFF_W3 + o * NH + i] * h2[i];
+    y[o] = acc;
+  }
+}
+
+void orc_mlp_forward(int64_t N, const double *x, const double *params, double *y) {
+  double z1[NH], h1[NH], z2[NH], h2[NH];
+  for (int64_t n = 0; n < N; ++n) forward_one(x + n * NIN, params, z1, h1, z2, h2, y + n * NOUT);
+}
+
+/* Mean-squared loss and its gradient (grad [NPARAM], overwritten). */
+double orc_mlp_backward(int64_t N, const double *x, const double *target, const double *params,
+                        double *grad, double *y_out) {
+  for (int i = 0; i < NPARAM; ++i) grad[i] = 0.0;
+  double loss = 0.0;
+  double z1[NH], h1[NH], z2[NH], h2[NH], y[NOUT], dz2[NH], dz1[NH];
+  for (int64_t n = 0; n < N; ++n) {
+    const double *xn = x + n * NIN;
+    forward_one(xn, params, z1, h1, z2, h2, y);
+    if (y_out) {
+      y_out[2 * n] = y[0];
+      y_out[2 * n + 1] = y[1];
+    }
+    double dy[NOUT];
+    for (int o = 0; o < NOUT; ++o) {
+      double e = y[o] - target[n * NOUT + o];
+      loss += e * e;
+      dy[o] = 2.0 * e / (double)N;
+    }
+    for (int o = 0; o < NOUT; ++o) {
+      grad[OFF_B3 + o] += dy[o];
+      for (int i = 0; i < NH; ++i) grad[OFF_W3 + o * NH + i] += dy[o] * h2[i];
+    }
+    for (int i = 0; i < NH; ++i) {
+      double dh = 0.0;
+      for (int o = 0; o < NOUT; ++o) dh += dy[o] * params[OFF_W3 + o * NH + i];
+      dz2[i] = dh * gelu_grad(z2[i]);
+    }
+    for (int o = 0; o < NH; ++o) {
+      grad[OFF_B2 + o] += dz2[o];
+      for (int i = 0; i < NH; ++i) grad[OFF_W2 + o * NH + i] += dz2[o] * h1[i];
+    }
+    for (int i = 0; i < NH; ++i) {
+      double dh = 0.0;
+      for (int o = 0; o < NH; ++o) dh += dz2[o] * params[OFF_W2 + o * NH + i];
+      dz1[i] = dh * gelu_grad(z1[i]);
+    }
+    for (int o = 0; o < NH; ++o) {
+      grad[OFF_B1 + o] += dz1[o];
+      for (int i = 0; i < NIN; ++i) grad[OFF_W1 + o * NIN + i] += dz1[o] * xn[i];
+    }
+  }
+  return loss / (double)N;
+}
+
+/* Adam (Kingma and Ba, 2015) with bias correction; step counts from 1. */
+void orc_adam_step(int64_t P, double *params, const double *grad, double *m, double *v,
+                   int64_t step, double lr, double beta1, double beta2, double eps) {
+  double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+  for (int64_t i = 0; i < P; ++i) {
+    m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+    v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+    double mh = m[i] / c1, vh = v[i] / c2;
+    params[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}
+
+/* RMS over a window of (|p - a_k| - r_k): the fallback test statistic. */
+void orc_mlp_residual_rms(int64_t N, int W, const double *win, const double *p, double *rms) {
+  for (int64_t n = 0; n < N; ++n) {
+    const double *w = win + n * W * 3;
+    double acc = 0.0;
+    for (int k = 0; k < W; ++k) {
+      double res = hypot(p[2 * n] - w[3 * k], p[2 * n + 1] - w[3 * k + 1]) - w[3 * k + 2];
+      acc += res * res;
+    }
+    rms[n] = sqrt(acc / W);
+  }
+}

@@ -84,22 +84,20 @@ def lib():
 
 def _register_learned(L):
     """Declare the learned-part entry points when the library has them."""
-    P = C.POINTER
+    P, D, I64 = C.POINTER, C.c_double, C.c_int64
     if hasattr(L, "orc_mlp_forward"):
-        L.orc_mlp_forward.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double)]
-        L.orc_mlp_backward.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double),
-                                       P(C.c_double), P(C.c_double)]
-        L.orc_mlp_backward.restype = C.c_double
-        L.orc_adam_step.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), P(C.c_double),
-                                    P(C.c_double), C.c_int64, C.c_double, C.c_double,
-                                    C.c_double, C.c_double]
-        L.orc_window_features.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_double),
-                                          P(C.c_double)]
-        L.orc_mlp_residual_rms.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_double),
-                                           P(C.c_double)]
+        L.orc_mlp_num_params.restype = I64
+        L.orc_window_features.argtypes = [I64, C.c_int, P(D), P(D), P(D)]
+        L.orc_mlp_target.argtypes = [I64, P(D), P(D), P(D)]
+        L.orc_mlp_decode.argtypes = [I64, P(D), P(D), P(D)]
+        L.orc_mlp_forward.argtypes = [I64, P(D), P(D), P(D)]
+        L.orc_mlp_backward.argtypes = [I64, P(D), P(D), P(D), P(D), P(D)]
+        L.orc_mlp_backward.restype = D
+        L.orc_adam_step.argtypes = [I64, P(D), P(D), P(D), P(D), I64, D, D, D, D]
+        L.orc_mlp_residual_rms.argtypes = [I64, C.c_int, P(D), P(D), P(D)]
     if hasattr(L, "orc_policy_forward"):
-        L.orc_policy_forward.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(C.c_uint8),
-                                         P(C.c_double), P(C.c_double)]
+        L.orc_policy_num_params.restype = I64
+        L.orc_policy_forward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D)]
 
 
 def _p(a, ctype):
@@ -246,4 +244,74 @@ def rollout(cfg: dict, env_ids, n_agents, n_targets, seed: int, T: int, episode:
         "pair": np.concatenate([[0], np.cumsum(na.astype(np.int64) * nt)]),
         "token": np.concatenate([[0], np.cumsum(na.astype(np.int64) * (na + nt))]),
     }
+    return out
+
+
+# ---------------------------------------------------------------- learned part
+def mlp_num_params() -> int:
+    return int(lib().orc_mlp_num_params())
+
+
+def window_features(win: np.ndarray):
+    """win [N, W, 3] -> features [N, 64], frame [N, 5]."""
+    win = np.ascontiguousarray(win, np.float64)
+    N, W, _ = win.shape
+    feat = np.zeros((N, 64))
+    frame = np.zeros((N, 5))
+    lib().orc_window_features(N, W, _p(win, C.c_double), _p(feat, C.c_double),
+                              _p(frame, C.c_double))
+    return feat, frame
+
+
+def mlp_target(frame, p):
+    frame = np.ascontiguousarray(frame, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    y = np.zeros((frame.shape[0], 2))
+    lib().orc_mlp_target(frame.shape[0], _p(frame, C.c_double), _p(p, C.c_double),
+                         _p(y, C.c_double))
+    return y
+
+
+def mlp_decode(frame, y):
+    frame = np.ascontiguousarray(frame, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    p = np.zeros((frame.shape[0], 2))
+    lib().orc_mlp_decode(frame.shape[0], _p(frame, C.c_double), _p(y, C.c_double),
+                         _p(p, C.c_double))
+    return p
+
+
+def mlp_forward(x, params):
+    x = np.ascontiguousarray(x, np.float64)
+    params = np.ascontiguousarray(params, np.float64)
+    y = np.zeros((x.shape[0], 2))
+    lib().orc_mlp_forward(x.shape[0], _p(x, C.c_double), _p(params, C.c_double),
+                          _p(y, C.c_double))
+    return y
+
+
+def mlp_backward(x, target, params):
+    """(loss, grad, y) of the mean-squared loss."""
+    x = np.ascontiguousarray(x, np.float64)
+    target = np.ascontiguousarray(target, np.float64)
+    params = np.ascontiguousarray(params, np.float64)
+    grad = np.zeros_like(params)
+    y = np.zeros((x.shape[0], 2))
+    loss = lib().orc_mlp_backward(x.shape[0], _p(x, C.c_double), _p(target, C.c_double),
+                                  _p(params, C.c_double), _p(grad, C.c_double), _p(y, C.c_double))
+    return loss, grad, y
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on float64 arrays."""
+    lib().orc_adam_step(params.shape[0], _p(params, C.c_double), _p(grad, C.c_double),
+                        _p(m, C.c_double), _p(v, C.c_double), step, lr, beta1, beta2, eps)
+
+
+def residual_rms(win, p):
+    win = np.ascontiguousarray(win, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    N, W, _ = win.shape
+    out = np.zeros(N)
+    lib().orc_mlp_residual_rms(N, W, _p(win, C.c_double), _p(p, C.c_double), _p(out, C.c_double))
     return out

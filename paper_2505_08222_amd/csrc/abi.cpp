@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "env_internal.h"
+#include "learned_internal.h"
 #include "mi_lrauv.h"
 
 #ifndef MIL_CODE_VERSION
@@ -246,6 +247,9 @@ std::string device_key(mil_env *h) {
 extern "C" {
 
 const char *env_last_error(void) { return g_last_error.c_str(); }
+
+// Shared with the learned-part ABI in the same library.
+int mil_set_error(int code, const char *msg) { return fail(code, "%s", msg); }
 
 int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
                const int32_t *counts, mil_env **out) {
@@ -652,6 +656,14 @@ int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
          << ", \"waves_per_block\": " << bestW << ", \"probe_steps\": " << probe_steps
          << ", \"ms\": " << best << ", \"trials_ms\": {" << trials.str() << "}}\n";
   }
+  return MIL_OK;
+}
+
+int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream) {
+  if (!h || !d_win) return fail(MIL_EINVAL, "null argument");
+  if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
+  if (mil::launch_env_windows(h->ds, h->W, d_win, d_sigma, d_truth, stream))
+    return fail(MIL_EHIP, "window copy launch failed");
   return MIL_OK;
 }
 

@@ -22,6 +22,7 @@
 #include <math.h>
 
 #include "env_internal.h"
+#include "learned_internal.h"
 #include "ls_device.h"
 #include "rng.h"
 
@@ -702,6 +703,39 @@ __global__ void get_state_kernel(DevState s, float *agent, float *target) {
     target[4 * k + 2] = s.tpsi[k];
     target[4 * k + 3] = s.tv[k];
   }
+}
+
+// Every tracker's window (entry 0 = newest) with its env's range-noise std
+// and the true target position: one thread per env.
+__global__ void env_windows_kernel(DevState s, int32_t W, float *win, float *sigma, float *truth) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= s.E) return;
+  const int na = s.cnt_a[e], nt = s.cnt_t[e];
+  const int64_t ab = s.aoff[e], tb = s.toff[e], pb = s.poff[e];
+  for (int i = 0; i < na; ++i) {
+    for (int j = 0; j < nt; ++j) {
+      const int64_t p = pb + (int64_t)i * nt + j;
+      float *w = win + p * W * 3;
+      for (int k = 0; k < W; ++k) {
+        w[3 * k] = s.hx[(int64_t)k * s.A + ab + i];
+        w[3 * k + 1] = s.hy[(int64_t)k * s.A + ab + i];
+        w[3 * k + 2] = s.hr[(int64_t)k * s.P + p];
+      }
+      if (sigma) sigma[p] = s.sigma[e];
+      if (truth) {
+        truth[2 * p] = s.tx[tb + j];
+        truth[2 * p + 1] = s.ty[tb + j];
+      }
+    }
+  }
+}
+
+int launch_env_windows(const DevState &s, int32_t W, float *win, float *sigma, float *truth,
+                       void *stream) {
+  const int bs = 128;
+  hipLaunchKernelGGL(env_windows_kernel, dim3((unsigned)((s.E + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, s, W, win, sigma, truth);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 // ---------------------------------------------------------------------------

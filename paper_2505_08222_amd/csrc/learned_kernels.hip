@@ -1,0 +1,660 @@
+// Learned range-only estimator on gfx950: a 64 -> 128 -> 128 -> 2 MLP with
+// GELU (tanh form), BF16 operands on MFMA with FP32 accumulation (or FP32
+// operands on the FP32 MFMA, for gradient checks), trained by hand-written
+// forward/backward kernels and Adam; inference is fused with the window
+// features, a residual test against the measured ranges and a compacted
+// exact-LS fallback (arXiv 2505.08222, Sec. II-A, is the exact estimator it
+// stands in for).
+//
+// MFMA operand layout (16x16 output tile, lane l = 0..63): lane l supplies
+// row (l % 16) of A and column (l % 16) of B for the K-slice (l / 16), i.e.
+// 8 consecutive K for v_mfma_f32_16x16x32_bf16 and 1 for
+// v_mfma_f32_16x16x4_f32; it receives D rows 4 * (l / 16) + j, column l % 16.
+// Both operands are therefore read K-contiguous: A as [m][k], B as [n][k].
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <math.h>
+
+#include "learned_internal.h"
+#include "ls_device.h"
+#include "rng.h"
+
+namespace mil {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float gelu_f(float x) {
+  const float c = 0.7978845608028654f;
+  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  const float c = 0.7978845608028654f;
+  const float th = tanhf(c * (x + 0.044715f * x * x * x));
+  const float du = c * (1.0f + 3.0f * 0.044715f * x * x);
+  return 0.5f * (1.0f + th) + 0.5f * x * (1.0f - th * th) * du;
+}
+
+template <typename T>
+__device__ __forceinline__ T to_t(float v);
+template <>
+__device__ __forceinline__ __bf16 to_t<__bf16>(float v) {
+  return __float2bfloat16(v);
+}
+template <>
+__device__ __forceinline__ float to_t<float>(float v) {
+  return v;
+}
+__device__ __forceinline__ float to_f(__bf16 v) { return __bfloat162float(v); }
+__device__ __forceinline__ float to_f(float v) { return v; }
+
+// Block-cooperative GEMM: D[m][n] = sum_k A[m][k] B[n][k] for an M x N
+// output in 16 x 16 tiles spread over the block's wavefronts; `epi(m, n, v)`
+// consumes every output. A, B are K-contiguous with row strides lda, ldb.
+template <typename T, typename Epi>
+__device__ __forceinline__ void block_gemm(const T *A, int lda, const T *B, int ldb, int M, int N,
+                                           int K, Epi epi) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int tn = N >> 4, tiles = (M >> 4) * tn;
+  const int row = lane & 15, kg = lane >> 4;
+  for (int t = wave; t < tiles; t += nw) {
+    const int m0 = (t / tn) << 4, n0 = (t % tn) << 4;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (sizeof(T) == 2) {
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + (m0 + row) * lda + k0 + 8 * kg);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(B + (n0 + row) * ldb + k0 + 8 * kg);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+      }
+    } else {
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const float a = A[(m0 + row) * lda + k0 + kg];
+        const float b = B[(n0 + row) * ldb + k0 + kg];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) epi(m0 + 4 * kg + j, n0 + row, acc[j]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weights in MFMA-ready form: W1 [128][64], W2 [128][128] and W2^T in the
+// operand type, with rows padded to LDP = K + 8 elements (16 B) so that a
+// lane's 8 consecutive K are 16-byte aligned.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void prepare_weights_kernel(const float *__restrict__ th, T *__restrict__ w1,
+                                       T *__restrict__ w2, T *__restrict__ w2t) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < kHidden * kIn) {
+    const int o = k / kIn, i = k % kIn;
+    w1[o * kLdIn + i] = to_t<T>(th[kOffW1 + k]);
+  }
+  if (k < kHidden * kHidden) {
+    const int o = k / kHidden, i = k % kHidden;
+    const T v = to_t<T>(th[kOffW2 + k]);
+    w2[o * kLdH + i] = v;
+    w2t[i * kLdH + o] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Features of one window (entry order as stored; all entries present):
+// centroid frame rotated so x runs along the chord a_0 - a_{W-1}.
+// ---------------------------------------------------------------------------
+constexpr int kMaxW = (kIn - 1) / 3;  // 21 entries fit the 64 inputs
+
+__device__ __forceinline__ bool window_features(const float *w, int W, float (&x)[kIn],
+                                                float (&frame)[5]) {
+  float mx = 0.f, my = 0.f, mr = 0.f;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < kMaxW; ++k) {
+    if (k < W) {
+      mx += w[3 * k];
+      my += w[3 * k + 1];
+      const float r = w[3 * k + 2];
+      ok = ok && (r == r);
+      mr += r;
+    }
+  }
+  const float invw = 1.0f / (float)W;
+  mx *= invw;
+  my *= invw;
+  mr *= invw;
+  const float cx = w[0] - w[3 * (W - 1)], cy = w[1] - w[3 * (W - 1) + 1];
+  const float len = sqrtf(cx * cx + cy * cy);
+  float c = 1.0f, s = 0.0f;
+  if (len > 1e-6f) {
+    c = cx / len;
+    s = cy / len;
+  }
+#pragma unroll
+  for (int i = 0; i < kIn; ++i) x[i] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMaxW; ++k) {
+    if (k < W) {
+      const float dx = w[3 * k] - mx, dy = w[3 * k + 1] - my;
+      x[3 * k] = (c * dx + s * dy) * 0.1f;
+      x[3 * k + 1] = (-s * dx + c * dy) * 0.1f;
+      x[3 * k + 2] = (w[3 * k + 2] - mr) * 0.1f;
+    } else if (k == W) {
+      x[3 * k] = mr * 1e-3f;
+    }
+  }
+  if (W == kMaxW) x[3 * kMaxW] = mr * 1e-3f;
+  frame[0] = mx;
+  frame[1] = my;
+  frame[2] = c;
+  frame[3] = s;
+  frame[4] = mr;
+  return ok;
+}
+
+__global__ void features_kernel(const float *__restrict__ win, int64_t N, int32_t W,
+                                float *__restrict__ xout, float *__restrict__ frame) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float x[kIn], fr[5];
+  window_features(win + n * W * 3, W, x, fr);
+  float4 *xo = reinterpret_cast<float4 *>(xout + n * kIn);
+#pragma unroll
+  for (int q = 0; q < kIn / 4; ++q) xo[q] = make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) frame[n * 5 + q] = fr[q];
+}
+
+// y_target = R(-theta)(p - abar) / rbar
+__global__ void targets_kernel(const float *__restrict__ frame, const float *__restrict__ p,
+                               int64_t N, float *__restrict__ y) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const float *fr = frame + n * 5;
+  const float dx = p[2 * n] - fr[0], dy = p[2 * n + 1] - fr[1];
+  y[2 * n] = (fr[2] * dx + fr[3] * dy) / fr[4];
+  y[2 * n + 1] = (-fr[3] * dx + fr[2] * dy) / fr[4];
+}
+
+// ---------------------------------------------------------------------------
+// Training step on a tile of S samples: forward, squared-error gradient,
+// backward; writes this block's partial gradient (FP32) and loss.
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+struct TrainLds {
+  T x[S][kIn + 8];           // X
+  T xt[kIn][S + 8];          // X^T
+  float z1[S][kHidden];      // pre-activations
+  T h1[S][kHidden + 8];      // gelu(z1)
+  T h1t[kHidden][S + 8];
+  float z2[S][kHidden];
+  T h2[S][kHidden + 8];      // gelu(z2), later dZ2
+  T dz2t[kHidden][S + 8];
+  T dz1t[kHidden][S + 8];
+  float y[S][2];
+  float dy[S][2];
+};
+
+template <typename T, int S>
+__global__ void __launch_bounds__(256)
+train_tile_kernel(int64_t N, const float *__restrict__ xin, const int64_t *__restrict__ index,
+                  const float *__restrict__ target, const float *__restrict__ th,
+                  const T *__restrict__ w1, const T *__restrict__ w2,
+                  const T *__restrict__ w2t, float *__restrict__ partial,
+                  float *__restrict__ loss_partial, float inv_n) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TrainLds<T, S> &L = *reinterpret_cast<TrainLds<T, S> *>(smem);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t s0 = (int64_t)blockIdx.x * S;
+  // ---- load X (and X^T) for the tile; rows past N are zero
+  for (int e = tid; e < S * kIn; e += nthr) {
+    const int s = e / kIn, i = e % kIn;
+    float v = 0.0f;
+    if (s0 + s < N) {
+      const int64_t src = index ? index[s0 + s] : s0 + s;
+      v = xin[src * kIn + i];
+    }
+    L.x[s][i] = to_t<T>(v);
+    L.xt[i][s] = to_t<T>(v);
+  }
+  __syncthreads();
+  // ---- layer 1
+  block_gemm<T>(&L.x[0][0], kIn + 8, w1, kLdIn, S, kHidden, kIn, [&](int m, int n, float v) {
+    const float z = v + th[kOffB1 + n];
+    L.z1[m][n] = z;
+    const T h = to_t<T>(gelu_f(z));
+    L.h1[m][n] = h;
+    L.h1t[n][m] = h;
+  });
+  __syncthreads();
+  // ---- layer 2
+  block_gemm<T>(&L.h1[0][0], kHidden + 8, w2, kLdH, S, kHidden, kHidden,
+                [&](int m, int n, float v) {
+                  const float z = v + th[kOffB2 + n];
+                  L.z2[m][n] = z;
+                  L.h2[m][n] = to_t<T>(gelu_f(z));
+                });
+  __syncthreads();
+  // ---- layer 3 (two outputs) and the loss gradient
+  if (tid < 2 * S) {
+    const int s = tid >> 1, o = tid & 1;
+    float acc = th[kOffB3 + o];
+    for (int i = 0; i < kHidden; ++i) acc += th[kOffW3 + o * kHidden + i] * to_f(L.h2[s][i]);
+    L.y[s][o] = acc;
+    float d = 0.0f;
+    if (s0 + s < N) {
+      const int64_t src = index ? index[s0 + s] : s0 + s;
+      d = acc - target[src * 2 + o];
+    }
+    L.dy[s][o] = 2.0f * d * inv_n;
+    L.y[s][o] = d * d;  // reuse: squared error
+  }
+  __syncthreads();
+  float *gp = partial + (int64_t)blockIdx.x * kNumParams;
+  if (tid == 0) {
+    float l = 0.0f;
+    for (int s = 0; s < S; ++s) l += L.y[s][0] + L.y[s][1];
+    loss_partial[blockIdx.x] = l;
+  }
+  // dW3, db3
+  for (int e = tid; e < 2 * kHidden; e += nthr) {
+    const int o = e / kHidden, i = e % kHidden;
+    float acc = 0.0f;
+    for (int s = 0; s < S; ++s) acc += L.dy[s][o] * to_f(L.h2[s][i]);
+    gp[kOffW3 + e] = acc;
+  }
+  if (tid < 2) {
+    float acc = 0.0f;
+    for (int s = 0; s < S; ++s) acc += L.dy[s][tid];
+    gp[kOffB3 + tid] = acc;
+  }
+  __syncthreads();
+  // dZ2 = (dY W3) * gelu'(Z2), written over h2 and transposed into dz2t
+  for (int e = tid; e < S * kHidden; e += nthr) {
+    const int s = e / kHidden, i = e % kHidden;
+    const float dh = L.dy[s][0] * th[kOffW3 + i] + L.dy[s][1] * th[kOffW3 + kHidden + i];
+    const T d = to_t<T>(dh * gelu_grad_f(L.z2[s][i]));
+    L.h2[s][i] = d;
+    L.dz2t[i][s] = d;
+  }
+  __syncthreads();
+  // db2
+  for (int o = tid; o < kHidden; o += nthr) {
+    float acc = 0.0f;
+    for (int s = 0; s < S; ++s) acc += to_f(L.dz2t[o][s]);
+    gp[kOffB2 + o] = acc;
+  }
+  // dW2[o][i] = sum_s dZ2[s][o] H1[s][i]
+  block_gemm<T>(&L.dz2t[0][0], S + 8, &L.h1t[0][0], S + 8, kHidden, kHidden, S,
+                [&](int m, int n, float v) { gp[kOffW2 + m * kHidden + n] = v; });
+  // dH1 = dZ2 W2 (B operand = W2^T rows), dZ1 = dH1 * gelu'(Z1)
+  block_gemm<T>(&L.h2[0][0], kHidden + 8, w2t, kLdH, S, kHidden, kHidden,
+                [&](int m, int n, float v) { L.dz1t[n][m] = to_t<T>(v * gelu_grad_f(L.z1[m][n])); });
+  __syncthreads();
+  for (int o = tid; o < kHidden; o += nthr) {
+    float acc = 0.0f;
+    for (int s = 0; s < S; ++s) acc += to_f(L.dz1t[o][s]);
+    gp[kOffB1 + o] = acc;
+  }
+  // dW1[o][i] = sum_s dZ1[s][o] X[s][i]
+  block_gemm<T>(&L.dz1t[0][0], S + 8, &L.xt[0][0], S + 8, kHidden, kIn, S,
+                [&](int m, int n, float v) { gp[kOffW1 + m * kIn + n] = v; });
+}
+
+// Deterministic sum of the per-block partial gradients and losses.
+__global__ void reduce_grad_kernel(const float *__restrict__ partial, int nblocks,
+                                   float *__restrict__ grad, const float *__restrict__ loss_partial,
+                                   float *__restrict__ loss, float inv_n) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < kNumParams) {
+    float acc = 0.0f;
+    for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * kNumParams + p];
+    grad[p] = acc;
+  }
+  if (p == 0 && loss) {
+    double l = 0.0;
+    for (int b = 0; b < nblocks; ++b) l += loss_partial[b];
+    *loss = (float)(l * inv_n);
+  }
+}
+
+// Adam (Kingma and Ba) with bias correction; step counts from 1.
+__global__ void adam_kernel(int64_t P, float *__restrict__ th, const float *__restrict__ g,
+                            float *__restrict__ m, float *__restrict__ v, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Forward only (training evaluation): tile of 64 samples per block.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FwdLds {
+  T x[64][kIn + 8];
+  T h1[64][kHidden + 8];
+  T h2[64][kHidden + 8];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict__ th,
+               const T *__restrict__ w1, const T *__restrict__ w2, float *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FwdLds<T> &L = *reinterpret_cast<FwdLds<T> *>(smem);
+  const int tid = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < 64 * kIn; e += blockDim.x) {
+    const int s = e / kIn, i = e % kIn;
+    L.x[s][i] = to_t<T>(s0 + s < N ? xin[(s0 + s) * kIn + i] : 0.0f);
+  }
+  __syncthreads();
+  block_gemm<T>(&L.x[0][0], kIn + 8, w1, kLdIn, 64, kHidden, kIn, [&](int m, int n, float v) {
+    L.h1[m][n] = to_t<T>(gelu_f(v + th[kOffB1 + n]));
+  });
+  __syncthreads();
+  block_gemm<T>(&L.h1[0][0], kHidden + 8, w2, kLdH, 64, kHidden, kHidden,
+                [&](int m, int n, float v) { L.h2[m][n] = to_t<T>(gelu_f(v + th[kOffB2 + n])); });
+  __syncthreads();
+  if (tid < 128) {
+    const int s = tid >> 1, o = tid & 1;
+    float acc = th[kOffB3 + o];
+    for (int i = 0; i < kHidden; ++i) acc += th[kOffW3 + o * kHidden + i] * to_f(L.h2[s][i]);
+    if (s0 + s < N) y[(s0 + s) * 2 + o] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: persistent blocks keep the BF16 weights in LDS and loop over
+// tiles of 64 windows: features -> MLP -> decode -> residual test. Windows
+// failing the test (or with missing entries) are appended to a list that the
+// fallback kernel solves exactly.
+// ---------------------------------------------------------------------------
+struct InferLds {
+  __bf16 w1[kHidden][kLdIn];
+  __bf16 w2[kHidden][kLdH];
+  float w3[2][kHidden];
+  float b1[kHidden], b2[kHidden], b3[4];  // b3 padded: keeps x 16-byte aligned
+  __bf16 x[64][kIn + 8];
+  __bf16 h1[64][kHidden + 8];
+  __bf16 h2[64][kHidden + 8];
+  float frame[64][5];
+  float ypart[64][2][4];
+  int ok[64];
+};
+
+static_assert(offsetof(InferLds, x) % 16 == 0, "MFMA operands need 16-byte rows");
+static_assert(offsetof(InferLds, h1) % 16 == 0, "MFMA operands need 16-byte rows");
+static_assert(sizeof(InferLds) <= 160 * 1024, "LDS");
+
+__global__ void __launch_bounds__(256)
+infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *__restrict__ th,
+             const __bf16 *__restrict__ w1g, const __bf16 *__restrict__ w2g,
+             const float *__restrict__ sigma, float k_sigma, float *__restrict__ out,
+             uint8_t *__restrict__ flag, int32_t *__restrict__ fb_count,
+             int32_t *__restrict__ fb_list) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  InferLds &L = *reinterpret_cast<InferLds *>(smem);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kHidden * kLdIn; e += blockDim.x) (&L.w1[0][0])[e] = w1g[e];
+  for (int e = tid; e < kHidden * kLdH; e += blockDim.x) (&L.w2[0][0])[e] = w2g[e];
+  for (int e = tid; e < 2 * kHidden; e += blockDim.x) (&L.w3[0][0])[e] = th[kOffW3 + e];
+  for (int e = tid; e < kHidden; e += blockDim.x) {
+    L.b1[e] = th[kOffB1 + e];
+    L.b2[e] = th[kOffB2 + e];
+  }
+  if (tid < 2) L.b3[tid] = th[kOffB3 + tid];
+  __syncthreads();
+  const int64_t ntiles = (N + 63) / 64;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t s0 = tile * 64;
+    // features: thread s < 64 takes window s0 + s
+    if (tid < 64) {
+      float x[kIn], fr[5];
+      int ok = 0;
+      if (s0 + tid < N) ok = window_features(win + (s0 + tid) * W * 3, W, x, fr) ? 1 : 0;
+      else {
+        for (int i = 0; i < kIn; ++i) x[i] = 0.0f;
+        fr[0] = fr[1] = fr[3] = 0.0f;
+        fr[2] = fr[4] = 1.0f;
+      }
+      for (int i = 0; i < kIn; ++i) L.x[tid][i] = __float2bfloat16(x[i]);
+      for (int q = 0; q < 5; ++q) L.frame[tid][q] = fr[q];
+      L.ok[tid] = ok;
+    }
+    __syncthreads();
+    block_gemm<__bf16>(&L.x[0][0], kIn + 8, &L.w1[0][0], kLdIn, 64, kHidden, kIn,
+                       [&](int m, int n, float v) { L.h1[m][n] = __float2bfloat16(gelu_f(v + L.b1[n])); });
+    __syncthreads();
+    block_gemm<__bf16>(&L.h1[0][0], kHidden + 8, &L.w2[0][0], kLdH, 64, kHidden, kHidden,
+                       [&](int m, int n, float v) { L.h2[m][n] = __float2bfloat16(gelu_f(v + L.b2[n])); });
+    __syncthreads();
+    {  // layer 3: four threads per (window, output), 32 inputs each
+      const int s = tid >> 2, part = tid & 3;
+      float acc[2] = {0.0f, 0.0f};
+      for (int i = part * 32; i < part * 32 + 32; ++i) {
+        const float h = __bfloat162float(L.h2[s][i]);
+        acc[0] += L.w3[0][i] * h;
+        acc[1] += L.w3[1][i] * h;
+      }
+      L.ypart[s][0][part] = acc[0];
+      L.ypart[s][1][part] = acc[1];
+    }
+    __syncthreads();
+    if (tid < 64 && s0 + tid < N) {
+      const int64_t n = s0 + tid;
+      const float y0 = L.b3[0] + ((L.ypart[tid][0][0] + L.ypart[tid][0][1]) +
+                                  (L.ypart[tid][0][2] + L.ypart[tid][0][3]));
+      const float y1 = L.b3[1] + ((L.ypart[tid][1][0] + L.ypart[tid][1][1]) +
+                                  (L.ypart[tid][1][2] + L.ypart[tid][1][3]));
+      const float *fr = L.frame[tid];
+      const float ux = fr[4] * y0, uy = fr[4] * y1;
+      const float px = fr[0] + fr[2] * ux - fr[3] * uy;
+      const float py = fr[1] + fr[3] * ux + fr[2] * uy;
+      bool accept = false;
+      if (L.ok[tid]) {
+        const float *w = win + n * W * 3;
+        float acc = 0.0f;
+        for (int k = 0; k < W; ++k) {
+          const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
+          const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
+          acc += res * res;
+        }
+        const float rms = sqrtf(acc / (float)W);
+        accept = rms <= k_sigma * sigma[n];
+      }
+      if (accept) {
+        out[2 * n] = px;
+        out[2 * n + 1] = py;
+        flag[n] = 1;
+      } else {
+        const int slot = atomicAdd(fb_count, 1);
+        fb_list[slot] = (int32_t)n;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int WC>
+__global__ void fallback_kernel(const float *__restrict__ win, int32_t W,
+                                const int32_t *__restrict__ fb_count,
+                                const int32_t *__restrict__ fb_list, int32_t gn_iters, float tau,
+                                float *__restrict__ out, uint8_t *__restrict__ flag) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= *fb_count) return;
+  const int64_t n = fb_list[idx];
+  const float *w = win + n * W * 3;
+  float hx[WC], hy[WC], hr[WC];
+#pragma unroll
+  for (int k = 0; k < WC; ++k) {
+    const bool in = k < W;
+    hx[k] = in ? w[3 * k] : 0.f;
+    hy[k] = in ? w[3 * k + 1] : 0.f;
+    hr[k] = in ? w[3 * k + 2] : __int_as_float(0x7fc00000);
+  }
+  double px = 0.0, py = 0.0;
+  const bool ok = ls_masked<WC>(hx, hy, hr, W, gn_iters, (double)tau, px, py);
+  out[2 * n] = ok ? (float)px : 0.0f;
+  out[2 * n + 1] = ok ? (float)py : 0.0f;
+  flag[n] = ok ? 0 : 2;
+}
+
+__global__ void zero_i32_kernel(int32_t *p) { *p = 0; }
+
+// Glorot-uniform init: weight (o, i) of a layer with fan_in + fan_out = f
+// is a * (2u - 1), a = sqrt(6 / f), u from Philox(counter = (index, 0, 0,
+// kPurposeMlpInit)); biases 0.
+__global__ void init_kernel(float *th, uint32_t k0, uint32_t k1) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNumParams) return;
+  float a = 0.0f;
+  if (p < kOffB1) a = sqrtf(6.0f / (kIn + kHidden));
+  else if (p >= kOffW2 && p < kOffB2) a = sqrtf(6.0f / (kHidden + kHidden));
+  else if (p >= kOffW3 && p < kOffB3) a = sqrtf(6.0f / (kHidden + kOut));
+  const u32x4 x = philox4x32_10((uint32_t)p, 0u, 0u, kPurposeMlpInit, k0, k1);
+  th[p] = a * (2.0f * u01(x.x) - 1.0f);
+}
+
+int launch_init(float *th, uint64_t seed, void *stream) {
+  hipLaunchKernelGGL(init_kernel, dim3((kNumParams + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, th, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int ok_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+// Dynamic LDS above 64 KB has to be requested per kernel (gfx950 has 160 KB).
+static int allow_lds(const void *kernel, size_t bytes) {
+  if (bytes <= 65536) return 0;
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+                 hipSuccess ? 0 : -1;
+}
+
+int launch_prepare(const float *th, int precision, void *prep, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int n = kHidden * kHidden, bs = 256;
+  if (precision == 0) {
+    __bf16 *w1 = (__bf16 *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
+    hipLaunchKernelGGL(prepare_weights_kernel<__bf16>, dim3((n + bs - 1) / bs), dim3(bs), 0, st,
+                       th, w1, w2, w2t);
+  } else {
+    float *w1 = (float *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
+    hipLaunchKernelGGL(prepare_weights_kernel<float>, dim3((n + bs - 1) / bs), dim3(bs), 0, st,
+                       th, w1, w2, w2t);
+  }
+  return ok_launch();
+}
+
+int launch_features(const float *win, int64_t N, int32_t W, float *x, float *frame, void *stream) {
+  if (N <= 0) return 0;
+  const int bs = 128;
+  hipLaunchKernelGGL(features_kernel, dim3((unsigned)((N + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, win, N, W, x, frame);
+  return ok_launch();
+}
+
+int launch_targets(const float *frame, const float *p, int64_t N, float *y, void *stream) {
+  if (N <= 0) return 0;
+  const int bs = 256;
+  hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((N + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, frame, p, N, y);
+  return ok_launch();
+}
+
+int launch_forward(int64_t N, const float *x, const float *th, int precision, const void *prep,
+                   float *y, void *stream) {
+  if (N <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned blocks = (unsigned)((N + 63) / 64);
+  if (precision == 0) {
+    const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn;
+    if (allow_lds((const void *)forward_kernel<__bf16>, sizeof(FwdLds<__bf16>))) return -1;
+    hipLaunchKernelGGL(forward_kernel<__bf16>, dim3(blocks), dim3(256), sizeof(FwdLds<__bf16>),
+                       st, N, x, th, w1, w2, y);
+  } else {
+    const float *w1 = (const float *)prep, *w2 = w1 + kHidden * kLdIn;
+    if (allow_lds((const void *)forward_kernel<float>, sizeof(FwdLds<float>))) return -1;
+    hipLaunchKernelGGL(forward_kernel<float>, dim3(blocks), dim3(256), sizeof(FwdLds<float>), st,
+                       N, x, th, w1, w2, y);
+  }
+  return ok_launch();
+}
+
+int64_t train_blocks(int64_t N, int precision) {
+  const int S = precision == 0 ? kTileBf16 : kTileF32;
+  return (N + S - 1) / S;
+}
+
+int launch_train(int64_t N, const float *x, const int64_t *index, const float *target,
+                 const float *th, int precision, const void *prep, float *partial,
+                 float *loss_partial, float *grad, float *loss, void *stream) {
+  if (N <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nb = train_blocks(N, precision);
+  const float inv_n = 1.0f / (float)N;
+  if (precision == 0) {
+    const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
+    if (allow_lds((const void *)train_tile_kernel<__bf16, kTileBf16>,
+                  sizeof(TrainLds<__bf16, kTileBf16>)))
+      return -1;
+    hipLaunchKernelGGL((train_tile_kernel<__bf16, kTileBf16>), dim3((unsigned)nb), dim3(256),
+                       sizeof(TrainLds<__bf16, kTileBf16>), st, N, x, index, target, th, w1, w2,
+                       w2t, partial, loss_partial, inv_n);
+  } else {
+    const float *w1 = (const float *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
+    if (allow_lds((const void *)train_tile_kernel<float, kTileF32>, sizeof(TrainLds<float, kTileF32>)))
+      return -1;
+    hipLaunchKernelGGL((train_tile_kernel<float, kTileF32>), dim3((unsigned)nb), dim3(256),
+                       sizeof(TrainLds<float, kTileF32>), st, N, x, index, target, th, w1, w2,
+                       w2t, partial, loss_partial, inv_n);
+  }
+  if (ok_launch()) return -1;
+  hipLaunchKernelGGL(reduce_grad_kernel, dim3((kNumParams + 255) / 256), dim3(256), 0, st,
+                     partial, (int)nb, grad, loss_partial, loss, inv_n);
+  return ok_launch();
+}
+
+int launch_adam(int64_t P, float *th, const float *g, float *m, float *v, float lr, float b1,
+                float b2, float eps, int32_t step, void *stream) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  const int bs = 256;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((P + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, P, th, g, m, v, lr, b1, b2, eps, c1, c2);
+  return ok_launch();
+}
+
+int launch_infer(const float *win, int64_t N, int32_t W, const float *th, const void *prep,
+                 const float *sigma, float k_sigma, int32_t gn_iters, float tau, float *out,
+                 uint8_t *flag, int32_t *fb_count, int32_t *fb_list, int num_cus, void *stream) {
+  if (N <= 0) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn;
+  if (allow_lds((const void *)infer_kernel, sizeof(InferLds))) return -1;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, fb_count);
+  const int64_t ntiles = (N + 63) / 64;
+  const unsigned grid = (unsigned)(ntiles < (int64_t)num_cus ? ntiles : num_cus);
+  hipLaunchKernelGGL(infer_kernel, dim3(grid), dim3(256), sizeof(InferLds), st, win, N, W, th, w1,
+                     w2, sigma, k_sigma, out, flag, fb_count, fb_list);
+  if (ok_launch()) return -1;
+  const unsigned fb_blocks = (unsigned)((N + 255) / 256);
+  if (W <= 16)
+    hipLaunchKernelGGL(fallback_kernel<16>, dim3(fb_blocks), dim3(256), 0, st, win, W, fb_count,
+                       fb_list, gn_iters, tau, out, flag);
+  else
+    hipLaunchKernelGGL(fallback_kernel<21>, dim3(fb_blocks), dim3(256), 0, st, win, W, fb_count,
+                       fb_list, gn_iters, tau, out, flag);
+  return ok_launch();
+}
+
+}  // namespace mil

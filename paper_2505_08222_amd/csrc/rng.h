@@ -67,6 +67,8 @@ enum : uint32_t {
   kPurposeReset = 2,
   kPurposeConfig = 3,
   kPurposePolicy = 4,
+  kPurposeMlpInit = 5,
+  kPurposePolicyInit = 6,
 };
 enum : uint32_t {
   kEntTargetBlock = 16,  // + j/2 for step draws, + j for reset draws
