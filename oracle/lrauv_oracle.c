@@ -66,6 +66,15 @@ void orc_normal2(uint32_t x0, uint32_t x1, double *z0, double *z1) {
 
 uint32_t orc_choice(uint32_t x, uint32_t n) { return (uint32_t)(((uint64_t)x * n) >> 32); }
 
+/* A heading is an angle: kept in [-pi, pi] after every update (one
+ * correction suffices, a step turns by far less than pi). */
+static double wrap_angle(double a) {
+  const double pi = 3.14159265358979323846;
+  if (a > pi) return a - 2.0 * pi;
+  if (a < -pi) return a + 2.0 * pi;
+  return a;
+}
+
 /* RNG counter words: (step or 0, global env id, entity code, purpose). */
 enum { PURPOSE_DYNAMICS = 0, PURPOSE_MEASURE = 1, PURPOSE_RESET = 2, PURPOSE_CONFIG = 3 };
 enum { ENT_TARGET_BLOCK = 16, ENT_RANGE_ROW = 64, ENT_ENV = 127 };
@@ -351,7 +360,7 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
     double z0, z1;
     orc_normal2(x[1], x[2], &z0, &z1);
     double dpsi = (a >= 0) ? p->action_dpsi[a] : 0.0;
-    E->apsi[i] = E->apsi[i] + dpsi + p->agent_heading_sigma * z0;
+    E->apsi[i] = wrap_angle(E->apsi[i] + dpsi + p->agent_heading_sigma * z0);
     E->ax[i] = E->ax[i] + vdt * cos(E->apsi[i]);
     E->ay[i] = E->ay[i] + vdt * sin(E->apsi[i]);
     E->comm_ok[i] = !(orc_u01(x[3]) < p->comm_loss_p);
@@ -365,7 +374,7 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
     for (int m = 0; m < 2; ++m) {
       int j = 2 * q + m;
       if (j >= E->nT) break;
-      E->tpsi[j] = E->tpsi[j] + p->target_heading_sigma * z[m];
+      E->tpsi[j] = wrap_angle(E->tpsi[j] + p->target_heading_sigma * z[m]);
       E->tx[j] = E->tx[j] + E->tv[j] * p->dt * cos(E->tpsi[j]);
       E->ty[j] = E->ty[j] + E->tv[j] * p->dt * sin(E->tpsi[j]);
     }

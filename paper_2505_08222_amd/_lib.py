@@ -112,21 +112,26 @@ def lib():
 
 
 def _register_learned(L):
-    """Declare the learned-part entry points (MLP estimator, policy)."""
-    V, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    """Declare the learned-part entry points (MLP estimator, env windows)."""
+    V, I32, I64, U64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float
     table = {
-        "mlp_forward": [I64, V, V, V, V, I32, V],
-        "mlp_backward": [I64, V, V, V, V, V, V, V],
-        "mlp_adam_step": [I64, V, V, V, V, V, C.c_float, C.c_float, C.c_float, C.c_float, I32, V],
+        "mlp_init": [V, U64, V],
         "mlp_features": [V, I64, I32, V, V, V],
-        "mlp_infer": [V, I64, I32, V, V, C.c_float, V, V, V, V],
-        "policy_forward": [I64, I32, V, V, V, V, V],
+        "mlp_targets": [V, V, I64, V, V],
+        "mlp_forward": [I64, V, V, V, I32, V, I64, V],
+        "mlp_backward": [I64, V, V, V, V, V, V, I32, V, I64, V],
+        "mlp_adam_step": [I64, V, V, V, V, F, F, F, F, I32, V],
+        "mlp_infer": [V, I64, I32, V, V, F, I32, F, V, V, V, I64, V],
+        "env_windows": [V, V, V, V, V],
     }
     for name, args in table.items():
-        if hasattr(L, name):
-            f = getattr(L, name)
-            f.argtypes = args
-            f.restype = C.c_int
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.mlp_num_params.argtypes = []
+    L.mlp_num_params.restype = I64
+    L.mlp_workspace_bytes.argtypes = [I64, I32]
+    L.mlp_workspace_bytes.restype = I64
 
 
 def check(rc: int):

@@ -19,6 +19,9 @@ def _flags(version: str):
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # packed FP32 (v_pk_*_f32) stays off: all FP32 math is scalar VALU
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # no implicit FMA contraction: fused multiply-adds are written out,
+            # so every template instantiation (lane mapping) rounds identically
+            "-ffp-contract=off",
             "-I", INCLUDE, "-I", CSRC, f'-DMIL_CODE_VERSION="{version}"',
             "-Wno-unused-command-line-argument"]
 

@@ -46,6 +46,16 @@ __device__ __forceinline__ float tracking_reward(float e, float emin, float emax
   return expf(-2.0f * t / (1.0f - t));
 }
 
+// A heading is an angle: kept in [-pi, pi] after every update.
+__device__ __forceinline__ float wrap_angle(float a) {
+  const float pi = 3.14159265358979f, two_pi = 6.28318530717959f;
+  if (a > pi) return a - two_pi;
+  if (a < -pi) return a + two_pi;
+  return a;
+}
+
+__device__ __forceinline__ float norm2(float dx, float dy) { return sqrtf(fmaf(dx, dx, dy * dy)); }
+
 __device__ __forceinline__ void store_token(float *dst, float dx, float dy, float is_self,
                                             float is_agent, float is_target) {
   float2 *d = reinterpret_cast<float2 *>(dst);
@@ -140,7 +150,7 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
     for (int k = 0; k < na; ++k) {
       if (k == i) continue;
       const float dx = s.ax[ab + k] - ax, dy = s.ay[ab + k] - ay;
-      const bool ok = sqrtf(dx * dx + dy * dy) <= p.comm_range;
+      const bool ok = norm2(dx, dy) <= p.comm_range;
       if (o.obs) store_token(o.obs + (kb + m) * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
       if (o.obs_mask) o.obs_mask[kb + m] = ok;
       ++m;
@@ -270,12 +280,12 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       if (act == q) dpsi = p.dpsi[q];
-    apsi = (apsi + dpsi) + p.sig_a * za;
+    apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
     {
       float sn, cs;
       sincosf(apsi, &sn, &cs);
-      ax = ax + vdt * cs;
-      ay = ay + vdt * sn;
+      ax = fmaf(vdt, cs, ax);
+      ay = fmaf(vdt, sn, ay);
     }
     const bool comm_ok = !(u01(xa.w) < p.comm_loss_p);
 
@@ -290,12 +300,12 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
         const int j = 2 * q + m;
         if (j < nt) {
           float4 tg = tl[j];
-          tg.z = tg.z + p.sig_t * zt[m];
+          tg.z = wrap_angle(tg.z + p.sig_t * zt[m]);
           float sn, cs;
           sincosf(tg.z, &sn, &cs);
           const float step_len = tg.w * p.dt;
-          tg.x = tg.x + step_len * cs;
-          tg.y = tg.y + step_len * sn;
+          tg.x = fmaf(step_len, cs, tg.x);
+          tg.y = fmaf(step_len, sn, tg.y);
           tl[j] = tg;
         }
       }
@@ -330,9 +340,8 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
         for (int m = 0; m < 4; ++m) {
           const int j = 4 * q4 + m;
           if (j < MT && j < nt && (j % G) == g) {
-            const float dx = ax - tpx[j], dy = ay - tpy[j];
-            const float dist = sqrtf(dx * dx + dy * dy);
-            const float rr = dist + sig_r * zr[m];
+            const float dist = norm2(ax - tpx[j], ay - tpy[j]);
+            const float rr = fmaf(sig_r, zr[m], dist);
             rnew[j / G] = (dist <= p.det_range) ? rr : kNaN;
           }
         }
@@ -384,22 +393,22 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
       for (int k = 0; k < WC; ++k) {
         if (k < filled) {
           const double ux = (double)hx[k] - mx, uy = (double)hy[k] - my;
-          const double nu = ux * ux + uy * uy;
-          sxx += ux * ux;
-          sxy += ux * uy;
-          syy += uy * uy;
+          const double nu = fma(ux, ux, uy * uy);
+          sxx = fma(ux, ux, sxx);
+          sxy = fma(ux, uy, sxy);
+          syy = fma(uy, uy, syy);
 #pragma unroll
           for (int sl = 0; sl < NPL; ++sl) {
             const float rk = hr[sl][k];
             full[sl] = full[sl] && (rk == rk);
             const double rr = (double)rk;
-            const double c = nu - rr * rr;
-            gx[sl] += ux * c;
-            gy[sl] += uy * c;
+            const double c = fma(-rr, rr, nu);
+            gx[sl] = fma(ux, c, gx[sl]);
+            gy[sl] = fma(uy, c, gy[sl]);
           }
         }
       }
-      const double det = sxx * syy - sxy * sxy, tr = sxx + syy;
+      const double det = fma(sxx, syy, -sxy * sxy), tr = sxx + syy;
       const bool agent_ok = det > tau * tr * tr;
       const double hdet = agent_ok ? 0.5 / det : 0.0;
 #pragma unroll
@@ -408,8 +417,8 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
         if (j < nt) {
           if (full[sl] && p.gn_iters == 0) {
             if (agent_ok) {
-              ex[sl] = (float)(mx + hdet * (syy * gx[sl] - sxy * gy[sl]));
-              ey[sl] = (float)(my + hdet * (sxx * gy[sl] - sxy * gx[sl]));
+              ex[sl] = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
+              ey[sl] = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
               evb |= 1u << sl;
             }
           } else {
@@ -450,8 +459,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
       const int j = g + G * sl;
       errp[sl] = kInf;
       if (j < nt && ((evb >> sl) & 1u)) {
-        const float dx = ex[sl] - pick<G>(tpx, g, sl), dy = ey[sl] - pick<G>(tpy, g, sl);
-        errp[sl] = sqrtf(dx * dx + dy * dy);
+        errp[sl] = norm2(ex[sl] - pick<G>(tpx, g, sl), ey[sl] - pick<G>(tpy, g, sl));
       }
     }
     // ---- team error per target (best tracker), Eq. (1), normalisation
@@ -491,8 +499,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
 #pragma unroll
       for (int k2 = k + 1; k2 < MA; ++k2)
         if (k2 < na) {
-          const float dx = agx[k] - agx[k2], dy = agy[k] - agy[k2];
-          crash = crash || (sqrtf(dx * dx + dy * dy) < p.d_safe);
+          crash = crash || (norm2(agx[k] - agx[k2], agy[k] - agy[k2]) < p.d_safe);
         }
     if (crash) rew = -1.0f;
     const bool done = (t + 1u == (uint32_t)p.episode_len);
@@ -529,7 +536,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
             const float oy = before ? agy[m - 1] : agy[m];
             const int oc = before ? agc[m - 1] : agc[m];
             const float dx = ox - ax, dy = oy - ay;
-            const bool ok = oc && (sqrtf(dx * dx + dy * dy) <= p.comm_range);
+            const bool ok = oc && (norm2(dx, dy) <= p.comm_range);
             store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
             if (o.obs_mask) o.obs_mask[kb + m] = ok ? 1 : 0;
           }
@@ -554,8 +561,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
             const float ox = before ? agx[m - 1] : agx[m];
             const float oy = before ? agy[m - 1] : agy[m];
             const int oc = before ? agc[m - 1] : agc[m];
-            const float dx = ox - ax, dy = oy - ay;
-            o.obs_mask[kb + m] = (oc && (sqrtf(dx * dx + dy * dy) <= p.comm_range)) ? 1 : 0;
+            o.obs_mask[kb + m] = (oc && (norm2(ox - ax, oy - ay) <= p.comm_range)) ? 1 : 0;
           }
         }
 #pragma unroll
@@ -670,8 +676,7 @@ __global__ void __launch_bounds__(1024) metrics_kernel(DevParams p, DevState s, 
     for (int j = 0; j < nt; ++j) {
       float dmin = __int_as_float(0x7f800000);
       for (int i = 0; i < na; ++i) {
-        const float dx = s.ax[ab + i] - s.tx[tb + j], dy = s.ay[ab + i] - s.ty[tb + j];
-        dmin = fminf(dmin, sqrtf(dx * dx + dy * dy));
+        dmin = fminf(dmin, norm2(s.ax[ab + i] - s.tx[tb + j], s.ay[ab + i] - s.ty[tb + j]));
       }
       if (dmin > p.lost_range) v[5] += 1.0;
     }

@@ -108,16 +108,19 @@ constexpr int kMaxW = (kIn - 1) / 3;  // 21 entries fit the 64 inputs
 
 __device__ __forceinline__ bool window_features(const float *w, int W, float (&x)[kIn],
                                                 float (&frame)[5]) {
+  // means taken over offsets from entry 0 (small numbers, so FP32 keeps them
+  // accurate), then the centroid is entry 0 plus the mean offset
+  const float x0 = w[0], y0 = w[1], r0 = w[2];
   float mx = 0.f, my = 0.f, mr = 0.f;
   bool ok = true;
 #pragma unroll
   for (int k = 0; k < kMaxW; ++k) {
     if (k < W) {
-      mx += w[3 * k];
-      my += w[3 * k + 1];
+      mx += w[3 * k] - x0;
+      my += w[3 * k + 1] - y0;
       const float r = w[3 * k + 2];
       ok = ok && (r == r);
-      mr += r;
+      mr += r - r0;
     }
   }
   const float invw = 1.0f / (float)W;
@@ -125,7 +128,7 @@ __device__ __forceinline__ bool window_features(const float *w, int W, float (&x
   my *= invw;
   mr *= invw;
   const float cx = w[0] - w[3 * (W - 1)], cy = w[1] - w[3 * (W - 1) + 1];
-  const float len = sqrtf(cx * cx + cy * cy);
+  const float len = sqrtf(fmaf(cx, cx, cy * cy));
   float c = 1.0f, s = 0.0f;
   if (len > 1e-6f) {
     c = cx / len;
@@ -136,20 +139,20 @@ __device__ __forceinline__ bool window_features(const float *w, int W, float (&x
 #pragma unroll
   for (int k = 0; k < kMaxW; ++k) {
     if (k < W) {
-      const float dx = w[3 * k] - mx, dy = w[3 * k + 1] - my;
-      x[3 * k] = (c * dx + s * dy) * 0.1f;
-      x[3 * k + 1] = (-s * dx + c * dy) * 0.1f;
-      x[3 * k + 2] = (w[3 * k + 2] - mr) * 0.1f;
+      const float dx = (w[3 * k] - x0) - mx, dy = (w[3 * k + 1] - y0) - my;
+      x[3 * k] = fmaf(c, dx, s * dy) * 0.1f;
+      x[3 * k + 1] = fmaf(-s, dx, c * dy) * 0.1f;
+      x[3 * k + 2] = ((w[3 * k + 2] - r0) - mr) * 0.1f;
     } else if (k == W) {
-      x[3 * k] = mr * 1e-3f;
+      x[3 * k] = (r0 + mr) * 1e-3f;
     }
   }
-  if (W == kMaxW) x[3 * kMaxW] = mr * 1e-3f;
-  frame[0] = mx;
-  frame[1] = my;
+  if (W == kMaxW) x[3 * kMaxW] = (r0 + mr) * 1e-3f;
+  frame[0] = x0 + mx;
+  frame[1] = y0 + my;
   frame[2] = c;
   frame[3] = s;
-  frame[4] = mr;
+  frame[4] = r0 + mr;
   return ok;
 }
 

@@ -36,12 +36,12 @@ __device__ __forceinline__ bool ls_masked(const T (&hx)[WC], const T (&hy)[WC],
     if (k < filled && hr[k] == hr[k]) {
       const double ux = (double)hx[k] - mx, uy = (double)hy[k] - my;
       const double d = (double)hr[k] - mr;
-      const double c = ux * ux + uy * uy - d * (2.0 * mr + d);
-      sxx += ux * ux;
-      sxy += ux * uy;
-      syy += uy * uy;
-      gx += ux * c;
-      gy += uy * c;
+      const double c = fma(-d, fma(2.0, mr, d), fma(ux, ux, uy * uy));
+      sxx = fma(ux, ux, sxx);
+      sxy = fma(ux, uy, sxy);
+      syy = fma(uy, uy, syy);
+      gx = fma(ux, c, gx);
+      gy = fma(uy, c, gy);
     }
   }
   const double det = sxx * syy - sxy * sxy, tr = sxx + syy;

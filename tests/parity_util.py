@@ -15,6 +15,13 @@ import numpy as np
 REL = 1e-5
 
 
+def angle_diff(a, b):
+    """|a - b| as angles (headings are kept in [-pi, pi], so the two sides may
+    sit on opposite sides of the cut)."""
+    d = np.mod(np.asarray(a, np.float64) - np.asarray(b, np.float64) + np.pi, 2 * np.pi) - np.pi
+    return np.abs(d)
+
+
 def gpu_rollout_records(env, T, record, actions=None):
     out = env.rollout(T, actions=actions, record=record)
     return {k: v.cpu().numpy() for k, v in out.items()}
@@ -47,12 +54,12 @@ def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
     oa, ot = orc["agent"], orc["target"]
     dpos_a = np.abs(ga[..., :2] - oa[..., :2]).max(-1)  # [T, A]
     dpos_t = np.abs(gt[..., :2] - ot[..., :2]).max(-1)
-    dpsi = np.abs(ga[..., 4] - oa[..., 2])
+    dpsi = angle_diff(ga[..., 4], oa[..., 2])
     report["pos_rel"] = max(dpos_a.max(), dpos_t.max()) / s
     report["psi_rel"] = dpsi.max() / np.pi
     assert report["pos_rel"] <= REL, f"{label} positions differ: {report['pos_rel']:.3g}"
     assert report["psi_rel"] <= REL, f"{label} headings differ: {report['psi_rel']:.3g}"
-    report["tpsi_rel"] = np.abs(gt[..., 4] - ot[..., 2]).max() / np.pi
+    report["tpsi_rel"] = angle_diff(gt[..., 4], ot[..., 2]).max() / np.pi
     assert report["tpsi_rel"] <= REL, f"{label} target headings differ"
     assert (np.abs(gt[..., 3] - ot[..., 3]) <= 1e-6 * np.abs(ot[..., 3]) + 1e-7).all()
     # ---- actions (random policy: exact integer draws)

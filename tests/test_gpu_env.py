@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2505_08222_amd.configs import CONFIGS, env_config  # noqa: E402
 
-from parity_util import compare_rollout  # noqa: E402
+from parity_util import angle_diff, compare_rollout  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -126,7 +126,8 @@ def test_full_size_ragged_sampled(orc):
         ga = a_state[o["agent"][k]:o["agent"][k + 1]]
         ra = ref["agent"][-1][ref["csr"]["agent"][n]:ref["csr"]["agent"][n + 1]]
         assert np.abs(ga[:, :2] - ra[:, :2]).max() <= 1e-5 * s
-        assert np.abs(ga[:, 2] - ra[:, 2]).max() <= 1e-5 * np.pi
+        assert angle_diff(ga[:, 2], ra[:, 2]).max() <= 1e-5 * np.pi
+        assert (np.abs(ga[:, 2]) <= np.pi + 1e-6).all()
         gt = t_state[o["target"][k]:o["target"][k + 1]]
         rt = ref["target"][-1][ref["csr"]["target"][n]:ref["csr"]["target"][n + 1]]
         assert np.abs(gt[:, :2] - rt[:, :2]).max() <= 1e-5 * s
@@ -230,6 +231,8 @@ def test_graph_replay_matches_eager():
 
 
 def test_metrics_match_oracle(orc):
+    """The reduction equals the sums of the per-step records it summarises;
+    those records are held to the oracle's by the rollout parity tests."""
     cfg = env_config("ragged", episode_len=60)
     E, T = 400, 60
     env = _env(cfg, E, seed=0)
@@ -238,15 +241,26 @@ def test_metrics_match_oracle(orc):
     m = env.metrics().cpu().numpy()
     sel = np.arange(E)
     ref = _oracle(orc, cfg, env, sel, 0, T)
-    em = ref["env_metrics"].sum(0)
-    np.testing.assert_allclose(m[0], em[0], rtol=1e-5, atol=1e-3)   # reward sum
-    assert m[4] == em[4]  # crash steps
-    assert m[6] == E * T and m[7] == env.A * T
-    # tracking-error sums agree with the GPU's own per-step records exactly
+    compare_rollout(out, ref, env, sel, cfg, label="metrics")
+    np.testing.assert_allclose(m[0], out["reward"].astype(np.float64).sum(), rtol=1e-9)
     err = out["err"].astype(np.float64)
     fin = np.isfinite(err)
     np.testing.assert_allclose(m[1], err[fin].sum(), rtol=1e-9)
+    np.testing.assert_allclose(m[2], (err[fin] ** 2).sum(), rtol=1e-6)
     assert m[3] == fin.sum()
+    em = ref["env_metrics"].sum(0)
+    assert m[4] == em[4] == (out["reward"] == -1).sum()  # crash steps
+    # lost targets at the end, from the final positions
+    a_state, t_state = (x.cpu().numpy() for x in env.state())
+    o = env.order
+    lost = 0
+    for k in range(E):
+        ag = a_state[o["agent"][k]:o["agent"][k + 1], :2]
+        tg = t_state[o["target"][k]:o["target"][k + 1], :2]
+        d = np.hypot(ag[:, None, 0] - tg[None, :, 0], ag[:, None, 1] - tg[None, :, 1]).min(0)
+        lost += (d > cfg["lost_range"]).sum()
+    assert m[5] == lost == em[5]
+    assert m[6] == E * T and m[7] == env.A * T
 
 
 def test_reset_observation(orc):

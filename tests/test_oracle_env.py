@@ -53,7 +53,9 @@ def test_constant_turn_closed_form(orc, action, delta):
     ang = a0[:, 2] + (T + 1) * delta / 2
     want = a0[:, :2] + g * np.column_stack([np.cos(ang), np.sin(ang)])
     np.testing.assert_allclose(aT[:, :2], want, rtol=0, atol=1e-9)
-    np.testing.assert_allclose(aT[:, 2], a0[:, 2] + T * delta, rtol=0, atol=1e-12)
+    dpsi = np.mod(aT[:, 2] - (a0[:, 2] + T * delta) + np.pi, 2 * np.pi) - np.pi
+    np.testing.assert_allclose(dpsi, 0, atol=1e-12)
+    assert (np.abs(out["agent"][..., 2]) <= np.pi).all()  # headings stay angles
 
 
 def test_noise_free_ranges_are_distances(orc):
