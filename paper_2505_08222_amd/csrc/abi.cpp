@@ -90,7 +90,7 @@ struct mil_env {
   struct {
     int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class;
     int64_t ax, ay, apsi, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
-    int64_t state_begin, state_end, status, snap, total;
+    int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
   mil::DevParams dp{};
   mil::DevState ds{};
@@ -220,8 +220,8 @@ int check_outputs(const mil_env_outputs *o) {
 int run_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
                 hipStream_t st) {
   const int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
-                                     h->ds, (int32_t)h->t, T, h->episode, d_actions,
-                                     dev_out(outs), st);
+                                     h->ds, (const mil::DevState *)(h->ws + h->off.devstate),
+                                     (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st);
   if (rc == -2) return fail(MIL_EINVAL, "no kernel for size class %d / window %d", h->size_class,
                             h->wcap);
   if (rc != 0) return fail(MIL_EHIP, "rollout launch failed: %s",
@@ -349,6 +349,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.classes = take((int64_t)h->cls.size() * sizeof(mil::ClassInfo));
   f.wave_class = take(h->max_waves);
   f.status = take(256);
+  f.devstate = take(sizeof(mil::DevState));
   f.state_begin = o;
   f.ax = take(A * 4);
   f.ay = take(A * 4);
@@ -453,6 +454,8 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.Tt = h->toff[E];
   d.P = h->poff[E];
   d.K = h->koff[E];
+  HIP_CHECK(hipMemcpyAsync(h->ws + h->off.devstate, &h->ds, sizeof(mil::DevState),
+                           hipMemcpyHostToDevice, st));
   const int rc = upload_mapping(h, st);
   if (rc) return rc;
   h->t = -1;
@@ -521,8 +524,9 @@ int env_graph_capture(mil_env *h, uint64_t episode, int32_t T, const mil_env_out
   HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   int lrc = mil::launch_reset(h->dp, h->ds, (uint32_t)episode, dev_out(outs), st);
   if (!lrc)
-    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds, 0,
-                              T, (uint32_t)episode, nullptr, dev_out(outs), st);
+    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                              (const mil::DevState *)(h->ws + h->off.devstate), 0, T,
+                              (uint32_t)episode, nullptr, dev_out(outs), st);
   if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
   hipGraph_t g = nullptr;
   hipError_t ec = hipStreamEndCapture(st, &g);

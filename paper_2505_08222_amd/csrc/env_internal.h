@@ -47,8 +47,10 @@ struct DevState {
   int64_t E, A, Tt, P, K;
 };
 
-// Output pointers (mirrors mil_env_outputs).
+// Output pointers (mirrors mil_env_outputs) and the per-step strides of the
+// step-major output arrays.
 struct DevOut {
+  int64_t E, A, Tt, P, K;
   float *obs;
   uint8_t *obs_mask;
   float *reward;
@@ -64,9 +66,12 @@ struct DevOut {
 // Kernel launchers (env_kernels.hip). All enqueue on `stream`.
 int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const DevOut &o,
                  void *stream);
+// d_state: a device copy of `s` (the rollout reads it through this pointer so
+// that the state pointers need not stay in scalar registers across steps).
 int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_block,
-                   int num_waves, const DevParams &p, const DevState &s, int32_t t0, int32_t T,
-                   uint32_t episode, const int32_t *actions, const DevOut &o, void *stream);
+                   int num_waves, const DevParams &p, const DevState &s, const DevState *d_state,
+                   int32_t t0, int32_t T, uint32_t episode, const int32_t *actions,
+                   const DevOut &o, void *stream);
 int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
                    void *stream);
 int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream);

@@ -43,7 +43,7 @@ __device__ __forceinline__ float tracking_reward(float e, float emin, float emax
   if (e < emin) return 1.0f;
   if (!(e < emax)) return 0.0f;
   const float t = (e - emin) / (emax - emin);
-  return expf(-2.0f * t / (1.0f - t));
+  return __expf(-2.0f * t / (1.0f - t));
 }
 
 // A heading is an angle: kept in [-pi, pi] after every update.
@@ -54,7 +54,12 @@ __device__ __forceinline__ float wrap_angle(float a) {
   return a;
 }
 
-__device__ __forceinline__ float norm2(float dx, float dy) { return sqrtf(fmaf(dx, dx, dy * dy)); }
+__device__ __forceinline__ float norm2(float dx, float dy) { return fast_sqrt(fmaf(dx, dx, dy * dy)); }
+
+// sin and cos of an angle in radians via the revolution-based hardware ops.
+__device__ __forceinline__ void sincos_rad(float a, float &s, float &c) {
+  sincos_rev(a * 0.15915494309189535f, s, c);
+}
 
 __device__ __forceinline__ void store_token(float *dst, float dx, float dy, float is_self,
                                             float is_agent, float is_target) {
@@ -176,7 +181,7 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 // ---------------------------------------------------------------------------
 template <int S, int WC, int G>
 __global__ void __launch_bounds__(256)
-rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T,
+rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
                uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
   constexpr int MA = S, MT = S;
   constexpr int NPL = (MT + G - 1) / G;  // (agent, target) pairs per lane
@@ -188,6 +193,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
   if (wave >= num_waves) return;
+  const DevState &s = *sp;  // prologue and epilogue only (reloaded after the loop)
   const ClassInfo C = s.classes[s.wave_class[wave]];
   const int na = C.na, nt = C.nt;
   const int lpe = na * G;
@@ -266,7 +272,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
     const u32x4 xa = philox4x32_10(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
     int act;
     if (actions) {
-      act = actions[(int64_t)step * s.A + aidx];
+      act = actions[(int64_t)step * o.A + aidx];
       if (act < 0 || act >= p.n_actions) {
         act = -1;
         if (active) status |= kStatusBadAction;
@@ -283,7 +289,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
     apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
     {
       float sn, cs;
-      sincosf(apsi, &sn, &cs);
+      sincos_rad(apsi, sn, cs);
       ax = fmaf(vdt, cs, ax);
       ay = fmaf(vdt, sn, ay);
     }
@@ -302,7 +308,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
           float4 tg = tl[j];
           tg.z = wrap_angle(tg.z + p.sig_t * zt[m]);
           float sn, cs;
-          sincosf(tg.z, &sn, &cs);
+          sincos_rad(tg.z, sn, cs);
           const float step_len = tg.w * p.dt;
           tg.x = fmaf(step_len, cs, tg.x);
           tg.y = fmaf(step_len, sn, tg.y);
@@ -516,15 +522,15 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
             acc_err2 += (double)ej[j] * (double)ej[j];
             acc_cnt += 1;
           }
-        if (o.reward) o.reward[(int64_t)step * s.E + e] = rew;
-        if (o.done) o.done[(int64_t)step * s.E + e] = done ? 1 : 0;
+        if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
+        if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
         if (o.err) {
 #pragma unroll
           for (int j = 0; j < MT; ++j)
-            if (j < nt) o.err[(int64_t)step * s.Tt + tbase + j] = ej[j];
+            if (j < nt) o.err[(int64_t)step * o.Tt + tbase + j] = ej[j];
         }
       }
-      const int64_t kb = (int64_t)step * s.K + kbase;
+      const int64_t kb = (int64_t)step * o.K + kbase;
       if (o.obs) {
         float *ob = o.obs + kb * 6;
         if (g == 0) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
@@ -569,9 +575,9 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
           if (j < nt && (j % G) == g) o.obs_mask[kb + na + j] = ((evb >> (j / G)) & 1u) ? 1 : 0;
       }
       if (g == 0) {
-        if (o.actions) o.actions[(int64_t)step * s.A + aidx] = act;
+        if (o.actions) o.actions[(int64_t)step * o.A + aidx] = act;
         if (o.gstate) {
-          float *gs = o.gstate + ((int64_t)step * (s.A + s.Tt) + gbase + i) * 6;
+          float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + i) * 6;
           gs[0] = ax; gs[1] = ay; gs[2] = 0.0f; gs[3] = p.agent_speed; gs[4] = apsi; gs[5] = 0.0f;
         }
       }
@@ -582,7 +588,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
             const int j = 2 * q + m;
             if (j < nt) {
               const float4 tg = tl[j];
-              float *gs = o.gstate + ((int64_t)step * (s.A + s.Tt) + gbase + na + j) * 6;
+              float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + na + j) * 6;
               gs[0] = tg.x; gs[1] = tg.y; gs[2] = 0.0f; gs[3] = tg.w; gs[4] = tg.z; gs[5] = 1.0f;
             }
           }
@@ -592,7 +598,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
       for (int sl = 0; sl < NPL; ++sl) {
         const int j = g + G * sl;
         if (j < nt) {
-          const int64_t pidx = (int64_t)step * s.P + pbase + j;
+          const int64_t pidx = (int64_t)step * o.P + pbase + j;
           const bool ok = (evb >> sl) & 1u;
           if (o.est) {
             o.est[2 * pidx] = ok ? ex[sl] : 0.0f;
@@ -607,8 +613,9 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
     }
   }
 
-  // ---- store state back
+  // ---- store state back (state pointers re-read from the device copy)
   if (active) {
+    const DevState &s = *sp;
     if (g == 0) {
       s.ax[aidx] = ax;
       s.ay[aidx] = ay;
@@ -654,7 +661,7 @@ rollout_kernel(DevParams p, DevState s, int32_t num_waves, int32_t t0, int32_t T
       s.miacc[2 * e + 1] = acc_crash;
     }
   }
-  if (status) atomicOr(s.status, status);
+  if (status) atomicOr(sp->status, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -767,7 +774,7 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
 
 template <int S, int WC, int G>
 static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
-                            const DevState &s, int32_t t0, int32_t T, uint32_t episode,
+                            const DevState *s, int32_t t0, int32_t T, uint32_t episode,
                             const int32_t *actions, const DevOut &o, hipStream_t st) {
   const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
   const size_t lds = (size_t)waves_per_block * 64 * S * sizeof(float4);
@@ -777,10 +784,17 @@ static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams 
 }
 
 int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num_waves,
-                   const DevParams &p, const DevState &s, int32_t t0, int32_t T, uint32_t episode,
-                   const int32_t *actions, const DevOut &o, void *stream) {
+                   const DevParams &p, const DevState &hs, const DevState *s, int32_t t0,
+                   int32_t T, uint32_t episode, const int32_t *actions, const DevOut &o_in,
+                   void *stream) {
   hipStream_t st = (hipStream_t)stream;
   if (num_waves <= 0 || T <= 0) return 0;
+  DevOut o = o_in;
+  o.E = hs.E;
+  o.A = hs.A;
+  o.Tt = hs.Tt;
+  o.P = hs.P;
+  o.K = hs.K;
 #define MIL_ROLL(SC, WCV, GV)                                                                 \
   if (size_class == SC && wcap == WCV && G == GV)                                            \
     return launch_rollout_t<SC, WCV, GV>(waves_per_block, num_waves, p, s, t0, T, episode,   \

@@ -45,14 +45,23 @@ __device__ __forceinline__ float u01(uint32_t x) {
   return __uint2float_rn(x >> 9) * 0x1p-23f + 0x1p-24f;
 }
 
-// Box-Muller (1958). The angle 2*pi*u1 is evaluated with sincospi on the
-// exactly representable argument 2*u1, avoiding a rounded 2*pi product.
+// Native transcendental instructions of gfx950 (about 1-2 ulp): log2, sqrt,
+// and sin/cos of an angle given in revolutions (v_sin_f32(x) = sin(2 pi x)).
+__device__ __forceinline__ float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ void sincos_rev(float rev, float &s, float &c) {
+  s = __builtin_amdgcn_sinf(rev);
+  c = __builtin_amdgcn_cosf(rev);
+}
+
+// Box-Muller (1958): z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = ... sin(2 pi u1);
+// the angle 2 pi u1 is passed to the hardware as u1 revolutions, exactly.
 __device__ __forceinline__ void normal2(uint32_t x0, uint32_t x1, float &z0, float &z1) {
   const float u0 = u01(x0);
   const float u1 = u01(x1);
-  const float rad = sqrtf(-2.0f * logf(u0));
+  const float rad = fast_sqrt(-2.0f * fast_ln(u0));
   float s, c;
-  sincospif(2.0f * u1, &s, &c);
+  sincos_rev(u1, s, c);
   z0 = rad * c;
   z1 = rad * s;
 }

@@ -50,7 +50,8 @@ def test_rng_words_and_transforms(orc):
     for k in range(512):
         z0, z1 = orc.normal2(int(w[k, 0]), int(w[k, 1]))
         z2, z3 = orc.normal2(int(w[k, 2]), int(w[k, 3]))
-        np.testing.assert_allclose(z[k], [z0, z1, z2, z3], rtol=4e-6, atol=4e-6)
+        # native log2/sqrt/sin/cos instructions: ~2 ulp each
+        np.testing.assert_allclose(z[k], [z0, z1, z2, z3], rtol=1e-5, atol=1e-5)
 
 
 def test_ragged_counts_match_oracle(orc):

@@ -106,12 +106,19 @@ def test_infer_fallback_rule(orc):
 
 
 def test_training_reduces_loss():
+    """A few hundred Adam steps of the BF16 kernels cut the error on windows
+    whose exact estimate lies within twice the mean range (ill-conditioned
+    windows give arbitrarily far estimates; they are left to the fallback)."""
     from paper_2505_08222_amd import learned
     from paper_2505_08222_amd.env import est_exact
-    win = torch.from_numpy(range_windows(40000, 16, seed=21, spread=1.0)).cuda()
+    win = torch.from_numpy(range_windows(60000, 16, seed=21, spread=1.0, far=800.0)).cuda()
     ex, ev = est_exact(win)
-    keep = ev.bool()
-    x, frame = learned.features(win[keep])
-    y = learned.targets(frame, ex[keep])
-    params, hist = learned.train(x, y, epochs=3, batch=4096, lr=3e-3, seed=0)
-    assert hist[-1][1] < 0.3 * hist[0][1], hist
+    x, frame = learned.features(win)
+    y = learned.targets(frame, ex)
+    keep = ev.bool() & (y.norm(dim=1) <= 2.0)
+    x, y = x[keep].contiguous(), y[keep].contiguous()
+    base = float((y - y.mean(0)).pow(2).sum(1).mean())
+    params, hist = learned.train(x, y, epochs=6, batch=1024, lr=3e-3, lr_final=3e-4, seed=0)
+    pred = learned.forward(x, params, "bf16")
+    mse = float((pred - y).pow(2).sum(1).mean())
+    assert mse < 0.3 * base, (mse, base, hist[-3:])
