@@ -63,12 +63,120 @@ def cpu_baseline(cfg, env, T, budget_s):
                       f"config), FP64 C with OpenMP over envs, {el:.1f} s"}
 
 
+def bench_learned(args):
+    """Learned estimator (the learned-estimator configuration): windows of 16
+    from ragged-configuration rollouts, Adam training of the BF16 MLP with the
+    library's kernels, then guarded inference on a disjoint set, compared with
+    the exact estimator on error (m) and throughput."""
+    import numpy as np
+    import torch
+
+    from paper_2505_08222_amd import learned
+    from paper_2505_08222_amd.configs import CONFIGS
+    from paper_2505_08222_amd.env import est_exact
+
+    c = CONFIGS["learned"]
+    cfg = dict(c["env"])
+    torch.cuda.set_device(0)
+    n_train, n_infer = c["train_windows"], c["infer_windows"]
+    if args.envs:  # smaller runs for quick checks
+        scale = args.envs / c["num_envs"]
+        n_train, n_infer = max(20000, int(n_train * scale)), max(20000, int(n_infer * scale))
+    E = args.envs or c["num_envs"]
+    t0 = time.perf_counter()
+    tr = learned.rollout_windows(cfg, E, n_train, seed=0)
+    te = learned.rollout_windows(cfg, E, n_infer, seed=1, first_step=125)
+    log(f"[learned] windows: train {tr['win'].shape[0]}, infer {te['win'].shape[0]} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    x, frame = learned.features(tr["win"])
+    y = learned.targets(frame, tr["exact"])
+    keep = y.norm(dim=1) <= 2.0
+    x, y = x[keep].contiguous(), y[keep].contiguous()
+    log(f"[learned] training set {x.shape[0]} windows (exact estimate within 2x the mean range)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, hist = learned.train(x, y, epochs=2, batch=8192, lr=2e-3, lr_final=5e-5, seed=0,
+                                 log=lambda m: None)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"[learned] trained {len(hist)} logged steps in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
+        f"{hist[-1][1]:.3e}")
+    win, sigma, truth = te["win"], te["sigma"], te["truth"]
+    N = win.shape[0]
+    work = learned._work(N, "bf16", win.device)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            out = fn()
+            b.record()
+            torch.cuda.synchronize()
+            evs.append(a.elapsed_time(b))
+        return out, float(np.median(evs))
+
+    (p_mlp, flag), ms_mlp = timed(lambda: learned.infer(win, params, sigma, 3.0, work=work))
+    (p_ex, v_ex), ms_ex = timed(lambda: est_exact(win))
+    (p_ex32, _), ms_ex32 = timed(lambda: est_exact(win, accum="fp32"))
+    (p_gn, v_gn), ms_gn = timed(lambda: est_exact(win, gn_iters=8))
+    xi, _ = learned.features(win)
+    (_, _), ms_fwd = timed(lambda: (learned.forward(xi, params, "bf16"), None))
+    flag = flag.cpu().numpy()
+    pm, pe, pt = p_mlp.cpu().numpy(), p_ex.cpu().numpy(), truth.cpu().numpy()
+    pg = p_gn.cpu().numpy()
+    ve = v_ex.cpu().numpy().astype(bool)
+    acc = flag == 1
+    rng_ = np.hypot(*(pt - win[:, :, :2].mean(1).cpu().numpy()).T)
+    d_me = np.hypot(*(pm - pe).T)
+    bins = [(0, 100), (100, 500), (500, 1e9)]
+    by_bin = {}
+    for lo, hi in bins:
+        m = acc & ve & (rng_ >= lo) & (rng_ < hi)
+        mt = ve & (rng_ >= lo) & (rng_ < hi)
+        name = f"{int(lo)}-{int(hi) if hi < 1e8 else 'inf'} m"
+        by_bin[name] = {
+            "windows": int(mt.sum()), "accepted_frac": float(m.sum() / max(mt.sum(), 1)),
+            "rms_learned_vs_exact_m": float(np.sqrt(np.mean(d_me[m] ** 2))) if m.any() else None,
+            "rms_exact_vs_truth_m": float(np.sqrt(np.mean(np.hypot(*(pe[mt] - pt[mt]).T) ** 2))) if mt.any() else None,
+            "rms_final_vs_truth_m": float(np.sqrt(np.mean(np.hypot(*(pm[mt] - pt[mt]).T) ** 2))) if mt.any() else None,
+        }
+    flops = 2.0 * (64 * 128 + 128 * 128 + 128 * 2) * N
+    res = {
+        "metric": METRIC,
+        "value": ms_ex / ms_mlp,
+        "unit": "x (exact FP64 LS time / guarded learned time, same GPU, same windows)",
+        "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": ms_mlp,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"learned estimator: 16-entry windows from ragged-configuration "
+                               f"rollouts, train {x.shape[0]}, infer {N}",
+                   "train_windows": int(x.shape[0]), "infer_windows": int(N)},
+        "infer_ms": {"learned_guarded": ms_mlp, "mlp_forward_only": ms_fwd,
+                     "exact_fp64": ms_ex, "exact_fp32": ms_ex32, "exact_gauss_newton8": ms_gn},
+        "speedup_vs": {"exact_fp64": ms_ex / ms_mlp, "exact_fp32": ms_ex32 / ms_mlp,
+                       "exact_gauss_newton8": ms_gn / ms_mlp},
+        "accepted_frac": float(acc.mean()),
+        "rms_learned_vs_exact_m_accepted": float(np.sqrt(np.mean(d_me[acc & ve] ** 2))),
+        "median_learned_vs_exact_m_accepted": float(np.median(d_me[acc & ve])),
+        "by_range": by_bin,
+        "train": {"seconds": train_s, "loss_first": hist[0][1], "loss_last": hist[-1][1]},
+        "mfma": {"forward_tflops": flops / (ms_fwd / 1e3) / 1e12, "peak_tflops": 2500.0,
+                 "frac": flops / (ms_fwd / 1e3) / 1e12 / 2500.0},
+        "gauss_newton_vs_truth_rms_m": float(np.sqrt(np.mean(np.hypot(*(pg[ve] - pt[ve]).T) ** 2))),
+    }
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["plain", "batched", "ragged"])
+    ap.add_argument("--workload", default="batched",
+                    choices=["plain", "batched", "ragged", "learned"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -85,6 +193,10 @@ def main():
 
     from paper_2505_08222_amd.configs import CONFIGS, env_config
     from paper_2505_08222_amd.env import Env
+
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args)), flush=True)
+        return
 
     c = CONFIGS[args.workload]
     cfg = env_config(args.workload)

@@ -66,13 +66,21 @@ def test_ragged_counts_match_oracle(orc):
     assert sorted(ids.tolist()) == list(range(4096))
 
 
-@pytest.mark.parametrize("name", ["plain", "batched_small", "ragged_small"])
+@pytest.mark.parametrize("name", ["plain", "batched_small", "ragged_small", "window16_5x5",
+                                  "gauss_newton", "detection_comm_loss"])
 def test_rollout_parity(orc, name):
     if name == "plain":
         c = CONFIGS["plain"]
         cfg, E, T = env_config("plain"), c["num_envs"], c["steps"]
     elif name == "batched_small":
         cfg, E, T = env_config("batched"), 96, 120
+    elif name == "window16_5x5":  # the policy / learned-estimator shape: W = 16, 5 x 5
+        cfg, E, T = env_config("policy", episode_len=80), 64, 80
+    elif name == "gauss_newton":  # refinement path of the tracker
+        cfg, E, T = env_config("ragged", episode_len=60, gn_iters=4), 120, 60
+    elif name == "detection_comm_loss":  # missing ranges and dropped broadcasts
+        cfg, E, T = env_config("ragged", episode_len=60, det_range=1200.0, comm_range=120.0,
+                               comm_loss_p=0.3), 150, 60
     else:
         cfg, E, T = env_config("ragged", episode_len=150), 300, 150
     seed = 0
