@@ -170,13 +170,88 @@ def bench_learned(args):
     return res
 
 
+def policy_flops_per_agent_step(n_tok, d=64, heads=4, ffn=256, layers=2, n_out=8):
+    """Algorithmic FLOPs of one agent's forward pass (dense layers + attention)."""
+    per_layer = (2 * n_tok * d * 3 * d + 2 * 2 * heads * n_tok * n_tok * (d // heads)
+                 + 2 * n_tok * d * d + 2 * 2 * n_tok * d * ffn)
+    return 2 * n_tok * 6 * d + layers * per_layer + 2 * d * n_out
+
+
+def bench_policy(args):
+    """Full rollout with the attention policy: 16384 envs x 5 agents x 5
+    targets x 1000 steps, each step = policy forward on every agent's
+    observation, then the environment step, captured as one HIP graph."""
+    import numpy as np
+    import torch
+
+    from paper_2505_08222_amd import policy
+    from paper_2505_08222_amd.configs import CONFIGS, env_config
+    from paper_2505_08222_amd.env import Env
+
+    c = CONFIGS["policy"]
+    cfg = env_config("policy")
+    E = args.envs or c["num_envs"]
+    T = c["steps"]
+    torch.cuda.set_device(0)
+    env = Env(cfg, E, seed=c["seed"])
+    params = policy.init_params(c["seed"])
+    pr = policy.PolicyRollout(env, params)
+    gout, gm = pr.capture(T, record=("reward", "done"))
+    for _ in range(args.warmup):
+        pr.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        pr.launch()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
+    # the policy kernel alone, on the final observation, timed with events
+    n_tok = cfg["n_agents"] + cfg["n_targets"]
+    env.reset(0)
+    obs = env.rollout(1, record=("obs", "obs_mask"))
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    policy.forward(obs["obs"][0], obs["obs_mask"][0], params, n_tok, cfg["n_agents"])
+    torch.cuda.synchronize()
+    durs = []
+    for _ in range(5):
+        a.record(stream)
+        policy.forward(obs["obs"][0], obs["obs_mask"][0], params, n_tok, cfg["n_agents"])
+        b.record(stream)
+        torch.cuda.synchronize()
+        durs.append(a.elapsed_time(b))
+    pol_ms = float(np.median(durs))
+    flops = policy_flops_per_agent_step(n_tok) * env.A
+    tflops = flops / (pol_ms / 1e3) / 1e12
+    m = gm.cpu().numpy()
+    return {
+        "metric": METRIC, "value": E * T * args.steps / elapsed, "unit": "env-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"policy: {E} envs x 5 agents x 5 targets x {T} steps, attention "
+                               "policy (d 64, 4 heads, 2 layers, FFN 256, random init) + env step "
+                               "per step, one HIP graph", "envs": E, "episode_steps": T},
+        "agent_steps_per_s": env.A * T * args.steps / elapsed,
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "traffic": None, "kernel": "policy_kernel",
+                     "kernel_ms": pol_ms, "flops_per_launch": flops},
+        "episode_metrics": {"mean_reward": float(m[0] / max(m[6], 1)),
+                            "crash_steps": float(m[4])},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="batched",
-                    choices=["plain", "batched", "ragged", "learned"])
+                    choices=["plain", "batched", "ragged", "learned", "policy"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -196,6 +271,9 @@ def main():
 
     if args.workload == "learned":
         print(json.dumps(bench_learned(args)), flush=True)
+        return
+    if args.workload == "policy":
+        print(json.dumps(bench_policy(args)), flush=True)
         return
 
     c = CONFIGS[args.workload]

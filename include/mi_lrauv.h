@@ -284,6 +284,43 @@ int mlp_infer(const float *d_win, int64_t N, int32_t W, const float *d_params,
  * the true target position (either may be NULL). */
 int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Attention policy: the per-agent transformer actor of Sec. III-B
+ * (TransfMAPPO) without its recurrent token, forward only, BF16 MFMA with FP32
+ * accumulation. Each agent's tokens (its observation, [self, agents, targets],
+ * n_tok = n_agents + n_targets <= 16) are embedded 6 -> 64, pass 2 pre-LN
+ * layers of 4-head self-attention (keys with mask 0 excluded) and a 256-wide
+ * GELU feed-forward block, and the self token's final LayerNorm gives 8
+ * logits, of which the first n_actions define the action distribution.
+ * Actions are inverse-CDF draws with u from Philox(counter = (step, global env
+ * id, agent index, 4 | episode << 4), key = seed).
+ * Parameters: one FP32 vector of policy_num_params() floats, in this order:
+ * embedding W [64][6], b [64]; per layer: LN1 gain, offset [64], Wqkv
+ * [192][64] (Q, K, V rows; head h uses features 16h..16h+15), bqkv [192], Wo
+ * [64][64], bo [64], LN2 gain, offset [64], W1 [256][64], b1 [256], W2
+ * [64][256], b2 [64]; final LN gain, offset [64]; Wh [8][64], bh [8].
+ * ------------------------------------------------------------------------- */
+int64_t policy_num_params(void);
+/* Workspace for policy_forward / env_policy_rollout (256-byte aligned). */
+int64_t policy_workspace_bytes(int64_t num_agents, int64_t num_tokens);
+/* Glorot-uniform weights (Philox keyed by seed), LN gains 1, offsets/biases 0. */
+int policy_init(float *d_params, uint64_t seed, void *stream);
+/* Logits [A][8] (d_logits, may be NULL) and sampled actions [A] (d_actions,
+ * may be NULL) of A agents, agent a being agent a % n_agents of env
+ * a / n_agents; d_obs [A * n_tok][6], d_mask [A * n_tok]. */
+int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions, const float *d_obs,
+                   const uint8_t *d_mask, const float *d_params, float *d_logits,
+                   int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
+                   int64_t work_bytes, void *stream);
+/* Closed loop on a bound fixed-count batch: reset(episode), then T times
+ * {policy on the latest observation -> actions; env step}, then (d_metrics
+ * not NULL) the metrics reduction. outs as for env_rollout ([T][...]). With
+ * capture = 1 the sequence is captured as the handle's HIP graph (replayed by
+ * env_graph_launch) instead of run. */
+int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
+                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
+                       void *d_work, int64_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

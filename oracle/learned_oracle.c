@@ -203,3 +203,143 @@ void orc_mlp_residual_rms(int64_t N, int W, const double *win, const double *p, 
     rms[n] = sqrt(acc / W);
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Attention policy (the TransfMAPPO actor of Sec. III-B, without its        */
+/* recurrent token; random initialisation, forward only). Tokens of one      */
+/* agent: [self, other agents, targets], each (dx, dy, dz, one-hot type).    */
+/* Pre-LN transformer: h = E x + e; for each layer: h += Wo MHA(LN1(h)) + bo,*/
+/* h += W2 gelu(W1 LN2(h) + b1) + b2; logits = Wh LN_f(h_self) + bh.         */
+/* Keys whose observation mask is 0 are excluded from attention.            */
+/* Parameter order: E [64][6], e [64]; per layer: ln1 g,b [64], Wqkv [192][64]*/
+/* (Q, K, V rows; head h uses features 16h..16h+15), bqkv [192], Wo [64][64],*/
+/* bo, ln2 g,b, W1 [256][64], b1 [256], W2 [64][256], b2 [64]; lnf g,b [64]; */
+/* Wh [8][64], bh [8] (the first n_actions rows are used).                   */
+/* ------------------------------------------------------------------------ */
+#define PD 64
+#define PH 4
+#define PDH 16
+#define PF 256
+#define PL 2
+#define PA 8
+#define P_LAYER (2 * PD + 3 * PD * PD + 3 * PD + PD * PD + PD + 2 * PD + PF * PD + PF + PD * PF + PD)
+#define P_TOTAL (PD * 6 + PD + PL * P_LAYER + 2 * PD + PA * PD + PA)
+
+int64_t orc_policy_num_params(void) { return P_TOTAL; }
+
+static void layer_norm(const double *x, const double *g, const double *b, double *y) {
+  double m = 0.0, v = 0.0;
+  for (int i = 0; i < PD; ++i) m += x[i];
+  m /= PD;
+  for (int i = 0; i < PD; ++i) v += (x[i] - m) * (x[i] - m);
+  v /= PD;
+  double inv = 1.0 / sqrt(v + 1e-5);
+  for (int i = 0; i < PD; ++i) y[i] = (x[i] - m) * inv * g[i] + b[i];
+}
+
+/* tokens [A][n_tok][6], mask [A][n_tok] -> logits [A][PA] */
+void orc_policy_forward(int64_t A, int n_tok, const double *tokens, const uint8_t *mask,
+                        const double *th, double *logits) {
+  enum { MAXT = 32 };
+  double h[MAXT][PD], a[MAXT][PD], q[MAXT][3 * PD], o[MAXT][PD], f[PF];
+  for (int64_t ag = 0; ag < A; ++ag) {
+    const double *x = tokens + ag * n_tok * 6;
+    const uint8_t *mk = mask + ag * n_tok;
+    const double *p = th;
+    const double *E = p; p += PD * 6;
+    const double *e = p; p += PD;
+    for (int t = 0; t < n_tok; ++t)
+      for (int d = 0; d < PD; ++d) {
+        double acc = e[d];
+        for (int c = 0; c < 6; ++c) acc += E[d * 6 + c] * x[t * 6 + c];
+        h[t][d] = acc;
+      }
+    for (int l = 0; l < PL; ++l) {
+      const double *g1 = p; p += PD;
+      const double *b1n = p; p += PD;
+      const double *Wqkv = p; p += 3 * PD * PD;
+      const double *bqkv = p; p += 3 * PD;
+      const double *Wo = p; p += PD * PD;
+      const double *bo = p; p += PD;
+      const double *g2 = p; p += PD;
+      const double *b2n = p; p += PD;
+      const double *W1 = p; p += PF * PD;
+      const double *b1 = p; p += PF;
+      const double *W2 = p; p += PD * PF;
+      const double *b2 = p; p += PD;
+      for (int t = 0; t < n_tok; ++t) layer_norm(h[t], g1, b1n, a[t]);
+      for (int t = 0; t < n_tok; ++t)
+        for (int r = 0; r < 3 * PD; ++r) {
+          double acc = bqkv[r];
+          for (int i = 0; i < PD; ++i) acc += Wqkv[r * PD + i] * a[t][i];
+          q[t][r] = acc;
+        }
+      for (int hd = 0; hd < PH; ++hd)
+        for (int t = 0; t < n_tok; ++t) {
+          double s[MAXT], mx = -INFINITY;
+          for (int u = 0; u < n_tok; ++u) {
+            if (!mk[u]) { s[u] = -INFINITY; continue; }
+            double acc = 0.0;
+            for (int c = 0; c < PDH; ++c) acc += q[t][hd * PDH + c] * q[u][PD + hd * PDH + c];
+            s[u] = acc / 4.0; /* sqrt(16) */
+            if (s[u] > mx) mx = s[u];
+          }
+          double z = 0.0;
+          for (int u = 0; u < n_tok; ++u) {
+            s[u] = mk[u] ? exp(s[u] - mx) : 0.0;
+            z += s[u];
+          }
+          for (int c = 0; c < PDH; ++c) {
+            double acc = 0.0;
+            for (int u = 0; u < n_tok; ++u) acc += s[u] * q[u][2 * PD + hd * PDH + c];
+            o[t][hd * PDH + c] = acc / z;
+          }
+        }
+      for (int t = 0; t < n_tok; ++t)
+        for (int d = 0; d < PD; ++d) {
+          double acc = bo[d];
+          for (int i = 0; i < PD; ++i) acc += Wo[d * PD + i] * o[t][i];
+          h[t][d] += acc;
+        }
+      for (int t = 0; t < n_tok; ++t) {
+        layer_norm(h[t], g2, b2n, a[t]);
+        for (int r = 0; r < PF; ++r) {
+          double acc = b1[r];
+          for (int i = 0; i < PD; ++i) acc += W1[r * PD + i] * a[t][i];
+          f[r] = gelu(acc);
+        }
+        for (int d = 0; d < PD; ++d) {
+          double acc = b2[d];
+          for (int r = 0; r < PF; ++r) acc += W2[d * PF + r] * f[r];
+          h[t][d] += acc;
+        }
+      }
+    }
+    const double *gf = p; p += PD;
+    const double *bf = p; p += PD;
+    const double *Wh = p; p += PA * PD;
+    const double *bh = p; p += PA;
+    double s0[PD];
+    layer_norm(h[0], gf, bf, s0);
+    for (int k = 0; k < PA; ++k) {
+      double acc = bh[k];
+      for (int i = 0; i < PD; ++i) acc += Wh[k * PD + i] * s0[i];
+      logits[ag * PA + k] = acc;
+    }
+  }
+}
+
+/* Inverse-CDF draw from softmax(logits[0..n-1]) with uniform u in (0,1):
+ * the smallest k whose cumulative probability exceeds u. */
+int orc_policy_sample(const double *logits, int n, double u) {
+  double mx = -INFINITY, z = 0.0;
+  for (int k = 0; k < n; ++k)
+    if (logits[k] > mx) mx = logits[k];
+  for (int k = 0; k < n; ++k) z += exp(logits[k] - mx);
+  double c = 0.0;
+  for (int k = 0; k < n; ++k) {
+    c += exp(logits[k] - mx) / z;
+    if (u < c) return k;
+  }
+  return n - 1;
+}

@@ -98,6 +98,8 @@ def _register_learned(L):
     if hasattr(L, "orc_policy_forward"):
         L.orc_policy_num_params.restype = I64
         L.orc_policy_forward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D)]
+        L.orc_policy_sample.argtypes = [P(D), C.c_int, D]
+        L.orc_policy_sample.restype = C.c_int
 
 
 def _p(a, ctype):
@@ -315,3 +317,25 @@ def residual_rms(win, p):
     out = np.zeros(N)
     lib().orc_mlp_residual_rms(N, W, _p(win, C.c_double), _p(p, C.c_double), _p(out, C.c_double))
     return out
+
+
+# ---------------------------------------------------------------- attention policy
+def policy_num_params() -> int:
+    return int(lib().orc_policy_num_params())
+
+
+def policy_forward(tokens, mask, params):
+    """tokens [A, n_tok, 6], mask [A, n_tok] -> logits [A, 8]."""
+    tokens = np.ascontiguousarray(tokens, np.float64)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    params = np.ascontiguousarray(params, np.float64)
+    A, n_tok, _ = tokens.shape
+    out = np.zeros((A, 8))
+    lib().orc_policy_forward(A, n_tok, _p(tokens, C.c_double), _p(mask, C.c_uint8),
+                             _p(params, C.c_double), _p(out, C.c_double))
+    return out
+
+
+def policy_sample(logits, n, u) -> int:
+    lg = np.ascontiguousarray(logits, np.float64)
+    return int(lib().orc_policy_sample(_p(lg, C.c_double), n, u))

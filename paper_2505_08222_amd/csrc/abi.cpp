@@ -18,6 +18,7 @@
 #include "env_internal.h"
 #include "learned_internal.h"
 #include "mi_lrauv.h"
+#include "policy_internal.h"
 
 #ifndef MIL_CODE_VERSION
 #define MIL_CODE_VERSION "dev"
@@ -668,6 +669,211 @@ int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *
   if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
   if (mil::launch_env_windows(h->ds, h->W, d_win, d_sigma, d_truth, stream))
     return fail(MIL_EHIP, "window copy launch failed");
+  return MIL_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Attention policy
+// ---------------------------------------------------------------------------
+namespace {
+
+struct PolicyWork {
+  int64_t prep, obs, mask, actions, total;
+};
+
+PolicyWork policy_work(int64_t A, int64_t K) {
+  PolicyWork w{};
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  w.prep = take(mil::kPolPrepBytes);
+  w.obs = take(K * 6 * 4);
+  w.mask = take(K);
+  w.actions = take(A * 4);
+  w.total = o;
+  return w;
+}
+
+int num_cus_env() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+  }
+  return n;
+}
+
+void prepared_ptrs(char *prep, __bf16 **wq, __bf16 **wo, __bf16 **w1, __bf16 **w2) {
+  __bf16 *b = (__bf16 *)prep;
+  *wq = b;
+  *wo = *wq + mil::kPolPrepWqkv;
+  *w1 = *wo + mil::kPolPrepWo;
+  *w2 = *w1 + mil::kPolPrepW1;
+}
+
+int policy_tile(int n_tok) {
+  const int at = mil::kPolRows / n_tok;
+  return at < mil::kPolMaxAgents ? at : mil::kPolMaxAgents;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t policy_num_params(void) { return mil::kPolNumParams; }
+
+int64_t policy_workspace_bytes(int64_t num_agents, int64_t num_tokens) {
+  return policy_work(num_agents > 0 ? num_agents : 1, num_tokens > 0 ? num_tokens : 1).total;
+}
+
+int policy_init(float *d_params, uint64_t seed, void *stream) {
+  if (!d_params) return fail(MIL_EINVAL, "null argument");
+  if (mil::launch_policy_init(d_params, seed, stream)) return fail(MIL_EHIP, "init launch failed");
+  return MIL_OK;
+}
+
+int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions, const float *d_obs,
+                   const uint8_t *d_mask, const float *d_params, float *d_logits,
+                   int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
+                   int64_t work_bytes, void *stream) {
+  if (A < 0 || n_tok < 1 || n_tok > mil::kPolMaxTok || n_agents < 1 || n_actions < 1 ||
+      n_actions > mil::kPolActions || (A % n_agents) != 0)
+    return fail(MIL_EINVAL, "need n_tok in 1..16, n_actions in 1..8, A a multiple of n_agents");
+  if (A == 0) return MIL_OK;
+  if (!d_obs || !d_mask || !d_params) return fail(MIL_EINVAL, "null argument");
+  const PolicyWork w = policy_work(A, A * n_tok);
+  if (!d_work || (((uintptr_t)d_work) & 255)) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (work_bytes < w.prep + mil::kPolPrepBytes) return fail(MIL_ESHAPE, "workspace too small");
+  char *ws = (char *)d_work;
+  mil::PolicyArgs a{};
+  __bf16 *wq, *wo, *w1, *w2;
+  prepared_ptrs(ws + w.prep, &wq, &wo, &w1, &w2);
+  if (mil::launch_policy_prepare(d_params, wq, wo, w1, w2, stream))
+    return fail(MIL_EHIP, "policy prepare failed");
+  a.A = A;
+  a.n_tok = n_tok;
+  a.agents_per_tile = policy_tile(n_tok);
+  a.obs = d_obs;
+  a.mask = d_mask;
+  a.params = d_params;
+  a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
+  a.logits = d_logits;
+  a.actions = d_actions;
+  a.n_agents = n_agents;
+  a.n_actions = n_actions;
+  a.t = t;
+  a.episode = episode;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.env_ids = nullptr;
+  if (mil::launch_policy(a, num_cus_env(), stream)) return fail(MIL_EHIP, "policy launch failed");
+  return MIL_OK;
+}
+
+int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
+                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
+                       void *d_work, int64_t work_bytes, void *stream) {
+  if (!h || !d_params) return fail(MIL_EINVAL, "null argument");
+  if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
+  if (h->P.ragged) return fail(MIL_EINVAL, "the policy needs a batch with fixed counts");
+  const int na = h->P.n_agents, n_tok = h->P.n_agents + h->P.n_targets;
+  if (n_tok > mil::kPolMaxTok || h->P.n_actions > mil::kPolActions)
+    return fail(MIL_EINVAL, "the policy supports at most 16 tokens per agent and 8 actions");
+  if (T < 1 || T > h->P.episode_len) return fail(MIL_EINVAL, "T must be in 1..episode_len");
+  if (episode >= (1ull << 28)) return fail(MIL_EINVAL, "episode must be < 2^28");
+  int rc = check_outputs(outs);
+  if (rc) return rc;
+  const int64_t A = h->aoff[h->E], K = h->koff[h->E];
+  const PolicyWork w = policy_work(A, K);
+  if (!d_work || (((uintptr_t)d_work) & 255)) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (work_bytes < w.total) return fail(MIL_ESHAPE, "workspace too small (policy_workspace_bytes)");
+  char *ws = (char *)d_work;
+  float *wobs = (float *)(ws + w.obs);
+  uint8_t *wmask = (uint8_t *)(ws + w.mask);
+  int32_t *wact = (int32_t *)(ws + w.actions);
+  __bf16 *wq, *wo, *w1, *w2;
+  prepared_ptrs(ws + w.prep, &wq, &wo, &w1, &w2);
+  hipStream_t st = (hipStream_t)stream;
+  if (capture) {
+    if (h->gexec) {
+      hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+    if (h->graph) {
+      hipGraphDestroy(h->graph);
+      h->graph = nullptr;
+    }
+    HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+  }
+  int lrc = mil::launch_policy_prepare(d_params, wq, wo, w1, w2, st);
+  mil::DevOut r0{};
+  r0.obs = wobs;
+  r0.obs_mask = wmask;
+  if (!lrc) lrc = mil::launch_reset(h->dp, h->ds, (uint32_t)episode, r0, st);
+  const mil::DevOut full = dev_out(outs);
+  const bool keep_obs = full.obs && full.obs_mask;
+  for (int32_t t = 0; t < T && !lrc; ++t) {
+    mil::PolicyArgs a{};
+    a.A = A;
+    a.n_tok = n_tok;
+    a.agents_per_tile = policy_tile(n_tok);
+    a.obs = (t == 0 || !keep_obs) ? wobs : full.obs + (int64_t)(t - 1) * K * 6;
+    a.mask = (t == 0 || !keep_obs) ? wmask : full.obs_mask + (int64_t)(t - 1) * K;
+    a.params = d_params;
+    a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
+    a.actions = wact;
+    a.n_agents = na;
+    a.n_actions = h->P.n_actions;
+    a.t = (uint32_t)t;
+    a.episode = (uint32_t)episode;
+    a.key0 = h->dp.key0;
+    a.key1 = h->dp.key1;
+    a.env_ids = h->ds.env_id;
+    lrc = mil::launch_policy(a, num_cus_env(), st);
+    if (lrc) break;
+    // this step's outputs: the caller's slice of step t, with the observation
+    // kept in the workspace when the caller does not record it
+    mil::DevOut o{};
+    auto slice = [&](auto *p, int64_t per) { return p ? p + (int64_t)t * per : p; };
+    o.obs = keep_obs ? slice(full.obs, K * 6) : wobs;
+    o.obs_mask = keep_obs ? slice(full.obs_mask, K) : wmask;
+    o.reward = slice(full.reward, h->E);
+    o.done = slice(full.done, h->E);
+    o.est = slice(full.est, h->poff[h->E] * 2);
+    o.est_valid = slice(full.est_valid, h->poff[h->E]);
+    o.gstate = slice(full.gstate, (A + h->toff[h->E]) * 6);
+    o.actions = slice(full.actions, A);
+    o.ranges = slice(full.ranges, h->poff[h->E]);
+    o.err = slice(full.err, h->toff[h->E]);
+    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                              (const mil::DevState *)(h->ws + h->off.devstate), t, 1,
+                              (uint32_t)episode, wact, o, st);
+  }
+  if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
+  if (capture) {
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(st, &g);
+    if (lrc || ec != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      return fail(MIL_EHIP, "policy graph capture failed: %s", hipGetErrorString(ec));
+    }
+    h->graph = g;
+    HIP_CHECK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    h->graph_T = T;
+    h->episode = (uint32_t)episode;
+    h->t = -1;
+    return MIL_OK;
+  }
+  if (lrc) return fail(MIL_EHIP, "policy rollout launch failed: %s", hipGetErrorString(hipGetLastError()));
+  h->episode = (uint32_t)episode;
+  h->t = T;
   return MIL_OK;
 }
 

@@ -1,0 +1,59 @@
+// Constants, parameter layout and launchers of the attention policy
+// (policy_kernels.hip). The FP32 parameter vector is, in order: token
+// embedding W [64][6], b [64]; per layer: ln1 gain, offset [64], Wqkv
+// [192][64] (Q, K, V rows), bqkv [192], Wo [64][64], bo [64], ln2 gain,
+// offset [64], W1 [256][64], b1 [256], W2 [64][256], b2 [64]; final
+// LayerNorm gain, offset [64]; head Wh [8][64], bh [8]. Weight matrices are
+// row-major (output, input).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mil {
+
+constexpr int kPolD = 64, kPolHeads = 4, kPolDh = 16, kPolF = 256, kPolLayers = 2;
+constexpr int kPolActions = 8;   // head rows (the first n_actions are used)
+constexpr int kPolMaxTok = 16;   // tokens per agent (agents + targets of an env)
+constexpr int kPolRows = 160;    // token rows per tile
+constexpr int kPolMaxAgents = 16;
+constexpr int kPolLdD = kPolD + 8, kPolLdF = kPolF + 8;
+// offsets inside one layer
+constexpr int kPolLn1G = 0, kPolLn1B = 64, kPolWqkv = 128, kPolBqkv = kPolWqkv + 3 * 64 * 64;
+constexpr int kPolWo = kPolBqkv + 192, kPolBo = kPolWo + 64 * 64, kPolLn2G = kPolBo + 64;
+constexpr int kPolLn2B = kPolLn2G + 64, kPolW1 = kPolLn2B + 64, kPolB1 = kPolW1 + 256 * 64;
+constexpr int kPolW2 = kPolB1 + 256, kPolB2 = kPolW2 + 64 * 256;
+constexpr int kPolLayerParams = kPolB2 + 64;
+// offsets in the whole vector
+constexpr int kPolOffEmbW = 0, kPolOffEmbB = 64 * 6, kPolOffLayer0 = kPolOffEmbB + 64;
+constexpr int kPolOffFinal = kPolOffLayer0 + kPolLayers * kPolLayerParams;
+constexpr int kPolLnfG = 0, kPolLnfB = 64, kPolWh = 128, kPolBh = kPolWh + kPolActions * 64;
+constexpr int kPolNumParams = kPolOffFinal + kPolBh + kPolActions;
+// MFMA-ready BF16 weights (elements)
+constexpr int64_t kPolPrepWqkv = (int64_t)kPolLayers * 3 * kPolD * kPolLdD;
+constexpr int64_t kPolPrepWo = (int64_t)kPolLayers * kPolD * kPolLdD;
+constexpr int64_t kPolPrepW1 = (int64_t)kPolLayers * kPolF * kPolLdD;
+constexpr int64_t kPolPrepW2 = (int64_t)kPolLayers * kPolD * kPolLdF;
+constexpr int64_t kPolPrepBytes = (kPolPrepWqkv + kPolPrepWo + kPolPrepW1 + kPolPrepW2) * 2;
+
+struct PolicyArgs {
+  int64_t A;                 // agents (fixed count per env)
+  int32_t n_tok;             // tokens per agent
+  int32_t agents_per_tile;
+  const float *obs;          // [A * n_tok][6]
+  const uint8_t *mask;       // [A * n_tok]
+  const float *params;       // FP32 master parameters
+  const __bf16 *wqkv, *wo, *w1, *w2;
+  float *logits;             // [A][8] or null
+  int32_t *actions;          // [A] or null
+  int64_t n_agents;          // agents per env
+  int32_t n_actions;
+  uint32_t t, episode, key0, key1;
+  const uint32_t *env_ids;   // packed env -> global id (null: identity)
+};
+
+int launch_policy_init(float *th, uint64_t seed, void *stream);
+int launch_policy_prepare(const float *th, __bf16 *wqkv, __bf16 *wo, __bf16 *w1, __bf16 *w2,
+                          void *stream);
+int launch_policy(const PolicyArgs &args, int num_cus, void *stream);
+
+}  // namespace mil

@@ -1,0 +1,94 @@
+"""Attention policy of the full-rollout workload: argument marshalling for the
+policy kernels in libmilrauv.so (see include/mi_lrauv.h, "Attention policy")."""
+import ctypes as C
+
+import torch
+
+from ._lib import EnvOutputs, check, lib, ptr
+from .env import Env, _stream
+
+_SIG = {
+    "policy_init": [C.c_void_p, C.c_uint64, C.c_void_p],
+    "policy_forward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
+                       C.c_void_p, C.c_int64, C.c_void_p],
+    "env_policy_rollout": [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p, C.POINTER(EnvOutputs),
+                           C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
+}
+_done = False
+
+
+def _l():
+    global _done
+    L = lib()
+    if not _done:
+        for k, v in _SIG.items():
+            getattr(L, k).argtypes = v
+            getattr(L, k).restype = C.c_int
+        L.policy_num_params.restype = C.c_int64
+        L.policy_workspace_bytes.argtypes = [C.c_int64, C.c_int64]
+        L.policy_workspace_bytes.restype = C.c_int64
+        _done = True
+    return L
+
+
+def num_params() -> int:
+    return int(_l().policy_num_params())
+
+
+def _work(A, K, device):
+    n = int(_l().policy_workspace_bytes(int(A), int(K)))
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, C.c_void_p(buf.data_ptr() + off), n
+
+
+def init_params(seed=0, device="cuda") -> torch.Tensor:
+    p = torch.empty(num_params(), dtype=torch.float32, device=device)
+    check(_l().policy_init(ptr(p), C.c_uint64(seed), _stream()))
+    return p
+
+
+def forward(obs, mask, params, n_tok, n_agents, n_actions=5, seed=0, t=0, episode=0):
+    """obs [A * n_tok, 6], mask [A * n_tok] -> (logits [A, 8], actions [A])."""
+    A = obs.shape[0] // n_tok
+    logits = torch.empty((A, 8), dtype=torch.float32, device=obs.device)
+    actions = torch.empty((A,), dtype=torch.int32, device=obs.device)
+    buf, w, n = _work(A, A * n_tok, obs.device)
+    check(_l().policy_forward(A, n_tok, n_agents, n_actions, ptr(obs.contiguous()),
+                              ptr(mask.contiguous()), ptr(params), ptr(logits), ptr(actions),
+                              C.c_uint64(seed), t, episode, w, n, _stream()))
+    del buf
+    return logits, actions
+
+
+class PolicyRollout:
+    """Closed-loop rollouts of a fixed-count Env driven by the policy."""
+
+    def __init__(self, env: Env, params: torch.Tensor):
+        self.env, self.params = env, params
+        self._buf, self._w, self._n = _work(env.A, env.K, env.device)
+
+    def run(self, T, episode=0, record=("reward", "done"), metrics=True):
+        out = self.env._alloc(record, T)
+        m = torch.zeros(8, dtype=torch.float64, device=self.env.device) if metrics else None
+        check(_l().env_policy_rollout(self.env._h, C.c_uint64(episode), int(T), ptr(self.params),
+                                      C.byref(Env._struct(out)), ptr(m), 0, self._w, self._n,
+                                      _stream()))
+        return out, m
+
+    def capture(self, T, episode=0, record=("reward", "done")):
+        self.graph_out = self.env._alloc(record, T)
+        self.graph_metrics = torch.zeros(8, dtype=torch.float64, device=self.env.device)
+        torch.cuda.current_stream().synchronize()
+        side = torch.cuda.Stream(device=self.env.device)
+        with torch.cuda.stream(side):
+            check(_l().env_policy_rollout(self.env._h, C.c_uint64(episode), int(T),
+                                          ptr(self.params), C.byref(Env._struct(self.graph_out)),
+                                          ptr(self.graph_metrics), 1, self._w, self._n,
+                                          _stream()))
+        self._side = side
+        return self.graph_out, self.graph_metrics
+
+    def launch(self):
+        self.env.launch_graph()

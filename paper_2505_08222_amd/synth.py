@@ -49,3 +49,26 @@ def window_targets(N: int, W: int, seed: int = 0, **kw) -> np.ndarray:
     dist = rng.uniform(20.0, kw.get("far", 3000.0), size=(N, 1))
     ang = rng.uniform(-np.pi, np.pi, size=(N, 1))
     return (a[:, :1, :] + np.stack([dist * np.cos(ang), dist * np.sin(ang)], axis=-1))[:, 0, :]
+
+
+def policy_tokens(A: int, n_agents: int, n_targets: int, seed: int = 0, p_missing: float = 0.2):
+    """Observation tokens [A, n_agents + n_targets, 6] and masks of the entity
+    layout (self, other agents, targets): random offsets (std 300 m), one-hot
+    types, random missing entries (the self token is always present)."""
+    rng = np.random.default_rng(seed)
+    T = n_agents + n_targets
+    x = np.zeros((A, T, 6), np.float32)
+    x[:, :, :2] = rng.normal(0, 300.0, (A, T, 2))
+    x[:, 0, :3] = 0
+    x[:, 0, 3] = 1
+    x[:, 1:n_agents, 4] = 1
+    x[:, n_agents:, 5] = 1
+    mask = (rng.random((A, T)) > p_missing).astype(np.uint8)
+    mask[:, 0] = 1
+    x[..., :3] *= mask[..., None]
+    return x, mask
+
+
+def policy_params(n: int, seed: int = 0, scale: float = 0.08) -> np.ndarray:
+    """A random FP32 parameter vector of length n (normal, std `scale`)."""
+    return np.random.default_rng(seed).normal(0, scale, n).astype(np.float32)

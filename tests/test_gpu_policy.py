@@ -1,0 +1,97 @@
+"""GPU checks of the attention policy: logits against the FP64 oracle on
+shared synthetic tokens and parameters (BF16 tolerance), action sampling
+agreement, initialisation statistics, and closed-loop rollout determinism /
+graph replay / consistency with the plain step."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2505_08222_amd.configs import env_config  # noqa: E402
+from paper_2505_08222_amd.synth import policy_params, policy_tokens  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n_agents,n_targets", [(5, 5), (2, 2), (1, 1), (8, 8)])
+def test_policy_logits_and_actions(orc, n_agents, n_targets):
+    from paper_2505_08222_amd import policy
+    A = 64 * n_agents
+    x, mask = policy_tokens(A, n_agents, n_targets, seed=n_agents * 10 + n_targets)
+    th = policy_params(orc.policy_num_params(), seed=3)
+    n_tok = n_agents + n_targets
+    seed, t, ep = 77, 5, 2
+    logits, actions = policy.forward(torch.from_numpy(x.reshape(-1, 6)).cuda(),
+                                     torch.from_numpy(mask.reshape(-1)).cuda(),
+                                     torch.from_numpy(th).cuda(), n_tok, n_agents, 5,
+                                     seed=seed, t=t, episode=ep)
+    g = logits.cpu().numpy()
+    ref = orc.policy_forward(x.astype(np.float64), mask, th.astype(np.float64))
+    err = np.abs(g - ref).max() / max(1.0, np.abs(ref).max())
+    assert err < 3e-2, err
+    # sampling: u from Philox(t, env, agent, 4 | episode << 4) with key = seed
+    env = np.arange(A) // n_agents
+    ctr = np.stack([np.full(A, t), env, np.arange(A) % n_agents, np.full(A, (ep << 4) | 4)],
+                   1).astype(np.uint32)
+    u = np.array([orc.u01(int(w)) for w in orc.philox(ctr, seed)[:, 0]])
+    want = np.array([orc.policy_sample(ref[a], 5, u[a]) for a in range(A)])
+    got = actions.cpu().numpy()
+    agree = (got == want).mean()
+    assert agree >= 0.95, agree
+    # a disagreement only where u sits within the logit error of a boundary
+    for a in np.flatnonzero(got != want):
+        p = np.exp(ref[a, :5] - ref[a, :5].max())
+        c = np.cumsum(p / p.sum())
+        assert np.min(np.abs(c - u[a])) < 0.05
+
+
+def test_policy_init_statistics():
+    from paper_2505_08222_amd import policy
+    p = policy.init_params(1).cpu().numpy()
+    p2 = policy.init_params(1).cpu().numpy()
+    np.testing.assert_array_equal(p, p2)
+    D = 64
+    emb = p[:D * 6]
+    assert np.abs(emb).max() <= np.sqrt(6 / (6 + D)) and abs(emb.mean()) < 0.02
+    assert (p[D * 6:D * 7] == 0).all()  # embedding bias
+    layer0 = D * 7
+    assert (p[layer0:layer0 + D] == 1).all() and (p[layer0 + D:layer0 + 2 * D] == 0).all()
+
+
+def test_policy_rollout_deterministic_and_graph():
+    from paper_2505_08222_amd import policy
+    from paper_2505_08222_amd.env import Env
+    cfg = env_config("policy", episode_len=40)
+    E, T = 512, 40
+    params = policy.init_params(0)
+    rec = ("obs", "obs_mask", "reward", "done", "actions", "gstate")
+    a = Env(cfg, E, seed=0)
+    ra, ma = policy.PolicyRollout(a, params).run(T, record=rec)
+    b = Env(cfg, E, seed=0)
+    pr = policy.PolicyRollout(b, params)
+    gout, gm = pr.capture(T, record=rec)
+    for rep in range(2):
+        for v in gout.values():
+            v.zero_()
+        pr.launch()
+        torch.cuda.synchronize()
+        for k in rec:
+            np.testing.assert_array_equal(gout[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
+        np.testing.assert_array_equal(gm.cpu().numpy(), ma.cpu().numpy())
+    acts = ra["actions"].cpu().numpy()
+    assert acts.min() >= 0 and acts.max() <= 4
+    # the environment driven by the recorded actions reproduces the rollout
+    c = Env(cfg, E, seed=0)
+    c.reset(0)
+    rc = c.rollout(T, actions=ra["actions"], record=rec)
+    for k in rec:
+        np.testing.assert_array_equal(rc[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
+
+
+def test_policy_rejects_ragged():
+    from paper_2505_08222_amd import policy
+    from paper_2505_08222_amd._lib import MilError
+    from paper_2505_08222_amd.env import Env
+    env = Env(env_config("ragged"), 100, seed=0)
+    with pytest.raises(MilError):
+        policy.PolicyRollout(env, policy.init_params(0)).run(5)
