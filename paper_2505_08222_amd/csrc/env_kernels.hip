@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <cmath>
+
 #include "env_internal.h"
 #include "learned_internal.h"
 #include "ls_device.h"
@@ -55,6 +57,16 @@ __device__ __forceinline__ float wrap_angle(float a) {
 }
 
 __device__ __forceinline__ float norm2(float dx, float dy) { return fast_sqrt(fmaf(dx, dx, dy * dy)); }
+
+// 1/d for finite d > 0: the hardware estimate refined by two Newton steps
+// (each doubles the number of correct bits), instead of the long IEEE divide
+// sequence.
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
 
 // sin and cos of an angle in radians via the revolution-based hardware ops.
 __device__ __forceinline__ void sincos_rad(float a, float &s, float &c) {
@@ -177,9 +189,13 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 // ---------------------------------------------------------------------------
 // Rollout: T steps per launch. S = largest supported entity count per env
 // (agents and targets), WC = register window capacity (W <= WC), G = lanes
-// per agent.
+// per agent. FULL = false is the lean form for the common case: actions
+// drawn in-kernel, only obs / obs_mask / reward / done recorded, no
+// detection cut, no dropped broadcasts, no Gauss-Newton refinement. It gives
+// the same bits as the full form on those outputs and carries none of the
+// other paths' pointers and registers.
 // ---------------------------------------------------------------------------
-template <int S, int WC, int G>
+template <int S, int WC, int G, bool FULL>
 __global__ void __launch_bounds__(256)
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
                uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
@@ -220,6 +236,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   const float vdt = p.agent_speed * p.dt;
   const int nB = (nt + 1) >> 1;
   const double tau = (double)p.tau;
+  const double invW = 1.0 / (double)W;
   const float kInf = __int_as_float(0x7f800000);
   const float kNaN = __int_as_float(0x7fc00000);
   float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
@@ -271,7 +288,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
     const u32x4 xa = philox4x32_10(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
     int act;
-    if (actions) {
+    if (FULL && actions) {
       act = actions[(int64_t)step * o.A + aidx];
       if (act < 0 || act >= p.n_actions) {
         act = -1;
@@ -293,7 +310,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       ax = fmaf(vdt, cs, ax);
       ay = fmaf(vdt, sn, ay);
     }
-    const bool comm_ok = !(u01(xa.w) < p.comm_loss_p);
+    const bool comm_ok = FULL ? !(u01(xa.w) < p.comm_loss_p) : true;
 
     // ---- targets owned by this lane (blocks of two): heading random walk
     for (int q = r; q < nB; q += lpe) {
@@ -348,7 +365,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           if (j < MT && j < nt && (j % G) == g) {
             const float dist = norm2(ax - tpx[j], ay - tpy[j]);
             const float rr = fmaf(sig_r, zr[m], dist);
-            rnew[j / G] = (dist <= p.det_range) ? rr : kNaN;
+            rnew[j / G] = (!FULL || dist <= p.det_range) ? rr : kNaN;
           }
         }
       }
@@ -383,7 +400,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           mx += (double)hx[k];
           my += (double)hy[k];
         }
-      const double invn = 1.0 / (double)filled;
+      const double invn = (filled == W) ? invW : 1.0 / (double)filled;  // filled is uniform
       mx *= invn;
       my *= invn;
       bool full[NPL];
@@ -416,26 +433,28 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       }
       const double det = fma(sxx, syy, -sxy * sxy), tr = sxx + syy;
       const bool agent_ok = det > tau * tr * tr;
-      const double hdet = agent_ok ? 0.5 / det : 0.0;
+      const double hdet = agent_ok ? 0.5 * recip(det) : 0.0;
 #pragma unroll
       for (int sl = 0; sl < NPL; ++sl) {
         const int j = g + G * sl;
         if (j < nt) {
-          if (full[sl] && p.gn_iters == 0) {
+          if (full[sl] && (!FULL || p.gn_iters == 0)) {
             if (agent_ok) {
               ex[sl] = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
               ey[sl] = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
               evb |= 1u << sl;
             }
-          } else {
+          } else if (FULL) {
             pending |= 1u << sl;
+          } else if (active) {
+            status |= kStatusNonFinite;  // lean form: every range is finite unless the state is not
           }
         }
       }
     }
     // general path: missing entries or Gauss-Newton refinement (one copy of
     // the solver, the tracker's history selected into a scratch row)
-    while (pending) {
+    while (FULL && pending) {
       const int sl = __builtin_ctz(pending);
       pending &= pending - 1;
       float row[WC];
@@ -496,7 +515,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         const int src = base_lane + k * G;
         agx[k] = __shfl(ax, src);
         agy[k] = __shfl(ay, src);
-        agc[k] = __shfl((int)comm_ok, src);
+        agc[k] = FULL ? __shfl((int)comm_ok, src) : 1;
       }
     }
     bool crash = false;
@@ -511,7 +530,55 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     const bool done = (t + 1u == (uint32_t)p.episode_len);
 
     // ---- outputs
-    if (active) {
+    if constexpr (!FULL) {
+      if (active) {
+        if (r == 0) {
+          acc_rew += (double)rew;
+          acc_crash += crash ? 1 : 0;
+#pragma unroll
+          for (int j = 0; j < MT; ++j)
+            if (j < nt && ej[j] < kInf) {
+              acc_err += (double)ej[j];
+              acc_err2 += (double)ej[j] * (double)ej[j];
+              acc_cnt += 1;
+            }
+          if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
+          if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
+        }
+        const int64_t kb = (int64_t)step * o.K + kbase;
+        float *ob = o.obs ? o.obs + kb * 6 : nullptr;
+        uint8_t *om = o.obs_mask ? o.obs_mask + kb : nullptr;
+        if (g == 0) {
+          if (ob) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
+          if (om) om[0] = 1;
+        }
+#pragma unroll
+        for (int m = 1; m < MA; ++m) {
+          if (m < na && (m % G) == g) {
+            const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
+            const float ox = before ? agx[m - 1] : agx[m];
+            const float oy = before ? agy[m - 1] : agy[m];
+            const float dx = ox - ax, dy = oy - ay;
+            const bool ok = norm2(dx, dy) <= p.comm_range;
+            if (ob) store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
+            if (om) om[m] = ok ? 1 : 0;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          if (j < nt && (j % G) == g) {
+            const int sl = j / G;
+            const bool ok = (evb >> sl) & 1u;
+            if (ob)
+              store_token(ob + (na + j) * 6, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f,
+                          0.0f, 0.0f, 1.0f);
+            if (om) om[na + j] = ok ? 1 : 0;
+          }
+        }
+        if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
+          status |= kStatusNonFinite;
+      }
+    } else if (active) {
       if (r == 0) {
         acc_rew += (double)rew;
         acc_crash += crash ? 1 : 0;
@@ -772,13 +839,13 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
   return 0;
 }
 
-template <int S, int WC, int G>
+template <int S, int WC, int G, bool FULL>
 static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
                             const DevState *s, int32_t t0, int32_t T, uint32_t episode,
                             const int32_t *actions, const DevOut &o, hipStream_t st) {
   const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
   const size_t lds = (size_t)waves_per_block * 64 * S * sizeof(float4);
-  hipLaunchKernelGGL((rollout_kernel<S, WC, G>), dim3(blocks), dim3(64 * waves_per_block), lds,
+  hipLaunchKernelGGL((rollout_kernel<S, WC, G, FULL>), dim3(blocks), dim3(64 * waves_per_block), lds,
                      st, p, s, num_waves, t0, T, episode, actions, o);
   return check_launch();
 }
@@ -795,10 +862,16 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   o.Tt = hs.Tt;
   o.P = hs.P;
   o.K = hs.K;
+  // the lean form applies when none of the full form's extra paths is asked for
+  const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
+                    !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
+                    p.comm_loss_p == 0.0f && p.gn_iters == 0;
 #define MIL_ROLL(SC, WCV, GV)                                                                 \
   if (size_class == SC && wcap == WCV && G == GV)                                            \
-    return launch_rollout_t<SC, WCV, GV>(waves_per_block, num_waves, p, s, t0, T, episode,   \
-                                         actions, o, st);
+    return lean ? launch_rollout_t<SC, WCV, GV, false>(waves_per_block, num_waves, p, s, t0, \
+                                                       T, episode, actions, o, st)           \
+                : launch_rollout_t<SC, WCV, GV, true>(waves_per_block, num_waves, p, s, t0,  \
+                                                      T, episode, actions, o, st);
   MIL_ROLL(2, 10, 1)
   MIL_ROLL(2, 10, 2)
   MIL_ROLL(2, 16, 1)

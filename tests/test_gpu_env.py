@@ -153,6 +153,28 @@ def test_full_size_ragged_sampled(orc):
     print("ragged-full", rep)
 
 
+@pytest.mark.parametrize("cfgname,E,T", [("batched", 4096, 500), ("ragged", 3000, 120)])
+def test_lean_form_matches_full_bitwise(cfgname, E, T):
+    """Recording only obs, obs_mask, reward and done (the benchmark's launch
+    form, compiled without the other outputs' paths) gives the same bits,
+    final state and metrics as the full form that the parity tests hold to
+    the oracle."""
+    cfg = env_config(cfgname, episode_len=T)
+    lean_env = _env(cfg, E, seed=0)
+    full_env = _env(cfg, E, seed=0)
+    lean_env.reset(0)
+    full_env.reset(0)
+    lean = _np(lean_env.rollout(T, record=("obs", "obs_mask", "reward", "done")))
+    full = _np(full_env.rollout(T, record=ALL))
+    for k in lean:
+        np.testing.assert_array_equal(lean[k], full[k], err_msg=k)
+    for a, b in zip(lean_env.state(), full_env.state()):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    np.testing.assert_array_equal(lean_env.metrics().cpu().numpy(),
+                                  full_env.metrics().cpu().numpy())
+    assert lean_env.status() == 0
+
+
 def test_step_equals_rollout_bitwise():
     cfg = env_config("ragged", episode_len=40)
     E, T = 500, 40
