@@ -33,12 +33,62 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, env, T, budget_s):
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload
-    (whole episodes of the first envs in packed order, chunk by chunk, until
-    the time budget is used)."""
-    import numpy as np
+# Sources each dominant kernel is built from; the HBM traffic measured with
+# rocprofv3 counters is reported only while their hash is the one it was
+# measured on.
+KERNEL_SOURCES = {
+    "rollout_kernel": ["env_kernels.hip", "env_internal.h", "ls_device.h", "rng.h"],
+    "policy_kernel": ["policy_kernels.hip", "policy_internal.h", "mfma_tile.h", "rng.h"],
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_counters.md")
 
+
+def kernel_version(kernel):
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2505_08222_amd", "csrc", name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    copy-kernel calibration) from the committed counter summary, or None when
+    there is none for this workload or the kernel changed since."""
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    ver = kernel_version(kernel)
+    pat = re.compile(r"^traffic\s+(\S+)\s+(\S+)\s+(\S+)\s+(\d+)\s+(\d+)\s*$")
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            m = pat.match(line.strip())
+            if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == ver:
+                return int(m.group(4)) + int(m.group(5))
+    return None
+
+
+def copy_probe():
+    """A plain 256 MiB device-to-device copy (the calibration kernel for the
+    FETCH_SIZE / WRITE_SIZE counters): 3 launches."""
+    import torch
+    n = 64 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
+def cpu_baseline(cfg, env, T, budget_s):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload:
+    whole episodes of the envs in packed order, 256 envs per call, recording
+    the same outputs as the GPU run; when every env is done it goes on with
+    the next episode (a new reset draw) until the time budget is used."""
     from oracle import oracle as orc
 
     threads = min(os.cpu_count() or 1, 16)
@@ -46,21 +96,105 @@ def cpu_baseline(cfg, env, T, budget_s):
     ids, na, nt = env.order["env_ids"], env.n_agents, env.n_targets
     chunk = 256
     done_envsteps = 0
-    done_envs = 0
+    calls = 0
     t0 = time.perf_counter()
-    k = 0
-    while k < len(ids) and time.perf_counter() - t0 < budget_s:
+    k, episode = 0, 0
+    while time.perf_counter() - t0 < budget_s:
         sl = slice(k, min(k + chunk, len(ids)))
-        orc.rollout(cfg, ids[sl], na[sl], nt[sl], env.seed, T,
+        orc.rollout(cfg, ids[sl], na[sl], nt[sl], env.seed, T, episode=episode,
                     records=("reward", "done", "obs", "obs_mask"), n_threads=threads)
-        done_envs += sl.stop - sl.start
         done_envsteps += (sl.stop - sl.start) * T
+        calls += 1
         k = sl.stop
+        if k >= len(ids):
+            k, episode = 0, episode + 1
     el = time.perf_counter() - t0
+    envs_run = done_envsteps // T
     return {"value": done_envsteps / el, "unit": "env-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{done_envs} of {len(ids)} envs x {T} steps (whole episodes, same seed and "
-                      f"config), FP64 C with OpenMP over envs, {el:.1f} s"}
+            "sample": f"{envs_run} env-episodes x {T} steps ({envs_run / len(ids):.2f} passes over "
+                      f"the {len(ids)} envs, same seed and config, obs/mask/reward/done recorded), "
+                      f"FP64 C with OpenMP over envs, {el:.1f} s"}
+
+
+def cpu_baseline_policy(cfg, env, params, budget_s):
+    """The oracle on a bounded sample of the policy workload: the first 16
+    envs for 50 steps (oracle environment rollout, OpenMP over envs), then
+    the oracle policy forward (single thread) on every agent's observation of
+    every step, repeated until the budget is used; env-steps/s of the sum."""
+    import numpy as np
+
+    from oracle import oracle as orc
+
+    threads = min(os.cpu_count() or 1, 16)
+    orc.lib()
+    E, T = 16, 50
+    ids, na, nt = env.order["env_ids"][:E], env.n_agents[:E], env.n_targets[:E]
+    n_tok = int(na[0] + nt[0])
+    th = params.detach().cpu().numpy().astype(np.float64)
+    t_env = t_pol = 0.0
+    done = 0
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s:
+        t0 = time.perf_counter()
+        ref = orc.rollout(cfg, ids, na, nt, env.seed, T, episode=done,
+                          records=("obs", "obs_mask", "reward", "done"), n_threads=threads)
+        t1 = time.perf_counter()
+        for t in range(T):
+            orc.policy_forward(ref["obs"][t].reshape(-1, n_tok, 6),
+                               ref["obs_mask"][t].reshape(-1, n_tok), th)
+        t2 = time.perf_counter()
+        t_env += t1 - t0
+        t_pol += t2 - t1
+        done += 1
+    return {"value": done * E * T / (t_env + t_pol), "unit": "env-steps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{done} x ({E} envs x {T} steps): oracle env rollout (FP64 C, OpenMP over "
+                      f"envs, {t_env:.1f} s) + oracle policy forward on every agent-step (FP64 C, one "
+                      f"thread, {t_pol:.1f} s)"}
+
+
+def env_sweep(args, cfgname="batched", sizes=(4096, 16384, 65536, 262144, 1048576), T=100):
+    """Env-count sweep of the rollout kernel at one shape (2 agents x 2
+    targets): where the path turns from latency- to bandwidth-bound. Each
+    point: autotuned mapping, T-step rollout recording obs/mask/reward/done,
+    median of 5 event-timed launches."""
+    import numpy as np
+    import torch
+
+    from paper_2505_08222_amd.configs import env_config
+    from paper_2505_08222_amd.env import Env
+
+    cfg = env_config(cfgname, episode_len=T)
+    stream = torch.cuda.current_stream()
+    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.jsonl")
+    points = []
+    for E in sizes:
+        env = Env(cfg, E, seed=0)
+        env.reset(0)
+        if not args.no_autotune:
+            env.autotune(probe_steps=20, cache_path=cache)
+        out = env._alloc(RECORD, T)
+        durs = []
+        for _ in range(6):
+            env.reset(0)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            env.rollout(T, record=RECORD, out=out)
+            b.record(stream)
+            torch.cuda.synchronize()
+            durs.append(a.elapsed_time(b))
+        ms = float(np.median(durs[1:]))
+        alg = float(bytes_per_env_step(env.n_agents.astype(np.int64),
+                                       env.n_targets.astype(np.int64)).sum()) * T
+        gbs = alg / (ms / 1e3) / 1e9
+        points.append({"envs": E, "steps": T, "kernel_ms": ms, "env_steps_per_s": E * T / (ms / 1e3),
+                       "hbm_gbps_algorithmic": gbs, "frac": gbs / HBM_PEAK_GBS,
+                       "lanes_per_agent": env.get_mapping()[0], "waves_per_block": env.get_mapping()[1]})
+        log(f"[sweep] {E} envs: {ms:.3f} ms, {gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.1%})")
+        del out, env
+        torch.cuda.empty_cache()
+    return points
 
 
 def bench_learned(args):
@@ -90,12 +224,17 @@ def bench_learned(args):
         f"({time.perf_counter() - t0:.1f} s)")
     x, frame = learned.features(tr["win"])
     y = learned.targets(frame, tr["exact"])
-    keep = y.norm(dim=1) <= 2.0
+    # labels the network can learn: exact estimates within 2x the mean range,
+    # from windows whose agent track is not near-collinear (the exact solve is
+    # noise there, and those windows fall back to it anyway)
+    kap_tr = window_condition(tr["win"])
+    keep = (y.norm(dim=1) <= 2.0) & (kap_tr <= 1e3)
     x, y = x[keep].contiguous(), y[keep].contiguous()
-    log(f"[learned] training set {x.shape[0]} windows (exact estimate within 2x the mean range)")
+    log(f"[learned] training set {x.shape[0]} windows (exact estimate within 2x the mean range, "
+        f"condition number of the track <= 1e3)")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    params, hist = learned.train(x, y, epochs=2, batch=8192, lr=2e-3, lr_final=5e-5, seed=0,
+    params, hist = learned.train(x, y, epochs=8, batch=8192, lr=2e-3, lr_final=3e-5, seed=0,
                                  log=lambda m: None)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
@@ -130,8 +269,16 @@ def bench_learned(args):
     ve = v_ex.cpu().numpy().astype(bool)
     acc = flag == 1
     rng_ = np.hypot(*(pt - win[:, :, :2].mean(1).cpu().numpy()).T)
+    kap = window_condition(win).cpu().numpy()
     d_me = np.hypot(*(pm - pe).T)
     bins = [(0, 100), (100, 500), (500, 1e9)]
+    by_kappa = {}
+    for lo, hi in [(1, 10), (10, 100), (100, 1e3), (1e3, np.inf)]:
+        m = acc & ve & (kap >= lo) & (kap < hi)
+        mt = ve & (kap >= lo) & (kap < hi)
+        by_kappa[f"kappa {lo:g}-{hi:g}"] = {
+            "windows": int(mt.sum()), "accepted_frac": float(m.sum() / max(mt.sum(), 1)),
+            "rms_learned_vs_exact_m": float(np.sqrt(np.mean(d_me[m] ** 2))) if m.any() else None}
     by_bin = {}
     for lo, hi in bins:
         m = acc & ve & (rng_ >= lo) & (rng_ < hi)
@@ -162,12 +309,28 @@ def bench_learned(args):
         "rms_learned_vs_exact_m_accepted": float(np.sqrt(np.mean(d_me[acc & ve] ** 2))),
         "median_learned_vs_exact_m_accepted": float(np.median(d_me[acc & ve])),
         "by_range": by_bin,
+        "by_condition": by_kappa,
         "train": {"seconds": train_s, "loss_first": hist[0][1], "loss_last": hist[-1][1]},
         "mfma": {"forward_tflops": flops / (ms_fwd / 1e3) / 1e12, "peak_tflops": 2500.0,
                  "frac": flops / (ms_fwd / 1e3) / 1e12 / 2500.0},
         "gauss_newton_vs_truth_rms_m": float(np.sqrt(np.mean(np.hypot(*(pg[ve] - pt[ve]).T) ** 2))),
     }
     return res
+
+
+def window_condition(win):
+    """Condition number of S = sum_k u_k u_k^T (agent positions about their
+    centroid) for each window [N, W, 3]."""
+    import torch
+    a = win[..., :2].double()
+    u = a - a.mean(dim=1, keepdim=True)
+    sxx = (u[..., 0] ** 2).sum(1)
+    syy = (u[..., 1] ** 2).sum(1)
+    sxy = (u[..., 0] * u[..., 1]).sum(1)
+    tr, det = sxx + syy, sxx * syy - sxy * sxy
+    disc = torch.sqrt(torch.clamp(tr * tr / 4 - det, min=0.0))
+    lmax, lmin = tr / 2 + disc, tr / 2 - disc
+    return (lmax / torch.clamp(lmin, min=1e-300)).float()
 
 
 def policy_flops_per_agent_step(n_tok, d=64, heads=4, ffn=256, layers=2, n_out=8):
@@ -228,6 +391,10 @@ def bench_policy(args):
     flops = policy_flops_per_agent_step(n_tok) * env.A
     tflops = flops / (pol_ms / 1e3) / 1e12
     m = gm.cpu().numpy()
+    extra = {}
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        extra["cpu_baseline"] = cpu_baseline_policy(cfg, env, params, args.cpu_seconds)
     return {
         "metric": METRIC, "value": E * T * args.steps / elapsed, "unit": "env-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -238,10 +405,13 @@ def bench_policy(args):
                                "per step, one HIP graph", "envs": E, "episode_steps": T},
         "agent_steps_per_s": env.A * T * args.steps / elapsed,
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": tflops / 2500.0, "traffic": None, "kernel": "policy_kernel",
+                     "frac": tflops / 2500.0,
+                     "traffic": measured_traffic("policy_kernel", "policy") if E == c["num_envs"] else None,
+                     "kernel": "policy_kernel",
                      "kernel_ms": pol_ms, "flops_per_launch": flops},
         "episode_metrics": {"mean_reward": float(m[0] / max(m[6], 1)),
                             "crash_steps": float(m[4])},
+        **extra,
     }
 
 
@@ -254,8 +424,12 @@ def main():
                     choices=["plain", "batched", "ragged", "learned", "policy"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the env-count sweep that follows the batched workload")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain copy kernel used to calibrate HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -269,6 +443,9 @@ def main():
     from paper_2505_08222_amd.configs import CONFIGS, env_config
     from paper_2505_08222_amd.env import Env
 
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.workload == "learned":
         print(json.dumps(bench_learned(args)), flush=True)
         return
@@ -356,7 +533,8 @@ def main():
         "hbm_gbps_algorithmic": achieved,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("rollout_kernel", args.workload) if E == c["num_envs"] else None,
             "kernel": "rollout_kernel", "kernel_ms": kern_ms, "bytes_per_launch": alg_bytes,
         },
         "episode_metrics": {
@@ -365,6 +543,12 @@ def main():
             "crash_steps": float(m[4]), "lost_targets": float(m[5]),
         },
     }
+    if result["roofline"]["traffic"] is not None:
+        result["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
+    if args.workload == "batched" and not args.no_sweep and E == c["num_envs"]:
+        del out, gout
+        torch.cuda.empty_cache()
+        result["sweep"] = env_sweep(args)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(cfg, env, T, args.cpu_seconds)

@@ -41,11 +41,11 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // Eq. (1): 1 below eps_min, exp(-2t/(1-t)) with t = (e-eps_min)/(eps_max-eps_min)
 // up to eps_max, 0 from eps_max on (the limit of the exponential there).
-__device__ __forceinline__ float tracking_reward(float e, float emin, float emax) {
+__device__ __forceinline__ float tracking_reward(float e, float emin, float emax, float inv_span) {
   if (e < emin) return 1.0f;
   if (!(e < emax)) return 0.0f;
-  const float t = (e - emin) / (emax - emin);
-  return __expf(-2.0f * t / (1.0f - t));
+  const float t = (e - emin) * inv_span;  // inv_span = 1 / (emax - emin)
+  return __expf(-2.0f * t * __builtin_amdgcn_rcpf(1.0f - t));
 }
 
 // A heading is an angle: kept in [-pi, pi] after every update.
@@ -79,6 +79,14 @@ __device__ __forceinline__ void store_token(float *dst, float dx, float dy, floa
   d[0] = make_float2(dx, dy);
   d[1] = make_float2(0.0f, is_self);
   d[2] = make_float2(is_agent, is_target);
+}
+
+// A Philox draw whose key schedule is rebuilt at the call (a few scalar adds)
+// instead of being held in 20 scalar registers across the step loop.
+__device__ __forceinline__ u32x4 draw(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                      uint32_t key0, uint32_t key1) {
+  asm volatile("" : "+s"(key0), "+s"(key1));
+  return philox4x32_10(c0, c1, c2, c3, key0, key1);
 }
 
 // Element (g + G*sl) of a per-env array held with compile-time indices.
@@ -204,6 +212,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   constexpr int NQ = (MT + 3) / 4;       // range-noise draws per agent
   // per wavefront: the targets of its envs, (x, y, heading, speed)
   extern __shared__ float4 lds_targets[];
+  __shared__ float lds_dpsi[4][8];  // per wavefront: the action table
 
   const int lane = threadIdx.x & 63;
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -237,6 +246,8 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   const int nB = (nt + 1) >> 1;
   const double tau = (double)p.tau;
   const double invW = 1.0 / (double)W;
+  const float inv_span = 1.0f / (p.eps_max - p.eps_min);
+  const float inv_nt = 1.0f / (float)nt;
   const float kInf = __int_as_float(0x7f800000);
   const float kNaN = __int_as_float(0x7fc00000);
   float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
@@ -280,13 +291,14 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     acc_crash = s.miacc[2 * e + 1];
   }
   uint32_t status = 0;
+  if (lane < 8) lds_dpsi[wib][lane] = p.dpsi[lane];
   wave_lds_fence();
 
   for (int step = 0; step < T; ++step) {
     const uint32_t t = (uint32_t)(t0 + step);
 
     // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
-    const u32x4 xa = philox4x32_10(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
+    const u32x4 xa = draw(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
     int act;
     if (FULL && actions) {
       act = actions[(int64_t)step * o.A + aidx];
@@ -299,10 +311,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     }
     float za, zb;
     normal2(xa.y, xa.z, za, zb);
-    float dpsi = 0.0f;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (act == q) dpsi = p.dpsi[q];
+    const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
     apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
     {
       float sn, cs;
@@ -315,7 +324,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     // ---- targets owned by this lane (blocks of two): heading random walk
     for (int q = r; q < nB; q += lpe) {
       const u32x4 xt =
-          philox4x32_10(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
+          draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
       float zt[2];
       normal2(xt.x, xt.y, zt[0], zt[1]);
 #pragma unroll
@@ -354,8 +363,8 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 #pragma unroll
     for (int q4 = 0; q4 < NQ; ++q4) {
       if (4 * q4 < nt) {
-        const u32x4 xr = philox4x32_10(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4,
-                                       c3meas, p.key0, p.key1);
+        const u32x4 xr = draw(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4, c3meas,
+                              p.key0, p.key1);
         float zr[4];
         normal2(xr.x, xr.y, zr[0], zr[1]);
         normal2(xr.z, xr.w, zr[2], zr[3]);
@@ -498,11 +507,11 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         for (int k = 0; k < MA; ++k) {
           if (k < na) v = fminf(v, __shfl(errp[j / G], base_lane + k * G + (j % G)));
         }
-        rsum += tracking_reward(v, p.eps_min, p.eps_max);
+        rsum += tracking_reward(v, p.eps_min, p.eps_max, inv_span);
       }
       ej[j] = v;
     }
-    float rew = rsum / (float)nt;
+    float rew = rsum * inv_nt;
     // ---- agents' positions and broadcasts; crash penalty
     float agx[MA], agy[MA];
     int agc[MA];

@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include "learned_internal.h"
+#include "mfma_tile.h"
 #include "ls_device.h"
 #include "rng.h"
 
@@ -375,14 +376,16 @@ forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Inference: persistent blocks keep the BF16 weights in LDS and loop over
-// tiles of 64 windows: features -> MLP -> decode -> residual test. Windows
-// failing the test (or with missing entries) are appended to a list that the
-// fallback kernel solves exactly.
+// Inference: persistent blocks (two per CU) loop over tiles of 64 windows.
+// The tile's windows (contiguous in memory) are staged in LDS with coalesced
+// loads; features, the two hidden layers (column-stationary MFMA, weight
+// fragments from L2 in registers), the output layer, the decode and the
+// residual test all read that copy. Windows failing the test (or with
+// missing entries) are appended, one atomic per wavefront, to a list that
+// the fallback kernel solves exactly.
 // ---------------------------------------------------------------------------
 struct InferLds {
-  __bf16 w1[kHidden][kLdIn];
-  __bf16 w2[kHidden][kLdH];
+  float win[64 * kMaxW * 3];
   float w3[2][kHidden];
   float b1[kHidden], b2[kHidden], b3[4];  // b3 padded: keeps x 16-byte aligned
   __bf16 x[64][kIn + 8];
@@ -394,8 +397,9 @@ struct InferLds {
 };
 
 static_assert(offsetof(InferLds, x) % 16 == 0, "MFMA operands need 16-byte rows");
-static_assert(offsetof(InferLds, h1) % 16 == 0, "MFMA operands need 16-byte rows");
-static_assert(sizeof(InferLds) <= 160 * 1024, "LDS");
+static_assert(offsetof(InferLds, h1) % 16 == 0 && offsetof(InferLds, h2) % 16 == 0,
+              "MFMA operands need 16-byte rows");
+static_assert(sizeof(InferLds) <= 80 * 1024, "two inference blocks per CU");
 
 __global__ void __launch_bounds__(256)
 infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *__restrict__ th,
@@ -406,24 +410,29 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
   extern __shared__ __align__(16) unsigned char smem[];
   InferLds &L = *reinterpret_cast<InferLds *>(smem);
   const int tid = threadIdx.x;
-  for (int e = tid; e < kHidden * kLdIn; e += blockDim.x) (&L.w1[0][0])[e] = w1g[e];
-  for (int e = tid; e < kHidden * kLdH; e += blockDim.x) (&L.w2[0][0])[e] = w2g[e];
   for (int e = tid; e < 2 * kHidden; e += blockDim.x) (&L.w3[0][0])[e] = th[kOffW3 + e];
   for (int e = tid; e < kHidden; e += blockDim.x) {
     L.b1[e] = th[kOffB1 + e];
     L.b2[e] = th[kOffB2 + e];
   }
   if (tid < 2) L.b3[tid] = th[kOffB3 + tid];
-  __syncthreads();
   const int64_t ntiles = (N + 63) / 64;
+  const int wlen = W * 3;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t s0 = tile * 64;
+    const int nw = (N - s0) < 64 ? (int)(N - s0) : 64;  // windows in this tile
+    {
+      const float *src = win + s0 * wlen;
+      for (int e = tid; e < nw * wlen; e += blockDim.x) L.win[e] = src[e];
+    }
+    __syncthreads();
     // features: thread s < 64 takes window s0 + s
     if (tid < 64) {
       float x[kIn], fr[5];
       int ok = 0;
-      if (s0 + tid < N) ok = window_features(win + (s0 + tid) * W * 3, W, x, fr) ? 1 : 0;
-      else {
+      if (tid < nw) {
+        ok = window_features(L.win + tid * wlen, W, x, fr) ? 1 : 0;
+      } else {
         for (int i = 0; i < kIn; ++i) x[i] = 0.0f;
         fr[0] = fr[1] = fr[3] = 0.0f;
         fr[2] = fr[4] = 1.0f;
@@ -433,11 +442,14 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       L.ok[tid] = ok;
     }
     __syncthreads();
-    block_gemm<__bf16>(&L.x[0][0], kIn + 8, &L.w1[0][0], kLdIn, 64, kHidden, kIn,
-                       [&](int m, int n, float v) { L.h1[m][n] = __float2bfloat16(gelu_f(v + L.b1[n])); });
+    gemm_cs_bf16<kIn>(&L.x[0][0], kIn + 8, w1g, kLdIn, 64, kHidden, [&](int m, int n, float v) {
+      L.h1[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b1[n]));
+    });
     __syncthreads();
-    block_gemm<__bf16>(&L.h1[0][0], kHidden + 8, &L.w2[0][0], kLdH, 64, kHidden, kHidden,
-                       [&](int m, int n, float v) { L.h2[m][n] = __float2bfloat16(gelu_f(v + L.b2[n])); });
+    gemm_cs_bf16<kHidden>(&L.h1[0][0], kHidden + 8, w2g, kLdH, 64, kHidden,
+                          [&](int m, int n, float v) {
+                            L.h2[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b2[n]));
+                          });
     __syncthreads();
     {  // layer 3: four threads per (window, output), 32 inputs each
       const int s = tid >> 2, part = tid & 3;
@@ -451,35 +463,44 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       L.ypart[s][1][part] = acc[1];
     }
     __syncthreads();
-    if (tid < 64 && s0 + tid < N) {
+    if (tid < 64) {
       const int64_t n = s0 + tid;
-      const float y0 = L.b3[0] + ((L.ypart[tid][0][0] + L.ypart[tid][0][1]) +
-                                  (L.ypart[tid][0][2] + L.ypart[tid][0][3]));
-      const float y1 = L.b3[1] + ((L.ypart[tid][1][0] + L.ypart[tid][1][1]) +
-                                  (L.ypart[tid][1][2] + L.ypart[tid][1][3]));
-      const float *fr = L.frame[tid];
-      const float ux = fr[4] * y0, uy = fr[4] * y1;
-      const float px = fr[0] + fr[2] * ux - fr[3] * uy;
-      const float py = fr[1] + fr[3] * ux + fr[2] * uy;
-      bool accept = false;
-      if (L.ok[tid]) {
-        const float *w = win + n * W * 3;
-        float acc = 0.0f;
-        for (int k = 0; k < W; ++k) {
-          const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
-          const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
-          acc += res * res;
+      bool accept = false, fail = false;
+      if (tid < nw) {
+        const float y0 = L.b3[0] + ((L.ypart[tid][0][0] + L.ypart[tid][0][1]) +
+                                    (L.ypart[tid][0][2] + L.ypart[tid][0][3]));
+        const float y1 = L.b3[1] + ((L.ypart[tid][1][0] + L.ypart[tid][1][1]) +
+                                    (L.ypart[tid][1][2] + L.ypart[tid][1][3]));
+        const float *fr = L.frame[tid];
+        const float ux = fr[4] * y0, uy = fr[4] * y1;
+        const float px = fr[0] + fr[2] * ux - fr[3] * uy;
+        const float py = fr[1] + fr[3] * ux + fr[2] * uy;
+        if (L.ok[tid]) {
+          const float *w = L.win + tid * wlen;
+          float acc = 0.0f;
+          for (int k = 0; k < W; ++k) {
+            const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
+            const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
+            acc += res * res;
+          }
+          const float rms = sqrtf(acc / (float)W);
+          accept = rms <= k_sigma * sigma[n];
         }
-        const float rms = sqrtf(acc / (float)W);
-        accept = rms <= k_sigma * sigma[n];
+        if (accept) {
+          out[2 * n] = px;
+          out[2 * n + 1] = py;
+          flag[n] = 1;
+        }
+        fail = !accept;
       }
-      if (accept) {
-        out[2 * n] = px;
-        out[2 * n + 1] = py;
-        flag[n] = 1;
-      } else {
-        const int slot = atomicAdd(fb_count, 1);
-        fb_list[slot] = (int32_t)n;
+      // wavefront-aggregated append to the fallback list
+      const uint64_t m = __ballot(fail);
+      int base = 0;
+      if (tid == 0 && m) base = atomicAdd(fb_count, __popcll(m));
+      base = __shfl(base, 0);
+      if (fail) {
+        const int rank = __popcll(m & ((1ull << tid) - 1ull));
+        fb_list[base + rank] = (int32_t)n;
       }
     }
     __syncthreads();
@@ -643,10 +664,12 @@ int launch_infer(const float *win, int64_t N, int32_t W, const float *th, const 
   if (N <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn;
+  if (W < 3 || W > kMaxW) return -1;
   if (allow_lds((const void *)infer_kernel, sizeof(InferLds))) return -1;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, fb_count);
   const int64_t ntiles = (N + 63) / 64;
-  const unsigned grid = (unsigned)(ntiles < (int64_t)num_cus ? ntiles : num_cus);
+  const int64_t slots = 2 * (int64_t)num_cus;  // two resident blocks per CU
+  const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
   hipLaunchKernelGGL(infer_kernel, dim3(grid), dim3(256), sizeof(InferLds), st, win, N, W, th, w1,
                      w2, sigma, k_sigma, out, flag, fb_count, fb_list);
   if (ok_launch()) return -1;

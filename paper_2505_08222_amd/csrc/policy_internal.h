@@ -14,7 +14,7 @@ namespace mil {
 constexpr int kPolD = 64, kPolHeads = 4, kPolDh = 16, kPolF = 256, kPolLayers = 2;
 constexpr int kPolActions = 8;   // head rows (the first n_actions are used)
 constexpr int kPolMaxTok = 16;   // tokens per agent (agents + targets of an env)
-constexpr int kPolRows = 160;    // token rows per tile
+constexpr int kPolRows = 80;     // token rows per tile (two tiles' LDS fit one CU)
 constexpr int kPolMaxAgents = 16;
 constexpr int kPolLdD = kPolD + 8, kPolLdF = kPolF + 8;
 // offsets inside one layer
@@ -28,6 +28,15 @@ constexpr int kPolOffEmbW = 0, kPolOffEmbB = 64 * 6, kPolOffLayer0 = kPolOffEmbB
 constexpr int kPolOffFinal = kPolOffLayer0 + kPolLayers * kPolLayerParams;
 constexpr int kPolLnfG = 0, kPolLnfB = 64, kPolWh = 128, kPolBh = kPolWh + kPolActions * 64;
 constexpr int kPolNumParams = kPolOffFinal + kPolBh + kPolActions;
+// LDS copy of the small FP32 parameters: embedding W [64][6] and b [64]; per
+// layer ln1 gain/offset, bqkv, bo, ln2 gain/offset, b1, b2; the final
+// LayerNorm and head exactly as in the vector.
+constexpr int kSmEmbW = 0, kSmEmbB = 64 * 6, kSmLayer0 = kSmEmbB + 64;
+constexpr int kSmLn1G = 0, kSmLn1B = 64, kSmBqkv = 128, kSmBo = kSmBqkv + 192, kSmLn2G = kSmBo + 64;
+constexpr int kSmLn2B = kSmLn2G + 64, kSmB1 = kSmLn2B + 64, kSmB2 = kSmB1 + 256;
+constexpr int kSmLayer = kSmB2 + 64;
+constexpr int kSmFinal = kSmLayer0 + kPolLayers * kSmLayer;
+constexpr int kSmTotal = kSmFinal + kPolBh + kPolActions;
 // MFMA-ready BF16 weights (elements)
 constexpr int64_t kPolPrepWqkv = (int64_t)kPolLayers * 3 * kPolD * kPolLdD;
 constexpr int64_t kPolPrepWo = (int64_t)kPolLayers * kPolD * kPolLdD;

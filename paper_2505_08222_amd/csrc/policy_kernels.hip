@@ -2,9 +2,11 @@
 // transformer actor of arXiv 2505.08222, Sec. III-B (TransfMAPPO, entity
 // tokens, LayerNorm throughout), without its recurrent token; forward only.
 //
-// A persistent block takes tiles of agents (at most 160 token rows): tokens
-// are embedded on VALU, every dense layer (QKV, output projection, FFN) runs
-// as BF16 MFMA with FP32 accumulation over the tile's stacked token rows, and
+// A persistent block (two per CU) takes tiles of agents (at most 80 token
+// rows); the small FP32 parameters (embedding, LayerNorms, biases, head) are
+// staged in LDS once per block. Tokens are embedded on VALU, every dense
+// layer (QKV, output projection, FFN) runs as BF16 MFMA with FP32
+// accumulation over the tile's stacked token rows, and
 // attention (n_tok <= 16 keys per agent, 4 heads of 16) runs on VALU with
 // keys whose observation mask is 0 excluded. The residual stream stays in
 // LDS in FP32. The self token's final LayerNorm feeds the action head; the
@@ -13,20 +15,13 @@
 #include <hip/hip_bf16.h>
 #include <math.h>
 
+#include "mfma_tile.h"
 #include "policy_internal.h"
 #include "rng.h"
 
 namespace mil {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-
 namespace {
-
-__device__ __forceinline__ float gelu_tanh(float x) {
-  const float c = 0.7978845608028654f;
-  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
-}
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -34,61 +29,49 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// D[m][n] = sum_k A[m][k] B[n][k] over 16x16 tiles; both operands K-contiguous
-// BF16 (lane l: row l%16, 8 consecutive K at 8*(l/16); D rows 4*(l/16)+j).
-// Column-stationary: a wavefront takes a 16-wide block of output columns,
-// keeps that block's weight fragments (B, from global memory / L2) in
-// registers, and sweeps every row tile of A (LDS) with them.
-template <int K, typename Epi>
-__device__ __forceinline__ void gemm_bf16(const __bf16 *A, int lda, const __bf16 *B, int ldb, int M,
-                                          int N, Epi epi) {
-  constexpr int KS = K / 32;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const int tm = M >> 4, tn = N >> 4;
-  const int row = lane & 15, kg = lane >> 4;
-  for (int ct = wave; ct < tn; ct += nw) {
-    const int n0 = ct << 4;
-    bf16x8 b[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      b[ks] = *reinterpret_cast<const bf16x8 *>(B + (n0 + row) * ldb + ks * 32 + 8 * kg);
-    for (int mt = 0; mt < tm; ++mt) {
-      const int m0 = mt << 4;
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8 a =
-            *reinterpret_cast<const bf16x8 *>(A + (m0 + row) * lda + ks * 32 + 8 * kg);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[ks], acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) epi(m0 + 4 * kg + j, n0 + row, acc[j]);
-    }
+// Position in the parameter vector of entry i of the LDS copy of the small
+// FP32 parameters (embedding, LayerNorms, biases, head).
+__device__ __forceinline__ int small_param_src(int i) {
+  if (i < kSmLayer0) return i;  // embedding W, b: the vector's first entries
+  if (i < kSmFinal) {
+    const int l = (i - kSmLayer0) / kSmLayer, r = (i - kSmLayer0) % kSmLayer;
+    const int lp = kPolOffLayer0 + l * kPolLayerParams;
+    if (r < kSmBqkv) return lp + kPolLn1G + r;                    // ln1 gain, offset
+    if (r < kSmBo) return lp + kPolBqkv + (r - kSmBqkv);
+    if (r < kSmLn2G) return lp + kPolBo + (r - kSmBo);
+    if (r < kSmB1) return lp + kPolLn2G + (r - kSmLn2G);           // ln2 gain, offset
+    if (r < kSmB2) return lp + kPolB1 + (r - kSmB1);
+    return lp + kPolB2 + (r - kSmB2);
   }
+  return kPolOffFinal + (i - kSmFinal);  // final LayerNorm and head
 }
 
 }  // namespace
 
 struct PolicyLds {
+  float prm[kSmTotal];                    // small FP32 parameters
   float h[kPolRows][kPolD];               // residual stream
   __bf16 xn[kPolRows][kPolD + 8];         // LayerNorm output / attention output
-  __bf16 buf[kPolRows][3 * kPolD + 8];    // QKV, or one half of the FFN hidden layer
+  __bf16 buf[kPolRows][3 * kPolD + 8];    // QKV, or one half of the FFN hidden layer, or raw tokens
   uint8_t mask[kPolRows];
   float logits[kPolMaxAgents][kPolActions];
 };
-static_assert(sizeof(PolicyLds) <= 160 * 1024, "policy LDS");
-static_assert(offsetof(PolicyLds, xn) % 16 == 0 && offsetof(PolicyLds, buf) % 16 == 0, "align");
+static_assert(sizeof(PolicyLds) <= 80 * 1024, "two policy blocks per CU");
+static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 == 0 &&
+                  offsetof(PolicyLds, buf) % 16 == 0,
+              "align");
 
 // LayerNorm of every row (one wavefront per row, lane = feature) into xn.
 __device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const float *g,
                                                 const float *b) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const float gl = g[lane], bl = b[lane];
   for (int r = wave; r < rows; r += nw) {
     const float x = L.h[r][lane];
     const float mean = wave_sum(x) * (1.0f / kPolD);
     const float d = x - mean;
     const float var = wave_sum(d * d) * (1.0f / kPolD);
-    L.xn[r][lane] = __float2bfloat16(d * rsqrtf(var + 1e-5f) * g[lane] + b[lane]);
+    L.xn[r][lane] = __float2bfloat16(fmaf(d * rsqrtf(var + 1e-5f), gl, bl));
   }
 }
 
@@ -101,99 +84,122 @@ policy_kernel(PolicyArgs a) {
   const int at = a.agents_per_tile;
   const int rows_used = at * nt;
   const int rows = (rows_used + 15) & ~15;
-  const float *th = a.params;
   const int64_t ntiles = (a.A + at - 1) / at;
+  for (int i = tid; i < kSmTotal; i += nthr) L.prm[i] = a.params[small_param_src(i)];
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t ag0 = tile * at;
-    // ---- tokens: embed 6 -> 64 (VALU), masks
+    const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;  // agents in this tile
+    const int nrow = (int)nag * nt;
+    // ---- raw tokens of the tile (contiguous in memory) staged through LDS
+    float *x_raw = reinterpret_cast<float *>(&L.buf[0][0]);
+    const float *src = a.obs + ag0 * nt * 6;
+    for (int e = tid; e < rows * 6; e += nthr) x_raw[e] = e < nrow * 6 ? src[e] : 0.0f;
+    for (int r = tid; r < rows; r += nthr) L.mask[r] = r < nrow ? a.mask[ag0 * nt + r] : 0;
+    __syncthreads();
+    // ---- embed 6 -> 64 (VALU)
     for (int e = tid; e < rows * kPolD; e += nthr) {
-      const int r = e / kPolD, d = e % kPolD;
-      const int al = r / nt;
-      float acc = 0.0f;
-      if (r < rows_used && ag0 + al < a.A) {
-        const float *x = a.obs + ((ag0 + al) * nt + (r % nt)) * 6;
-        acc = th[kPolOffEmbB + d];
+      const int r = e >> 6, d = e & (kPolD - 1);
+      float acc = L.prm[kSmEmbB + d];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) acc = fmaf(th[kPolOffEmbW + d * 6 + c], x[c], acc);
-      }
-      L.h[r][d] = acc;
-    }
-    for (int r = tid; r < rows; r += nthr) {
-      const int al = r / nt;
-      L.mask[r] = (r < rows_used && ag0 + al < a.A) ? a.mask[(ag0 + al) * nt + (r % nt)] : 0;
+      for (int c = 0; c < 6; ++c) acc = fmaf(L.prm[kSmEmbW + d * 6 + c], x_raw[r * 6 + c], acc);
+      L.h[r][d] = r < nrow ? acc : 0.0f;
     }
     __syncthreads();
     for (int l = 0; l < kPolLayers; ++l) {
-      const float *lp = th + kPolOffLayer0 + l * kPolLayerParams;
+      const float *lp = L.prm + kSmLayer0 + l * kSmLayer;
       const __bf16 *wq = a.wqkv + l * (3 * kPolD) * kPolLdD;
       const __bf16 *wo = a.wo + l * kPolD * kPolLdD;
       const __bf16 *w1 = a.w1 + l * kPolF * kPolLdD;
       const __bf16 *w2 = a.w2 + l * kPolD * kPolLdF;
       // ---- attention block
-      layer_norm_rows(L, rows, lp + kPolLn1G, lp + kPolLn1B);
+      layer_norm_rows(L, rows, lp + kSmLn1G, lp + kSmLn1B);
       __syncthreads();
-      gemm_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows, 3 * kPolD,
-                [&](int m, int n, float v) { L.buf[m][n] = __float2bfloat16(v + lp[kPolBqkv + n]); });
+      gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows, 3 * kPolD,
+                       [&](int m, int n, float v) { L.buf[m][n] = __float2bfloat16(v + lp[kSmBqkv + n]); });
       __syncthreads();
       for (int e = tid; e < at * kPolHeads * nt; e += nthr) {
         const int al = e / (kPolHeads * nt), rem = e % (kPolHeads * nt);
         const int hd = rem / nt, tq = rem % nt;
         const int r0 = al * nt, rq = r0 + tq;
-        float q[kPolDh];
-#pragma unroll
-        for (int c = 0; c < kPolDh; ++c) q[c] = __bfloat162float(L.buf[rq][hd * kPolDh + c]);
+        const bf16x8 *qp = reinterpret_cast<const bf16x8 *>(&L.buf[rq][hd * kPolDh]);
+        const bf16x8 q0 = qp[0], q1 = qp[1];
         float s[kPolMaxTok];
         float mx = -INFINITY;
-        for (int u = 0; u < nt; ++u) {
-          float acc = 0.0f;
 #pragma unroll
-          for (int c = 0; c < kPolDh; ++c)
-            acc = fmaf(q[c], __bfloat162float(L.buf[r0 + u][kPolD + hd * kPolDh + c]), acc);
-          s[u] = L.mask[r0 + u] ? acc * 0.25f : -INFINITY;
+        for (int u = 0; u < kPolMaxTok; ++u) {
+          s[u] = -INFINITY;
+          if (u < nt && L.mask[r0 + u]) {
+            const bf16x8 *kp = reinterpret_cast<const bf16x8 *>(&L.buf[r0 + u][kPolD + hd * kPolDh]);
+            const bf16x8 k0 = kp[0], k1 = kp[1];
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc = fmaf((float)q0[c], (float)k0[c], acc);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc = fmaf((float)q1[c], (float)k1[c], acc);
+            s[u] = acc * 0.25f;
+          }
           mx = fmaxf(mx, s[u]);
         }
         float z = 0.0f;
-        for (int u = 0; u < nt; ++u) {
-          s[u] = L.mask[r0 + u] ? __expf(s[u] - mx) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < kPolMaxTok; ++u) {
+          s[u] = s[u] > -INFINITY ? __expf(s[u] - mx) : 0.0f;
           z += s[u];
         }
         const float iz = z > 0.0f ? 1.0f / z : 0.0f;  // rows of absent agents have no keys
+        float o[kPolDh];
 #pragma unroll
-        for (int c = 0; c < kPolDh; ++c) {
-          float acc = 0.0f;
-          for (int u = 0; u < nt; ++u)
-            acc = fmaf(s[u], __bfloat162float(L.buf[r0 + u][2 * kPolD + hd * kPolDh + c]), acc);
-          L.xn[rq][hd * kPolDh + c] = __float2bfloat16(acc * iz);
+        for (int c = 0; c < kPolDh; ++c) o[c] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kPolMaxTok; ++u) {
+          if (u < nt && s[u] > 0.0f) {
+            const bf16x8 *vp =
+                reinterpret_cast<const bf16x8 *>(&L.buf[r0 + u][2 * kPolD + hd * kPolDh]);
+            const bf16x8 v0 = vp[0], v1 = vp[1];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) o[c] = fmaf(s[u], (float)v0[c], o[c]);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) o[8 + c] = fmaf(s[u], (float)v1[c], o[8 + c]);
+          }
         }
+        bf16x8 w0, w1v;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          w0[c] = __float2bfloat16(o[c] * iz);
+          w1v[c] = __float2bfloat16(o[8 + c] * iz);
+        }
+        bf16x8 *op = reinterpret_cast<bf16x8 *>(&L.xn[rq][hd * kPolDh]);
+        op[0] = w0;
+        op[1] = w1v;
       }
       __syncthreads();
-      gemm_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows, kPolD,
-                [&](int m, int n, float v) { L.h[m][n] += v + lp[kPolBo + n]; });
+      gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows, kPolD,
+                       [&](int m, int n, float v) { L.h[m][n] += v + lp[kSmBo + n]; });
       __syncthreads();
       // ---- feed-forward block, hidden layer in two halves of 128
-      layer_norm_rows(L, rows, lp + kPolLn2G, lp + kPolLn2B);
+      layer_norm_rows(L, rows, lp + kSmLn2G, lp + kSmLn2B);
       __syncthreads();
       for (int half = 0; half < 2; ++half) {
-        gemm_bf16<kPolD>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD, rows, 128,
-                  [&](int m, int n, float v) {
-                    L.buf[m][n] = __float2bfloat16(gelu_tanh(v + lp[kPolB1 + half * 128 + n]));
-                  });
+        gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD, rows, 128,
+                         [&](int m, int n, float v) {
+                           L.buf[m][n] = __float2bfloat16(gelu_tanh_fast(v + lp[kSmB1 + half * 128 + n]));
+                         });
         __syncthreads();
-        gemm_bf16<128>(&L.buf[0][0], 3 * kPolD + 8, w2 + half * 128, kPolLdF, rows, kPolD,
-                  [&](int m, int n, float v) { L.h[m][n] += v + (half == 0 ? lp[kPolB2 + n] : 0.0f); });
+        gemm_cs_bf16<128>(&L.buf[0][0], 3 * kPolD + 8, w2 + half * 128, kPolLdF, rows, kPolD,
+                       [&](int m, int n, float v) { L.h[m][n] += v + (half == 0 ? lp[kSmB2 + n] : 0.0f); });
         __syncthreads();
       }
     }
     // ---- head on the self token of each agent: final LayerNorm, logits
     {
       const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
-      const float *fp = th + kPolOffFinal;
+      const float *fp = L.prm + kSmFinal;
       for (int al = wave; al < at; al += nw) {
         const float x = L.h[al * nt][lane];
         const float mean = wave_sum(x) * (1.0f / kPolD);
         const float d = x - mean;
         const float var = wave_sum(d * d) * (1.0f / kPolD);
-        const float sv = d * rsqrtf(var + 1e-5f) * fp[kPolLnfG + lane] + fp[kPolLnfB + lane];
+        const float sv = fmaf(d * rsqrtf(var + 1e-5f), fp[kPolLnfG + lane], fp[kPolLnfB + lane]);
         for (int k = 0; k < kPolActions; ++k) {
           const float v = wave_sum(fp[kPolWh + k * kPolD + lane] * sv);
           if (lane == 0) L.logits[al][k] = v + fp[kPolBh + k];
@@ -202,9 +208,8 @@ policy_kernel(PolicyArgs a) {
     }
     __syncthreads();
     // ---- actions: inverse-CDF draw from softmax over the first n_actions logits
-    for (int al = tid; al < at; al += nthr) {
+    for (int al = tid; al < nag; al += nthr) {
       const int64_t ag = ag0 + al;
-      if (ag >= a.A) continue;
       if (a.logits)
         for (int k = 0; k < kPolActions; ++k) a.logits[ag * kPolActions + k] = L.logits[al][k];
       if (a.actions) {
@@ -306,7 +311,8 @@ int launch_policy(const PolicyArgs &args, int num_cus, void *stream) {
     lds_set = true;
   }
   const int64_t ntiles = (args.A + args.agents_per_tile - 1) / args.agents_per_tile;
-  const int64_t grid = ntiles < (int64_t)num_cus ? ntiles : (int64_t)num_cus;
+  const int64_t slots = 2 * (int64_t)num_cus;  // two resident blocks per CU
+  const int64_t grid = ntiles < slots ? ntiles : slots;
   if (grid <= 0) return 0;
   hipLaunchKernelGGL(policy_kernel, dim3((unsigned)grid), dim3(256), sizeof(PolicyLds),
                      (hipStream_t)stream, args);
