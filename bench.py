@@ -244,7 +244,7 @@ def bench_learned(args):
     N = win.shape[0]
     work = learned._work(N, "bf16", win.device)
 
-    def timed(fn, reps=5):
+    def timed(fn, reps=max(1, args.steps)):
         fn()
         torch.cuda.synchronize()
         evs = []
@@ -295,7 +295,7 @@ def bench_learned(args):
         "metric": METRIC,
         "value": ms_ex / ms_mlp,
         "unit": "x (exact FP64 LS time / guarded learned time, same GPU, same windows)",
-        "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": ms_mlp,
+        "n_gpus": 1, "steps": max(1, args.steps), "warmup": 1, "ms_per_step": ms_mlp,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"learned estimator: 16-entry windows from ragged-configuration "

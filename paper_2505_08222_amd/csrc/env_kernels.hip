@@ -204,7 +204,7 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 // other paths' pointers and registers.
 // ---------------------------------------------------------------------------
 template <int S, int WC, int G, bool FULL>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (S == 2 && WC == 10 && !FULL) ? 3 : 1)
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
                uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
   constexpr int MA = S, MT = S;

@@ -306,20 +306,35 @@ train_tile_kernel(int64_t N, const float *__restrict__ xin, const int64_t *__res
                 [&](int m, int n, float v) { gp[kOffW1 + m * kIn + n] = v; });
 }
 
-// Deterministic sum of the per-block partial gradients and losses.
-__global__ void reduce_grad_kernel(const float *__restrict__ partial, int nblocks,
-                                   float *__restrict__ grad, const float *__restrict__ loss_partial,
-                                   float *__restrict__ loss, float inv_n) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < kNumParams) {
-    float acc = 0.0f;
-    for (int b = 0; b < nblocks; ++b) acc += partial[(int64_t)b * kNumParams + p];
-    grad[p] = acc;
-  }
-  if (p == 0 && loss) {
+// Deterministic sum of the per-block partial gradients and losses: a block
+// takes 64 parameters; its four wavefronts each sum every fourth partial in
+// order, and the four sums are added in a fixed order. Block 0 also sums the
+// loss partials (fixed tree in FP64).
+__global__ void __launch_bounds__(256)
+reduce_grad_kernel(const float *__restrict__ partial, int nblocks, float *__restrict__ grad,
+                   const float *__restrict__ loss_partial, float *__restrict__ loss, float inv_n) {
+  __shared__ float part4[4][64];
+  __shared__ double lred[256];
+  const int pl = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int p = blockIdx.x * 64 + pl;
+  float acc = 0.0f;
+  if (p < kNumParams)
+    for (int b = grp; b < nblocks; b += 4) acc += partial[(int64_t)b * kNumParams + p];
+  part4[grp][pl] = acc;
+  if (blockIdx.x == 0 && loss) {
     double l = 0.0;
-    for (int b = 0; b < nblocks; ++b) l += loss_partial[b];
-    *loss = (float)(l * inv_n);
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) l += loss_partial[b];
+    lred[threadIdx.x] = l;
+  }
+  __syncthreads();
+  if (grp == 0 && p < kNumParams)
+    grad[p] = (part4[0][pl] + part4[1][pl]) + (part4[2][pl] + part4[3][pl]);
+  if (blockIdx.x == 0 && loss) {
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) lred[threadIdx.x] += lred[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(lred[0] * inv_n);
   }
 }
 
@@ -345,6 +360,7 @@ struct FwdLds {
   T x[64][kIn + 8];
   T h1[64][kHidden + 8];
   T h2[64][kHidden + 8];
+  float b1[kHidden], b2[kHidden], w3[2][kHidden], b3[4];
 };
 
 template <typename T>
@@ -359,19 +375,48 @@ forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict
     const int s = e / kIn, i = e % kIn;
     L.x[s][i] = to_t<T>(s0 + s < N ? xin[(s0 + s) * kIn + i] : 0.0f);
   }
+  for (int e = tid; e < kHidden; e += blockDim.x) {
+    L.b1[e] = th[kOffB1 + e];
+    L.b2[e] = th[kOffB2 + e];
+    L.w3[0][e] = th[kOffW3 + e];
+    L.w3[1][e] = th[kOffW3 + kHidden + e];
+  }
+  if (tid < 2) L.b3[tid] = th[kOffB3 + tid];
   __syncthreads();
-  block_gemm<T>(&L.x[0][0], kIn + 8, w1, kLdIn, 64, kHidden, kIn, [&](int m, int n, float v) {
-    L.h1[m][n] = to_t<T>(gelu_f(v + th[kOffB1 + n]));
-  });
+  if constexpr (sizeof(T) == 2) {
+    // BF16 operands: the weight-stationary tile GEMM and the fast GELU (its
+    // output is rounded to BF16 anyway)
+    gemm_rs_bf16<kIn, kHidden>(&L.x[0][0], kIn + 8, w1, kLdIn, 64, [&](int m, int n, float v) {
+      L.h1[m][n] = to_t<T>(gelu_tanh_fast(v + L.b1[n]));
+    });
+    __syncthreads();
+    gemm_rs_bf16<kHidden, kHidden>(&L.h1[0][0], kHidden + 8, w2, kLdH, 64,
+                          [&](int m, int n, float v) { L.h2[m][n] = to_t<T>(gelu_tanh_fast(v + L.b2[n])); });
+  } else {
+    block_gemm<T>(&L.x[0][0], kIn + 8, w1, kLdIn, 64, kHidden, kIn, [&](int m, int n, float v) {
+      L.h1[m][n] = to_t<T>(gelu_f(v + L.b1[n]));
+    });
+    __syncthreads();
+    block_gemm<T>(&L.h1[0][0], kHidden + 8, w2, kLdH, 64, kHidden, kHidden,
+                  [&](int m, int n, float v) { L.h2[m][n] = to_t<T>(gelu_f(v + L.b2[n])); });
+  }
   __syncthreads();
-  block_gemm<T>(&L.h1[0][0], kHidden + 8, w2, kLdH, 64, kHidden, kHidden,
-                [&](int m, int n, float v) { L.h2[m][n] = to_t<T>(gelu_f(v + th[kOffB2 + n])); });
-  __syncthreads();
-  if (tid < 128) {
-    const int s = tid >> 1, o = tid & 1;
-    float acc = th[kOffB3 + o];
-    for (int i = 0; i < kHidden; ++i) acc += th[kOffW3 + o * kHidden + i] * to_f(L.h2[s][i]);
-    if (s0 + s < N) y[(s0 + s) * 2 + o] = acc;
+  {  // output layer: four threads per (sample, output), 32 inputs each, fixed sum order
+    const int s = tid >> 2, part = tid & 3;
+    float a0 = 0.0f, a1 = 0.0f;
+    for (int i = part * 32; i < part * 32 + 32; ++i) {
+      const float h = to_f(L.h2[s][i]);
+      a0 += L.w3[0][i] * h;
+      a1 += L.w3[1][i] * h;
+    }
+    a0 += __shfl_xor(a0, 1);
+    a1 += __shfl_xor(a1, 1);
+    a0 += __shfl_xor(a0, 2);
+    a1 += __shfl_xor(a1, 2);
+    if (part == 0 && s0 + s < N) {
+      y[(s0 + s) * 2] = L.b3[0] + a0;
+      y[(s0 + s) * 2 + 1] = L.b3[1] + a1;
+    }
   }
 }
 
@@ -426,27 +471,63 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       for (int e = tid; e < nw * wlen; e += blockDim.x) L.win[e] = src[e];
     }
     __syncthreads();
-    // features: thread s < 64 takes window s0 + s
-    if (tid < 64) {
-      float x[kIn], fr[5];
-      int ok = 0;
-      if (tid < nw) {
-        ok = window_features(L.win + tid * wlen, W, x, fr) ? 1 : 0;
-      } else {
-        for (int i = 0; i < kIn; ++i) x[i] = 0.0f;
-        fr[0] = fr[1] = fr[3] = 0.0f;
-        fr[2] = fr[4] = 1.0f;
+    // features (the same quantities as window_features): four threads per
+    // window, each taking entries part, part + 4, ...; the window's sums are
+    // combined across the four threads
+    {
+      const int s = tid >> 2, part = tid & 3;
+      const bool live = s < nw;
+      const float *w = L.win + (live ? s : 0) * wlen;
+      const float x0 = w[0], y0 = w[1], r0 = w[2];
+      float mx = 0.f, my = 0.f, mr = 0.f, bad = 0.f;
+      for (int k = part; k < W; k += 4) {
+        mx += w[3 * k] - x0;
+        my += w[3 * k + 1] - y0;
+        const float r = w[3 * k + 2];
+        bad += (r == r) ? 0.f : 1.f;
+        mr += r - r0;
       }
-      for (int i = 0; i < kIn; ++i) L.x[tid][i] = __float2bfloat16(x[i]);
-      for (int q = 0; q < 5; ++q) L.frame[tid][q] = fr[q];
-      L.ok[tid] = ok;
+#pragma unroll
+      for (int m = 1; m <= 2; m <<= 1) {
+        mx += __shfl_xor(mx, m);
+        my += __shfl_xor(my, m);
+        mr += __shfl_xor(mr, m);
+        bad += __shfl_xor(bad, m);
+      }
+      const float invw = 1.0f / (float)W;
+      mx *= invw;
+      my *= invw;
+      mr *= invw;
+      const float cx = w[0] - w[3 * (W - 1)], cy = w[1] - w[3 * (W - 1) + 1];
+      const float len = sqrtf(fmaf(cx, cx, cy * cy));
+      float c = 1.0f, sn = 0.0f;
+      if (len > 1e-6f) {
+        c = cx / len;
+        sn = cy / len;
+      }
+      for (int k = part; k < W; k += 4) {
+        const float dx = (w[3 * k] - x0) - mx, dy = (w[3 * k + 1] - y0) - my;
+        L.x[s][3 * k] = __float2bfloat16(live ? fmaf(c, dx, sn * dy) * 0.1f : 0.0f);
+        L.x[s][3 * k + 1] = __float2bfloat16(live ? fmaf(-sn, dx, c * dy) * 0.1f : 0.0f);
+        L.x[s][3 * k + 2] = __float2bfloat16(live ? ((w[3 * k + 2] - r0) - mr) * 0.1f : 0.0f);
+      }
+      for (int i = 3 * W + part; i < kIn; i += 4)
+        L.x[s][i] = __float2bfloat16((live && i == 3 * W) ? (r0 + mr) * 1e-3f : 0.0f);
+      if (part == 0) {
+        L.frame[s][0] = live ? x0 + mx : 0.0f;
+        L.frame[s][1] = live ? y0 + my : 0.0f;
+        L.frame[s][2] = live ? c : 1.0f;
+        L.frame[s][3] = live ? sn : 0.0f;
+        L.frame[s][4] = live ? r0 + mr : 1.0f;
+        L.ok[s] = (live && bad == 0.f) ? 1 : 0;
+      }
     }
     __syncthreads();
-    gemm_cs_bf16<kIn>(&L.x[0][0], kIn + 8, w1g, kLdIn, 64, kHidden, [&](int m, int n, float v) {
+    gemm_rs_bf16<kIn, kHidden>(&L.x[0][0], kIn + 8, w1g, kLdIn, 64, [&](int m, int n, float v) {
       L.h1[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b1[n]));
     });
     __syncthreads();
-    gemm_cs_bf16<kHidden>(&L.h1[0][0], kHidden + 8, w2g, kLdH, 64, kHidden,
+    gemm_rs_bf16<kHidden, kHidden>(&L.h1[0][0], kHidden + 8, w2g, kLdH, 64,
                           [&](int m, int n, float v) {
                             L.h2[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b2[n]));
                           });
@@ -644,7 +725,7 @@ int launch_train(int64_t N, const float *x, const int64_t *index, const float *t
                        w2t, partial, loss_partial, inv_n);
   }
   if (ok_launch()) return -1;
-  hipLaunchKernelGGL(reduce_grad_kernel, dim3((kNumParams + 255) / 256), dim3(256), 0, st,
+  hipLaunchKernelGGL(reduce_grad_kernel, dim3((kNumParams + 63) / 64), dim3(256), 0, st,
                      partial, (int)nb, grad, loss_partial, loss, inv_n);
   return ok_launch();
 }

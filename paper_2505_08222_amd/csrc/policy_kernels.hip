@@ -23,11 +23,18 @@ namespace mil {
 
 namespace {
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  return v;
+// Exchange with lane ^ 16 and lane ^ 32 through the cross-row swap
+// instructions (VALU, no LDS round trip).
+__device__ __forceinline__ int xor16i(int v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return (threadIdx.x & 16) ? (int)r[0] : (int)r[1];
 }
+__device__ __forceinline__ int xor32i(int v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return (threadIdx.x & 32) ? (int)r[0] : (int)r[1];
+}
+__device__ __forceinline__ float xor16f(float v) { return __int_as_float(xor16i(__float_as_int(v))); }
+__device__ __forceinline__ float xor32f(float v) { return __int_as_float(xor32i(__float_as_int(v))); }
 
 // Position in the parameter vector of entry i of the LDS copy of the small
 // FP32 parameters (embedding, LayerNorms, biases, head).
@@ -50,32 +57,82 @@ __device__ __forceinline__ int small_param_src(int i) {
 
 struct PolicyLds {
   float prm[kSmTotal];                    // small FP32 parameters
-  float h[kPolRows][kPolD];               // residual stream
+  float h[kPolRows][kPolD + 4];           // residual stream (rows padded: conflict-free row reads)
   __bf16 xn[kPolRows][kPolD + 8];         // LayerNorm output / attention output
-  __bf16 buf[kPolRows][3 * kPolD + 8];    // QKV, or one half of the FFN hidden layer, or raw tokens
+  // Q, K planes [rows][72] and V transposed [64][88]; or one half of the FFN hidden layer
+  // [rows][136]; or raw tokens; or the head's scratch
+  __bf16 buf[3 * kPolRows * (kPolD + 8)];
   uint8_t mask[kPolRows];
   float logits[kPolMaxAgents][kPolActions];
 };
 static_assert(sizeof(PolicyLds) <= 80 * 1024, "two policy blocks per CU");
+constexpr int kPlane = kPolRows * (kPolD + 8);  // one Q / K / V plane (elements)
+constexpr int kLdQ = kPolD + 8;                  // row stride of a plane
+constexpr int kLdVt = kPolRows + 8;              // row stride of V^T
+static_assert(kPolD * kLdVt <= kPlane, "V^T fits its plane");
+constexpr int kLdHid = 128 + 8;                  // row stride of the FFN hidden half
+static_assert(kPolRows * kLdHid <= 3 * kPlane, "FFN half fits the buffer");
+static_assert(kPolMaxAgents * (kPolD + 4) * 4 <= sizeof(__bf16) * 3 * kPlane,
+              "head scratch fits the buffer");
+static_assert((kPlane * 2) % 16 == 0, "plane alignment");
 static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 == 0 &&
                   offsetof(PolicyLds, buf) % 16 == 0,
               "align");
 
-// LayerNorm of every row (one wavefront per row, lane = feature) into xn.
-__device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const float *g,
-                                                const float *b) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  const float gl = g[lane], bl = b[lane];
-  for (int r = wave; r < rows; r += nw) {
-    const float x = L.h[r][lane];
-    const float mean = wave_sum(x) * (1.0f / kPolD);
-    const float d = x - mean;
-    const float var = wave_sum(d * d) * (1.0f / kPolD);
-    L.xn[r][lane] = __float2bfloat16(fmaf(d * rsqrtf(var + 1e-5f), gl, bl));
+// LayerNorm (eps 1e-5) of one 64-wide FP32 row held in LDS, one thread per
+// row: mean, then variance, then the normalised row scaled by gain g and
+// shifted by offset b (both in LDS), each pass re-reading the row (few
+// registers, four partial sums each). out(q, y[8]) receives features 8q..8q+7.
+template <typename Out>
+__device__ __forceinline__ void ln_row(const float *x, const float *g, const float *b, Out out) {
+  const float4 *xp = reinterpret_cast<const float4 *>(x);
+  float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < kPolD / 4; ++q) {
+    const float4 v = xp[q];
+    s4[0] += v.x;
+    s4[1] += v.y;
+    s4[2] += v.z;
+    s4[3] += v.w;
+  }
+  const float mean = ((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
+  float q4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int q = 0; q < kPolD / 4; ++q) {
+    const float4 v = xp[q];
+    q4[0] = fmaf(v.x - mean, v.x - mean, q4[0]);
+    q4[1] = fmaf(v.y - mean, v.y - mean, q4[1]);
+    q4[2] = fmaf(v.z - mean, v.z - mean, q4[2]);
+    q4[3] = fmaf(v.w - mean, v.w - mean, q4[3]);
+  }
+  const float inv = rsqrtf(((q4[0] + q4[1]) + (q4[2] + q4[3])) * (1.0f / kPolD) + 1e-5f);
+#pragma unroll
+  for (int q = 0; q < kPolD / 8; ++q) {
+    const float4 v0 = xp[2 * q], v1 = xp[2 * q + 1];
+    const float xv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    float y[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) y[c] = fmaf((xv[c] - mean) * inv, g[8 * q + c], b[8 * q + c]);
+    out(q, y);
   }
 }
 
-__global__ void __launch_bounds__(256)
+// LayerNorm of every row of the residual stream into xn (BF16).
+__device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const float *g,
+                                                const float *b) {
+  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+    bf16x8 *o = reinterpret_cast<bf16x8 *>(&L.xn[r][0]);
+    ln_row(&L.h[r][0], g, b, [&](int q, const float(&y)[8]) {
+      bf16x8 w;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) w[c] = __float2bfloat16(y[c]);
+      o[q] = w;
+    });
+  }
+}
+
+// at least two wavefronts per SIMD: two resident blocks of four per CU
+__global__ void __launch_bounds__(256, 2)
 policy_kernel(PolicyArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   PolicyLds &L = *reinterpret_cast<PolicyLds *>(smem);
@@ -86,23 +143,52 @@ policy_kernel(PolicyArgs a) {
   const int rows = (rows_used + 15) & ~15;
   const int64_t ntiles = (a.A + at - 1) / at;
   for (int i = tid; i < kSmTotal; i += nthr) L.prm[i] = a.params[small_param_src(i)];
+  // raw tokens and masks of a tile are contiguous in memory; each thread
+  // holds its share of the next tile's in registers while this one computes
+  constexpr int kTokRegs = (kPolRows * 6 + 255) / 256;
+  static_assert(kTokRegs * 256 >= kPolRows * 6 && kPolRows <= 256, "token prefetch");
+  float tok[kTokRegs];
+  uint8_t msk = 0;
+  auto fetch = [&](int64_t tile) {
+    const int64_t ag0 = tile * at;
+    const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;
+    const int nrow = (int)nag * nt;
+    const float *src = a.obs + ag0 * nt * 6;
+#pragma unroll
+    for (int q = 0; q < kTokRegs; ++q) {
+      const int e = tid + q * nthr;
+      tok[q] = (tile < ntiles && e < nrow * 6) ? src[e] : 0.0f;
+    }
+    msk = (tile < ntiles && tid < nrow) ? a.mask[ag0 * nt + tid] : 0;
+  };
+  fetch(blockIdx.x);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t ag0 = tile * at;
     const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;  // agents in this tile
     const int nrow = (int)nag * nt;
-    // ---- raw tokens of the tile (contiguous in memory) staged through LDS
-    float *x_raw = reinterpret_cast<float *>(&L.buf[0][0]);
-    const float *src = a.obs + ag0 * nt * 6;
-    for (int e = tid; e < rows * 6; e += nthr) x_raw[e] = e < nrow * 6 ? src[e] : 0.0f;
-    for (int r = tid; r < rows; r += nthr) L.mask[r] = r < nrow ? a.mask[ag0 * nt + r] : 0;
+    // ---- raw tokens of the tile staged through LDS, the next tile's fetched
+    float *x_raw = reinterpret_cast<float *>(&L.buf[0]);
+#pragma unroll
+    for (int q = 0; q < kTokRegs; ++q) {
+      const int e = tid + q * nthr;
+      if (e < rows * 6) x_raw[e] = tok[q];
+    }
+    if (tid < rows) L.mask[tid] = msk;
+    fetch(tile + gridDim.x);
     __syncthreads();
     // ---- embed 6 -> 64 (VALU)
-    for (int e = tid; e < rows * kPolD; e += nthr) {
-      const int r = e >> 6, d = e & (kPolD - 1);
-      float acc = L.prm[kSmEmbB + d];
+    {  // thread (feature d, row group): the feature's weights stay in registers
+      const int d = tid & (kPolD - 1);
+      float wv[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc = fmaf(L.prm[kSmEmbW + d * 6 + c], x_raw[r * 6 + c], acc);
-      L.h[r][d] = r < nrow ? acc : 0.0f;
+      for (int c = 0; c < 6; ++c) wv[c] = L.prm[kSmEmbW + d * 6 + c];
+      const float bd = L.prm[kSmEmbB + d];
+      for (int r = tid >> 6; r < rows; r += nthr >> 6) {
+        float acc = bd;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc = fmaf(wv[c], x_raw[r * 6 + c], acc);
+        L.h[r][d] = r < nrow ? acc : 0.0f;
+      }
     }
     __syncthreads();
     for (int l = 0; l < kPolLayers; ++l) {
@@ -114,96 +200,161 @@ policy_kernel(PolicyArgs a) {
       // ---- attention block
       layer_norm_rows(L, rows, lp + kSmLn1G, lp + kSmLn1B);
       __syncthreads();
-      gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows, 3 * kPolD,
-                       [&](int m, int n, float v) { L.buf[m][n] = __float2bfloat16(v + lp[kSmBqkv + n]); });
+      __bf16 *Qp = L.buf, *Kp = L.buf + kPlane, *Vt = L.buf + 2 * kPlane;
+      gemm_rs_bf16<kPolD, 3 * kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows,
+                          [&](int m, int n, float v) {
+                            const __bf16 x = __float2bfloat16(v + lp[kSmBqkv + n]);
+                            if (n < 2 * kPolD) L.buf[(n >> 6) * kPlane + m * kLdQ + (n & 63)] = x;
+                            else Vt[(n - 2 * kPolD) * kLdVt + m] = x;
+                          });
       __syncthreads();
-      for (int e = tid; e < at * kPolHeads * nt; e += nthr) {
-        const int al = e / (kPolHeads * nt), rem = e % (kPolHeads * nt);
-        const int hd = rem / nt, tq = rem % nt;
-        const int r0 = al * nt, rq = r0 + tq;
-        const bf16x8 *qp = reinterpret_cast<const bf16x8 *>(&L.buf[rq][hd * kPolDh]);
-        const bf16x8 q0 = qp[0], q1 = qp[1];
-        float s[kPolMaxTok];
-        float mx = -INFINITY;
+      // attention on the matrix cores: one wavefront per (agent, head); the
+      // transposed products S^T = K Q^T and O^T = V^T P^T are single 16x16
+      // tiles (tokens padded to 16, head dim 16 padded to the instruction's
+      // K = 32 with zeros), so each lane holds four keys of one query and the
+      // softmax needs only two cross-lane steps
+      {
+        const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+        const int row = lane & 15, kg = lane >> 4;
+        const bf16x8 zero8 = {};
+        constexpr int NP = 2;  // (agent, head) pairs in flight per wavefront
+        for (int pr0 = wave * NP; pr0 < at * kPolHeads; pr0 += nw * NP) {
+          int r0[NP], hd[NP];
+          bool live[NP];
+          floatx4 st[NP];
 #pragma unroll
-        for (int u = 0; u < kPolMaxTok; ++u) {
-          s[u] = -INFINITY;
-          if (u < nt && L.mask[r0 + u]) {
-            const bf16x8 *kp = reinterpret_cast<const bf16x8 *>(&L.buf[r0 + u][kPolD + hd * kPolDh]);
-            const bf16x8 k0 = kp[0], k1 = kp[1];
-            float acc = 0.0f;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc = fmaf((float)q0[c], (float)k0[c], acc);
-#pragma unroll
-            for (int c = 0; c < 8; ++c) acc = fmaf((float)q1[c], (float)k1[c], acc);
-            s[u] = acc * 0.25f;
+          for (int i = 0; i < NP; ++i) {
+            const int pr = pr0 + i;
+            live[i] = pr < at * kPolHeads;
+            r0[i] = live[i] ? (pr / kPolHeads) * nt : 0;
+            hd[i] = pr % kPolHeads;
+            bf16x8 ka = zero8, qb = zero8;  // A = K (row = key), B = Q (column = query)
+            if (kg < 2 && row < nt) {
+              ka = *reinterpret_cast<const bf16x8 *>(Kp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 8 * kg);
+              qb = *reinterpret_cast<const bf16x8 *>(Qp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 8 * kg);
+            }
+            st[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            st[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, qb, st[i], 0, 0, 0);
           }
-          mx = fmaxf(mx, s[u]);
-        }
-        float z = 0.0f;
+          // st[i][j] = S[query row][key 4 kg + j]
+          float x[NP][4], m[NP], z[NP];
 #pragma unroll
-        for (int u = 0; u < kPolMaxTok; ++u) {
-          s[u] = s[u] > -INFINITY ? __expf(s[u] - mx) : 0.0f;
-          z += s[u];
-        }
-        const float iz = z > 0.0f ? 1.0f / z : 0.0f;  // rows of absent agents have no keys
-        float o[kPolDh];
+          for (int i = 0; i < NP; ++i) {
+            m[i] = -INFINITY;
 #pragma unroll
-        for (int c = 0; c < kPolDh; ++c) o[c] = 0.0f;
+            for (int j = 0; j < 4; ++j) {
+              const int key = 4 * kg + j;
+              const bool ok = key < nt && L.mask[r0[i] + (key < nt ? key : 0)];
+              x[i][j] = ok ? st[i][j] * 0.25f : -INFINITY;
+              m[i] = fmaxf(m[i], x[i][j]);
+            }
+          }
 #pragma unroll
-        for (int u = 0; u < kPolMaxTok; ++u) {
-          if (u < nt && s[u] > 0.0f) {
-            const bf16x8 *vp =
-                reinterpret_cast<const bf16x8 *>(&L.buf[r0 + u][2 * kPolD + hd * kPolDh]);
-            const bf16x8 v0 = vp[0], v1 = vp[1];
+          for (int i = 0; i < NP; ++i) m[i] = fmaxf(m[i], xor16f(m[i]));
 #pragma unroll
-            for (int c = 0; c < 8; ++c) o[c] = fmaf(s[u], (float)v0[c], o[c]);
+          for (int i = 0; i < NP; ++i) m[i] = fmaxf(m[i], xor32f(m[i]));
 #pragma unroll
-            for (int c = 0; c < 8; ++c) o[8 + c] = fmaf(s[u], (float)v1[c], o[8 + c]);
+          for (int i = 0; i < NP; ++i) {
+            z[i] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              x[i][j] = x[i][j] > -INFINITY ? __expf(x[i][j] - m[i]) : 0.0f;
+              z[i] += x[i][j];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < NP; ++i) z[i] += xor16f(z[i]);
+#pragma unroll
+          for (int i = 0; i < NP; ++i) z[i] += xor32f(z[i]);
+          // B = P^T (column = query, K = key): lanes of group 0 take keys 0-7
+          // (groups 0, 1), group 1 keys 8-15 (groups 2, 3)
+          floatx4 ot[NP];
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            const bf16x2 d0 = bf16x2{__float2bfloat16(x[i][0]), __float2bfloat16(x[i][1])};
+            const bf16x2 d1 = bf16x2{__float2bfloat16(x[i][2]), __float2bfloat16(x[i][3])};
+            const int w0 = __builtin_bit_cast(int, d0), w1 = __builtin_bit_cast(int, d1);
+            // group 0 takes its own words and group 1's (lane ^ 16); group 1
+            // takes groups 2 (lane ^ 48) and 3 (lane ^ 32)
+            const int w0x16 = xor16i(w0), w1x16 = xor16i(w1);
+            const int w0x32 = xor32i(w0), w1x32 = xor32i(w1);
+            const int w0x48 = xor32i(w0x16), w1x48 = xor32i(w1x16);
+            const int e0 = kg == 0 ? w0 : w0x48, e1 = kg == 0 ? w1 : w1x48;
+            const int e2 = kg == 0 ? w0x16 : w0x32, e3 = kg == 0 ? w1x16 : w1x32;
+            bf16x8 pb = zero8, va = zero8;  // A = V^T (row = head dim, K = key)
+            if (kg < 2) {
+              const bf16x2 p0 = __builtin_bit_cast(bf16x2, e0), p1 = __builtin_bit_cast(bf16x2, e1);
+              const bf16x2 p2 = __builtin_bit_cast(bf16x2, e2), p3 = __builtin_bit_cast(bf16x2, e3);
+              pb = bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+              // keys at or beyond nt are loaded (inside the buffer) but replaced by 0
+              const __bf16 *vr = Vt + (hd[i] * kPolDh + row) * kLdVt + r0[i] + 8 * kg;
+              const __bf16 zb = {};
+              if ((r0[i] & 1) == 0) {  // 4-byte aligned key pairs
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                  const bf16x2 v2 = reinterpret_cast<const bf16x2 *>(vr)[t];
+                  va[2 * t] = 8 * kg + 2 * t < nt ? v2[0] : zb;
+                  va[2 * t + 1] = 8 * kg + 2 * t + 1 < nt ? v2[1] : zb;
+                }
+              } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) va[t] = 8 * kg + t < nt ? vr[t] : zb;
+              }
+            }
+            ot[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            ot[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, pb, ot[i], 0, 0, 0);
+          }
+          // ot[i][j] = O[query row][head dim 4 kg + j]
+#pragma unroll
+          for (int i = 0; i < NP; ++i) {
+            if (live[i] && row < nt) {
+              const float iz = z[i] > 0.0f ? 1.0f / z[i] : 0.0f;  // no keys: zero output
+              bf16x4 o4;
+#pragma unroll
+              for (int j = 0; j < 4; ++j) o4[j] = __float2bfloat16(ot[i][j] * iz);
+              *reinterpret_cast<bf16x4 *>(&L.xn[r0[i] + row][hd[i] * kPolDh + 4 * kg]) = o4;
+            }
           }
         }
-        bf16x8 w0, w1v;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          w0[c] = __float2bfloat16(o[c] * iz);
-          w1v[c] = __float2bfloat16(o[8 + c] * iz);
-        }
-        bf16x8 *op = reinterpret_cast<bf16x8 *>(&L.xn[rq][hd * kPolDh]);
-        op[0] = w0;
-        op[1] = w1v;
       }
       __syncthreads();
-      gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows, kPolD,
+      gemm_rs_bf16<kPolD, kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows,
                        [&](int m, int n, float v) { L.h[m][n] += v + lp[kSmBo + n]; });
       __syncthreads();
       // ---- feed-forward block, hidden layer in two halves of 128
       layer_norm_rows(L, rows, lp + kSmLn2G, lp + kSmLn2B);
       __syncthreads();
       for (int half = 0; half < 2; ++half) {
-        gemm_cs_bf16<kPolD>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD, rows, 128,
+        gemm_rs_bf16<kPolD, 128>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD, rows,
                          [&](int m, int n, float v) {
-                           L.buf[m][n] = __float2bfloat16(gelu_tanh_fast(v + lp[kSmB1 + half * 128 + n]));
+                           L.buf[m * kLdHid + n] = __float2bfloat16(gelu_tanh_fast(v + lp[kSmB1 + half * 128 + n]));
                          });
         __syncthreads();
-        gemm_cs_bf16<128>(&L.buf[0][0], 3 * kPolD + 8, w2 + half * 128, kPolLdF, rows, kPolD,
+        gemm_rs_bf16<128, kPolD>(L.buf, kLdHid, w2 + half * 128, kPolLdF, rows,
                        [&](int m, int n, float v) { L.h[m][n] += v + (half == 0 ? lp[kSmB2 + n] : 0.0f); });
         __syncthreads();
       }
     }
-    // ---- head on the self token of each agent: final LayerNorm, logits
+    // ---- head on the self token of each agent: final LayerNorm (one thread
+    // per agent, into a scratch copy in the QKV buffer), then one thread per
+    // (agent, logit)
     {
-      const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
       const float *fp = L.prm + kSmFinal;
-      for (int al = wave; al < at; al += nw) {
-        const float x = L.h[al * nt][lane];
-        const float mean = wave_sum(x) * (1.0f / kPolD);
-        const float d = x - mean;
-        const float var = wave_sum(d * d) * (1.0f / kPolD);
-        const float sv = fmaf(d * rsqrtf(var + 1e-5f), fp[kPolLnfG + lane], fp[kPolLnfB + lane]);
-        for (int k = 0; k < kPolActions; ++k) {
-          const float v = wave_sum(fp[kPolWh + k * kPolD + lane] * sv);
-          if (lane == 0) L.logits[al][k] = v + fp[kPolBh + k];
-        }
+      float(*sv)[kPolD + 4] = reinterpret_cast<float(*)[kPolD + 4]>(L.buf);
+      for (int al = tid; al < at; al += nthr) {
+        ln_row(&L.h[al * nt][0], fp + kPolLnfG, fp + kPolLnfB, [&](int q, const float(&y)[8]) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) sv[al][8 * q + c] = y[c];
+        });
+      }
+      __syncthreads();
+      for (int e = tid; e < at * kPolActions; e += nthr) {
+        const int al = e / kPolActions, k = e % kPolActions;
+        const float *w = fp + kPolWh + k * kPolD;
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int d = 0; d < kPolD; ++d) acc[d & 3] = fmaf(w[d], sv[al][d], acc[d & 3]);
+        L.logits[al][k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + fp[kPolBh + k];
       }
     }
     __syncthreads();
