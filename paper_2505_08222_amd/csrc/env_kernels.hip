@@ -89,6 +89,12 @@ __device__ __forceinline__ u32x4 draw(uint32_t c0, uint32_t c1, uint32_t c2, uin
   return philox4x32_10(c0, c1, c2, c3, key0, key1);
 }
 
+// Observation tokens a wavefront can stage: 64 agents (lanes) of at most
+// 2S tokens each. Only a token's offset word and mask are staged; the type
+// columns follow from the token's position and are rebuilt while copying.
+template <int S>
+constexpr int kStageTok = 64 * 2 * S;
+
 // Element (g + G*sl) of a per-env array held with compile-time indices.
 template <int G, int N>
 __device__ __forceinline__ float pick(const float (&arr)[N], int g, int sl) {
@@ -203,14 +209,16 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 // the same bits as the full form on those outputs and carries none of the
 // other paths' pointers and registers.
 // ---------------------------------------------------------------------------
-template <int S, int WC, int G, bool FULL>
-__global__ void __launch_bounds__(256, (S == 2 && WC == 10 && !FULL) ? 3 : 1)
+template <int S, int WC, int G, bool FULL, bool STAGE>
+__global__ void __launch_bounds__(256, (!FULL && WC == 10 && S <= 5) ? 2 : 1)
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
                uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
+  constexpr bool stage = STAGE && !FULL;
   constexpr int MA = S, MT = S;
   constexpr int NPL = (MT + G - 1) / G;  // (agent, target) pairs per lane
   constexpr int NQ = (MT + 3) / 4;       // range-noise draws per agent
-  // per wavefront: the targets of its envs, (x, y, heading, speed)
+  // per wavefront: the targets of its envs, (x, y, heading, speed); then
+  // (lean form) the staging area of the wavefront's observation block
   extern __shared__ float4 lds_targets[];
   __shared__ float lds_dpsi[4][8];  // per wavefront: the action table
 
@@ -251,6 +259,20 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   const float kInf = __int_as_float(0x7f800000);
   const float kNaN = __int_as_float(0x7fc00000);
   float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
+  // staging of the wavefront's observation tokens (offsets only; the type
+  // columns follow from the token's position) and masks, in output order
+  float2 *st_xy = reinterpret_cast<float2 *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT) +
+                  (size_t)wib * kStageTok<S>;
+  uint8_t *st_m = reinterpret_cast<uint8_t *>(reinterpret_cast<float2 *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT) +
+                                              (size_t)(blockDim.x >> 6) * kStageTok<S>) +
+                  (size_t)wib * kStageTok<S>;
+  const int ntok = na + nt;
+  const int agent_w = el * na + i;  // agent index inside the wavefront
+  const int64_t env_left = C.nenv - (int64_t)(wave - C.wave0) * epw;  // >= 1 for a live wave
+  const int64_t nenv_w = env_left < epw ? env_left : epw;
+  const int ntok_w = (int)nenv_w * na * ntok;  // tokens of the wavefront's active agents
+  const int64_t kbase_w = C.koff0 + (int64_t)(wave - C.wave0) * epw * na * ntok;
+  const int m_lane0 = lane % ntok, m_step = 64 % ntok;  // token positions for the block copy
 
   // ---- load state: targets of the env into LDS (each lane its own blocks)
   for (int q = r; q < nB; q += lpe) {
@@ -554,13 +576,23 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
           if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
         }
+        // this lane's tokens: into the staging area (position = output order)
+        // for a large batch, else straight to the output
+        const int tb = agent_w * ntok;
         const int64_t kb = (int64_t)step * o.K + kbase;
         float *ob = o.obs ? o.obs + kb * 6 : nullptr;
         uint8_t *om = o.obs_mask ? o.obs_mask + kb : nullptr;
-        if (g == 0) {
-          if (ob) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
-          if (om) om[0] = 1;
-        }
+        auto emit = [&](int m, float dx, float dy, bool ok, float is_self, float is_agent,
+                        float is_target) {
+          if constexpr (stage) {
+            st_xy[tb + m] = make_float2(dx, dy);
+            st_m[tb + m] = ok ? 1 : 0;
+          } else {
+            if (ob) store_token(ob + m * 6, dx, dy, is_self, is_agent, is_target);
+            if (om) om[m] = ok ? 1 : 0;
+          }
+        };
+        if (g == 0) emit(0, 0.0f, 0.0f, true, 1.0f, 0.0f, 0.0f);
 #pragma unroll
         for (int m = 1; m < MA; ++m) {
           if (m < na && (m % G) == g) {
@@ -569,8 +601,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             const float oy = before ? agy[m - 1] : agy[m];
             const float dx = ox - ax, dy = oy - ay;
             const bool ok = norm2(dx, dy) <= p.comm_range;
-            if (ob) store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
-            if (om) om[m] = ok ? 1 : 0;
+            emit(m, ok ? dx : 0.0f, ok ? dy : 0.0f, ok, 0.0f, 1.0f, 0.0f);
           }
         }
 #pragma unroll
@@ -578,14 +609,31 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           if (j < nt && (j % G) == g) {
             const int sl = j / G;
             const bool ok = (evb >> sl) & 1u;
-            if (ob)
-              store_token(ob + (na + j) * 6, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f,
-                          0.0f, 0.0f, 1.0f);
-            if (om) om[na + j] = ok ? 1 : 0;
+            emit(na + j, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, ok, 0.0f, 0.0f, 1.0f);
           }
         }
         if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
           status |= kStatusNonFinite;
+      }
+      // the wavefront's token block is contiguous in the output: one lane per
+      // token, consecutive lanes on consecutive tokens
+      if constexpr (stage) {
+        wave_lds_fence();
+        const int64_t kw = (int64_t)step * o.K + kbase_w;
+        float2 *ob = o.obs ? reinterpret_cast<float2 *>(o.obs + kw * 6) : nullptr;
+        uint8_t *om = o.obs_mask ? o.obs_mask + kw : nullptr;
+        int m = m_lane0;  // position of token `t` inside its agent's token list
+        for (int t = lane; t < ntok_w; t += 64) {
+          if (ob) {
+            ob[3 * t] = st_xy[t];
+            ob[3 * t + 1] = make_float2(0.0f, m == 0 ? 1.0f : 0.0f);
+            ob[3 * t + 2] = make_float2((m >= 1 && m < na) ? 1.0f : 0.0f, m >= na ? 1.0f : 0.0f);
+          }
+          if (om) om[t] = st_m[t];
+          m += m_step;
+          if (m >= ntok) m -= ntok;
+        }
+        wave_lds_fence();  // the staging area is rewritten next step
       }
     } else if (active) {
       if (r == 0) {
@@ -831,6 +879,14 @@ int launch_env_windows(const DevState &s, int32_t W, float *win, float *sigma, f
 // ---------------------------------------------------------------------------
 static int check_launch() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
+static int device_cus() {
+  int dev = 0, n = 0;
+  hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+    n = 256;
+  return n;
+}
+
 int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const DevOut &o,
                  void *stream) {
   hipStream_t st = (hipStream_t)stream;
@@ -848,14 +904,16 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
   return 0;
 }
 
-template <int S, int WC, int G, bool FULL>
+template <int S, int WC, int G, bool FULL, bool STAGE>
 static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
                             const DevState *s, int32_t t0, int32_t T, uint32_t episode,
                             const int32_t *actions, const DevOut &o, hipStream_t st) {
   const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
-  const size_t lds = (size_t)waves_per_block * 64 * S * sizeof(float4);
-  hipLaunchKernelGGL((rollout_kernel<S, WC, G, FULL>), dim3(blocks), dim3(64 * waves_per_block), lds,
-                     st, p, s, num_waves, t0, T, episode, actions, o);
+  // per wavefront: target slab, then (lean form) token offsets and masks
+  const size_t lds = (size_t)waves_per_block *
+                     (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0));
+  hipLaunchKernelGGL((rollout_kernel<S, WC, G, FULL, STAGE>), dim3(blocks),
+                     dim3(64 * waves_per_block), lds, st, p, s, num_waves, t0, T, episode, actions, o);
   return check_launch();
 }
 
@@ -875,12 +933,20 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
                     !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
                     p.comm_loss_p == 0.0f && p.gn_iters == 0;
-#define MIL_ROLL(SC, WCV, GV)                                                                 \
-  if (size_class == SC && wcap == WCV && G == GV)                                            \
-    return lean ? launch_rollout_t<SC, WCV, GV, false>(waves_per_block, num_waves, p, s, t0, \
-                                                       T, episode, actions, o, st)           \
-                : launch_rollout_t<SC, WCV, GV, true>(waves_per_block, num_waves, p, s, t0,  \
-                                                      T, episode, actions, o, st);
+  // the lean form stages its observation block for a coalesced write once at
+  // least two wavefronts per SIMD take turns on the store path (large
+  // batches); small batches are latency-bound and write directly
+  const bool stage = lean && num_waves >= 8 * device_cus();
+#define MIL_ROLL(SC, WCV, GV)                                                                       \
+  if (size_class == SC && wcap == WCV && G == GV) {                                                \
+    if (!lean)                                                                                      \
+      return launch_rollout_t<SC, WCV, GV, true, false>(waves_per_block, num_waves, p, s, t0, T,  \
+                                                        episode, actions, o, st);                 \
+    return stage ? launch_rollout_t<SC, WCV, GV, false, true>(waves_per_block, num_waves, p, s,   \
+                                                              t0, T, episode, actions, o, st)     \
+                 : launch_rollout_t<SC, WCV, GV, false, false>(waves_per_block, num_waves, p, s,  \
+                                                               t0, T, episode, actions, o, st);   \
+  }
   MIL_ROLL(2, 10, 1)
   MIL_ROLL(2, 10, 2)
   MIL_ROLL(2, 16, 1)

@@ -153,12 +153,14 @@ def test_full_size_ragged_sampled(orc):
     print("ragged-full", rep)
 
 
-@pytest.mark.parametrize("cfgname,E,T", [("batched", 4096, 500), ("ragged", 3000, 120)])
+@pytest.mark.parametrize("cfgname,E,T", [("batched", 4096, 500), ("ragged", 3000, 120),
+                                         ("ragged", 65536, 12), ("batched", 262144, 12)])
 def test_lean_form_matches_full_bitwise(cfgname, E, T):
     """Recording only obs, obs_mask, reward and done (the benchmark's launch
     form, compiled without the other outputs' paths) gives the same bits,
     final state and metrics as the full form that the parity tests hold to
-    the oracle."""
+    the oracle. The two large batches take the staged, coalesced write of
+    the observation block; the small ones write directly."""
     cfg = env_config(cfgname, episode_len=T)
     lean_env = _env(cfg, E, seed=0)
     full_env = _env(cfg, E, seed=0)
