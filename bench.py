@@ -197,6 +197,44 @@ def env_sweep(args, cfgname="batched", sizes=(4096, 16384, 65536, 262144, 104857
     return points
 
 
+def train_estimator(args):
+    """The learned estimator's network, trained by the library's kernels on
+    windows of ragged-configuration rollouts (W = 16): 1e7 windows, labels =
+    exact estimates within 2x the mean range from tracks with condition
+    number <= 1e3 (elsewhere the exact solve is noise, and those windows fall
+    back to it anyway), 8 epochs of Adam. Returns (params, history, seconds,
+    number of training windows)."""
+    import torch
+
+    from paper_2505_08222_amd import learned
+    from paper_2505_08222_amd.configs import CONFIGS
+
+    c = CONFIGS["learned"]
+    cfg = dict(c["env"])
+    n_train = c["train_windows"]
+    if args.envs:
+        n_train = max(20000, int(n_train * args.envs / c["num_envs"]))
+    E = args.envs or c["num_envs"]
+    t0 = time.perf_counter()
+    tr = learned.rollout_windows(cfg, E, n_train, seed=0)
+    x, frame = learned.features(tr["win"])
+    y = learned.targets(frame, tr["exact"])
+    kap_tr = window_condition(tr["win"])
+    keep = (y.norm(dim=1) <= 2.0) & (kap_tr <= 1e3)
+    x, y = x[keep].contiguous(), y[keep].contiguous()
+    log(f"[learned] training set {x.shape[0]} of {tr['win'].shape[0]} windows "
+        f"({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, hist = learned.train(x, y, epochs=8, batch=8192, lr=2e-3, lr_final=3e-5, seed=0,
+                                 log=lambda m: None)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    log(f"[learned] trained {len(hist)} logged steps in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
+        f"{hist[-1][1]:.3e}")
+    return params, hist, train_s, int(x.shape[0])
+
+
 def bench_learned(args):
     """Learned estimator (the learned-estimator configuration): windows of 16
     from ragged-configuration rollouts, Adam training of the BF16 MLP with the
@@ -212,34 +250,14 @@ def bench_learned(args):
     c = CONFIGS["learned"]
     cfg = dict(c["env"])
     torch.cuda.set_device(0)
-    n_train, n_infer = c["train_windows"], c["infer_windows"]
+    n_infer = c["infer_windows"]
     if args.envs:  # smaller runs for quick checks
-        scale = args.envs / c["num_envs"]
-        n_train, n_infer = max(20000, int(n_train * scale)), max(20000, int(n_infer * scale))
+        n_infer = max(20000, int(n_infer * args.envs / c["num_envs"]))
     E = args.envs or c["num_envs"]
+    params, hist, train_s, n_fit = train_estimator(args)
     t0 = time.perf_counter()
-    tr = learned.rollout_windows(cfg, E, n_train, seed=0)
     te = learned.rollout_windows(cfg, E, n_infer, seed=1, first_step=125)
-    log(f"[learned] windows: train {tr['win'].shape[0]}, infer {te['win'].shape[0]} "
-        f"({time.perf_counter() - t0:.1f} s)")
-    x, frame = learned.features(tr["win"])
-    y = learned.targets(frame, tr["exact"])
-    # labels the network can learn: exact estimates within 2x the mean range,
-    # from windows whose agent track is not near-collinear (the exact solve is
-    # noise there, and those windows fall back to it anyway)
-    kap_tr = window_condition(tr["win"])
-    keep = (y.norm(dim=1) <= 2.0) & (kap_tr <= 1e3)
-    x, y = x[keep].contiguous(), y[keep].contiguous()
-    log(f"[learned] training set {x.shape[0]} windows (exact estimate within 2x the mean range, "
-        f"condition number of the track <= 1e3)")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    params, hist = learned.train(x, y, epochs=8, batch=8192, lr=2e-3, lr_final=3e-5, seed=0,
-                                 log=lambda m: None)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
-    log(f"[learned] trained {len(hist)} logged steps in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
-        f"{hist[-1][1]:.3e}")
+    log(f"[learned] inference windows {te['win'].shape[0]} ({time.perf_counter() - t0:.1f} s)")
     win, sigma, truth = te["win"], te["sigma"], te["truth"]
     N = win.shape[0]
     work = learned._work(N, "bf16", win.device)
@@ -299,8 +317,8 @@ def bench_learned(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"learned estimator: 16-entry windows from ragged-configuration "
-                               f"rollouts, train {x.shape[0]}, infer {N}",
-                   "train_windows": int(x.shape[0]), "infer_windows": int(N)},
+                               f"rollouts, train {n_fit}, infer {N}",
+                   "train_windows": int(n_fit), "infer_windows": int(N)},
         "infer_ms": {"learned_guarded": ms_mlp, "mlp_forward_only": ms_fwd,
                      "exact_fp64": ms_ex, "exact_fp32": ms_ex32, "exact_gauss_newton8": ms_gn},
         "speedup_vs": {"exact_fp64": ms_ex / ms_mlp, "exact_fp32": ms_ex32 / ms_mlp,
@@ -356,23 +374,35 @@ def bench_policy(args):
     E = args.envs or c["num_envs"]
     T = c["steps"]
     torch.cuda.set_device(0)
-    env = Env(cfg, E, seed=c["seed"])
     params = policy.init_params(c["seed"])
-    pr = policy.PolicyRollout(env, params)
-    gout, gm = pr.capture(T, record=("reward", "done"))
-    for _ in range(args.warmup):
-        pr.launch()
-    torch.cuda.synchronize()
+    mlp = None if args.no_learned_loop else train_estimator(args)[0]
+
+    def timed_loop(mlp_params):
+        env = Env(cfg, E, seed=c["seed"])
+        pr = policy.PolicyRollout(env, params, mlp_params=mlp_params, k_sigma=3.0)
+        gout, gm = pr.capture(T, record=("reward", "done"))
+        for _ in range(args.warmup):
+            pr.launch()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            pr.launch()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return env, gm, max(wall, ev0.elapsed_time(ev1) / 1e3)
+
+    env, gm, elapsed = timed_loop(mlp)
+    exact_loop = None
+    if mlp is not None:
+        _, gm_exact, el_exact = timed_loop(None)
+        exact_loop = {"env_steps_per_s": E * T * args.steps / el_exact,
+                      "ms_per_step": el_exact * 1e3 / args.steps,
+                      "mean_reward": float(gm_exact[0] / max(float(gm_exact[6]), 1))}
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        pr.launch()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
     # the policy kernel alone, on the final observation, timed with events
     n_tok = cfg["n_agents"] + cfg["n_targets"]
     env.reset(0)
@@ -402,7 +432,11 @@ def bench_policy(args):
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"policy: {E} envs x 5 agents x 5 targets x {T} steps, attention "
                                "policy (d 64, 4 heads, 2 layers, FFN 256, random init) + env step "
-                               "per step, one HIP graph", "envs": E, "episode_steps": T},
+                               + ("with the learned estimator (exact fallback at 3 sigma) in the loop"
+                                  if mlp is not None else "with the exact estimator")
+                               + " per step, one HIP graph", "envs": E, "episode_steps": T,
+                   "estimator": "learned" if mlp is not None else "exact"},
+        "exact_estimator_loop": exact_loop,
         "agent_steps_per_s": env.A * T * args.steps / elapsed,
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0,
@@ -428,6 +462,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the env-count sweep that follows the batched workload")
+    ap.add_argument("--no-learned-loop", action="store_true",
+                    help="policy workload: keep the exact estimator in the loop")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain copy kernel used to calibrate HBM counters")
     args = ap.parse_args()

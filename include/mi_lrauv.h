@@ -312,14 +312,28 @@ int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions
                    const uint8_t *d_mask, const float *d_params, float *d_logits,
                    int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
                    int64_t work_bytes, void *stream);
+/* Workspace for env_policy_rollout on this bound batch (256-byte aligned):
+ * the policy's, plus (learned != 0) every tracker's window, sigma, estimate
+ * and flag and the learned estimator's own workspace. -1 on a bad handle. */
+int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned);
 /* Closed loop on a bound fixed-count batch: reset(episode), then T times
  * {policy on the latest observation -> actions; env step}, then (d_metrics
  * not NULL) the metrics reduction. outs as for env_rollout ([T][...]). With
  * capture = 1 the sequence is captured as the handle's HIP graph (replayed by
- * env_graph_launch) instead of run. */
+ * env_graph_launch) instead of run.
+ * d_mlp_params (may be NULL): parameters of the learned estimator (mlp_*). When
+ * given, each env step is split around it: the step moves the entities, draws
+ * the ranges and pushes the windows; every tracker's window goes through
+ * mlp_infer (residual test at k_sigma * sigma_r, exact fallback); then the step
+ * takes those estimates (for trackers whose window is full; shorter windows keep
+ * the exact estimator) and computes reward and observation. Needs window <= 21.
+ * Errors: MIL_EINVAL (ragged batch, too many tokens or actions, bad T/episode,
+ * window too long for the learned estimator), MIL_ESHAPE (workspace smaller
+ * than env_policy_workspace_bytes), MIL_EALIGN, MIL_EHIP. */
 int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
-                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
-                       void *d_work, int64_t work_bytes, void *stream);
+                       const float *d_mlp_params, float k_sigma, const mil_env_outputs *outs,
+                       double *d_metrics, int32_t capture, void *d_work, int64_t work_bytes,
+                       void *stream);
 
 #ifdef __cplusplus
 }

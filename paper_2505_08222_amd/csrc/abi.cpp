@@ -718,6 +718,37 @@ void prepared_ptrs(char *prep, __bf16 **wq, __bf16 **wo, __bf16 **w1, __bf16 **w
   *w2 = *w1 + mil::kPolPrepW1;
 }
 
+// env_policy_rollout's workspace: the policy's, then (learned estimator in
+// the loop) windows [P][W][3], sigma [P], estimates [P][2], flags [P] and the
+// estimator's workspace.
+struct EnvPolicyWork {
+  PolicyWork pol;
+  int64_t win, sig, est, flag, mlp, mlp_bytes, total;
+};
+
+EnvPolicyWork env_policy_work(const mil_env *h, bool learned) {
+  EnvPolicyWork w{};
+  const int64_t A = h->aoff[h->E], K = h->koff[h->E], P = h->poff[h->E];
+  w.pol = policy_work(A, K);
+  int64_t o = w.pol.total;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  if (learned) {
+    const int64_t W = h->P.window;
+    w.win = take(P * W * 3 * 4);
+    w.sig = take(P * 4);
+    w.est = take(P * 2 * 4);
+    w.flag = take(P);
+    w.mlp_bytes = mlp_workspace_bytes(P, 0);
+    w.mlp = take(w.mlp_bytes);
+  }
+  w.total = o;
+  return w;
+}
+
 int policy_tile(int n_tok) {
   const int at = mil::kPolRows / n_tok;
   return at < mil::kPolMaxAgents ? at : mil::kPolMaxAgents;
@@ -777,9 +808,15 @@ int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions
   return MIL_OK;
 }
 
+int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned) {
+  if (!h || !h->ws) return -1;
+  return env_policy_work(h, learned != 0).total;
+}
+
 int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
-                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
-                       void *d_work, int64_t work_bytes, void *stream) {
+                       const float *d_mlp_params, float k_sigma, const mil_env_outputs *outs,
+                       double *d_metrics, int32_t capture, void *d_work, int64_t work_bytes,
+                       void *stream) {
   if (!h || !d_params) return fail(MIL_EINVAL, "null argument");
   if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
   if (h->P.ragged) return fail(MIL_EINVAL, "the policy needs a batch with fixed counts");
@@ -790,10 +827,14 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
   if (episode >= (1ull << 28)) return fail(MIL_EINVAL, "episode must be < 2^28");
   int rc = check_outputs(outs);
   if (rc) return rc;
-  const int64_t A = h->aoff[h->E], K = h->koff[h->E];
-  const PolicyWork w = policy_work(A, K);
+  const bool learned = d_mlp_params != nullptr;
+  if (learned && (h->P.window > 21 || !(k_sigma >= 0.0f)))
+    return fail(MIL_EINVAL, "the learned estimator needs window <= 21 and k_sigma >= 0");
+  const int64_t A = h->aoff[h->E], K = h->koff[h->E], Pn = h->poff[h->E];
+  const EnvPolicyWork ew = env_policy_work(h, learned);
+  const PolicyWork &w = ew.pol;
   if (!d_work || (((uintptr_t)d_work) & 255)) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
-  if (work_bytes < w.total) return fail(MIL_ESHAPE, "workspace too small (policy_workspace_bytes)");
+  if (work_bytes < ew.total) return fail(MIL_ESHAPE, "workspace too small (env_policy_workspace_bytes)");
   char *ws = (char *)d_work;
   float *wobs = (float *)(ws + w.obs);
   uint8_t *wmask = (uint8_t *)(ws + w.mask);
@@ -852,9 +893,29 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
     o.actions = slice(full.actions, A);
     o.ranges = slice(full.ranges, h->poff[h->E]);
     o.err = slice(full.err, h->toff[h->E]);
-    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                              (const mil::DevState *)(h->ws + h->off.devstate), t, 1,
-                              (uint32_t)episode, wact, o, st);
+    const mil::DevState *dstate = (const mil::DevState *)(h->ws + h->off.devstate);
+    if (!learned) {
+      lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                                dstate, t, 1, (uint32_t)episode, wact, o, st);
+    } else {
+      // move, estimate every tracker from its window, then observe
+      float *win = (float *)(ws + ew.win), *sig = (float *)(ws + ew.sig);
+      float *est = (float *)(ws + ew.est);
+      uint8_t *flag = (uint8_t *)(ws + ew.flag);
+      lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                                dstate, t, 1, (uint32_t)episode, wact, o, st,
+                                mil::DevExt{1, nullptr, nullptr});
+      if (!lrc) lrc = mil::launch_env_windows(h->ds, h->P.window, win, sig, nullptr, st);
+      if (!lrc)
+        lrc = mlp_infer(win, Pn, h->P.window, d_mlp_params, sig, k_sigma, 0, h->P.guard_tau, est,
+                        flag, ws + ew.mlp, ew.mlp_bytes, st) == MIL_OK
+                  ? 0
+                  : -1;
+      if (!lrc)
+        lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
+                                  h->ds, dstate, t, 1, (uint32_t)episode, wact, o, st,
+                                  mil::DevExt{2, est, flag});
+    }
   }
   if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
   if (capture) {

@@ -63,6 +63,17 @@ struct DevOut {
   float *err;
 };
 
+// Split step of the full kernel, for an estimator that runs between its two
+// halves: phase 1 moves the entities, draws the ranges and pushes the window;
+// phase 2 takes each tracker's estimate from est [P][2] / flag [P] (flag 0 or
+// 1: estimate present, 2: refused, hold the previous one) once its window is
+// full, then computes reward, observation and outputs. phase 0: whole step.
+struct DevExt {
+  int32_t phase;
+  const float *est;
+  const uint8_t *flag;
+};
+
 // Kernel launchers (env_kernels.hip). All enqueue on `stream`.
 int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const DevOut &o,
                  void *stream);
@@ -71,7 +82,7 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
 int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_block,
                    int num_waves, const DevParams &p, const DevState &s, const DevState *d_state,
                    int32_t t0, int32_t T, uint32_t episode, const int32_t *actions,
-                   const DevOut &o, void *stream);
+                   const DevOut &o, void *stream, const DevExt &ext = DevExt{0, nullptr, nullptr});
 int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
                    void *stream);
 int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream);

@@ -212,8 +212,11 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 template <int S, int WC, int G, bool FULL, bool STAGE>
 __global__ void __launch_bounds__(256, (!FULL && WC == 10 && S <= 5) ? 2 : 1)
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
-               uint32_t episode, const int32_t *__restrict__ actions, DevOut o) {
+               uint32_t episode, const int32_t *__restrict__ actions, DevOut o, DevExt ext) {
   constexpr bool stage = STAGE && !FULL;
+  // split step (full form only): phase 1 moves, phase 2 observes
+  const bool move = !FULL || ext.phase != 2;
+  const bool observe = !FULL || ext.phase != 1;
   constexpr int MA = S, MT = S;
   constexpr int NPL = (MT + G - 1) / G;  // (agent, target) pairs per lane
   constexpr int NQ = (MT + 3) / 4;       // range-noise draws per agent
@@ -331,11 +334,11 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     } else {
       act = (int)choice(xa.x, (uint32_t)p.n_actions);
     }
-    float za, zb;
-    normal2(xa.y, xa.z, za, zb);
-    const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
-    apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
-    {
+    if (move) {
+      float za, zb;
+      normal2(xa.y, xa.z, za, zb);
+      const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
+      apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
       float sn, cs;
       sincos_rad(apsi, sn, cs);
       ax = fmaf(vdt, cs, ax);
@@ -344,7 +347,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     const bool comm_ok = FULL ? !(u01(xa.w) < p.comm_loss_p) : true;
 
     // ---- targets owned by this lane (blocks of two): heading random walk
-    for (int q = r; q < nB; q += lpe) {
+    for (int q = r; move && q < nB; q += lpe) {
       const u32x4 xt =
           draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
       float zt[2];
@@ -378,42 +381,45 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     }
     wave_lds_fence();  // every lane has read before next step's owners write
 
+    if (move) {
     // ---- noisy ranges after the move; missing beyond the detection range
-    float rnew[NPL];
+      float rnew[NPL];
 #pragma unroll
-    for (int sl = 0; sl < NPL; ++sl) rnew[sl] = kNaN;
+      for (int sl = 0; sl < NPL; ++sl) rnew[sl] = kNaN;
 #pragma unroll
-    for (int q4 = 0; q4 < NQ; ++q4) {
-      if (4 * q4 < nt) {
-        const u32x4 xr = draw(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4, c3meas,
-                              p.key0, p.key1);
-        float zr[4];
-        normal2(xr.x, xr.y, zr[0], zr[1]);
-        normal2(xr.z, xr.w, zr[2], zr[3]);
+      for (int q4 = 0; q4 < NQ; ++q4) {
+        if (4 * q4 < nt) {
+          const u32x4 xr = draw(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4, c3meas,
+                                p.key0, p.key1);
+          float zr[4];
+          normal2(xr.x, xr.y, zr[0], zr[1]);
+          normal2(xr.z, xr.w, zr[2], zr[3]);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int j = 4 * q4 + m;
-          if (j < MT && j < nt && (j % G) == g) {
-            const float dist = norm2(ax - tpx[j], ay - tpy[j]);
-            const float rr = fmaf(sig_r, zr[m], dist);
-            rnew[j / G] = (!FULL || dist <= p.det_range) ? rr : kNaN;
+          for (int m = 0; m < 4; ++m) {
+            const int j = 4 * q4 + m;
+            if (j < MT && j < nt && (j % G) == g) {
+              const float dist = norm2(ax - tpx[j], ay - tpy[j]);
+              const float rr = fmaf(sig_r, zr[m], dist);
+              rnew[j / G] = (!FULL || dist <= p.det_range) ? rr : kNaN;
+            }
           }
         }
       }
+  
+      // ---- range history: entry 0 is the newest
+#pragma unroll
+      for (int k = WC - 1; k > 0; --k) {
+        hx[k] = hx[k - 1];
+        hy[k] = hy[k - 1];
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) hr[sl][k] = hr[sl][k - 1];
+      }
+      hx[0] = ax;
+      hy[0] = ay;
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
     }
-
-    // ---- range history: entry 0 is the newest
-#pragma unroll
-    for (int k = WC - 1; k > 0; --k) {
-      hx[k] = hx[k - 1];
-      hy[k] = hy[k - 1];
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) hr[sl][k] = hr[sl][k - 1];
-    }
-    hx[0] = ax;
-    hy[0] = ay;
-#pragma unroll
-    for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
+    if (!observe) continue;  // phase 1 ends here: the estimator runs next
     const int filled = min((int)t + 1, W);
 
     // ---- trackers (Sec. II-A): linearised LS about the centroid of the
@@ -423,7 +429,21 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     // term of the centred form vanishes because sum u_k = 0). Other trackers
     // take the general path below.
     uint32_t pending = 0;
-    if (filled >= 3) {
+    if (FULL && ext.phase == 2 && filled == W) {
+      // estimates from the external estimator (window full)
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) {
+        const int j = g + G * sl;
+        if (j < nt) {
+          const int64_t pidx = pbase + j;
+          if (ext.flag[pidx] != 2) {
+            ex[sl] = ext.est[2 * pidx];
+            ey[sl] = ext.est[2 * pidx + 1];
+            evb |= 1u << sl;
+          }
+        }
+      }
+    } else if (filled >= 3) {
       double mx = 0.0, my = 0.0;
 #pragma unroll
       for (int k = 0; k < WC; ++k)
@@ -907,20 +927,22 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
 template <int S, int WC, int G, bool FULL, bool STAGE>
 static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
                             const DevState *s, int32_t t0, int32_t T, uint32_t episode,
-                            const int32_t *actions, const DevOut &o, hipStream_t st) {
+                            const int32_t *actions, const DevOut &o, hipStream_t st,
+                            const DevExt &ext) {
   const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
   // per wavefront: target slab, then (lean form) token offsets and masks
   const size_t lds = (size_t)waves_per_block *
                      (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0));
   hipLaunchKernelGGL((rollout_kernel<S, WC, G, FULL, STAGE>), dim3(blocks),
-                     dim3(64 * waves_per_block), lds, st, p, s, num_waves, t0, T, episode, actions, o);
+                     dim3(64 * waves_per_block), lds, st, p, s, num_waves, t0, T, episode, actions, o,
+                     ext);
   return check_launch();
 }
 
 int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num_waves,
                    const DevParams &p, const DevState &hs, const DevState *s, int32_t t0,
                    int32_t T, uint32_t episode, const int32_t *actions, const DevOut &o_in,
-                   void *stream) {
+                   void *stream, const DevExt &ext) {
   hipStream_t st = (hipStream_t)stream;
   if (num_waves <= 0 || T <= 0) return 0;
   DevOut o = o_in;
@@ -932,7 +954,7 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   // the lean form applies when none of the full form's extra paths is asked for
   const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
                     !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
-                    p.comm_loss_p == 0.0f && p.gn_iters == 0;
+                    p.comm_loss_p == 0.0f && p.gn_iters == 0 && ext.phase == 0;
   // the lean form stages its observation block for a coalesced write once at
   // least two wavefronts per SIMD take turns on the store path (large
   // batches); small batches are latency-bound and write directly
@@ -941,11 +963,11 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   if (size_class == SC && wcap == WCV && G == GV) {                                                \
     if (!lean)                                                                                      \
       return launch_rollout_t<SC, WCV, GV, true, false>(waves_per_block, num_waves, p, s, t0, T,  \
-                                                        episode, actions, o, st);                 \
+                                                        episode, actions, o, st, ext);            \
     return stage ? launch_rollout_t<SC, WCV, GV, false, true>(waves_per_block, num_waves, p, s,   \
-                                                              t0, T, episode, actions, o, st)     \
+                                                              t0, T, episode, actions, o, st, ext) \
                  : launch_rollout_t<SC, WCV, GV, false, false>(waves_per_block, num_waves, p, s,  \
-                                                               t0, T, episode, actions, o, st);   \
+                                                               t0, T, episode, actions, o, st, ext);\
   }
   MIL_ROLL(2, 10, 1)
   MIL_ROLL(2, 10, 2)

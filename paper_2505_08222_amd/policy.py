@@ -12,8 +12,9 @@ _SIG = {
     "policy_forward": [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint32,
                        C.c_void_p, C.c_int64, C.c_void_p],
-    "env_policy_rollout": [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p, C.POINTER(EnvOutputs),
-                           C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p],
+    "env_policy_rollout": [C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p, C.c_void_p, C.c_float,
+                           C.POINTER(EnvOutputs), C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
+                           C.c_void_p],
 }
 _done = False
 
@@ -28,6 +29,8 @@ def _l():
         L.policy_num_params.restype = C.c_int64
         L.policy_workspace_bytes.argtypes = [C.c_int64, C.c_int64]
         L.policy_workspace_bytes.restype = C.c_int64
+        L.env_policy_workspace_bytes.argtypes = [C.c_void_p, C.c_int32]
+        L.env_policy_workspace_bytes.restype = C.c_int64
         _done = True
     return L
 
@@ -63,18 +66,30 @@ def forward(obs, mask, params, n_tok, n_agents, n_actions=5, seed=0, t=0, episod
 
 
 class PolicyRollout:
-    """Closed-loop rollouts of a fixed-count Env driven by the policy."""
+    """Closed-loop rollouts of a fixed-count Env driven by the policy; with
+    `mlp_params` the learned estimator (exact fallback at k_sigma * sigma_r)
+    supplies the trackers' estimates inside the loop."""
 
-    def __init__(self, env: Env, params: torch.Tensor):
+    def __init__(self, env: Env, params: torch.Tensor, mlp_params: torch.Tensor = None,
+                 k_sigma: float = 3.0):
         self.env, self.params = env, params
-        self._buf, self._w, self._n = _work(env.A, env.K, env.device)
+        self.mlp_params, self.k_sigma = mlp_params, float(k_sigma)
+        n = int(_l().env_policy_workspace_bytes(env._h, int(mlp_params is not None)))
+        assert n > 0, "the env must be bound"
+        self._buf = torch.empty(n + 256, dtype=torch.uint8, device=env.device)
+        off = (-self._buf.data_ptr()) % 256
+        self._w, self._n = C.c_void_p(self._buf.data_ptr() + off), n
+
+    def _call(self, T, episode, out, metrics, capture):
+        check(_l().env_policy_rollout(self.env._h, C.c_uint64(episode), int(T), ptr(self.params),
+                                      ptr(self.mlp_params), C.c_float(self.k_sigma),
+                                      C.byref(Env._struct(out)), ptr(metrics), int(capture),
+                                      self._w, self._n, _stream()))
 
     def run(self, T, episode=0, record=("reward", "done"), metrics=True):
         out = self.env._alloc(record, T)
         m = torch.zeros(8, dtype=torch.float64, device=self.env.device) if metrics else None
-        check(_l().env_policy_rollout(self.env._h, C.c_uint64(episode), int(T), ptr(self.params),
-                                      C.byref(Env._struct(out)), ptr(m), 0, self._w, self._n,
-                                      _stream()))
+        self._call(T, episode, out, m, 0)
         return out, m
 
     def capture(self, T, episode=0, record=("reward", "done")):
@@ -83,10 +98,7 @@ class PolicyRollout:
         torch.cuda.current_stream().synchronize()
         side = torch.cuda.Stream(device=self.env.device)
         with torch.cuda.stream(side):
-            check(_l().env_policy_rollout(self.env._h, C.c_uint64(episode), int(T),
-                                          ptr(self.params), C.byref(Env._struct(self.graph_out)),
-                                          ptr(self.graph_metrics), 1, self._w, self._n,
-                                          _stream()))
+            self._call(T, episode, self.graph_out, self.graph_metrics, 1)
         self._side = side
         return self.graph_out, self.graph_metrics
 

@@ -95,3 +95,64 @@ def test_policy_rejects_ragged():
     env = Env(env_config("ragged"), 100, seed=0)
     with pytest.raises(MilError):
         policy.PolicyRollout(env, policy.init_params(0)).run(5)
+
+
+def test_learned_estimator_in_loop_falls_back_to_exact():
+    """With a network whose every estimate fails the residual test (zero
+    weights, k_sigma = 0), the split step with the learned estimator in the
+    loop takes the exact fallback everywhere and reproduces the closed loop
+    with the in-step exact estimator (same actions and validity; estimates,
+    rewards and tokens to FP64-solver rounding, the two solves being written
+    differently)."""
+    from paper_2505_08222_amd import learned, policy
+    from paper_2505_08222_amd.env import Env
+    cfg = env_config("policy", episode_len=30)
+    E, T = 256, 30
+    params = policy.init_params(0)
+    rec = ("obs", "obs_mask", "reward", "done", "actions", "est", "est_valid")
+    a = Env(cfg, E, seed=4)
+    ra, ma = policy.PolicyRollout(a, params).run(T, record=rec)
+    b = Env(cfg, E, seed=4)
+    zero = torch.zeros(learned.num_params(), dtype=torch.float32, device="cuda")
+    rb, mb = policy.PolicyRollout(b, params, mlp_params=zero, k_sigma=0.0).run(T, record=rec)
+    ra = {k: v.cpu().numpy() for k, v in ra.items()}
+    rb = {k: v.cpu().numpy() for k, v in rb.items()}
+    for k in ("actions", "done", "est_valid", "obs_mask"):
+        np.testing.assert_array_equal(rb[k], ra[k], err_msg=k)
+    np.testing.assert_allclose(rb["est"], ra["est"], rtol=0, atol=2e-3)
+    np.testing.assert_allclose(rb["obs"], ra["obs"], rtol=0, atol=2e-3)
+    np.testing.assert_allclose(rb["reward"], ra["reward"], rtol=0, atol=1e-4)
+
+
+def test_learned_estimator_in_loop_uses_network_on_current_windows():
+    """With every network estimate accepted (k_sigma huge), the estimates the
+    closed loop records at its last step are exactly what mlp_infer gives on
+    the windows the environment holds after that step; graph replay equals the
+    eager loop."""
+    from paper_2505_08222_amd import learned, policy
+    from paper_2505_08222_amd.env import Env
+    cfg = env_config("policy", episode_len=24)
+    E, T = 128, 24
+    params = policy.init_params(1)
+    mlp = learned.init_params(5)
+    rec = ("obs", "obs_mask", "reward", "done", "actions", "est", "est_valid")
+    a = Env(cfg, E, seed=2)
+    pr = policy.PolicyRollout(a, params, mlp_params=mlp, k_sigma=1e9)
+    ra, ma = pr.run(T, record=rec)
+    win, sigma, _ = learned.env_windows(a)
+    out, flag = learned.infer(win, mlp, sigma, k_sigma=1e9)
+    assert (flag.cpu().numpy() == 1).all()
+    np.testing.assert_array_equal(ra["est"][-1].cpu().numpy(), out.cpu().numpy())
+    assert ra["est_valid"][-1].cpu().numpy().all()
+    # graph replay of the same loop
+    b = Env(cfg, E, seed=2)
+    pb = policy.PolicyRollout(b, params, mlp_params=mlp, k_sigma=1e9)
+    gout, gm = pb.capture(T, record=rec)
+    for _ in range(2):
+        for v in gout.values():
+            v.zero_()
+        pb.launch()
+        torch.cuda.synchronize()
+        for k in rec:
+            np.testing.assert_array_equal(gout[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
+        np.testing.assert_array_equal(gm.cpu().numpy(), ma.cpu().numpy())
