@@ -204,6 +204,57 @@ void orc_mlp_residual_rms(int64_t N, int W, const double *win, const double *p, 
   }
 }
 
+/* Distance along the network's bearing. The decoded point p fixes a
+ * direction e from the window centroid c; the estimate is moved along it to
+ * the distance d minimising J(d) = sum_k (|c + d e - a_k| - r_k)^2, by `iters`
+ * Gauss-Newton steps on d from d0 = |p - c| (a step is kept only if J falls).
+ * Missing ranges (NaN) are skipped. With p = c the point is returned as is. */
+void orc_range_refine(int64_t N, int W, const double *win, const double *centre,
+                      const double *p_in, int iters, double *p_out) {
+  for (int64_t n = 0; n < N; ++n) {
+    const double *w = win + n * W * 3;
+    const double cx = centre[2 * n], cy = centre[2 * n + 1];
+    double ex = p_in[2 * n] - cx, ey = p_in[2 * n + 1] - cy;
+    double d = hypot(ex, ey);
+    if (!(d > 0.0)) {
+      p_out[2 * n] = p_in[2 * n];
+      p_out[2 * n + 1] = p_in[2 * n + 1];
+      continue;
+    }
+    ex /= d;
+    ey /= d;
+    for (int it = 0; it < iters; ++it) {
+      double g = 0.0, h = 0.0, j0 = 0.0;
+      for (int k = 0; k < W; ++k) {
+        const double r = w[3 * k + 2];
+        if (r != r) continue;
+        const double dx = cx + d * ex - w[3 * k], dy = cy + d * ey - w[3 * k + 1];
+        const double dist = hypot(dx, dy);
+        const double rho = dist - r;
+        j0 += rho * rho;
+        if (dist > 0.0) {
+          const double jd = (dx * ex + dy * ey) / dist; /* d rho / d d */
+          g += jd * rho;
+          h += jd * jd;
+        }
+      }
+      if (!(h > 0.0)) break;
+      const double dn = d - g / h;
+      double j1 = 0.0;
+      for (int k = 0; k < W; ++k) {
+        const double r = w[3 * k + 2];
+        if (r != r) continue;
+        const double rho = hypot(cx + dn * ex - w[3 * k], cy + dn * ey - w[3 * k + 1]) - r;
+        j1 += rho * rho;
+      }
+      if (!(j1 < j0)) break;
+      d = dn;
+    }
+    p_out[2 * n] = cx + d * ex;
+    p_out[2 * n + 1] = cy + d * ey;
+  }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Attention policy (the TransfMAPPO actor of Sec. III-B, without its        */
 /* recurrent token; random initialisation, forward only). Tokens of one      */

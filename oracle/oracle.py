@@ -95,6 +95,7 @@ def _register_learned(L):
         L.orc_mlp_backward.restype = D
         L.orc_adam_step.argtypes = [I64, P(D), P(D), P(D), P(D), I64, D, D, D, D]
         L.orc_mlp_residual_rms.argtypes = [I64, C.c_int, P(D), P(D), P(D)]
+        L.orc_range_refine.argtypes = [I64, C.c_int, P(D), P(D), P(D), C.c_int, P(D)]
     if hasattr(L, "orc_policy_forward"):
         L.orc_policy_num_params.restype = I64
         L.orc_policy_forward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D)]
@@ -308,6 +309,18 @@ def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-
     """In place on float64 arrays."""
     lib().orc_adam_step(params.shape[0], _p(params, C.c_double), _p(grad, C.c_double),
                         _p(m, C.c_double), _p(v, C.c_double), step, lr, beta1, beta2, eps)
+
+
+def range_refine(win, centre, p, iters=3):
+    """The estimate moved along its bearing from `centre` to the distance that
+    best fits the window's ranges (learned estimator decode step)."""
+    win = np.ascontiguousarray(win, np.float64)
+    centre = np.ascontiguousarray(centre, np.float64)
+    p = np.ascontiguousarray(p, np.float64)
+    out = np.zeros_like(p)
+    lib().orc_range_refine(p.shape[0], win.shape[1], _p(win, C.c_double), _p(centre, C.c_double),
+                           _p(p, C.c_double), int(iters), _p(out, C.c_double))
+    return out
 
 
 def residual_rms(win, p):

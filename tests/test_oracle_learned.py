@@ -137,3 +137,55 @@ def test_residual_of_exact_point_is_zero(orc):
     d = p - a.mean(1)
     p2 = p + 5.0 * d / np.linalg.norm(d, axis=1, keepdims=True)
     assert (orc.residual_rms(win, p2) > 4.5).all()
+
+
+def _bearing_setup(N=200, W=16, seed=3, noise=0.0):
+    from paper_2505_08222_amd.synth import range_windows, window_targets
+    win = range_windows(N, W, seed=seed, far=800.0).astype(np.float64)
+    tgt = window_targets(N, W, seed=seed, far=800.0)
+    if noise == 0.0:  # exact ranges
+        win[..., 2] = np.hypot(win[..., 0] - tgt[:, None, 0], win[..., 1] - tgt[:, None, 1])
+    centre = win[..., :2].mean(1)
+    return win, tgt, centre
+
+
+def test_range_refine_recovers_truth_from_exact_ranges(orc):
+    """Noise-free ranges, the true bearing and a wrong start distance: the
+    refined point is the target."""
+    win, tgt, centre = _bearing_setup()
+    u = tgt - centre
+    start = centre + u * np.random.default_rng(0).uniform(0.7, 1.3, (len(u), 1))
+    out = orc.range_refine(win, centre, start, iters=8)
+    np.testing.assert_allclose(out, tgt, atol=1e-6)
+
+
+def test_range_refine_matches_brute_force_line_search(orc):
+    """Noisy ranges: the refined distance along the bearing is the minimiser of
+    the range residual on a fine grid around it (brute force, 1 mm cells)."""
+    win, tgt, centre = _bearing_setup(N=40, seed=5)
+    rng = np.random.default_rng(1)
+    start = tgt + rng.normal(0, 20.0, tgt.shape)
+    out = orc.range_refine(win, centre, start, iters=20)
+    for n in range(len(win)):
+        e = (start[n] - centre[n]) / np.linalg.norm(start[n] - centre[n])
+        d_ref = np.dot(out[n] - centre[n], e)
+        grid = d_ref + np.arange(-2.0, 2.0, 1e-3)
+        pts = centre[n] + grid[:, None] * e
+        J = ((np.hypot(pts[:, None, 0] - win[n, None, :, 0], pts[:, None, 1] - win[n, None, :, 1])
+              - win[n, None, :, 2]) ** 2).sum(1)
+        assert abs(grid[np.argmin(J)] - d_ref) <= 2e-3
+        # the refined point stays on the start's bearing
+        v = out[n] - centre[n]
+        assert abs(v[0] * e[1] - v[1] * e[0]) <= 1e-9 * max(1.0, np.linalg.norm(v))
+
+
+def test_range_refine_edge_cases(orc):
+    win, tgt, centre = _bearing_setup(N=10)
+    same = orc.range_refine(win, centre, centre.copy(), iters=3)
+    np.testing.assert_array_equal(same, centre)  # no bearing: returned as is
+    w2 = win.copy()
+    w2[:, 5:, 2] = np.nan  # missing entries are skipped
+    out = orc.range_refine(w2, centre, centre + 0.9 * (tgt - centre), iters=8)
+    np.testing.assert_allclose(out, tgt, atol=1e-6)
+    zero = orc.range_refine(win, centre, centre + 0.9 * (tgt - centre), iters=0)
+    np.testing.assert_allclose(zero, centre + 0.9 * (tgt - centre))
