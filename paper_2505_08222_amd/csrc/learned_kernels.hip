@@ -423,12 +423,14 @@ forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict
 // ---------------------------------------------------------------------------
 // Inference: persistent blocks (two per CU) loop over tiles of 64 windows.
 // The tile's windows (contiguous in memory) are staged in LDS with coalesced
-// loads; features, the two hidden layers (column-stationary MFMA, weight
-// fragments from L2 in registers), the output layer, the decode and the
-// residual test all read that copy. Windows failing the test (or with
+// loads; features, the two hidden layers (MFMA, weight fragments from L2 in
+// registers), the output layer, the decode (network bearing, distance fitted
+// to the ranges) and the residual test all read that copy. Windows failing the test (or with
 // missing entries) are appended, one atomic per wavefront, to a list that
 // the fallback kernel solves exactly.
 // ---------------------------------------------------------------------------
+constexpr int kRefineIters = 3;  // distance-fit steps of the decode
+
 struct InferLds {
   float win[64 * kMaxW * 3];
   float w3[2][kHidden];
@@ -544,29 +546,81 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       L.ypart[s][1][part] = acc[1];
     }
     __syncthreads();
-    if (tid < 64) {
-      const int64_t n = s0 + tid;
-      bool accept = false, fail = false;
-      if (tid < nw) {
-        const float y0 = L.b3[0] + ((L.ypart[tid][0][0] + L.ypart[tid][0][1]) +
-                                    (L.ypart[tid][0][2] + L.ypart[tid][0][3]));
-        const float y1 = L.b3[1] + ((L.ypart[tid][1][0] + L.ypart[tid][1][1]) +
-                                    (L.ypart[tid][1][2] + L.ypart[tid][1][3]));
-        const float *fr = L.frame[tid];
-        const float ux = fr[4] * y0, uy = fr[4] * y1;
-        const float px = fr[0] + fr[2] * ux - fr[3] * uy;
-        const float py = fr[1] + fr[3] * ux + fr[2] * uy;
-        if (L.ok[tid]) {
-          const float *w = L.win + tid * wlen;
-          float acc = 0.0f;
-          for (int k = 0; k < W; ++k) {
-            const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
-            const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
-            acc += res * res;
+    {  // decode, distance fit and residual test: four threads per window
+      const int sw = tid >> 2, part = tid & 3;
+      const bool live = sw < nw;
+      const int64_t n = s0 + sw;
+      const float *fr = L.frame[sw];
+      const float *w = L.win + (live ? sw : 0) * wlen;
+      auto sum4 = [](float v) {
+        v += __shfl_xor(v, 1);
+        return v + __shfl_xor(v, 2);
+      };
+      const float y0 = L.b3[0] + ((L.ypart[sw][0][0] + L.ypart[sw][0][1]) +
+                                  (L.ypart[sw][0][2] + L.ypart[sw][0][3]));
+      const float y1 = L.b3[1] + ((L.ypart[sw][1][0] + L.ypart[sw][1][1]) +
+                                  (L.ypart[sw][1][2] + L.ypart[sw][1][3]));
+      const float ux = fr[4] * y0, uy = fr[4] * y1;
+      float px = fr[0] + fr[2] * ux - fr[3] * uy;
+      float py = fr[1] + fr[3] * ux + fr[2] * uy;
+      const bool ok = live && L.ok[sw];
+      // the network fixes the bearing from the centroid; the distance along
+      // it is fitted to the window's ranges (Gauss-Newton on d, a step kept
+      // only if the squared residual falls)
+      float ex = px - fr[0], ey = py - fr[1];
+      float d = sqrtf(fmaf(ex, ex, ey * ey));
+      const bool fit = ok && d > 0.0f;  // the same for the window's four threads
+      if (fit) {
+        ex /= d;
+        ey /= d;
+      }
+      for (int it = 0; it < kRefineIters; ++it) {
+        float gs = 0.0f, hs = 0.0f, j0 = 0.0f;
+        if (fit) {
+          for (int k = part; k < W; k += 4) {
+            const float dx = fmaf(d, ex, fr[0]) - w[3 * k], dy = fmaf(d, ey, fr[1]) - w[3 * k + 1];
+            const float dist = sqrtf(fmaf(dx, dx, dy * dy));
+            const float rho = dist - w[3 * k + 2];
+            j0 = fmaf(rho, rho, j0);
+            if (dist > 0.0f) {
+              const float jd = fmaf(dx, ex, dy * ey) / dist;
+              gs = fmaf(jd, rho, gs);
+              hs = fmaf(jd, jd, hs);
+            }
           }
-          const float rms = sqrtf(acc / (float)W);
-          accept = rms <= k_sigma * sigma[n];
         }
+        gs = sum4(gs);
+        hs = sum4(hs);
+        j0 = sum4(j0);
+        const bool step_ok = fit && hs > 0.0f;
+        const float dn = step_ok ? d - gs / hs : d;
+        float j1 = 0.0f;
+        if (step_ok) {
+          for (int k = part; k < W; k += 4) {
+            const float dx = fmaf(dn, ex, fr[0]) - w[3 * k], dy = fmaf(dn, ey, fr[1]) - w[3 * k + 1];
+            const float rho = sqrtf(fmaf(dx, dx, dy * dy)) - w[3 * k + 2];
+            j1 = fmaf(rho, rho, j1);
+          }
+        }
+        j1 = sum4(j1);
+        if (step_ok && j1 < j0) d = dn;
+      }
+      if (fit) {
+        px = fmaf(d, ex, fr[0]);
+        py = fmaf(d, ey, fr[1]);
+      }
+      float acc = 0.0f;
+      if (ok) {
+        for (int k = part; k < W; k += 4) {
+          const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
+          const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
+          acc += res * res;
+        }
+      }
+      acc = sum4(acc);
+      bool accept = false, fail = false;
+      if (live && part == 0) {
+        accept = ok && sqrtf(acc / (float)W) <= k_sigma * sigma[n];
         if (accept) {
           out[2 * n] = px;
           out[2 * n + 1] = py;
@@ -576,11 +630,12 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       }
       // wavefront-aggregated append to the fallback list
       const uint64_t m = __ballot(fail);
+      const int lane = tid & 63;
       int base = 0;
-      if (tid == 0 && m) base = atomicAdd(fb_count, __popcll(m));
+      if (lane == 0 && m) base = atomicAdd(fb_count, __popcll(m));
       base = __shfl(base, 0);
       if (fail) {
-        const int rank = __popcll(m & ((1ull << tid) - 1ull));
+        const int rank = __popcll(m & ((1ull << lane) - 1ull));
         fb_list[base + rank] = (int32_t)n;
       }
     }

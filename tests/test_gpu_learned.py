@@ -122,3 +122,51 @@ def test_training_reduces_loss():
     pred = learned.forward(x, params, "bf16")
     mse = float((pred - y).pow(2).sum(1).mean())
     assert mse < 0.3 * base, (mse, base, hist[-3:])
+
+
+@pytest.fixture(scope="module")
+def trained_params():
+    from paper_2505_08222_amd import learned
+    from paper_2505_08222_amd.env import est_exact
+    win = torch.from_numpy(range_windows(60000, 16, seed=21, spread=1.0, far=800.0)).cuda()
+    ex, ev = est_exact(win)
+    x, frame = learned.features(win)
+    y = learned.targets(frame, ex)
+    keep = ev.bool() & (y.norm(dim=1) <= 2.0)
+    params, _ = learned.train(x[keep].contiguous(), y[keep].contiguous(), epochs=6, batch=1024,
+                              lr=3e-3, lr_final=3e-4, seed=0)
+    return params
+
+
+def test_infer_decode_fits_distance_along_bearing(orc, trained_params):
+    """Every network estimate (all accepted here) sits at the distance along
+    its bearing from the window centroid that best fits the ranges: the FP64
+    oracle's line fit, started from the GPU's estimate, leaves it in place
+    (to FP32 rounding of the residual sums)."""
+    from paper_2505_08222_amd import learned
+    win = range_windows(20000, 16, seed=13, far=800.0)
+    sigma = np.random.default_rng(2).uniform(0.5, 3.0, 20000).astype(np.float32)
+    out, flag = learned.infer(torch.from_numpy(win).cuda(), trained_params,
+                              torch.from_numpy(sigma).cuda(), k_sigma=1e9)
+    out = out.cpu().numpy().astype(np.float64)
+    assert (flag.cpu().numpy() == 1).all()
+    w64 = win.astype(np.float64)
+    centre = w64[..., :2].mean(1)
+    ref = orc.range_refine(w64, centre, out, iters=20)
+    rbar = w64[..., 2].mean(1)
+    moved = np.hypot(*(ref - out).T)
+    frac = (moved <= 0.05 + 1e-4 * rbar).mean()
+    assert frac >= 0.99, (frac, np.percentile(moved, [50, 99, 100]))
+
+
+def test_infer_acceptance_with_trained_network(trained_params):
+    """With the distance fitted to the ranges, most windows of the training
+    distribution pass the 3-sigma residual test."""
+    from paper_2505_08222_amd import learned
+    win = range_windows(20000, 16, seed=17, far=800.0)
+    sigma = np.random.default_rng(3).uniform(0.5, 3.0, 20000).astype(np.float32)
+    _, flag = learned.infer(torch.from_numpy(win).cuda(), trained_params,
+                            torch.from_numpy(sigma).cuda(), k_sigma=3.0)
+    acc = (flag.cpu().numpy() == 1).mean()
+    print("accepted fraction", acc)
+    assert acc >= 0.5, acc
