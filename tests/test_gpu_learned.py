@@ -170,3 +170,25 @@ def test_infer_acceptance_with_trained_network(trained_params):
     acc = (flag.cpu().numpy() == 1).mean()
     print("accepted fraction", acc)
     assert acc >= 0.5, acc
+
+
+def test_trained_network_gains_over_exact_estimator(trained_params):
+    """What the trained network gains over the estimator without it: on
+    windows of the training distribution, the guarded learned estimates are
+    closer to the true target positions (RMS) than the exact estimates."""
+    from paper_2505_08222_amd import learned
+    from paper_2505_08222_amd.env import est_exact
+    from paper_2505_08222_amd.synth import window_targets
+    N = 20000
+    win = range_windows(N, 16, seed=29, far=800.0)
+    truth = window_targets(N, 16, seed=29, far=800.0)
+    sigma = np.random.default_rng(4).uniform(0.5, 3.0, N).astype(np.float32)
+    w = torch.from_numpy(win).cuda()
+    out, flag = learned.infer(w, trained_params, torch.from_numpy(sigma).cuda(), k_sigma=3.0)
+    ex, ev = est_exact(w)
+    v = ev.cpu().numpy().astype(bool) & (flag.cpu().numpy() != 2)
+    err_l = np.hypot(*(out.cpu().numpy()[v] - truth[v]).T)
+    err_x = np.hypot(*(ex.cpu().numpy()[v] - truth[v]).T)
+    rms_l, rms_x = np.sqrt((err_l ** 2).mean()), np.sqrt((err_x ** 2).mean())
+    print("RMS vs truth: learned (guarded)", rms_l, "exact", rms_x)
+    assert rms_l < rms_x, (rms_l, rms_x)
