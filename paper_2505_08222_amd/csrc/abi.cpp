@@ -667,7 +667,8 @@ int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
 int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream) {
   if (!h || !d_win) return fail(MIL_EINVAL, "null argument");
   if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
-  if (mil::launch_env_windows(h->ds, h->W, d_win, d_sigma, d_truth, stream))
+  if (mil::launch_env_windows(h->ds, h->W, h->P.n_agents * h->P.n_targets, d_win, d_sigma, d_truth,
+                              stream))
     return fail(MIL_EHIP, "window copy launch failed");
   return MIL_OK;
 }
@@ -905,7 +906,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
       lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
                                 dstate, t, 1, (uint32_t)episode, wact, o, st,
                                 mil::DevExt{1, nullptr, nullptr});
-      if (!lrc) lrc = mil::launch_env_windows(h->ds, h->P.window, win, sig, nullptr, st);
+      if (!lrc)
+        lrc = mil::launch_env_windows(h->ds, h->P.window, h->P.n_agents * h->P.n_targets, win, sig,
+                                      nullptr, st);
       if (!lrc)
         lrc = mlp_infer(win, Pn, h->P.window, d_mlp_params, sig, k_sigma, 0, h->P.guard_tau, est,
                         flag, ws + ew.mlp, ew.mlp_bytes, st) == MIL_OK

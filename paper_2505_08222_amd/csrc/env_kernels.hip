@@ -862,35 +862,41 @@ __global__ void get_state_kernel(DevState s, float *agent, float *target) {
 }
 
 // Every tracker's window (entry 0 = newest) with its env's range-noise std
-// and the true target position: one thread per env.
-__global__ void env_windows_kernel(DevState s, int32_t W, float *win, float *sigma, float *truth) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// and the true target position: one thread per (env, pair slot, window
+// entry), the entry index fastest, so consecutive threads write consecutive
+// 12-byte entries of the output.
+__global__ void env_windows_kernel(DevState s, int32_t W, int32_t slots, float *win, float *sigma,
+                                   float *truth) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t q = tid / W;
+  const int k = (int)(tid - q * W);
+  const int64_t e = q / slots;
+  const int slot = (int)(q - e * slots);
   if (e >= s.E) return;
   const int na = s.cnt_a[e], nt = s.cnt_t[e];
-  const int64_t ab = s.aoff[e], tb = s.toff[e], pb = s.poff[e];
-  for (int i = 0; i < na; ++i) {
-    for (int j = 0; j < nt; ++j) {
-      const int64_t p = pb + (int64_t)i * nt + j;
-      float *w = win + p * W * 3;
-      for (int k = 0; k < W; ++k) {
-        w[3 * k] = s.hx[(int64_t)k * s.A + ab + i];
-        w[3 * k + 1] = s.hy[(int64_t)k * s.A + ab + i];
-        w[3 * k + 2] = s.hr[(int64_t)k * s.P + p];
-      }
-      if (sigma) sigma[p] = s.sigma[e];
-      if (truth) {
-        truth[2 * p] = s.tx[tb + j];
-        truth[2 * p + 1] = s.ty[tb + j];
-      }
+  if (slot >= na * nt) return;
+  const int i = slot / nt, j = slot - i * nt;
+  const int64_t a = s.aoff[e] + i;
+  const int64_t p = s.poff[e] + slot;
+  float *w = win + (p * W + k) * 3;
+  w[0] = s.hx[(int64_t)k * s.A + a];
+  w[1] = s.hy[(int64_t)k * s.A + a];
+  w[2] = s.hr[(int64_t)k * s.P + p];
+  if (k == 0) {
+    if (sigma) sigma[p] = s.sigma[e];
+    if (truth) {
+      truth[2 * p] = s.tx[s.toff[e] + j];
+      truth[2 * p + 1] = s.ty[s.toff[e] + j];
     }
   }
 }
 
-int launch_env_windows(const DevState &s, int32_t W, float *win, float *sigma, float *truth,
-                       void *stream) {
-  const int bs = 128;
-  hipLaunchKernelGGL(env_windows_kernel, dim3((unsigned)((s.E + bs - 1) / bs)), dim3(bs), 0,
-                     (hipStream_t)stream, s, W, win, sigma, truth);
+int launch_env_windows(const DevState &s, int32_t W, int32_t slots, float *win, float *sigma,
+                       float *truth, void *stream) {
+  const int bs = 256;
+  const int64_t n = s.E * (int64_t)slots * W;
+  hipLaunchKernelGGL(env_windows_kernel, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0,
+                     (hipStream_t)stream, s, W, slots, win, sigma, truth);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -44,7 +44,8 @@ int launch_infer(const float *win, int64_t N, int32_t W, const float *th, const 
 
 // env_kernels.hip: tracker windows of a bound environment
 struct DevState;
-int launch_env_windows(const DevState &s, int32_t W, float *win, float *sigma, float *truth,
-                       void *stream);
+// slots = the largest pair count of an env (max agents x max targets)
+int launch_env_windows(const DevState &s, int32_t W, int32_t slots, float *win, float *sigma,
+                       float *truth, void *stream);
 
 }  // namespace mil

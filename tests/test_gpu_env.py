@@ -340,3 +340,35 @@ def test_errors_are_reported():
         env.step()  # past the episode
     with pytest.raises(MilError):
         env.set_mapping(3, 1)
+
+
+def test_env_windows_match_oracle(orc):
+    """The exported tracker windows (entry k = the state k steps back: agent
+    position and range) with each env's range sigma and the true target
+    position, against the oracle's records of the same rollout."""
+    from paper_2505_08222_amd import learned
+    cfg = env_config("ragged", window=16, episode_len=40)
+    E, T, W = 300, 40, 16
+    env = _env(cfg, E, seed=6)
+    env.reset(0)
+    env.rollout(T, record=())
+    win, sigma, truth = (x.cpu().numpy() for x in learned.env_windows(env))
+    sel = np.arange(E)
+    ref = _oracle(orc, cfg, env, sel, 6, T)
+    o = env.order
+    s = cfg["area"] / 2
+    cp = np.concatenate([[0], np.cumsum(env.n_agents * env.n_targets)])
+    for k in range(E):
+        na, nt = env.n_agents[k], env.n_targets[k]
+        for i in range(na):
+            a = ref["csr"]["agent"][k] + i
+            for j in range(nt):
+                p = cp[k] + i * nt + j
+                g = o["pair"][k] + i * nt + j
+                for q in range(W):
+                    t = T - 1 - q
+                    assert np.abs(win[g, q, :2] - ref["agent"][t, a, :2]).max() <= 1e-5 * s
+                    assert abs(win[g, q, 2] - ref["ranges"][t, p]) <= 1e-5 * s
+                assert abs(sigma[g] - ref["sigma_r"][k]) <= 1e-6 * ref["sigma_r"][k]
+                tg = ref["csr"]["target"][k] + j
+                assert np.abs(truth[g] - ref["target"][T - 1, tg, :2]).max() <= 1e-5 * s
