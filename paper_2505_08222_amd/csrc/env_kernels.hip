@@ -474,7 +474,9 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 #pragma unroll
           for (int sl = 0; sl < NPL; ++sl) {
             const float rk = hr[sl][k];
-            full[sl] = full[sl] && (rk == rk);
+            // lean form: every range is finite while the state is (checked
+            // on the estimate below instead of on each entry)
+            if constexpr (FULL) full[sl] = full[sl] && (rk == rk);
             const double rr = (double)rk;
             const double c = fma(-rr, rr, nu);
             gx[sl] = fma(ux, c, gx[sl]);
@@ -491,9 +493,15 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         if (j < nt) {
           if (full[sl] && (!FULL || p.gn_iters == 0)) {
             if (agent_ok) {
-              ex[sl] = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
-              ey[sl] = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
-              evb |= 1u << sl;
+              const float nx = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
+              const float ny = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
+              if (FULL || (nx == nx && ny == ny)) {
+                ex[sl] = nx;
+                ey[sl] = ny;
+                evb |= 1u << sl;
+              } else if (active) {
+                status |= kStatusNonFinite;  // lean form: hold, flag the broken state
+              }
             }
           } else if (FULL) {
             pending |= 1u << sl;
