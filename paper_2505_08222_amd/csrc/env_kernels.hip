@@ -57,6 +57,8 @@ __device__ __forceinline__ float wrap_angle(float a) {
 }
 
 __device__ __forceinline__ float norm2(float dx, float dy) { return fast_sqrt(fmaf(dx, dx, dy * dy)); }
+// |(dx, dy)|^2, for comparisons against a squared radius (no square root)
+__device__ __forceinline__ float sqnorm(float dx, float dy) { return fmaf(dx, dx, dy * dy); }
 
 // 1/d for finite d > 0: the hardware estimate refined by two Newton steps
 // (each doubles the number of correct bits), instead of the long IEEE divide
@@ -181,7 +183,7 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
     for (int k = 0; k < na; ++k) {
       if (k == i) continue;
       const float dx = s.ax[ab + k] - ax, dy = s.ay[ab + k] - ay;
-      const bool ok = norm2(dx, dy) <= p.comm_range;
+      const bool ok = sqnorm(dx, dy) <= p.comm_range * p.comm_range;
       if (o.obs) store_token(o.obs + (kb + m) * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
       if (o.obs_mask) o.obs_mask[kb + m] = ok;
       ++m;
@@ -258,6 +260,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   const double tau = (double)p.tau;
   const double invW = 1.0 / (double)W;
   const float inv_span = 1.0f / (p.eps_max - p.eps_min);
+  const float comm2 = p.comm_range * p.comm_range, dsafe2 = p.d_safe * p.d_safe;
   const float inv_nt = 1.0f / (float)nt;
   const float kInf = __int_as_float(0x7f800000);
   const float kNaN = __int_as_float(0x7fc00000);
@@ -583,7 +586,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 #pragma unroll
       for (int k2 = k + 1; k2 < MA; ++k2)
         if (k2 < na) {
-          crash = crash || (norm2(agx[k] - agx[k2], agy[k] - agy[k2]) < p.d_safe);
+          crash = crash || (sqnorm(agx[k] - agx[k2], agy[k] - agy[k2]) < dsafe2);
         }
     if (crash) rew = -1.0f;
     const bool done = (t + 1u == (uint32_t)p.episode_len);
@@ -628,7 +631,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             const float ox = before ? agx[m - 1] : agx[m];
             const float oy = before ? agy[m - 1] : agy[m];
             const float dx = ox - ax, dy = oy - ay;
-            const bool ok = norm2(dx, dy) <= p.comm_range;
+            const bool ok = sqnorm(dx, dy) <= comm2;
             emit(m, ok ? dx : 0.0f, ok ? dy : 0.0f, ok, 0.0f, 1.0f, 0.0f);
           }
         }
@@ -694,7 +697,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             const float oy = before ? agy[m - 1] : agy[m];
             const int oc = before ? agc[m - 1] : agc[m];
             const float dx = ox - ax, dy = oy - ay;
-            const bool ok = oc && (norm2(dx, dy) <= p.comm_range);
+            const bool ok = oc && (sqnorm(dx, dy) <= comm2);
             store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
             if (o.obs_mask) o.obs_mask[kb + m] = ok ? 1 : 0;
           }
@@ -719,7 +722,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             const float ox = before ? agx[m - 1] : agx[m];
             const float oy = before ? agy[m - 1] : agy[m];
             const int oc = before ? agc[m - 1] : agc[m];
-            o.obs_mask[kb + m] = (oc && (norm2(ox - ax, oy - ay) <= p.comm_range)) ? 1 : 0;
+            o.obs_mask[kb + m] = (oc && (sqnorm(ox - ax, oy - ay) <= comm2)) ? 1 : 0;
           }
         }
 #pragma unroll
