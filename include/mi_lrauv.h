@@ -272,7 +272,10 @@ int mlp_backward(int64_t N, const float *d_x, const int64_t *d_index, const floa
 /* Adam (Kingma and Ba) with bias correction on P parameters; step >= 1. */
 int mlp_adam_step(int64_t P, float *d_params, const float *d_grad, float *d_m, float *d_v,
                   float lr, float beta1, float beta2, float eps, int32_t step, void *stream);
-/* Estimates of N windows: the BF16 network, accepted when the RMS over the
+/* Estimates of N windows: the BF16 network gives the bearing p - c from the
+ * window's centroid c; the distance along that bearing is fitted to the
+ * window's ranges (three Gauss-Newton steps on the distance, each kept only if
+ * the squared residual falls). The estimate is accepted when the RMS over the
  * window of (|p - a_k| - r_k) is <= k_sigma * d_sigma[n]; otherwise (or with a
  * missing entry) the exact solve of est_exact (gn_iters, tau). d_flag [N]:
  * 1 network, 0 exact fallback, 2 neither (exact solve refused). */
