@@ -192,3 +192,33 @@ def test_trained_network_gains_over_exact_estimator(trained_params):
     rms_l, rms_x = np.sqrt((err_l ** 2).mean()), np.sqrt((err_x ** 2).mean())
     print("RMS vs truth: learned (guarded)", rms_l, "exact", rms_x)
     assert rms_l < rms_x, (rms_l, rms_x)
+
+
+def test_infer_full_size_sampled(orc, trained_params):
+    """The learned configuration's inference size (1e6 windows of 16): on a
+    sample of 20000 windows, accepted estimates pass the residual test and
+    every other window carries exactly the exact estimator's output."""
+    from paper_2505_08222_amd import learned
+    from paper_2505_08222_amd.env import est_exact
+    N = 1_000_000
+    win = range_windows(N, 16, seed=31, far=3000.0)
+    sigma = np.random.default_rng(5).uniform(0.5, 3.0, N).astype(np.float32)
+    w = torch.from_numpy(win).cuda()
+    out, flag = learned.infer(w, trained_params, torch.from_numpy(sigma).cuda(), k_sigma=3.0)
+    ex, ev = est_exact(w)
+    sel = np.sort(np.random.default_rng(6).choice(N, 20000, replace=False))
+    out, flag = out.cpu().numpy()[sel], flag.cpu().numpy()[sel]
+    ex, ev = ex.cpu().numpy()[sel], ev.cpu().numpy()[sel]
+    acc = flag == 1
+    rms = orc.residual_rms(win[sel].astype(np.float64), out.astype(np.float64))
+    assert (rms[acc] <= 3.0 * sigma[sel][acc] * (1 + 1e-4) + 1e-3).all()
+    fb = flag == 0
+    np.testing.assert_array_equal(out[fb], ex[fb])
+    np.testing.assert_array_equal(flag[~acc] == 0, ev[~acc].astype(bool))
+
+
+def test_infer_empty():
+    from paper_2505_08222_amd import learned
+    out, flag = learned.infer(torch.zeros((0, 16, 3), device="cuda"), learned.init_params(0),
+                              torch.zeros((0,), device="cuda"))
+    assert out.shape == (0, 2) and flag.shape == (0,)

@@ -156,3 +156,48 @@ def test_learned_estimator_in_loop_uses_network_on_current_windows():
         for k in rec:
             np.testing.assert_array_equal(gout[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
         np.testing.assert_array_equal(gm.cpu().numpy(), ma.cpu().numpy())
+
+
+def test_full_size_policy_loop_sampled(orc):
+    """The full-rollout workload's launch configuration (16384 envs, 5 x 5,
+    W 16, learned estimator in the loop, one captured graph), 16 steps: graph
+    replay equals the eager loop bit for bit, the policy's logits on the
+    recorded observations of sampled agents match the FP64 oracle to BF16
+    tolerance, and the environment driven by the recorded actions with the
+    exact estimator agrees with the loop until the first full window (where
+    the learned estimates take over)."""
+    from paper_2505_08222_amd import learned, policy
+    from paper_2505_08222_amd.env import Env
+    cfg = env_config("policy", episode_len=16)
+    E, T = 16384, 16
+    params = policy.init_params(0)
+    mlp = learned.init_params(2)
+    rec = ("obs", "obs_mask", "reward", "done", "actions")
+    a = Env(cfg, E, seed=0)
+    ra, ma = policy.PolicyRollout(a, params, mlp_params=mlp, k_sigma=3.0).run(T, record=rec)
+    b = Env(cfg, E, seed=0)
+    pb = policy.PolicyRollout(b, params, mlp_params=mlp, k_sigma=3.0)
+    gout, gm = pb.capture(T, record=rec)
+    pb.launch()
+    torch.cuda.synchronize()
+    for k in rec:
+        np.testing.assert_array_equal(gout[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
+    np.testing.assert_array_equal(gm.cpu().numpy(), ma.cpu().numpy())
+    # logits of sampled agents on the observation of step 9
+    n_tok = 10
+    obs = ra["obs"][9].reshape(-1, n_tok, 6)
+    mask = ra["obs_mask"][9].reshape(-1, n_tok)
+    sel = np.random.default_rng(0).choice(E * 5, 256, replace=False)
+    sel_t = torch.from_numpy(sel).cuda()
+    logits, _ = policy.forward(obs[sel_t].reshape(-1, 6).contiguous(),
+                               mask[sel_t].reshape(-1).contiguous(), params, n_tok, 1, 5)
+    ref = orc.policy_forward(obs[sel_t].cpu().numpy().astype(np.float64), mask[sel_t].cpu().numpy(),
+                             params.cpu().numpy().astype(np.float64))
+    err = np.abs(logits.cpu().numpy() - ref).max() / max(1.0, np.abs(ref).max())
+    assert err < 3e-2, err
+    # before the first full window (t < W - 1) the loop is the plain env step
+    c = Env(cfg, E, seed=0)
+    c.reset(0)
+    rc = c.rollout(T, actions=ra["actions"], record=rec)
+    for k in rec:
+        np.testing.assert_array_equal(rc[k][:15].cpu().numpy(), ra[k][:15].cpu().numpy(), err_msg=k)
