@@ -61,6 +61,8 @@ typedef enum mil_status {
 #define MIL_STATUS_BAD_ACTION 0x1u /* an action index was outside 0..n_actions-1;
                                       that agent kept its heading */
 #define MIL_STATUS_NONFINITE 0x2u  /* a position or heading became non-finite */
+#define MIL_STATUS_SCHEDULE 0x4u   /* a dynamic-schedule chunk wait gave up (the rollout's
+                                      results are then not to be trusted) */
 
 /* Environment parameters (SI units). Meaning of each field, with the passage
  * of the paper it comes from:
@@ -205,6 +207,18 @@ int env_get_state(mil_env *h, float *d_agent, float *d_target, void *stream);
  * Every mapping gives bit-identical results. */
 int env_set_mapping(mil_env *h, int32_t lanes_per_agent, int32_t waves_per_block);
 int env_get_mapping(const mil_env *h, int32_t *lanes_per_agent, int32_t *waves_per_block);
+/* Rollout schedule. chunk_steps = -1: static, one wavefront per group of
+ * environments for all T steps. 0 (default): automatic, dynamic when there
+ * are more groups than wavefronts the GPU holds at once and T >= 32, with
+ * chunks of about 128 steps. > 0: dynamic with chunks of that many steps.
+ * Dynamic: the rollout launch is preceded by a small kernel that clears the
+ * queue in the workspace; the persistent wavefronts take (chunk, group) units
+ * from an atomic counter, chunk-major, save the group's state after each
+ * chunk and wait, before a group's next chunk, until the previous one has
+ * published its state. Every schedule gives bit-identical results. Setting it
+ * drops a captured graph. */
+int env_set_schedule(mil_env *h, int32_t chunk_steps);
+int env_get_schedule(const mil_env *h, int32_t *chunk_steps);
 /* Time every mapping on probe_steps steps writing `outs` (buffers sized for
  * probe_steps steps; NULL = no outputs), with the state saved before and
  * restored after each probe, and keep the fastest. If cache_path is not NULL

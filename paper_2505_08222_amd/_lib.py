@@ -14,6 +14,7 @@ _lib = None
 MIL_OK = 0
 STATUS_BAD_ACTION = 0x1
 STATUS_NONFINITE = 0x2
+STATUS_SCHEDULE = 0x4
 
 
 class MilError(RuntimeError):
@@ -95,6 +96,8 @@ def lib():
         "env_get_state": [V, V, V, V],
         "env_set_mapping": [V, I32, I32],
         "env_get_mapping": [V, P(I32), P(I32)],
+        "env_set_schedule": [V, I32],
+        "env_get_schedule": [V, P(I32)],
         "env_autotune": [V, I32, P(EnvOutputs), C.c_char_p, V],
         "env_destroy": [V],
         "est_exact": [V, I64, I32, I32, C.c_float, I32, V, V, V],

@@ -82,6 +82,7 @@ struct mil_env {
   };
   std::vector<Cls> cls;
   int G = 1, wpb = 1;
+  int32_t sched = 0;  // rollout schedule: -1 static, 0 automatic, > 0 chunk steps
   std::vector<mil::ClassInfo> cinfo;
   std::vector<uint8_t> wave_class;
   int num_waves = 0, max_waves = 0;
@@ -89,7 +90,7 @@ struct mil_env {
   char *ws = nullptr;
   int64_t ws_bytes = 0;
   struct {
-    int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class;
+    int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue;
     int64_t ax, ay, apsi, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
     int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
@@ -222,7 +223,8 @@ int run_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_o
                 hipStream_t st) {
   const int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
                                      h->ds, (const mil::DevState *)(h->ws + h->off.devstate),
-                                     (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st);
+                                     (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st,
+                                     mil::DevExt{0, nullptr, nullptr}, h->sched);
   if (rc == -2) return fail(MIL_EINVAL, "no kernel for size class %d / window %d", h->size_class,
                             h->wcap);
   if (rc != 0) return fail(MIL_EHIP, "rollout launch failed: %s",
@@ -349,6 +351,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.koff = take((E + 1) * 8);
   f.classes = take((int64_t)h->cls.size() * sizeof(mil::ClassInfo));
   f.wave_class = take(h->max_waves);
+  f.queue = take(((int64_t)h->max_waves + 1) * 4);
   f.status = take(256);
   f.devstate = take(sizeof(mil::DevState));
   f.state_begin = o;
@@ -450,6 +453,7 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.macc = (double *)(h->ws + h->off.macc);
   d.miacc = (int32_t *)(h->ws + h->off.miacc);
   d.status = (uint32_t *)(h->ws + h->off.status);
+  d.queue = (int32_t *)(h->ws + h->off.queue);
   d.E = E;
   d.A = h->aoff[E];
   d.Tt = h->toff[E];
@@ -527,7 +531,8 @@ int env_graph_capture(mil_env *h, uint64_t episode, int32_t T, const mil_env_out
   if (!lrc)
     lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
                               (const mil::DevState *)(h->ws + h->off.devstate), 0, T,
-                              (uint32_t)episode, nullptr, dev_out(outs), st);
+                              (uint32_t)episode, nullptr, dev_out(outs), st,
+                              mil::DevExt{0, nullptr, nullptr}, h->sched);
   if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
   hipGraph_t g = nullptr;
   hipError_t ec = hipStreamEndCapture(st, &g);
@@ -591,6 +596,25 @@ int env_get_mapping(const mil_env *h, int32_t *lanes_per_agent, int32_t *waves_p
   if (!h) return fail(MIL_EINVAL, "null handle");
   if (lanes_per_agent) *lanes_per_agent = h->G;
   if (waves_per_block) *waves_per_block = h->wpb;
+  return MIL_OK;
+}
+
+int env_set_schedule(mil_env *h, int32_t chunk_steps) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (chunk_steps < -1) return fail(MIL_EINVAL, "chunk_steps must be -1, 0 or positive");
+  h->sched = chunk_steps;
+  if (h->gexec) {  // a captured graph holds the old launch shape
+    hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+    hipGraphDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  return MIL_OK;
+}
+
+int env_get_schedule(const mil_env *h, int32_t *chunk_steps) {
+  if (!h || !chunk_steps) return fail(MIL_EINVAL, "null argument");
+  *chunk_steps = h->sched;
   return MIL_OK;
 }
 
@@ -897,7 +921,8 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
     const mil::DevState *dstate = (const mil::DevState *)(h->ws + h->off.devstate);
     if (!learned) {
       lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                                dstate, t, 1, (uint32_t)episode, wact, o, st);
+                                dstate, t, 1, (uint32_t)episode, wact, o, st,
+                                mil::DevExt{0, nullptr, nullptr}, h->sched);
     } else {
       // move, estimate every tracker from its window, then observe
       float *win = (float *)(ws + ew.win), *sig = (float *)(ws + ew.sig);
@@ -905,7 +930,7 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
       uint8_t *flag = (uint8_t *)(ws + ew.flag);
       lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
                                 dstate, t, 1, (uint32_t)episode, wact, o, st,
-                                mil::DevExt{1, nullptr, nullptr});
+                                mil::DevExt{1, nullptr, nullptr}, h->sched);
       if (!lrc)
         lrc = mil::launch_env_windows(h->ds, h->P.window, h->P.n_agents * h->P.n_targets, win, sig,
                                       nullptr, st);
@@ -917,7 +942,7 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
       if (!lrc)
         lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
                                   h->ds, dstate, t, 1, (uint32_t)episode, wact, o, st,
-                                  mil::DevExt{2, est, flag});
+                                  mil::DevExt{2, est, flag}, h->sched);
     }
   }
   if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);

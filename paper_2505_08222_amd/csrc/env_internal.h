@@ -44,6 +44,7 @@ struct DevState {
   double *macc;                              // [E][3] reward, err, err^2 sums
   int32_t *miacc;                            // [E][2] err count, crash steps
   uint32_t *status;                          // [1]
+  int32_t *queue;                            // [1 + groups] dynamic-schedule counter, chunk flags
   int64_t E, A, Tt, P, K;
 };
 
@@ -79,10 +80,14 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
                  void *stream);
 // d_state: a device copy of `s` (the rollout reads it through this pointer so
 // that the state pointers need not stay in scalar registers across steps).
+// sched: -1 static (one wavefront per group for all T steps), 0 automatic
+// (dynamic when the groups outnumber the wavefronts the GPU holds at once),
+// > 0 dynamic with chunks of that many steps.
 int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_block,
                    int num_waves, const DevParams &p, const DevState &s, const DevState *d_state,
                    int32_t t0, int32_t T, uint32_t episode, const int32_t *actions,
-                   const DevOut &o, void *stream, const DevExt &ext = DevExt{0, nullptr, nullptr});
+                   const DevOut &o, void *stream, const DevExt &ext = DevExt{0, nullptr, nullptr},
+                   int32_t sched = 0);
 int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
                    void *stream);
 int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream);

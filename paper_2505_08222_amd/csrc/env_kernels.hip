@@ -97,6 +97,76 @@ __device__ __forceinline__ u32x4 draw(uint32_t c0, uint32_t c1, uint32_t c2, uin
 template <int S>
 constexpr int kStageTok = 64 * 2 * S;
 
+// Dynamic schedule of the rollout. A unit is (chunk c, wave group w): the
+// steps [c*span, (c+1)*span) of the environments that the static mapping
+// gives to wavefront w. Units are numbered chunk-major, u = c*groups + w, and
+// handed out by an atomic counter in queue[0]; queue[1 + w] counts the chunks
+// of group w that are complete (their state is back in memory). Unit (c, w)
+// waits for queue[1 + w] >= c; unit (c-1, w) has a smaller number, so it was
+// taken earlier by a wavefront that is running, and the wait ends.
+//
+// Hand-over. The state a group carries from one chunk to the next is written
+// and read with device-coherent accesses (relaxed atomics at agent scope: the
+// stores write through and the loads miss in the per-XCD L2 caches, so a
+// wavefront on another XCD sees the memory copy). Publishing therefore needs
+// only the completion of those stores before the flag store, and taking over
+// only the flag load before the state loads; no cache-wide write-back or
+// invalidation is involved.
+constexpr uint32_t kStatusSchedule = 0x4u;  // a chunk wait gave up (never expected)
+constexpr int kMaxPolls = 1 << 22;
+
+// (global address space spelled out: a generic pointer would become a flat
+// access, which also counts against the LDS wait counter)
+template <typename T>
+__device__ __forceinline__ T ld_dc(const T *p) {
+  using GT = __attribute__((address_space(1))) T;
+  return __hip_atomic_load((GT *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dc(T *p, T v) {
+  using GT = __attribute__((address_space(1))) T;
+  __hip_atomic_store((GT *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int take_unit(int32_t *queue, int lane) {
+  int u = 0;
+  if (lane == 0)
+    u = __hip_atomic_fetch_add((__attribute__((address_space(1))) int32_t *)queue, 1,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __builtin_amdgcn_readlane(u, 0);
+}
+
+// Wait (lane 0 polls) until the group has `need` chunks complete. False if
+// the poll limit ran out.
+__device__ __forceinline__ bool wait_chunks(int32_t *flag, int need, int lane) {
+  int ok = 1;
+  if (lane == 0) {
+    for (int polls = 0; ld_dc(flag) < need; ++polls) {
+      if (polls >= kMaxPolls) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  ok = __builtin_amdgcn_readlane(ok, 0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");  // state loads stay after the poll
+  return ok != 0;
+}
+
+// Publish that the group's state for `done` chunks is in memory: every store
+// of this wavefront has completed before the flag is written.
+__device__ __forceinline__ void publish_chunks(int32_t *flag, int done, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  if (lane == 0) st_dc(flag, done);
+}
+
+__global__ void queue_init_kernel(int32_t *queue, int32_t n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) queue[i] = 0;
+}
+
 // Element (g + G*sl) of a per-env array held with compile-time indices.
 template <int G, int N>
 __device__ __forceinline__ float pick(const float (&arr)[N], int g, int sl) {
@@ -214,7 +284,8 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 template <int S, int WC, int G, bool FULL, bool STAGE>
 __global__ void __launch_bounds__(256, (!FULL && WC == 10 && S <= 5) ? 2 : 1)
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
-               uint32_t episode, const int32_t *__restrict__ actions, DevOut o, DevExt ext) {
+               uint32_t episode, const int32_t *__restrict__ actions, DevOut o, DevExt ext,
+               int32_t chunk) {
   constexpr bool stage = STAGE && !FULL;
   // split step (full form only): phase 1 moves, phase 2 observes
   const bool move = !FULL || ext.phase != 2;
@@ -229,9 +300,27 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 
   const int lane = threadIdx.x & 63;
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
-  if (wave >= num_waves) return;
-  const DevState &s = *sp;  // prologue and epilogue only (reloaded after the loop)
+  if (lane < 8) lds_dpsi[wib][lane] = p.dpsi[lane];
+  wave_lds_fence();
+
+  // static schedule (chunk 0): wavefront = group, all T steps; dynamic: units
+  // from the queue (see take_unit)
+  const bool dyn = chunk > 0;
+  const int span = dyn ? chunk : T;
+  const int units = dyn ? num_waves * ((T + span - 1) / span) : num_waves;
+  int unit = dyn ? take_unit(sp->queue, lane)
+                 : __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
+  while (unit < units) {
+  const int cix = unit / num_waves;
+  const int wave = unit - cix * num_waves;
+  uint32_t status = 0;
+  if (cix > 0 && !wait_chunks(sp->queue + 1 + wave, cix, lane) && lane == 0)
+    status |= kStatusSchedule;
+  const int s_begin = cix * span;
+  const int s_end = min(T, s_begin + span);
+  // prologue and epilogue only (reloaded after the loop); a copy, so that the
+  // device-coherent accesses below do not make the compiler re-read each field
+  const DevState s = *sp;
   const ClassInfo C = s.classes[s.wave_class[wave]];
   const int na = C.na, nt = C.nt;
   const int lpe = na * G;
@@ -287,42 +376,40 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       const int j = 2 * q + m;
       if (j < nt) {
         const int64_t idx = tbase + j;
-        tl[j] = make_float4(s.tx[idx], s.ty[idx], s.tpsi[idx], s.tv[idx]);
+        tl[j] = make_float4(ld_dc(&s.tx[idx]), ld_dc(&s.ty[idx]), ld_dc(&s.tpsi[idx]), s.tv[idx]);
       }
     }
   }
-  float ax = s.ax[aidx], ay = s.ay[aidx], apsi = s.apsi[aidx];
+  float ax = ld_dc(&s.ax[aidx]), ay = ld_dc(&s.ay[aidx]), apsi = ld_dc(&s.apsi[aidx]);
   float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
   uint32_t evb = 0;
 #pragma unroll
   for (int k = 0; k < WC; ++k) {
-    hx[k] = (k < W) ? s.hx[(int64_t)k * s.A + aidx] : 0.0f;
-    hy[k] = (k < W) ? s.hy[(int64_t)k * s.A + aidx] : 0.0f;
+    hx[k] = (k < W) ? ld_dc(&s.hx[(int64_t)k * s.A + aidx]) : 0.0f;
+    hy[k] = (k < W) ? ld_dc(&s.hy[(int64_t)k * s.A + aidx]) : 0.0f;
   }
 #pragma unroll
   for (int sl = 0; sl < NPL; ++sl) {
     const int j = g + G * sl;
     const int64_t pidx = pbase + (j < nt ? j : 0);
 #pragma unroll
-    for (int k = 0; k < WC; ++k) hr[sl][k] = (k < W) ? s.hr[(int64_t)k * s.P + pidx] : 0.0f;
-    ex[sl] = s.ex[pidx];
-    ey[sl] = s.ey[pidx];
-    if (j < nt && s.ev[pidx]) evb |= 1u << sl;
+    for (int k = 0; k < WC; ++k) hr[sl][k] = (k < W) ? ld_dc(&s.hr[(int64_t)k * s.P + pidx]) : 0.0f;
+    ex[sl] = ld_dc(&s.ex[pidx]);
+    ey[sl] = ld_dc(&s.ey[pidx]);
+    if (j < nt && ld_dc(&s.ev[pidx])) evb |= 1u << sl;
   }
   double acc_rew = 0.0, acc_err = 0.0, acc_err2 = 0.0;
   int acc_cnt = 0, acc_crash = 0;
   if (active && r == 0) {
-    acc_rew = s.macc[3 * e];
-    acc_err = s.macc[3 * e + 1];
-    acc_err2 = s.macc[3 * e + 2];
-    acc_cnt = s.miacc[2 * e];
-    acc_crash = s.miacc[2 * e + 1];
+    acc_rew = ld_dc(&s.macc[3 * e]);
+    acc_err = ld_dc(&s.macc[3 * e + 1]);
+    acc_err2 = ld_dc(&s.macc[3 * e + 2]);
+    acc_cnt = ld_dc(&s.miacc[2 * e]);
+    acc_crash = ld_dc(&s.miacc[2 * e + 1]);
   }
-  uint32_t status = 0;
-  if (lane < 8) lds_dpsi[wib][lane] = p.dpsi[lane];
-  wave_lds_fence();
+  wave_lds_fence();  // the target slab is complete
 
-  for (int step = 0; step < T; ++step) {
+  for (int step = s_begin; step < s_end; ++step) {
     const uint32_t t = (uint32_t)(t0 + step);
 
     // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
@@ -770,16 +857,16 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 
   // ---- store state back (state pointers re-read from the device copy)
   if (active) {
-    const DevState &s = *sp;
+    const DevState s = *sp;
     if (g == 0) {
-      s.ax[aidx] = ax;
-      s.ay[aidx] = ay;
-      s.apsi[aidx] = apsi;
+      st_dc(&s.ax[aidx], ax);
+      st_dc(&s.ay[aidx], ay);
+      st_dc(&s.apsi[aidx], apsi);
 #pragma unroll
       for (int k = 0; k < WC; ++k) {
         if (k < W) {
-          s.hx[(int64_t)k * s.A + aidx] = hx[k];
-          s.hy[(int64_t)k * s.A + aidx] = hy[k];
+          st_dc(&s.hx[(int64_t)k * s.A + aidx], hx[k]);
+          st_dc(&s.hy[(int64_t)k * s.A + aidx], hy[k]);
         }
       }
     }
@@ -789,9 +876,9 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         const int j = 2 * q + m;
         if (j < nt) {
           const float4 tg = tl[j];
-          s.tx[tbase + j] = tg.x;
-          s.ty[tbase + j] = tg.y;
-          s.tpsi[tbase + j] = tg.z;
+          st_dc(&s.tx[tbase + j], tg.x);
+          st_dc(&s.ty[tbase + j], tg.y);
+          st_dc(&s.tpsi[tbase + j], tg.z);
         }
       }
     }
@@ -802,21 +889,26 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         const int64_t pidx = pbase + j;
 #pragma unroll
         for (int k = 0; k < WC; ++k)
-          if (k < W) s.hr[(int64_t)k * s.P + pidx] = hr[sl][k];
-        s.ex[pidx] = ex[sl];
-        s.ey[pidx] = ey[sl];
-        s.ev[pidx] = (evb >> sl) & 1u;
+          if (k < W) st_dc(&s.hr[(int64_t)k * s.P + pidx], hr[sl][k]);
+        st_dc(&s.ex[pidx], ex[sl]);
+        st_dc(&s.ey[pidx], ey[sl]);
+        st_dc(&s.ev[pidx], (uint8_t)((evb >> sl) & 1u));
       }
     }
     if (r == 0) {
-      s.macc[3 * e] = acc_rew;
-      s.macc[3 * e + 1] = acc_err;
-      s.macc[3 * e + 2] = acc_err2;
-      s.miacc[2 * e] = acc_cnt;
-      s.miacc[2 * e + 1] = acc_crash;
+      st_dc(&s.macc[3 * e], acc_rew);
+      st_dc(&s.macc[3 * e + 1], acc_err);
+      st_dc(&s.macc[3 * e + 2], acc_err2);
+      st_dc(&s.miacc[2 * e], acc_cnt);
+      st_dc(&s.miacc[2 * e + 1], acc_crash);
     }
   }
   if (status) atomicOr(sp->status, status);
+  wave_lds_fence();  // the next unit rewrites the target slab
+  if (!dyn) break;
+  if (s_end < T) publish_chunks(sp->queue + 1 + wave, cix + 1, lane);
+  unit = take_unit(sp->queue, lane);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -941,25 +1033,71 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
   return 0;
 }
 
+// Wavefronts of one rollout instantiation the GPU holds at once, for blocks
+// of `waves_per_block` wavefronts (cached per instantiation and block size).
+template <int S, int WC, int G, bool FULL, bool STAGE>
+static int resident_waves(int waves_per_block, size_t lds) {
+  static int cached[5] = {0, 0, 0, 0, 0};
+  int &c = cached[waves_per_block];
+  if (c == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(&rollout_kernel<S, WC, G, FULL, STAGE>),
+            64 * waves_per_block, lds) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    c = nb * device_cus() * waves_per_block;
+  }
+  return c;
+}
+
+// Steps per chunk of the automatic dynamic schedule: about 128, evenly split.
+static int auto_chunk(int32_t T) {
+  const int n = (T + 64) / 128;
+  return n <= 1 ? T : (T + n - 1) / n;
+}
+
 template <int S, int WC, int G, bool FULL, bool STAGE>
 static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams &p,
-                            const DevState *s, int32_t t0, int32_t T, uint32_t episode,
-                            const int32_t *actions, const DevOut &o, hipStream_t st,
-                            const DevExt &ext) {
-  const int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
+                            const DevState &hs, const DevState *s, int32_t t0, int32_t T,
+                            uint32_t episode, const int32_t *actions, const DevOut &o,
+                            hipStream_t st, const DevExt &ext, int32_t sched) {
   // per wavefront: target slab, then (lean form) token offsets and masks
   const size_t lds = (size_t)waves_per_block *
                      (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0));
+  int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
+  int32_t chunk = 0;
+  if (sched >= 0 && hs.queue) {
+    const int resident = resident_waves<S, WC, G, FULL, STAGE>(waves_per_block, lds);
+    if (sched > 0)
+      chunk = sched < T ? sched : T;
+    else if (num_waves > resident && T >= 32)
+      chunk = auto_chunk(T);
+    if (chunk > 0) {
+      const int64_t units = (int64_t)num_waves * ((T + chunk - 1) / chunk);
+      if (units + resident >= (int64_t)INT32_MAX) {
+        chunk = 0;  // beyond the counter's range: static schedule
+      } else {
+        const int64_t want = (units + waves_per_block - 1) / waves_per_block;
+        const int64_t cap = resident / waves_per_block;
+        blocks = (int)(want < cap ? want : cap);
+        const int32_t nq = num_waves + 1;
+        hipLaunchKernelGGL(queue_init_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0,
+                           st, hs.queue, nq);
+        if (check_launch()) return -1;
+      }
+    }
+  }
   hipLaunchKernelGGL((rollout_kernel<S, WC, G, FULL, STAGE>), dim3(blocks),
                      dim3(64 * waves_per_block), lds, st, p, s, num_waves, t0, T, episode, actions, o,
-                     ext);
+                     ext, chunk);
   return check_launch();
 }
 
 int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num_waves,
                    const DevParams &p, const DevState &hs, const DevState *s, int32_t t0,
                    int32_t T, uint32_t episode, const int32_t *actions, const DevOut &o_in,
-                   void *stream, const DevExt &ext) {
+                   void *stream, const DevExt &ext, int32_t sched) {
   hipStream_t st = (hipStream_t)stream;
   if (num_waves <= 0 || T <= 0) return 0;
   DevOut o = o_in;
@@ -976,15 +1114,18 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   // least two wavefronts per SIMD take turns on the store path (large
   // batches); small batches are latency-bound and write directly
   const bool stage = lean && num_waves >= 8 * device_cus();
-#define MIL_ROLL(SC, WCV, GV)                                                                       \
-  if (size_class == SC && wcap == WCV && G == GV) {                                                \
-    if (!lean)                                                                                      \
-      return launch_rollout_t<SC, WCV, GV, true, false>(waves_per_block, num_waves, p, s, t0, T,  \
-                                                        episode, actions, o, st, ext);            \
-    return stage ? launch_rollout_t<SC, WCV, GV, false, true>(waves_per_block, num_waves, p, s,   \
-                                                              t0, T, episode, actions, o, st, ext) \
-                 : launch_rollout_t<SC, WCV, GV, false, false>(waves_per_block, num_waves, p, s,  \
-                                                               t0, T, episode, actions, o, st, ext);\
+#define MIL_ROLL(SC, WCV, GV)                                                                \
+  if (size_class == SC && wcap == WCV && G == GV) {                                         \
+    if (!lean)                                                                               \
+      return launch_rollout_t<SC, WCV, GV, true, false>(waves_per_block, num_waves, p, hs, s, \
+                                                        t0, T, episode, actions, o, st, ext, \
+                                                        sched);                              \
+    return stage ? launch_rollout_t<SC, WCV, GV, false, true>(waves_per_block, num_waves, p, \
+                                                              hs, s, t0, T, episode, actions, \
+                                                              o, st, ext, sched)             \
+                 : launch_rollout_t<SC, WCV, GV, false, false>(waves_per_block, num_waves, p, \
+                                                               hs, s, t0, T, episode, actions, \
+                                                               o, st, ext, sched);           \
   }
   MIL_ROLL(2, 10, 1)
   MIL_ROLL(2, 10, 2)

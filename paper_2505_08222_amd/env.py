@@ -156,6 +156,15 @@ class Env:
         check(lib().env_get_mapping(self._h, C.byref(g), C.byref(w)))
         return g.value, w.value
 
+    def set_schedule(self, chunk_steps: int):
+        """-1 static, 0 automatic, > 0 dynamic with chunks of that many steps."""
+        check(lib().env_set_schedule(self._h, int(chunk_steps)))
+
+    def get_schedule(self) -> int:
+        c = C.c_int32()
+        check(lib().env_get_schedule(self._h, C.byref(c)))
+        return c.value
+
     def autotune(self, probe_steps: int = 20, record=DEFAULT_RECORD, cache_path=None):
         out = self._alloc(record, probe_steps)
         check(lib().env_autotune(self._h, int(probe_steps), C.byref(self._struct(out)),

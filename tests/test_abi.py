@@ -120,6 +120,10 @@ def test_calls_out_of_order_are_rejected(milib):
     g, w = C.c_int32(), C.c_int32()
     L.env_get_mapping(h, C.byref(g), C.byref(w))
     assert (g.value, w.value) == (2, 4)
+    assert L.env_set_schedule(h, -2) == -1
+    assert L.env_set_schedule(h, 7) == 0
+    sc = C.c_int32()
+    assert L.env_get_schedule(h, C.byref(sc)) == 0 and sc.value == 7
     assert L.env_bind(h, C.c_void_p(0x1001), 1 << 30, None) == -3  # misaligned
     L.env_destroy(h)
     assert L.est_exact(None, 10, 2, 0, C.c_float(1e-4), 0, None, None, None) == -1
