@@ -208,9 +208,10 @@ int env_get_state(mil_env *h, float *d_agent, float *d_target, void *stream);
 int env_set_mapping(mil_env *h, int32_t lanes_per_agent, int32_t waves_per_block);
 int env_get_mapping(const mil_env *h, int32_t *lanes_per_agent, int32_t *waves_per_block);
 /* Rollout schedule. chunk_steps = -1: static, one wavefront per group of
- * environments for all T steps. 0 (default): automatic, dynamic when there
- * are more groups than wavefronts the GPU holds at once and T >= 32, with
- * chunks of about 128 steps. > 0: dynamic with chunks of that many steps.
+ * environments for all T steps. 0 (default): automatic, dynamic with chunks
+ * of about 128 steps when the groups number between one and eight times the
+ * wavefronts the GPU holds at once and T >= 192 (two chunks or more), else
+ * static. > 0: dynamic with chunks of that many steps.
  * Dynamic: the rollout launch is preceded by a small kernel that clears the
  * queue in the workspace; the persistent wavefronts take (chunk, group) units
  * from an atomic counter, chunk-major, save the group's state after each

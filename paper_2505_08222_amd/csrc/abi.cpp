@@ -90,7 +90,7 @@ struct mil_env {
   char *ws = nullptr;
   int64_t ws_bytes = 0;
   struct {
-    int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue;
+    int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue, mpart;
     int64_t ax, ay, apsi, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
     int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
@@ -352,6 +352,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.classes = take((int64_t)h->cls.size() * sizeof(mil::ClassInfo));
   f.wave_class = take(h->max_waves);
   f.queue = take(((int64_t)h->max_waves + 1) * 4);
+  f.mpart = take((int64_t)mil::kMetricBlocks * 6 * 8);
   f.status = take(256);
   f.devstate = take(sizeof(mil::DevState));
   f.state_begin = o;
@@ -454,6 +455,7 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.miacc = (int32_t *)(h->ws + h->off.miacc);
   d.status = (uint32_t *)(h->ws + h->off.status);
   d.queue = (int32_t *)(h->ws + h->off.queue);
+  d.mpart = (double *)(h->ws + h->off.mpart);
   d.E = E;
   d.A = h->aoff[E];
   d.Tt = h->toff[E];

@@ -26,6 +26,9 @@ struct ClassInfo {
   int32_t wave0, nwaves;
 };
 
+// Blocks of the metrics reduction (each sums a contiguous range of envs).
+constexpr int kMetricBlocks = 256;
+
 // Device pointers into the caller's workspace.
 struct DevState {
   const uint32_t *env_id;  // [E] global id of each packed env
@@ -45,6 +48,7 @@ struct DevState {
   int32_t *miacc;                            // [E][2] err count, crash steps
   uint32_t *status;                          // [1]
   int32_t *queue;                            // [1 + groups] dynamic-schedule counter, chunk flags
+  double *mpart;                             // [kMetricBlocks][6] metrics partial sums
   int64_t E, A, Tt, P, K;
 };
 
@@ -81,8 +85,9 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
 // d_state: a device copy of `s` (the rollout reads it through this pointer so
 // that the state pointers need not stay in scalar registers across steps).
 // sched: -1 static (one wavefront per group for all T steps), 0 automatic
-// (dynamic when the groups outnumber the wavefronts the GPU holds at once),
-// > 0 dynamic with chunks of that many steps.
+// (dynamic when the groups number one to eight times the wavefronts the GPU
+// holds at once and T spans two chunks), > 0 dynamic with chunks of that
+// many steps.
 int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_block,
                    int num_waves, const DevParams &p, const DevState &s, const DevState *d_state,
                    int32_t t0, int32_t T, uint32_t episode, const int32_t *actions,

@@ -127,6 +127,21 @@ __device__ __forceinline__ void st_dc(T *p, T v) {
   using GT = __attribute__((address_space(1))) T;
   __hip_atomic_store((GT *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Carried state: device-coherent under the dynamic schedule (dc, uniform),
+// ordinary cached accesses under the static one.
+template <typename T>
+__device__ __forceinline__ T ld_st(const T *p, bool dc) {
+  using GT = __attribute__((address_space(1))) T;
+  return dc ? ld_dc(p) : *(const GT *)p;
+}
+template <typename T>
+__device__ __forceinline__ void st_st(T *p, T v, bool dc) {
+  using GT = __attribute__((address_space(1))) T;
+  if (dc)
+    st_dc(p, v);
+  else
+    *(GT *)p = v;
+}
 
 __device__ __forceinline__ int take_unit(int32_t *queue, int lane) {
   int u = 0;
@@ -376,36 +391,39 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       const int j = 2 * q + m;
       if (j < nt) {
         const int64_t idx = tbase + j;
-        tl[j] = make_float4(ld_dc(&s.tx[idx]), ld_dc(&s.ty[idx]), ld_dc(&s.tpsi[idx]), s.tv[idx]);
+        tl[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
+                            ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
       }
     }
   }
-  float ax = ld_dc(&s.ax[aidx]), ay = ld_dc(&s.ay[aidx]), apsi = ld_dc(&s.apsi[aidx]);
+  float ax = ld_st(&s.ax[aidx], dyn), ay = ld_st(&s.ay[aidx], dyn);
+  float apsi = ld_st(&s.apsi[aidx], dyn);
   float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
   uint32_t evb = 0;
 #pragma unroll
   for (int k = 0; k < WC; ++k) {
-    hx[k] = (k < W) ? ld_dc(&s.hx[(int64_t)k * s.A + aidx]) : 0.0f;
-    hy[k] = (k < W) ? ld_dc(&s.hy[(int64_t)k * s.A + aidx]) : 0.0f;
+    hx[k] = (k < W) ? ld_st(&s.hx[(int64_t)k * s.A + aidx], dyn) : 0.0f;
+    hy[k] = (k < W) ? ld_st(&s.hy[(int64_t)k * s.A + aidx], dyn) : 0.0f;
   }
 #pragma unroll
   for (int sl = 0; sl < NPL; ++sl) {
     const int j = g + G * sl;
     const int64_t pidx = pbase + (j < nt ? j : 0);
 #pragma unroll
-    for (int k = 0; k < WC; ++k) hr[sl][k] = (k < W) ? ld_dc(&s.hr[(int64_t)k * s.P + pidx]) : 0.0f;
-    ex[sl] = ld_dc(&s.ex[pidx]);
-    ey[sl] = ld_dc(&s.ey[pidx]);
-    if (j < nt && ld_dc(&s.ev[pidx])) evb |= 1u << sl;
+    for (int k = 0; k < WC; ++k)
+      hr[sl][k] = (k < W) ? ld_st(&s.hr[(int64_t)k * s.P + pidx], dyn) : 0.0f;
+    ex[sl] = ld_st(&s.ex[pidx], dyn);
+    ey[sl] = ld_st(&s.ey[pidx], dyn);
+    if (j < nt && ld_st(&s.ev[pidx], dyn)) evb |= 1u << sl;
   }
   double acc_rew = 0.0, acc_err = 0.0, acc_err2 = 0.0;
   int acc_cnt = 0, acc_crash = 0;
   if (active && r == 0) {
-    acc_rew = ld_dc(&s.macc[3 * e]);
-    acc_err = ld_dc(&s.macc[3 * e + 1]);
-    acc_err2 = ld_dc(&s.macc[3 * e + 2]);
-    acc_cnt = ld_dc(&s.miacc[2 * e]);
-    acc_crash = ld_dc(&s.miacc[2 * e + 1]);
+    acc_rew = ld_st(&s.macc[3 * e], dyn);
+    acc_err = ld_st(&s.macc[3 * e + 1], dyn);
+    acc_err2 = ld_st(&s.macc[3 * e + 2], dyn);
+    acc_cnt = ld_st(&s.miacc[2 * e], dyn);
+    acc_crash = ld_st(&s.miacc[2 * e + 1], dyn);
   }
   wave_lds_fence();  // the target slab is complete
 
@@ -859,14 +877,14 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   if (active) {
     const DevState s = *sp;
     if (g == 0) {
-      st_dc(&s.ax[aidx], ax);
-      st_dc(&s.ay[aidx], ay);
-      st_dc(&s.apsi[aidx], apsi);
+      st_st(&s.ax[aidx], ax, dyn);
+      st_st(&s.ay[aidx], ay, dyn);
+      st_st(&s.apsi[aidx], apsi, dyn);
 #pragma unroll
       for (int k = 0; k < WC; ++k) {
         if (k < W) {
-          st_dc(&s.hx[(int64_t)k * s.A + aidx], hx[k]);
-          st_dc(&s.hy[(int64_t)k * s.A + aidx], hy[k]);
+          st_st(&s.hx[(int64_t)k * s.A + aidx], hx[k], dyn);
+          st_st(&s.hy[(int64_t)k * s.A + aidx], hy[k], dyn);
         }
       }
     }
@@ -876,9 +894,9 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         const int j = 2 * q + m;
         if (j < nt) {
           const float4 tg = tl[j];
-          st_dc(&s.tx[tbase + j], tg.x);
-          st_dc(&s.ty[tbase + j], tg.y);
-          st_dc(&s.tpsi[tbase + j], tg.z);
+          st_st(&s.tx[tbase + j], tg.x, dyn);
+          st_st(&s.ty[tbase + j], tg.y, dyn);
+          st_st(&s.tpsi[tbase + j], tg.z, dyn);
         }
       }
     }
@@ -889,18 +907,18 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         const int64_t pidx = pbase + j;
 #pragma unroll
         for (int k = 0; k < WC; ++k)
-          if (k < W) st_dc(&s.hr[(int64_t)k * s.P + pidx], hr[sl][k]);
-        st_dc(&s.ex[pidx], ex[sl]);
-        st_dc(&s.ey[pidx], ey[sl]);
-        st_dc(&s.ev[pidx], (uint8_t)((evb >> sl) & 1u));
+          if (k < W) st_st(&s.hr[(int64_t)k * s.P + pidx], hr[sl][k], dyn);
+        st_st(&s.ex[pidx], ex[sl], dyn);
+        st_st(&s.ey[pidx], ey[sl], dyn);
+        st_st(&s.ev[pidx], (uint8_t)((evb >> sl) & 1u), dyn);
       }
     }
     if (r == 0) {
-      st_dc(&s.macc[3 * e], acc_rew);
-      st_dc(&s.macc[3 * e + 1], acc_err);
-      st_dc(&s.macc[3 * e + 2], acc_err2);
-      st_dc(&s.miacc[2 * e], acc_cnt);
-      st_dc(&s.miacc[2 * e + 1], acc_crash);
+      st_st(&s.macc[3 * e], acc_rew, dyn);
+      st_st(&s.macc[3 * e + 1], acc_err, dyn);
+      st_st(&s.macc[3 * e + 2], acc_err2, dyn);
+      st_st(&s.miacc[2 * e], acc_cnt, dyn);
+      st_st(&s.miacc[2 * e + 1], acc_crash, dyn);
     }
   }
   if (status) atomicOr(sp->status, status);
@@ -912,14 +930,29 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 }
 
 // ---------------------------------------------------------------------------
-// Metrics: one block; fixed assignment of envs to threads and a fixed tree,
-// so the sums are reproducible run to run.
+// Metrics: each block sums a fixed range of envs (thread t takes envs t,
+// t + 256, ... of its range, then a fixed tree), a second one-block kernel
+// sums the block partials in block order: reproducible run to run.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) metrics_kernel(DevParams p, DevState s, int32_t steps,
-                                                       double *out) {
-  __shared__ double red[1024][6];
+constexpr int kMetricThreads = 256;
+
+__device__ __forceinline__ void block_sum6(double (&v)[6], double (*red)[6]) {
+  for (int c = 0; c < 6; ++c) red[threadIdx.x][c] = v[c];
+  __syncthreads();
+  for (int w = kMetricThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int c = 0; c < 6; ++c) red[threadIdx.x][c] += red[threadIdx.x + w][c];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kMetricThreads) metrics_partial_kernel(DevParams p, DevState s,
+                                                                         int64_t per_block) {
+  __shared__ double red[kMetricThreads][6];
   double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int64_t e = threadIdx.x; e < s.E; e += blockDim.x) {
+  const int64_t e0 = (int64_t)blockIdx.x * per_block;
+  const int64_t e1 = min(s.E, e0 + per_block);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kMetricThreads) {
     v[0] += s.macc[3 * e];
     v[1] += s.macc[3 * e + 1];
     v[2] += s.macc[3 * e + 2];
@@ -935,13 +968,19 @@ __global__ void __launch_bounds__(1024) metrics_kernel(DevParams p, DevState s, 
       if (dmin > p.lost_range) v[5] += 1.0;
     }
   }
-  for (int c = 0; c < 6; ++c) red[threadIdx.x][c] = v[c];
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int c = 0; c < 6; ++c) red[threadIdx.x][c] += red[threadIdx.x + w][c];
-    __syncthreads();
-  }
+  block_sum6(v, red);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 6; ++c) s.mpart[6 * blockIdx.x + c] = red[0][c];
+}
+
+__global__ void __launch_bounds__(kMetricThreads) metrics_final_kernel(DevState s, int32_t steps,
+                                                                       int32_t nblocks,
+                                                                       double *out) {
+  __shared__ double red[kMetricThreads][6];
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblocks; b += kMetricThreads)
+    for (int c = 0; c < 6; ++c) v[c] += s.mpart[6 * b + c];
+  block_sum6(v, red);
   if (threadIdx.x == 0) {
     for (int c = 0; c < 6; ++c) out[c] = red[0][c];
     out[6] = (double)s.E * (double)steps;
@@ -1069,10 +1108,14 @@ static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams 
   int32_t chunk = 0;
   if (sched >= 0 && hs.queue) {
     const int resident = resident_waves<S, WC, G, FULL, STAGE>(waves_per_block, lds);
-    if (sched > 0)
+    if (sched > 0) {
       chunk = sched < T ? sched : T;
-    else if (num_waves > resident && T >= 32)
+    } else if (num_waves > resident && num_waves < 8 * resident) {
+      // a few rounds of wavefronts: the last round would run part-empty;
+      // with many rounds the hardware's own dispatch leaves little idle
       chunk = auto_chunk(T);
+      if (chunk >= T) chunk = 0;  // one chunk: nothing to rebalance
+    }
     if (chunk > 0) {
       const int64_t units = (int64_t)num_waves * ((T + chunk - 1) / chunk);
       if (units + resident >= (int64_t)INT32_MAX) {
@@ -1143,8 +1186,16 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
 
 int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
                    void *stream) {
-  hipLaunchKernelGGL(metrics_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, p, s, steps,
-                     d_metrics);
+  hipStream_t st = (hipStream_t)stream;
+  int64_t nb = (s.E + kMetricThreads - 1) / kMetricThreads;
+  if (nb > kMetricBlocks) nb = kMetricBlocks;
+  if (nb < 1) nb = 1;
+  const int64_t per_block = (s.E + nb - 1) / nb;
+  hipLaunchKernelGGL(metrics_partial_kernel, dim3((unsigned)nb), dim3(kMetricThreads), 0, st, p, s,
+                     per_block);
+  if (check_launch()) return -1;
+  hipLaunchKernelGGL(metrics_final_kernel, dim3(1), dim3(kMetricThreads), 0, st, s, steps,
+                     (int32_t)nb, d_metrics);
   return check_launch();
 }
 
