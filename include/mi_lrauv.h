@@ -222,7 +222,9 @@ int env_set_schedule(mil_env *h, int32_t chunk_steps);
 int env_get_schedule(const mil_env *h, int32_t *chunk_steps);
 /* Time every mapping on probe_steps steps writing `outs` (buffers sized for
  * probe_steps steps; NULL = no outputs), with the state saved before and
- * restored after each probe, and keep the fastest. If cache_path is not NULL
+ * restored after each probe, and keep the fastest. Under the automatic
+ * schedule each mapping is probed in the schedule a long rollout of the
+ * batch would get with it (dynamic ones in two chunks). If cache_path is not NULL
  * the choice is looked up in, and appended to, that JSON-lines file, keyed by
  * device, batch shape and code version. Needs a reset; synchronous. */
 int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,

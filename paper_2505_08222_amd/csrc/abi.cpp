@@ -220,11 +220,11 @@ int check_outputs(const mil_env_outputs *o) {
 }
 
 int run_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
-                hipStream_t st) {
+                hipStream_t st, int32_t sched) {
   const int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
                                      h->ds, (const mil::DevState *)(h->ws + h->off.devstate),
                                      (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st,
-                                     mil::DevExt{0, nullptr, nullptr}, h->sched);
+                                     mil::DevExt{0, nullptr, nullptr}, sched);
   if (rc == -2) return fail(MIL_EINVAL, "no kernel for size class %d / window %d", h->size_class,
                             h->wcap);
   if (rc != 0) return fail(MIL_EHIP, "rollout launch failed: %s",
@@ -497,7 +497,7 @@ int env_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_o
   int rc = check_outputs(outs);
   if (rc) return rc;
   if (T == 0) return MIL_OK;
-  rc = run_rollout(h, T, d_actions, outs, (hipStream_t)stream);
+  rc = run_rollout(h, T, d_actions, outs, (hipStream_t)stream, h->sched);
   if (rc) return rc;
   h->t += T;
   return MIL_OK;
@@ -659,7 +659,9 @@ int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
       float ms_min = 1e30f;
       for (int rep = 0; rep < 2; ++rep) {
         HIP_CHECK(hipEventRecord(e0, st));
-        rc = run_rollout(h, probe_steps, nullptr, outs, st);
+        // probed in the schedule a long rollout of this batch would get
+        rc = run_rollout(h, probe_steps, nullptr, outs, st,
+                         h->sched == 0 ? mil::kSchedProbe : h->sched);
         if (rc) return rc;
         HIP_CHECK(hipEventRecord(e1, st));
         HIP_CHECK(hipMemcpyAsync(state, snap, sbytes, hipMemcpyDeviceToDevice, st));

@@ -84,6 +84,9 @@ int launch_reset(const DevParams &p, const DevState &s, uint32_t episode, const 
                  void *stream);
 // d_state: a device copy of `s` (the rollout reads it through this pointer so
 // that the state pointers need not stay in scalar registers across steps).
+// kSchedProbe: the automatic choice made as if T were long (two chunks of
+// T/2 when a long rollout would be dynamic), for the autotuner's probes.
+constexpr int32_t kSchedProbe = -2;
 // sched: -1 static (one wavefront per group for all T steps), 0 automatic
 // (dynamic when the groups number one to eight times the wavefronts the GPU
 // holds at once and T spans two chunks), > 0 dynamic with chunks of that

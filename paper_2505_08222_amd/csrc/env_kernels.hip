@@ -1106,14 +1106,14 @@ static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams 
                      (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0));
   int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
   int32_t chunk = 0;
-  if (sched >= 0 && hs.queue) {
+  if ((sched >= 0 || sched == kSchedProbe) && hs.queue) {
     const int resident = resident_waves<S, WC, G, FULL, STAGE>(waves_per_block, lds);
     if (sched > 0) {
       chunk = sched < T ? sched : T;
     } else if (num_waves > resident && num_waves < 8 * resident) {
       // a few rounds of wavefronts: the last round would run part-empty;
       // with many rounds the hardware's own dispatch leaves little idle
-      chunk = auto_chunk(T);
+      chunk = sched == kSchedProbe ? (T + 1) / 2 : auto_chunk(T);
       if (chunk >= T) chunk = 0;  // one chunk: nothing to rebalance
     }
     if (chunk > 0) {
