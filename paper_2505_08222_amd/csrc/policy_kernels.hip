@@ -117,18 +117,85 @@ __device__ __forceinline__ void ln_row(const float *x, const float *g, const flo
   }
 }
 
-// LayerNorm of every row of the residual stream into xn (BF16).
+// Sum over the four lanes of a quad (DPP butterfly, lanes xor 1 then xor 2);
+// every lane of the quad ends with the same value.
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// LayerNorm (eps 1e-5) of every row of the residual stream into xn (BF16):
+// four lanes per row, 16 features each held in registers, quad sums for the
+// mean and the variance; 64 rows per pass of the block's 256 threads.
 __device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const float *g,
                                                 const float *b) {
-  for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-    bf16x8 *o = reinterpret_cast<bf16x8 *>(&L.xn[r][0]);
-    ln_row(&L.h[r][0], g, b, [&](int q, const float(&y)[8]) {
-      bf16x8 w;
+  const int q = threadIdx.x & 3;
+  const float4 *gp = reinterpret_cast<const float4 *>(g + 16 * q);
+  const float4 *bp = reinterpret_cast<const float4 *>(b + 16 * q);
+  for (int r0 = 0; r0 < rows; r0 += 64) {
+    const int r = r0 + (threadIdx.x >> 2);
+    const int rr = r < rows ? r : rows - 1;  // whole quads stay active
+    const float4 *xp = reinterpret_cast<const float4 *>(&L.h[rr][16 * q]);
+    float x[16];
 #pragma unroll
-      for (int c = 0; c < 8; ++c) w[c] = __float2bfloat16(y[c]);
-      o[q] = w;
-    });
+    for (int i = 0; i < 4; ++i) {
+      const float4 v = xp[i];
+      x[4 * i] = v.x;
+      x[4 * i + 1] = v.y;
+      x[4 * i + 2] = v.z;
+      x[4 * i + 3] = v.w;
+    }
+    float s4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s4[i] = (x[4 * i] + x[4 * i + 1]) + (x[4 * i + 2] + x[4 * i + 3]);
+    const float mean = quad_sum((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float t = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t = fmaf(x[4 * i + c] - mean, x[4 * i + c] - mean, t);
+      s4[i] = t;
+    }
+    const float var = quad_sum((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
+    const float inv = rsqrtf(var + 1e-5f);
+    bf16x8 w[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float4 gv = gp[i], bv = bp[i];
+      const float gg[4] = {gv.x, gv.y, gv.z, gv.w}, bb[4] = {bv.x, bv.y, bv.z, bv.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        w[i >> 1][4 * (i & 1) + c] = __float2bfloat16(fmaf((x[4 * i + c] - mean) * inv, gg[c], bb[c]));
+    }
+    if (r < rows) {
+      bf16x8 *o = reinterpret_cast<bf16x8 *>(&L.xn[r][16 * q]);
+      o[0] = w[0];
+      o[1] = w[1];
+    }
   }
+}
+
+// Bias of four consecutive features (FP32, LDS) added to an MFMA result.
+__device__ __forceinline__ floatx4 add4(const floatx4 &v, const float *bias) {
+  const float4 b = *reinterpret_cast<const float4 *>(bias);
+  return floatx4{v[0] + b.x, v[1] + b.y, v[2] + b.z, v[3] + b.w};
+}
+
+__device__ __forceinline__ bf16x4 to_bf16x4(const floatx4 &v) {
+  return bf16x4{__float2bfloat16(v[0]), __float2bfloat16(v[1]), __float2bfloat16(v[2]),
+                __float2bfloat16(v[3])};
+}
+
+// h[m][n..n+3] += v (+ bias)
+__device__ __forceinline__ void residual4(float *h, const floatx4 &v) {
+  float4 *p = reinterpret_cast<float4 *>(h);
+  float4 x = *p;
+  x.x += v[0];
+  x.y += v[1];
+  x.z += v[2];
+  x.w += v[3];
+  *p = x;
 }
 
 // at least two wavefronts per SIMD: two resident blocks of four per CU
@@ -201,12 +268,18 @@ policy_kernel(PolicyArgs a) {
       layer_norm_rows(L, rows, lp + kSmLn1G, lp + kSmLn1B);
       __syncthreads();
       __bf16 *Qp = L.buf, *Kp = L.buf + kPlane, *Vt = L.buf + 2 * kPlane;
-      gemm_rs_bf16<kPolD, 3 * kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows,
-                          [&](int m, int n, float v) {
-                            const __bf16 x = __float2bfloat16(v + lp[kSmBqkv + n]);
-                            if (n < 2 * kPolD) L.buf[(n >> 6) * kPlane + m * kLdQ + (n & 63)] = x;
-                            else Vt[(n - 2 * kPolD) * kLdVt + m] = x;
-                          });
+      gemm_rs_bf16_t<kPolD, 3 * kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows,
+                                       [&](int m, int n, const floatx4 &v) {
+                                         const bf16x4 x = to_bf16x4(add4(v, lp + kSmBqkv + n));
+                                         if (n < 2 * kPolD) {
+                                           *reinterpret_cast<bf16x4 *>(
+                                               &L.buf[(n >> 6) * kPlane + m * kLdQ + (n & 63)]) = x;
+                                         } else {
+#pragma unroll
+                                           for (int j = 0; j < 4; ++j)
+                                             Vt[(n - 2 * kPolD + j) * kLdVt + m] = x[j];
+                                         }
+                                       });
       __syncthreads();
       // attention on the matrix cores: one wavefront per (agent, head); the
       // transposed products S^T = K Q^T and O^T = V^T P^T are single 16x16
@@ -318,20 +391,27 @@ policy_kernel(PolicyArgs a) {
         }
       }
       __syncthreads();
-      gemm_rs_bf16<kPolD, kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows,
-                       [&](int m, int n, float v) { L.h[m][n] += v + lp[kSmBo + n]; });
+      gemm_rs_bf16_t<kPolD, kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows,
+                                   [&](int m, int n, const floatx4 &v) {
+                                     residual4(&L.h[m][n], add4(v, lp + kSmBo + n));
+                                   });
       __syncthreads();
       // ---- feed-forward block, hidden layer in two halves of 128
       layer_norm_rows(L, rows, lp + kSmLn2G, lp + kSmLn2B);
       __syncthreads();
       for (int half = 0; half < 2; ++half) {
-        gemm_rs_bf16<kPolD, 128>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD, rows,
-                         [&](int m, int n, float v) {
-                           L.buf[m * kLdHid + n] = __float2bfloat16(gelu_tanh_fast(v + lp[kSmB1 + half * 128 + n]));
-                         });
+        gemm_rs_bf16_t<kPolD, 128>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD,
+                                   rows, [&](int m, int n, const floatx4 &v) {
+                                     const floatx4 y = add4(v, lp + kSmB1 + half * 128 + n);
+                                     *reinterpret_cast<bf16x4 *>(&L.buf[m * kLdHid + n]) =
+                                         to_bf16x4(floatx4{gelu_tanh_fast(y[0]), gelu_tanh_fast(y[1]),
+                                                           gelu_tanh_fast(y[2]), gelu_tanh_fast(y[3])});
+                                   });
         __syncthreads();
-        gemm_rs_bf16<128, kPolD>(L.buf, kLdHid, w2 + half * 128, kPolLdF, rows,
-                       [&](int m, int n, float v) { L.h[m][n] += v + (half == 0 ? lp[kSmB2 + n] : 0.0f); });
+        gemm_rs_bf16_t<128, kPolD>(L.buf, kLdHid, w2 + half * 128, kPolLdF, rows,
+                                   [&](int m, int n, const floatx4 &v) {
+                                     residual4(&L.h[m][n], half == 0 ? add4(v, lp + kSmB2 + n) : v);
+                                   });
         __syncthreads();
       }
     }
