@@ -63,6 +63,7 @@ struct PolicyLds {
   // [rows][136]; or raw tokens; or the head's scratch
   __bf16 buf[3 * kPolRows * (kPolD + 8)];
   uint8_t mask[kPolRows];
+  uint32_t mbits[kPolMaxAgents];          // per agent: bit k = observation mask of token k
   float logits[kPolMaxAgents][kPolActions];
 };
 static_assert(sizeof(PolicyLds) <= 80 * 1024, "two policy blocks per CU");
@@ -229,6 +230,9 @@ policy_kernel(PolicyArgs a) {
     msk = (tile < ntiles && tid < nrow) ? a.mask[ag0 * nt + tid] : 0;
   };
   fetch(blockIdx.x);
+  // weight fragments are loaded one GEMM ahead (the first layer's QKV here)
+  BFrag<kPolD, 3 * kPolD> fq;
+  load_bfrag(fq, a.wqkv, kPolLdD);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t ag0 = tile * at;
     const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;  // agents in this tile
@@ -256,11 +260,15 @@ policy_kernel(PolicyArgs a) {
         for (int c = 0; c < 6; ++c) acc = fmaf(wv[c], x_raw[r * 6 + c], acc);
         L.h[r][d] = r < nrow ? acc : 0.0f;
       }
+      if (tid < at) {
+        uint32_t bits = 0;
+        for (int k = 0; k < nt; ++k) bits |= (uint32_t)(L.mask[tid * nt + k] != 0) << k;
+        L.mbits[tid] = bits;
+      }
     }
     __syncthreads();
     for (int l = 0; l < kPolLayers; ++l) {
       const float *lp = L.prm + kSmLayer0 + l * kSmLayer;
-      const __bf16 *wq = a.wqkv + l * (3 * kPolD) * kPolLdD;
       const __bf16 *wo = a.wo + l * kPolD * kPolLdD;
       const __bf16 *w1 = a.w1 + l * kPolF * kPolLdD;
       const __bf16 *w2 = a.w2 + l * kPolD * kPolLdF;
@@ -268,7 +276,9 @@ policy_kernel(PolicyArgs a) {
       layer_norm_rows(L, rows, lp + kSmLn1G, lp + kSmLn1B);
       __syncthreads();
       __bf16 *Qp = L.buf, *Kp = L.buf + kPlane, *Vt = L.buf + 2 * kPlane;
-      gemm_rs_bf16_t<kPolD, 3 * kPolD>(&L.xn[0][0], kPolD + 8, wq, kPolLdD, rows,
+      BFrag<kPolD, kPolD> fo;
+      load_bfrag(fo, wo, kPolLdD);
+      gemm_rs_bf16_tf<kPolD, 3 * kPolD>(&L.xn[0][0], kPolD + 8, fq, rows,
                                        [&](int m, int n, const floatx4 &v) {
                                          const bf16x4 x = to_bf16x4(add4(v, lp + kSmBqkv + n));
                                          if (n < 2 * kPolD) {
@@ -290,16 +300,17 @@ policy_kernel(PolicyArgs a) {
         const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
         const int row = lane & 15, kg = lane >> 4;
         const bf16x8 zero8 = {};
-        constexpr int NP = 2;  // (agent, head) pairs in flight per wavefront
+        constexpr int NP = 4;  // (agent, head) pairs in flight per wavefront
         for (int pr0 = wave * NP; pr0 < at * kPolHeads; pr0 += nw * NP) {
-          int r0[NP], hd[NP];
+          int r0[NP], hd[NP], ag[NP];
           bool live[NP];
           floatx4 st[NP];
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             const int pr = pr0 + i;
             live[i] = pr < at * kPolHeads;
-            r0[i] = live[i] ? (pr / kPolHeads) * nt : 0;
+            ag[i] = live[i] ? pr / kPolHeads : 0;
+            r0[i] = ag[i] * nt;
             hd[i] = pr % kPolHeads;
             bf16x8 ka = zero8, qb = zero8;  // A = K (row = key), B = Q (column = query)
             if (kg < 2 && row < nt) {
@@ -314,10 +325,10 @@ policy_kernel(PolicyArgs a) {
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             m[i] = -INFINITY;
+            const uint32_t mb = L.mbits[ag[i]] >> (4 * kg);  // keys >= nt have no bit
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              const int key = 4 * kg + j;
-              const bool ok = key < nt && L.mask[r0[i] + (key < nt ? key : 0)];
+              const bool ok = (mb >> j) & 1u;
               x[i][j] = ok ? st[i][j] * 0.25f : -INFINITY;
               m[i] = fmaxf(m[i], x[i][j]);
             }
@@ -391,7 +402,9 @@ policy_kernel(PolicyArgs a) {
         }
       }
       __syncthreads();
-      gemm_rs_bf16_t<kPolD, kPolD>(&L.xn[0][0], kPolD + 8, wo, kPolLdD, rows,
+      BFrag<kPolD, 128> f1;
+      load_bfrag(f1, w1, kPolLdD);
+      gemm_rs_bf16_tf<kPolD, kPolD>(&L.xn[0][0], kPolD + 8, fo, rows,
                                    [&](int m, int n, const floatx4 &v) {
                                      residual4(&L.h[m][n], add4(v, lp + kSmBo + n));
                                    });
@@ -399,8 +412,11 @@ policy_kernel(PolicyArgs a) {
       // ---- feed-forward block, hidden layer in two halves of 128
       layer_norm_rows(L, rows, lp + kSmLn2G, lp + kSmLn2B);
       __syncthreads();
+#pragma unroll
       for (int half = 0; half < 2; ++half) {
-        gemm_rs_bf16_t<kPolD, 128>(&L.xn[0][0], kPolD + 8, w1 + half * 128 * kPolLdD, kPolLdD,
+        BFrag<128, kPolD> f2;
+        load_bfrag(f2, w2 + half * 128, kPolLdF);
+        gemm_rs_bf16_tf<kPolD, 128>(&L.xn[0][0], kPolD + 8, f1,
                                    rows, [&](int m, int n, const floatx4 &v) {
                                      const floatx4 y = add4(v, lp + kSmB1 + half * 128 + n);
                                      *reinterpret_cast<bf16x4 *>(&L.buf[m * kLdHid + n]) =
@@ -408,7 +424,11 @@ policy_kernel(PolicyArgs a) {
                                                            gelu_tanh_fast(y[2]), gelu_tanh_fast(y[3])});
                                    });
         __syncthreads();
-        gemm_rs_bf16_t<128, kPolD>(L.buf, kLdHid, w2 + half * 128, kPolLdF, rows,
+        if (half == 0)
+          load_bfrag(f1, w1 + 128 * kPolLdD, kPolLdD);  // the second half's W1
+        else  // the next layer's QKV, or the first layer's for the next tile
+          load_bfrag(fq, a.wqkv + (l + 1 < kPolLayers ? l + 1 : 0) * (3 * kPolD) * kPolLdD, kPolLdD);
+        gemm_rs_bf16_tf<128, kPolD>(L.buf, kLdHid, f2, rows,
                                    [&](int m, int n, const floatx4 &v) {
                                      residual4(&L.h[m][n], half == 0 ? add4(v, lp + kSmB2 + n) : v);
                                    });
