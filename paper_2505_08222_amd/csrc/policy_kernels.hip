@@ -21,20 +21,9 @@
 
 namespace mil {
 
-namespace {
+typedef int int2v __attribute__((ext_vector_type(2)));
 
-// Exchange with lane ^ 16 and lane ^ 32 through the cross-row swap
-// instructions (VALU, no LDS round trip).
-__device__ __forceinline__ int xor16i(int v) {
-  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-  return (threadIdx.x & 16) ? (int)r[0] : (int)r[1];
-}
-__device__ __forceinline__ int xor32i(int v) {
-  const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-  return (threadIdx.x & 32) ? (int)r[0] : (int)r[1];
-}
-__device__ __forceinline__ float xor16f(float v) { return __int_as_float(xor16i(__float_as_int(v))); }
-__device__ __forceinline__ float xor32f(float v) { return __int_as_float(xor32i(__float_as_int(v))); }
+namespace {
 
 // Position in the parameter vector of entry i of the LDS copy of the small
 // FP32 parameters (embedding, LayerNorms, biases, head).
@@ -211,6 +200,9 @@ policy_kernel(PolicyArgs a) {
   const int rows = (rows_used + 15) & ~15;
   const int64_t ntiles = (a.A + at - 1) / at;
   for (int i = tid; i < kSmTotal; i += nthr) L.prm[i] = a.params[small_param_src(i)];
+  // the V^T plane's padding columns are read (and multiplied by zero) in
+  // attention but never written: start the whole plane at zero
+  for (int i = tid; i < kPolD * kLdVt; i += nthr) L.buf[2 * kPlane + i] = __bf16{};
   // raw tokens and masks of a tile are contiguous in memory; each thread
   // holds its share of the next tile's in registers while this one computes
   constexpr int kTokRegs = (kPolRows * 6 + 255) / 256;
@@ -291,15 +283,14 @@ policy_kernel(PolicyArgs a) {
                                          }
                                        });
       __syncthreads();
-      // attention on the matrix cores: one wavefront per (agent, head); the
-      // transposed products S^T = K Q^T and O^T = V^T P^T are single 16x16
-      // tiles (tokens padded to 16, head dim 16 padded to the instruction's
-      // K = 32 with zeros), so each lane holds four keys of one query and the
-      // softmax needs only two cross-lane steps
+      // attention on the matrix cores, per (agent, head): S^T = K Q^T and
+      // O^T = V^T P^T are single 16x16x16 products (tokens padded to 16, the
+      // head dimension is the instruction's K), so each lane holds four keys
+      // of one query, exactly the four that the second product takes from it:
+      // the softmax needs only two cross-lane steps and P never moves
       {
         const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
         const int row = lane & 15, kg = lane >> 4;
-        const bf16x8 zero8 = {};
         constexpr int NP = 4;  // (agent, head) pairs in flight per wavefront
         for (int pr0 = wave * NP; pr0 < at * kPolHeads; pr0 += nw * NP) {
           int r0[NP], hd[NP], ag[NP];
@@ -312,31 +303,44 @@ policy_kernel(PolicyArgs a) {
             ag[i] = live[i] ? pr / kPolHeads : 0;
             r0[i] = ag[i] * nt;
             hd[i] = pr % kPolHeads;
-            bf16x8 ka = zero8, qb = zero8;  // A = K (row = key), B = Q (column = query)
-            if (kg < 2 && row < nt) {
-              ka = *reinterpret_cast<const bf16x8 *>(Kp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 8 * kg);
-              qb = *reinterpret_cast<const bf16x8 *>(Qp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 8 * kg);
-            }
-            st[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            st[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka, qb, st[i], 0, 0, 0);
+            // A = K (row = key), B = Q (column = query); rows past the
+            // agent's tokens hold finite values of other rows: their keys are
+            // masked below and their queries' outputs are not written
+            const bf16x4 ka =
+                *reinterpret_cast<const bf16x4 *>(Kp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 4 * kg);
+            const bf16x4 qb =
+                *reinterpret_cast<const bf16x4 *>(Qp + (r0[i] + row) * kLdQ + hd[i] * kPolDh + 4 * kg);
+            st[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ka, qb, floatx4{0.0f, 0.0f, 0.0f, 0.0f},
+                                                             0, 0, 0);
           }
-          // st[i][j] = S[query row][key 4 kg + j]
+          // st[i][j] = S[query row][key 4 kg + j]; keys without a mask bit
+          // (masked, or at or beyond nt) are excluded
           float x[NP][4], m[NP], z[NP];
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             m[i] = -INFINITY;
-            const uint32_t mb = L.mbits[ag[i]] >> (4 * kg);  // keys >= nt have no bit
+            const uint32_t mb = L.mbits[ag[i]] >> (4 * kg);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-              const bool ok = (mb >> j) & 1u;
-              x[i][j] = ok ? st[i][j] * 0.25f : -INFINITY;
+              x[i][j] = ((mb >> j) & 1u) ? st[i][j] * 0.25f : -INFINITY;
               m[i] = fmaxf(m[i], x[i][j]);
             }
           }
+          // max and sum over the four lane groups of a query: each swap
+          // leaves a lane's own value in one result and its partner's in the
+          // other, and both operations are symmetric
 #pragma unroll
-          for (int i = 0; i < NP; ++i) m[i] = fmaxf(m[i], xor16f(m[i]));
+          for (int i = 0; i < NP; ++i) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(m[i]), __float_as_int(m[i]),
+                                                            false, false);
+            m[i] = fmaxf(__int_as_float(r[0]), __int_as_float(r[1]));
+          }
 #pragma unroll
-          for (int i = 0; i < NP; ++i) m[i] = fmaxf(m[i], xor32f(m[i]));
+          for (int i = 0; i < NP; ++i) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(m[i]), __float_as_int(m[i]),
+                                                            false, false);
+            m[i] = fmaxf(__int_as_float(r[0]), __int_as_float(r[1]));
+          }
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             z[i] = 0.0f;
@@ -347,52 +351,43 @@ policy_kernel(PolicyArgs a) {
             }
           }
 #pragma unroll
-          for (int i = 0; i < NP; ++i) z[i] += xor16f(z[i]);
+          for (int i = 0; i < NP; ++i) {
+            const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(z[i]), __float_as_int(z[i]),
+                                                            false, false);
+            z[i] = __int_as_float(r[0]) + __int_as_float(r[1]);
+          }
 #pragma unroll
-          for (int i = 0; i < NP; ++i) z[i] += xor32f(z[i]);
-          // B = P^T (column = query, K = key): lanes of group 0 take keys 0-7
-          // (groups 0, 1), group 1 keys 8-15 (groups 2, 3)
+          for (int i = 0; i < NP; ++i) {
+            const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(z[i]), __float_as_int(z[i]),
+                                                            false, false);
+            z[i] = __int_as_float(r[0]) + __int_as_float(r[1]);
+          }
+          // A = V^T (row = head dimension, K = key), B = P^T (column =
+          // query, K = key): this lane's own four probabilities. Keys at or
+          // beyond nt meet P = 0 and read finite V^T values (written by the
+          // QKV epilogue, or the plane's zeroed padding).
           floatx4 ot[NP];
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
-            const bf16x2 d0 = bf16x2{__float2bfloat16(x[i][0]), __float2bfloat16(x[i][1])};
-            const bf16x2 d1 = bf16x2{__float2bfloat16(x[i][2]), __float2bfloat16(x[i][3])};
-            const int w0 = __builtin_bit_cast(int, d0), w1 = __builtin_bit_cast(int, d1);
-            // group 0 takes its own words and group 1's (lane ^ 16); group 1
-            // takes groups 2 (lane ^ 48) and 3 (lane ^ 32)
-            const int w0x16 = xor16i(w0), w1x16 = xor16i(w1);
-            const int w0x32 = xor32i(w0), w1x32 = xor32i(w1);
-            const int w0x48 = xor32i(w0x16), w1x48 = xor32i(w1x16);
-            const int e0 = kg == 0 ? w0 : w0x48, e1 = kg == 0 ? w1 : w1x48;
-            const int e2 = kg == 0 ? w0x16 : w0x32, e3 = kg == 0 ? w1x16 : w1x32;
-            bf16x8 pb = zero8, va = zero8;  // A = V^T (row = head dim, K = key)
-            if (kg < 2) {
-              const bf16x2 p0 = __builtin_bit_cast(bf16x2, e0), p1 = __builtin_bit_cast(bf16x2, e1);
-              const bf16x2 p2 = __builtin_bit_cast(bf16x2, e2), p3 = __builtin_bit_cast(bf16x2, e3);
-              pb = bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
-              // keys at or beyond nt are loaded (inside the buffer) but replaced by 0
-              const __bf16 *vr = Vt + (hd[i] * kPolDh + row) * kLdVt + r0[i] + 8 * kg;
-              const __bf16 zb = {};
-              if ((r0[i] & 1) == 0) {  // 4-byte aligned key pairs
+            const bf16x4 pb = bf16x4{__float2bfloat16(x[i][0]), __float2bfloat16(x[i][1]),
+                                     __float2bfloat16(x[i][2]), __float2bfloat16(x[i][3])};
+            const __bf16 *vr = Vt + (hd[i] * kPolDh + row) * kLdVt + r0[i] + 4 * kg;
+            bf16x4 va;
+            if ((r0[i] & 1) == 0) {  // 4-byte aligned key pairs
+              const uint32_t *v32 = reinterpret_cast<const uint32_t *>(vr);
+              va = __builtin_bit_cast(bf16x4, int2v{(int)v32[0], (int)v32[1]});
+            } else {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                  const bf16x2 v2 = reinterpret_cast<const bf16x2 *>(vr)[t];
-                  va[2 * t] = 8 * kg + 2 * t < nt ? v2[0] : zb;
-                  va[2 * t + 1] = 8 * kg + 2 * t + 1 < nt ? v2[1] : zb;
-                }
-              } else {
-#pragma unroll
-                for (int t = 0; t < 8; ++t) va[t] = 8 * kg + t < nt ? vr[t] : zb;
-              }
+              for (int t = 0; t < 4; ++t) va[t] = vr[t];
             }
-            ot[i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-            ot[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(va, pb, ot[i], 0, 0, 0);
+            ot[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(va, pb, floatx4{0.0f, 0.0f, 0.0f, 0.0f},
+                                                             0, 0, 0);
           }
           // ot[i][j] = O[query row][head dim 4 kg + j]
 #pragma unroll
           for (int i = 0; i < NP; ++i) {
             if (live[i] && row < nt) {
-              const float iz = z[i] > 0.0f ? 1.0f / z[i] : 0.0f;  // no keys: zero output
+              const float iz = z[i] > 0.0f ? __builtin_amdgcn_rcpf(z[i]) : 0.0f;  // no keys: zero output
               bf16x4 o4;
 #pragma unroll
               for (int j = 0; j < 4; ++j) o4[j] = __float2bfloat16(ot[i][j] * iz);
