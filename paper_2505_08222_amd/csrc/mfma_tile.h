@@ -158,12 +158,14 @@ __device__ __forceinline__ void gemm_rs_bf16_t(const __bf16 *A, int lda, const _
 }
 
 // GELU, tanh form (Hendrycks & Gimpel), for activations that are rounded to
-// BF16 next: tanh(y) = 1 - 2 / (1 + e^{2y}) with the hardware exponential and
-// reciprocal.
+// BF16 next: 0.5 x (1 + tanh(y)) with y = sqrt(2/pi) (x + 0.044715 x^3) is
+// the same function as x * sigma(2y) = x / (1 + 2^u), u = -2 y log2(e),
+// evaluated with the hardware base-2 exponential and reciprocal.
 __device__ __forceinline__ float gelu_tanh_fast(float x) {
-  const float y = 0.7978845608028654f * fmaf(0.044715f * x, x * x, x);
-  const float th = 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + __expf(2.0f * y));
-  return 0.5f * x * (1.0f + th);
+  constexpr float a = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+  constexpr float b = a * 0.044715f;
+  const float u = x * fmaf(b, x * x, a);
+  return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
 }
 
 }  // namespace mil

@@ -69,44 +69,6 @@ static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 =
                   offsetof(PolicyLds, buf) % 16 == 0,
               "align");
 
-// LayerNorm (eps 1e-5) of one 64-wide FP32 row held in LDS, one thread per
-// row: mean, then variance, then the normalised row scaled by gain g and
-// shifted by offset b (both in LDS), each pass re-reading the row (few
-// registers, four partial sums each). out(q, y[8]) receives features 8q..8q+7.
-template <typename Out>
-__device__ __forceinline__ void ln_row(const float *x, const float *g, const float *b, Out out) {
-  const float4 *xp = reinterpret_cast<const float4 *>(x);
-  float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int q = 0; q < kPolD / 4; ++q) {
-    const float4 v = xp[q];
-    s4[0] += v.x;
-    s4[1] += v.y;
-    s4[2] += v.z;
-    s4[3] += v.w;
-  }
-  const float mean = ((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
-  float q4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-  for (int q = 0; q < kPolD / 4; ++q) {
-    const float4 v = xp[q];
-    q4[0] = fmaf(v.x - mean, v.x - mean, q4[0]);
-    q4[1] = fmaf(v.y - mean, v.y - mean, q4[1]);
-    q4[2] = fmaf(v.z - mean, v.z - mean, q4[2]);
-    q4[3] = fmaf(v.w - mean, v.w - mean, q4[3]);
-  }
-  const float inv = rsqrtf(((q4[0] + q4[1]) + (q4[2] + q4[3])) * (1.0f / kPolD) + 1e-5f);
-#pragma unroll
-  for (int q = 0; q < kPolD / 8; ++q) {
-    const float4 v0 = xp[2 * q], v1 = xp[2 * q + 1];
-    const float xv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-    float y[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) y[c] = fmaf((xv[c] - mean) * inv, g[8 * q + c], b[8 * q + c]);
-    out(q, y);
-  }
-}
-
 // Sum over the four lanes of a quad (DPP butterfly, lanes xor 1 then xor 2);
 // every lane of the quad ends with the same value.
 __device__ __forceinline__ float quad_sum(float v) {
@@ -430,26 +392,53 @@ policy_kernel(PolicyArgs a) {
         __syncthreads();
       }
     }
-    // ---- head on the self token of each agent: final LayerNorm (one thread
-    // per agent, into a scratch copy in the QKV buffer), then one thread per
-    // (agent, logit)
+    // ---- head on the self token of each agent: final LayerNorm (four lanes
+    // per agent, into a scratch copy in the QKV buffer), then four lanes per
+    // (agent, logit), each a 16-feature partial dot product
     {
       const float *fp = L.prm + kSmFinal;
       float(*sv)[kPolD + 4] = reinterpret_cast<float(*)[kPolD + 4]>(L.buf);
-      for (int al = tid; al < at; al += nthr) {
-        ln_row(&L.h[al * nt][0], fp + kPolLnfG, fp + kPolLnfB, [&](int q, const float(&y)[8]) {
+      const int q = tid & 3;
+      for (int al = tid >> 2; al < at; al += nthr >> 2) {  // al is uniform on a quad
+        const float4 *xp = reinterpret_cast<const float4 *>(&L.h[al * nt][16 * q]);
+        float x[16];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) sv[al][8 * q + c] = y[c];
-        });
+        for (int i = 0; i < 4; ++i) {
+          const float4 v = xp[i];
+          x[4 * i] = v.x;
+          x[4 * i + 1] = v.y;
+          x[4 * i + 2] = v.z;
+          x[4 * i + 3] = v.w;
+        }
+        float sum = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sum += x[c];
+        const float mean = quad_sum(sum) * (1.0f / kPolD);
+        float sq = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) sq = fmaf(x[c] - mean, x[c] - mean, sq);
+        const float inv = rsqrtf(quad_sum(sq) * (1.0f / kPolD) + 1e-5f);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          sv[al][16 * q + c] =
+              fmaf((x[c] - mean) * inv, fp[kPolLnfG + 16 * q + c], fp[kPolLnfB + 16 * q + c]);
       }
       __syncthreads();
-      for (int e = tid; e < at * kPolActions; e += nthr) {
+      for (int e = tid >> 2; e < at * kPolActions; e += nthr >> 2) {
         const int al = e / kPolActions, k = e % kPolActions;
-        const float *w = fp + kPolWh + k * kPolD;
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        const float4 *w = reinterpret_cast<const float4 *>(fp + kPolWh + k * kPolD + 16 * q);
+        const float4 *v = reinterpret_cast<const float4 *>(&sv[al][16 * q]);
+        float acc = 0.0f;
 #pragma unroll
-        for (int d = 0; d < kPolD; ++d) acc[d & 3] = fmaf(w[d], sv[al][d], acc[d & 3]);
-        L.logits[al][k] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + fp[kPolBh + k];
+        for (int i = 0; i < 4; ++i) {
+          const float4 wv = w[i], xv = v[i];
+          acc = fmaf(wv.x, xv.x, acc);
+          acc = fmaf(wv.y, xv.y, acc);
+          acc = fmaf(wv.z, xv.z, acc);
+          acc = fmaf(wv.w, xv.w, acc);
+        }
+        acc = quad_sum(acc);
+        if (q == 0) L.logits[al][k] = acc + fp[kPolBh + k];
       }
     }
     __syncthreads();
