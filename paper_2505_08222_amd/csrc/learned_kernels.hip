@@ -421,11 +421,12 @@ forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Inference: persistent blocks (two per CU) loop over tiles of 64 windows.
+// Inference: persistent blocks (as many as fit a CU) loop over tiles of 64 windows.
 // The tile's windows (contiguous in memory) are staged in LDS with coalesced
-// loads; features, the two hidden layers (MFMA, weight fragments from L2 in
-// registers), the output layer, the decode (network bearing, distance fitted
-// to the ranges) and the residual test all read that copy. Windows failing the test (or with
+// loads; features, the two hidden layers (MFMA; both layers' weight fragments
+// are loaded into registers once per block), the output layer (fused into the
+// second layer's epilogue), the decode (network bearing, distance fitted to
+// the ranges) and the residual test all read that copy. Windows failing the test (or with
 // missing entries) are appended, one atomic per wavefront, to a list that
 // the fallback kernel solves exactly.
 // ---------------------------------------------------------------------------
@@ -437,16 +438,16 @@ struct InferLds {
   float b1[kHidden], b2[kHidden], b3[4];  // b3 padded: keeps x 16-byte aligned
   __bf16 x[64][kIn + 8];
   __bf16 h1[64][kHidden + 8];
-  __bf16 h2[64][kHidden + 8];
   float frame[64][5];
-  float ypart[64][2][4];
+  float ypart[64][4][2];  // output layer partial sums: [window][wavefront][output]
   int ok[64];
 };
 
 static_assert(offsetof(InferLds, x) % 16 == 0, "MFMA operands need 16-byte rows");
-static_assert(offsetof(InferLds, h1) % 16 == 0 && offsetof(InferLds, h2) % 16 == 0,
-              "MFMA operands need 16-byte rows");
-static_assert(sizeof(InferLds) <= 80 * 1024, "two inference blocks per CU");
+static_assert(offsetof(InferLds, h1) % 16 == 0 && offsetof(InferLds, b1) % 16 == 0 &&
+                  offsetof(InferLds, b2) % 16 == 0 && offsetof(InferLds, w3) % 16 == 0,
+              "MFMA operands and float4 parameter reads need 16-byte alignment");
+static_assert(sizeof(InferLds) <= 52 * 1024, "three inference blocks per CU");
 
 __global__ void __launch_bounds__(256)
 infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *__restrict__ th,
@@ -463,6 +464,11 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
     L.b2[e] = th[kOffB2 + e];
   }
   if (tid < 2) L.b3[tid] = th[kOffB3 + tid];
+  // both hidden layers' weight fragments stay in registers for every tile
+  BFrag<kIn, kHidden> f1;
+  BFrag<kHidden, kHidden> f2;
+  load_bfrag(f1, w1g, kLdIn);
+  load_bfrag(f2, w2g, kLdH);
   const int64_t ntiles = (N + 63) / 64;
   const int wlen = W * 3;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -489,13 +495,10 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
         bad += (r == r) ? 0.f : 1.f;
         mr += r - r0;
       }
-#pragma unroll
-      for (int m = 1; m <= 2; m <<= 1) {
-        mx += __shfl_xor(mx, m);
-        my += __shfl_xor(my, m);
-        mr += __shfl_xor(mr, m);
-        bad += __shfl_xor(bad, m);
-      }
+      mx = quad_sum(mx);
+      my = quad_sum(my);
+      mr = quad_sum(mr);
+      bad = quad_sum(bad);
       const float invw = 1.0f / (float)W;
       mx *= invw;
       my *= invw;
@@ -525,25 +528,55 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       }
     }
     __syncthreads();
-    gemm_rs_bf16<kIn, kHidden>(&L.x[0][0], kIn + 8, w1g, kLdIn, 64, [&](int m, int n, float v) {
-      L.h1[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b1[n]));
-    });
+    gemm_rs_bf16_tf<kIn, kHidden>(&L.x[0][0], kIn + 8, f1, 64,
+                                  [&](int m, int n, const floatx4 &v) {
+                                    const float4 b = *reinterpret_cast<const float4 *>(&L.b1[n]);
+                                    const bf16x4 h = {__float2bfloat16(gelu_tanh_fast(v[0] + b.x)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[1] + b.y)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[2] + b.z)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[3] + b.w))};
+                                    *reinterpret_cast<bf16x4 *>(&L.h1[m][n]) = h;
+                                  });
     __syncthreads();
-    gemm_rs_bf16<kHidden, kHidden>(&L.h1[0][0], kHidden + 8, w2g, kLdH, 64,
-                          [&](int m, int n, float v) {
-                            L.h2[m][n] = __float2bfloat16(gelu_tanh_fast(v + L.b2[n]));
-                          });
-    __syncthreads();
-    {  // layer 3: four threads per (window, output), 32 inputs each
-      const int s = tid >> 2, part = tid & 3;
-      float acc[2] = {0.0f, 0.0f};
-      for (int i = part * 32; i < part * 32 + 32; ++i) {
-        const float h = __bfloat162float(L.h2[s][i]);
-        acc[0] += L.w3[0][i] * h;
-        acc[1] += L.w3[1][i] * h;
+    // second hidden layer and the output layer together: each lane rounds its
+    // four GELU outputs to BF16 (the activation precision) and takes their
+    // part of both output dot products; the four lanes of a row, then the four
+    // wavefronts (fixed order, in the decode) complete them
+    {
+      const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kg = lane >> 4;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 a[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          a[ks] = *reinterpret_cast<const bf16x8 *>(&L.h1[16 * mt + row][ks * 32 + 8 * kg]);
+        float y0 = 0.0f, y1 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f2.v[c][ks], a[ks], acc, 0, 0, 0);
+          const int n = ((wave + 4 * c) << 4) + 4 * kg;
+          const float4 b = *reinterpret_cast<const float4 *>(&L.b2[n]);
+          const float4 u0 = *reinterpret_cast<const float4 *>(&L.w3[0][n]);
+          const float4 u1 = *reinterpret_cast<const float4 *>(&L.w3[1][n]);
+          const float bb[4] = {b.x, b.y, b.z, b.w}, w0[4] = {u0.x, u0.y, u0.z, u0.w},
+                      w1[4] = {u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float h = __bfloat162float(__float2bfloat16(gelu_tanh_fast(acc[j] + bb[j])));
+            y0 = fmaf(w0[j], h, y0);
+            y1 = fmaf(w1[j], h, y1);
+          }
+        }
+        y0 = col_sum4(y0);
+        y1 = col_sum4(y1);
+        if (kg == 0) {
+          L.ypart[16 * mt + row][wave][0] = y0;
+          L.ypart[16 * mt + row][wave][1] = y1;
+        }
       }
-      L.ypart[s][0][part] = acc[0];
-      L.ypart[s][1][part] = acc[1];
     }
     __syncthreads();
     {  // decode, distance fit and residual test: four threads per window
@@ -552,75 +585,78 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
       const int64_t n = s0 + sw;
       const float *fr = L.frame[sw];
       const float *w = L.win + (live ? sw : 0) * wlen;
-      auto sum4 = [](float v) {
-        v += __shfl_xor(v, 1);
-        return v + __shfl_xor(v, 2);
-      };
-      const float y0 = L.b3[0] + ((L.ypart[sw][0][0] + L.ypart[sw][0][1]) +
-                                  (L.ypart[sw][0][2] + L.ypart[sw][0][3]));
-      const float y1 = L.b3[1] + ((L.ypart[sw][1][0] + L.ypart[sw][1][1]) +
-                                  (L.ypart[sw][1][2] + L.ypart[sw][1][3]));
+      auto sum4 = [](float v) { return quad_sum(v); };
+      const float y0 = L.b3[0] + ((L.ypart[sw][0][0] + L.ypart[sw][1][0]) +
+                                  (L.ypart[sw][2][0] + L.ypart[sw][3][0]));
+      const float y1 = L.b3[1] + ((L.ypart[sw][0][1] + L.ypart[sw][1][1]) +
+                                  (L.ypart[sw][2][1] + L.ypart[sw][3][1]));
       const float ux = fr[4] * y0, uy = fr[4] * y1;
       float px = fr[0] + fr[2] * ux - fr[3] * uy;
       float py = fr[1] + fr[3] * ux + fr[2] * uy;
       const bool ok = live && L.ok[sw];
       // the network fixes the bearing from the centroid; the distance along
       // it is fitted to the window's ranges (Gauss-Newton on d, a step kept
-      // only if the squared residual falls)
+      // only if the squared residual falls). A rejected step would be
+      // proposed again from the same point, so the fit stops there, and one
+      // pass per point gives the residual, its derivative and the
+      // curvature: the residual of the last kept point is the test's.
       float ex = px - fr[0], ey = py - fr[1];
-      float d = sqrtf(fmaf(ex, ex, ey * ey));
+      float d = __builtin_amdgcn_sqrtf(fmaf(ex, ex, ey * ey));
       const bool fit = ok && d > 0.0f;  // the same for the window's four threads
       if (fit) {
-        ex /= d;
-        ey /= d;
+        const float inv = __builtin_amdgcn_rcpf(d);
+        ex *= inv;
+        ey *= inv;
       }
-      for (int it = 0; it < kRefineIters; ++it) {
-        float gs = 0.0f, hs = 0.0f, j0 = 0.0f;
-        if (fit) {
-          for (int k = part; k < W; k += 4) {
-            const float dx = fmaf(d, ex, fr[0]) - w[3 * k], dy = fmaf(d, ey, fr[1]) - w[3 * k + 1];
-            const float dist = sqrtf(fmaf(dx, dx, dy * dy));
-            const float rho = dist - w[3 * k + 2];
-            j0 = fmaf(rho, rho, j0);
-            if (dist > 0.0f) {
-              const float jd = fmaf(dx, ex, dy * ey) / dist;
-              gs = fmaf(jd, rho, gs);
-              hs = fmaf(jd, jd, hs);
-            }
+      // (sum of squared residuals, their derivative / 2, Gauss-Newton
+      // curvature) at distance dd along the bearing, over the whole window
+      auto eval = [&](float dd, float &j, float &g, float &h) {
+        j = 0.0f;
+        g = 0.0f;
+        h = 0.0f;
+        for (int k = part; k < W; k += 4) {
+          const float dx = fmaf(dd, ex, fr[0]) - w[3 * k], dy = fmaf(dd, ey, fr[1]) - w[3 * k + 1];
+          const float dist = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+          const float rho = dist - w[3 * k + 2];
+          j = fmaf(rho, rho, j);
+          if (dist > 0.0f) {
+            const float jd = fmaf(dx, ex, dy * ey) * __builtin_amdgcn_rcpf(dist);
+            g = fmaf(jd, rho, g);
+            h = fmaf(jd, jd, h);
           }
         }
-        gs = sum4(gs);
-        hs = sum4(hs);
-        j0 = sum4(j0);
-        const bool step_ok = fit && hs > 0.0f;
-        const float dn = step_ok ? d - gs / hs : d;
-        float j1 = 0.0f;
-        if (step_ok) {
-          for (int k = part; k < W; k += 4) {
-            const float dx = fmaf(dn, ex, fr[0]) - w[3 * k], dy = fmaf(dn, ey, fr[1]) - w[3 * k + 1];
-            const float rho = sqrtf(fmaf(dx, dx, dy * dy)) - w[3 * k + 2];
-            j1 = fmaf(rho, rho, j1);
-          }
-        }
-        j1 = sum4(j1);
-        if (step_ok && j1 < j0) d = dn;
-      }
+        j = sum4(j);
+        g = sum4(g);
+        h = sum4(h);
+      };
+      float acc = 0.0f;
       if (fit) {
+        float j, g, h;
+        eval(d, j, g, h);
+        for (int it = 0; it < kRefineIters && h > 0.0f; ++it) {
+          const float dn = d - g * __builtin_amdgcn_rcpf(h);
+          float j1, g1, h1;
+          eval(dn, j1, g1, h1);
+          if (!(j1 < j)) break;
+          d = dn;
+          j = j1;
+          g = g1;
+          h = h1;
+        }
         px = fmaf(d, ex, fr[0]);
         py = fmaf(d, ey, fr[1]);
-      }
-      float acc = 0.0f;
-      if (ok) {
+        acc = j;
+      } else if (ok) {  // the network's point at the centroid itself: no bearing
         for (int k = part; k < W; k += 4) {
           const float dx = px - w[3 * k], dy = py - w[3 * k + 1];
-          const float res = sqrtf(dx * dx + dy * dy) - w[3 * k + 2];
-          acc += res * res;
+          const float res = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) - w[3 * k + 2];
+          acc = fmaf(res, res, acc);
         }
+        acc = sum4(acc);
       }
-      acc = sum4(acc);
       bool accept = false, fail = false;
       if (live && part == 0) {
-        accept = ok && sqrtf(acc / (float)W) <= k_sigma * sigma[n];
+        accept = ok && __builtin_amdgcn_sqrtf(acc * (1.0f / (float)W)) <= k_sigma * sigma[n];
         if (accept) {
           out[2 * n] = px;
           out[2 * n + 1] = py;
@@ -804,7 +840,14 @@ int launch_infer(const float *win, int64_t N, int32_t W, const float *th, const 
   if (allow_lds((const void *)infer_kernel, sizeof(InferLds))) return -1;
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(1), 0, st, fb_count);
   const int64_t ntiles = (N + 63) / 64;
-  const int64_t slots = 2 * (int64_t)num_cus;  // two resident blocks per CU
+  static int per_cu = 0;  // resident blocks per CU (registers and LDS decide)
+  if (per_cu == 0) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)infer_kernel, 256,
+                                                     sizeof(InferLds)) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 2;
+  }
+  const int64_t slots = (int64_t)per_cu * num_cus;
   const unsigned grid = (unsigned)(ntiles < slots ? ntiles : slots);
   hipLaunchKernelGGL(infer_kernel, dim3(grid), dim3(256), sizeof(InferLds), st, win, N, W, th, w1,
                      w2, sigma, k_sigma, out, flag, fb_count, fb_list);

@@ -157,6 +157,25 @@ __device__ __forceinline__ void gemm_rs_bf16_t(const __bf16 *A, int lda, const _
   }
 }
 
+// Sum over the four lanes of a quad (DPP butterfly, lanes xor 1 then xor 2);
+// every lane of the quad ends with the same value. The whole quad must be
+// active.
+__device__ __forceinline__ float quad_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  return v;
+}
+
+// Sum over the four lanes l % 16 + 16 g (g = 0..3) of a wavefront: each
+// cross-row swap leaves a lane's own value in one result and its partner's in
+// the other, and the sum is symmetric.
+__device__ __forceinline__ float col_sum4(float v) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+  v = __int_as_float(r[0]) + __int_as_float(r[1]);
+  r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+
 // GELU, tanh form (Hendrycks & Gimpel), for activations that are rounded to
 // BF16 next: 0.5 x (1 + tanh(y)) with y = sqrt(2/pi) (x + 0.044715 x^3) is
 // the same function as x * sigma(2y) = x / (1 + 2^u), u = -2 y log2(e),

@@ -69,14 +69,6 @@ static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 =
                   offsetof(PolicyLds, buf) % 16 == 0,
               "align");
 
-// Sum over the four lanes of a quad (DPP butterfly, lanes xor 1 then xor 2);
-// every lane of the quad ends with the same value.
-__device__ __forceinline__ float quad_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  return v;
-}
-
 // LayerNorm (eps 1e-5) of every row of the residual stream into xn (BF16):
 // four lanes per row, 16 features each held in registers, quad sums for the
 // mean and the variance; 64 rows per pass of the block's 256 threads.
