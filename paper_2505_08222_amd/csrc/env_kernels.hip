@@ -326,379 +326,452 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   int unit = dyn ? take_unit(sp->queue, lane)
                  : __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
   while (unit < units) {
-  const int cix = unit / num_waves;
-  const int wave = unit - cix * num_waves;
-  uint32_t status = 0;
-  if (cix > 0 && !wait_chunks(sp->queue + 1 + wave, cix, lane) && lane == 0)
-    status |= kStatusSchedule;
-  const int s_begin = cix * span;
-  const int s_end = min(T, s_begin + span);
-  // prologue and epilogue only (reloaded after the loop); a copy, so that the
-  // device-coherent accesses below do not make the compiler re-read each field
-  const DevState s = *sp;
-  const ClassInfo C = s.classes[s.wave_class[wave]];
-  const int na = C.na, nt = C.nt;
-  const int lpe = na * G;
-  const int epw = 64 / lpe;
-  const int el = lane / lpe;
-  const int r = lane - el * lpe;
-  const int i = r / G;
-  const int g = r - i * G;
-  const int64_t ce_raw = (int64_t)(wave - C.wave0) * epw + el;
-  const bool active = (el < epw) && (ce_raw < C.nenv);
-  const int64_t ce = active ? ce_raw : 0;
-  const int64_t e = C.env0 + ce;
-  const int64_t aidx = C.aoff0 + ce * na + i;
-  const int64_t tbase = C.toff0 + ce * nt;
-  const int64_t pbase = C.poff0 + ce * na * nt + (int64_t)i * nt;
-  const int64_t kbase = C.koff0 + ce * na * (na + nt) + (int64_t)i * (na + nt);
-  const int64_t gbase = C.aoff0 + C.toff0 + ce * (na + nt);
-  const int base_lane = el * lpe;
-  const uint32_t env_id = s.env_id[e];
-  const float sig_r = s.sigma[e];
-  const int W = p.window;
-  const uint32_t c3dyn = (episode << 4) | kPurposeDynamics;
-  const uint32_t c3meas = (episode << 4) | kPurposeMeasure;
-  const float vdt = p.agent_speed * p.dt;
-  const int nB = (nt + 1) >> 1;
-  const double tau = (double)p.tau;
-  const double invW = 1.0 / (double)W;
-  const float inv_span = 1.0f / (p.eps_max - p.eps_min);
-  const float comm2 = p.comm_range * p.comm_range, dsafe2 = p.d_safe * p.d_safe;
-  const float inv_nt = 1.0f / (float)nt;
-  const float kInf = __int_as_float(0x7f800000);
-  const float kNaN = __int_as_float(0x7fc00000);
-  float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
-  // staging of the wavefront's observation tokens (offsets only; the type
-  // columns follow from the token's position) and masks, in output order
-  float2 *st_xy = reinterpret_cast<float2 *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT) +
-                  (size_t)wib * kStageTok<S>;
-  uint8_t *st_m = reinterpret_cast<uint8_t *>(reinterpret_cast<float2 *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT) +
-                                              (size_t)(blockDim.x >> 6) * kStageTok<S>) +
-                  (size_t)wib * kStageTok<S>;
-  const int ntok = na + nt;
-  const int agent_w = el * na + i;  // agent index inside the wavefront
-  const int64_t env_left = C.nenv - (int64_t)(wave - C.wave0) * epw;  // >= 1 for a live wave
-  const int64_t nenv_w = env_left < epw ? env_left : epw;
-  const int ntok_w = (int)nenv_w * na * ntok;  // tokens of the wavefront's active agents
-  const int64_t kbase_w = C.koff0 + (int64_t)(wave - C.wave0) * epw * na * ntok;
-  const int m_lane0 = lane % ntok, m_step = 64 % ntok;  // token positions for the block copy
+    const int cix = unit / num_waves;
+    const int wave = unit - cix * num_waves;
+    uint32_t status = 0;
+    if (cix > 0 && !wait_chunks(sp->queue + 1 + wave, cix, lane) && lane == 0)
+      status |= kStatusSchedule;
+    const int s_begin = cix * span;
+    const int s_end = min(T, s_begin + span);
+    // prologue and epilogue only (reloaded after the loop); a copy, so that the
+    // device-coherent accesses below do not make the compiler re-read each field
+    const DevState s = *sp;
+    const ClassInfo C = s.classes[s.wave_class[wave]];
+    const int na = C.na, nt = C.nt;
+    const int lpe = na * G;
+    const int epw = 64 / lpe;
+    const int el = lane / lpe;
+    const int r = lane - el * lpe;
+    const int i = r / G;
+    const int g = r - i * G;
+    const int64_t ce_raw = (int64_t)(wave - C.wave0) * epw + el;
+    const bool active = (el < epw) && (ce_raw < C.nenv);
+    const int64_t ce = active ? ce_raw : 0;
+    const int64_t e = C.env0 + ce;
+    const int64_t aidx = C.aoff0 + ce * na + i;
+    const int64_t tbase = C.toff0 + ce * nt;
+    const int64_t pbase = C.poff0 + ce * na * nt + (int64_t)i * nt;
+    const int64_t kbase = C.koff0 + ce * na * (na + nt) + (int64_t)i * (na + nt);
+    const int64_t gbase = C.aoff0 + C.toff0 + ce * (na + nt);
+    const int base_lane = el * lpe;
+    const uint32_t env_id = s.env_id[e];
+    const float sig_r = s.sigma[e];
+    const int W = p.window;
+    const uint32_t c3dyn = (episode << 4) | kPurposeDynamics;
+    const uint32_t c3meas = (episode << 4) | kPurposeMeasure;
+    const float vdt = p.agent_speed * p.dt;
+    const int nB = (nt + 1) >> 1;
+    const double tau = (double)p.tau;
+    const double invW = 1.0 / (double)W;
+    const float inv_span = 1.0f / (p.eps_max - p.eps_min);
+    const float comm2 = p.comm_range * p.comm_range, dsafe2 = p.d_safe * p.d_safe;
+    const float inv_nt = 1.0f / (float)nt;
+    const float kInf = __int_as_float(0x7f800000);
+    const float kNaN = __int_as_float(0x7fc00000);
+    float4 *tl = lds_targets + (wib * 64 + (el < 64 ? el : 63)) * MT;  // this env's targets
+    // staging of the wavefront's observation tokens (offsets only; the type
+    // columns follow from the token's position) and masks, in output order
+    float2 *const st_base =
+        reinterpret_cast<float2 *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT);
+    float2 *st_xy = st_base + (size_t)wib * kStageTok<S>;
+    uint8_t *st_m = reinterpret_cast<uint8_t *>(st_base + (size_t)(blockDim.x >> 6) * kStageTok<S>) +
+                    (size_t)wib * kStageTok<S>;
+    const int ntok = na + nt;
+    const int agent_w = el * na + i;  // agent index inside the wavefront
+    const int64_t env_left = C.nenv - (int64_t)(wave - C.wave0) * epw;  // >= 1 for a live wave
+    const int64_t nenv_w = env_left < epw ? env_left : epw;
+    const int ntok_w = (int)nenv_w * na * ntok;  // tokens of the wavefront's active agents
+    const int64_t kbase_w = C.koff0 + (int64_t)(wave - C.wave0) * epw * na * ntok;
+    const int m_lane0 = lane % ntok, m_step = 64 % ntok;  // token positions for the block copy
 
-  // ---- load state: targets of the env into LDS (each lane its own blocks)
-  for (int q = r; q < nB; q += lpe) {
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-      const int j = 2 * q + m;
-      if (j < nt) {
-        const int64_t idx = tbase + j;
-        tl[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
-                            ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
-      }
-    }
-  }
-  float ax = ld_st(&s.ax[aidx], dyn), ay = ld_st(&s.ay[aidx], dyn);
-  float apsi = ld_st(&s.apsi[aidx], dyn);
-  float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
-  uint32_t evb = 0;
-#pragma unroll
-  for (int k = 0; k < WC; ++k) {
-    hx[k] = (k < W) ? ld_st(&s.hx[(int64_t)k * s.A + aidx], dyn) : 0.0f;
-    hy[k] = (k < W) ? ld_st(&s.hy[(int64_t)k * s.A + aidx], dyn) : 0.0f;
-  }
-#pragma unroll
-  for (int sl = 0; sl < NPL; ++sl) {
-    const int j = g + G * sl;
-    const int64_t pidx = pbase + (j < nt ? j : 0);
-#pragma unroll
-    for (int k = 0; k < WC; ++k)
-      hr[sl][k] = (k < W) ? ld_st(&s.hr[(int64_t)k * s.P + pidx], dyn) : 0.0f;
-    ex[sl] = ld_st(&s.ex[pidx], dyn);
-    ey[sl] = ld_st(&s.ey[pidx], dyn);
-    if (j < nt && ld_st(&s.ev[pidx], dyn)) evb |= 1u << sl;
-  }
-  double acc_rew = 0.0, acc_err = 0.0, acc_err2 = 0.0;
-  int acc_cnt = 0, acc_crash = 0;
-  if (active && r == 0) {
-    acc_rew = ld_st(&s.macc[3 * e], dyn);
-    acc_err = ld_st(&s.macc[3 * e + 1], dyn);
-    acc_err2 = ld_st(&s.macc[3 * e + 2], dyn);
-    acc_cnt = ld_st(&s.miacc[2 * e], dyn);
-    acc_crash = ld_st(&s.miacc[2 * e + 1], dyn);
-  }
-  wave_lds_fence();  // the target slab is complete
-
-  for (int step = s_begin; step < s_end; ++step) {
-    const uint32_t t = (uint32_t)(t0 + step);
-
-    // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
-    const u32x4 xa = draw(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
-    int act;
-    if (FULL && actions) {
-      act = actions[(int64_t)step * o.A + aidx];
-      if (act < 0 || act >= p.n_actions) {
-        act = -1;
-        if (active) status |= kStatusBadAction;
-      }
-    } else {
-      act = (int)choice(xa.x, (uint32_t)p.n_actions);
-    }
-    if (move) {
-      float za, zb;
-      normal2(xa.y, xa.z, za, zb);
-      const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
-      apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
-      float sn, cs;
-      sincos_rad(apsi, sn, cs);
-      ax = fmaf(vdt, cs, ax);
-      ay = fmaf(vdt, sn, ay);
-    }
-    const bool comm_ok = FULL ? !(u01(xa.w) < p.comm_loss_p) : true;
-
-    // ---- targets owned by this lane (blocks of two): heading random walk
-    for (int q = r; move && q < nB; q += lpe) {
-      const u32x4 xt =
-          draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
-      float zt[2];
-      normal2(xt.x, xt.y, zt[0], zt[1]);
+    // ---- load state: targets of the env into LDS (each lane its own blocks)
+    for (int q = r; q < nB; q += lpe) {
 #pragma unroll
       for (int m = 0; m < 2; ++m) {
         const int j = 2 * q + m;
         if (j < nt) {
-          float4 tg = tl[j];
-          tg.z = wrap_angle(tg.z + p.sig_t * zt[m]);
-          float sn, cs;
-          sincos_rad(tg.z, sn, cs);
-          const float step_len = tg.w * p.dt;
-          tg.x = fmaf(step_len, cs, tg.x);
-          tg.y = fmaf(step_len, sn, tg.y);
-          tl[j] = tg;
+          const int64_t idx = tbase + j;
+          tl[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
+                              ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
         }
       }
     }
-    wave_lds_fence();
-    float tpx[MT], tpy[MT];
+    float ax = ld_st(&s.ax[aidx], dyn), ay = ld_st(&s.ay[aidx], dyn);
+    float apsi = ld_st(&s.apsi[aidx], dyn);
+    float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
+    uint32_t evb = 0;
 #pragma unroll
-    for (int j = 0; j < MT; ++j) {
-      tpx[j] = 0.0f;
-      tpy[j] = 0.0f;
-      if (j < nt) {
-        const float4 v = tl[j];
-        tpx[j] = v.x;
-        tpy[j] = v.y;
-      }
+    for (int k = 0; k < WC; ++k) {
+      hx[k] = (k < W) ? ld_st(&s.hx[(int64_t)k * s.A + aidx], dyn) : 0.0f;
+      hy[k] = (k < W) ? ld_st(&s.hy[(int64_t)k * s.A + aidx], dyn) : 0.0f;
     }
-    wave_lds_fence();  // every lane has read before next step's owners write
-
-    if (move) {
-    // ---- noisy ranges after the move; missing beyond the detection range
-      float rnew[NPL];
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) rnew[sl] = kNaN;
-#pragma unroll
-      for (int q4 = 0; q4 < NQ; ++q4) {
-        if (4 * q4 < nt) {
-          const u32x4 xr = draw(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4, c3meas,
-                                p.key0, p.key1);
-          float zr[4];
-          normal2(xr.x, xr.y, zr[0], zr[1]);
-          normal2(xr.z, xr.w, zr[2], zr[3]);
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const int j = 4 * q4 + m;
-            if (j < MT && j < nt && (j % G) == g) {
-              const float dist = norm2(ax - tpx[j], ay - tpy[j]);
-              const float rr = fmaf(sig_r, zr[m], dist);
-              rnew[j / G] = (!FULL || dist <= p.det_range) ? rr : kNaN;
-            }
-          }
-        }
-      }
-  
-      // ---- range history: entry 0 is the newest
-#pragma unroll
-      for (int k = WC - 1; k > 0; --k) {
-        hx[k] = hx[k - 1];
-        hy[k] = hy[k - 1];
-#pragma unroll
-        for (int sl = 0; sl < NPL; ++sl) hr[sl][k] = hr[sl][k - 1];
-      }
-      hx[0] = ax;
-      hy[0] = ay;
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
-    }
-    if (!observe) continue;  // phase 1 ends here: the estimator runs next
-    const int filled = min((int)t + 1, W);
-
-    // ---- trackers (Sec. II-A): linearised LS about the centroid of the
-    // agent's window, FP64. With every entry present and no refinement the
-    // agent's 2x2 matrix S = sum u u^T and G = sum u |u|^2 are shared by its
-    // trackers and each tracker only adds g = G - sum u_k r_k^2 (the r-bar^2
-    // term of the centred form vanishes because sum u_k = 0). Other trackers
-    // take the general path below.
-    uint32_t pending = 0;
-    if (FULL && ext.phase == 2 && filled == W) {
-      // estimates from the external estimator (window full)
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) {
-        const int j = g + G * sl;
-        if (j < nt) {
-          const int64_t pidx = pbase + j;
-          if (ext.flag[pidx] != 2) {
-            ex[sl] = ext.est[2 * pidx];
-            ey[sl] = ext.est[2 * pidx + 1];
-            evb |= 1u << sl;
-          }
-        }
-      }
-    } else if (filled >= 3) {
-      double mx = 0.0, my = 0.0;
-#pragma unroll
-      for (int k = 0; k < WC; ++k)
-        if (k < filled) {
-          mx += (double)hx[k];
-          my += (double)hy[k];
-        }
-      const double invn = (filled == W) ? invW : 1.0 / (double)filled;  // filled is uniform
-      mx *= invn;
-      my *= invn;
-      bool full[NPL];
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) full[sl] = (g + G * sl) < nt;
-      double sxx = 0.0, sxy = 0.0, syy = 0.0, gx[NPL], gy[NPL];
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) {
-        gx[sl] = 0.0;
-        gy[sl] = 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < WC; ++k) {
-        if (k < filled) {
-          const double ux = (double)hx[k] - mx, uy = (double)hy[k] - my;
-          const double nu = fma(ux, ux, uy * uy);
-          sxx = fma(ux, ux, sxx);
-          sxy = fma(ux, uy, sxy);
-          syy = fma(uy, uy, syy);
-#pragma unroll
-          for (int sl = 0; sl < NPL; ++sl) {
-            const float rk = hr[sl][k];
-            // lean form: every range is finite while the state is (checked
-            // on the estimate below instead of on each entry)
-            if constexpr (FULL) full[sl] = full[sl] && (rk == rk);
-            const double rr = (double)rk;
-            const double c = fma(-rr, rr, nu);
-            gx[sl] = fma(ux, c, gx[sl]);
-            gy[sl] = fma(uy, c, gy[sl]);
-          }
-        }
-      }
-      const double det = fma(sxx, syy, -sxy * sxy), tr = sxx + syy;
-      const bool agent_ok = det > tau * tr * tr;
-      const double hdet = agent_ok ? 0.5 * recip(det) : 0.0;
-#pragma unroll
-      for (int sl = 0; sl < NPL; ++sl) {
-        const int j = g + G * sl;
-        if (j < nt) {
-          if (full[sl] && (!FULL || p.gn_iters == 0)) {
-            if (agent_ok) {
-              const float nx = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
-              const float ny = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
-              if (FULL || (nx == nx && ny == ny)) {
-                ex[sl] = nx;
-                ey[sl] = ny;
-                evb |= 1u << sl;
-              } else if (active) {
-                status |= kStatusNonFinite;  // lean form: hold, flag the broken state
-              }
-            }
-          } else if (FULL) {
-            pending |= 1u << sl;
-          } else if (active) {
-            status |= kStatusNonFinite;  // lean form: every range is finite unless the state is not
-          }
-        }
-      }
-    }
-    // general path: missing entries or Gauss-Newton refinement (one copy of
-    // the solver, the tracker's history selected into a scratch row)
-    while (FULL && pending) {
-      const int sl = __builtin_ctz(pending);
-      pending &= pending - 1;
-      float row[WC];
-#pragma unroll
-      for (int k = 0; k < WC; ++k) {
-        float v = hr[0][k];
-#pragma unroll
-        for (int q = 1; q < NPL; ++q) v = (sl == q) ? hr[q][k] : v;
-        row[k] = v;
-      }
-      double px, py;
-      if (ls_masked<WC>(hx, hy, row, filled, p.gn_iters, tau, px, py)) {
-#pragma unroll
-        for (int q = 0; q < NPL; ++q)
-          if (sl == q) {
-            ex[q] = (float)px;
-            ey[q] = (float)py;
-          }
-        evb |= 1u << sl;
-      }
-    }
-
-    // ---- tracking error of this lane's trackers
-    float errp[NPL];
 #pragma unroll
     for (int sl = 0; sl < NPL; ++sl) {
       const int j = g + G * sl;
-      errp[sl] = kInf;
-      if (j < nt && ((evb >> sl) & 1u)) {
-        errp[sl] = norm2(ex[sl] - pick<G>(tpx, g, sl), ey[sl] - pick<G>(tpy, g, sl));
-      }
+      const int64_t pidx = pbase + (j < nt ? j : 0);
+#pragma unroll
+      for (int k = 0; k < WC; ++k)
+        hr[sl][k] = (k < W) ? ld_st(&s.hr[(int64_t)k * s.P + pidx], dyn) : 0.0f;
+      ex[sl] = ld_st(&s.ex[pidx], dyn);
+      ey[sl] = ld_st(&s.ey[pidx], dyn);
+      if (j < nt && ld_st(&s.ev[pidx], dyn)) evb |= 1u << sl;
     }
-    // ---- team error per target (best tracker), Eq. (1), normalisation
-    float ej[MT];
-    float rsum = 0.0f;
-#pragma unroll
-    for (int j = 0; j < MT; ++j) {
-      float v = kInf;
-      if (j < nt) {
-#pragma unroll
-        for (int k = 0; k < MA; ++k) {
-          if (k < na) v = fminf(v, __shfl(errp[j / G], base_lane + k * G + (j % G)));
-        }
-        rsum += tracking_reward(v, p.eps_min, p.eps_max, inv_span);
-      }
-      ej[j] = v;
+    double acc_rew = 0.0, acc_err = 0.0, acc_err2 = 0.0;
+    int acc_cnt = 0, acc_crash = 0;
+    if (active && r == 0) {
+      acc_rew = ld_st(&s.macc[3 * e], dyn);
+      acc_err = ld_st(&s.macc[3 * e + 1], dyn);
+      acc_err2 = ld_st(&s.macc[3 * e + 2], dyn);
+      acc_cnt = ld_st(&s.miacc[2 * e], dyn);
+      acc_crash = ld_st(&s.miacc[2 * e + 1], dyn);
     }
-    float rew = rsum * inv_nt;
-    // ---- agents' positions and broadcasts; crash penalty
-    float agx[MA], agy[MA];
-    int agc[MA];
-#pragma unroll
-    for (int k = 0; k < MA; ++k) {
-      agx[k] = 0.0f;
-      agy[k] = 0.0f;
-      agc[k] = 0;
-      if (k < na) {
-        const int src = base_lane + k * G;
-        agx[k] = __shfl(ax, src);
-        agy[k] = __shfl(ay, src);
-        agc[k] = FULL ? __shfl((int)comm_ok, src) : 1;
-      }
-    }
-    bool crash = false;
-#pragma unroll
-    for (int k = 0; k < MA; ++k)
-#pragma unroll
-      for (int k2 = k + 1; k2 < MA; ++k2)
-        if (k2 < na) {
-          crash = crash || (sqnorm(agx[k] - agx[k2], agy[k] - agy[k2]) < dsafe2);
-        }
-    if (crash) rew = -1.0f;
-    const bool done = (t + 1u == (uint32_t)p.episode_len);
+    wave_lds_fence();  // the target slab is complete
 
-    // ---- outputs
-    if constexpr (!FULL) {
-      if (active) {
+    for (int step = s_begin; step < s_end; ++step) {
+      const uint32_t t = (uint32_t)(t0 + step);
+
+      // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
+      const u32x4 xa = draw(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
+      int act;
+      if (FULL && actions) {
+        act = actions[(int64_t)step * o.A + aidx];
+        if (act < 0 || act >= p.n_actions) {
+          act = -1;
+          if (active) status |= kStatusBadAction;
+        }
+      } else {
+        act = (int)choice(xa.x, (uint32_t)p.n_actions);
+      }
+      if (move) {
+        float za, zb;
+        normal2(xa.y, xa.z, za, zb);
+        const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
+        apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
+        float sn, cs;
+        sincos_rad(apsi, sn, cs);
+        ax = fmaf(vdt, cs, ax);
+        ay = fmaf(vdt, sn, ay);
+      }
+      const bool comm_ok = FULL ? !(u01(xa.w) < p.comm_loss_p) : true;
+
+      // ---- targets owned by this lane (blocks of two): heading random walk
+      for (int q = r; move && q < nB; q += lpe) {
+        const u32x4 xt =
+            draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
+        float zt[2];
+        normal2(xt.x, xt.y, zt[0], zt[1]);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int j = 2 * q + m;
+          if (j < nt) {
+            float4 tg = tl[j];
+            tg.z = wrap_angle(tg.z + p.sig_t * zt[m]);
+            float sn, cs;
+            sincos_rad(tg.z, sn, cs);
+            const float step_len = tg.w * p.dt;
+            tg.x = fmaf(step_len, cs, tg.x);
+            tg.y = fmaf(step_len, sn, tg.y);
+            tl[j] = tg;
+          }
+        }
+      }
+      wave_lds_fence();
+      float tpx[MT], tpy[MT];
+#pragma unroll
+      for (int j = 0; j < MT; ++j) {
+        tpx[j] = 0.0f;
+        tpy[j] = 0.0f;
+        if (j < nt) {
+          const float4 v = tl[j];
+          tpx[j] = v.x;
+          tpy[j] = v.y;
+        }
+      }
+      wave_lds_fence();  // every lane has read before next step's owners write
+
+      if (move) {
+      // ---- noisy ranges after the move; missing beyond the detection range
+        float rnew[NPL];
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) rnew[sl] = kNaN;
+#pragma unroll
+        for (int q4 = 0; q4 < NQ; ++q4) {
+          if (4 * q4 < nt) {
+            const u32x4 xr = draw(t, env_id, kEntRangeRow + 8u * (uint32_t)i + (uint32_t)q4, c3meas,
+                                  p.key0, p.key1);
+            float zr[4];
+            normal2(xr.x, xr.y, zr[0], zr[1]);
+            normal2(xr.z, xr.w, zr[2], zr[3]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const int j = 4 * q4 + m;
+              if (j < MT && j < nt && (j % G) == g) {
+                const float dist = norm2(ax - tpx[j], ay - tpy[j]);
+                const float rr = fmaf(sig_r, zr[m], dist);
+                rnew[j / G] = (!FULL || dist <= p.det_range) ? rr : kNaN;
+              }
+            }
+          }
+        }
+  
+        // ---- range history: entry 0 is the newest
+#pragma unroll
+        for (int k = WC - 1; k > 0; --k) {
+          hx[k] = hx[k - 1];
+          hy[k] = hy[k - 1];
+#pragma unroll
+          for (int sl = 0; sl < NPL; ++sl) hr[sl][k] = hr[sl][k - 1];
+        }
+        hx[0] = ax;
+        hy[0] = ay;
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
+      }
+      if (!observe) continue;  // phase 1 ends here: the estimator runs next
+      const int filled = min((int)t + 1, W);
+
+      // ---- trackers (Sec. II-A): linearised LS about the centroid of the
+      // agent's window, FP64. With every entry present and no refinement the
+      // agent's 2x2 matrix S = sum u u^T and G = sum u |u|^2 are shared by its
+      // trackers and each tracker only adds g = G - sum u_k r_k^2 (the r-bar^2
+      // term of the centred form vanishes because sum u_k = 0). Other trackers
+      // take the general path below.
+      uint32_t pending = 0;
+      if (FULL && ext.phase == 2 && filled == W) {
+        // estimates from the external estimator (window full)
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt) {
+            const int64_t pidx = pbase + j;
+            if (ext.flag[pidx] != 2) {
+              ex[sl] = ext.est[2 * pidx];
+              ey[sl] = ext.est[2 * pidx + 1];
+              evb |= 1u << sl;
+            }
+          }
+        }
+      } else if (filled >= 3) {
+        double mx = 0.0, my = 0.0;
+#pragma unroll
+        for (int k = 0; k < WC; ++k)
+          if (k < filled) {
+            mx += (double)hx[k];
+            my += (double)hy[k];
+          }
+        const double invn = (filled == W) ? invW : 1.0 / (double)filled;  // filled is uniform
+        mx *= invn;
+        my *= invn;
+        bool full[NPL];
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) full[sl] = (g + G * sl) < nt;
+        double sxx = 0.0, sxy = 0.0, syy = 0.0, gx[NPL], gy[NPL];
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          gx[sl] = 0.0;
+          gy[sl] = 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < WC; ++k) {
+          if (k < filled) {
+            const double ux = (double)hx[k] - mx, uy = (double)hy[k] - my;
+            const double nu = fma(ux, ux, uy * uy);
+            sxx = fma(ux, ux, sxx);
+            sxy = fma(ux, uy, sxy);
+            syy = fma(uy, uy, syy);
+#pragma unroll
+            for (int sl = 0; sl < NPL; ++sl) {
+              const float rk = hr[sl][k];
+              // lean form: every range is finite while the state is (checked
+              // on the estimate below instead of on each entry)
+              if constexpr (FULL) full[sl] = full[sl] && (rk == rk);
+              const double rr = (double)rk;
+              const double c = fma(-rr, rr, nu);
+              gx[sl] = fma(ux, c, gx[sl]);
+              gy[sl] = fma(uy, c, gy[sl]);
+            }
+          }
+        }
+        const double det = fma(sxx, syy, -sxy * sxy), tr = sxx + syy;
+        const bool agent_ok = det > tau * tr * tr;
+        const double hdet = agent_ok ? 0.5 * recip(det) : 0.0;
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt) {
+            if (full[sl] && (!FULL || p.gn_iters == 0)) {
+              if (agent_ok) {
+                const float nx = (float)fma(hdet, fma(syy, gx[sl], -sxy * gy[sl]), mx);
+                const float ny = (float)fma(hdet, fma(sxx, gy[sl], -sxy * gx[sl]), my);
+                if (FULL || (nx == nx && ny == ny)) {
+                  ex[sl] = nx;
+                  ey[sl] = ny;
+                  evb |= 1u << sl;
+                } else if (active) {
+                  status |= kStatusNonFinite;  // lean form: hold, flag the broken state
+                }
+              }
+            } else if (FULL) {
+              pending |= 1u << sl;
+            } else if (active) {
+              status |= kStatusNonFinite;  // lean form: every range is finite unless the state is not
+            }
+          }
+        }
+      }
+      // general path: missing entries or Gauss-Newton refinement (one copy of
+      // the solver, the tracker's history selected into a scratch row)
+      while (FULL && pending) {
+        const int sl = __builtin_ctz(pending);
+        pending &= pending - 1;
+        float row[WC];
+#pragma unroll
+        for (int k = 0; k < WC; ++k) {
+          float v = hr[0][k];
+#pragma unroll
+          for (int q = 1; q < NPL; ++q) v = (sl == q) ? hr[q][k] : v;
+          row[k] = v;
+        }
+        double px, py;
+        if (ls_masked<WC>(hx, hy, row, filled, p.gn_iters, tau, px, py)) {
+#pragma unroll
+          for (int q = 0; q < NPL; ++q)
+            if (sl == q) {
+              ex[q] = (float)px;
+              ey[q] = (float)py;
+            }
+          evb |= 1u << sl;
+        }
+      }
+
+      // ---- tracking error of this lane's trackers
+      float errp[NPL];
+#pragma unroll
+      for (int sl = 0; sl < NPL; ++sl) {
+        const int j = g + G * sl;
+        errp[sl] = kInf;
+        if (j < nt && ((evb >> sl) & 1u)) {
+          errp[sl] = norm2(ex[sl] - pick<G>(tpx, g, sl), ey[sl] - pick<G>(tpy, g, sl));
+        }
+      }
+      // ---- team error per target (best tracker), Eq. (1), normalisation
+      float ej[MT];
+      float rsum = 0.0f;
+#pragma unroll
+      for (int j = 0; j < MT; ++j) {
+        float v = kInf;
+        if (j < nt) {
+#pragma unroll
+          for (int k = 0; k < MA; ++k) {
+            if (k < na) v = fminf(v, __shfl(errp[j / G], base_lane + k * G + (j % G)));
+          }
+          rsum += tracking_reward(v, p.eps_min, p.eps_max, inv_span);
+        }
+        ej[j] = v;
+      }
+      float rew = rsum * inv_nt;
+      // ---- agents' positions and broadcasts; crash penalty
+      float agx[MA], agy[MA];
+      int agc[MA];
+#pragma unroll
+      for (int k = 0; k < MA; ++k) {
+        agx[k] = 0.0f;
+        agy[k] = 0.0f;
+        agc[k] = 0;
+        if (k < na) {
+          const int src = base_lane + k * G;
+          agx[k] = __shfl(ax, src);
+          agy[k] = __shfl(ay, src);
+          agc[k] = FULL ? __shfl((int)comm_ok, src) : 1;
+        }
+      }
+      bool crash = false;
+#pragma unroll
+      for (int k = 0; k < MA; ++k)
+#pragma unroll
+        for (int k2 = k + 1; k2 < MA; ++k2)
+          if (k2 < na) {
+            crash = crash || (sqnorm(agx[k] - agx[k2], agy[k] - agy[k2]) < dsafe2);
+          }
+      if (crash) rew = -1.0f;
+      const bool done = (t + 1u == (uint32_t)p.episode_len);
+
+      // ---- outputs
+      if constexpr (!FULL) {
+        if (active) {
+          if (r == 0) {
+            acc_rew += (double)rew;
+            acc_crash += crash ? 1 : 0;
+#pragma unroll
+            for (int j = 0; j < MT; ++j)
+              if (j < nt && ej[j] < kInf) {
+                acc_err += (double)ej[j];
+                acc_err2 += (double)ej[j] * (double)ej[j];
+                acc_cnt += 1;
+              }
+            if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
+            if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
+          }
+          // this lane's tokens: into the staging area (position = output order)
+          // for a large batch, else straight to the output
+          const int tb = agent_w * ntok;
+          const int64_t kb = (int64_t)step * o.K + kbase;
+          float *ob = o.obs ? o.obs + kb * 6 : nullptr;
+          uint8_t *om = o.obs_mask ? o.obs_mask + kb : nullptr;
+          auto emit = [&](int m, float dx, float dy, bool ok, float is_self, float is_agent,
+                          float is_target) {
+            if constexpr (stage) {
+              st_xy[tb + m] = make_float2(dx, dy);
+              st_m[tb + m] = ok ? 1 : 0;
+            } else {
+              if (ob) store_token(ob + m * 6, dx, dy, is_self, is_agent, is_target);
+              if (om) om[m] = ok ? 1 : 0;
+            }
+          };
+          if (g == 0) emit(0, 0.0f, 0.0f, true, 1.0f, 0.0f, 0.0f);
+#pragma unroll
+          for (int m = 1; m < MA; ++m) {
+            if (m < na && (m % G) == g) {
+              const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
+              const float ox = before ? agx[m - 1] : agx[m];
+              const float oy = before ? agy[m - 1] : agy[m];
+              const float dx = ox - ax, dy = oy - ay;
+              const bool ok = sqnorm(dx, dy) <= comm2;
+              emit(m, ok ? dx : 0.0f, ok ? dy : 0.0f, ok, 0.0f, 1.0f, 0.0f);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < MT; ++j) {
+            if (j < nt && (j % G) == g) {
+              const int sl = j / G;
+              const bool ok = (evb >> sl) & 1u;
+              emit(na + j, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, ok, 0.0f, 0.0f, 1.0f);
+            }
+          }
+          if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
+            status |= kStatusNonFinite;
+        }
+        // the wavefront's token block is contiguous in the output: one lane per
+        // token, consecutive lanes on consecutive tokens
+        if constexpr (stage) {
+          wave_lds_fence();
+          const int64_t kw = (int64_t)step * o.K + kbase_w;
+          float2 *ob = o.obs ? reinterpret_cast<float2 *>(o.obs + kw * 6) : nullptr;
+          uint8_t *om = o.obs_mask ? o.obs_mask + kw : nullptr;
+          int m = m_lane0;  // position of token `t` inside its agent's token list
+          for (int t = lane; t < ntok_w; t += 64) {
+            if (ob) {
+              ob[3 * t] = st_xy[t];
+              ob[3 * t + 1] = make_float2(0.0f, m == 0 ? 1.0f : 0.0f);
+              ob[3 * t + 2] = make_float2((m >= 1 && m < na) ? 1.0f : 0.0f, m >= na ? 1.0f : 0.0f);
+            }
+            if (om) om[t] = st_m[t];
+            m += m_step;
+            if (m >= ntok) m -= ntok;
+          }
+          wave_lds_fence();  // the staging area is rewritten next step
+        }
+      } else if (active) {
         if (r == 0) {
           acc_rew += (double)rew;
           acc_crash += crash ? 1 : 0;
@@ -711,146 +784,119 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             }
           if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
           if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
+          if (o.err) {
+#pragma unroll
+            for (int j = 0; j < MT; ++j)
+              if (j < nt) o.err[(int64_t)step * o.Tt + tbase + j] = ej[j];
+          }
         }
-        // this lane's tokens: into the staging area (position = output order)
-        // for a large batch, else straight to the output
-        const int tb = agent_w * ntok;
         const int64_t kb = (int64_t)step * o.K + kbase;
-        float *ob = o.obs ? o.obs + kb * 6 : nullptr;
-        uint8_t *om = o.obs_mask ? o.obs_mask + kb : nullptr;
-        auto emit = [&](int m, float dx, float dy, bool ok, float is_self, float is_agent,
-                        float is_target) {
-          if constexpr (stage) {
-            st_xy[tb + m] = make_float2(dx, dy);
-            st_m[tb + m] = ok ? 1 : 0;
-          } else {
-            if (ob) store_token(ob + m * 6, dx, dy, is_self, is_agent, is_target);
-            if (om) om[m] = ok ? 1 : 0;
-          }
-        };
-        if (g == 0) emit(0, 0.0f, 0.0f, true, 1.0f, 0.0f, 0.0f);
+        if (o.obs) {
+          float *ob = o.obs + kb * 6;
+          if (g == 0) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
 #pragma unroll
-        for (int m = 1; m < MA; ++m) {
-          if (m < na && (m % G) == g) {
-            const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
-            const float ox = before ? agx[m - 1] : agx[m];
-            const float oy = before ? agy[m - 1] : agy[m];
-            const float dx = ox - ax, dy = oy - ay;
-            const bool ok = sqnorm(dx, dy) <= comm2;
-            emit(m, ok ? dx : 0.0f, ok ? dy : 0.0f, ok, 0.0f, 1.0f, 0.0f);
+          for (int m = 1; m < MA; ++m) {
+            if (m < na && (m % G) == g) {
+              const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
+              const float ox = before ? agx[m - 1] : agx[m];
+              const float oy = before ? agy[m - 1] : agy[m];
+              const int oc = before ? agc[m - 1] : agc[m];
+              const float dx = ox - ax, dy = oy - ay;
+              const bool ok = oc && (sqnorm(dx, dy) <= comm2);
+              store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
+              if (o.obs_mask) o.obs_mask[kb + m] = ok ? 1 : 0;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < MT; ++j) {
+            if (j < nt && (j % G) == g) {
+              const int sl = j / G;
+              const bool ok = (evb >> sl) & 1u;
+              store_token(ob + (na + j) * 6, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, 0.0f,
+                          0.0f, 1.0f);
+              if (o.obs_mask) o.obs_mask[kb + na + j] = ok ? 1 : 0;
+            }
+          }
+          if (o.obs_mask && g == 0) o.obs_mask[kb] = 1;
+        } else if (o.obs_mask) {
+          if (g == 0) o.obs_mask[kb] = 1;
+#pragma unroll
+          for (int m = 1; m < MA; ++m) {
+            if (m < na && (m % G) == g) {
+              const bool before = (m - 1) < i;
+              const float ox = before ? agx[m - 1] : agx[m];
+              const float oy = before ? agy[m - 1] : agy[m];
+              const int oc = before ? agc[m - 1] : agc[m];
+              o.obs_mask[kb + m] = (oc && (sqnorm(ox - ax, oy - ay) <= comm2)) ? 1 : 0;
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < MT; ++j)
+            if (j < nt && (j % G) == g) o.obs_mask[kb + na + j] = ((evb >> (j / G)) & 1u) ? 1 : 0;
+        }
+        if (g == 0) {
+          if (o.actions) o.actions[(int64_t)step * o.A + aidx] = act;
+          if (o.gstate) {
+            float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + i) * 6;
+            gs[0] = ax; gs[1] = ay; gs[2] = 0.0f; gs[3] = p.agent_speed; gs[4] = apsi; gs[5] = 0.0f;
+          }
+        }
+        if (o.gstate) {
+          for (int q = r; q < nB; q += lpe) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+              const int j = 2 * q + m;
+              if (j < nt) {
+                const float4 tg = tl[j];
+                float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + na + j) * 6;
+                gs[0] = tg.x; gs[1] = tg.y; gs[2] = 0.0f; gs[3] = tg.w; gs[4] = tg.z; gs[5] = 1.0f;
+              }
+            }
           }
         }
 #pragma unroll
-        for (int j = 0; j < MT; ++j) {
-          if (j < nt && (j % G) == g) {
-            const int sl = j / G;
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt) {
+            const int64_t pidx = (int64_t)step * o.P + pbase + j;
             const bool ok = (evb >> sl) & 1u;
-            emit(na + j, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, ok, 0.0f, 0.0f, 1.0f);
+            if (o.est) {
+              o.est[2 * pidx] = ok ? ex[sl] : 0.0f;
+              o.est[2 * pidx + 1] = ok ? ey[sl] : 0.0f;
+            }
+            if (o.est_valid) o.est_valid[pidx] = ok ? 1 : 0;
+            if (o.ranges) o.ranges[pidx] = hr[sl][0];
           }
         }
         if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
           status |= kStatusNonFinite;
       }
-      // the wavefront's token block is contiguous in the output: one lane per
-      // token, consecutive lanes on consecutive tokens
-      if constexpr (stage) {
-        wave_lds_fence();
-        const int64_t kw = (int64_t)step * o.K + kbase_w;
-        float2 *ob = o.obs ? reinterpret_cast<float2 *>(o.obs + kw * 6) : nullptr;
-        uint8_t *om = o.obs_mask ? o.obs_mask + kw : nullptr;
-        int m = m_lane0;  // position of token `t` inside its agent's token list
-        for (int t = lane; t < ntok_w; t += 64) {
-          if (ob) {
-            ob[3 * t] = st_xy[t];
-            ob[3 * t + 1] = make_float2(0.0f, m == 0 ? 1.0f : 0.0f);
-            ob[3 * t + 2] = make_float2((m >= 1 && m < na) ? 1.0f : 0.0f, m >= na ? 1.0f : 0.0f);
-          }
-          if (om) om[t] = st_m[t];
-          m += m_step;
-          if (m >= ntok) m -= ntok;
-        }
-        wave_lds_fence();  // the staging area is rewritten next step
-      }
-    } else if (active) {
-      if (r == 0) {
-        acc_rew += (double)rew;
-        acc_crash += crash ? 1 : 0;
-#pragma unroll
-        for (int j = 0; j < MT; ++j)
-          if (j < nt && ej[j] < kInf) {
-            acc_err += (double)ej[j];
-            acc_err2 += (double)ej[j] * (double)ej[j];
-            acc_cnt += 1;
-          }
-        if (o.reward) o.reward[(int64_t)step * o.E + e] = rew;
-        if (o.done) o.done[(int64_t)step * o.E + e] = done ? 1 : 0;
-        if (o.err) {
-#pragma unroll
-          for (int j = 0; j < MT; ++j)
-            if (j < nt) o.err[(int64_t)step * o.Tt + tbase + j] = ej[j];
-        }
-      }
-      const int64_t kb = (int64_t)step * o.K + kbase;
-      if (o.obs) {
-        float *ob = o.obs + kb * 6;
-        if (g == 0) store_token(ob, 0.0f, 0.0f, 1.0f, 0.0f, 0.0f);
-#pragma unroll
-        for (int m = 1; m < MA; ++m) {
-          if (m < na && (m % G) == g) {
-            const bool before = (m - 1) < i;  // other agent k = m-1 if m-1 < i else m
-            const float ox = before ? agx[m - 1] : agx[m];
-            const float oy = before ? agy[m - 1] : agy[m];
-            const int oc = before ? agc[m - 1] : agc[m];
-            const float dx = ox - ax, dy = oy - ay;
-            const bool ok = oc && (sqnorm(dx, dy) <= comm2);
-            store_token(ob + m * 6, ok ? dx : 0.0f, ok ? dy : 0.0f, 0.0f, 1.0f, 0.0f);
-            if (o.obs_mask) o.obs_mask[kb + m] = ok ? 1 : 0;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < MT; ++j) {
-          if (j < nt && (j % G) == g) {
-            const int sl = j / G;
-            const bool ok = (evb >> sl) & 1u;
-            store_token(ob + (na + j) * 6, ok ? ex[sl] - ax : 0.0f, ok ? ey[sl] - ay : 0.0f, 0.0f,
-                        0.0f, 1.0f);
-            if (o.obs_mask) o.obs_mask[kb + na + j] = ok ? 1 : 0;
-          }
-        }
-        if (o.obs_mask && g == 0) o.obs_mask[kb] = 1;
-      } else if (o.obs_mask) {
-        if (g == 0) o.obs_mask[kb] = 1;
-#pragma unroll
-        for (int m = 1; m < MA; ++m) {
-          if (m < na && (m % G) == g) {
-            const bool before = (m - 1) < i;
-            const float ox = before ? agx[m - 1] : agx[m];
-            const float oy = before ? agy[m - 1] : agy[m];
-            const int oc = before ? agc[m - 1] : agc[m];
-            o.obs_mask[kb + m] = (oc && (sqnorm(ox - ax, oy - ay) <= comm2)) ? 1 : 0;
-          }
-        }
-#pragma unroll
-        for (int j = 0; j < MT; ++j)
-          if (j < nt && (j % G) == g) o.obs_mask[kb + na + j] = ((evb >> (j / G)) & 1u) ? 1 : 0;
-      }
+    }
+
+    // ---- store state back (state pointers re-read from the device copy)
+    if (active) {
+      const DevState s = *sp;
       if (g == 0) {
-        if (o.actions) o.actions[(int64_t)step * o.A + aidx] = act;
-        if (o.gstate) {
-          float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + i) * 6;
-          gs[0] = ax; gs[1] = ay; gs[2] = 0.0f; gs[3] = p.agent_speed; gs[4] = apsi; gs[5] = 0.0f;
+        st_st(&s.ax[aidx], ax, dyn);
+        st_st(&s.ay[aidx], ay, dyn);
+        st_st(&s.apsi[aidx], apsi, dyn);
+#pragma unroll
+        for (int k = 0; k < WC; ++k) {
+          if (k < W) {
+            st_st(&s.hx[(int64_t)k * s.A + aidx], hx[k], dyn);
+            st_st(&s.hy[(int64_t)k * s.A + aidx], hy[k], dyn);
+          }
         }
       }
-      if (o.gstate) {
-        for (int q = r; q < nB; q += lpe) {
+      for (int q = r; q < nB; q += lpe) {
 #pragma unroll
-          for (int m = 0; m < 2; ++m) {
-            const int j = 2 * q + m;
-            if (j < nt) {
-              const float4 tg = tl[j];
-              float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + na + j) * 6;
-              gs[0] = tg.x; gs[1] = tg.y; gs[2] = 0.0f; gs[3] = tg.w; gs[4] = tg.z; gs[5] = 1.0f;
-            }
+        for (int m = 0; m < 2; ++m) {
+          const int j = 2 * q + m;
+          if (j < nt) {
+            const float4 tg = tl[j];
+            st_st(&s.tx[tbase + j], tg.x, dyn);
+            st_st(&s.ty[tbase + j], tg.y, dyn);
+            st_st(&s.tpsi[tbase + j], tg.z, dyn);
           }
         }
       }
@@ -858,74 +904,28 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       for (int sl = 0; sl < NPL; ++sl) {
         const int j = g + G * sl;
         if (j < nt) {
-          const int64_t pidx = (int64_t)step * o.P + pbase + j;
-          const bool ok = (evb >> sl) & 1u;
-          if (o.est) {
-            o.est[2 * pidx] = ok ? ex[sl] : 0.0f;
-            o.est[2 * pidx + 1] = ok ? ey[sl] : 0.0f;
-          }
-          if (o.est_valid) o.est_valid[pidx] = ok ? 1 : 0;
-          if (o.ranges) o.ranges[pidx] = hr[sl][0];
+          const int64_t pidx = pbase + j;
+#pragma unroll
+          for (int k = 0; k < WC; ++k)
+            if (k < W) st_st(&s.hr[(int64_t)k * s.P + pidx], hr[sl][k], dyn);
+          st_st(&s.ex[pidx], ex[sl], dyn);
+          st_st(&s.ey[pidx], ey[sl], dyn);
+          st_st(&s.ev[pidx], (uint8_t)((evb >> sl) & 1u), dyn);
         }
       }
-      if (!(fabsf(ax) < kInf) || !(fabsf(ay) < kInf) || !(fabsf(apsi) < kInf))
-        status |= kStatusNonFinite;
-    }
-  }
-
-  // ---- store state back (state pointers re-read from the device copy)
-  if (active) {
-    const DevState s = *sp;
-    if (g == 0) {
-      st_st(&s.ax[aidx], ax, dyn);
-      st_st(&s.ay[aidx], ay, dyn);
-      st_st(&s.apsi[aidx], apsi, dyn);
-#pragma unroll
-      for (int k = 0; k < WC; ++k) {
-        if (k < W) {
-          st_st(&s.hx[(int64_t)k * s.A + aidx], hx[k], dyn);
-          st_st(&s.hy[(int64_t)k * s.A + aidx], hy[k], dyn);
-        }
+      if (r == 0) {
+        st_st(&s.macc[3 * e], acc_rew, dyn);
+        st_st(&s.macc[3 * e + 1], acc_err, dyn);
+        st_st(&s.macc[3 * e + 2], acc_err2, dyn);
+        st_st(&s.miacc[2 * e], acc_cnt, dyn);
+        st_st(&s.miacc[2 * e + 1], acc_crash, dyn);
       }
     }
-    for (int q = r; q < nB; q += lpe) {
-#pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int j = 2 * q + m;
-        if (j < nt) {
-          const float4 tg = tl[j];
-          st_st(&s.tx[tbase + j], tg.x, dyn);
-          st_st(&s.ty[tbase + j], tg.y, dyn);
-          st_st(&s.tpsi[tbase + j], tg.z, dyn);
-        }
-      }
-    }
-#pragma unroll
-    for (int sl = 0; sl < NPL; ++sl) {
-      const int j = g + G * sl;
-      if (j < nt) {
-        const int64_t pidx = pbase + j;
-#pragma unroll
-        for (int k = 0; k < WC; ++k)
-          if (k < W) st_st(&s.hr[(int64_t)k * s.P + pidx], hr[sl][k], dyn);
-        st_st(&s.ex[pidx], ex[sl], dyn);
-        st_st(&s.ey[pidx], ey[sl], dyn);
-        st_st(&s.ev[pidx], (uint8_t)((evb >> sl) & 1u), dyn);
-      }
-    }
-    if (r == 0) {
-      st_st(&s.macc[3 * e], acc_rew, dyn);
-      st_st(&s.macc[3 * e + 1], acc_err, dyn);
-      st_st(&s.macc[3 * e + 2], acc_err2, dyn);
-      st_st(&s.miacc[2 * e], acc_cnt, dyn);
-      st_st(&s.miacc[2 * e + 1], acc_crash, dyn);
-    }
-  }
-  if (status) atomicOr(sp->status, status);
-  wave_lds_fence();  // the next unit rewrites the target slab
-  if (!dyn) break;
-  if (s_end < T) publish_chunks(sp->queue + 1 + wave, cix + 1, lane);
-  unit = take_unit(sp->queue, lane);
+    if (status) atomicOr(sp->status, status);
+    wave_lds_fence();  // the next unit rewrites the target slab
+    if (!dyn) break;
+    if (s_end < T) publish_chunks(sp->queue + 1 + wave, cix + 1, lane);
+    unit = take_unit(sp->queue, lane);
   }
 }
 

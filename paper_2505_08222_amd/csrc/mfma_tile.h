@@ -35,16 +35,19 @@ __device__ __forceinline__ void gemm_rs_bf16(const __bf16 *A, int lda, const __b
   for (int c = 0; c < NCT; ++c)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
-      b[c][ks] = *reinterpret_cast<const bf16x8 *>(B + (((wave + c * NW) << 4) + row) * ldb + ks * 32 + 8 * kg);
+      b[c][ks] = *reinterpret_cast<const bf16x8 *>(B + (((wave + c * NW) << 4) + row) * ldb +
+                                                   ks * 32 + 8 * kg);
   bf16x8 a[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a[ks] = *reinterpret_cast<const bf16x8 *>(A + row * lda + ks * 32 + 8 * kg);
+  for (int ks = 0; ks < KS; ++ks)
+    a[ks] = *reinterpret_cast<const bf16x8 *>(A + row * lda + ks * 32 + 8 * kg);
   for (int mt = 0; mt < tm; ++mt) {
     const int m0 = mt << 4;
     bf16x8 an[KS];
     const int mn = (mt + 1 < tm ? m0 + 16 : m0);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) an[ks] = *reinterpret_cast<const bf16x8 *>(A + (mn + row) * lda + ks * 32 + 8 * kg);
+    for (int ks = 0; ks < KS; ++ks)
+      an[ks] = *reinterpret_cast<const bf16x8 *>(A + (mn + row) * lda + ks * 32 + 8 * kg);
     floatx4 acc[NCT];
 #pragma unroll
     for (int c = 0; c < NCT; ++c) {
@@ -78,10 +81,16 @@ __device__ __forceinline__ void load_bfrag(BFrag<K, N> &f, const __bf16 *B, int 
   for (int c = 0; c < BFrag<K, N>::NCT; ++c)
 #pragma unroll
     for (int ks = 0; ks < BFrag<K, N>::KS; ++ks)
-      f.v[c][ks] = *reinterpret_cast<const bf16x8 *>(B + (((wave + c * 4) << 4) + row) * ldb + ks * 32 + 8 * kg);
+      f.v[c][ks] = *reinterpret_cast<const bf16x8 *>(B + (((wave + c * 4) << 4) + row) * ldb +
+                                                     ks * 32 + 8 * kg);
 }
 
-// gemm_rs_bf16_t with the weight fragments already in registers.
+// The same walk with the operands' roles swapped in the instruction (weights
+// as its A, activations as its B) and the weight fragments already in
+// registers. The 16x16 result comes out transposed: lane l receives row
+// m0 + l%16 and the four consecutive columns n0 + 4*(l/16) + j, and epi4(m,
+// n, v) consumes v[j] = D[m][n + j], so that the epilogue reads and writes
+// four neighbouring features at once.
 template <int K, int N, typename Epi4>
 __device__ __forceinline__ void gemm_rs_bf16_tf(const __bf16 *A, int lda, const BFrag<K, N> &f,
                                                 int M, Epi4 epi4) {
@@ -92,13 +101,15 @@ __device__ __forceinline__ void gemm_rs_bf16_tf(const __bf16 *A, int lda, const 
   const int tm = M >> 4;
   bf16x8 a[KS];
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a[ks] = *reinterpret_cast<const bf16x8 *>(A + row * lda + ks * 32 + 8 * kg);
+  for (int ks = 0; ks < KS; ++ks)
+    a[ks] = *reinterpret_cast<const bf16x8 *>(A + row * lda + ks * 32 + 8 * kg);
   for (int mt = 0; mt < tm; ++mt) {
     const int m0 = mt << 4;
     bf16x8 an[KS];
     const int mn = (mt + 1 < tm ? m0 + 16 : m0);
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) an[ks] = *reinterpret_cast<const bf16x8 *>(A + (mn + row) * lda + ks * 32 + 8 * kg);
+    for (int ks = 0; ks < KS; ++ks)
+      an[ks] = *reinterpret_cast<const bf16x8 *>(A + (mn + row) * lda + ks * 32 + 8 * kg);
     floatx4 acc[NCT];
 #pragma unroll
     for (int c = 0; c < NCT; ++c) {
@@ -106,49 +117,6 @@ __device__ __forceinline__ void gemm_rs_bf16_tf(const __bf16 *A, int lda, const 
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks)
         acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.v[c][ks], a[ks], acc[c], 0, 0, 0);
-    }
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) epi4(m0 + row, ((wave + c * NW) << 4) + 4 * kg, acc[c]);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) a[ks] = an[ks];
-  }
-}
-
-// The same walk with the operands' roles swapped in the instruction (weights
-// as its A, activations as its B), so that the 16x16 result comes out
-// transposed: lane l receives row m0 + l%16 and the four consecutive columns
-// n0 + 4*(l/16) + j. epi4(m, n, v) consumes v[j] = D[m][n + j], which lets
-// the epilogue read and write four neighbouring features at once.
-template <int K, int N, typename Epi4>
-__device__ __forceinline__ void gemm_rs_bf16_t(const __bf16 *A, int lda, const __bf16 *B, int ldb,
-                                               int M, Epi4 epi4) {
-  constexpr int KS = K / 32, NW = 4, NCT = N / (16 * NW);
-  static_assert(N % (16 * NW) == 0 && K % 32 == 0, "shape");
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = lane & 15, kg = lane >> 4;
-  const int tm = M >> 4;
-  bf16x8 b[NCT][KS];
-#pragma unroll
-  for (int c = 0; c < NCT; ++c)
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-      b[c][ks] = *reinterpret_cast<const bf16x8 *>(B + (((wave + c * NW) << 4) + row) * ldb + ks * 32 + 8 * kg);
-  bf16x8 a[KS];
-#pragma unroll
-  for (int ks = 0; ks < KS; ++ks) a[ks] = *reinterpret_cast<const bf16x8 *>(A + row * lda + ks * 32 + 8 * kg);
-  for (int mt = 0; mt < tm; ++mt) {
-    const int m0 = mt << 4;
-    bf16x8 an[KS];
-    const int mn = (mt + 1 < tm ? m0 + 16 : m0);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) an[ks] = *reinterpret_cast<const bf16x8 *>(A + (mn + row) * lda + ks * 32 + 8 * kg);
-    floatx4 acc[NCT];
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) {
-      acc[c] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[c][ks], a[ks], acc[c], 0, 0, 0);
     }
 #pragma unroll
     for (int c = 0; c < NCT; ++c) epi4(m0 + row, ((wave + c * NW) << 4) + 4 * kg, acc[c]);
