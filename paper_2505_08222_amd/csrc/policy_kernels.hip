@@ -245,7 +245,7 @@ policy_kernel(PolicyArgs a) {
       {
         const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
         const int row = lane & 15, kg = lane >> 4;
-        constexpr int NP = 4;  // (agent, head) pairs in flight per wavefront
+        constexpr int NP = 8;  // (agent, head) pairs in flight per wavefront
         for (int pr0 = wave * NP; pr0 < at * kPolHeads; pr0 += nw * NP) {
           int r0[NP], hd[NP], ag[NP];
           bool live[NP];
