@@ -343,8 +343,9 @@ int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned);
  * env_graph_launch) instead of run.
  * d_mlp_params (may be NULL): parameters of the learned estimator (mlp_*). When
  * given, each env step is split around it: the step moves the entities, draws
- * the ranges and pushes the windows; every tracker's window goes through
- * mlp_infer (residual test at k_sigma * sigma_r, exact fallback); then the step
+ * the ranges, pushes the windows and writes every tracker's window to the
+ * workspace; they go through mlp_infer (residual test at k_sigma * sigma_r,
+ * exact fallback); then the step
  * takes those estimates (for trackers whose window is full; shorter windows keep
  * the exact estimator) and computes reward and observation. Needs window <= 21.
  * Errors: MIL_EINVAL (ragged batch, too many tokens or actions, bad T/episode,

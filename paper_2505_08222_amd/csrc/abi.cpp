@@ -932,12 +932,10 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
       float *win = (float *)(ws + ew.win), *sig = (float *)(ws + ew.sig);
       float *est = (float *)(ws + ew.est);
       uint8_t *flag = (uint8_t *)(ws + ew.flag);
+      // (phase 1 also writes every tracker's window and noise std for the network)
       lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
                                 dstate, t, 1, (uint32_t)episode, wact, o, st,
-                                mil::DevExt{1, nullptr, nullptr}, h->sched);
-      if (!lrc)
-        lrc = mil::launch_env_windows(h->ds, h->P.window, h->P.n_agents * h->P.n_targets, win, sig,
-                                      nullptr, st);
+                                mil::DevExt{1, nullptr, nullptr, win, sig}, h->sched);
       if (!lrc)
         lrc = mlp_infer(win, Pn, h->P.window, d_mlp_params, sig, k_sigma, 0, h->P.guard_tau, est,
                         flag, ws + ew.mlp, ew.mlp_bytes, st) == MIL_OK

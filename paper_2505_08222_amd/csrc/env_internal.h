@@ -69,14 +69,19 @@ struct DevOut {
 };
 
 // Split step of the full kernel, for an estimator that runs between its two
-// halves: phase 1 moves the entities, draws the ranges and pushes the window;
-// phase 2 takes each tracker's estimate from est [P][2] / flag [P] (flag 0 or
-// 1: estimate present, 2: refused, hold the previous one) once its window is
-// full, then computes reward, observation and outputs. phase 0: whole step.
+// halves: phase 1 moves the entities, draws the ranges and pushes the window,
+// and (win not null) hands every tracker's window to the estimator: win
+// [P][W][3] (agent x, agent y, range; entry 0 newest) and wsig [P] (the env's
+// range-noise std); phase 2 takes each tracker's estimate from est [P][2] /
+// flag [P] (flag 0 or 1: estimate present, 2: refused, hold the previous one)
+// once its window is full, then computes reward, observation and outputs.
+// phase 0: whole step.
 struct DevExt {
   int32_t phase;
   const float *est;
   const uint8_t *flag;
+  float *win = nullptr;
+  float *wsig = nullptr;
 };
 
 // Kernel launchers (env_kernels.hip). All enqueue on `stream`.

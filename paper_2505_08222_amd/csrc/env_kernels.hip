@@ -527,6 +527,35 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 #pragma unroll
         for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
       }
+      if (FULL && ext.win && move && active) {
+        // phase 1 hands the windows to the estimator (entry 0 newest)
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt) {
+            const int64_t pidx = pbase + j;
+            float *dst = ext.win + pidx * (int64_t)(3 * W);
+            if (WC % 4 == 0 && W == WC) {  // 16-byte aligned windows: 12-float groups
+              float4 *d4 = reinterpret_cast<float4 *>(dst);
+#pragma unroll
+              for (int k = 0; k < WC; k += 4) {
+                d4[3 * (k / 4)] = make_float4(hx[k], hy[k], hr[sl][k], hx[k + 1]);
+                d4[3 * (k / 4) + 1] = make_float4(hy[k + 1], hr[sl][k + 1], hx[k + 2], hy[k + 2]);
+                d4[3 * (k / 4) + 2] = make_float4(hr[sl][k + 2], hx[k + 3], hy[k + 3], hr[sl][k + 3]);
+              }
+            } else {
+#pragma unroll
+              for (int k = 0; k < WC; ++k)
+                if (k < W) {
+                  dst[3 * k] = hx[k];
+                  dst[3 * k + 1] = hy[k];
+                  dst[3 * k + 2] = hr[sl][k];
+                }
+            }
+            if (ext.wsig) ext.wsig[pidx] = sig_r;
+          }
+        }
+      }
       if (!observe) continue;  // phase 1 ends here: the estimator runs next
       const int filled = min((int)t + 1, W);
 
