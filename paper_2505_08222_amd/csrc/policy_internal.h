@@ -15,6 +15,7 @@ constexpr int kPolD = 64, kPolHeads = 4, kPolDh = 16, kPolF = 256, kPolLayers = 
 constexpr int kPolActions = 8;   // head rows (the first n_actions are used)
 constexpr int kPolMaxTok = 16;   // tokens per agent (agents + targets of an env)
 constexpr int kPolRows = 80;     // token rows per tile (two tiles' LDS fit one CU)
+constexpr int kPolBlocksPerCU = 2;
 constexpr int kPolMaxAgents = 16;
 constexpr int kPolLdD = kPolD + 8, kPolLdF = kPolF + 8;
 // offsets inside one layer

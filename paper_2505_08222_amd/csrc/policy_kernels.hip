@@ -44,26 +44,28 @@ __device__ __forceinline__ int small_param_src(int i) {
 
 }  // namespace
 
+constexpr int kPlane = kPolRows * (kPolD + 8);  // one Q / K / V plane (elements)
+constexpr int kLdQ = kPolD + 8;                  // row stride of a plane
+constexpr int kLdVt = kPolRows + 8;              // row stride of V^T
+constexpr int kLdHid = 128 + 8;                  // row stride of the FFN hidden half
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// the staging buffer: Q and K planes then V^T; or one half of the FFN hidden
+// layer; or the raw tokens; or the head's scratch (16 spare elements: the last
+// agent's attention reads up to 15 keys past its first row)
+constexpr int kBufElems =
+    cmax(cmax(2 * kPlane + kPolD * kLdVt, kPolRows * kLdHid),
+         cmax(kPolMaxAgents * (kPolD + 4) * 2, kPolRows * 6 * 2)) + 16;
+
 struct PolicyLds {
   float prm[kSmTotal];                    // small FP32 parameters
   float h[kPolRows][kPolD + 4];           // residual stream (rows padded: conflict-free row reads)
   __bf16 xn[kPolRows][kPolD + 8];         // LayerNorm output / attention output
-  // Q, K planes [rows][72] and V transposed [64][88]; or one half of the FFN hidden layer
-  // [rows][136]; or raw tokens; or the head's scratch
-  __bf16 buf[3 * kPolRows * (kPolD + 8)];
+  __bf16 buf[kBufElems];
   uint8_t mask[kPolRows];
   uint32_t mbits[kPolMaxAgents];          // per agent: bit k = observation mask of token k
   float logits[kPolMaxAgents][kPolActions];
 };
-static_assert(sizeof(PolicyLds) <= 80 * 1024, "two policy blocks per CU");
-constexpr int kPlane = kPolRows * (kPolD + 8);  // one Q / K / V plane (elements)
-constexpr int kLdQ = kPolD + 8;                  // row stride of a plane
-constexpr int kLdVt = kPolRows + 8;              // row stride of V^T
-static_assert(kPolD * kLdVt <= kPlane, "V^T fits its plane");
-constexpr int kLdHid = 128 + 8;                  // row stride of the FFN hidden half
-static_assert(kPolRows * kLdHid <= 3 * kPlane, "FFN half fits the buffer");
-static_assert(kPolMaxAgents * (kPolD + 4) * 4 <= sizeof(__bf16) * 3 * kPlane,
-              "head scratch fits the buffer");
+static_assert(sizeof(PolicyLds) <= 160 * 1024 / kPolBlocksPerCU, "resident policy blocks per CU");
 static_assert((kPlane * 2) % 16 == 0, "plane alignment");
 static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 == 0 &&
                   offsetof(PolicyLds, buf) % 16 == 0,
@@ -142,8 +144,8 @@ __device__ __forceinline__ void residual4(float *h, const floatx4 &v) {
   *p = x;
 }
 
-// at least two wavefronts per SIMD: two resident blocks of four per CU
-__global__ void __launch_bounds__(256, 2)
+// kPolBlocksPerCU resident blocks of four wavefronts per CU
+__global__ void __launch_bounds__(256, kPolBlocksPerCU)
 policy_kernel(PolicyArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   PolicyLds &L = *reinterpret_cast<PolicyLds *>(smem);
@@ -163,6 +165,7 @@ policy_kernel(PolicyArgs a) {
   static_assert(kTokRegs * 256 >= kPolRows * 6 && kPolRows <= 256, "token prefetch");
   float tok[kTokRegs];
   uint8_t msk = 0;
+  uint32_t eid_next = 0;
   auto fetch = [&](int64_t tile) {
     const int64_t ag0 = tile * at;
     const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;
@@ -174,6 +177,9 @@ policy_kernel(PolicyArgs a) {
       tok[q] = (tile < ntiles && e < nrow * 6) ? src[e] : 0.0f;
     }
     msk = (tile < ntiles && tid < nrow) ? a.mask[ag0 * nt + tid] : 0;
+    // the global env id of agent tid of the tile, for its action draw
+    const int64_t env = (ag0 + tid) / a.n_agents;
+    eid_next = (tile < ntiles && tid < nag) ? (a.env_ids ? a.env_ids[env] : (uint32_t)env) : 0u;
   };
   fetch(blockIdx.x);
   // weight fragments are loaded one GEMM ahead (the first layer's QKV here)
@@ -191,6 +197,7 @@ policy_kernel(PolicyArgs a) {
       if (e < rows * 6) x_raw[e] = tok[q];
     }
     if (tid < rows) L.mask[tid] = msk;
+    const uint32_t eid = eid_next;  // this tile's, fetched a tile ahead
     fetch(tile + gridDim.x);
     __syncthreads();
     // ---- embed 6 -> 64 (VALU)
@@ -435,15 +442,16 @@ policy_kernel(PolicyArgs a) {
     }
     __syncthreads();
     // ---- actions: inverse-CDF draw from softmax over the first n_actions logits
-    for (int al = tid; al < nag; al += nthr) {
+    if (tid < nag) {  // nag <= kPolMaxAgents: one thread per agent
+      const int al = tid;
       const int64_t ag = ag0 + al;
       if (a.logits)
         for (int k = 0; k < kPolActions; ++k) a.logits[ag * kPolActions + k] = L.logits[al][k];
       if (a.actions) {
         const int64_t env = ag / a.n_agents;
         const uint32_t i = (uint32_t)(ag - env * a.n_agents);
-        const u32x4 x = philox4x32_10(a.t, a.env_ids ? a.env_ids[env] : (uint32_t)env, i,
-                                      (a.episode << 4) | kPurposePolicy, a.key0, a.key1);
+        const u32x4 x = philox4x32_10(a.t, eid, i, (a.episode << 4) | kPurposePolicy, a.key0,
+                                      a.key1);
         const float u = u01(x.x);
         float mx = -INFINITY;
         for (int k = 0; k < a.n_actions; ++k) mx = fmaxf(mx, L.logits[al][k]);
@@ -538,7 +546,7 @@ int launch_policy(const PolicyArgs &args, int num_cus, void *stream) {
     lds_set = true;
   }
   const int64_t ntiles = (args.A + args.agents_per_tile - 1) / args.agents_per_tile;
-  const int64_t slots = 2 * (int64_t)num_cus;  // two resident blocks per CU
+  const int64_t slots = (int64_t)kPolBlocksPerCU * num_cus;  // resident blocks
   const int64_t grid = ntiles < slots ? ntiles : slots;
   if (grid <= 0) return 0;
   hipLaunchKernelGGL(policy_kernel, dim3((unsigned)grid), dim3(256), sizeof(PolicyLds),
