@@ -182,6 +182,40 @@ __global__ void queue_init_kernel(int32_t *queue, int32_t n) {
   if (i < n) queue[i] = 0;
 }
 
+// Broadcast inside an environment of the 2x2 kernels, by DPP (no LDS round
+// trip). With S = 2 an environment spans lpe = n_a * G lanes (1, 2 or 4)
+// starting at a multiple of lpe, so it never leaves an aligned quad: the
+// value of lane base + OFF reaches every lane of the environment through one
+// quad permutation, whose pattern depends only on OFF and lpe. Whole quads
+// are active.
+template <int OFF>
+__device__ __forceinline__ int env_bcast_q(int v, int lpe) {
+  constexpr int p4 = (OFF & 3) * 0x55;  // lpe 4: every lane takes OFF
+  constexpr int p2 = (OFF & 1) | ((OFF & 1) << 2) | ((2 + (OFF & 1)) << 4) | ((2 + (OFF & 1)) << 6);
+  const int w4 = __builtin_amdgcn_mov_dpp(v, p4, 0xF, 0xF, false);
+  const int w2 = __builtin_amdgcn_mov_dpp(v, p2, 0xF, 0xF, false);
+  return lpe == 4 ? w4 : (lpe == 2 ? w2 : v);  // lpe 1: OFF is 0, the lane itself
+}
+
+// Value of lane base_lane + off of the wavefront (off < lpe, a compile-time
+// constant after unrolling): DPP for S = 2, ds_bpermute for larger envs.
+template <int S, typename T>
+__device__ __forceinline__ T env_shfl(T v, int base_lane, int off, int lpe) {
+  if constexpr (S == 2) {
+    int w = 0;
+    const int x = __builtin_bit_cast(int, v);
+    switch (off) {
+      case 0: w = env_bcast_q<0>(x, lpe); break;
+      case 1: w = env_bcast_q<1>(x, lpe); break;
+      case 2: w = env_bcast_q<2>(x, lpe); break;
+      default: w = env_bcast_q<3>(x, lpe); break;
+    }
+    return __builtin_bit_cast(T, w);
+  } else {
+    return __shfl(v, base_lane + off);
+  }
+}
+
 // Element (g + G*sl) of a per-env array held with compile-time indices.
 template <int G, int N>
 __device__ __forceinline__ float pick(const float (&arr)[N], int g, int sl) {
@@ -692,7 +726,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         if (j < nt) {
 #pragma unroll
           for (int k = 0; k < MA; ++k) {
-            if (k < na) v = fminf(v, __shfl(errp[j / G], base_lane + k * G + (j % G)));
+            if (k < na) v = fminf(v, env_shfl<S>(errp[j / G], base_lane, k * G + (j % G), lpe));
           }
           rsum += tracking_reward(v, p.eps_min, p.eps_max, inv_span);
         }
@@ -708,10 +742,9 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         agy[k] = 0.0f;
         agc[k] = 0;
         if (k < na) {
-          const int src = base_lane + k * G;
-          agx[k] = __shfl(ax, src);
-          agy[k] = __shfl(ay, src);
-          agc[k] = FULL ? __shfl((int)comm_ok, src) : 1;
+          agx[k] = env_shfl<S>(ax, base_lane, k * G, lpe);
+          agy[k] = env_shfl<S>(ay, base_lane, k * G, lpe);
+          agc[k] = FULL ? env_shfl<S>((int)comm_ok, base_lane, k * G, lpe) : 1;
         }
       }
       bool crash = false;
