@@ -91,6 +91,11 @@ __device__ __forceinline__ u32x4 draw(uint32_t c0, uint32_t c1, uint32_t c2, uin
   return philox4x32_10(c0, c1, c2, c3, key0, key1);
 }
 
+// Environments of at most two targets keep them in registers in every lane
+// (one draw block: no owner has to broadcast them through LDS).
+template <int S>
+constexpr bool kRegTargets = (S == 2);
+
 // Observation tokens a wavefront can stage: 64 agents (lanes) of at most
 // 2S tokens each. Only a token's offset word and mask are staged; the type
 // columns follow from the token's position and are rebuilt while copying.
@@ -418,15 +423,31 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     const int64_t kbase_w = C.koff0 + (int64_t)(wave - C.wave0) * epw * na * ntok;
     const int m_lane0 = lane % ntok, m_step = 64 % ntok;  // token positions for the block copy
 
-    // ---- load state: targets of the env into LDS (each lane its own blocks)
-    for (int q = r; q < nB; q += lpe) {
+    // ---- load state: targets of the env into LDS (each lane its own blocks);
+    // with at most two targets (one draw block), every lane of the env keeps
+    // them in registers and advances them itself (the same draws and
+    // arithmetic in each lane), so no LDS round trip is needed
+    float4 treg[kRegTargets<S> ? 2 : 1];
+    if constexpr (kRegTargets<S>) {
 #pragma unroll
-      for (int m = 0; m < 2; ++m) {
-        const int j = 2 * q + m;
+      for (int j = 0; j < 2; ++j) {
+        treg[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (j < nt) {
           const int64_t idx = tbase + j;
-          tl[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
-                              ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
+          treg[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
+                                ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
+        }
+      }
+    } else {
+      for (int q = r; q < nB; q += lpe) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const int j = 2 * q + m;
+          if (j < nt) {
+            const int64_t idx = tbase + j;
+            tl[j] = make_float4(ld_st(&s.tx[idx], dyn), ld_st(&s.ty[idx], dyn),
+                                ld_st(&s.tpsi[idx], dyn), s.tv[idx]);
+          }
         }
       }
     }
@@ -488,40 +509,60 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       }
       const bool comm_ok = FULL ? !(u01(xa.w) < p.comm_loss_p) : true;
 
-      // ---- targets owned by this lane (blocks of two): heading random walk
-      for (int q = r; move && q < nB; q += lpe) {
-        const u32x4 xt =
-            draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
-        float zt[2];
-        normal2(xt.x, xt.y, zt[0], zt[1]);
+      // ---- targets (blocks of two, each owned by one lane, or by every lane
+      // of the env when they stay in registers): heading random walk
+      auto walk = [&](float4 &tg, float z) {
+        tg.z = wrap_angle(tg.z + p.sig_t * z);
+        float sn, cs;
+        sincos_rad(tg.z, sn, cs);
+        const float step_len = tg.w * p.dt;
+        tg.x = fmaf(step_len, cs, tg.x);
+        tg.y = fmaf(step_len, sn, tg.y);
+      };
+      float tpx[MT], tpy[MT];
+      if constexpr (kRegTargets<S>) {
+        if (move) {
+          const u32x4 xt = draw(t, env_id, kEntTargetBlock, c3dyn, p.key0, p.key1);
+          float zt[2];
+          normal2(xt.x, xt.y, zt[0], zt[1]);
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const int j = 2 * q + m;
-          if (j < nt) {
-            float4 tg = tl[j];
-            tg.z = wrap_angle(tg.z + p.sig_t * zt[m]);
-            float sn, cs;
-            sincos_rad(tg.z, sn, cs);
-            const float step_len = tg.w * p.dt;
-            tg.x = fmaf(step_len, cs, tg.x);
-            tg.y = fmaf(step_len, sn, tg.y);
-            tl[j] = tg;
+          for (int j = 0; j < 2; ++j)
+            if (j < nt) walk(treg[j], zt[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          tpx[j] = j < nt ? treg[j].x : 0.0f;
+          tpy[j] = j < nt ? treg[j].y : 0.0f;
+        }
+      } else {
+        for (int q = r; move && q < nB; q += lpe) {
+          const u32x4 xt =
+              draw(t, env_id, kEntTargetBlock + (uint32_t)q, c3dyn, p.key0, p.key1);
+          float zt[2];
+          normal2(xt.x, xt.y, zt[0], zt[1]);
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            const int j = 2 * q + m;
+            if (j < nt) {
+              float4 tg = tl[j];
+              walk(tg, zt[m]);
+              tl[j] = tg;
+            }
           }
         }
-      }
-      wave_lds_fence();
-      float tpx[MT], tpy[MT];
+        wave_lds_fence();
 #pragma unroll
-      for (int j = 0; j < MT; ++j) {
-        tpx[j] = 0.0f;
-        tpy[j] = 0.0f;
-        if (j < nt) {
-          const float4 v = tl[j];
-          tpx[j] = v.x;
-          tpy[j] = v.y;
+        for (int j = 0; j < MT; ++j) {
+          tpx[j] = 0.0f;
+          tpy[j] = 0.0f;
+          if (j < nt) {
+            const float4 v = tl[j];
+            tpx[j] = v.x;
+            tpy[j] = v.y;
+          }
         }
+        wave_lds_fence();  // every lane has read before next step's owners write
       }
-      wave_lds_fence();  // every lane has read before next step's owners write
 
       if (move) {
       // ---- noisy ranges after the move; missing beyond the detection range
@@ -909,7 +950,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
             for (int m = 0; m < 2; ++m) {
               const int j = 2 * q + m;
               if (j < nt) {
-                const float4 tg = tl[j];
+                const float4 tg = kRegTargets<S> ? treg[m] : tl[j];
                 float *gs = o.gstate + ((int64_t)step * (o.A + o.Tt) + gbase + na + j) * 6;
                 gs[0] = tg.x; gs[1] = tg.y; gs[2] = 0.0f; gs[3] = tg.w; gs[4] = tg.z; gs[5] = 1.0f;
               }
@@ -955,7 +996,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         for (int m = 0; m < 2; ++m) {
           const int j = 2 * q + m;
           if (j < nt) {
-            const float4 tg = tl[j];
+            const float4 tg = kRegTargets<S> ? treg[m] : tl[j];
             st_st(&s.tx[tbase + j], tg.x, dyn);
             st_st(&s.ty[tbase + j], tg.y, dyn);
             st_st(&s.tpsi[tbase + j], tg.z, dyn);
