@@ -208,9 +208,16 @@ policy_kernel(PolicyArgs a) {
       for (int c = 0; c < 6; ++c) wv[c] = L.prm[kSmEmbW + d * 6 + c];
       const float bd = L.prm[kSmEmbB + d];
       for (int r = tid >> 6; r < rows; r += nthr >> 6) {
+        // the row's six inputs as three 8-byte reads (rows start 24 bytes apart)
+        const float2 *xr = reinterpret_cast<const float2 *>(x_raw + r * 6);
+        const float2 x01 = xr[0], x23 = xr[1], x45 = xr[2];
         float acc = bd;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) acc = fmaf(wv[c], x_raw[r * 6 + c], acc);
+        acc = fmaf(wv[0], x01.x, acc);
+        acc = fmaf(wv[1], x01.y, acc);
+        acc = fmaf(wv[2], x23.x, acc);
+        acc = fmaf(wv[3], x23.y, acc);
+        acc = fmaf(wv[4], x45.x, acc);
+        acc = fmaf(wv[5], x45.y, acc);
         L.h[r][d] = r < nrow ? acc : 0.0f;
       }
       if (tid < at) {
