@@ -10,7 +10,10 @@
 // wave-uniform trip counts. Per-lane state (the agent, the targets the lane
 // owns, its trackers' range histories and estimates) stays in registers for
 // the whole rollout; target positions are broadcast through a per-wavefront
-// LDS slab, agent positions and tracking errors through ds_bpermute.
+// LDS slab, agent positions and tracking errors through ds_bpermute (2x2
+// batches: targets advanced in every lane of the env, broadcasts by DPP
+// quad permutations). Large batches may run under a dynamic schedule that
+// hands chunks of steps between wavefronts (see take_unit).
 //
 // Step semantics (arXiv 2505.08222): kinematic surrogate with heading noise
 // (Sec. III-A-3), noisy ranges after the move, one range-only least-squares

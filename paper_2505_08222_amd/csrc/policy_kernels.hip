@@ -6,11 +6,11 @@
 // rows); the small FP32 parameters (embedding, LayerNorms, biases, head) are
 // staged in LDS once per block. Tokens are embedded on VALU, every dense
 // layer (QKV, output projection, FFN) runs as BF16 MFMA with FP32
-// accumulation over the tile's stacked token rows, and
-// attention (n_tok <= 16 keys per agent, 4 heads of 16) runs on VALU with
-// keys whose observation mask is 0 excluded. The residual stream stays in
-// LDS in FP32. The self token's final LayerNorm feeds the action head; the
-// action is an inverse-CDF draw from Philox (purpose 4).
+// accumulation over the tile's stacked token rows, and attention (n_tok <= 16
+// keys per agent, 4 heads of 16) runs as two 16x16x16 MFMA products per
+// (agent, head) with keys whose observation mask is 0 excluded. The residual
+// stream stays in LDS in FP32. The self token's final LayerNorm feeds the
+// action head; the action is an inverse-CDF draw from Philox (purpose 4).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <math.h>
