@@ -71,43 +71,53 @@ static_assert(offsetof(PolicyLds, h) % 16 == 0 && offsetof(PolicyLds, xn) % 16 =
                   offsetof(PolicyLds, buf) % 16 == 0,
               "align");
 
+// Sum over a lane pair (DPP, lanes xor 1); both lanes end with the same value.
+__device__ __forceinline__ float pair_sum(float v) {
+  return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 // LayerNorm (eps 1e-5) of every row of the residual stream into xn (BF16):
-// four lanes per row, 16 features each held in registers, quad sums for the
-// mean and the variance; 64 rows per pass of the block's 256 threads.
+// two lanes per row, 32 features each held in registers, pair sums for the
+// mean and the variance; 128 rows per pass of the block's 256 threads (one
+// pass for a full tile).
 __device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const float *g,
                                                 const float *b) {
-  const int q = threadIdx.x & 3;
-  const float4 *gp = reinterpret_cast<const float4 *>(g + 16 * q);
-  const float4 *bp = reinterpret_cast<const float4 *>(b + 16 * q);
-  for (int r0 = 0; r0 < rows; r0 += 64) {
-    const int r = r0 + (threadIdx.x >> 2);
-    const int rr = r < rows ? r : rows - 1;  // whole quads stay active
-    const float4 *xp = reinterpret_cast<const float4 *>(&L.h[rr][16 * q]);
-    float x[16];
+  const int q = threadIdx.x & 1;
+  const float4 *gp = reinterpret_cast<const float4 *>(g + 32 * q);
+  const float4 *bp = reinterpret_cast<const float4 *>(b + 32 * q);
+  for (int r0 = 0; r0 < rows; r0 += 128) {
+    const int r = r0 + (threadIdx.x >> 1);
+    const int rr = r < rows ? r : rows - 1;  // whole pairs stay active
+    const float4 *xp = reinterpret_cast<const float4 *>(&L.h[rr][32 * q]);
+    float x[32];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const float4 v = xp[i];
       x[4 * i] = v.x;
       x[4 * i + 1] = v.y;
       x[4 * i + 2] = v.z;
       x[4 * i + 3] = v.w;
     }
-    float s4[4];
+    float s8[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s4[i] = (x[4 * i] + x[4 * i + 1]) + (x[4 * i + 2] + x[4 * i + 3]);
-    const float mean = quad_sum((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
+    for (int i = 0; i < 8; ++i) s8[i] = (x[4 * i] + x[4 * i + 1]) + (x[4 * i + 2] + x[4 * i + 3]);
+    const float mean =
+        pair_sum(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]))) *
+        (1.0f / kPolD);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       float t = 0.0f;
 #pragma unroll
       for (int c = 0; c < 4; ++c) t = fmaf(x[4 * i + c] - mean, x[4 * i + c] - mean, t);
-      s4[i] = t;
+      s8[i] = t;
     }
-    const float var = quad_sum((s4[0] + s4[1]) + (s4[2] + s4[3])) * (1.0f / kPolD);
+    const float var =
+        pair_sum(((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]))) *
+        (1.0f / kPolD);
     const float inv = rsqrtf(var + 1e-5f);
-    bf16x8 w[2];
+    bf16x8 w[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 8; ++i) {
       const float4 gv = gp[i], bv = bp[i];
       const float gg[4] = {gv.x, gv.y, gv.z, gv.w}, bb[4] = {bv.x, bv.y, bv.z, bv.w};
 #pragma unroll
@@ -115,9 +125,9 @@ __device__ __forceinline__ void layer_norm_rows(PolicyLds &L, int rows, const fl
         w[i >> 1][4 * (i & 1) + c] = __float2bfloat16(fmaf((x[4 * i + c] - mean) * inv, gg[c], bb[c]));
     }
     if (r < rows) {
-      bf16x8 *o = reinterpret_cast<bf16x8 *>(&L.xn[r][16 * q]);
-      o[0] = w[0];
-      o[1] = w[1];
+      bf16x8 *o = reinterpret_cast<bf16x8 *>(&L.xn[r][32 * q]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = w[i];
     }
   }
 }
