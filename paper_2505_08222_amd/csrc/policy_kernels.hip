@@ -50,11 +50,14 @@ constexpr int kLdVt = kPolRows + 8;              // row stride of V^T
 constexpr int kLdHid = 128 + 8;                  // row stride of the FFN hidden half
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 // the staging buffer: Q and K planes then V^T; or one half of the FFN hidden
-// layer; or the raw tokens; or the head's scratch (16 spare elements: the last
-// agent's attention reads up to 15 keys past its first row)
+// layer; or the raw tokens; or the head's scratch. The last agent of a tile
+// reads 16 keys from its first row on: up to row (at - 1) * n_tok + 15, which
+// passes the V^T row stride (kPolRows + 8) for n_tok = 5 (16 agents, row 90),
+// so spare elements follow the plane
+constexpr int kVtSpare = 16;
 constexpr int kBufElems =
-    cmax(cmax(2 * kPlane + kPolD * kLdVt, kPolRows * kLdHid),
-         cmax(kPolMaxAgents * (kPolD + 4) * 2, kPolRows * 6 * 2)) + 16;
+    cmax(cmax(2 * kPlane + kPolD * kLdVt + kVtSpare, kPolRows * kLdHid),
+         cmax(kPolMaxAgents * (kPolD + 4) * 2, kPolRows * 6 * 2));
 
 struct PolicyLds {
   float prm[kSmTotal];                    // small FP32 parameters
@@ -166,9 +169,11 @@ policy_kernel(PolicyArgs a) {
   const int rows = (rows_used + 15) & ~15;
   const int64_t ntiles = (a.A + at - 1) / at;
   for (int i = tid; i < kSmTotal; i += nthr) L.prm[i] = a.params[small_param_src(i)];
-  // the V^T plane's padding columns are read (and multiplied by zero) in
-  // attention but never written: start the whole plane at zero
-  for (int i = tid; i < kPolD * kLdVt; i += nthr) L.buf[2 * kPlane + i] = __bf16{};
+  // the V^T plane's padding columns, and with five tokens per agent the
+  // spare elements after the plane, are read in attention (and multiplied by
+  // a zero probability, which leaves a NaN or Inf in stale LDS standing) but
+  // never written: start them at zero
+  for (int i = tid; i < kPolD * kLdVt + kVtSpare; i += nthr) L.buf[2 * kPlane + i] = __bf16{};
   // raw tokens and masks of a tile are contiguous in memory; each thread
   // holds its share of the next tile's in registers while this one computes
   constexpr int kTokRegs = (kPolRows * 6 + 255) / 256;

@@ -13,10 +13,16 @@ from paper_2505_08222_amd.synth import policy_params, policy_tokens  # noqa: E40
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n_agents,n_targets", [(5, 5), (2, 2), (1, 1), (8, 8)])
-def test_policy_logits_and_actions(orc, n_agents, n_targets):
+# tiles of 80 token rows hold floor(80 / tokens) agents (at most 16); the
+# cases cover full and partial last tiles, token counts (7, 11) whose tiles
+# end inside a 16-row MFMA block, and five tokens, whose last agent's
+# attention reads keys past the V^T row stride
+@pytest.mark.parametrize("n_agents,n_targets,n_envs", [(5, 5, 64), (2, 2, 64), (1, 1, 64),
+                                                       (8, 8, 64), (5, 5, 13), (3, 4, 37),
+                                                       (6, 5, 21), (2, 3, 41)])
+def test_policy_logits_and_actions(orc, n_agents, n_targets, n_envs):
     from paper_2505_08222_amd import policy
-    A = 64 * n_agents
+    A = n_envs * n_agents
     x, mask = policy_tokens(A, n_agents, n_targets, seed=n_agents * 10 + n_targets)
     th = policy_params(orc.policy_num_params(), seed=3)
     n_tok = n_agents + n_targets
