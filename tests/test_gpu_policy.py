@@ -64,10 +64,11 @@ def test_policy_init_statistics():
     assert (p[layer0:layer0 + D] == 1).all() and (p[layer0 + D:layer0 + 2 * D] == 0).all()
 
 
-def test_policy_rollout_deterministic_and_graph():
+@pytest.mark.parametrize("n_agents,n_targets", [(5, 5), (2, 3)])
+def test_policy_rollout_deterministic_and_graph(n_agents, n_targets):
     from paper_2505_08222_amd import policy
     from paper_2505_08222_amd.env import Env
-    cfg = env_config("policy", episode_len=40)
+    cfg = env_config("policy", episode_len=40, n_agents=n_agents, n_targets=n_targets)
     E, T = 512, 40
     params = policy.init_params(0)
     rec = ("obs", "obs_mask", "reward", "done", "actions", "gstate")
