@@ -29,7 +29,7 @@
  *   pairs   [P]   P = sum n_agents*n_targets, pair (i,j) at i*n_targets + j
  *   tokens  [K]   K = sum n_agents*(n_agents+n_targets); agent i's tokens are
  *                 [self, the other agents in index order, the targets in
- *                 index order] (the TransfMAPPO entity tokens, Sec. III-B).
+ *                 index order] (the TransfMAPPO entity tokens, Sec. IV-B-1).
  * A handle is not thread-safe; distinct handles are independent.
  */
 #ifndef MI_LRAUV_H
@@ -72,17 +72,17 @@ typedef enum mil_status {
  *                       (agent,target) tracker keeps (3..16).
  *  episode_len          steps per episode; done is set on the last one and
  *                       stepping past it is an error (termination only at the
- *                       step limit, Sec. III-A-2 "Termination").
+ *                       step limit, Sec. IV-A-2 "Termination").
  *  n_actions, action_dpsi  heading change per discrete action (rad); the
  *                       paper's agents only steer at constant speed (Sec.
- *                       III-A-2 "Actions Space").
+ *                       IV-A-2 "Actions Space").
  *  gn_iters             Gauss-Newton refinements after the linearised
- *                       least-squares solve (0 = plain LS, Sec. II-A).
+ *                       least-squares solve (0 = plain LS, Sec. III-A).
  *  dt, agent_speed      step duration and constant agent speed; agents move
  *                       p += v dt (cos psi, sin psi) after turning (Sec.
- *                       III-A-3).
+ *                       IV-A-3).
  *  agent_heading_sigma  std of the Gaussian heading noise added each step
- *                       (0.02 rad in Sec. III-A-3).
+ *                       (0.02 rad in Sec. IV-A-3).
  *  target_heading_sigma std of the targets' random-walk heading jitter.
  *  target_speed_lo/hi   per-target constant speed, uniform in [lo, hi].
  *  range_sigma_lo/hi    per-env range-noise std, uniform in [lo, hi].
@@ -90,7 +90,7 @@ typedef enum mil_status {
  *                       [-area/2, area/2]^2; agents uniformly in the disk of
  *                       this radius about the centre.
  *  det_range            true distances beyond this give no range (the
- *                       paper's 450 m detection limit, Sec. III-A-2); INF
+ *                       paper's 450 m detection limit, Sec. IV-A-2); INF
  *                       disables it.
  *  comm_range, comm_loss_p  an agent receives another agent's position only
  *                       within comm_range and when that agent's broadcast is
@@ -132,7 +132,7 @@ typedef struct mil_env_layout {
  *  obs       [K][6] token = (dx, dy, dz, is_self, is_agent, is_target): the
  *            offset of the entity from the observing agent (other agents
  *            from what they broadcast, targets from the agent's own tracker)
- *            and a one-hot type (Sec. III-A-2 "Observation Space", TransfMAPPO
+ *            and a one-hot type (Sec. IV-A-2 "Observation Space", TransfMAPPO
  *            caption). A missing offset is written as zeros.
  *  obs_mask  [K] uint8, 1 if the offset is present.
  *  reward    [E] team reward: mean over targets of Eq. (1) on the best
@@ -162,7 +162,11 @@ typedef struct mil_env_outputs {
 typedef struct mil_env mil_env; /* opaque handle */
 
 /* Create a batch of num_envs environments (host only; no device memory is
- * touched). seed keys every random draw (Philox4x32-10, key = seed): ragged
+ * touched): the Gym-like tracking environment constructed from its agent and
+ * target counts (the UTrackingEnv interface sketched in Sec. IV-A-1, with the
+ * environment of Sec. IV-A-2 in its simplified GPU form of Sec. IV-A-3),
+ * batched over independent environments; each environment is one instance
+ * of the Dec-POMDP of Sec. III-B (n = agent count). seed keys every random draw (Philox4x32-10, key = seed): ragged
  * counts, spawns, noise and random actions. counts (optional, host [2][E]:
  * agents then targets) overrides the drawn ragged counts. */
 int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
@@ -175,15 +179,24 @@ int env_get_order(const mil_env *h, int64_t *env_ids, int64_t *agent_off, int64_
 /* Attach the caller's device workspace (>= workspace_bytes, 256-B aligned)
  * and upload the packed tables. Synchronous on `stream`. */
 int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream);
-/* Start episode `episode` in every env: spawn agents and targets, draw the
- * per-env range noise, clear trackers and metrics. outs may carry obs /
+/* Start episode `episode` in every env: reset() of the Gym-like interface
+ * (Sec. IV-A-1), returning the first observation and the global state.
+ * Spawn agents and targets, draw the per-env range noise, clear trackers
+ * and metrics. outs may carry obs /
  * obs_mask / gstate for the initial observation (other fields ignored). */
 int env_reset(mil_env *h, uint64_t episode, const mil_env_outputs *outs, void *stream);
-/* One step of every env. d_actions [A] int32 (packed agent order) or NULL
- * for uniformly random actions drawn in the kernel. */
+/* One step of every env: step(actions) of the Gym-like interface (Sec.
+ * IV-A-1), i.e. one transition P(s'|s,u) of the Dec-POMDP (Sec. III-B) with
+ * its shared reward r(s,u) (Eq. (1), normalised, crash penalty; Sec.
+ * IV-A-2) and per-agent observations O(s,a) (entity tokens, Sec. IV-A-2):
+ * turn and move every vehicle (Sec. IV-A-3), draw noisy ranges, update each
+ * tracker (Sec. III-A), observe, reward, done. d_actions [A] int32 (packed
+ * agent order) or NULL for uniformly random actions drawn in the kernel. */
 int env_step(mil_env *h, const int32_t *d_actions, const mil_env_outputs *outs, void *stream);
-/* T steps in one persistent launch; state stays in registers between steps.
- * d_actions [T][A] or NULL (random). Bit-identical to T calls of env_step. */
+/* T steps of env_step in one persistent launch (the many-step simulation on
+ * the GPU that Sec. IV-A-3 introduces; Table I measures its steps per
+ * second); state stays in registers between steps. d_actions [T][A] or NULL
+ * (random). Bit-identical to T calls of env_step. */
 int env_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
                 void *stream);
 /* Capture reset(episode) + rollout(T) + metrics reduction as one HIP graph on
@@ -233,7 +246,7 @@ int env_destroy(mil_env *h);
 /* Description of the last error on this thread (never NULL). */
 const char *env_last_error(void);
 
-/* Range-only localisation of N independent windows (Sec. II-A, linearised
+/* Range-only localisation of N independent windows (Sec. III-A, linearised
  * least squares about the window centroid, then gn_iters Gauss-Newton steps
  * on the range residuals). d_win [N][W][3] = (agent x, agent y, range); a NaN
  * range marks a missing entry. Outputs d_out [N][2], d_valid [N] (0 when fewer
@@ -251,7 +264,7 @@ int rng_philox(const uint32_t *d_ctr, int64_t n, uint64_t seed, uint32_t *d_out,
 
 
 /* ---------------------------------------------------------------------------
- * Learned range-only estimator (stands in for the exact solve of Sec. II-A;
+ * Learned range-only estimator (stands in for the exact solve of Sec. III-A;
  * the exact estimator remains its fallback and the judge of its error).
  * Network: 64 -> 128 -> 128 -> 2, GELU (tanh form) after each hidden layer.
  * Parameters: one FP32 vector of mlp_num_params() floats, in this order:
@@ -305,7 +318,7 @@ int mlp_infer(const float *d_win, int64_t N, int32_t W, const float *d_params,
 int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream);
 
 /* ---------------------------------------------------------------------------
- * Attention policy: the per-agent transformer actor of Sec. III-B
+ * Attention policy: the per-agent transformer actor of Sec. IV-B-1
  * (TransfMAPPO) without its recurrent token, forward only, BF16 MFMA with FP32
  * accumulation. Each agent's tokens (its observation, [self, agents, targets],
  * n_tok = n_agents + n_targets <= 16) are embedded 6 -> 64, pass 2 pre-LN

@@ -3,7 +3,7 @@
  * policy. TEST INFRASTRUCTURE ONLY (see lrauv_oracle.h).
  *
  * The learned estimator is not in the paper: it stands in for the per-target
- * range-only estimator of Sec. II-A. Its readings (features, output
+ * range-only estimator of Sec. III-A. Its readings (features, output
  * parameterisation, loss) are listed in the design doc; this file writes them out
  * plainly in FP64.
  *
@@ -256,7 +256,7 @@ void orc_range_refine(int64_t N, int W, const double *win, const double *centre,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Attention policy (the TransfMAPPO actor of Sec. III-B, without its        */
+/* Attention policy (the TransfMAPPO actor of Sec. IV-B-1, without its        */
 /* recurrent token; random initialisation, forward only). Tokens of one      */
 /* agent: [self, other agents, targets], each (dx, dy, dz, one-hot type).    */
 /* Pre-LN transformer: h = E x + e; for each layer: h += Wo MHA(LN1(h)) + bo,*/

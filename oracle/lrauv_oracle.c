@@ -102,7 +102,7 @@ void orc_env_counts(const orc_params *p, uint64_t seed, int64_t n, const int64_t
 }
 
 /* ------------------------------------------------------------------------ */
-/* Range-only localisation (Sec. II-A: trilateration linearised by least     */
+/* Range-only localisation (Sec. III-A: trilateration linearised by least     */
 /* squares). With a_k the agent positions and r_k the ranges, the squared    */
 /* range equations |a_k - p|^2 = r_k^2 are written about the window centroid */
 /* abar (p = abar + q, u_k = a_k - abar): 2 u_k.q - |q|^2 = |u_k|^2 - r_k^2. */
@@ -261,7 +261,7 @@ typedef struct {
   int comm_ok[OMAX];
 } oenv;
 
-/* Spawn (Sec. III-A-2 spawns entities on the surface / at depth with
+/* Spawn (Sec. IV-A-2 spawns entities on the surface / at depth with
  * pairwise spacing; the batched configurations instead place agents in a
  * disk about the centre of the area and targets uniformly in the square). */
 static void env_reset(const orc_params *p, uint64_t seed, uint64_t episode, oenv *E) {
@@ -296,8 +296,8 @@ static void env_reset(const orc_params *p, uint64_t seed, uint64_t episode, oenv
   }
 }
 
-/* Observation of agent i (Sec. III-A-2 "Observation Space"; token layout of
- * the TransfMAPPO actor, Sec. III-B): self, the other agents in index order,
+/* Observation of agent i (Sec. IV-A-2 "Observation Space"; token layout of
+ * the TransfMAPPO actor, Sec. IV-B-1): self, the other agents in index order,
  * the targets in index order. Each token is the relative 3D offset plus a
  * one-hot entity type. Other agents use what they broadcast (missing beyond
  * the comm range or when the broadcast was dropped); targets use agent i's
@@ -341,7 +341,7 @@ typedef struct {
   int32_t *actions;
 } ostep_out;
 
-/* One step t -> t+1 (Sec. III-A-2 step structure, Sec. III-A-3 kinematic
+/* One step t -> t+1 (Sec. IV-A-2 step structure, Sec. IV-A-3 kinematic
  * surrogate): agents turn then move, targets random-walk, ranges are measured
  * after the move, each (agent,target) tracker takes the new range into its
  * window and re-solves, then reward, observation and done are formed. */

@@ -9,15 +9,15 @@
  *
  * Paper: "Scaling Multi-Agent Reinforcement Learning for Underwater Acoustic
  * Tracking via Autonomous Vehicles" (arXiv 2505.08222).
- *   - kinematic surrogate and heading noise: Sec. III-A-3 (JaxLrauv);
- *   - step structure, per-(agent,target) tracker, spawn: Sec. III-A-2;
- *   - observation and global state: Sec. III-A-2, "Observation Space" and the
- *     TransfMAPPO figure caption (Sec. III-B);
+ *   - kinematic surrogate and heading noise: Sec. IV-A-3 (JaxLrauv);
+ *   - step structure, per-(agent,target) tracker, spawn: Sec. IV-A-2;
+ *   - observation and global state: Sec. IV-A-2, "Observation Space" and the
+ *     TransfMAPPO figure caption (Sec. IV-B-1);
  *   - tracking reward: Eq. (1); normalisation and crash penalty: text after
  *     Eq. (2);
- *   - range-only least-squares localisation: Sec. II-A;
+ *   - range-only least-squares localisation: Sec. III-A;
  *   - partial observability limits (450 m detection, 1500 m comms): Sec.
- *     III-A-2, "Why is UTracking a difficult environment?".
+ *     IV-A-2, "Why is UTracking a difficult environment?".
  * Where the paper is silent (RNG assignment, estimator guards, the multi-agent
  * tracking error) the oracle follows the readings listed in the design doc.
  *
@@ -106,7 +106,7 @@ void orc_env_counts(const orc_params *p, uint64_t seed, int64_t n,
                     const int64_t *env_ids, int32_t *n_agents, int32_t *n_targets);
 
 /* ---- range-only localisation of one target from one agent's window
- * (Sec. II-A, linearised least squares, optional Gauss-Newton on the range
+ * (Sec. III-A, linearised least squares, optional Gauss-Newton on the range
  * residuals). Inputs: n entries of agent position (ax, ay) and range r.
  * Returns 1 and writes (px, py) on success, 0 when fewer than 3 entries or
  * the conditioning guard fails. Pinned: exact recovery, numpy lstsq, grid

@@ -6,8 +6,8 @@ arithmetic of the method.
 
 Paper constants used as defaults (arXiv 2505.08222):
   * Eq. (1) thresholds eps_min = 10 m, eps_max = 50 m;
-  * agent heading noise 0.02 rad (Sec. III-A-3);
-  * detection range 450 m and communication range 1500 m (Sec. III-A-2). The
+  * agent heading noise 0.02 rad (Sec. IV-A-3);
+  * detection range 450 m and communication range 1500 m (Sec. IV-A-2). The
     batched workloads place targets uniformly in a square of 2-4 km with the
     agents near the centre, so the detection cut is lifted (det_range = inf)
     to keep every tracker busy; 450 m is kept as the "lost target" distance.

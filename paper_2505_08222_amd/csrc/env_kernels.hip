@@ -16,10 +16,10 @@
 // hands chunks of steps between wavefronts (see take_unit).
 //
 // Step semantics (arXiv 2505.08222): kinematic surrogate with heading noise
-// (Sec. III-A-3), noisy ranges after the move, one range-only least-squares
-// tracker per (agent, target) over the last W ranges (Sec. II-A, III-A-2),
+// (Sec. IV-A-3), noisy ranges after the move, one range-only least-squares
+// tracker per (agent, target) over the last W ranges (Sec. III-A, IV-A-2),
 // tracking reward Eq. (1) normalised by the number of targets with the crash
-// penalty (text after Eq. 2), entity-token observation (Sec. III-A-2 and the
+// penalty (text after Eq. 2), entity-token observation (Sec. IV-A-2 and the
 // TransfMAPPO caption), termination at the step limit only.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -488,7 +488,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     for (int step = s_begin; step < s_end; ++step) {
       const uint32_t t = (uint32_t)(t0 + step);
 
-      // ---- agent: action, heading noise, turn then move (Sec. III-A-3)
+      // ---- agent: action, heading noise, turn then move (Sec. IV-A-3)
       const u32x4 xa = draw(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
       int act;
       if (FULL && actions) {
@@ -637,7 +637,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       if (!observe) continue;  // phase 1 ends here: the estimator runs next
       const int filled = min((int)t + 1, W);
 
-      // ---- trackers (Sec. II-A): linearised LS about the centroid of the
+      // ---- trackers (Sec. III-A): linearised LS about the centroid of the
       // agent's window, FP64. With every entry present and no refinement the
       // agent's 2x2 matrix S = sum u u^T and G = sum u |u|^2 are shared by its
       // trackers and each tracker only adds g = G - sum u_k r_k^2 (the r-bar^2

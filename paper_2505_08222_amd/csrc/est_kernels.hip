@@ -4,7 +4,7 @@
 // est_exact: one thread per window. A block stages its windows through LDS
 // with coalesced 16-byte loads (the [N][W][3] layout is contiguous per
 // block), then every thread solves its own window in registers: linearised
-// least squares about the window centroid (arXiv 2505.08222, Sec. II-A) in
+// least squares about the window centroid (arXiv 2505.08222, Sec. III-A) in
 // FP64 (or FP32 on request), optionally refined by Gauss-Newton.
 #include <hip/hip_runtime.h>
 

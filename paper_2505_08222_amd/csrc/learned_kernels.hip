@@ -3,7 +3,7 @@
 // operands on the FP32 MFMA, for gradient checks), trained by hand-written
 // forward/backward kernels and Adam; inference is fused with the window
 // features, a residual test against the measured ranges and a compacted
-// exact-LS fallback (arXiv 2505.08222, Sec. II-A, is the exact estimator it
+// exact-LS fallback (arXiv 2505.08222, Sec. III-A, is the exact estimator it
 // stands in for).
 //
 // MFMA operand layout (16x16 output tile, lane l = 0..63): lane l supplies

@@ -1,5 +1,5 @@
 // Range-only least-squares localisation of one target from one tracker's
-// window, device side (arXiv 2505.08222, Sec. II-A: the squared-range
+// window, device side (arXiv 2505.08222, Sec. III-A: the squared-range
 // equations linearised by least squares). Shared by the environment
 // kernels and the batched estimator kernel.
 #pragma once

@@ -1,5 +1,5 @@
 // Attention policy of the full-rollout workload on gfx950: the per-agent
-// transformer actor of arXiv 2505.08222, Sec. III-B (TransfMAPPO, entity
+// transformer actor of arXiv 2505.08222, Sec. IV-B-1 (TransfMAPPO, entity
 // tokens, LayerNorm throughout), without its recurrent token; forward only.
 //
 // A persistent block (two per CU) takes tiles of agents (at most 80 token

@@ -3,7 +3,7 @@
 Every step runs in the HIP library; torch supplies device memory and the
 stream. Tensors follow the paper's definitions (arXiv 2505.08222):
   obs      [K, 6]  entity tokens (dx, dy, dz, is_self, is_agent, is_target) of
-                   every agent, agent-major, env by env (Sec. III-A-2 and the
+                   every agent, agent-major, env by env (Sec. IV-A-2 and the
                    TransfMAPPO caption)
   obs_mask [K]     1 where the offset is known
   reward   [E]     Eq. (1) tracking reward, normalised, -1 on a crash

@@ -1,6 +1,6 @@
 """Pins of the oracle's environment step (CPU only).
 
-Closed forms of the kinematic surrogate (Sec. III-A-3), noise-free ranges,
+Closed forms of the kinematic surrogate (Sec. IV-A-3), noise-free ranges,
 Eq. (1) worked values, the crash rule, and an end-to-end invariant: with
 noise-free ranges and static targets every tracker recovers its target
 exactly, so the tracking reward is 1 and each target token is the true offset.

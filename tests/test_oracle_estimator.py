@@ -1,6 +1,6 @@
 """Pins of the oracle's range-only estimator (CPU only).
 
-The linearised least-squares solve (Sec. II-A) is pinned to: exact recovery
+The linearised least-squares solve (Sec. III-A) is pinned to: exact recovery
 from noise-free ranges, numpy's SVD least squares on the same linear system,
 a brute-force grid search of the linearised objective, the invariances of the
 geometry, and (for the Gauss-Newton refinement) a brute-force grid search of

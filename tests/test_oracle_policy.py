@@ -1,7 +1,7 @@
 """Pins of the attention-policy oracle (CPU only): the forward pass against
 torch's float64 layers (layer_norm, linear, softmax attention with key
 masking, tanh GELU), permutation invariance over the non-self tokens (the
-property Sec. III-B builds on), and the inverse-CDF sampler."""
+property Sec. IV-B-1 builds on), and the inverse-CDF sampler."""
 import numpy as np
 import pytest
 
