@@ -937,7 +937,8 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
                                 dstate, t, 1, (uint32_t)episode, wact, o, st,
                                 mil::DevExt{1, nullptr, nullptr, win, sig}, h->sched);
       if (!lrc)
-        lrc = mlp_infer(win, Pn, h->P.window, d_mlp_params, sig, k_sigma, 0, h->P.guard_tau, est,
+        lrc = mlp_infer(win, Pn, h->P.window, d_mlp_params, sig, k_sigma, h->P.gn_iters,
+                        h->P.guard_tau, est,
                         flag, ws + ew.mlp, ew.mlp_bytes, st) == MIL_OK
                   ? 0
                   : -1;
