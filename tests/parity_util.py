@@ -33,6 +33,45 @@ def select(gpu_arr, csr_gpu, packed_idx, width=1):
     return np.concatenate(parts, axis=1)
 
 
+def track_condition(agent_hist, W):
+    """kappa(S) of each agent's tracker window at every step: S = sum of
+    u u^T over the last min(t+1, W) positions about their centroid.
+    agent_hist [T, A, >=2] (oracle positions) -> [T, A]."""
+    T, A = agent_hist.shape[:2]
+    kap = np.full((T, A), np.inf)
+    for t in range(T):
+        n = min(t + 1, W)
+        if n < 3:
+            continue
+        a = agent_hist[t - n + 1:t + 1, :, :2]
+        u = a - a.mean(0, keepdims=True)
+        sxx, syy = (u[..., 0] ** 2).sum(0), (u[..., 1] ** 2).sum(0)
+        sxy = (u[..., 0] * u[..., 1]).sum(0)
+        tr, det = sxx + syy, sxx * syy - sxy * sxy
+        disc = np.sqrt(np.maximum(tr * tr / 4 - det, 0.0))
+        lmin = tr / 2 - disc
+        with np.errstate(divide="ignore", invalid="ignore"):
+            kap[t] = np.where(lmin > 0, (tr / 2 + disc) / lmin, np.inf)
+    return kap
+
+
+KAPPA_BINS = ((1.0, 1e2), (1e2, 1e3), (1e3, 1e4), (1e4, np.inf))
+
+
+def kappa_bins(orc, na, nt, W, rel, valid):
+    """Fraction of valid end-to-end estimates within 1e-5 relative, by the
+    condition number of their agent's window."""
+    kap_a = track_condition(orc["agent"], W)
+    agent_of_pair = np.repeat(np.arange(int(na.sum())), np.repeat(nt, na))
+    kap = kap_a[:, agent_of_pair]
+    out = {}
+    for lo, hi in KAPPA_BINS:
+        m = valid & (kap >= lo) & (kap < hi)
+        out[f"{lo:g}-{hi:g}"] = (int(m.sum()), float((rel[m] <= REL).mean()) if m.any() else None,
+                                 float(np.median(rel[m])) if m.any() else None)
+    return out
+
+
 def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
     """gpu: dict of numpy [T, ...] arrays in packed order (all envs);
     orc: oracle rollout of the selected envs (in the order of packed_idx)."""
@@ -91,16 +130,28 @@ def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
     np.testing.assert_array_equal(gv, orc["est_valid"], err_msg=f"{label} estimate validity")
     pair_env = np.repeat(np.arange(E), na * nt)
     tol_est = REL * s + 4.0 * orc["sens"] * delta[:, pair_env]
-    tol_est = np.where(np.isfinite(tol_est), tol_est, np.inf)
     de = np.abs(ge - orc["est"]).max(-1)
     v = orc["est_valid"].astype(bool)
-    ratio = np.where(v, de / tol_est, 0.0)
+    # an estimate whose window sits on the guard's edge has no finite
+    # sensitivity (a tiny input change refuses it); it gets no free pass: it
+    # is counted, must stay rare, and is pinned exactly by the teacher-forced
+    # tests, which hand the GPU's own windows to the oracle
+    inf_sens = v & ~np.isfinite(tol_est)
+    report["est_infinite_sensitivity"] = int(inf_sens.sum())
+    assert inf_sens.sum() <= max(2, v.sum() // 200), f"{label}: {inf_sens.sum()} edge estimates"
+    tol_est = np.where(np.isfinite(tol_est), tol_est, REL * s)
+    ratio = np.where(v & ~inf_sens, de / tol_est, 0.0)
     report["est_max_ratio"] = float(ratio.max()) if ratio.size else 0.0
-    report["est_plain_rel_max"] = float((de[v] / s).max()) if v.any() else 0.0
-    report["est_frac_within_1e-5"] = float((de[v] / s <= REL).mean()) if v.any() else 1.0
+    den = np.maximum(np.abs(orc["est"]).max(-1), s)
+    rel = de / den
+    report["est_plain_rel_max"] = float(rel[v].max()) if v.any() else 0.0
+    report["est_frac_within_1e-5"] = float((rel[v] <= REL).mean()) if v.any() else 1.0
+    report["est_by_kappa"] = kappa_bins(orc, na, nt, cfg["window"], rel, v)
     assert report["est_max_ratio"] <= 1.0, f"{label} estimates differ beyond bound: {report}"
     # ---- tracking error, rewards, crash, done
-    tol_pair = np.where(v, tol_est, 0.0)
+    # downstream (tracking error, reward, tokens) an edge estimate carries the
+    # difference it actually has
+    tol_pair = np.where(v, np.where(inf_sens, de, tol_est), 0.0)
     tol_e = np.zeros((T, int(ct[-1])))
     for k in range(E):
         tp = tol_pair[:, cp[k]:cp[k + 1]].reshape(T, na[k], nt[k]).max(1)
@@ -109,7 +160,13 @@ def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
     o_err = orc["err"]
     assert (np.isinf(g_err) == np.isinf(o_err)).all(), f"{label} tracking-error presence"
     f = np.isfinite(o_err)
-    assert (np.abs(g_err[f] - o_err[f]) <= tol_e[f] + REL * s).all(), f"{label} tracking error"
+    lim = tol_e[f] + REL * np.maximum(np.abs(o_err[f]), s)
+    dif = np.abs(g_err[f] - o_err[f])
+    if not (dif <= lim).all():
+        w = np.argmax(dif - lim)
+        raise AssertionError(f"{label} tracking error: {dif[w]:.6g} beyond {lim[w]:.6g} "
+                             f"(oracle {o_err[f][w]:.6g}, gpu {g_err[f][w]:.6g}, "
+                             f"{int((dif > lim).sum())} of {dif.size})")
     grw = gpu["reward"][:, packed_idx]
     crash_g = grw == -1.0
     np.testing.assert_array_equal(crash_g, orc["crash"].astype(bool), err_msg=f"{label} crash")

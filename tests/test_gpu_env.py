@@ -67,7 +67,8 @@ def test_ragged_counts_match_oracle(orc):
 
 
 @pytest.mark.parametrize("name", ["plain", "batched_small", "ragged_small", "window16_5x5",
-                                  "gauss_newton", "detection_comm_loss"])
+                                  "gauss_newton", "detection_comm_loss", "fixed_8x8",
+                                  "fixed_7x6", "ragged_w3", "ragged_w7", "ragged_w12"])
 def test_rollout_parity(orc, name):
     if name == "plain":
         c = CONFIGS["plain"]
@@ -81,6 +82,13 @@ def test_rollout_parity(orc, name):
     elif name == "detection_comm_loss":  # missing ranges and dropped broadcasts
         cfg, E, T = env_config("ragged", episode_len=60, det_range=1200.0, comm_range=120.0,
                                comm_loss_p=0.3), 150, 60
+    elif name == "fixed_8x8":  # the largest shape class: 8 agents x 8 targets
+        cfg, E, T = env_config("batched", episode_len=60, n_agents=8, n_targets=8), 40, 60
+    elif name == "fixed_7x6":
+        cfg, E, T = env_config("batched", episode_len=60, n_agents=7, n_targets=6), 50, 60
+    elif name.startswith("ragged_w"):  # other window lengths (3..16 are accepted)
+        W = int(name[len("ragged_w"):])
+        cfg, E, T = env_config("ragged", episode_len=50, window=W), 200, 50
     else:
         cfg, E, T = env_config("ragged", episode_len=150), 300, 150
     seed = 0
