@@ -4,8 +4,11 @@
 One benchmark step = one replay of the captured HIP graph {reset, T-step
 persistent rollout writing observations, masks, rewards and done flags,
 metrics reduction} over the whole batch, inputs resident in HBM. Default
-workload: 4096 envs x 2 agents x 2 targets x 500 steps (the plain batched
-configuration). Prints one JSON line.
+(`--workload all`): the ragged batch (65536 envs, agents and targets uniform
+1..5 per env, 1000 steps) is the headline; the plain batched workload (4096
+envs x 2x2 x 500 steps, with an env-count sweep), the learned estimator and
+the closed loop with the attention policy follow as sections of the same JSON
+line. `--workload NAME` runs one of them alone.
 """
 import argparse
 import json
@@ -84,6 +87,29 @@ def copy_probe():
                       "launches": 3}), flush=True)
 
 
+def host_cpu():
+    """Cores the oracle may use on this host and what they are."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "usable_cores": usable}
+
+
+def oracle_threads():
+    """Every core this process may run on (the lease's share of the host)."""
+    return host_cpu()["usable_cores"]
+
+
 def cpu_baseline(cfg, env, T, budget_s):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload:
     whole episodes of the envs in packed order, 256 envs per call, recording
@@ -91,10 +117,10 @@ def cpu_baseline(cfg, env, T, budget_s):
     the next episode (a new reset draw) until the time budget is used."""
     from oracle import oracle as orc
 
-    threads = min(os.cpu_count() or 1, 16)
+    threads = oracle_threads()
     orc.lib()
     ids, na, nt = env.order["env_ids"], env.n_agents, env.n_targets
-    chunk = 256
+    chunk = 64 * threads
     done_envsteps = 0
     calls = 0
     t0 = time.perf_counter()
@@ -111,7 +137,7 @@ def cpu_baseline(cfg, env, T, budget_s):
     el = time.perf_counter() - t0
     envs_run = done_envsteps // T
     return {"value": done_envsteps / el, "unit": "env-steps/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
             "sample": f"{envs_run} env-episodes x {T} steps ({envs_run / len(ids):.2f} passes over "
                       f"the {len(ids)} envs, same seed and config, obs/mask/reward/done recorded), "
                       f"FP64 C with OpenMP over envs, {el:.1f} s"}
@@ -126,7 +152,7 @@ def cpu_baseline_policy(cfg, env, params, budget_s):
 
     from oracle import oracle as orc
 
-    threads = min(os.cpu_count() or 1, 16)
+    threads = oracle_threads()
     orc.lib()
     E, T = 16, 50
     ids, na, nt = env.order["env_ids"][:E], env.n_agents[:E], env.n_targets[:E]
@@ -148,7 +174,7 @@ def cpu_baseline_policy(cfg, env, params, budget_s):
         t_pol += t2 - t1
         done += 1
     return {"value": done * E * T / (t_env + t_pol), "unit": "env-steps/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", **host_cpu(),
             "sample": f"{done} x ({E} envs x {T} steps): oracle env rollout (FP64 C, OpenMP over "
                       f"envs, {t_env:.1f} s) + oracle policy forward on every agent-step (FP64 C, one "
                       f"thread, {t_pol:.1f} s)"}
@@ -197,13 +223,29 @@ def env_sweep(args, cfgname="batched", sizes=(4096, 16384, 65536, 262144, 104857
     return points
 
 
+TRAIN_BATCH = 8192
+
+
+def mlp_train_flops_per_sample(d_in=64, h=128, d_out=2):
+    """Algorithmic FLOPs of one training sample: forward, the three weight
+    gradients, and the input gradients of the second and output layers."""
+    fwd = 2 * (d_in * h + h * h + h * d_out)
+    return fwd + fwd + 2 * (h * d_out + h * h)
+
+
+def mlp_infer_flops_per_window(d_in=64, h=128, d_out=2):
+    return 2 * (d_in * h + h * h + h * d_out)
+
+
 def train_estimator(args):
     """The learned estimator's network, trained by the library's kernels on
     windows of ragged-configuration rollouts (W = 16): 1e7 windows, labels =
     exact estimates within 2x the mean range from tracks with condition
     number <= 1e3 (elsewhere the exact solve is noise, and those windows fall
-    back to it anyway), 8 epochs of Adam. Returns (params, history, seconds,
-    number of training windows)."""
+    back to it anyway), 8 epochs of Adam. Then 20 further steps on the same
+    data are timed with events (forward, backward, gradient reduction, Adam)
+    for the training roofline. Returns (params, info)."""
+    import numpy as np
     import torch
 
     from paper_2505_08222_amd import learned
@@ -217,25 +259,83 @@ def train_estimator(args):
     E = args.envs or c["num_envs"]
     t0 = time.perf_counter()
     tr = learned.rollout_windows(cfg, E, n_train, seed=0)
+    n_windows = int(tr["win"].shape[0])
     x, frame = learned.features(tr["win"])
     y = learned.targets(frame, tr["exact"])
     kap_tr = window_condition(tr["win"])
     keep = (y.norm(dim=1) <= 2.0) & (kap_tr <= 1e3)
     x, y = x[keep].contiguous(), y[keep].contiguous()
-    log(f"[learned] training set {x.shape[0]} of {tr['win'].shape[0]} windows "
+    del tr, frame, kap_tr, keep
+    log(f"[learned] training set {x.shape[0]} of {n_windows} windows "
         f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    params, hist = learned.train(x, y, epochs=8, batch=8192, lr=2e-3, lr_final=3e-5, seed=0,
-                                 log=lambda m: None)
+    params, hist = learned.train(x, y, epochs=8, batch=TRAIN_BATCH, lr=2e-3, lr_final=3e-5,
+                                 seed=0, log=lambda m: None)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     log(f"[learned] trained {len(hist)} logged steps in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
         f"{hist[-1][1]:.3e}")
-    return params, hist, train_s, int(x.shape[0])
+    # training step alone: a copy of the weights, 20 steps timed with events
+    p2 = params.clone()
+    opt = learned.Adam(p2, lr=3e-5)
+    work = learned._work(TRAIN_BATCH, "bf16", x.device)
+    gen = torch.Generator(device=x.device)
+    gen.manual_seed(1)
+    idx = [torch.randperm(x.shape[0], generator=gen, device=x.device)[:TRAIN_BATCH]
+           for _ in range(21)]
+    _, g = learned.loss_and_grad(x, y, p2, index=idx[0], work=work)
+    opt.step(g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for k in range(1, 21):
+        _, g = learned.loss_and_grad(x, y, p2, index=idx[k], work=work)
+        opt.step(g)
+    b.record(stream)
+    torch.cuda.synchronize()
+    step_ms = a.elapsed_time(b) / 20
+    flops = mlp_train_flops_per_sample() * TRAIN_BATCH
+    tflops = flops / (step_ms / 1e3) / 1e12
+    info = {"seconds": train_s, "windows_generated": n_windows, "train_windows": int(x.shape[0]),
+            "epochs": 8, "batch": TRAIN_BATCH, "loss_first": hist[0][1], "loss_last": hist[-1][1],
+            "step_ms": step_ms, "samples_per_s": TRAIN_BATCH / (step_ms / 1e3),
+            "mfma": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "flops_per_step": flops,
+                     "kernels": "mlp_backward (train tiles + gradient reduction) + mlp_adam_step"}}
+    del x, y, work, idx
+    torch.cuda.empty_cache()
+    return params, info
 
 
-def bench_learned(args):
+def cpu_baseline_exact(win_cpu, budget_s):
+    """The oracle's exact estimator (FP64 C, OpenMP over windows) on the
+    inference windows, closed form and with 8 Gauss-Newton steps: windows per
+    second, on as many windows as fit the time budget."""
+    from oracle import oracle as orc
+
+    threads = oracle_threads()
+    orc.lib()
+    out = {}
+    for gn in (0, 8):
+        n = min(len(win_cpu), 65536)
+        done, t0 = 0, time.perf_counter()
+        while True:
+            orc.ls_batch(win_cpu[:n], gn_iters=gn, n_threads=threads)
+            done += n
+            el = time.perf_counter() - t0
+            if el >= budget_s / 2 or done >= len(win_cpu) * 4:
+                break
+            n = min(len(win_cpu), n * 2)
+        out[f"gauss_newton_{gn}"] = {"value": done / el, "unit": "windows/s"}
+    return {"value": out["gauss_newton_0"]["value"], "unit": "windows/s (exact estimator, closed form)",
+            "cores": threads, "kind": "oracle", **host_cpu(), "by_kind": out,
+            "sample": f"the first windows of the inference set, FP64 C with OpenMP over windows, "
+                      f"closed form and 8 Gauss-Newton steps, about {budget_s / 2:.0f} s each"}
+
+
+def bench_learned(args, steps, cpu_seconds=None, trained=None):
     """Learned estimator (the learned-estimator configuration): windows of 16
     from ragged-configuration rollouts, Adam training of the BF16 MLP with the
     library's kernels, then guarded inference on a disjoint set, compared with
@@ -254,7 +354,7 @@ def bench_learned(args):
     if args.envs:  # smaller runs for quick checks
         n_infer = max(20000, int(n_infer * args.envs / c["num_envs"]))
     E = args.envs or c["num_envs"]
-    params, hist, train_s, n_fit = train_estimator(args)
+    params, train_info = trained if trained is not None else train_estimator(args)
     t0 = time.perf_counter()
     te = learned.rollout_windows(cfg, E, n_infer, seed=1, first_step=125)
     log(f"[learned] inference windows {te['win'].shape[0]} ({time.perf_counter() - t0:.1f} s)")
@@ -262,7 +362,7 @@ def bench_learned(args):
     N = win.shape[0]
     work = learned._work(N, "bf16", win.device)
 
-    def timed(fn, reps=max(1, args.steps)):
+    def timed(fn, reps=max(1, steps)):
         fn()
         torch.cuda.synchronize()
         evs = []
@@ -289,6 +389,7 @@ def bench_learned(args):
     rng_ = np.hypot(*(pt - win[:, :, :2].mean(1).cpu().numpy()).T)
     kap = window_condition(win).cpu().numpy()
     d_me = np.hypot(*(pm - pe).T)
+    d_et = np.hypot(*(pe - pt).T)
     bins = [(0, 100), (100, 500), (500, 1e9)]
     by_kappa = {}
     for lo, hi in [(1, 10), (10, 100), (100, 1e3), (1e3, np.inf)]:
@@ -305,34 +406,49 @@ def bench_learned(args):
         by_bin[name] = {
             "windows": int(mt.sum()), "accepted_frac": float(m.sum() / max(mt.sum(), 1)),
             "rms_learned_vs_exact_m": float(np.sqrt(np.mean(d_me[m] ** 2))) if m.any() else None,
-            "rms_exact_vs_truth_m": float(np.sqrt(np.mean(np.hypot(*(pe[mt] - pt[mt]).T) ** 2))) if mt.any() else None,
+            "rms_exact_vs_truth_m": float(np.sqrt(np.mean(d_et[mt] ** 2))) if mt.any() else None,
             "rms_final_vs_truth_m": float(np.sqrt(np.mean(np.hypot(*(pm[mt] - pt[mt]).T) ** 2))) if mt.any() else None,
         }
-    flops = 2.0 * (64 * 128 + 128 * 128 + 128 * 2) * N
+    # where the exact estimate is itself within 1 m of the truth (a well-posed
+    # window), how far the accepted network estimates are from it
+    wp = acc & ve & (d_et <= 1.0)
+    well_posed = {"windows": int((ve & (d_et <= 1.0)).sum()), "accepted": int(wp.sum()),
+                  "rms_learned_vs_exact_m": float(np.sqrt(np.mean(d_me[wp] ** 2))) if wp.any() else None}
+    flops = mlp_infer_flops_per_window() * N
     res = {
         "metric": METRIC,
         "value": ms_ex / ms_mlp,
         "unit": "x (exact FP64 LS time / guarded learned time, same GPU, same windows)",
-        "n_gpus": 1, "steps": max(1, args.steps), "warmup": 1, "ms_per_step": ms_mlp,
+        "n_gpus": 1, "steps": max(1, steps), "warmup": 1, "ms_per_step": ms_mlp,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": f"learned estimator: 16-entry windows from ragged-configuration "
-                               f"rollouts, train {n_fit}, infer {N}",
-                   "train_windows": int(n_fit), "infer_windows": int(N)},
+                               f"rollouts, train {train_info['train_windows']}, infer {N}",
+                   "train_windows": train_info["train_windows"], "infer_windows": int(N)},
         "infer_ms": {"learned_guarded": ms_mlp, "mlp_forward_only": ms_fwd,
                      "exact_fp64": ms_ex, "exact_fp32": ms_ex32, "exact_gauss_newton8": ms_gn},
+        "windows_per_s": {"learned_guarded": N / (ms_mlp / 1e3), "exact_fp64": N / (ms_ex / 1e3),
+                          "exact_gauss_newton8": N / (ms_gn / 1e3)},
         "speedup_vs": {"exact_fp64": ms_ex / ms_mlp, "exact_fp32": ms_ex32 / ms_mlp,
                        "exact_gauss_newton8": ms_gn / ms_mlp},
         "accepted_frac": float(acc.mean()),
         "rms_learned_vs_exact_m_accepted": float(np.sqrt(np.mean(d_me[acc & ve] ** 2))),
         "median_learned_vs_exact_m_accepted": float(np.median(d_me[acc & ve])),
+        "where_exact_within_1m_of_truth": well_posed,
         "by_range": by_bin,
         "by_condition": by_kappa,
-        "train": {"seconds": train_s, "loss_first": hist[0][1], "loss_last": hist[-1][1]},
-        "mfma": {"forward_tflops": flops / (ms_fwd / 1e3) / 1e12, "peak_tflops": 2500.0,
-                 "frac": flops / (ms_fwd / 1e3) / 1e12 / 2500.0},
+        "train": train_info,
+        "roofline": {"bound": "mfma", "achieved": flops / (ms_fwd / 1e3) / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": flops / (ms_fwd / 1e3) / 1e12 / 2500.0,
+                     "kernel": "forward_kernel", "kernel_ms": ms_fwd, "flops_per_launch": flops},
+        "guarded_inference_mfma_frac": flops / (ms_mlp / 1e3) / 1e12 / 2500.0,
         "gauss_newton_vs_truth_rms_m": float(np.sqrt(np.mean(np.hypot(*(pg[ve] - pt[ve]).T) ** 2))),
     }
+    if cpu_seconds:
+        log("[bench] cpu baseline (oracle), exact estimator on the inference windows")
+        res["cpu_baseline"] = cpu_baseline_exact(win.cpu().numpy().astype(np.float64), cpu_seconds)
+    del work, win, te
+    torch.cuda.empty_cache()
     return res
 
 
@@ -358,10 +474,12 @@ def policy_flops_per_agent_step(n_tok, d=64, heads=4, ffn=256, layers=2, n_out=8
     return 2 * n_tok * 6 * d + layers * per_layer + 2 * d * n_out
 
 
-def bench_policy(args):
+def bench_policy(args, steps, warmup, mlp="train", cpu_seconds=None):
     """Full rollout with the attention policy: 16384 envs x 5 agents x 5
     targets x 1000 steps, each step = policy forward on every agent's
-    observation, then the environment step, captured as one HIP graph."""
+    observation, then the environment step, captured as one HIP graph.
+    `mlp`: trained learned-estimator weights for the loop, "train" to train
+    them here, None for the exact estimator."""
     import numpy as np
     import torch
 
@@ -375,20 +493,23 @@ def bench_policy(args):
     T = c["steps"]
     torch.cuda.set_device(0)
     params = policy.init_params(c["seed"])
-    mlp = None if args.no_learned_loop else train_estimator(args)[0]
+    if args.no_learned_loop:
+        mlp = None
+    elif isinstance(mlp, str):
+        mlp = train_estimator(args)[0]
 
     def timed_loop(mlp_params):
         env = Env(cfg, E, seed=c["seed"])
         pr = policy.PolicyRollout(env, params, mlp_params=mlp_params, k_sigma=3.0)
         gout, gm = pr.capture(T, record=("reward", "done"))
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             pr.launch()
         torch.cuda.synchronize()
         stream = torch.cuda.current_stream()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         ev0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(steps):
             pr.launch()
         ev1.record(stream)
         torch.cuda.synchronize()
@@ -399,8 +520,9 @@ def bench_policy(args):
     exact_loop = None
     if mlp is not None:
         _, gm_exact, el_exact = timed_loop(None)
-        exact_loop = {"env_steps_per_s": E * T * args.steps / el_exact,
-                      "ms_per_step": el_exact * 1e3 / args.steps,
+        exact_loop = {"env_steps_per_s": E * T * steps / el_exact,
+                      "agent_steps_per_s": env.A * T * steps / el_exact,
+                      "ms_per_step": el_exact * 1e3 / steps,
                       "mean_reward": float(gm_exact[0] / max(float(gm_exact[6]), 1))}
     stream = torch.cuda.current_stream()
     # the policy kernel alone, on the final observation, timed with events
@@ -422,13 +544,13 @@ def bench_policy(args):
     tflops = flops / (pol_ms / 1e3) / 1e12
     m = gm.cpu().numpy()
     extra = {}
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        extra["cpu_baseline"] = cpu_baseline_policy(cfg, env, params, args.cpu_seconds)
+    if cpu_seconds:
+        log("[bench] cpu baseline (oracle), policy loop")
+        extra["cpu_baseline"] = cpu_baseline_policy(cfg, env, params, cpu_seconds)
     return {
-        "metric": METRIC, "value": E * T * args.steps / elapsed, "unit": "env-steps/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": E * T * steps / elapsed, "unit": "env-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": f"policy: {E} envs x 5 agents x 5 targets x {T} steps, attention "
                                "policy (d 64, 4 heads, 2 layers, FFN 256, random init) + env step "
@@ -437,7 +559,7 @@ def bench_policy(args):
                                + " per step, one HIP graph", "envs": E, "episode_steps": T,
                    "estimator": "learned" if mlp is not None else "exact"},
         "exact_estimator_loop": exact_loop,
-        "agent_steps_per_s": env.A * T * args.steps / elapsed,
+        "agent_steps_per_s": env.A * T * steps / elapsed,
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0,
                      "traffic": measured_traffic("policy_kernel", "policy") if E == c["num_envs"] else None,
@@ -449,52 +571,23 @@ def bench_policy(args):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched",
-                    choices=["plain", "batched", "ragged", "learned", "policy"])
-    ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the env-count sweep that follows the batched workload")
-    ap.add_argument("--no-learned-loop", action="store_true",
-                    help="policy workload: keep the exact estimator in the loop")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="only run the plain copy kernel used to calibrate HBM counters")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(environments are independent: a multi-GPU run would shard env ranges, "
-              "see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-
+def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
+    """A plain-step workload (plain, batched or ragged): the captured graph of
+    reset + rollout + metrics, replayed `steps` times after `warmup` replays;
+    the dominant kernel (the persistent rollout) timed alone with events on
+    its stream for the roofline."""
     import numpy as np
     import torch
 
     from paper_2505_08222_amd.configs import CONFIGS, env_config
     from paper_2505_08222_amd.env import Env
 
-    if args.copy_probe:
-        copy_probe()
-        return
-    if args.workload == "learned":
-        print(json.dumps(bench_learned(args)), flush=True)
-        return
-    if args.workload == "policy":
-        print(json.dumps(bench_policy(args)), flush=True)
-        return
-
-    c = CONFIGS[args.workload]
-    cfg = env_config(args.workload)
+    c = CONFIGS[workload]
+    cfg = env_config(workload)
     E = args.envs or c["num_envs"]
     T = c["steps"]
     torch.cuda.set_device(0)
-    log(f"[bench] workload={args.workload} envs={E} steps/episode={T}")
+    log(f"[bench] workload={workload} envs={E} steps/episode={T}")
     env = Env(cfg, E, seed=c["seed"])
     mapping = env.get_mapping()
     if not args.no_autotune:
@@ -504,7 +597,7 @@ def main():
         mapping = env.autotune(probe_steps=min(20, T), cache_path=cache)
         log(f"[bench] autotuned mapping lanes_per_agent={mapping[0]} waves_per_block={mapping[1]}")
     gout, gmetrics = env.capture_graph(T, episode=0, record=RECORD)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         env.launch_graph()
     torch.cuda.synchronize()
     log("[bench] warmup done")
@@ -513,15 +606,15 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(args.steps):
+    for _ in range(steps):
         env.launch_graph()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
-    log(f"[bench] timed {args.steps} graph replays: {gpu_ms:.3f} ms (events), {wall*1e3:.3f} ms wall")
+    log(f"[bench] timed {steps} graph replays: {gpu_ms:.3f} ms (events), {wall*1e3:.3f} ms wall")
     elapsed = max(wall, gpu_ms / 1e3)
-    env_steps = E * T * args.steps
+    env_steps = E * T * steps
     value = env_steps / elapsed
     m = gmetrics.cpu().numpy()
 
@@ -549,28 +642,28 @@ def main():
         "value": value,
         "unit": "env-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed * 1e3 / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {E} envs x {T} steps, "
+            "workload": f"{workload}: {E} envs x {T} steps, "
                         + ("agents and targets uniform 1..5 per env"
                            if cfg["ragged"] else f"{cfg['n_agents']} agents x {cfg['n_targets']} targets")
                         + f", window {cfg['window']}, one HIP graph (reset + rollout + metrics)",
             "envs": E, "episode_steps": T, "agents": int(env.A), "targets": int(env.Tt),
             "tokens": int(env.K), "lanes_per_agent": mapping[0], "waves_per_block": mapping[1],
         },
-        "agent_steps_per_s": float(env.A) * T * args.steps / elapsed,
+        "agent_steps_per_s": float(env.A) * T * steps / elapsed,
         "hbm_gbps_algorithmic": achieved,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("rollout_kernel", args.workload) if E == c["num_envs"] else None,
+            "traffic": measured_traffic("rollout_kernel", workload) if E == c["num_envs"] else None,
             "kernel": "rollout_kernel", "kernel_ms": kern_ms, "bytes_per_launch": alg_bytes,
         },
         "episode_metrics": {
@@ -581,13 +674,73 @@ def main():
     }
     if result["roofline"]["traffic"] is not None:
         result["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
-    if args.workload == "batched" and not args.no_sweep and E == c["num_envs"]:
+    if sweep and E == c["num_envs"]:
         del out, gout
         torch.cuda.empty_cache()
         result["sweep"] = env_sweep(args)
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        result["cpu_baseline"] = cpu_baseline(cfg, env, T, args.cpu_seconds)
+    if cpu_seconds:
+        log(f"[bench] cpu baseline (oracle), {workload}")
+        result["cpu_baseline"] = cpu_baseline(cfg, env, T, cpu_seconds)
+    env.close()
+    return result
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "plain", "batched", "ragged", "learned", "policy"])
+    ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the env-count sweep of the batched workload")
+    ap.add_argument("--no-learned-loop", action="store_true",
+                    help="policy workload: keep the exact estimator in the loop")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain copy kernel used to calibrate HBM counters")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(environments are independent: a multi-GPU run would shard env ranges, "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe()
+        return
+    cpu_s = None if args.no_cpu_baseline else args.cpu_seconds
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args, args.steps, cpu_seconds=cpu_s)), flush=True)
+        return
+    if args.workload == "policy":
+        print(json.dumps(bench_policy(args, args.steps, args.warmup, cpu_seconds=cpu_s)),
+              flush=True)
+        return
+    if args.workload != "all":
+        print(json.dumps(bench_env(args, args.workload, args.steps, args.warmup,
+                                   sweep=args.workload == "batched" and not args.no_sweep,
+                                   cpu_seconds=cpu_s)), flush=True)
+        return
+    # headline: the ragged batch, the largest single-GPU configuration
+    t_start = time.perf_counter()
+    result = bench_env(args, "ragged", args.steps, args.warmup, cpu_seconds=cpu_s)
+    # the other workloads, each with its own dominant kernel and CPU baseline;
+    # fewer replays for the long closed loop
+    sec_cpu = None if cpu_s is None else max(2.0, cpu_s / 2)
+    result["batched"] = bench_env(args, "batched", args.steps, args.warmup,
+                                  sweep=not args.no_sweep, cpu_seconds=sec_cpu)
+    mlp, train_info = train_estimator(args)
+    result["learned"] = bench_learned(args, args.steps, cpu_seconds=sec_cpu, trained=(mlp, train_info))
+    result["policy"] = bench_policy(args, min(args.steps, 3), min(args.warmup, 1), mlp=mlp,
+                                    cpu_seconds=sec_cpu)
+    for k in ("batched", "learned", "policy"):
+        for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
+            result[k].pop(key, None)
+    result["bench_seconds"] = time.perf_counter() - t_start
     print(json.dumps(result), flush=True)
 
 
