@@ -11,6 +11,30 @@ from paper_2505_08222_amd.synth import range_windows  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
+def bf16(a):
+    """Round float32 values to the nearest BF16 (ties to even), as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def param_blocks(d_in=64, h=128, d_out=2):
+    """[lo, hi) of W1, b1, W2, b2, W3, b3 in the parameter vector."""
+    sizes = [h * d_in, h, h * h, h, d_out * h, d_out]
+    edges = np.concatenate([[0], np.cumsum(sizes)])
+    return list(zip(edges[:-1], edges[1:]))
+
+
+def bf16_weights(th):
+    """The parameter vector with the two hidden layers' weight matrices
+    rounded to BF16, as the kernels' MFMA operands hold them."""
+    out = np.array(th, np.float32, copy=True)
+    (w1lo, w1hi), _, (w2lo, w2hi) = param_blocks()[:3]
+    out[w1lo:w1hi] = bf16(out[w1lo:w1hi])
+    out[w2lo:w2hi] = bf16(out[w2lo:w2hi])
+    return out
+
+
 def _params(orc, seed=0, scale=0.15):
     return np.random.default_rng(seed).normal(0, scale, orc.mlp_num_params()).astype(np.float32)
 
@@ -56,6 +80,18 @@ def test_gradient(orc, precision, tol):
     assert rel < tol, rel
     if precision == "fp32":
         np.testing.assert_allclose(g, rg, rtol=1e-3, atol=1e-5 * np.abs(rg).max())
+    else:
+        # element by element: each gradient entry is held to four times what
+        # rounding the inputs and weights to BF16 moves it in the FP64 oracle
+        # (the kernel also rounds the hidden activations, of the same order),
+        # plus 2^-7 of the RMS of its parameter block
+        _, rg16, _ = orc.mlp_backward(bf16(x[idx]).astype(np.float64), tgt[idx].astype(np.float64),
+                                      bf16_weights(th).astype(np.float64))
+        tol_e = 4.0 * np.abs(rg16 - rg)
+        for lo, hi in param_blocks():
+            tol_e[lo:hi] += 2.0 ** -7 * np.sqrt(np.mean(rg[lo:hi] ** 2))
+        bad = np.abs(g - rg) > tol_e
+        assert not bad.any(), (int(bad.sum()), np.flatnonzero(bad)[:10])
 
 
 def test_adam(orc):
@@ -157,6 +193,52 @@ def test_infer_decode_fits_distance_along_bearing(orc, trained_params):
     moved = np.hypot(*(ref - out).T)
     frac = (moved <= 0.05 + 1e-4 * rbar).mean()
     assert frac >= 0.99, (frac, np.percentile(moved, [50, 99, 100]))
+
+
+def test_infer_matches_oracle_chain(orc, trained_params):
+    """Accepted network estimates element by element against the oracle's
+    chain: window features -> FP64 network on the BF16-rounded features and
+    weights -> decode -> three distance steps along the bearing. Tolerance,
+    per window: the oracle chain's own change when the network output moves
+    by tol_y in either coordinate, where tol_y is eight times what rounding
+    the features and weights to BF16 moves the FP64 output (the kernel also
+    rounds both hidden layers' activations to BF16, an error of the same
+    order but not the same draw) plus one BF16 ulp (2^-7) of the output's
+    size."""
+    from paper_2505_08222_amd import learned
+    N = 20000
+    win = range_windows(N, 16, seed=41, far=800.0)
+    sigma = np.random.default_rng(8).uniform(0.5, 3.0, N).astype(np.float32)
+    out, flag = learned.infer(torch.from_numpy(win).cuda(), trained_params,
+                              torch.from_numpy(sigma).cuda(), k_sigma=3.0)
+    pg, acc = out.cpu().numpy().astype(np.float64), flag.cpu().numpy() == 1
+    assert acc.mean() > 0.5
+    th = trained_params.cpu().numpy()
+    w64 = win.astype(np.float64)
+    x, frame = orc.window_features(w64)
+    y_ref = orc.mlp_forward(x, th.astype(np.float64))
+    y_o = orc.mlp_forward(bf16(x.astype(np.float32)).astype(np.float64),
+                          bf16_weights(th).astype(np.float64))
+    centre = w64[..., :2].mean(1)
+
+    def chain(y):
+        return orc.range_refine(w64, centre, orc.mlp_decode(frame, y), iters=3)
+
+    p_o = chain(y_o)
+    tol_y = 8.0 * np.abs(y_o - y_ref).max(1) + 2.0 ** -7 * np.hypot(*y_o.T)
+    tol_p = np.zeros(N)
+    for k in range(2):
+        for sgn in (-1.0, 1.0):
+            yy = y_o.copy()
+            yy[:, k] += sgn * tol_y
+            tol_p = np.maximum(tol_p, np.hypot(*(chain(yy) - p_o).T))
+    dist = np.hypot(*(p_o - centre).T)
+    lim = tol_p + 1e-5 * dist + 1e-3
+    d = np.hypot(*(pg - p_o).T)
+    bad = acc & (d > lim)
+    print(f"accepted {acc.sum()}: median |gpu - oracle| {np.median(d[acc]):.3g} m, median bound "
+          f"{np.median(lim[acc]):.3g} m, worst ratio {(d[acc] / lim[acc]).max():.3g}")
+    assert not bad.any(), (int(bad.sum()), (d[bad] / lim[bad])[:10])
 
 
 def test_infer_acceptance_with_trained_network(trained_params):

@@ -95,6 +95,43 @@ def test_policy_rollout_deterministic_and_graph(n_agents, n_targets):
         np.testing.assert_array_equal(rc[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
 
 
+@pytest.mark.parametrize("learned_loop", [False, True])
+def test_closed_loop_actions_follow_oracle_policy(orc, learned_loop):
+    """In the closed loop, the action of step t is the oracle's inverse-CDF
+    draw from the oracle policy's logits on the loop's own observation of step
+    t - 1, with u from Philox(t, env id, agent, 4 | episode << 4) keyed by the
+    env seed: at least 95% agree at every checked step, and each disagreement
+    has u within 0.05 of a CDF boundary of the oracle's softmax."""
+    from paper_2505_08222_amd import learned, policy
+    from paper_2505_08222_amd.env import Env
+    cfg = env_config("policy", episode_len=24)
+    E, T, seed, episode = 96, 24, 3, 0
+    params = policy.init_params(2)
+    mlp = learned.init_params(7) if learned_loop else None
+    rec = ("obs", "obs_mask", "actions")
+    env = Env(cfg, E, seed=seed)
+    out, _ = policy.PolicyRollout(env, params, mlp_params=mlp, k_sigma=3.0).run(T, record=rec)
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    na, n_tok = cfg["n_agents"], cfg["n_agents"] + cfg["n_targets"]
+    A = E * na
+    th = params.cpu().numpy().astype(np.float64)
+    env_of = env.order["env_ids"][np.arange(A) // na]
+    for t in (1, 7, 15, 16, 23):
+        logits = orc.policy_forward(out["obs"][t - 1].reshape(A, n_tok, 6).astype(np.float64),
+                                    out["obs_mask"][t - 1].reshape(A, n_tok), th)
+        ctr = np.stack([np.full(A, t), env_of, np.arange(A) % na,
+                        np.full(A, (episode << 4) | 4)], 1).astype(np.uint32)
+        u = np.array([orc.u01(int(w)) for w in orc.philox(ctr, seed)[:, 0]])
+        want = np.array([orc.policy_sample(logits[a], cfg["n_actions"], u[a]) for a in range(A)])
+        got = out["actions"][t]
+        agree = (got == want).mean()
+        assert agree >= 0.95, (t, agree)
+        for a in np.flatnonzero(got != want):
+            p = np.exp(logits[a, :5] - logits[a, :5].max())
+            c = np.cumsum(p / p.sum())
+            assert np.min(np.abs(c - u[a])) < 0.05, (t, a)
+
+
 def test_policy_rejects_ragged():
     from paper_2505_08222_amd import policy
     from paper_2505_08222_amd._lib import MilError
