@@ -312,6 +312,20 @@ int mlp_adam_step(int64_t P, float *d_params, const float *d_grad, float *d_m, f
 int mlp_infer(const float *d_win, int64_t N, int32_t W, const float *d_params,
               const float *d_sigma, float k_sigma, int32_t gn_iters, float tau, float *d_out,
               uint8_t *d_flag, void *d_work, int64_t work_bytes, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mlp_infer
+ * with no workspace argument. Same kernels and results as mlp_infer (bit for
+ * bit). Its scratch (BF16 weight copies, the fallback counter and list) is one
+ * static device array of about 4.4 MB per GPU, held until the process ends;
+ * N above MIL_NOALLOC_MAX_WINDOWS is rejected with MIL_EINVAL. Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller. Allocates nothing
+ * (no hipMalloc, no hipFree); the array's address is looked up once per device
+ * on first use. Errors: as mlp_infer, plus MIL_EHIP if the lookup fails. */
+#define MIL_NOALLOC_MAX_WINDOWS (1 << 20)
+int mlp_infer_noalloc(const float *d_win, int64_t N, int32_t W, const float *d_params,
+                      const float *d_sigma, float k_sigma, int32_t gn_iters, float tau,
+                      float *d_out, uint8_t *d_flag, void *stream);
 /* Every tracker's current window of a bound environment: d_win [P][W][3]
  * (entry 0 = newest), d_sigma [P] its env's range-noise std, d_truth [P][2]
  * the true target position (either may be NULL). */

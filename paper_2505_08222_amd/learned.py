@@ -106,6 +106,23 @@ def infer(win: torch.Tensor, params: torch.Tensor, sigma: torch.Tensor, k_sigma=
     return out, flag
 
 
+def infer_noalloc(win: torch.Tensor, params: torch.Tensor, sigma: torch.Tensor, k_sigma=3.0,
+                  gn_iters=0, tau=1e-4, out=None, flag=None):
+    """infer() without a workspace: the library's static scratch (at most
+    MIL_NOALLOC_MAX_WINDOWS windows per call; calls on one GPU must not overlap).
+    `out` and `flag` may be given preallocated."""
+    win = win.contiguous()
+    N, W, _ = win.shape
+    if out is None:
+        out = torch.empty((N, 2), dtype=torch.float32, device=win.device)
+    if flag is None:
+        flag = torch.empty((N,), dtype=torch.uint8, device=win.device)
+    check(lib().mlp_infer_noalloc(ptr(win), N, W, ptr(params), ptr(sigma.contiguous()),
+                                  float(k_sigma), int(gn_iters), float(tau), ptr(out), ptr(flag),
+                                  _stream()))
+    return out, flag
+
+
 def env_windows(env: Env):
     """Current windows of every tracker: (win [P, W, 3], sigma [P], truth [P, 2])."""
     W = env.layout.window

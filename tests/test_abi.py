@@ -127,3 +127,14 @@ def test_calls_out_of_order_are_rejected(milib):
     assert L.env_bind(h, C.c_void_p(0x1001), 1 << 30, None) == -3  # misaligned
     L.env_destroy(h)
     assert L.est_exact(None, 10, 2, 0, C.c_float(1e-4), 0, None, None, None) == -1
+
+
+def test_noalloc_inference_rejects_oversized_batches(milib):
+    """The workspace-free inference refuses more windows than its static
+    scratch holds, before touching any device."""
+    L = milib.lib()
+    too_many = (1 << 20) + 1
+    rc = L.mlp_infer_noalloc(None, too_many, 16, None, None, 3.0, 0, 1e-4, None, None, None)
+    assert rc == -1
+    assert b"MIL_NOALLOC_MAX_WINDOWS" in L.env_last_error()
+    assert L.mlp_infer_noalloc(None, 0, 16, None, None, 3.0, 0, 1e-4, None, None, None) == 0
