@@ -295,10 +295,23 @@ int mlp_forward(int64_t N, const float *d_x, const float *d_params, float *d_y, 
                 void *d_work, int64_t work_bytes, void *stream);
 /* Mean over the N samples of |y - target|^2 into *d_loss (may be NULL) and
  * its gradient into d_grad [mlp_num_params()]. Sample s reads row
- * d_index[s] of d_x and d_target (d_index NULL: row s). Deterministic. */
+ * d_index[s] of d_x and d_target (d_index NULL: row s). Deterministic.
+ * Precision 0 needs d_x and d_params 16-byte aligned (MIL_EALIGN). */
 int mlp_backward(int64_t N, const float *d_x, const int64_t *d_index, const float *d_target,
                  const float *d_params, float *d_grad, float *d_loss, int32_t precision,
                  void *d_work, int64_t work_bytes, void *stream);
+/* One Adam step of the BF16 network on N samples: the gradient of
+ * mlp_backward (precision 0, same sample selection, deterministic) and the
+ * Adam update of mlp_adam_step applied to it, in two kernels: a persistent
+ * kernel whose blocks each accumulate the weight gradients of several
+ * 32-sample tiles in registers, then a fixed-order reduction that updates
+ * d_params, d_m, d_v in place. d_grad (may be NULL) receives the gradient,
+ * d_loss (may be NULL) the loss before the update. Workspace as for
+ * mlp_backward with precision 0. */
+int mlp_train_step(int64_t N, const float *d_x, const int64_t *d_index, const float *d_target,
+                   float *d_params, float *d_m, float *d_v, float lr, float beta1, float beta2,
+                   float eps, int32_t step, float *d_grad, float *d_loss, void *d_work,
+                   int64_t work_bytes, void *stream);
 /* Adam (Kingma and Ba) with bias correction on P parameters; step >= 1. */
 int mlp_adam_step(int64_t P, float *d_params, const float *d_grad, float *d_m, float *d_v,
                   float lr, float beta1, float beta2, float eps, int32_t step, void *stream);

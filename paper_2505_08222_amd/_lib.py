@@ -124,6 +124,7 @@ def _register_learned(L):
         "mlp_forward": [I64, V, V, V, I32, V, I64, V],
         "mlp_backward": [I64, V, V, V, V, V, V, I32, V, I64, V],
         "mlp_adam_step": [I64, V, V, V, V, F, F, F, F, I32, V],
+        "mlp_train_step": [I64, V, V, V, V, V, V, F, F, F, F, I32, V, V, V, I64, V],
         "mlp_infer": [V, I64, I32, V, V, F, I32, F, V, V, V, I64, V],
         "mlp_infer_noalloc": [V, I64, I32, V, V, F, I32, F, V, V, V],
         "env_windows": [V, V, V, V, V],

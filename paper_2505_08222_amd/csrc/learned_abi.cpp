@@ -22,7 +22,7 @@ WorkLayout work_layout(int64_t N, int precision) {
   o = align256(o + mil::kPrepBytes);
   const int64_t nb = mil::train_blocks(N > 0 ? N : 1, precision);
   w.partial = o;
-  o = align256(o + nb * mil::kNumParams * 4);
+  o = align256(o + nb * mil::train_partial_floats(precision) * 4);
   w.loss_partial = o;
   o = align256(o + nb * 4);
   w.fb_count = o;
@@ -113,11 +113,14 @@ int mlp_backward(int64_t N, const float *d_x, const int64_t *d_index, const floa
                  void *d_work, int64_t work_bytes, void *stream) {
   if (N < 1 || (precision != 0 && precision != 1)) return set_error(MIL_EINVAL, "bad N or precision");
   if (!d_x || !d_target || !d_params || !d_grad) return set_error(MIL_EINVAL, "null argument");
+  if (precision == 0 && ((((uintptr_t)d_x) | ((uintptr_t)d_params)) & 15))
+    return set_error(MIL_EALIGN, "d_x and d_params must be 16-byte aligned");
   const WorkLayout w = work_layout(N, precision);
   int rc = check_work(d_work, work_bytes, w.fb_count);
   if (rc) return rc;
   char *ws = (char *)d_work;
-  if (mil::launch_prepare(d_params, precision, ws + w.prep, stream) ||
+  // BF16: the training kernel converts its weight fragments itself
+  if ((precision != 0 && mil::launch_prepare(d_params, precision, ws + w.prep, stream)) ||
       mil::launch_train(N, d_x, d_index, d_target, d_params, precision, ws + w.prep,
                         (float *)(ws + w.partial), (float *)(ws + w.loss_partial), d_grad, d_loss,
                         stream))
@@ -133,6 +136,27 @@ int mlp_adam_step(int64_t P, float *d_params, const float *d_grad, float *d_m, f
   if (!d_params || !d_grad || !d_m || !d_v) return set_error(MIL_EINVAL, "null argument");
   if (mil::launch_adam(P, d_params, d_grad, d_m, d_v, lr, beta1, beta2, eps, step, stream))
     return set_error(MIL_EHIP, "adam launch failed");
+  return MIL_OK;
+}
+
+int mlp_train_step(int64_t N, const float *d_x, const int64_t *d_index, const float *d_target,
+                   float *d_params, float *d_m, float *d_v, float lr, float beta1, float beta2,
+                   float eps, int32_t step, float *d_grad, float *d_loss, void *d_work,
+                   int64_t work_bytes, void *stream) {
+  if (N < 1 || step < 1) return set_error(MIL_EINVAL, "need N >= 1 and step >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return set_error(MIL_EINVAL, "bad Adam constants");
+  if (!d_x || !d_target || !d_params || !d_m || !d_v) return set_error(MIL_EINVAL, "null argument");
+  if ((((uintptr_t)d_x) | ((uintptr_t)d_params)) & 15)
+    return set_error(MIL_EALIGN, "d_x and d_params must be 16-byte aligned");
+  const WorkLayout w = work_layout(N, 0);
+  int rc = check_work(d_work, work_bytes, w.fb_count);
+  if (rc) return rc;
+  char *ws = (char *)d_work;
+  if (mil::launch_train_step(N, d_x, d_index, d_target, d_params, d_m, d_v, lr, beta1, beta2, eps,
+                             step, (float *)(ws + w.partial), (float *)(ws + w.loss_partial),
+                             d_grad, d_loss, stream))
+    return set_error(MIL_EHIP, "training step launch failed");
   return MIL_OK;
 }
 

@@ -22,6 +22,9 @@ constexpr int kLdH = kHidden + 8;
 // samples per training tile
 constexpr int kTileBf16 = 32;
 constexpr int kTileF32 = 16;
+// most blocks (partial gradients) of the persistent BF16 training kernel:
+// batches beyond kTrainBlocks tiles give each block several tiles
+constexpr int kTrainBlocks = 128;
 // bytes of the MFMA-ready weights (W1, W2, W2^T) for FP32 operands (the
 // larger of the two precisions)
 constexpr int64_t kPrepBytes = (int64_t)(kHidden * kLdIn + 2 * kHidden * kLdH) * 4;
@@ -33,9 +36,17 @@ int launch_targets(const float *frame, const float *p, int64_t N, float *y, void
 int launch_forward(int64_t N, const float *x, const float *th, int precision, const void *prep,
                    float *y, void *stream);
 int64_t train_blocks(int64_t N, int precision);
+// floats of one block's partial gradient
+int64_t train_partial_floats(int precision);
 int launch_train(int64_t N, const float *x, const int64_t *index, const float *target,
                  const float *th, int precision, const void *prep, float *partial,
                  float *loss_partial, float *grad, float *loss, void *stream);
+// BF16 training step: gradient (d_grad may be null) and, when m and v are
+// given, the Adam update of th, in two kernels
+int launch_train_step(int64_t N, const float *x, const int64_t *index, const float *target,
+                      float *th, float *m, float *v, float lr, float b1, float b2, float eps,
+                      int32_t step, float *partial, float *loss_partial, float *grad, float *loss,
+                      void *stream);
 int launch_adam(int64_t P, float *th, const float *g, float *m, float *v, float lr, float b1,
                 float b2, float eps, int32_t step, void *stream);
 int launch_infer(const float *win, int64_t N, int32_t W, const float *th, const void *prep,

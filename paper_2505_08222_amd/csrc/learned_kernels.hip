@@ -353,6 +353,518 @@ __global__ void adam_kernel(int64_t P, float *__restrict__ th, const float *__re
 }
 
 // ---------------------------------------------------------------------------
+// Training step, BF16 operands, persistent form. G blocks of four wavefronts;
+// block b takes the 32-sample tiles b, b + G, b + 2G, ... in that order and
+// keeps the two hidden layers' weight gradients in its MFMA accumulators
+// (registers) across its tiles, so that it writes one partial gradient per
+// block instead of one per tile. Each wavefront owns fixed output tiles of
+// every product, so its weight fragments are converted from the FP32 master
+// copy once per launch (no separate preparation kernel). The partial is
+// stored in accumulator order (one float4 per lane, coalesced); the
+// reduction maps it back to the parameter layout.
+//
+// Products per tile (S = 32 samples, features 128, inputs 64):
+//   Z1 = X W1^T, Z2 = H1 W2^T         weights as the MFMA's A operand, so a
+//                                      lane holds 4 consecutive features of
+//                                      one sample (bias, GELU, derivative)
+//   dW2 += dZ2^T H1, dW1 += dZ1^T X    accumulated, K = the tile's samples
+//   dH1 = dZ2 W2                       weights (W2^T rows) as the A operand
+// GELU is the tanh form x sigma(2y) evaluated as x / (1 + 2^u) (the same
+// function as the inference kernel's); its derivative, with s = sigma(2y),
+// is s + x s (1 - s) (-ln 2) du/dx.
+// ---------------------------------------------------------------------------
+constexpr int kStepS = 32;
+// partial vector: dW2 fragments, dW1 fragments, then b1, b2, W3, b3
+constexpr int kPartW2 = 0;
+constexpr int kPartW1 = kHidden * kHidden;
+constexpr int kPartSmall = kPartW1 + kHidden * kIn;
+constexpr int kPartFloats = ((kPartSmall + 2 * kHidden + kOut * kHidden + kOut) + 15) / 16 * 16;
+
+struct StepLds {
+  __bf16 x[kStepS][kIn + 8];         // X, sample-major
+  __bf16 xt[kIn][kStepS + 8];        // X^T
+  __bf16 h1[kStepS][kHidden + 8];    // H1 = gelu(Z1)
+  __bf16 h1t[kHidden][kStepS + 8];   // H1^T
+  union {
+    struct {
+      __bf16 h2[kStepS][kHidden + 8];    // H2 = gelu(Z2)
+      __bf16 h2t[kHidden][kStepS + 8];   // H2^T
+      __bf16 dz2[kStepS][kHidden + 8];   // dZ2, sample-major
+      __bf16 dz2t[kHidden][kStepS + 8];  // dZ2^T
+      __bf16 dz1t[kHidden][kStepS + 8];  // dZ1^T
+    } t;
+    __bf16 w2[kHidden][kHidden + 8];     // W2 staged for the fragments (set-up only)
+  } u;
+  float w3[kOut][kHidden];
+  float tg[kStepS][kOut];            // targets
+  float dyt[kOut][kStepS];           // dY^T
+  float se[kStepS];                  // squared error per sample
+};
+
+__device__ __forceinline__ void gelu_and_grad(float z, float &h, float &g) {
+  constexpr float a = -2.0f * 0.7978845608028654f * 1.4426950408889634f;
+  constexpr float b = a * 0.044715f;
+  constexpr float ln2 = 0.6931471805599453f;
+  const float z2 = z * z;
+  const float u = z * fmaf(b, z2, a);
+  const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
+  h = z * sg;
+  g = fmaf(z * sg * (1.0f - sg) * (-ln2), fmaf(3.0f * b, z2, a), sg);
+}
+
+// 8 consecutive FP32 weights as one BF16 fragment
+__device__ __forceinline__ bf16x8 frag8(const float *p) {
+  const float4 lo = *reinterpret_cast<const float4 *>(p);
+  const float4 hi = *reinterpret_cast<const float4 *>(p + 4);
+  bf16x8 r;
+  r[0] = __float2bfloat16(lo.x); r[1] = __float2bfloat16(lo.y);
+  r[2] = __float2bfloat16(lo.z); r[3] = __float2bfloat16(lo.w);
+  r[4] = __float2bfloat16(hi.x); r[5] = __float2bfloat16(hi.y);
+  r[6] = __float2bfloat16(hi.z); r[7] = __float2bfloat16(hi.w);
+  return r;
+}
+
+__device__ __forceinline__ float dot8(const bf16x8 h, const float4 a, const float4 b, float acc) {
+  acc = fmaf(a.x, to_f(h[0]), acc);
+  acc = fmaf(a.y, to_f(h[1]), acc);
+  acc = fmaf(a.z, to_f(h[2]), acc);
+  acc = fmaf(a.w, to_f(h[3]), acc);
+  acc = fmaf(b.x, to_f(h[4]), acc);
+  acc = fmaf(b.y, to_f(h[5]), acc);
+  acc = fmaf(b.z, to_f(h[6]), acc);
+  return fmaf(b.w, to_f(h[7]), acc);
+}
+
+__global__ void __launch_bounds__(256, 1)
+train_accum_kernel(int64_t N, int64_t ntiles, const float *__restrict__ xin,
+                   const int64_t *__restrict__ index, const float *__restrict__ target,
+                   const float *__restrict__ th, float *__restrict__ partial,
+                   float *__restrict__ loss_partial, float inv_n) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  StepLds &L = *reinterpret_cast<StepLds *>(smem);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int row = lane & 15, kg = lane >> 4;
+  // this thread's share of a tile's inputs: sample xs, inputs 8 xq .. 8 xq + 7
+  // (and, for xq = 0, the sample's target); the first tile's rows are
+  // requested before the weights
+  const int xs = tid >> 3, xq = tid & 7;
+  float4 xa = make_float4(0.f, 0.f, 0.f, 0.f), xb = xa;
+  float2 tgv = make_float2(0.f, 0.f);
+  auto fetch = [&](int64_t tile) {
+    const int64_t s = tile * kStepS + xs;
+    xa = make_float4(0.f, 0.f, 0.f, 0.f);
+    xb = xa;
+    tgv = make_float2(0.f, 0.f);
+    if (tile < ntiles && s < N) {
+      const int64_t src = index ? index[s] : s;
+      const float4 *p = reinterpret_cast<const float4 *>(xin + src * kIn + 8 * xq);
+      xa = p[0];
+      xb = p[1];
+      if (xq == 0) tgv = make_float2(target[src * 2], target[src * 2 + 1]);
+    }
+  };
+  fetch(blockIdx.x);
+  // ---- weight fragments (A operands) of W1, biases of this lane's
+  // features, W2 staged in LDS as BF16 (coalesced reads: all loads issued
+  // before the first store), W3
+  bf16x8 w1f[2][2], w2f[2][4], w2tf[2][4];
+  float b1r[2][4], b2r[2][4];
+  {
+    float4 w2raw[8][2];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = tid + 256 * k, o = e >> 4, i8 = (e & 15) << 3;
+      const float4 *src = reinterpret_cast<const float4 *>(th + kOffW2 + o * kHidden + i8);
+      w2raw[k][0] = src[0];
+      w2raw[k][1] = src[1];
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int n = ((wave + 4 * c) << 4) + row;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) w1f[c][ks] = frag8(th + kOffW1 + n * kIn + 32 * ks + 8 * kg);
+      const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        b1r[c][j] = th[kOffB1 + nf + j];
+        b2r[c][j] = th[kOffB2 + nf + j];
+      }
+    }
+    const float w3a = th[kOffW3 + tid];  // 256 threads = the 2 x 128 W3 entries
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = tid + 256 * k, o = e >> 4, i8 = (e & 15) << 3;
+      bf16x8 r;
+      r[0] = __float2bfloat16(w2raw[k][0].x); r[1] = __float2bfloat16(w2raw[k][0].y);
+      r[2] = __float2bfloat16(w2raw[k][0].z); r[3] = __float2bfloat16(w2raw[k][0].w);
+      r[4] = __float2bfloat16(w2raw[k][1].x); r[5] = __float2bfloat16(w2raw[k][1].y);
+      r[6] = __float2bfloat16(w2raw[k][1].z); r[7] = __float2bfloat16(w2raw[k][1].w);
+      *reinterpret_cast<bf16x8 *>(&L.u.w2[o][i8]) = r;
+    }
+    L.w3[tid / kHidden][tid % kHidden] = w3a;
+  }
+  __syncthreads();
+  float w3r[2][4][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int n = ((wave + 4 * c) << 4) + row;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      w2f[c][ks] = *reinterpret_cast<const bf16x8 *>(&L.u.w2[n][32 * ks + 8 * kg]);
+      bf16x8 t;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = L.u.w2[32 * ks + 8 * kg + q][n];
+      w2tf[c][ks] = t;
+    }
+    const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      w3r[c][j][0] = L.w3[0][nf + j];
+      w3r[c][j][1] = L.w3[1][nf + j];
+    }
+  }
+  // ---- accumulators: dW2 (o tiles 2w, 2w+1 x 8 i tiles), dW1 (x 4 i tiles)
+  floatx4 acc2[2][8], acc1[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc2[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc1[a][b] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  float acc_w3 = 0.0f, acc_b3 = 0.0f, acc_b1 = 0.0f, acc_b2 = 0.0f, acc_loss = 0.0f;
+  float b3v[2] = {th[kOffB3], th[kOffB3 + 1]};
+  __syncthreads();  // the W2 staging area becomes the tile's buffers
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t s0 = tile * kStepS;
+    // ---- X tile into LDS (the previous tile's last reads of x / xt are
+    // behind the barrier that ends it), then fetch the next tile's rows
+    {
+      bf16x8 v;
+      v[0] = __float2bfloat16(xa.x); v[1] = __float2bfloat16(xa.y);
+      v[2] = __float2bfloat16(xa.z); v[3] = __float2bfloat16(xa.w);
+      v[4] = __float2bfloat16(xb.x); v[5] = __float2bfloat16(xb.y);
+      v[6] = __float2bfloat16(xb.z); v[7] = __float2bfloat16(xb.w);
+      *reinterpret_cast<bf16x8 *>(&L.x[xs][8 * xq]) = v;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) L.xt[8 * xq + q][xs] = v[q];
+      if (xq == 0) {
+        L.tg[xs][0] = tgv.x;
+        L.tg[xs][1] = tgv.y;
+      }
+    }
+    fetch(tile + gridDim.x);
+    __syncthreads();
+    // ---- layer 1: Z1 = X W1^T + b1 (lane: features nf..nf+3 of sample m);
+    // gelu'(Z1) stays in this lane's registers for the backward pass
+    float g1r[2][2][4], g2r[2][2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int m = (mt << 4) + row;
+      bf16x8 xf[2];
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+        xf[ks] = *reinterpret_cast<const bf16x8 *>(&L.x[m][32 * ks + 8 * kg]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1f[c][ks], xf[ks], acc, 0, 0, 0);
+        const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+        bf16x4 hv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float h;
+          gelu_and_grad(acc[j] + b1r[c][j], h, g1r[mt][c][j]);
+          hv[j] = __float2bfloat16(h);
+          L.h1t[nf + j][m] = hv[j];
+        }
+        *reinterpret_cast<bf16x4 *>(&L.h1[m][nf]) = hv;
+      }
+    }
+    __syncthreads();
+    // ---- layer 2: Z2 = H1 W2^T + b2
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int m = (mt << 4) + row;
+      bf16x8 hf[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        hf[ks] = *reinterpret_cast<const bf16x8 *>(&L.h1[m][32 * ks + 8 * kg]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2f[c][ks], hf[ks], acc, 0, 0, 0);
+        const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+        bf16x4 hv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float h;
+          gelu_and_grad(acc[j] + b2r[c][j], h, g2r[mt][c][j]);
+          hv[j] = __float2bfloat16(h);
+          L.u.t.h2t[nf + j][m] = hv[j];
+        }
+        *reinterpret_cast<bf16x4 *>(&L.u.t.h2[m][nf]) = hv;
+      }
+    }
+    __syncthreads();
+    // ---- output layer: four lanes per (sample, output), 32 features each,
+    // quad sum; dY = 2 (Y - target) / N
+    {
+      const int d = tid >> 2, q = tid & 3, sm = d >> 1, o = d & 1;
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(&L.u.t.h2[sm][32 * q + 8 * k]);
+        const float4 wa = *reinterpret_cast<const float4 *>(&L.w3[o][32 * q + 8 * k]);
+        const float4 wb = *reinterpret_cast<const float4 *>(&L.w3[o][32 * q + 8 * k + 4]);
+        a = dot8(h, wa, wb, a);
+      }
+      const float y = quad_sum(a) + b3v[o];
+      const float dd = (s0 + sm < N) ? y - L.tg[sm][o] : 0.0f;
+      const float sq = dd * dd;
+      const float sq_other = __shfl_xor(sq, 4);  // the other output of the sample
+      if (q == 0) {
+        L.dyt[o][sm] = 2.0f * dd * inv_n;
+        if (o == 0) L.se[sm] = sq + sq_other;
+      }
+    }
+    __syncthreads();
+    // ---- dW3 (thread: W3 entry o, i), db3, loss; dZ2 = (dY W3) * gelu'(Z2)
+    // from this lane's own features
+    {
+      const int o = tid >> 7, i = tid & (kHidden - 1);
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kStepS / 8; ++k) {
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(&L.u.t.h2t[i][8 * k]);
+        const float4 da = *reinterpret_cast<const float4 *>(&L.dyt[o][8 * k]);
+        const float4 db = *reinterpret_cast<const float4 *>(&L.dyt[o][8 * k + 4]);
+        a = dot8(h, da, db, a);
+      }
+      acc_w3 += a;
+      if (tid < kOut) {
+        float bsum = 0.0f;
+        for (int sm = 0; sm < kStepS; ++sm) bsum += L.dyt[tid][sm];
+        acc_b3 += bsum;
+      }
+      if (tid == 0) {
+        float l = 0.0f;
+        for (int sm = 0; sm < kStepS; ++sm) l += L.se[sm];
+        acc_loss += l;
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int m = (mt << 4) + row;
+      const float dy0 = L.dyt[0][m], dy1 = L.dyt[1][m];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+        bf16x4 dv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float dh = fmaf(dy0, w3r[c][j][0], dy1 * w3r[c][j][1]);
+          dv[j] = __float2bfloat16(dh * g2r[mt][c][j]);
+          L.u.t.dz2t[nf + j][m] = dv[j];
+        }
+        *reinterpret_cast<bf16x4 *>(&L.u.t.dz2[m][nf]) = dv;
+      }
+    }
+    __syncthreads();
+    // ---- db2; dW2 += dZ2^T H1; dH1 = dZ2 W2 -> dZ1 = dH1 * gelu'(Z1)
+    if (tid < kHidden) {
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kStepS / 8; ++k) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(&L.u.t.dz2t[tid][8 * k]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a += to_f(v[q]);
+      }
+      acc_b2 += a;
+    }
+    {
+      bf16x8 af[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        af[a] = *reinterpret_cast<const bf16x8 *>(&L.u.t.dz2t[((2 * wave + a) << 4) + row][8 * kg]);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const bf16x8 bf = *reinterpret_cast<const bf16x8 *>(&L.h1t[(b << 4) + row][8 * kg]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          acc2[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf, acc2[a][b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const int m = (mt << 4) + row;
+      bf16x8 df[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        df[ks] = *reinterpret_cast<const bf16x8 *>(&L.u.t.dz2[m][32 * ks + 8 * kg]);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2tf[c][ks], df[ks], acc, 0, 0, 0);
+        const int nf = ((wave + 4 * c) << 4) + 4 * kg;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          L.u.t.dz1t[nf + j][m] = __float2bfloat16(acc[j] * g1r[mt][c][j]);
+      }
+    }
+    __syncthreads();
+    // ---- db1; dW1 += dZ1^T X
+    if (tid < kHidden) {
+      float a = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kStepS / 8; ++k) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(&L.u.t.dz1t[tid][8 * k]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a += to_f(v[q]);
+      }
+      acc_b1 += a;
+    }
+    {
+      bf16x8 af[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+        af[a] = *reinterpret_cast<const bf16x8 *>(&L.u.t.dz1t[((2 * wave + a) << 4) + row][8 * kg]);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const bf16x8 bf = *reinterpret_cast<const bf16x8 *>(&L.xt[(b << 4) + row][8 * kg]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+          acc1[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf, acc1[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- this block's partial: accumulator fragments, then the small vectors
+  float *gp = partial + (int64_t)blockIdx.x * kPartFloats;
+  float4 *g4 = reinterpret_cast<float4 *>(gp);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+      g4[(kPartW2 >> 2) + (((wave * 16 + a * 8 + b) << 6) + lane)] =
+          make_float4(acc2[a][b][0], acc2[a][b][1], acc2[a][b][2], acc2[a][b][3]);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      g4[(kPartW1 >> 2) + (((wave * 8 + a * 4 + b) << 6) + lane)] =
+          make_float4(acc1[a][b][0], acc1[a][b][1], acc1[a][b][2], acc1[a][b][3]);
+  if (tid < kHidden) {
+    gp[kPartSmall + tid] = acc_b1;
+    gp[kPartSmall + kHidden + tid] = acc_b2;
+  }
+  gp[kPartSmall + 2 * kHidden + tid] = acc_w3;  // 256 threads = the 2 x 128 W3 entries
+  if (tid < kOut) gp[kPartSmall + 2 * kHidden + kOut * kHidden + tid] = acc_b3;
+  if (tid == 0) loss_partial[blockIdx.x] = acc_loss;
+}
+
+// Parameter index of entry f of the partial vector (-1: padding).
+__device__ __forceinline__ int partial_param(int f) {
+  if (f < kPartW1) {  // dW2 fragment: tile (w, a, b), lane, element
+    const int t = f >> 8, ln = (f >> 2) & 63, jj = f & 3;
+    const int w = t >> 4, a = (t >> 3) & 1, b = t & 7;
+    const int o = ((2 * w + a) << 4) + 4 * (ln >> 4) + jj, i = (b << 4) + (ln & 15);
+    return kOffW2 + o * kHidden + i;
+  }
+  if (f < kPartSmall) {
+    const int g = f - kPartW1;
+    const int t = g >> 8, ln = (g >> 2) & 63, jj = g & 3;
+    const int w = t >> 3, a = (t >> 2) & 1, b = t & 3;
+    const int o = ((2 * w + a) << 4) + 4 * (ln >> 4) + jj, i = (b << 4) + (ln & 15);
+    return kOffW1 + o * kIn + i;
+  }
+  const int g = f - kPartSmall;
+  if (g < kHidden) return kOffB1 + g;
+  if (g < 2 * kHidden) return kOffB2 + (g - kHidden);
+  if (g < 2 * kHidden + kOut * kHidden) return kOffW3 + (g - 2 * kHidden);
+  if (g < 2 * kHidden + kOut * kHidden + kOut) return kOffB3 + (g - 2 * kHidden - kOut * kHidden);
+  return -1;
+}
+
+// Fixed-order sum of the G block partials and, with `adam`, the Adam update
+// of the same parameters. A block takes 32 float4 columns of the partial
+// vector; its eight wavefront-halves each sum every eighth partial in order,
+// and the eight sums are added in a fixed order. Block 0 also sums the loss
+// partials (fixed tree in FP64).
+__global__ void __launch_bounds__(256)
+reduce_step_kernel(const float *__restrict__ partial, int nblocks, float *__restrict__ grad,
+                   const float *__restrict__ loss_partial, float *__restrict__ loss, float inv_n,
+                   int adam, float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                   float lr, float b1, float b2, float eps, float c1, float c2) {
+  __shared__ float4 red[8][32];
+  __shared__ double lred[256];
+  const int colw = threadIdx.x & 31, grp = threadIdx.x >> 5;
+  const int col = blockIdx.x * 32 + colw;
+  constexpr int ncol = kPartFloats / 4;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (col < ncol) {
+    // partials grp, grp + 8, grp + 16, ... in order; four loads in flight
+    const float4 *p4 = reinterpret_cast<const float4 *>(partial);
+    for (int b0 = grp; b0 < nblocks; b0 += 32) {
+      float4 q[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int b = b0 + 8 * u;
+        q[u] = b < nblocks ? p4[(int64_t)b * ncol + col] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (b0 + 8 * u < nblocks) {
+          acc.x += q[u].x; acc.y += q[u].y; acc.z += q[u].z; acc.w += q[u].w;
+        }
+    }
+  }
+  red[grp][colw] = acc;
+  if (blockIdx.x == 0 && loss) {
+    double l = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) l += loss_partial[b];
+    lred[threadIdx.x] = l;
+  }
+  __syncthreads();
+  if (grp == 0 && col < ncol) {
+    float4 t = red[0][colw];
+#pragma unroll
+    for (int g = 1; g < 8; ++g) {
+      const float4 q = red[g][colw];
+      t.x += q.x; t.y += q.y; t.z += q.z; t.w += q.w;
+    }
+    const float tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int pidx = partial_param(4 * col + j);
+      if (pidx < 0) continue;
+      const float gi = tv[j];
+      if (grad) grad[pidx] = gi;
+      if (adam) {
+        const float mi = b1 * m[pidx] + (1.0f - b1) * gi;
+        const float vi = b2 * v[pidx] + (1.0f - b2) * gi * gi;
+        m[pidx] = mi;
+        v[pidx] = vi;
+        th[pidx] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+      }
+    }
+  }
+  if (blockIdx.x == 0 && loss) {
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) lred[threadIdx.x] += lred[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(lred[0] * inv_n);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Forward only (training evaluation): tile of 64 samples per block.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -788,8 +1300,47 @@ int launch_forward(int64_t N, const float *x, const float *th, int precision, co
 }
 
 int64_t train_blocks(int64_t N, int precision) {
-  const int S = precision == 0 ? kTileBf16 : kTileF32;
-  return (N + S - 1) / S;
+  if (precision == 0) {
+    const int64_t tiles = (N + kStepS - 1) / kStepS;
+    return tiles < kTrainBlocks ? tiles : kTrainBlocks;
+  }
+  return (N + kTileF32 - 1) / kTileF32;
+}
+
+int64_t train_partial_floats(int precision) {
+  return precision == 0 ? kPartFloats : kNumParams;
+}
+
+// BF16: the persistent accumulation kernel, then the fixed-order reduction
+// (with the Adam update of the same parameters when m and v are given).
+static int launch_step_bf16(int64_t N, const float *x, const int64_t *index, const float *target,
+                            float *th, float *partial, float *loss_partial, float *grad,
+                            float *loss, float *m, float *v, float lr, float b1, float b2,
+                            float eps, int32_t step, hipStream_t st) {
+  const int64_t ntiles = (N + kStepS - 1) / kStepS;
+  const int64_t nb = train_blocks(N, 0);
+  const float inv_n = 1.0f / (float)N;
+  if (allow_lds((const void *)train_accum_kernel, sizeof(StepLds))) return -1;
+  hipLaunchKernelGGL(train_accum_kernel, dim3((unsigned)nb), dim3(256), sizeof(StepLds), st, N,
+                     ntiles, x, index, target, th, partial, loss_partial, inv_n);
+  if (ok_launch()) return -1;
+  const bool adam = m && v;
+  const float c1 = adam ? 1.0f - powf(b1, (float)step) : 1.0f;
+  const float c2 = adam ? 1.0f - powf(b2, (float)step) : 1.0f;
+  constexpr int ncol = kPartFloats / 4;
+  hipLaunchKernelGGL(reduce_step_kernel, dim3((ncol + 31) / 32), dim3(256), 0, st, partial,
+                     (int)nb, grad, loss_partial, loss, inv_n, adam ? 1 : 0, th, m, v, lr, b1, b2,
+                     eps, c1, c2);
+  return ok_launch();
+}
+
+int launch_train_step(int64_t N, const float *x, const int64_t *index, const float *target,
+                      float *th, float *m, float *v, float lr, float b1, float b2, float eps,
+                      int32_t step, float *partial, float *loss_partial, float *grad, float *loss,
+                      void *stream) {
+  if (N <= 0) return 0;
+  return launch_step_bf16(N, x, index, target, th, partial, loss_partial, grad, loss, m, v, lr,
+                          b1, b2, eps, step, (hipStream_t)stream);
 }
 
 int launch_train(int64_t N, const float *x, const int64_t *index, const float *target,
@@ -800,13 +1351,8 @@ int launch_train(int64_t N, const float *x, const int64_t *index, const float *t
   const int64_t nb = train_blocks(N, precision);
   const float inv_n = 1.0f / (float)N;
   if (precision == 0) {
-    const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
-    if (allow_lds((const void *)train_tile_kernel<__bf16, kTileBf16>,
-                  sizeof(TrainLds<__bf16, kTileBf16>)))
-      return -1;
-    hipLaunchKernelGGL((train_tile_kernel<__bf16, kTileBf16>), dim3((unsigned)nb), dim3(256),
-                       sizeof(TrainLds<__bf16, kTileBf16>), st, N, x, index, target, th, w1, w2,
-                       w2t, partial, loss_partial, inv_n);
+    return launch_step_bf16(N, x, index, target, const_cast<float *>(th), partial, loss_partial,
+                            grad, loss, nullptr, nullptr, 0.f, 0.f, 0.f, 0.f, 1, st);
   } else {
     const float *w1 = (const float *)prep, *w2 = w1 + kHidden * kLdIn, *w2t = w2 + kHidden * kLdH;
     if (allow_lds((const void *)train_tile_kernel<float, kTileF32>, sizeof(TrainLds<float, kTileF32>)))

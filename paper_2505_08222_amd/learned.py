@@ -90,6 +90,25 @@ class Adam:
                                   self.b2, self.eps, self.step_count, _stream()))
 
 
+def train_step(x, target, opt: "Adam", index=None, lr=None, work=None, grad=None, loss=None):
+    """One fused Adam step of the BF16 network (gradient and update in two
+    kernels). Returns (loss, grad); `grad` may be given preallocated."""
+    N = x.shape[0] if index is None else index.shape[0]
+    params = opt.params
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    if work is None:
+        work = _work(N, "bf16", params.device)
+    _, w, n = work
+    opt.step_count += 1
+    check(lib().mlp_train_step(N, ptr(x), ptr(index), ptr(target), ptr(params), ptr(opt.m),
+                               ptr(opt.v), float(opt.lr if lr is None else lr), opt.b1, opt.b2,
+                               opt.eps, opt.step_count, ptr(grad), ptr(loss), w, n, _stream()))
+    return loss, grad
+
+
 def infer(win: torch.Tensor, params: torch.Tensor, sigma: torch.Tensor, k_sigma=3.0, gn_iters=0,
           tau=1e-4, work=None):
     """Estimates of windows [N, W, 3]: network with residual test, exact
@@ -178,15 +197,21 @@ def train(x, y, params=None, epochs=2, batch=8192, lr=2e-3, lr_final=1e-4, seed=
     gen = torch.Generator(device=device)
     gen.manual_seed(seed)
     work = _work(batch, precision, device)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=device)
     hist = []
     k = 0
     for ep in range(epochs):
         perm = torch.randperm(N, generator=gen, device=device)
         for b in range(steps_per_epoch):
             idx = perm[b * batch:(b + 1) * batch]
-            loss, grad = loss_and_grad(x, y, params, index=idx, precision=precision, work=work)
             cur = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * k / max(1, total - 1)))
-            opt.step(grad, lr=cur)
+            if precision == "bf16":
+                train_step(x, y, opt, index=idx, lr=cur, work=work, grad=grad, loss=loss)
+            else:
+                loss, grad = loss_and_grad(x, y, params, index=idx, precision=precision,
+                                           work=work)
+                opt.step(grad, lr=cur)
             if b % 50 == 0 or b == steps_per_epoch - 1:
                 hist.append((k, float(loss.item())))
                 if log:
