@@ -9,7 +9,10 @@ LIB = os.path.join(HERE, "liblrauv_oracle.so")
 
 def build(verbose: bool = False) -> str:
     srcs = [s for s in SRC if os.path.exists(s)]
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+    # -ffp-contract=off: no fused multiply-adds (the binary32 decisions of the
+    # pairwise spawn must round every product)
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-fopenmp", "-Wall",
+           "-Wextra",
            "-Wno-unused-parameter", *srcs, "-o", LIB + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))

@@ -235,6 +235,9 @@ void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
   }
 }
 
+/* Eq. (2): 1 when the nearest agent is within d_follow (inclusive). */
+double orc_follow_reward(double d, double d_follow) { return d <= d_follow ? 1.0 : 0.0; }
+
 /* Eq. (1). At e = eps_max the exponent tends to -inf, so the value is 0 and
  * the reward is continuous at both thresholds. */
 double orc_tracking_reward(double e, double eps_min, double eps_max) {
@@ -259,11 +262,72 @@ typedef struct {
   double ex[OMAX][OMAX], ey[OMAX][OMAX], es[OMAX][OMAX];
   int ev[OMAX][OMAX];
   int comm_ok[OMAX];
+  int rud[OMAX];  /* rudder position of each agent (action_mode 1) */
 } oenv;
 
+/* Pairwise spawn (Sec. IV-A-2: every entity at least spawn_min and at most
+ * spawn_max from every other; how the paper draws such a layout is not
+ * stated). Reading: the entities take distinct sites of a hexagonal patch
+ * about the centre of the area: the centre, the six sites of the first ring
+ * at distance s, and the six sites of the second ring at distance s sqrt(3)
+ * (each between two first-ring sites); 13 sites. Their order is a uniformly
+ * random permutation, the patch is rotated by a uniform angle, and each
+ * entity is moved off its site by a uniform offset in the square of
+ * half-side h. Neighbouring sites are s apart and the farthest two 2 sqrt(3) s,
+ * and an offset moves a pair's distance by at most 2 sqrt(2) h, so
+ *   s = spawn_min + 2 sqrt(2) h   and   2 sqrt(3) s + 2 sqrt(2) h <= spawn_max
+ * keep every pair within the bounds; h is 0.9 of the largest value that
+ * satisfies both. Random words, in order, from Philox(1 + k, env, 127, reset),
+ * k = 0, 1, ...: words 0..11 the Fisher-Yates choices (position i = 12 down
+ * to 1 swaps with a uniform choice in 0..i), word 12 the rotation, words
+ * 13 + 2n and 14 + 2n the offset of entity n (agents first, then targets).
+ * Returns 0, or -1 with more than 13 entities. */
+static int spawn_pairwise(const orc_params *p, uint64_t seed, uint64_t episode, uint32_t env_id,
+                          int nA, int nT, double *xs, double *ys) {
+  const int n = nA + nT;
+  if (n > 13) return -1;
+  const double two_pi = 6.283185307179586476925286766559, pi = two_pi / 2.0;
+  const double r2 = sqrt(2.0), r3 = sqrt(3.0);
+  const double h = 0.9 * (p->spawn_max - 2.0 * r3 * p->spawn_min) / (2.0 * r2 * (2.0 * r3 + 1.0));
+  const double s = p->spawn_min + 2.0 * r2 * h;
+  const uint32_t c3 = (uint32_t)((episode << 4) | PURPOSE_RESET);
+  uint32_t w[40];
+  for (int k = 0; k < 10; ++k) draw(seed, 1u + (uint32_t)k, env_id, ENT_ENV, c3, w + 4 * k);
+  int perm[13];
+  for (int i = 0; i < 13; ++i) perm[i] = i;
+  for (int i = 12; i >= 1; --i) {
+    int j = (int)orc_choice(w[12 - i], (uint32_t)(i + 1));
+    int tmp = perm[i];
+    perm[i] = perm[j];
+    perm[j] = tmp;
+  }
+  const double phi = two_pi * orc_u01(w[12]);
+  for (int m = 0; m < n; ++m) {
+    int site = perm[m];
+    double rad = 0.0, ang = 0.0;
+    if (site >= 1 && site <= 6) {
+      rad = s;
+      ang = (site - 1) * pi / 3.0;
+    } else if (site >= 7) {
+      rad = s * r3;
+      ang = pi / 6.0 + (site - 7) * pi / 3.0;
+    }
+    xs[m] = rad * cos(ang + phi) + h * (2.0 * orc_u01(w[13 + 2 * m]) - 1.0);
+    ys[m] = rad * sin(ang + phi) + h * (2.0 * orc_u01(w[14 + 2 * m]) - 1.0);
+  }
+  return 0;
+}
+
+int orc_spawn_pairwise(const orc_params *p, uint64_t seed, uint64_t episode, uint32_t env_id,
+                       int n_agents, int n_targets, double *x, double *y) {
+  return spawn_pairwise(p, seed, episode, env_id, n_agents, n_targets, x, y);
+}
+
 /* Spawn (Sec. IV-A-2 spawns entities on the surface / at depth with
- * pairwise spacing; the batched configurations instead place agents in a
- * disk about the centre of the area and targets uniformly in the square). */
+ * pairwise spacing, spawn_mode 1; the batched configurations instead place
+ * agents in a disk about the centre of the area and targets uniformly in the
+ * square, spawn_mode 0). Headings, target speeds and the range noise come
+ * from the same draws in both modes. */
 static void env_reset(const orc_params *p, uint64_t seed, uint64_t episode, oenv *E) {
   const double two_pi = 6.283185307179586476925286766559, pi = two_pi / 2.0;
   uint32_t c3 = (uint32_t)((episode << 4) | PURPOSE_RESET);
@@ -285,8 +349,21 @@ static void env_reset(const orc_params *p, uint64_t seed, uint64_t episode, oenv
   }
   draw(seed, 0u, E->env_id, ENT_ENV, c3, x);
   E->sigma_r = p->range_sigma_lo + (p->range_sigma_hi - p->range_sigma_lo) * orc_u01(x[0]);
+  if (p->spawn_mode == 1) {
+    double xs[2 * OMAX], ys[2 * OMAX];
+    spawn_pairwise(p, seed, episode, E->env_id, E->nA, E->nT, xs, ys);
+    for (int i = 0; i < E->nA; ++i) {
+      E->ax[i] = xs[i];
+      E->ay[i] = ys[i];
+    }
+    for (int j = 0; j < E->nT; ++j) {
+      E->tx[j] = xs[E->nA + j];
+      E->ty[j] = ys[E->nA + j];
+    }
+  }
   E->filled = 0;
   for (int i = 0; i < OMAX; ++i) {
+    E->rud[i] = (p->n_rudder - 1) / 2;
     E->comm_ok[i] = 1;
     for (int j = 0; j < OMAX; ++j) {
       E->ev[i][j] = 0;
@@ -359,7 +436,20 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
     if (a < 0 || a >= p->n_actions) a = -1;
     double z0, z1;
     orc_normal2(x[1], x[2], &z0, &z1);
-    double dpsi = (a >= 0) ? p->action_dpsi[a] : 0.0;
+    double dpsi;
+    if (p->action_mode == 1) {
+      /* rudder: one position down / keep / one up, within the range; an
+       * invalid action keeps the rudder */
+      if (a >= 0) {
+        int rr = E->rud[i] + a - 1;
+        if (rr < 0) rr = 0;
+        if (rr > p->n_rudder - 1) rr = p->n_rudder - 1;
+        E->rud[i] = rr;
+      }
+      dpsi = p->action_dpsi[E->rud[i]];
+    } else {
+      dpsi = (a >= 0) ? p->action_dpsi[a] : 0.0;
+    }
     E->apsi[i] = wrap_angle(E->apsi[i] + dpsi + p->agent_heading_sigma * z0);
     E->ax[i] = E->ax[i] + vdt * cos(E->apsi[i]);
     E->ay[i] = E->ay[i] + vdt * sin(E->apsi[i]);
@@ -449,7 +539,17 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
       if (d < e) e = d;
     }
     if (o->err) o->err[j] = e;
-    sum += orc_tracking_reward(e, p->eps_min, p->eps_max);
+    if (p->reward_mode == 1) {
+      /* Eq. (2): distance from the target to its nearest agent (true positions) */
+      double dmin = INFINITY;
+      for (int i = 0; i < E->nA; ++i) {
+        double d = hypot(E->ax[i] - E->tx[j], E->ay[i] - E->ty[j]);
+        if (d < dmin) dmin = d;
+      }
+      sum += orc_follow_reward(dmin, p->d_follow);
+    } else {
+      sum += orc_tracking_reward(e, p->eps_min, p->eps_max);
+    }
   }
   double reward = sum / E->nT;
   int crash = 0;
@@ -483,6 +583,13 @@ int orc_rollout(const orc_params *p, uint64_t seed, uint64_t episode, int64_t n_
                 int32_t T, const int32_t *actions, orc_traj *out, int n_threads) {
   if (!p || n_sel < 0 || T < 0 || p->window < 1 || p->window > OWMAX) return -1;
   if (p->n_actions < 1 || p->n_actions > 8) return -1;
+  if (p->action_mode != 0 && p->action_mode != 1) return -1;
+  if (p->action_mode == 1 && (p->n_rudder < 1 || p->n_rudder > 8 || p->n_actions != 3)) return -1;
+  if (p->reward_mode != 0 && p->reward_mode != 1) return -1;
+  if (p->spawn_mode != 0 && p->spawn_mode != 1) return -1;
+  if (p->spawn_mode == 1 && !(p->spawn_min >= 0.0 && p->spawn_max >= 2.0 * sqrt(3.0) * p->spawn_min))
+    return -1;
+  if (p->spawn_mode == 1 && p->n_agents + p->n_targets > 13) return -1;
   for (int64_t k = 0; k < n_sel; ++k)
     if (n_agents[k] < 1 || n_agents[k] > OMAX || n_targets[k] < 1 || n_targets[k] > OMAX)
       return -1;

@@ -58,6 +58,24 @@ typedef struct orc_params {
   double guard_tau;        /* conditioning guard of the 2x2 solves */
   double lost_range;       /* a target is lost at episode end when every
                               agent is farther than this (m) */
+  /* Paper-faithful variants (Sec. IV-A-2). */
+  int32_t action_mode;     /* 0: action k turns the heading by action_dpsi[k];
+                              1: rudder state: actions 0, 1, 2 move the rudder one
+                              position down, keep it, move it one position up
+                              ("Actions Space": only adjacent angles), and the
+                              heading changes by action_dpsi[rudder], the paper's
+                              linear theta(gamma) at each rudder angle */
+  int32_t n_rudder;        /* rudder positions in action_mode 1 (<= 8); they
+                              start at the middle one */
+  int32_t reward_mode;     /* 0: tracking reward Eq. (1); 1: follow reward Eq. (2) */
+  int32_t spawn_mode;      /* 0: agents in the disk, targets in the square;
+                              1: every entity at least spawn_min from every other
+                              and at most spawn_max apart (Sec. IV-A-2); needs
+                              n_agents + n_targets <= 13 and
+                              spawn_max >= 2 sqrt(3) spawn_min */
+  double d_follow;         /* Eq. (2): a target is followed when some agent is
+                              within this distance (m) */
+  double spawn_min, spawn_max; /* pairwise spawn distances of spawn_mode 1 (m) */
 } orc_params;
 
 /* Per-step records of an oracle rollout. Every pointer may be NULL. Entity
@@ -124,6 +142,14 @@ void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
 
 /* ---- Eq. (1): tracking reward of one target with error e. */
 double orc_tracking_reward(double e, double eps_min, double eps_max);
+/* ---- Eq. (2): follow reward of one target whose nearest agent is at
+ * distance d. Pinned: worked values. */
+double orc_follow_reward(double d, double d_follow);
+/* ---- spawn_mode 1 placement of n <= 13 entities (agents first, then
+ * targets, as in a reset) of env `env_id`: x, y [n]. Returns 0, or -1 with
+ * more than 13 entities. Pinned: pairwise bounds by brute force. */
+int orc_spawn_pairwise(const orc_params *p, uint64_t seed, uint64_t episode, uint32_t env_id,
+                       int n_agents, int n_targets, double *x, double *y);
 
 /* ---- full episode(s): reset then T steps for the selected envs.
  * env_ids: global env ids (they key the RNG); counts per selected env.

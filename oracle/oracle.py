@@ -27,6 +27,9 @@ class OrcParams(C.Structure):
         ("det_range", C.c_double), ("comm_range", C.c_double), ("comm_loss_p", C.c_double),
         ("eps_min", C.c_double), ("eps_max", C.c_double), ("d_safe", C.c_double),
         ("guard_tau", C.c_double), ("lost_range", C.c_double),
+        ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
+        ("spawn_mode", C.c_int32), ("d_follow", C.c_double), ("spawn_min", C.c_double),
+        ("spawn_max", C.c_double),
     ]
 
 
@@ -73,6 +76,11 @@ def lib():
                                    P(C.c_double), P(C.c_uint8), C.c_int]
         L.orc_tracking_reward.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_tracking_reward.restype = C.c_double
+        L.orc_follow_reward.argtypes = [C.c_double, C.c_double]
+        L.orc_follow_reward.restype = C.c_double
+        L.orc_spawn_pairwise.argtypes = [P(OrcParams), C.c_uint64, C.c_uint64, C.c_uint32,
+                                         C.c_int, C.c_int, P(C.c_double), P(C.c_double)]
+        L.orc_spawn_pairwise.restype = C.c_int
         L.orc_rollout.argtypes = [P(OrcParams), C.c_uint64, C.c_uint64, C.c_int64, P(C.c_int64),
                                   P(C.c_int32), P(C.c_int32), C.c_int32, P(C.c_int32),
                                   P(OrcTraj), C.c_int]
@@ -190,6 +198,22 @@ def ls_batch(win: np.ndarray, gn_iters=0, tau=1e-4, n_threads=1):
 
 def tracking_reward(e: float, eps_min=10.0, eps_max=50.0) -> float:
     return lib().orc_tracking_reward(e, eps_min, eps_max)
+
+
+def follow_reward(d: float, d_follow=50.0) -> float:
+    return lib().orc_follow_reward(d, d_follow)
+
+
+def spawn_pairwise(cfg: dict, seed: int, episode: int, env_id: int, n_agents: int,
+                   n_targets: int):
+    """Pairwise spawn of one env: (x [n], y [n], status 0 or -1)."""
+    n = n_agents + n_targets
+    x = np.zeros(n)
+    y = np.zeros(n)
+    p = make_params(cfg)
+    k = lib().orc_spawn_pairwise(C.byref(p), seed, episode, env_id, n_agents, n_targets,
+                                 _p(x, C.c_double), _p(y, C.c_double))
+    return x, y, int(k)
 
 
 # ---------------------------------------------------------------- rollout

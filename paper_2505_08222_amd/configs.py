@@ -24,6 +24,8 @@ BASE = dict(
     target_speed_lo=0.5, target_speed_hi=0.5, range_sigma_lo=1.0, range_sigma_hi=1.0,
     det_range=math.inf, comm_range=1500.0, comm_loss_p=0.0, eps_min=10.0, eps_max=50.0,
     d_safe=10.0, guard_tau=1e-4, lost_range=450.0,
+    action_mode=0, n_rudder=5, reward_mode=0, spawn_mode=0, d_follow=50.0, spawn_min=50.0,
+    spawn_max=200.0,
 )
 
 
@@ -55,7 +57,25 @@ POLICY = dict(name="policy", num_envs=16384, steps=1000, seed=0, d_model=64, hea
               layers=2, ffn=256,
               env=_cfg(n_agents=5, n_targets=5, window=16, episode_len=1000, area=4000.0))
 
-CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY)}
+# The paper's own environment (Sec. IV-A-2, IV-A-3): 30 s steps at 1 m/s; the
+# rudder takes five equidistant angles in [-0.24, 0.24] rad, moves only to an
+# adjacent angle per step (actions: down, keep, up), and turns the heading by
+# the linear theta(gamma) that maps 0.24 rad to 1.45 rad at this speed and
+# step; targets at half the agents' speed; every entity spawned 50-200 m from
+# every other; 450 m detection, 1500 m communication with dropped
+# broadcasts; follow reward (Eq. (2), 50 m). A window of 10 ranges spans
+# 300 s and a 300 m track.
+RUDDER_ANGLES = [-0.24, -0.12, 0.0, 0.12, 0.24]
+THETA_PER_RUDDER = 1.45 / 0.24  # rad of heading per rad of rudder, 1 m/s, 30 s
+PAPER = dict(name="paper", num_envs=16384, steps=300, seed=0,
+             env=_cfg(n_agents=5, n_targets=5, ragged=1, episode_len=300, dt=30.0,
+                      agent_speed=1.0, area=4000.0, action_mode=1, n_actions=3, n_rudder=5,
+                      action_dpsi=[THETA_PER_RUDDER * g for g in RUDDER_ANGLES],
+                      target_speed_lo=0.5, target_speed_hi=0.5, det_range=450.0,
+                      comm_range=1500.0, comm_loss_p=0.1, reward_mode=1, d_follow=50.0,
+                      spawn_mode=1, spawn_min=50.0, spawn_max=200.0))
+
+CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY, PAPER)}
 
 
 def env_config(name: str, **overrides) -> dict:
