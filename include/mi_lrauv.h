@@ -100,7 +100,24 @@ typedef enum mil_status {
  *                       closer (text after Eq. (2)).
  *  guard_tau            2x2 solves are refused when det <= tau * trace^2.
  *  lost_range           a target counts as lost at the end of a rollout when
- *                       every agent is farther than this. */
+ *                       every agent is farther than this.
+ * Paper-faithful variants (Sec. IV-A-2 and IV-A-3):
+ *  action_mode          0: action k turns the heading by action_dpsi[k];
+ *                       1: rudder state: each agent's rudder sits at one of
+ *                       n_rudder angles (starting at the middle one) and
+ *                       actions 0, 1, 2 move it one angle down, keep it, move
+ *                       it one angle up (only adjacent angles, "Actions
+ *                       Space"); the heading turns by action_dpsi[rudder], the
+ *                       linear theta(gamma) at that angle. Needs n_actions = 3;
+ *                       an invalid action keeps the rudder.
+ *  reward_mode          0: tracking reward, Eq. (1); 1: follow reward, Eq. (2):
+ *                       a target scores 1 when its nearest agent (true
+ *                       positions) is within d_follow.
+ *  spawn_mode           0: as above; 1: every entity at least spawn_min and at
+ *                       most spawn_max from every other: jittered sites of a
+ *                       randomly rotated hexagonal patch about the centre, in
+ *                       random order (needs n_agents + n_targets <= 13 and
+ *                       spawn_max >= 2 sqrt(3) spawn_min). */
 typedef struct mil_env_params {
   int32_t n_agents, n_targets, ragged, window;
   int32_t episode_len, n_actions, gn_iters, reserved0;
@@ -111,6 +128,8 @@ typedef struct mil_env_params {
   float range_sigma_lo, range_sigma_hi;
   float det_range, comm_range, comm_loss_p;
   float eps_min, eps_max, d_safe, guard_tau, lost_range;
+  int32_t action_mode, n_rudder, reward_mode, spawn_mode;
+  float d_follow, spawn_min, spawn_max;
 } mil_env_params;
 
 /* Sizes of a created environment batch. */

@@ -38,6 +38,9 @@ class EnvParams(C.Structure):
         ("det_range", C.c_float), ("comm_range", C.c_float), ("comm_loss_p", C.c_float),
         ("eps_min", C.c_float), ("eps_max", C.c_float), ("d_safe", C.c_float),
         ("guard_tau", C.c_float), ("lost_range", C.c_float),
+        ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
+        ("spawn_mode", C.c_int32), ("d_follow", C.c_float), ("spawn_min", C.c_float),
+        ("spawn_max", C.c_float),
     ]
 
 

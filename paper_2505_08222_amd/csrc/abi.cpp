@@ -91,7 +91,7 @@ struct mil_env {
   int64_t ws_bytes = 0;
   struct {
     int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue, mpart;
-    int64_t ax, ay, apsi, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
+    int64_t ax, ay, apsi, arud, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
     int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
   mil::DevParams dp{};
@@ -125,6 +125,17 @@ bool valid_params(const mil_env_params *p, std::string &why) {
   if (!(p->eps_min < p->eps_max)) return bad("eps_min must be < eps_max");
   if (!(p->comm_loss_p >= 0.f && p->comm_loss_p <= 1.f)) return bad("comm_loss_p in [0,1]");
   if (!(p->guard_tau >= 0.f)) return bad("guard_tau must be >= 0");
+  if (p->action_mode != 0 && p->action_mode != 1) return bad("action_mode must be 0 or 1");
+  if (p->action_mode == 1 &&
+      (p->n_actions != 3 || p->n_rudder < 1 || p->n_rudder > MIL_MAX_ACTIONS))
+    return bad("rudder actions need n_actions = 3 and n_rudder in 1..8");
+  if (p->reward_mode != 0 && p->reward_mode != 1) return bad("reward_mode must be 0 or 1");
+  if (p->spawn_mode != 0 && p->spawn_mode != 1) return bad("spawn_mode must be 0 or 1");
+  if (p->spawn_mode == 1 &&
+      (p->n_agents + p->n_targets > 13 || !(p->spawn_min >= 0.f) ||
+       !((double)p->spawn_max >= 2.0 * std::sqrt(3.0) * (double)p->spawn_min)))
+    return bad("pairwise spawn needs n_agents + n_targets <= 13 and "
+               "spawn_max >= 2 sqrt(3) spawn_min");
   return true;
 }
 
@@ -193,6 +204,13 @@ void fill_dev_params(mil_env *h) {
   d.lost_range = p.lost_range;
   d.key0 = (uint32_t)h->seed;
   d.key1 = (uint32_t)(h->seed >> 32);
+  d.action_mode = p.action_mode;
+  d.n_rudder = p.n_rudder;
+  d.reward_mode = p.reward_mode;
+  d.spawn_mode = p.spawn_mode;
+  d.d_follow = p.d_follow;
+  d.spawn_min = p.spawn_min;
+  d.spawn_max = p.spawn_max;
 }
 
 mil::DevOut dev_out(const mil_env_outputs *o) {
@@ -359,6 +377,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.ax = take(A * 4);
   f.ay = take(A * 4);
   f.apsi = take(A * 4);
+  f.arud = take(A * 4);
   f.tx = take(Tt * 4);
   f.ty = take(Tt * 4);
   f.tpsi = take(Tt * 4);
@@ -440,6 +459,7 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.ax = F(h->off.ax);
   d.ay = F(h->off.ay);
   d.apsi = F(h->off.apsi);
+  d.arud = (int32_t *)(h->ws + h->off.arud);
   d.tx = F(h->off.tx);
   d.ty = F(h->off.ty);
   d.tpsi = F(h->off.tpsi);

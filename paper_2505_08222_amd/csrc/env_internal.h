@@ -14,6 +14,8 @@ struct DevParams {
   float det_range, comm_range, comm_loss_p;
   float eps_min, eps_max, d_safe, tau, lost_range;
   uint32_t key0, key1;
+  int32_t action_mode, n_rudder, reward_mode, spawn_mode;
+  float d_follow, spawn_min, spawn_max;
 };
 
 // One (agents, targets) shape. Environments of a shape are consecutive in
@@ -38,6 +40,7 @@ struct DevState {
   const ClassInfo *classes;                  // [num_classes]
   const uint8_t *wave_class;                 // [num_waves]
   float *ax, *ay, *apsi;                     // [A]
+  int32_t *arud;                             // [A] rudder position (action_mode 1)
   float *tx, *ty, *tpsi, *tv;                // [Tt]
   float *sigma;                              // [E]
   float *hx, *hy;                            // [W][A], entry 0 = newest

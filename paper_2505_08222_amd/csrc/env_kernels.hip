@@ -238,6 +238,66 @@ __device__ __forceinline__ float pick(const float (&arr)[N], int g, int sl) {
 }
 
 // ---------------------------------------------------------------------------
+// Pairwise spawn (Sec. IV-A-2: every entity 50-200 m from every other), by
+// the env's reset thread: entities take distinct sites of a hexagonal patch
+// about the centre (the centre, six sites at distance sp, six at sp sqrt(3)
+// between them), in a Fisher-Yates order, the patch rotated by a uniform
+// angle and each entity moved by a uniform offset in the square of half-side
+// h; sp = spawn_min + 2 sqrt(2) h and 2 sqrt(3) sp + 2 sqrt(2) h <= spawn_max
+// keep every pair within the bounds (h at 0.9 of its largest value). Words
+// of Philox(1 + k, env, env entity, reset), k = 0..9, in order: 12 swap
+// choices, the rotation, then two offset words per entity (agents first).
+// ---------------------------------------------------------------------------
+__device__ void spawn_pairwise(const DevParams &p, const DevState &s, int64_t e, uint32_t id,
+                               uint32_t c3, int na, int nt) {
+  const float r2 = 1.41421356237310f, r3 = 1.73205080756888f;
+  const float h = 0.9f * (p.spawn_max - 2.0f * r3 * p.spawn_min) / (2.0f * r2 * (2.0f * r3 + 1.0f));
+  const float sp = p.spawn_min + 2.0f * r2 * h;
+  uint32_t w[40];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    const u32x4 x = philox4x32_10(1u + (uint32_t)k, id, kEntEnv, c3, p.key0, p.key1);
+    w[4 * k] = x.x;
+    w[4 * k + 1] = x.y;
+    w[4 * k + 2] = x.z;
+    w[4 * k + 3] = x.w;
+  }
+  int perm[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) perm[k] = k;
+  for (int k = 12; k >= 1; --k) {
+    const int j = (int)choice(w[12 - k], (uint32_t)(k + 1));
+    const int tmp = perm[k];
+    perm[k] = perm[j];
+    perm[j] = tmp;
+  }
+  const float rot = u01(w[12]);  // revolutions
+  const int n = na + nt;
+  for (int m = 0; m < n; ++m) {
+    const int site = perm[m];
+    float rad = 0.0f, rev = 0.0f;
+    if (site >= 1 && site <= 6) {
+      rad = sp;
+      rev = (float)(site - 1) / 6.0f;
+    } else if (site >= 7) {
+      rad = sp * r3;
+      rev = 1.0f / 12.0f + (float)(site - 7) / 6.0f;
+    }
+    float sn, cs;
+    sincos_rev(rev + rot, sn, cs);
+    const float x = fmaf(rad, cs, h * (2.0f * u01(w[13 + 2 * m]) - 1.0f));
+    const float y = fmaf(rad, sn, h * (2.0f * u01(w[14 + 2 * m]) - 1.0f));
+    if (m < na) {
+      s.ax[s.aoff[e] + m] = x;
+      s.ay[s.aoff[e] + m] = y;
+    } else {
+      s.tx[s.toff[e] + (m - na)] = x;
+      s.ty[s.toff[e] + (m - na)] = y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Reset: one thread per (env, slot); slots 0..7 agents, 8..15 targets, 16 env.
 // ---------------------------------------------------------------------------
 __global__ void reset_kernel(DevParams p, DevState s, uint32_t episode) {
@@ -253,13 +313,16 @@ __global__ void reset_kernel(DevParams p, DevState s, uint32_t episode) {
     const int i = slot;
     if (i >= na) return;
     const u32x4 x = philox4x32_10(0u, id, (uint32_t)i, c3, p.key0, p.key1);
-    const float rad = p.spawn_r * sqrtf(u01(x.x));
-    float sn, cs;
-    sincospif(2.0f * u01(x.y), &sn, &cs);
     const int64_t a = s.aoff[e] + i;
-    s.ax[a] = rad * cs;
-    s.ay[a] = rad * sn;
+    if (p.spawn_mode == 0) {
+      const float rad = p.spawn_r * sqrtf(u01(x.x));
+      float sn, cs;
+      sincospif(2.0f * u01(x.y), &sn, &cs);
+      s.ax[a] = rad * cs;
+      s.ay[a] = rad * sn;
+    }
     s.apsi[a] = -3.14159265358979f + 6.28318530717959f * u01(x.z);
+    s.arud[a] = (p.n_rudder - 1) / 2;  // rudder at the middle angle
     const int64_t pb = s.poff[e] + (int64_t)i * nt;
     for (int j = 0; j < nt; ++j) s.ev[pb + j] = 0;
   } else if (slot < 16) {
@@ -267,13 +330,16 @@ __global__ void reset_kernel(DevParams p, DevState s, uint32_t episode) {
     if (j >= nt) return;
     const u32x4 x = philox4x32_10(0u, id, kEntTargetBlock + (uint32_t)j, c3, p.key0, p.key1);
     const int64_t q = s.toff[e] + j;
-    s.tx[q] = -0.5f * p.area + p.area * u01(x.x);
-    s.ty[q] = -0.5f * p.area + p.area * u01(x.y);
+    if (p.spawn_mode == 0) {
+      s.tx[q] = -0.5f * p.area + p.area * u01(x.x);
+      s.ty[q] = -0.5f * p.area + p.area * u01(x.y);
+    }
     s.tpsi[q] = -3.14159265358979f + 6.28318530717959f * u01(x.z);
     s.tv[q] = p.tv_lo + (p.tv_hi - p.tv_lo) * u01(x.w);
   } else {
     const u32x4 x = philox4x32_10(0u, id, kEntEnv, c3, p.key0, p.key1);
     s.sigma[e] = p.sr_lo + (p.sr_hi - p.sr_lo) * u01(x.x);
+    if (p.spawn_mode == 1) spawn_pairwise(p, s, e, id, c3, na, nt);
     s.macc[3 * e] = 0.0;
     s.macc[3 * e + 1] = 0.0;
     s.macc[3 * e + 2] = 0.0;
@@ -456,6 +522,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     }
     float ax = ld_st(&s.ax[aidx], dyn), ay = ld_st(&s.ay[aidx], dyn);
     float apsi = ld_st(&s.apsi[aidx], dyn);
+    int rud = (FULL && p.action_mode == 1) ? ld_st(&s.arud[aidx], dyn) : 0;
     float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
     uint32_t evb = 0;
 #pragma unroll
@@ -503,7 +570,15 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       if (move) {
         float za, zb;
         normal2(xa.y, xa.z, za, zb);
-        const float dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
+        float dpsi;
+        if (FULL && p.action_mode == 1) {
+          // rudder: one angle down / keep / one up (Sec. IV-A-2), then the
+          // heading change theta(gamma) of the rudder angle
+          if (act >= 0) rud = min(max(rud + act - 1, 0), p.n_rudder - 1);
+          dpsi = lds_dpsi[wib][rud];
+        } else {
+          dpsi = act >= 0 ? lds_dpsi[wib][act] : 0.0f;
+        }
         apsi = wrap_angle((apsi + dpsi) + p.sig_a * za);
         float sn, cs;
         sincos_rad(apsi, sn, cs);
@@ -791,6 +866,22 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           agc[k] = FULL ? env_shfl<S>((int)comm_ok, base_lane, k * G, lpe) : 1;
         }
       }
+      if (FULL && p.reward_mode == 1) {
+        // Eq. (2): a target scores 1 when its nearest agent is within d_follow
+        const float dfol2 = p.d_follow * p.d_follow;
+        float fsum = 0.0f;
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          if (j < nt) {
+            float dmin2 = kInf;
+#pragma unroll
+            for (int k = 0; k < MA; ++k)
+              if (k < na) dmin2 = fminf(dmin2, sqnorm(agx[k] - tpx[j], agy[k] - tpy[j]));
+            fsum += (dmin2 <= dfol2) ? 1.0f : 0.0f;
+          }
+        }
+        rew = fsum * inv_nt;
+      }
       bool crash = false;
 #pragma unroll
       for (int k = 0; k < MA; ++k)
@@ -986,6 +1077,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         st_st(&s.ax[aidx], ax, dyn);
         st_st(&s.ay[aidx], ay, dyn);
         st_st(&s.apsi[aidx], apsi, dyn);
+        if (FULL && p.action_mode == 1) st_st(&s.arud[aidx], rud, dyn);
 #pragma unroll
         for (int k = 0; k < WC; ++k) {
           if (k < W) {
@@ -1258,7 +1350,8 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   // the lean form applies when none of the full form's extra paths is asked for
   const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
                     !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
-                    p.comm_loss_p == 0.0f && p.gn_iters == 0 && ext.phase == 0;
+                    p.comm_loss_p == 0.0f && p.gn_iters == 0 && ext.phase == 0 &&
+                    p.action_mode == 0 && p.reward_mode == 0;
   // the lean form stages its observation block for a coalesced write once at
   // least two wavefronts per SIMD take turns on the store path (large
   // batches); small batches are latency-bound and write directly

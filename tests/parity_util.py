@@ -170,12 +170,30 @@ def compare_rollout(gpu, orc, env, packed_idx, cfg, label=""):
     grw = gpu["reward"][:, packed_idx]
     crash_g = grw == -1.0
     np.testing.assert_array_equal(crash_g, orc["crash"].astype(bool), err_msg=f"{label} crash")
-    tol_r = np.zeros((T, E))
-    for k in range(E):
-        tol_r[:, k] = 0.05 * tol_e[:, ct[k]:ct[k + 1]].sum(1) / nt[k] + REL
-    dr_ = np.abs(grw - orc["reward"])
-    report["reward_max_abs"] = float(dr_.max())
-    assert (dr_ <= tol_r).all(), f"{label} rewards differ: {report}"
+    if cfg.get("reward_mode", 0) == 1:
+        # Eq. (2): an indicator per target; it may differ only for a target
+        # whose nearest agent sits within the position difference of d_follow
+        flips = 0
+        for k in range(E):
+            ag = oa[:, ca[k]:ca[k + 1], :2]
+            tg = ot[:, ct[k]:ct[k + 1], :2]
+            dmin = np.hypot(ag[:, :, None, 0] - tg[:, None, :, 0],
+                            ag[:, :, None, 1] - tg[:, None, :, 1]).min(1)  # [T, nt]
+            margin = 2 * (dpos_a[:, ca[k]:ca[k + 1]].max(1)[:, None] + dpos_t[:, ct[k]:ct[k + 1]])
+            near = (np.abs(dmin - cfg["d_follow"]) <= margin + 1e-4).sum(1)
+            d = np.abs(grw[:, k] - orc["reward"][:, k]) * nt[k]
+            ok = ~crash_g[:, k]
+            assert (d[ok] <= near[ok] + 1e-4).all(), f"{label} follow reward env {k}"
+            flips += int(np.round(d[ok]).sum())
+        report["follow_flips"] = flips
+        report["reward_max_abs"] = float(np.abs(grw - orc["reward"]).max())
+    else:
+        tol_r = np.zeros((T, E))
+        for k in range(E):
+            tol_r[:, k] = 0.05 * tol_e[:, ct[k]:ct[k + 1]].sum(1) / nt[k] + REL
+        dr_ = np.abs(grw - orc["reward"])
+        report["reward_max_abs"] = float(dr_.max())
+        assert (dr_ <= tol_r).all(), f"{label} rewards differ: {report}"
     np.testing.assert_array_equal(gpu["done"][:, packed_idx], orc["done"])
     # ---- observations
     gob = select(gpu["obs"], o["token"], packed_idx)

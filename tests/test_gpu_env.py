@@ -68,7 +68,8 @@ def test_ragged_counts_match_oracle(orc):
 
 @pytest.mark.parametrize("name", ["plain", "batched_small", "ragged_small", "window16_5x5",
                                   "gauss_newton", "detection_comm_loss", "fixed_8x8",
-                                  "fixed_7x6", "ragged_w3", "ragged_w7", "ragged_w12"])
+                                  "fixed_7x6", "ragged_w3", "ragged_w7", "ragged_w12",
+                                  "paper", "paper_tracking", "paper_5x5"])
 def test_rollout_parity(orc, name):
     if name == "plain":
         c = CONFIGS["plain"]
@@ -86,6 +87,12 @@ def test_rollout_parity(orc, name):
         cfg, E, T = env_config("batched", episode_len=60, n_agents=8, n_targets=8), 40, 60
     elif name == "fixed_7x6":
         cfg, E, T = env_config("batched", episode_len=60, n_agents=7, n_targets=6), 50, 60
+    elif name == "paper":  # Sec. IV-A-2/3: 30 s steps, rudder, follow reward, 450 m, spawn
+        cfg, E, T = env_config("paper", episode_len=60), 300, 60
+    elif name == "paper_tracking":  # the same with the tracking reward, Eq. (1)
+        cfg, E, T = env_config("paper", episode_len=60, reward_mode=0), 300, 60
+    elif name == "paper_5x5":
+        cfg, E, T = env_config("paper", episode_len=60, ragged=0, window=16), 64, 60
     elif name.startswith("ragged_w"):  # other window lengths (3..16 are accepted)
         W = int(name[len("ragged_w"):])
         cfg, E, T = env_config("ragged", episode_len=50, window=W), 200, 50
@@ -377,6 +384,34 @@ def test_metrics_match_oracle(orc):
         lost += (d > cfg["lost_range"]).sum()
     assert m[5] == lost == em[5]
     assert m[6] == E * T and m[7] == env.A * T
+
+
+@pytest.mark.parametrize("name", ["ragged", "paper"])
+def test_reset_state_matches_oracle(orc, name):
+    """Spawned positions, headings and target speeds right after reset: the
+    disk and square of the plain workloads and the pairwise 50-200 m layout
+    of the paper's (with every pair inside the bounds on the GPU too)."""
+    cfg = env_config(name)
+    E = 500
+    env = _env(cfg, E, seed=8)
+    out = _np(env.reset(2, record=("gstate",)))
+    ref = _oracle(orc, cfg, env, np.arange(E), 8, 0, episode=2)
+    o = env.order
+    s = cfg["area"] / 2
+    for k in range(E):
+        na, nt = env.n_agents[k], env.n_targets[k]
+        gb = o["agent"][k] + o["target"][k]
+        gs = out["gstate"][gb:gb + na + nt]
+        ra = ref["init_agent"][ref["csr"]["agent"][k]:ref["csr"]["agent"][k + 1]]
+        rt = ref["init_target"][ref["csr"]["target"][k]:ref["csr"]["target"][k + 1]]
+        assert np.abs(gs[:na, :2] - ra[:, :2]).max() <= 1e-5 * s
+        assert np.abs(gs[na:, :2] - rt[:, :2]).max() <= 1e-5 * s
+        assert angle_diff(gs[:na, 4], ra[:, 2]).max() <= 1e-5 * np.pi
+        if cfg["spawn_mode"] == 1:
+            xy = gs[:, :2].astype(np.float64)
+            d = np.hypot(xy[:, None, 0] - xy[None, :, 0], xy[:, None, 1] - xy[None, :, 1])
+            iu = np.triu_indices(na + nt, 1)
+            assert (d[iu] >= cfg["spawn_min"] - 1e-3).all() and (d[iu] <= cfg["spawn_max"] + 1e-3).all()
 
 
 def test_reset_observation(orc):

@@ -48,6 +48,8 @@ CASES = {
     "gauss_newton": ("ragged", {"gn_iters": 4}, 200, 30),
     "detection_comm_loss": ("ragged", {"det_range": 1200.0, "comm_range": 120.0,
                                        "comm_loss_p": 0.3}, 300, 30),
+    "paper_follow": ("paper", {}, 300, 30),
+    "paper_tracking": ("paper", {"reward_mode": 0}, 300, 30),
 }
 
 
@@ -130,8 +132,16 @@ def test_teacher_forced_tracker_error_reward_obs(orc, name):
                 de = np.abs(g_j[f] - e_j[f]) / np.maximum(e_j[f], s)
                 worst_err = max(worst_err, float(de.max()))
                 assert (de <= REL).all(), f"{name} t={t} env {k}: tracking error {de.max():.3g}"
-            r = sum(orc.tracking_reward(float(x), cfg["eps_min"], cfg["eps_max"])
-                    for x in g_j) / nt[k]
+            if cfg["reward_mode"] == 1:
+                # Eq. (2) on the GPU's own positions: nearest agent within d_follow
+                dn = np.hypot(ag[:, None, 0] - tg[None, :, 0], ag[:, None, 1] - tg[None, :, 1]).min(0)
+                if (np.abs(dn - cfg["d_follow"]) <= 1e-3).any():
+                    flips += 1
+                    continue
+                r = float((dn <= cfg["d_follow"]).mean())
+            else:
+                r = sum(orc.tracking_reward(float(x), cfg["eps_min"], cfg["eps_max"])
+                        for x in g_j) / nt[k]
             dd = np.hypot(ag[:, None, 0] - ag[None, :, 0], ag[:, None, 1] - ag[None, :, 1])
             close = dd[np.triu_indices(na[k], 1)]
             crash = bool((close < cfg["d_safe"]).any())
@@ -160,6 +170,6 @@ def test_teacher_forced_tracker_error_reward_obs(orc, name):
     print(f"{name}: {solved} solves, {held} holds, {flips} guard flips at the threshold; worst "
           f"relative: estimate {worst_est:.2e}, tracking error {worst_err:.2e}, token "
           f"{worst_tok:.2e}; reward |diff| {worst_rew:.2e}")
-    assert flips <= max(1, solved // 100000)
+    assert flips <= max(3, solved // 100000)
     assert math.isfinite(worst_est)
     env.close()
