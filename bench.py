@@ -12,6 +12,7 @@ line. `--workload NAME` runs one of them alone.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -237,7 +238,34 @@ def mlp_infer_flops_per_window(d_in=64, h=128, d_out=2):
     return 2 * (d_in * h + h * h + h * d_out)
 
 
-def train_estimator(args):
+# Where the learned estimator's windows come from. "learned": the ragged
+# configuration with W = 16 (1 s steps: a 16 m track per window); "paper": the
+# paper's environment with W = 16 (30 s steps: a track of hundreds of metres,
+# where the range-only solve is well posed), with the targets held still (the
+# least-squares solve assumes a target that does not move within its window;
+# at the paper's half speed a target moves 240 m in 16 steps and the window
+# measures that model error instead) and no detection cut (complete windows).
+WINDOW_SOURCES = {
+    "learned": dict(env=None, num_envs=None, train=None, infer=None, train_first=100,
+                    train_every=50, infer_first=125, infer_every=50, epochs=8),
+    "paper": dict(env=dict(window=16, episode_len=300, ragged=1, target_speed_lo=0.0,
+                           target_speed_hi=0.0, det_range=math.inf),
+                  num_envs=16384, train=4_000_000, infer=1_000_000, train_first=16,
+                  train_every=4, infer_first=18, infer_every=4, epochs=40),
+}
+
+
+def window_source(variant):
+    """(env config, envs, train windows, inference windows, schedule)."""
+    from paper_2505_08222_amd.configs import CONFIGS, env_config
+    src = WINDOW_SOURCES[variant]
+    if variant == "learned":
+        c = CONFIGS["learned"]
+        return (dict(c["env"]), c["num_envs"], c["train_windows"], c["infer_windows"], src)
+    return (env_config("paper", **src["env"]), src["num_envs"], src["train"], src["infer"], src)
+
+
+def train_estimator(args, variant="learned"):
     """The learned estimator's network, trained by the library's kernels on
     windows of ragged-configuration rollouts (W = 16): 1e7 windows, labels =
     exact estimates within 2x the mean range from tracks with condition
@@ -251,14 +279,13 @@ def train_estimator(args):
     from paper_2505_08222_amd import learned
     from paper_2505_08222_amd.configs import CONFIGS
 
-    c = CONFIGS["learned"]
-    cfg = dict(c["env"])
-    n_train = c["train_windows"]
+    cfg, n_envs, n_train, _, src = window_source(variant)
     if args.envs:
-        n_train = max(20000, int(n_train * args.envs / c["num_envs"]))
-    E = args.envs or c["num_envs"]
+        n_train = max(20000, int(n_train * args.envs / n_envs))
+    E = args.envs or n_envs
     t0 = time.perf_counter()
-    tr = learned.rollout_windows(cfg, E, n_train, seed=0)
+    tr = learned.rollout_windows(cfg, E, n_train, seed=0, first_step=src["train_first"],
+                                 every=src["train_every"])
     n_windows = int(tr["win"].shape[0])
     x, frame = learned.features(tr["win"])
     y = learned.targets(frame, tr["exact"])
@@ -270,8 +297,8 @@ def train_estimator(args):
         f"({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    params, hist = learned.train(x, y, epochs=8, batch=TRAIN_BATCH, lr=2e-3, lr_final=3e-5,
-                                 seed=0, log=lambda m: None)
+    params, hist = learned.train(x, y, epochs=src["epochs"], batch=TRAIN_BATCH, lr=2e-3,
+                                 lr_final=3e-5, seed=0, log=lambda m: None)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     log(f"[learned] trained {len(hist)} logged steps in {train_s:.1f} s, loss {hist[0][1]:.3e} -> "
@@ -298,7 +325,7 @@ def train_estimator(args):
     flops = mlp_train_flops_per_sample() * TRAIN_BATCH
     tflops = flops / (step_ms / 1e3) / 1e12
     info = {"seconds": train_s, "windows_generated": n_windows, "train_windows": int(x.shape[0]),
-            "epochs": 8, "batch": TRAIN_BATCH, "loss_first": hist[0][1], "loss_last": hist[-1][1],
+            "epochs": src["epochs"], "batch": TRAIN_BATCH, "loss_first": hist[0][1], "loss_last": hist[-1][1],
             "step_ms": step_ms, "samples_per_s": TRAIN_BATCH / (step_ms / 1e3),
             "mfma": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": tflops / 2500.0, "flops_per_step": flops,
@@ -335,11 +362,12 @@ def cpu_baseline_exact(win_cpu, budget_s):
                       f"closed form and 8 Gauss-Newton steps, about {budget_s / 2:.0f} s each"}
 
 
-def bench_learned(args, steps, cpu_seconds=None, trained=None):
+def bench_learned(args, steps, cpu_seconds=None, trained=None, variant="learned"):
     """Learned estimator (the learned-estimator configuration): windows of 16
-    from ragged-configuration rollouts, Adam training of the BF16 MLP with the
-    library's kernels, then guarded inference on a disjoint set, compared with
-    the exact estimator on error (m) and throughput."""
+    from ragged-configuration rollouts (or, variant "paper", from the paper's
+    30 s environment), Adam training of the BF16 MLP with the library's
+    kernels, then guarded inference on a disjoint set, compared with the exact
+    estimator on error (m) and throughput."""
     import numpy as np
     import torch
 
@@ -347,16 +375,15 @@ def bench_learned(args, steps, cpu_seconds=None, trained=None):
     from paper_2505_08222_amd.configs import CONFIGS
     from paper_2505_08222_amd.env import est_exact
 
-    c = CONFIGS["learned"]
-    cfg = dict(c["env"])
+    cfg, n_envs, _, n_infer, src = window_source(variant)
     torch.cuda.set_device(0)
-    n_infer = c["infer_windows"]
     if args.envs:  # smaller runs for quick checks
-        n_infer = max(20000, int(n_infer * args.envs / c["num_envs"]))
-    E = args.envs or c["num_envs"]
-    params, train_info = trained if trained is not None else train_estimator(args)
+        n_infer = max(20000, int(n_infer * args.envs / n_envs))
+    E = args.envs or n_envs
+    params, train_info = trained if trained is not None else train_estimator(args, variant)
     t0 = time.perf_counter()
-    te = learned.rollout_windows(cfg, E, n_infer, seed=1, first_step=125)
+    te = learned.rollout_windows(cfg, E, n_infer, seed=1, first_step=src["infer_first"],
+                                 every=src["infer_every"])
     log(f"[learned] inference windows {te['win'].shape[0]} ({time.perf_counter() - t0:.1f} s)")
     win, sigma, truth = te["win"], te["sigma"], te["truth"]
     N = win.shape[0]
@@ -390,7 +417,7 @@ def bench_learned(args, steps, cpu_seconds=None, trained=None):
     kap = window_condition(win).cpu().numpy()
     d_me = np.hypot(*(pm - pe).T)
     d_et = np.hypot(*(pe - pt).T)
-    bins = [(0, 100), (100, 500), (500, 1e9)]
+    bins = [(0, 50), (50, 100), (100, 200), (200, 500), (500, 1e9)]
     by_kappa = {}
     for lo, hi in [(1, 10), (10, 100), (100, 1e3), (1e3, np.inf)]:
         m = acc & ve & (kap >= lo) & (kap < hi)
@@ -422,8 +449,10 @@ def bench_learned(args, steps, cpu_seconds=None, trained=None):
         "n_gpus": 1, "steps": max(1, steps), "warmup": 1, "ms_per_step": ms_mlp,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": f"learned estimator: 16-entry windows from ragged-configuration "
-                               f"rollouts, train {train_info['train_windows']}, infer {N}",
+        "config": {"workload": f"learned estimator: 16-entry windows from "
+                               + ("ragged-configuration" if variant == "learned" else
+                                  "paper-environment (30 s step)")
+                               + f" rollouts, train {train_info['train_windows']}, infer {N}",
                    "train_windows": train_info["train_windows"], "infer_windows": int(N)},
         "infer_ms": {"learned_guarded": ms_mlp, "mlp_forward_only": ms_fwd,
                      "exact_fp64": ms_ex, "exact_fp32": ms_ex32, "exact_gauss_newton8": ms_gn},
@@ -691,7 +720,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
-                    choices=["all", "plain", "batched", "ragged", "learned", "policy"])
+                    choices=["all", "plain", "batched", "ragged", "learned", "policy", "paper",
+                             "learned_paper"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -713,8 +743,10 @@ def main():
         copy_probe()
         return
     cpu_s = None if args.no_cpu_baseline else args.cpu_seconds
-    if args.workload == "learned":
-        print(json.dumps(bench_learned(args, args.steps, cpu_seconds=cpu_s)), flush=True)
+    if args.workload in ("learned", "learned_paper"):
+        variant = "paper" if args.workload == "learned_paper" else "learned"
+        print(json.dumps(bench_learned(args, args.steps, cpu_seconds=cpu_s, variant=variant)),
+              flush=True)
         return
     if args.workload == "policy":
         print(json.dumps(bench_policy(args, args.steps, args.warmup, cpu_seconds=cpu_s)),
@@ -737,7 +769,11 @@ def main():
     result["learned"] = bench_learned(args, args.steps, cpu_seconds=sec_cpu, trained=(mlp, train_info))
     result["policy"] = bench_policy(args, min(args.steps, 3), min(args.warmup, 1), mlp=mlp,
                                     cpu_seconds=sec_cpu)
-    for k in ("batched", "learned", "policy"):
+    # the paper's own environment (30 s steps, rudder, follow reward, 450 m
+    # detection, pairwise spawn) and the learned estimator on its windows
+    result["paper"] = bench_env(args, "paper", args.steps, args.warmup, cpu_seconds=sec_cpu)
+    result["learned_paper"] = bench_learned(args, args.steps, variant="paper")
+    for k in ("batched", "learned", "policy", "paper", "learned_paper"):
         for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
             result[k].pop(key, None)
     result["bench_seconds"] = time.perf_counter() - t_start
