@@ -17,6 +17,7 @@
 
 #define OMAX 8   /* most agents / targets per env */
 #define OWMAX 64 /* longest window */
+#define OROWS (OMAX * OWMAX) /* most rows of one tracker's solve (pooled windows) */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, as defined by Salmon, Moraes, Dror and Shaw, "Parallel    */
@@ -183,7 +184,8 @@ int orc_ls_estimate_sens(int n, const double *ax, const double *ay, const double
                          double tau, double *px, double *py, double *sens) {
   int ok = orc_ls_estimate(n, ax, ay, r, gn_iters, tau, px, py);
   if (!ok) return 0;
-  double bx[OWMAX], by[OWMAX], br[OWMAX];
+  if (n > OROWS) return 0;
+  double bx[OROWS], by[OROWS], br[OROWS];
   memcpy(bx, ax, sizeof(double) * n);
   memcpy(by, ay, sizeof(double) * n);
   memcpy(br, r, sizeof(double) * n);
@@ -263,6 +265,9 @@ typedef struct {
   int ev[OMAX][OMAX];
   int comm_ok[OMAX];
   int rud[OMAX];  /* rudder position of each agent (action_mode 1) */
+  /* rec[i][k][e]: agent i received agent k's broadcast (its position and
+   * ranges) of window entry e; rec[i][i][e] = 1 */
+  unsigned char rec[OMAX][OMAX][OWMAX];
 } oenv;
 
 /* Pairwise spawn (Sec. IV-A-2: every entity at least spawn_min and at most
@@ -480,6 +485,15 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
     E->hy[i][0] = E->ay[i];
   }
   if (E->filled < E->W) E->filled += 1;
+  /* what each agent receives this step (the same rule as its observation of
+   * the other agents): a broadcast that was not dropped, within comm_range */
+  for (int i = 0; i < E->nA; ++i) {
+    for (int k2 = 0; k2 < E->nA; ++k2) {
+      for (int k = E->W - 1; k > 0; --k) E->rec[i][k2][k] = E->rec[i][k2][k - 1];
+      const double dx = E->ax[k2] - E->ax[i], dy = E->ay[k2] - E->ay[i];
+      E->rec[i][k2][0] = (unsigned char)(k2 == i || (E->comm_ok[k2] && hypot(dx, dy) <= p->comm_range));
+    }
+  }
   /* noisy ranges after the move; missing beyond the detection range */
   for (int i = 0; i < E->nA; ++i) {
     for (int q = 0; 4 * q < E->nT; ++q) {
@@ -499,14 +513,20 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
   /* per-(agent,target) tracker over the valid window entries; hold on failure */
   for (int i = 0; i < E->nA; ++i) {
     for (int j = 0; j < E->nT; ++j) {
-      double wx[OWMAX], wy[OWMAX], wr[OWMAX];
+      double wx[OROWS], wy[OROWS], wr[OROWS];
       int n = 0;
-      for (int k = 0; k < E->filled; ++k) {
-        if (isnan(E->hr[i][j][k])) continue;
-        wx[n] = E->hx[i][k];
-        wy[n] = E->hy[i][k];
-        wr[n] = E->hr[i][j][k];
-        ++n;
+      /* rows: agent i's own entries, then (pooled) those of every other agent
+       * whose broadcast of that entry agent i received, agent by agent */
+      for (int k2 = 0; k2 < E->nA; ++k2) {
+        const int a = (k2 == 0) ? i : (k2 <= i ? k2 - 1 : k2);
+        if (a != i && !p->pooled) break;
+        for (int k = 0; k < E->filled; ++k) {
+          if (isnan(E->hr[a][j][k]) || !E->rec[i][a][k]) continue;
+          wx[n] = E->hx[a][k];
+          wy[n] = E->hy[a][k];
+          wr[n] = E->hr[a][j][k];
+          ++n;
+        }
       }
       double px, py, s = NAN;
       int ok = o->sens ? orc_ls_estimate_sens(n, wx, wy, wr, p->gn_iters, p->guard_tau, &px, &py, &s)
@@ -590,6 +610,7 @@ int orc_rollout(const orc_params *p, uint64_t seed, uint64_t episode, int64_t n_
   if (p->spawn_mode == 1 && !(p->spawn_min >= 0.0 && p->spawn_max >= 2.0 * sqrt(3.0) * p->spawn_min))
     return -1;
   if (p->spawn_mode == 1 && p->n_agents + p->n_targets > 13) return -1;
+  if (p->pooled != 0 && p->pooled != 1) return -1;
   for (int64_t k = 0; k < n_sel; ++k)
     if (n_agents[k] < 1 || n_agents[k] > OMAX || n_targets[k] < 1 || n_targets[k] > OMAX)
       return -1;

@@ -76,6 +76,11 @@ typedef struct orc_params {
   double d_follow;         /* Eq. (2): a target is followed when some agent is
                               within this distance (m) */
   double spawn_min, spawn_max; /* pairwise spawn distances of spawn_mode 1 (m) */
+  int32_t pooled;          /* 1: each agent's tracker of a target also uses the
+                              ranges to it that the agent received from the other
+                              agents (Sec. IV-A-2: every tracker is updated with
+                              all the information received); 0: own ranges only */
+  int32_t pad2_;
 } orc_params;
 
 /* Per-step records of an oracle rollout. Every pointer may be NULL. Entity

@@ -29,7 +29,7 @@ class OrcParams(C.Structure):
         ("guard_tau", C.c_double), ("lost_range", C.c_double),
         ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
         ("spawn_mode", C.c_int32), ("d_follow", C.c_double), ("spawn_min", C.c_double),
-        ("spawn_max", C.c_double),
+        ("spawn_max", C.c_double), ("pooled", C.c_int32), ("pad2_", C.c_int32),
     ]
 
 
@@ -118,7 +118,7 @@ def _p(a, ctype):
 def make_params(cfg: dict) -> OrcParams:
     p = OrcParams()
     for name, _ in OrcParams._fields_:
-        if name == "pad_":
+        if name in ("pad_", "pad2_"):
             continue
         if name == "action_dpsi":
             vals = list(cfg["action_dpsi"]) + [0.0] * (8 - len(cfg["action_dpsi"]))

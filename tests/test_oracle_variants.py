@@ -227,3 +227,68 @@ def test_paper_configuration_values():
     np.testing.assert_allclose(c["action_dpsi"], [-1.45, -0.725, 0.0, 0.725, 1.45])
     assert (c["det_range"], c["comm_range"], c["d_follow"]) == (450.0, 1500.0, 50.0)
     assert (c["spawn_min"], c["spawn_max"]) == (50.0, 200.0)
+
+
+# ----------------------------------------------------- pooled (communicated) LS
+def test_pooled_without_reception_equals_own_windows(orc):
+    """With nothing received (comm range 0) or one agent per env, the pooled
+    tracker has only its own rows: every estimate equals the unpooled one."""
+    for over in ({"comm_range": 0.0}, {"n_agents": 1, "ragged": 0}):
+        cfg0 = env_config("ragged", episode_len=40, **over)
+        cfg1 = dict(cfg0, pooled=1)
+        a, _, _ = _run(orc, cfg0, 40, 40)
+        b, _, _ = _run(orc, cfg1, 40, 40)
+        np.testing.assert_array_equal(a["est"], b["est"])
+        np.testing.assert_array_equal(a["est_valid"], b["est_valid"])
+
+
+def test_pooled_exact_recovery_noise_free(orc):
+    """Noise-free ranges and still targets: every pooled estimate is the true
+    target position (the rows of all agents are consistent)."""
+    cfg = env_config("ragged", episode_len=30, pooled=1, range_sigma_lo=0.0,
+                     range_sigma_hi=0.0, target_speed_lo=0.0, target_speed_hi=0.0,
+                     comm_range=5000.0)
+    out, na, nt = _run(orc, cfg, 30, 30)
+    csr = out["csr"]
+    v = out["est_valid"][-1].astype(bool)
+    assert v.mean() > 0.9
+    for e in range(30):
+        tg = out["target"][-1, csr["target"][e]:csr["target"][e + 1], :2]
+        est = out["est"][-1, csr["pair"][e]:csr["pair"][e + 1]].reshape(na[e], nt[e], 2)
+        ok = out["est_valid"][-1, csr["pair"][e]:csr["pair"][e + 1]].reshape(na[e], nt[e]) == 1
+        d = np.abs(est - tg[None, :, :]).max(-1)
+        assert (d[ok] < 1e-6).all()
+
+
+def test_pooled_rows_are_the_received_windows(orc):
+    """Each pooled estimate equals the linearised LS over the rows rebuilt from
+    the rollout's own records: the agent's positions and ranges of the last W
+    steps, plus those of each other agent at the steps where the observing
+    agent's token for it was present (its broadcast was received)."""
+    cfg = env_config("ragged", episode_len=25, pooled=1, comm_range=150.0, comm_loss_p=0.3)
+    E, T, W = 30, 25, cfg["window"]
+    out, na, nt = _run(orc, cfg, E, T)
+    csr = out["csr"]
+    checked = 0
+    for e in range(E):
+        A, N = na[e], nt[e]
+        ag = out["agent"][:, csr["agent"][e]:csr["agent"][e + 1], :2]
+        rg = out["ranges"][:, csr["pair"][e]:csr["pair"][e + 1]].reshape(T, A, N)
+        tok = out["obs_mask"][:, csr["token"][e]:csr["token"][e + 1]].reshape(T, A, A + N)
+        t = T - 1
+        for i in range(A):
+            others = [k for k in range(A) if k != i]
+            for j in range(N):
+                rows = []
+                for k in [i] + others:
+                    for s in range(t, max(-1, t - W), -1):
+                        heard = k == i or tok[s, i, 1 + others.index(k)] == 1
+                        if heard and not np.isnan(rg[s, k, j]):
+                            rows.append((ag[s, k, 0], ag[s, k, 1], rg[s, k, j]))
+                win = np.array(rows, np.float64)[None]
+                q, ok = orc.ls_batch(win)
+                p = csr["pair"][e] + i * N + j
+                if ok[0] and out["est_fresh"][t, p]:
+                    np.testing.assert_allclose(out["est"][t, p], q[0], rtol=0, atol=1e-9)
+                    checked += 1
+    assert checked > 40
