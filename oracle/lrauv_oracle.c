@@ -219,9 +219,9 @@ void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
 #pragma omp parallel for schedule(static)
 #endif
   for (int64_t i = 0; i < N; ++i) {
-    double ax[OWMAX], ay[OWMAX], r[OWMAX];
+    double ax[OROWS], ay[OROWS], r[OROWS];
     int n = 0;
-    for (int k = 0; k < W && k < OWMAX; ++k) {
+    for (int k = 0; k < W && k < OROWS; ++k) {
       const double *e = win + (i * W + k) * 3;
       if (isnan(e[2])) continue;
       ax[n] = e[0];

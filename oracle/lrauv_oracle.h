@@ -140,8 +140,9 @@ int orc_ls_estimate(int n, const double *ax, const double *ay, const double *r,
  * orc_traj.sens (used to derive per-element parity tolerances). */
 int orc_ls_estimate_sens(int n, const double *ax, const double *ay, const double *r,
                          int gn_iters, double tau, double *px, double *py, double *sens);
-/* Batched form over windows [N][W][3] = (ax, ay, r), r NaN = missing entry.
- * Entries are taken in window order; out [N][2]; valid [N]. */
+/* Batched form over windows [N][W][3] = (ax, ay, r), r NaN = missing entry,
+ * W <= 512 rows (pooled windows of 8 agents x 64 entries). Entries are taken
+ * in window order; out [N][2]; valid [N]. */
 void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
                   double *out, uint8_t *valid, int n_threads);
 

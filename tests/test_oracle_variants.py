@@ -292,3 +292,21 @@ def test_pooled_rows_are_the_received_windows(orc):
                     np.testing.assert_allclose(out["est"][t, p], q[0], rtol=0, atol=1e-9)
                     checked += 1
     assert checked > 40
+
+
+def test_batch_solver_takes_long_pooled_windows(orc):
+    """Pooled windows reach 8 agents x 16 entries: the batch solver uses every
+    row of a 128-row window (equal to the single solve on the same rows, and
+    different from the solve on its first 64)."""
+    rng = np.random.default_rng(4)
+    n = 128
+    a = np.cumsum(rng.normal(0, 3, (n, 2)), 0)
+    tgt = np.array([250.0, -90.0])
+    r = np.hypot(*(a - tgt).T) + rng.normal(0, 1.0, n)
+    win = np.column_stack([a, r])[None]
+    q, ok = orc.ls_batch(win)
+    okk, px, py = orc.ls_estimate(a[:, 0], a[:, 1], r)
+    assert ok[0] and okk
+    np.testing.assert_allclose(q[0], [px, py], rtol=0, atol=1e-9)
+    q64, _ = orc.ls_batch(win[:, :64])
+    assert np.abs(q64[0] - q[0]).max() > 1e-6
