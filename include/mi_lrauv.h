@@ -117,7 +117,13 @@ typedef enum mil_status {
  *                       most spawn_max from every other: jittered sites of a
  *                       randomly rotated hexagonal patch about the centre, in
  *                       random order (needs n_agents + n_targets <= 13 and
- *                       spawn_max >= 2 sqrt(3) spawn_min). */
+ *                       spawn_max >= 2 sqrt(3) spawn_min).
+ *  pooled               1: each agent's tracker of a target solves over its
+ *                       own window and the entries of every other agent whose
+ *                       broadcast of that step it received (not dropped,
+ *                       within comm_range; Sec. IV-A-2: trackers are updated
+ *                       with all the information received); needs gn_iters = 0
+ *                       and the exact estimator in the loop. */
 typedef struct mil_env_params {
   int32_t n_agents, n_targets, ragged, window;
   int32_t episode_len, n_actions, gn_iters, reserved0;
@@ -130,6 +136,7 @@ typedef struct mil_env_params {
   float eps_min, eps_max, d_safe, guard_tau, lost_range;
   int32_t action_mode, n_rudder, reward_mode, spawn_mode;
   float d_follow, spawn_min, spawn_max;
+  int32_t pooled;
 } mil_env_params;
 
 /* Sizes of a created environment batch. */

@@ -40,7 +40,7 @@ class EnvParams(C.Structure):
         ("guard_tau", C.c_float), ("lost_range", C.c_float),
         ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
         ("spawn_mode", C.c_int32), ("d_follow", C.c_float), ("spawn_min", C.c_float),
-        ("spawn_max", C.c_float),
+        ("spawn_max", C.c_float), ("pooled", C.c_int32),
     ]
 
 

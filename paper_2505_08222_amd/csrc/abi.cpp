@@ -91,7 +91,7 @@ struct mil_env {
   int64_t ws_bytes = 0;
   struct {
     int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue, mpart;
-    int64_t ax, ay, apsi, arud, tx, ty, tpsi, tv, sigma, hx, hy, hr, ex, ey, ev, macc, miacc;
+    int64_t ax, ay, apsi, arud, tx, ty, tpsi, tv, sigma, hx, hy, hr, hrec, ex, ey, ev, macc, miacc;
     int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
   mil::DevParams dp{};
@@ -131,6 +131,9 @@ bool valid_params(const mil_env_params *p, std::string &why) {
     return bad("rudder actions need n_actions = 3 and n_rudder in 1..8");
   if (p->reward_mode != 0 && p->reward_mode != 1) return bad("reward_mode must be 0 or 1");
   if (p->spawn_mode != 0 && p->spawn_mode != 1) return bad("spawn_mode must be 0 or 1");
+  if (p->pooled != 0 && p->pooled != 1) return bad("pooled must be 0 or 1");
+  if (p->pooled == 1 && p->gn_iters != 0)
+    return bad("the pooled tracker is the linearised solve: gn_iters must be 0");
   if (p->spawn_mode == 1 &&
       (p->n_agents + p->n_targets > 13 || !(p->spawn_min >= 0.f) ||
        !((double)p->spawn_max >= 2.0 * std::sqrt(3.0) * (double)p->spawn_min)))
@@ -211,6 +214,7 @@ void fill_dev_params(mil_env *h) {
   d.d_follow = p.d_follow;
   d.spawn_min = p.spawn_min;
   d.spawn_max = p.spawn_max;
+  d.pooled = p.pooled;
 }
 
 mil::DevOut dev_out(const mil_env_outputs *o) {
@@ -386,6 +390,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.hx = take((int64_t)h->W * A * 4);
   f.hy = take((int64_t)h->W * A * 4);
   f.hr = take((int64_t)h->W * P * 4);
+  f.hrec = take((int64_t)h->W * A);
   f.ex = take(P * 4);
   f.ey = take(P * 4);
   f.ev = take(P);
@@ -468,6 +473,7 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.hx = F(h->off.hx);
   d.hy = F(h->off.hy);
   d.hr = F(h->off.hr);
+  d.hrec = (uint8_t *)(h->ws + h->off.hrec);
   d.ex = F(h->off.ex);
   d.ey = F(h->off.ey);
   d.ev = (uint8_t *)(h->ws + h->off.ev);
@@ -877,6 +883,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
   int rc = check_outputs(outs);
   if (rc) return rc;
   const bool learned = d_mlp_params != nullptr;
+  if (learned && h->P.pooled)
+    return fail(MIL_EINVAL, "the learned estimator in the loop takes one agent's own window: "
+                            "pooled must be 0");
   if (learned && (h->P.window > 21 || !(k_sigma >= 0.0f)))
     return fail(MIL_EINVAL, "the learned estimator needs window <= 21 and k_sigma >= 0");
   const int64_t A = h->aoff[h->E], K = h->koff[h->E], Pn = h->poff[h->E];

@@ -16,6 +16,7 @@ struct DevParams {
   uint32_t key0, key1;
   int32_t action_mode, n_rudder, reward_mode, spawn_mode;
   float d_follow, spawn_min, spawn_max;
+  int32_t pooled;
 };
 
 // One (agents, targets) shape. Environments of a shape are consecutive in
@@ -45,6 +46,7 @@ struct DevState {
   float *sigma;                              // [E]
   float *hx, *hy;                            // [W][A], entry 0 = newest
   float *hr;                                 // [W][P]
+  uint8_t *hrec;                             // [W][A] received-broadcast bits (pooled)
   float *ex, *ey;                            // [P]
   uint8_t *ev;                               // [P]
   double *macc;                              // [E][3] reward, err, err^2 sums

@@ -525,10 +525,15 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
     int rud = (FULL && p.action_mode == 1) ? ld_st(&s.arud[aidx], dyn) : 0;
     float hx[WC], hy[WC], hr[NPL][WC], ex[NPL], ey[NPL];
     uint32_t evb = 0;
+    // pooled tracker: which agents' broadcasts of each window entry this
+    // agent received (bit k = agent k; its own bit always set)
+    uint32_t recm[FULL ? WC : 1];
 #pragma unroll
     for (int k = 0; k < WC; ++k) {
       hx[k] = (k < W) ? ld_st(&s.hx[(int64_t)k * s.A + aidx], dyn) : 0.0f;
       hy[k] = (k < W) ? ld_st(&s.hy[(int64_t)k * s.A + aidx], dyn) : 0.0f;
+      if constexpr (FULL)
+        recm[k] = (p.pooled && k < W) ? (uint32_t)ld_st(&s.hrec[(int64_t)k * s.A + aidx], dyn) : 0u;
     }
 #pragma unroll
     for (int sl = 0; sl < NPL; ++sl) {
@@ -679,6 +684,25 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         hy[0] = ay;
 #pragma unroll
         for (int sl = 0; sl < NPL; ++sl) hr[sl][0] = rnew[sl];
+        if constexpr (FULL) {
+          if (p.pooled) {
+            // what this agent receives this step: the observation's rule (a
+            // broadcast not dropped, within comm_range), its own entry always
+#pragma unroll
+            for (int k = WC - 1; k > 0; --k) recm[k] = recm[k - 1];
+            uint32_t bits = 0;
+#pragma unroll
+            for (int k = 0; k < MA; ++k) {
+              if (k < na) {
+                const float ox = env_shfl<S>(ax, base_lane, k * G, lpe);
+                const float oy = env_shfl<S>(ay, base_lane, k * G, lpe);
+                const int oc = env_shfl<S>((int)comm_ok, base_lane, k * G, lpe);
+                if (k == i || (oc && sqnorm(ox - ax, oy - ay) <= comm2)) bits |= 1u << k;
+              }
+            }
+            recm[0] = bits;
+          }
+        }
       }
       if (FULL && ext.win && move && active) {
         // phase 1 hands the windows to the estimator (entry 0 newest)
@@ -719,7 +743,82 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       // term of the centred form vanishes because sum u_k = 0). Other trackers
       // take the general path below.
       uint32_t pending = 0;
-      if (FULL && ext.phase == 2 && filled == W) {
+      if (FULL && p.pooled) {
+        // ---- pooled tracker: the agent's own entries and those of every
+        // agent whose broadcast of that entry it received; each lane's window
+        // goes to LDS, then a two-pass centred LS over the received rows (FP64)
+        constexpr int WS = WC * (2 + NPL);  // floats of one lane's window
+        float *pw = reinterpret_cast<float *>(lds_targets + (size_t)(blockDim.x >> 6) * 64 * MT) +
+                    (size_t)wib * 64 * WS;
+        {
+          float *mine = pw + lane * WS;
+#pragma unroll
+          for (int k = 0; k < WC; ++k) {
+            mine[k] = hx[k];
+            mine[WC + k] = hy[k];
+#pragma unroll
+            for (int sl = 0; sl < NPL; ++sl) mine[(2 + sl) * WC + k] = hr[sl][k];
+          }
+        }
+        wave_lds_fence();
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt) {
+            int n = 0;
+            double mx = 0.0, my = 0.0, mr = 0.0;
+            for (int k = 0; k < na; ++k) {
+              const float *src = pw + (base_lane + k * G + g) * WS;
+#pragma unroll
+              for (int e = 0; e < WC; ++e) {
+                const float rk = src[(2 + sl) * WC + e];
+                if (e < filled && ((recm[e] >> k) & 1u) && rk == rk) {
+                  mx += (double)src[e];
+                  my += (double)src[WC + e];
+                  mr += (double)rk;
+                  ++n;
+                }
+              }
+            }
+            if (n >= 3) {
+              const double inv = 1.0 / (double)n;
+              mx *= inv;
+              my *= inv;
+              mr *= inv;
+              double sxx = 0.0, sxy = 0.0, syy = 0.0, gx = 0.0, gy = 0.0;
+              for (int k = 0; k < na; ++k) {
+                const float *src = pw + (base_lane + k * G + g) * WS;
+#pragma unroll
+                for (int e = 0; e < WC; ++e) {
+                  const float rk = src[(2 + sl) * WC + e];
+                  if (e < filled && ((recm[e] >> k) & 1u) && rk == rk) {
+                    const double ux = (double)src[e] - mx, uy = (double)src[WC + e] - my;
+                    const double d = (double)rk - mr;
+                    const double c = fma(ux, ux, uy * uy) - d * fma(2.0, mr, d);
+                    sxx = fma(ux, ux, sxx);
+                    sxy = fma(ux, uy, sxy);
+                    syy = fma(uy, uy, syy);
+                    gx = fma(ux, c, gx);
+                    gy = fma(uy, c, gy);
+                  }
+                }
+              }
+              const double det = fma(sxx, syy, -sxy * sxy), tr = sxx + syy;
+              if (det > tau * tr * tr) {
+                const double hd = 0.5 / det;
+                const float nx = (float)fma(hd, fma(syy, gx, -sxy * gy), mx);
+                const float ny = (float)fma(hd, fma(sxx, gy, -sxy * gx), my);
+                if (nx == nx && ny == ny) {
+                  ex[sl] = nx;
+                  ey[sl] = ny;
+                  evb |= 1u << sl;
+                }
+              }
+            }
+          }
+        }
+        wave_lds_fence();  // every lane has read before the next step's writes
+      } else if (FULL && ext.phase == 2 && filled == W) {
         // estimates from the external estimator (window full)
 #pragma unroll
         for (int sl = 0; sl < NPL; ++sl) {
@@ -1078,6 +1177,13 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
         st_st(&s.ay[aidx], ay, dyn);
         st_st(&s.apsi[aidx], apsi, dyn);
         if (FULL && p.action_mode == 1) st_st(&s.arud[aidx], rud, dyn);
+        if constexpr (FULL) {
+          if (p.pooled) {
+#pragma unroll
+            for (int k = 0; k < WC; ++k)
+              if (k < W) st_st(&s.hrec[(int64_t)k * s.A + aidx], (uint8_t)recm[k], dyn);
+          }
+        }
 #pragma unroll
         for (int k = 0; k < WC; ++k) {
           if (k < W) {
@@ -1299,9 +1405,14 @@ static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams 
                             const DevState &hs, const DevState *s, int32_t t0, int32_t T,
                             uint32_t episode, const int32_t *actions, const DevOut &o,
                             hipStream_t st, const DevExt &ext, int32_t sched) {
-  // per wavefront: target slab, then (lean form) token offsets and masks
+  // per wavefront: target slab, then (lean form) token offsets and masks, or
+  // (full form, pooled tracker) every lane's window; the pooled form runs
+  // one wavefront per block to keep the block's LDS small
+  if (FULL && p.pooled) waves_per_block = 1;
+  constexpr int NPLT = (S + G - 1) / G;
   const size_t lds = (size_t)waves_per_block *
-                     (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0));
+                     (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0) +
+                      ((FULL && p.pooled) ? 64 * WC * (2 + NPLT) * sizeof(float) : 0));
   int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
   int32_t chunk = 0;
   if ((sched >= 0 || sched == kSchedProbe) && hs.queue) {
@@ -1351,7 +1462,7 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
                     !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
                     p.comm_loss_p == 0.0f && p.gn_iters == 0 && ext.phase == 0 &&
-                    p.action_mode == 0 && p.reward_mode == 0;
+                    p.action_mode == 0 && p.reward_mode == 0 && p.pooled == 0;
   // the lean form stages its observation block for a coalesced write once at
   // least two wavefronts per SIMD take turns on the store path (large
   // batches); small batches are latency-bound and write directly

@@ -69,7 +69,8 @@ def test_ragged_counts_match_oracle(orc):
 @pytest.mark.parametrize("name", ["plain", "batched_small", "ragged_small", "window16_5x5",
                                   "gauss_newton", "detection_comm_loss", "fixed_8x8",
                                   "fixed_7x6", "ragged_w3", "ragged_w7", "ragged_w12",
-                                  "paper", "paper_tracking", "paper_5x5"])
+                                  "paper", "paper_tracking", "paper_5x5", "pooled",
+                                  "pooled_paper", "pooled_8x8"])
 def test_rollout_parity(orc, name):
     if name == "plain":
         c = CONFIGS["plain"]
@@ -93,6 +94,14 @@ def test_rollout_parity(orc, name):
         cfg, E, T = env_config("paper", episode_len=60, reward_mode=0), 300, 60
     elif name == "paper_5x5":
         cfg, E, T = env_config("paper", episode_len=60, ragged=0, window=16), 64, 60
+    elif name == "pooled":  # trackers also use the ranges received from other agents
+        cfg, E, T = env_config("ragged", episode_len=50, pooled=1, comm_range=300.0,
+                               comm_loss_p=0.2, det_range=1500.0), 200, 50
+    elif name == "pooled_paper":
+        cfg, E, T = env_config("paper", episode_len=50, pooled=1), 200, 50
+    elif name == "pooled_8x8":  # the largest rows: 8 agents x 16 entries
+        cfg, E, T = env_config("batched", episode_len=40, n_agents=8, n_targets=8, window=16,
+                               pooled=1, comm_range=2000.0, comm_loss_p=0.1), 24, 40
     elif name.startswith("ragged_w"):  # other window lengths (3..16 are accepted)
         W = int(name[len("ragged_w"):])
         cfg, E, T = env_config("ragged", episode_len=50, window=W), 200, 50

@@ -173,3 +173,84 @@ def test_teacher_forced_tracker_error_reward_obs(orc, name):
     assert flips <= max(3, solved // 100000)
     assert math.isfinite(worst_est)
     env.close()
+
+
+POOLED_CASES = {
+    "pooled_ragged": ("ragged", {"pooled": 1, "comm_range": 300.0, "comm_loss_p": 0.2,
+                                 "det_range": 1500.0}, 200, 30),
+    "pooled_paper": ("paper", {"pooled": 1}, 200, 30),
+    "pooled_8x8_w16": ("batched", {"pooled": 1, "n_agents": 8, "n_targets": 8, "window": 16,
+                                   "comm_range": 2000.0, "comm_loss_p": 0.1}, 16, 30),
+}
+
+
+@pytest.mark.parametrize("name", list(POOLED_CASES))
+def test_teacher_forced_pooled_tracker(orc, name):
+    """Pooled tracker: after every step each tracker's rows are rebuilt from
+    the GPU's own records (positions, ranges, and the observing agent's
+    agent-token masks, which say whose broadcast it received) over the last W
+    steps, and solved by the FP64 oracle: solved trackers match within 1e-5
+    relative, refused ones hold their estimate bit for bit."""
+    from paper_2505_08222_amd.env import Env
+
+    base, over, E, T = POOLED_CASES[name]
+    cfg = env_config(base, episode_len=T, **over)
+    W, s, tau = cfg["window"], cfg["area"] / 2.0, cfg["guard_tau"]
+    env = Env(cfg, E, seed=13)
+    env.reset(0)
+    o = env.order
+    na, nt = env.n_agents, env.n_targets
+    hist = []
+    prev_est = np.zeros((env.P, 2), np.float32)
+    prev_valid = np.zeros(env.P, bool)
+    solved = held = flips = 0
+    worst = 0.0
+    rec = ("obs_mask", "est", "est_valid", "gstate", "ranges")
+    for t in range(T):
+        out = {k: v.cpu().numpy() for k, v in env.step(record=rec).items()}
+        hist.append(out)
+        steps = list(range(t, max(-1, t - W), -1))
+        wins = []
+        for k in range(E):
+            A, N = na[k], nt[k]
+            gb = o["agent"][k] + o["target"][k]
+            for i in range(A):
+                others = [m for m in range(A) if m != i]
+                for j in range(N):
+                    rows = []
+                    for a in [i] + others:
+                        for st in steps:
+                            h = hist[st]
+                            heard = a == i or h["obs_mask"][o["token"][k] + i * (A + N) + 1 +
+                                                           others.index(a)] == 1
+                            r = h["ranges"][o["pair"][k] + a * N + j]
+                            if heard and r == r:
+                                rows.append((h["gstate"][gb + a, 0], h["gstate"][gb + a, 1], r))
+                    wins.append(rows)
+        L = max(3, max(len(w) for w in wins))
+        arr = np.full((len(wins), L, 3), np.nan)
+        for n, w in enumerate(wins):
+            if w:
+                arr[n, :len(w)] = np.array(w, np.float64)
+        q, ok = orc.ls_batch(arr, tau=tau)
+        ok = ok.astype(bool)
+        est, ev = out["est"].astype(np.float64), out["est_valid"].astype(bool)
+        den = np.maximum(np.abs(q).max(1), s)
+        d = np.abs(est - q).max(1)
+        matches = ev & (d <= 1e-5 * den)
+        gpu_held = (out["est"] == prev_est).all(1) & (ev == prev_valid)
+        good = np.where(ok, matches, gpu_held)
+        bad = ~good
+        flips += int(bad.sum())
+        assert bad.sum() <= max(1, ok.sum() // 20000), (
+            f"{name} t={t}: {int(bad.sum())} trackers differ, e.g. {np.flatnonzero(bad)[:6]} "
+            f"(oracle ok {ok[bad][:6]}, gpu valid {ev[bad][:6]}, rel {(d / den)[bad][:6]})")
+        if (ok & good).any():
+            worst = max(worst, float((d / den)[ok & good].max()))
+        solved += int((ok & good).sum())
+        held += int((~ok & good).sum())
+        prev_est, prev_valid = out["est"].copy(), ev.copy()
+    print(f"{name}: {solved} pooled solves, {held} holds, {flips} guard flips; worst relative "
+          f"{worst:.2e}")
+    assert solved > 0 and flips <= max(2, solved // 20000)
+    env.close()
