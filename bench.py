@@ -721,7 +721,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "plain", "batched", "ragged", "learned", "policy", "paper",
-                             "learned_paper"])
+                             "paper_pooled", "learned_paper"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -772,8 +772,10 @@ def main():
     # the paper's own environment (30 s steps, rudder, follow reward, 450 m
     # detection, pairwise spawn) and the learned estimator on its windows
     result["paper"] = bench_env(args, "paper", args.steps, args.warmup, cpu_seconds=sec_cpu)
+    result["paper_pooled"] = bench_env(args, "paper_pooled", args.steps, args.warmup,
+                                       cpu_seconds=sec_cpu)
     result["learned_paper"] = bench_learned(args, args.steps, variant="paper")
-    for k in ("batched", "learned", "policy", "paper", "learned_paper"):
+    for k in ("batched", "learned", "policy", "paper", "paper_pooled", "learned_paper"):
         for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
             result[k].pop(key, None)
     result["bench_seconds"] = time.perf_counter() - t_start

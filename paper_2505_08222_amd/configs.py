@@ -75,7 +75,12 @@ PAPER = dict(name="paper", num_envs=16384, steps=300, seed=0,
                       comm_range=1500.0, comm_loss_p=0.1, reward_mode=1, d_follow=50.0,
                       spawn_mode=1, spawn_min=50.0, spawn_max=200.0))
 
-CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY, PAPER)}
+# The same with pooled trackers: each agent's tracker of a target also uses
+# the ranges received from the other agents (Sec. IV-A-2).
+PAPER_POOLED = dict(PAPER, name="paper_pooled", env=dict(PAPER["env"], pooled=1))
+
+CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY, PAPER,
+                                  PAPER_POOLED)}
 
 
 def env_config(name: str, **overrides) -> dict:
