@@ -77,7 +77,13 @@ static double wrap_angle(double a) {
 }
 
 /* RNG counter words: (step or 0, global env id, entity code, purpose). */
-enum { PURPOSE_DYNAMICS = 0, PURPOSE_MEASURE = 1, PURPOSE_RESET = 2, PURPOSE_CONFIG = 3 };
+enum {
+  PURPOSE_DYNAMICS = 0,
+  PURPOSE_MEASURE = 1,
+  PURPOSE_RESET = 2,
+  PURPOSE_CONFIG = 3,
+  PURPOSE_PF = 7 /* particle-filter draws: entity (8 agent + target) * 64 + particle */
+};
 enum { ENT_TARGET_BLOCK = 16, ENT_RANGE_ROW = 64, ENT_ENV = 127 };
 
 static void draw(uint64_t seed, uint32_t c0, uint32_t env, uint32_t entity, uint32_t c3,
@@ -237,6 +243,94 @@ void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Particle-filter tracker (Sec. II: a belief over the target's position held */
+/* as particles, moved by a motion model and resampled by the likelihood of   */
+/* the measured ranges). The paper names no variant; the reading is the       */
+/* bootstrap filter:                                                          */
+/*   seed   (no belief yet, first row (a, r)): particle k on the ring about a */
+/*          of radius r + sigma_l z_k at angle 2 pi (k + u_k) / n (one        */
+/*          particle per equal sector of the circle);                         */
+/*   move   (belief held): x_k <- x_k + q (z_k, z'_k), a random walk;         */
+/*   weight (rows not used to seed): w_k = prod_rows                          */
+/*          exp(-(|x_k - a| - r)^2 / (2 sigma_l^2)), taken relative to the    */
+/*          largest (the normalisation cancels in the resampling);            */
+/*   resample (systematic, Kitagawa 1996): with C_m = w_0 + ... + w_m and one */
+/*          offset U in [0, 1), output k copies particle                      */
+/*          min{ m : C_m > (k + U) C_{n-1} / n } (the last one if none);      */
+/*   estimate: the mean of the particles.                                     */
+/* z_k, z'_k: Box-Muller of words 0 and 1 of particle k, u_k = u01(word 2),   */
+/* U = u01(word 3 of particle 0).                                             */
+/* ------------------------------------------------------------------------ */
+#define ORC_PF_MAX 1024
+
+int orc_pf_update(int n, double *px, double *py, int init, int m, const double *ax,
+                  const double *ay, const double *r, double sigma_l, double q,
+                  const uint32_t *words, double *ex, double *ey, int32_t *src) {
+  const double two_pi = 6.283185307179586476925286766559;
+  if (n < 1 || n > ORC_PF_MAX) return 0;
+  if (!init && m < 1) return 0;
+  int first = 0; /* rows before this one seeded the belief */
+  if (!init) {
+    for (int k = 0; k < n; ++k) {
+      double z0, z1;
+      orc_normal2(words[4 * k], words[4 * k + 1], &z0, &z1);
+      const double ang = two_pi * ((double)k + orc_u01(words[4 * k + 2])) / (double)n;
+      const double rad = r[0] + sigma_l * z0;
+      px[k] = ax[0] + rad * cos(ang);
+      py[k] = ay[0] + rad * sin(ang);
+    }
+    first = 1;
+  } else {
+    for (int k = 0; k < n; ++k) {
+      double z0, z1;
+      orc_normal2(words[4 * k], words[4 * k + 1], &z0, &z1);
+      px[k] += q * z0;
+      py[k] += q * z1;
+    }
+  }
+  if (src)
+    for (int k = 0; k < n; ++k) src[k] = -1;
+  if (m > first) {
+    double lw[ORC_PF_MAX], cum[ORC_PF_MAX], ox[ORC_PF_MAX], oy[ORC_PF_MAX];
+    double best = -INFINITY;
+    for (int k = 0; k < n; ++k) {
+      lw[k] = 0.0;
+      for (int row = first; row < m; ++row) {
+        const double res = hypot(px[k] - ax[row], py[k] - ay[row]) - r[row];
+        lw[k] -= res * res / (2.0 * sigma_l * sigma_l);
+      }
+      if (lw[k] > best) best = lw[k];
+    }
+    double total = 0.0;
+    for (int k = 0; k < n; ++k) {
+      total += exp(lw[k] - best);
+      cum[k] = total;
+    }
+    const double U = orc_u01(words[3]);
+    for (int k = 0; k < n; ++k) {
+      const double point = ((double)k + U) / (double)n * total;
+      int j = 0;
+      while (j < n - 1 && !(cum[j] > point)) ++j;
+      ox[k] = px[j];
+      oy[k] = py[j];
+      if (src) src[k] = j;
+    }
+    for (int k = 0; k < n; ++k) {
+      px[k] = ox[k];
+      py[k] = oy[k];
+    }
+  }
+  double sx = 0.0, sy = 0.0;
+  for (int k = 0; k < n; ++k) {
+    sx += px[k];
+    sy += py[k];
+  }
+  *ex = sx / (double)n;
+  *ey = sy / (double)n;
+  return 1;
+}
+
 /* Eq. (2): 1 when the nearest agent is within d_follow (inclusive). */
 double orc_follow_reward(double d, double d_follow) { return d <= d_follow ? 1.0 : 0.0; }
 
@@ -268,6 +362,9 @@ typedef struct {
   /* rec[i][k][e]: agent i received agent k's broadcast (its position and
    * ranges) of window entry e; rec[i][i][e] = 1 */
   unsigned char rec[OMAX][OMAX][OWMAX];
+  /* particle filter (est_kind 1): particles of tracker (i, j), belief flag */
+  double ppx[OMAX][OMAX][ORC_PF_N], ppy[OMAX][OMAX][ORC_PF_N];
+  int pinit[OMAX][OMAX];
 } oenv;
 
 /* Pairwise spawn (Sec. IV-A-2: every entity at least spawn_min and at most
@@ -372,6 +469,7 @@ static void env_reset(const orc_params *p, uint64_t seed, uint64_t episode, oenv
     E->comm_ok[i] = 1;
     for (int j = 0; j < OMAX; ++j) {
       E->ev[i][j] = 0;
+      E->pinit[i][j] = 0;
       E->ex[i][j] = E->ey[i][j] = 0.0;
       E->es[i][j] = NAN;
     }
@@ -510,8 +608,52 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
       }
     }
   }
-  /* per-(agent,target) tracker over the valid window entries; hold on failure */
-  for (int i = 0; i < E->nA; ++i) {
+  /* est_kind 1: per-(agent,target) particle filter over this step's rows:
+   * the agent's own range, then (pooled) the ranges received from the other
+   * agents in index order; no belief and no row: no estimate (held) */
+  if (p->est_kind == 1) {
+    const uint32_t c3pf = (uint32_t)((episode << 4) | PURPOSE_PF);
+    const double sl = sqrt(E->sigma_r * E->sigma_r + p->pf_lik_sigma * p->pf_lik_sigma);
+    for (int i = 0; i < E->nA; ++i) {
+      for (int j = 0; j < E->nT; ++j) {
+        double wx[OMAX], wy[OMAX], wr[OMAX];
+        int n = 0;
+        for (int k2 = 0; k2 < E->nA; ++k2) {
+          const int a = (k2 == 0) ? i : (k2 <= i ? k2 - 1 : k2);
+          if (a != i && !p->pooled) break;
+          if (isnan(E->hr[a][j][0]) || !E->rec[i][a][0]) continue;
+          wx[n] = E->hx[a][0];
+          wy[n] = E->hy[a][0];
+          wr[n] = E->hr[a][j][0];
+          ++n;
+        }
+        uint32_t words[4 * ORC_PF_N];
+        for (int k = 0; k < ORC_PF_N; ++k)
+          draw(seed, t, E->env_id, (uint32_t)((8 * i + j) * ORC_PF_N + k), c3pf, words + 4 * k);
+        double px, py;
+        const int ok = orc_pf_update(ORC_PF_N, E->ppx[i][j], E->ppy[i][j], E->pinit[i][j], n, wx,
+                                     wy, wr, sl, p->pf_q, words, &px, &py, NULL);
+        if (ok) {
+          E->pinit[i][j] = 1;
+          E->ex[i][j] = px;
+          E->ey[i][j] = py;
+          E->ev[i][j] = 1;
+        }
+        const int pidx = i * E->nT + j;
+        if (o->ranges) o->ranges[pidx] = E->hr[i][j][0];
+        if (o->est) {
+          o->est[2 * pidx] = E->ev[i][j] ? E->ex[i][j] : 0.0;
+          o->est[2 * pidx + 1] = E->ev[i][j] ? E->ey[i][j] : 0.0;
+        }
+        if (o->est_valid) o->est_valid[pidx] = (uint8_t)E->ev[i][j];
+        if (o->est_fresh) o->est_fresh[pidx] = (uint8_t)ok;
+        if (o->sens) o->sens[pidx] = NAN;
+      }
+    }
+  }
+  /* est_kind 0: per-(agent,target) least squares over the valid window
+   * entries; hold on failure */
+  for (int i = 0; i < E->nA && p->est_kind == 0; ++i) {
     for (int j = 0; j < E->nT; ++j) {
       double wx[OROWS], wy[OROWS], wr[OROWS];
       int n = 0;
@@ -611,6 +753,8 @@ int orc_rollout(const orc_params *p, uint64_t seed, uint64_t episode, int64_t n_
     return -1;
   if (p->spawn_mode == 1 && p->n_agents + p->n_targets > 13) return -1;
   if (p->pooled != 0 && p->pooled != 1) return -1;
+  if (p->est_kind != 0 && p->est_kind != 1) return -1;
+  if (p->est_kind == 1 && !(p->pf_q >= 0.0 && p->pf_lik_sigma >= 0.0)) return -1;
   for (int64_t k = 0; k < n_sel; ++k)
     if (n_agents[k] < 1 || n_agents[k] > OMAX || n_targets[k] < 1 || n_targets[k] > OMAX)
       return -1;

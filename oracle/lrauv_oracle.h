@@ -81,7 +81,19 @@ typedef struct orc_params {
                               agents (Sec. IV-A-2: every tracker is updated with
                               all the information received); 0: own ranges only */
   int32_t pad2_;
+  /* Tracker model (Sec. II and Sec. IV-A-2: each agent keeps a least-squares
+   * or a particle-filter model of each target). */
+  int32_t est_kind;        /* 0: least squares over the window (Sec. III-A);
+                              1: particle filter of ORC_PF_N particles, updated
+                              with this step's ranges (see orc_pf_update) */
+  int32_t pad3_;
+  double pf_q;             /* std of each particle's random-walk move per step (m) */
+  double pf_lik_sigma;     /* added in quadrature to the env's range-noise std to
+                              give the likelihood's std (m) */
 } orc_params;
+
+/* Particles per tracker of the particle filter. */
+#define ORC_PF_N 64
 
 /* Per-step records of an oracle rollout. Every pointer may be NULL. Entity
  * arrays follow the selected envs in the order given, agents / targets /
@@ -156,6 +168,25 @@ double orc_follow_reward(double d, double d_follow);
  * more than 13 entities. Pinned: pairwise bounds by brute force. */
 int orc_spawn_pairwise(const orc_params *p, uint64_t seed, uint64_t episode, uint32_t env_id,
                        int n_agents, int n_targets, double *x, double *y);
+
+/* ---- one update of one tracker's particle filter (Sec. II: particles
+ * moved by a motion model and resampled by the measurement likelihood; the
+ * reading, a bootstrap filter with a random-walk move, a Gaussian range
+ * likelihood and systematic resampling, is spelled out at the definition).
+ * n <= 1024 particles (px, py), updated in place; init: 1 when they hold a
+ * belief; m measurement rows (ax, ay, r), the first of which seeds the belief
+ * when init is 0; sigma_l: likelihood std; q: move std; words [n][4]: the
+ * four random words particle k draws for this step (word 3 of particle 0 is
+ * the resampling offset). Returns 1 with the estimate (the particles' mean)
+ * in (ex, ey) when the tracker holds a belief afterwards, 0 when it has none
+ * (init 0 and no row; nothing written). src [n] (may be NULL): the index each
+ * particle was copied from by the resampling, -1 when there was none. Pinned:
+ * two-particle closed form of the resampling decision, offspring counts of
+ * systematic resampling, ring seeding geometry, translation equivariance,
+ * convergence on a static target. */
+int orc_pf_update(int n, double *px, double *py, int init, int m, const double *ax,
+                  const double *ay, const double *r, double sigma_l, double q,
+                  const uint32_t *words, double *ex, double *ey, int32_t *src);
 
 /* ---- full episode(s): reset then T steps for the selected envs.
  * env_ids: global env ids (they key the RNG); counts per selected env.

@@ -30,7 +30,11 @@ class OrcParams(C.Structure):
         ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
         ("spawn_mode", C.c_int32), ("d_follow", C.c_double), ("spawn_min", C.c_double),
         ("spawn_max", C.c_double), ("pooled", C.c_int32), ("pad2_", C.c_int32),
+        ("est_kind", C.c_int32), ("pad3_", C.c_int32), ("pf_q", C.c_double),
+        ("pf_lik_sigma", C.c_double),
     ]
+
+PF_N = 64  # particles per tracker (ORC_PF_N)
 
 
 _TRAJ_FIELDS = [
@@ -85,6 +89,11 @@ def lib():
                                   P(C.c_int32), P(C.c_int32), C.c_int32, P(C.c_int32),
                                   P(OrcTraj), C.c_int]
         L.orc_rollout.restype = C.c_int
+        L.orc_pf_update.argtypes = [C.c_int, P(C.c_double), P(C.c_double), C.c_int, C.c_int,
+                                    P(C.c_double), P(C.c_double), P(C.c_double), C.c_double,
+                                    C.c_double, P(C.c_uint32), P(C.c_double), P(C.c_double),
+                                    P(C.c_int32)]
+        L.orc_pf_update.restype = C.c_int
         _register_learned(L)
         _lib = L
     return _lib
@@ -118,7 +127,7 @@ def _p(a, ctype):
 def make_params(cfg: dict) -> OrcParams:
     p = OrcParams()
     for name, _ in OrcParams._fields_:
-        if name in ("pad_", "pad2_"):
+        if name in ("pad_", "pad2_", "pad3_"):
             continue
         if name == "action_dpsi":
             vals = list(cfg["action_dpsi"]) + [0.0] * (8 - len(cfg["action_dpsi"]))
@@ -214,6 +223,42 @@ def spawn_pairwise(cfg: dict, seed: int, episode: int, env_id: int, n_agents: in
     k = lib().orc_spawn_pairwise(C.byref(p), seed, episode, env_id, n_agents, n_targets,
                                  _p(x, C.c_double), _p(y, C.c_double))
     return x, y, int(k)
+
+
+# ---------------------------------------------------------------- particle filter
+PURPOSE_PF = 7
+
+
+def pf_words(seed: int, episode: int, t: int, env_id: int, agent: int, target: int,
+             n: int = PF_N) -> np.ndarray:
+    """The random words [n][4] tracker (agent, target) of env `env_id` draws at
+    step t: Philox(t, env id, (8 agent + target) n + k, 7 | episode << 4)."""
+    ctr = np.zeros((n, 4), np.uint32)
+    ctr[:, 0] = t
+    ctr[:, 1] = env_id
+    ctr[:, 2] = (8 * agent + target) * n + np.arange(n)
+    ctr[:, 3] = (episode << 4) | PURPOSE_PF
+    return philox(ctr, seed)
+
+
+def pf_update(px, py, init: bool, rows, sigma_l: float, q: float, words):
+    """One particle-filter update (orc_pf_update). rows [m][3] = (ax, ay, r).
+    Returns (ok, px, py, (ex, ey), src) with new particle arrays."""
+    px = np.array(px, np.float64)
+    py = np.array(py, np.float64)
+    n = px.shape[0]
+    rows = np.ascontiguousarray(np.asarray(rows, np.float64).reshape(-1, 3))
+    ax = np.ascontiguousarray(rows[:, 0])
+    ay = np.ascontiguousarray(rows[:, 1])
+    r = np.ascontiguousarray(rows[:, 2])
+    w = np.ascontiguousarray(words, np.uint32).reshape(n, 4)
+    src = np.empty(n, np.int32)
+    ex, ey = C.c_double(), C.c_double()
+    ok = lib().orc_pf_update(n, _p(px, C.c_double), _p(py, C.c_double), int(bool(init)),
+                             rows.shape[0], _p(ax, C.c_double), _p(ay, C.c_double),
+                             _p(r, C.c_double), sigma_l, q, _p(w, C.c_uint32), C.byref(ex),
+                             C.byref(ey), _p(src, C.c_int32))
+    return bool(ok), px, py, (ex.value, ey.value), src
 
 
 # ---------------------------------------------------------------- rollout

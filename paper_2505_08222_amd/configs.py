@@ -25,7 +25,7 @@ BASE = dict(
     det_range=math.inf, comm_range=1500.0, comm_loss_p=0.0, eps_min=10.0, eps_max=50.0,
     d_safe=10.0, guard_tau=1e-4, lost_range=450.0,
     action_mode=0, n_rudder=5, reward_mode=0, spawn_mode=0, d_follow=50.0, spawn_min=50.0,
-    spawn_max=200.0, pooled=0,
+    spawn_max=200.0, pooled=0, est_kind=0, pf_q=1.0, pf_lik_sigma=2.0,
 )
 
 
