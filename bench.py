@@ -8,7 +8,9 @@ metrics reduction} over the whole batch, inputs resident in HBM. Default
 1..5 per env, 1000 steps) is the headline; the plain batched workload (4096
 envs x 2x2 x 500 steps, with an env-count sweep), the learned estimator and
 the closed loop with the attention policy follow as sections of the same JSON
-line. `--workload NAME` runs one of them alone.
+line, then the paper's own environment (LS trackers, pooled LS, learned
+estimator on its windows) and the particle-filter tracker on the ragged batch
+and on the paper's environment. `--workload NAME` runs one of them alone.
 """
 import argparse
 import json
@@ -43,8 +45,14 @@ def log(msg):
 KERNEL_SOURCES = {
     "rollout_kernel": ["env_kernels.hip", "env_internal.h", "ls_device.h", "rng.h"],
     "policy_kernel": ["policy_kernels.hip", "policy_internal.h", "mfma_tile.h", "rng.h"],
+    "pf_kernel": ["pf_kernels.hip", "env_internal.h", "rng.h"],
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_counters.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "pf_kernel_valu_counters.md")
+# VALU issue capacity of the chip: 256 CUs x 4 SIMDs, each SIMD's vector unit
+# busy for one cycle per cycle at 2.4 GHz (a full-rate wave64 instruction
+# occupies it 4 cycles, a quarter-rate one 16)
+VALU_PEAK_CYCLES = 256 * 4 * 2.4e9
 
 
 def kernel_version(kernel):
@@ -72,6 +80,81 @@ def measured_traffic(kernel, workload):
             if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == ver:
                 return int(m.group(4)) + int(m.group(5))
     return None
+
+
+def measured_valu(kernel, workload):
+    """VALU-busy SIMD cycles per launch (4 x SQ_ACTIVE_INST_VALU, summed over
+    the chip) and VALU instructions per launch from the committed counter
+    summary, or None when there is none or the kernel changed since."""
+    import re
+    if not os.path.exists(VALU_FILE):
+        return None
+    ver = kernel_version(kernel)
+    pat = re.compile(r"^valu\s+(\S+)\s+(\S+)\s+(\S+)\s+(\d+)\s+(\d+)\s*$")
+    with open(VALU_FILE) as f:
+        for line in f:
+            m = pat.match(line.strip())
+            if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == ver:
+                return int(m.group(4)), int(m.group(5))
+    return None
+
+
+def pf_bytes_per_launch(env, cfg):
+    """Algorithmic HBM bytes of one particle-filter launch: each tracker's 64
+    particles read and written (1024 B), its rows read (16 B each: its own, or
+    with pooling one per agent of its env), its descriptor (16 B), belief and
+    estimate written (10 B) and belief read (1 B)."""
+    import numpy as np
+    na = env.n_agents.astype(np.int64)
+    nt = env.n_targets.astype(np.int64)
+    rows = na if cfg["pooled"] else np.ones_like(na)
+    return float((na * nt * (1024 + 16 * rows + 27)).sum())
+
+
+def pf_kernel_roofline(env, cfg, workload, full_size):
+    """The particle-filter kernel timed alone: mid-episode (after 20 steps),
+    event-timed repeats of the filter update on the stream it is launched on.
+    Its bound is VALU issue (Philox rounds, Box-Muller, the cross-lane scans):
+    the roofline reports the VALU-busy fraction from the committed counters
+    over the live duration, with the HBM view beside it."""
+    import numpy as np
+    import torch
+
+    stream = torch.cuda.current_stream()
+    env.reset(0)
+    env.rollout(20, record=())
+    reps = 10
+    durs = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            env.pf_update()
+        b.record(stream)
+        torch.cuda.synchronize()
+        durs.append(a.elapsed_time(b) / reps)
+    kern_ms = float(np.median(durs))
+    alg = pf_bytes_per_launch(env, cfg)
+    gbs = alg / (kern_ms / 1e3) / 1e9
+    hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": alg}
+    log(f"[bench] pf kernel {kern_ms*1e3:.1f} us/launch, {alg/1e6:.1f} MB algorithmic, "
+        f"{gbs:.0f} GB/s")
+    valu = measured_valu("pf_kernel", workload) if full_size else None
+    roof = {"kernel": "pf_kernel", "kernel_ms": kern_ms, "trackers": int(env.P),
+            "particles_per_tracker": 64,
+            "particle_updates_per_s": env.P * 64 / (kern_ms / 1e3)}
+    if valu is not None:
+        busy, insts = valu
+        ach = busy / (kern_ms / 1e3)
+        roof.update({"bound": "alu", "achieved": ach, "peak": VALU_PEAK_CYCLES,
+                     "unit": "VALU-busy SIMD cycles/s", "frac": ach / VALU_PEAK_CYCLES,
+                     "valu_busy_cycles_per_launch": busy, "valu_insts_per_launch": insts,
+                     "traffic": None, "hbm_view": hbm})
+    else:
+        roof.update(hbm)
+        roof["traffic"] = None
+    return roof
 
 
 def copy_probe():
@@ -121,7 +204,8 @@ def cpu_baseline(cfg, env, T, budget_s):
     threads = oracle_threads()
     orc.lib()
     ids, na, nt = env.order["env_ids"], env.n_agents, env.n_targets
-    chunk = 64 * threads
+    # the filter does 64 particle updates per tracker: fewer envs per call
+    chunk = (2 if cfg.get("est_kind", 0) == 1 else 64) * threads
     done_envsteps = 0
     calls = 0
     t0 = time.perf_counter()
@@ -647,8 +731,9 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
     value = env_steps / elapsed
     m = gmetrics.cpu().numpy()
 
-    # dominant kernel: the persistent rollout, timed alone with events on the
-    # stream it is launched on
+    pf = cfg.get("est_kind", 0) == 1
+    # dominant kernel: the persistent rollout (the particle filter when it is
+    # the tracker), timed alone with events on the stream it is launched on
     out = {k: torch.empty_like(v) for k, v in gout.items()}
     durs = []
     for _ in range(3):
@@ -663,7 +748,7 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
     bpe = bytes_per_env_step(env.n_agents.astype(np.int64), env.n_targets.astype(np.int64)).sum()
     alg_bytes = float(bpe) * T
     achieved = alg_bytes / (kern_ms / 1e3) / 1e9
-    log(f"[bench] rollout kernel {kern_ms:.3f} ms/launch, {alg_bytes/1e6:.1f} MB algorithmic, "
+    log(f"[bench] rollout {kern_ms:.3f} ms/launch, {alg_bytes/1e6:.1f} MB algorithmic, "
         f"{achieved:.1f} GB/s")
 
     result = {
@@ -683,18 +768,22 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
             "workload": f"{workload}: {E} envs x {T} steps, "
                         + ("agents and targets uniform 1..5 per env"
                            if cfg["ragged"] else f"{cfg['n_agents']} agents x {cfg['n_targets']} targets")
-                        + f", window {cfg['window']}, one HIP graph (reset + rollout + metrics)",
+                        + (f", particle filter (64 particles per tracker"
+                           + (", pooled ranges" if cfg["pooled"] else "") + ")" if pf else
+                           f", window {cfg['window']}")
+                        + ", one HIP graph (reset + rollout + metrics)",
             "envs": E, "episode_steps": T, "agents": int(env.A), "targets": int(env.Tt),
             "tokens": int(env.K), "lanes_per_agent": mapping[0], "waves_per_block": mapping[1],
         },
         "agent_steps_per_s": float(env.A) * T * steps / elapsed,
         "hbm_gbps_algorithmic": achieved,
+        "rollout_ms_per_launch": kern_ms,
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic("rollout_kernel", workload) if E == c["num_envs"] else None,
             "kernel": "rollout_kernel", "kernel_ms": kern_ms, "bytes_per_launch": alg_bytes,
-        },
+        } if not pf else pf_kernel_roofline(env, cfg, workload, E == c["num_envs"]),
         "episode_metrics": {
             "mean_reward": float(m[0] / max(m[6], 1)),
             "mean_tracking_error_m": float(m[1] / max(m[3], 1)),
@@ -721,7 +810,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "plain", "batched", "ragged", "learned", "policy", "paper",
-                             "paper_pooled", "learned_paper"])
+                             "paper_pooled", "learned_paper", "ragged_pf", "paper_pf"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -775,7 +864,14 @@ def main():
     result["paper_pooled"] = bench_env(args, "paper_pooled", args.steps, args.warmup,
                                        cpu_seconds=sec_cpu)
     result["learned_paper"] = bench_learned(args, args.steps, variant="paper")
-    for k in ("batched", "learned", "policy", "paper", "paper_pooled", "learned_paper"):
+    # the particle-filter tracker on the ragged batch and on the paper's
+    # environment (pooled ranges); fewer replays: each step is three launches
+    result["ragged_pf"] = bench_env(args, "ragged_pf", min(args.steps, 3), min(args.warmup, 1),
+                                    cpu_seconds=sec_cpu)
+    result["paper_pf"] = bench_env(args, "paper_pf", min(args.steps, 5), min(args.warmup, 1),
+                                   cpu_seconds=sec_cpu)
+    for k in ("batched", "learned", "policy", "paper", "paper_pooled", "learned_paper",
+              "ragged_pf", "paper_pf"):
         for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
             result[k].pop(key, None)
     result["bench_seconds"] = time.perf_counter() - t_start

@@ -69,7 +69,8 @@ typedef enum mil_status {
  *  n_agents, n_targets  fixed counts, or the maxima (1..8) when ragged = 1;
  *                       ragged counts are drawn per env, uniform in 1..max.
  *  window               W, number of most recent range measurements each
- *                       (agent,target) tracker keeps (3..16).
+ *                       (agent,target) tracker keeps (3..16); the particle
+ *                       filter (est_kind 1) keeps only the newest.
  *  episode_len          steps per episode; done is set on the last one and
  *                       stepping past it is an error (termination only at the
  *                       step limit, Sec. IV-A-2 "Termination").
@@ -123,7 +124,29 @@ typedef enum mil_status {
  *                       broadcast of that step it received (not dropped,
  *                       within comm_range; Sec. IV-A-2: trackers are updated
  *                       with all the information received); needs gn_iters = 0
- *                       and the exact estimator in the loop. */
+ *                       and the exact estimator in the loop.
+ * Tracker model (Sec. II; Sec. IV-A-2: each agent keeps a least-squares or a
+ * particle-filter model of each target):
+ *  est_kind             0: least squares over the window (Sec. III-A);
+ *                       1: particle filter of MIL_PF_PARTICLES particles per
+ *                       (agent, target) tracker, updated every step with that
+ *                       step's range (pooled: also the ranges received from
+ *                       the other agents, own first, then in agent order).
+ *                       Bootstrap filter: with no belief, the first range
+ *                       seeds particle k on its ring (radius r + sigma_l z,
+ *                       angle 2 pi (k + u) / 64); with a belief, each particle
+ *                       moves by a random walk of std pf_q, the remaining
+ *                       ranges weight it by the Gaussian range likelihood of
+ *                       std sigma_l = sqrt(range_sigma^2 + pf_lik_sigma^2) and
+ *                       systematic resampling draws the new set; the estimate
+ *                       is the particles' mean. A tracker without a belief and
+ *                       without a range keeps no estimate. Random words:
+ *                       Philox(step, env id, (8 agent + target) * 64 + k,
+ *                       7 | episode << 4) for particle k. Not with the learned
+ *                       estimator in the loop.
+ *  pf_q                 random-walk std per step (m), >= 0.
+ *  pf_lik_sigma         added in quadrature to the env's range-noise std in
+ *                       the likelihood (m), >= 0. */
 typedef struct mil_env_params {
   int32_t n_agents, n_targets, ragged, window;
   int32_t episode_len, n_actions, gn_iters, reserved0;
@@ -137,7 +160,12 @@ typedef struct mil_env_params {
   int32_t action_mode, n_rudder, reward_mode, spawn_mode;
   float d_follow, spawn_min, spawn_max;
   int32_t pooled;
+  int32_t est_kind;
+  float pf_q, pf_lik_sigma;
 } mil_env_params;
+
+/* Particles per tracker of the particle filter (one wavefront). */
+#define MIL_PF_PARTICLES 64
 
 /* Sizes of a created environment batch. */
 typedef struct mil_env_layout {
@@ -367,8 +395,22 @@ int mlp_infer_noalloc(const float *d_win, int64_t N, int32_t W, const float *d_p
                       float *d_out, uint8_t *d_flag, void *stream);
 /* Every tracker's current window of a bound environment: d_win [P][W][3]
  * (entry 0 = newest), d_sigma [P] its env's range-noise std, d_truth [P][2]
- * the true target position (either may be NULL). */
+ * the true target position (either may be NULL). MIL_EINVAL with the
+ * particle filter (est_kind 1), which keeps no window. */
 int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream);
+/* The particle filter's state of a bound environment with est_kind = 1:
+ * d_particles [P][MIL_PF_PARTICLES][2] (x, y) and d_belief [P] (1 when the
+ * tracker holds a belief; either may be NULL), as after the last step. The
+ * state is the filter's own (a step after a reset starts from no belief,
+ * whatever the arrays hold). MIL_EINVAL when est_kind is 0. */
+int env_pf_state(mil_env *h, float *d_particles, uint8_t *d_belief, void *stream);
+/* One more particle-filter update of every tracker (est_kind = 1) with the
+ * measurements of the last step taken, exactly as the step itself ran it
+ * (same random words): the particles move and are weighted and resampled
+ * again, and the estimates follow. For callers that time the filter alone or
+ * iterate it on one step's ranges. MIL_ESTATE before the first step after a
+ * reset, MIL_EINVAL when est_kind is 0. */
+int env_pf_update(mil_env *h, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Attention policy: the per-agent transformer actor of Sec. IV-B-1

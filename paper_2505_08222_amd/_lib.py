@@ -40,8 +40,12 @@ class EnvParams(C.Structure):
         ("guard_tau", C.c_float), ("lost_range", C.c_float),
         ("action_mode", C.c_int32), ("n_rudder", C.c_int32), ("reward_mode", C.c_int32),
         ("spawn_mode", C.c_int32), ("d_follow", C.c_float), ("spawn_min", C.c_float),
-        ("spawn_max", C.c_float), ("pooled", C.c_int32),
+        ("spawn_max", C.c_float), ("pooled", C.c_int32), ("est_kind", C.c_int32),
+        ("pf_q", C.c_float), ("pf_lik_sigma", C.c_float),
     ]
+
+
+PF_PARTICLES = 64  # MIL_PF_PARTICLES
 
 
 class EnvLayout(C.Structure):
@@ -131,6 +135,8 @@ def _register_learned(L):
         "mlp_infer": [V, I64, I32, V, V, F, I32, F, V, V, V, I64, V],
         "mlp_infer_noalloc": [V, I64, I32, V, V, F, I32, F, V, V, V],
         "env_windows": [V, V, V, V, V],
+        "env_pf_state": [V, V, V, V],
+        "env_pf_update": [V, V],
     }
     for name, args in table.items():
         f = getattr(L, name)

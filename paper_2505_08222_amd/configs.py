@@ -79,8 +79,20 @@ PAPER = dict(name="paper", num_envs=16384, steps=300, seed=0,
 # the ranges received from the other agents (Sec. IV-A-2).
 PAPER_POOLED = dict(PAPER, name="paper_pooled", env=dict(PAPER["env"], pooled=1))
 
+# The particle-filter tracker (Sec. II; the commented-out Sec. on the
+# vectorised filter motivates it for moving targets) on the ragged batch, and
+# on the paper's environment where every tracker also takes the ranges
+# received from the other agents. The random walk's std is about a target's
+# displacement per step; the likelihood's std adds 2 m (5 m) to the range
+# noise so that 64 particles on a ring of a few hundred metres do not all
+# collapse onto one.
+RAGGED_PF = dict(RAGGED, name="ragged_pf",
+                 env=dict(RAGGED["env"], est_kind=1, pf_q=1.0, pf_lik_sigma=2.0))
+PAPER_PF = dict(PAPER, name="paper_pf",
+                env=dict(PAPER["env"], pooled=1, est_kind=1, pf_q=15.0, pf_lik_sigma=5.0))
+
 CONFIGS = {c["name"]: c for c in (PLAIN, BATCHED, RAGGED, LEARNED, POLICY, PAPER,
-                                  PAPER_POOLED)}
+                                  PAPER_POOLED, RAGGED_PF, PAPER_PF)}
 
 
 def env_config(name: str, **overrides) -> dict:

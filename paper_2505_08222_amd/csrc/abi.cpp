@@ -92,6 +92,7 @@ struct mil_env {
   struct {
     int64_t env_id, cnt_a, cnt_t, aoff, toff, poff, koff, classes, wave_class, queue, mpart;
     int64_t ax, ay, apsi, arud, tx, ty, tpsi, tv, sigma, hx, hy, hr, hrec, ex, ey, ev, macc, miacc;
+    int64_t pmeta, pfxy, pfb, pfm;  // particle filter (est_kind 1)
     int64_t state_begin, state_end, status, snap, devstate, total;
   } off{};
   mil::DevParams dp{};
@@ -134,6 +135,10 @@ bool valid_params(const mil_env_params *p, std::string &why) {
   if (p->pooled != 0 && p->pooled != 1) return bad("pooled must be 0 or 1");
   if (p->pooled == 1 && p->gn_iters != 0)
     return bad("the pooled tracker is the linearised solve: gn_iters must be 0");
+  if (p->est_kind != 0 && p->est_kind != 1) return bad("est_kind must be 0 or 1");
+  if (p->est_kind == 1 && !(p->pf_q >= 0.f && p->pf_q < INFINITY && p->pf_lik_sigma >= 0.f &&
+                            p->pf_lik_sigma < INFINITY))
+    return bad("the particle filter needs finite pf_q >= 0 and pf_lik_sigma >= 0");
   if (p->spawn_mode == 1 &&
       (p->n_agents + p->n_targets > 13 || !(p->spawn_min >= 0.f) ||
        !((double)p->spawn_max >= 2.0 * std::sqrt(3.0) * (double)p->spawn_min)))
@@ -215,6 +220,11 @@ void fill_dev_params(mil_env *h) {
   d.spawn_min = p.spawn_min;
   d.spawn_max = p.spawn_max;
   d.pooled = p.pooled;
+  // the filter takes only the newest entry: the kernels keep a window of one
+  if (p.est_kind == 1) d.window = 1;
+  d.est_kind = p.est_kind;
+  d.pf_q = p.pf_q;
+  d.pf_lik_sigma = p.pf_lik_sigma;
 }
 
 mil::DevOut dev_out(const mil_env_outputs *o) {
@@ -241,12 +251,64 @@ int check_outputs(const mil_env_outputs *o) {
   return MIL_OK;
 }
 
+// Step k's slice of step-major outputs [T][...].
+mil::DevOut step_slice(const mil_env *h, const mil::DevOut &o, int64_t k) {
+  const int64_t E = h->E, A = h->aoff[E], Tt = h->toff[E], P = h->poff[E], K = h->koff[E];
+  auto at = [&](auto *q, int64_t per) { return q ? q + k * per : q; };
+  mil::DevOut s = o;
+  s.obs = at(o.obs, K * 6);
+  s.obs_mask = at(o.obs_mask, K);
+  s.reward = at(o.reward, E);
+  s.done = at(o.done, E);
+  s.est = at(o.est, P * 2);
+  s.est_valid = at(o.est_valid, P);
+  s.gstate = at(o.gstate, (A + Tt) * 6);
+  s.actions = at(o.actions, A);
+  s.ranges = at(o.ranges, P);
+  s.err = at(o.err, Tt);
+  return s;
+}
+
+// T steps from step t0 (outputs and actions step-major from the first). The
+// least-squares trackers run inside the persistent rollout kernel; with the
+// particle filter every step is the kernel's move half (which also hands each
+// tracker's newest range to the filter), the filter, and the observe half.
+int launch_steps(mil_env *h, int32_t t0, int32_t T, uint32_t episode, const int32_t *d_actions,
+                 const mil::DevOut &o, hipStream_t st, int32_t sched) {
+  const mil::DevState *dstate = (const mil::DevState *)(h->ws + h->off.devstate);
+  if (h->P.est_kind == 0)
+    return mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                               dstate, t0, T, episode, d_actions, o, st,
+                               mil::DevExt{0, nullptr, nullptr}, sched);
+  sched = -1;  // one or two steps per launch: the static schedule
+  // move(t0), filter(t0), then per step [observe(t), move(t + 1)] in one
+  // launch and filter(t + 1), and observe(t0 + T - 1) last
+  const int64_t A = h->aoff[h->E];
+  auto act_at = [&](int32_t k) { return d_actions ? d_actions + (int64_t)k * A : nullptr; };
+  mil::DevExt move{1, nullptr, nullptr};
+  move.meas = h->ds.pfm;
+  mil::DevExt both{3, nullptr, nullptr};
+  both.meas = h->ds.pfm;
+  int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                               dstate, t0, 1, episode, act_at(0), step_slice(h, o, 0), st, move,
+                               sched);
+  if (!rc) rc = mil::launch_pf(h->dp, h->ds, t0, episode, st);
+  for (int32_t k = 0; k + 1 < T && !rc; ++k) {
+    rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                             dstate, t0 + k, 2, episode, act_at(k), step_slice(h, o, k), st, both,
+                             sched);
+    if (!rc) rc = mil::launch_pf(h->dp, h->ds, t0 + k + 1, episode, st);
+  }
+  if (!rc)
+    rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
+                             dstate, t0 + T - 1, 1, episode, act_at(T - 1),
+                             step_slice(h, o, T - 1), st, mil::DevExt{2, nullptr, nullptr}, sched);
+  return rc;
+}
+
 int run_rollout(mil_env *h, int32_t T, const int32_t *d_actions, const mil_env_outputs *outs,
                 hipStream_t st, int32_t sched) {
-  const int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp,
-                                     h->ds, (const mil::DevState *)(h->ws + h->off.devstate),
-                                     (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st,
-                                     mil::DevExt{0, nullptr, nullptr}, sched);
+  const int rc = launch_steps(h, (int32_t)h->t, T, h->episode, d_actions, dev_out(outs), st, sched);
   if (rc == -2) return fail(MIL_EINVAL, "no kernel for size class %d / window %d", h->size_class,
                             h->wcap);
   if (rc != 0) return fail(MIL_EHIP, "rollout launch failed: %s",
@@ -343,6 +405,7 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   const int m = std::max(h->max_a, h->max_t);
   h->size_class = m <= 2 ? 2 : (m <= 5 ? 5 : 8);
   h->wcap = (h->W <= 10 && h->size_class < 8) ? 10 : 16;
+  if (params->est_kind == 1) h->wcap = 1;  // the filter keeps only the newest entry
   // wave-table capacity: the largest count over the supported mappings
   for (int G = 1; G <= 2; ++G) {
     int64_t nw = 0;
@@ -377,6 +440,9 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.mpart = take((int64_t)mil::kMetricBlocks * 6 * 8);
   f.status = take(256);
   f.devstate = take(sizeof(mil::DevState));
+  const bool pf = params->est_kind == 1;
+  f.pmeta = take(pf ? P * 16 : 0);
+  f.pfm = take(pf ? P * 16 : 0);
   f.state_begin = o;
   f.ax = take(A * 4);
   f.ay = take(A * 4);
@@ -396,6 +462,8 @@ int env_create(const mil_env_params *params, int64_t num_envs, uint64_t seed,
   f.ev = take(P);
   f.macc = take(E * 3 * 8);
   f.miacc = take(E * 2 * 4);
+  f.pfxy = take(pf ? P * mil::kPfParticles * 8 : 0);
+  f.pfb = take(pf ? P : 0);
   f.state_end = o;
   f.snap = take(f.state_end - f.state_begin);
   f.total = o;
@@ -482,6 +550,28 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.status = (uint32_t *)(h->ws + h->off.status);
   d.queue = (int32_t *)(h->ws + h->off.queue);
   d.mpart = (double *)(h->ws + h->off.mpart);
+  const bool pf = h->P.est_kind == 1;
+  d.pmeta = pf ? (const uint32_t *)(h->ws + h->off.pmeta) : nullptr;
+  d.pfxy = pf ? F(h->off.pfxy) : nullptr;
+  d.pfb = pf ? (uint8_t *)(h->ws + h->off.pfb) : nullptr;
+  d.pfm = pf ? F(h->off.pfm) : nullptr;
+  if (pf) {
+    // each tracker's env, (agent, target) code and counts, global agent index
+    std::vector<uint32_t> meta((size_t)h->poff[E] * 4);
+    for (int64_t k = 0; k < E; ++k)
+      for (int i = 0; i < h->na[k]; ++i)
+        for (int j = 0; j < h->nt[k]; ++j) {
+          const int64_t q = h->poff[k] + (int64_t)i * h->nt[k] + j;
+          meta[4 * q] = (uint32_t)k;
+          meta[4 * q + 1] = (uint32_t)(8 * i + j) | ((uint32_t)h->na[k] << 8) |
+                            ((uint32_t)h->nt[k] << 12);
+          meta[4 * q + 2] = (uint32_t)(h->aoff[k] + i);
+          meta[4 * q + 3] = 0u;
+        }
+    HIP_CHECK(hipMemcpyAsync(h->ws + h->off.pmeta, meta.data(), meta.size() * 4,
+                             hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipStreamSynchronize(st));  // `meta` is a host temporary
+  }
   d.E = E;
   d.A = h->aoff[E];
   d.Tt = h->toff[E];
@@ -556,11 +646,7 @@ int env_graph_capture(mil_env *h, uint64_t episode, int32_t T, const mil_env_out
   }
   HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
   int lrc = mil::launch_reset(h->dp, h->ds, (uint32_t)episode, dev_out(outs), st);
-  if (!lrc)
-    lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                              (const mil::DevState *)(h->ws + h->off.devstate), 0, T,
-                              (uint32_t)episode, nullptr, dev_out(outs), st,
-                              mil::DevExt{0, nullptr, nullptr}, h->sched);
+  if (!lrc) lrc = launch_steps(h, 0, T, (uint32_t)episode, nullptr, dev_out(outs), st, h->sched);
   if (!lrc && d_metrics) lrc = mil::launch_metrics(h->dp, h->ds, T, d_metrics, st);
   hipGraph_t g = nullptr;
   hipError_t ec = hipStreamEndCapture(st, &g);
@@ -718,8 +804,32 @@ int env_autotune(mil_env *h, int32_t probe_steps, const mil_env_outputs *outs,
   return MIL_OK;
 }
 
+int env_pf_state(mil_env *h, float *d_particles, uint8_t *d_belief, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (h->P.est_kind != 1) return fail(MIL_EINVAL, "the environment has no particle filter");
+  if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t P = h->poff[h->E];
+  if (d_particles && P)
+    HIP_CHECK(hipMemcpyAsync(d_particles, h->ds.pfxy, P * mil::kPfParticles * 8,
+                             hipMemcpyDeviceToDevice, st));
+  if (d_belief && P)
+    HIP_CHECK(hipMemcpyAsync(d_belief, h->ds.pfb, P, hipMemcpyDeviceToDevice, st));
+  return MIL_OK;
+}
+
+int env_pf_update(mil_env *h, void *stream) {
+  if (!h) return fail(MIL_EINVAL, "null handle");
+  if (h->P.est_kind != 1) return fail(MIL_EINVAL, "the environment has no particle filter");
+  if (!h->ws || h->t < 1) return fail(MIL_ESTATE, "no step has been taken since the reset");
+  if (mil::launch_pf(h->dp, h->ds, (int32_t)h->t - 1, h->episode, stream))
+    return fail(MIL_EHIP, "particle-filter launch failed: %s", hipGetErrorString(hipGetLastError()));
+  return MIL_OK;
+}
+
 int env_windows(mil_env *h, float *d_win, float *d_sigma, float *d_truth, void *stream) {
   if (!h || !d_win) return fail(MIL_EINVAL, "null argument");
+  if (h->P.est_kind != 0) return fail(MIL_EINVAL, "the particle filter keeps no window");
   if (!h->ws || h->t < 0) return fail(MIL_ESTATE, "env_reset has not been called");
   if (mil::launch_env_windows(h->ds, h->W, h->P.n_agents * h->P.n_targets, d_win, d_sigma, d_truth,
                               stream))
@@ -886,6 +996,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
   if (learned && h->P.pooled)
     return fail(MIL_EINVAL, "the learned estimator in the loop takes one agent's own window: "
                             "pooled must be 0");
+  if (learned && h->P.est_kind != 0)
+    return fail(MIL_EINVAL, "the learned estimator replaces the least-squares tracker: "
+                            "est_kind must be 0");
   if (learned && (h->P.window > 21 || !(k_sigma >= 0.0f)))
     return fail(MIL_EINVAL, "the learned estimator needs window <= 21 and k_sigma >= 0");
   const int64_t A = h->aoff[h->E], K = h->koff[h->E], Pn = h->poff[h->E];
@@ -953,9 +1066,7 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
     o.err = slice(full.err, h->toff[h->E]);
     const mil::DevState *dstate = (const mil::DevState *)(h->ws + h->off.devstate);
     if (!learned) {
-      lrc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                                dstate, t, 1, (uint32_t)episode, wact, o, st,
-                                mil::DevExt{0, nullptr, nullptr}, h->sched);
+      lrc = launch_steps(h, t, 1, (uint32_t)episode, wact, o, st, h->sched);
     } else {
       // move, estimate every tracker from its window, then observe
       float *win = (float *)(ws + ew.win), *sig = (float *)(ws + ew.sig);

@@ -17,6 +17,8 @@ struct DevParams {
   int32_t action_mode, n_rudder, reward_mode, spawn_mode;
   float d_follow, spawn_min, spawn_max;
   int32_t pooled;
+  int32_t est_kind;  // 0 least squares, 1 particle filter
+  float pf_q, pf_lik_sigma;
 };
 
 // One (agents, targets) shape. Environments of a shape are consecutive in
@@ -54,8 +56,18 @@ struct DevState {
   uint32_t *status;                          // [1]
   int32_t *queue;                            // [1 + groups] dynamic-schedule counter, chunk flags
   double *mpart;                             // [kMetricBlocks][6] metrics partial sums
+  // particle filter (est_kind 1; null otherwise)
+  // [P][4] per tracker: packed env index; 8 * agent + target | n_agents << 8 |
+  // n_targets << 12; global agent index; 0
+  const uint32_t *pmeta;
+  float *pfxy;            // [P][kPfParticles][2] particles
+  uint8_t *pfb;           // [P] 1 when the tracker holds a belief
+  float *pfm;             // [P][4] this step's agent x, y and range (move half's output)
   int64_t E, A, Tt, P, K;
 };
+
+// Particles per tracker: one per lane of a wavefront.
+constexpr int kPfParticles = 64;
 
 // Output pointers (mirrors mil_env_outputs) and the per-step strides of the
 // step-major output arrays.
@@ -80,6 +92,11 @@ struct DevOut {
 // range-noise std); phase 2 takes each tracker's estimate from est [P][2] /
 // flag [P] (flag 0 or 1: estimate present, 2: refused, hold the previous one)
 // once its window is full, then computes reward, observation and outputs.
+// With meas set, phase 1 also writes each tracker's newest entry to meas
+// [P][4] (agent x, y, range, 0). Phase 2 with est null: the estimator has
+// written the estimates into the state (ex, ey, ev) itself. Phase 3 (est
+// null, T = 2): the observe half of the launch's first step, then the move
+// half of its second, so that one launch sits between two filter updates.
 // phase 0: whole step.
 struct DevExt {
   int32_t phase;
@@ -87,6 +104,7 @@ struct DevExt {
   const uint8_t *flag;
   float *win = nullptr;
   float *wsig = nullptr;
+  float *meas = nullptr;
 };
 
 // Kernel launchers (env_kernels.hip). All enqueue on `stream`.
@@ -109,6 +127,11 @@ int launch_rollout(int size_class, int wcap, int lanes_per_agent, int waves_per_
 int launch_metrics(const DevParams &p, const DevState &s, int32_t steps, double *d_metrics,
                    void *stream);
 int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *stream);
+
+// pf_kernels.hip: one particle-filter update of every tracker for step t
+// (after the move half of step t wrote s.pfm); writes the particles, the
+// belief flags and, for trackers that hold a belief, ex / ey / ev.
+int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode, void *stream);
 
 // est_kernels.hip
 int launch_est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float tau,

@@ -405,14 +405,15 @@ __global__ void reset_obs_kernel(DevParams p, DevState s, DevOut o) {
 // other paths' pointers and registers.
 // ---------------------------------------------------------------------------
 template <int S, int WC, int G, bool FULL, bool STAGE>
-__global__ void __launch_bounds__(256, (!FULL && WC == 10 && S <= 5) ? 2 : 1)
+__global__ void __launch_bounds__(256, (!FULL && WC == 10 && S <= 5) ? 2 : ((FULL && WC == 1) ? (S == 2 ? 3 : 2) : 1))
 rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, int32_t T,
                uint32_t episode, const int32_t *__restrict__ actions, DevOut o, DevExt ext,
                int32_t chunk) {
   constexpr bool stage = STAGE && !FULL;
-  // split step (full form only): phase 1 moves, phase 2 observes
-  const bool move = !FULL || ext.phase != 2;
-  const bool observe = !FULL || ext.phase != 1;
+  // split step (full form only): phase 1 moves, phase 2 observes; phase 3
+  // observes the launch's first step and moves its second
+  const bool move_all = !FULL || ext.phase != 2;
+  const bool observe_all = !FULL || ext.phase != 1;
   constexpr int MA = S, MT = S;
   constexpr int NPL = (MT + G - 1) / G;  // (agent, target) pairs per lane
   constexpr int NQ = (MT + 3) / 4;       // range-noise draws per agent
@@ -559,6 +560,8 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
 
     for (int step = s_begin; step < s_end; ++step) {
       const uint32_t t = (uint32_t)(t0 + step);
+      const bool move = (FULL && ext.phase == 3) ? step > 0 : move_all;
+      const bool observe = (FULL && ext.phase == 3) ? step == 0 : observe_all;
 
       // ---- agent: action, heading noise, turn then move (Sec. IV-A-3)
       const u32x4 xa = draw(t, env_id, (uint32_t)i, c3dyn, p.key0, p.key1);
@@ -733,6 +736,15 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
           }
         }
       }
+      if (FULL && ext.meas && move && active) {
+        // phase 1 hands each tracker's newest entry to the particle filter
+#pragma unroll
+        for (int sl = 0; sl < NPL; ++sl) {
+          const int j = g + G * sl;
+          if (j < nt)
+            reinterpret_cast<float4 *>(ext.meas)[pbase + j] = make_float4(ax, ay, hr[sl][0], 0.0f);
+        }
+      }
       if (!observe) continue;  // phase 1 ends here: the estimator runs next
       const int filled = min((int)t + 1, W);
 
@@ -743,7 +755,9 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
       // term of the centred form vanishes because sum u_k = 0). Other trackers
       // take the general path below.
       uint32_t pending = 0;
-      if (FULL && p.pooled) {
+      if (FULL && ext.phase >= 2 && !ext.est) {
+        // the particle filter has written this step's estimates into the state
+      } else if (FULL && p.pooled) {
         // ---- pooled tracker: the agent's own entries and those of every
         // agent whose broadcast of that entry it received; each lane's window
         // goes to LDS, then a two-pass centred LS over the received rows (FP64)
@@ -1462,7 +1476,7 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   const bool lean = !actions && !o.est && !o.est_valid && !o.gstate && !o.actions && !o.ranges &&
                     !o.err && std::isinf(p.det_range) && p.det_range > 0.0f &&
                     p.comm_loss_p == 0.0f && p.gn_iters == 0 && ext.phase == 0 &&
-                    p.action_mode == 0 && p.reward_mode == 0 && p.pooled == 0;
+                    p.action_mode == 0 && p.reward_mode == 0 && p.pooled == 0 && p.est_kind == 0;
   // the lean form stages its observation block for a coalesced write once at
   // least two wavefronts per SIMD take turns on the store path (large
   // batches); small batches are latency-bound and write directly
@@ -1491,6 +1505,18 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
   MIL_ROLL(8, 16, 1)
   MIL_ROLL(8, 16, 2)
 #undef MIL_ROLL
+  // the particle filter's halves: full form with a window of one entry
+#define MIL_ROLL_PF(SC, GV)                                                                 \
+  if (size_class == SC && wcap == 1 && G == GV && !lean)                                    \
+    return launch_rollout_t<SC, 1, GV, true, false>(waves_per_block, num_waves, p, hs, s, t0, \
+                                                    T, episode, actions, o, st, ext, sched);
+  MIL_ROLL_PF(2, 1)
+  MIL_ROLL_PF(2, 2)
+  MIL_ROLL_PF(5, 1)
+  MIL_ROLL_PF(5, 2)
+  MIL_ROLL_PF(8, 1)
+  MIL_ROLL_PF(8, 2)
+#undef MIL_ROLL_PF
   return -2;
 }
 

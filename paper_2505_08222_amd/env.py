@@ -148,6 +148,19 @@ class Env:
         check(lib().env_get_state(self._h, ptr(a), ptr(t), _stream()))
         return a, t
 
+    def pf_state(self):
+        """Particle-filter state (est_kind 1): particles [P, 64, 2] and the
+        belief flags [P] as after the last step."""
+        from ._lib import PF_PARTICLES
+        xy = torch.empty((self.P, PF_PARTICLES, 2), dtype=torch.float32, device=self.device)
+        b = torch.empty(self.P, dtype=torch.uint8, device=self.device)
+        check(lib().env_pf_state(self._h, ptr(xy), ptr(b), _stream()))
+        return xy, b
+
+    def pf_update(self):
+        """One more filter update with the last step's ranges (est_kind 1)."""
+        check(lib().env_pf_update(self._h, _stream()))
+
     def set_mapping(self, lanes_per_agent: int, waves_per_block: int = 1):
         check(lib().env_set_mapping(self._h, int(lanes_per_agent), int(waves_per_block)))
 

@@ -138,3 +138,30 @@ def test_noalloc_inference_rejects_oversized_batches(milib):
     assert rc == -1
     assert b"MIL_NOALLOC_MAX_WINDOWS" in L.env_last_error()
     assert L.mlp_infer_noalloc(None, 0, 16, None, None, 3.0, 0, 1e-4, None, None, None) == 0
+
+
+def test_particle_filter_parameters_and_workspace(milib):
+    """est_kind 1 validates its parameters, adds the particles (P x 64 x 8
+    bytes and more) to the workspace, and env_pf_state refuses an
+    environment without a filter before touching any device."""
+    from paper_2505_08222_amd.configs import env_config
+    L = milib.lib()
+    cfg = env_config("ragged")
+    rc, h0 = _create(milib, cfg, 64)
+    assert rc == 0
+    lay0 = milib.EnvLayout()
+    L.env_query_layout(h0, C.byref(lay0))
+    assert L.env_pf_state(h0, None, None, None) == -1
+    L.env_destroy(h0)
+    rc, h1 = _create(milib, dict(cfg, est_kind=1, pf_q=1.0, pf_lik_sigma=2.0), 64)
+    assert rc == 0
+    lay1 = milib.EnvLayout()
+    L.env_query_layout(h1, C.byref(lay1))
+    assert lay1.num_pairs == lay0.num_pairs
+    # particles twice (state and its autotuning snapshot) plus per-tracker words
+    assert lay1.workspace_bytes - lay0.workspace_bytes >= 2 * lay1.num_pairs * 64 * 8
+    L.env_destroy(h1)
+    for key, val in [("est_kind", 2), ("pf_q", -1.0), ("pf_lik_sigma", float("inf"))]:
+        rc, _ = _create(milib, {**cfg, "est_kind": 1, key: val}, 4)
+        assert rc == -1, key
+        assert milib.lib().env_last_error()
