@@ -6,11 +6,17 @@
  * C ABI. Plain pointers and sizes only. Pointers named d_* are DEVICE
  * pointers (HIP global memory on the current device); all others are host.
  * Every call that takes a hipStream_t (passed as void*) only enqueues work on
- * that stream, in stream order, and never synchronises, unless stated.
+ * that stream, in stream order, and never synchronises, unless stated. With
+ * the particle filter (est_kind 1) a step also runs half of the batch on a
+ * second stream of the handle's own, forked from and joined back into the
+ * caller's stream by events within the same call (so stream order, and
+ * graph capture, hold as for one stream).
  *
  * Ownership: the caller allocates every device buffer (its size comes from
  * env_query_layout) and keeps it alive while the handle uses it; the library
- * owns only the host-side handle and any HIP graph it instantiates.
+ * owns only the host-side handle, any HIP graph it instantiates and, with
+ * the particle filter, that second stream and its two events (created by
+ * env_bind, released by env_destroy).
  *
  * Errors: every int-returning call returns 0 (MIL_OK) or a negative
  * mil_status; env_last_error() then describes the last failure of the

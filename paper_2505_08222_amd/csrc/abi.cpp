@@ -102,6 +102,13 @@ struct mil_env {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int32_t graph_T = 0;
+  // particle filter: the batch steps as two halves on two streams, so that
+  // one half's filter (VALU-bound) overlaps the other half's rollout launches
+  // (latency-bound)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int split_wave = 0;      // first wavefront group of the second half; 0: no split
+  int64_t split_pair = 0;  // its first tracker
 };
 
 namespace {
@@ -171,6 +178,22 @@ void build_waves(mil_env *h) {
     wave += (int)nw;
   }
   h->num_waves = wave;
+  // the filter's halves: the first wavefront group whose envs start at or
+  // past half of the trackers
+  h->split_wave = 0;
+  h->split_pair = 0;
+  if (h->P.est_kind == 1) {
+    const int64_t P = h->poff[h->E];
+    for (int w = 1; w < h->num_waves; ++w) {
+      const auto &ci = h->cinfo[h->wave_class[w]];
+      const int64_t e = ci.env0 + (int64_t)(w - ci.wave0) * (64 / (ci.na * h->G));
+      if (2 * h->poff[e] >= P) {
+        h->split_wave = w;
+        h->split_pair = h->poff[e];
+        break;
+      }
+    }
+  }
 }
 
 int upload_mapping(mil_env *h, hipStream_t st) {
@@ -281,28 +304,54 @@ int launch_steps(mil_env *h, int32_t t0, int32_t T, uint32_t episode, const int3
                                dstate, t0, T, episode, d_actions, o, st,
                                mil::DevExt{0, nullptr, nullptr}, sched);
   sched = -1;  // one or two steps per launch: the static schedule
-  // move(t0), filter(t0), then per step [observe(t), move(t + 1)] in one
-  // launch and filter(t + 1), and observe(t0 + T - 1) last
+  // per half: move(t0), filter(t0), then per step [observe(t), move(t + 1)]
+  // in one launch and filter(t + 1), and observe(t0 + T - 1) last
   const int64_t A = h->aoff[h->E];
   auto act_at = [&](int32_t k) { return d_actions ? d_actions + (int64_t)k * A : nullptr; };
-  mil::DevExt move{1, nullptr, nullptr};
-  move.meas = h->ds.pfm;
-  mil::DevExt both{3, nullptr, nullptr};
-  both.meas = h->ds.pfm;
-  int rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                               dstate, t0, 1, episode, act_at(0), step_slice(h, o, 0), st, move,
-                               sched);
-  if (!rc) rc = mil::launch_pf(h->dp, h->ds, t0, episode, st);
-  for (int32_t k = 0; k + 1 < T && !rc; ++k) {
-    rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                             dstate, t0 + k, 2, episode, act_at(k), step_slice(h, o, k), st, both,
-                             sched);
-    if (!rc) rc = mil::launch_pf(h->dp, h->ds, t0 + k + 1, episode, st);
+  const bool split = h->side && h->split_wave > 0;
+  const int halves = split ? 2 : 1;
+  hipStream_t sts[2] = {st, h->side};
+  const int wave_begin[2] = {0, h->split_wave};
+  const int wave_end[2] = {split ? h->split_wave : h->num_waves, h->num_waves};
+  const int64_t pair_begin[2] = {0, h->split_pair};
+  const int64_t pair_end[2] = {split ? h->split_pair : -1, -1};
+  if (split) {
+    if (hipEventRecord(h->ev_fork, st) != hipSuccess ||
+        hipStreamWaitEvent(h->side, h->ev_fork, 0) != hipSuccess)
+      return -1;
   }
-  if (!rc)
-    rc = mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, h->num_waves, h->dp, h->ds,
-                             dstate, t0 + T - 1, 1, episode, act_at(T - 1),
-                             step_slice(h, o, T - 1), st, mil::DevExt{2, nullptr, nullptr}, sched);
+  int rc = 0;
+  for (int g = 0; g < halves && !rc; ++g) {
+    mil::DevExt move{1, nullptr, nullptr};
+    move.meas = h->ds.pfm;
+    move.wave0 = wave_begin[g];
+    mil::DevExt both{3, nullptr, nullptr};
+    both.meas = h->ds.pfm;
+    both.wave0 = wave_begin[g];
+    mil::DevExt observe{2, nullptr, nullptr};
+    observe.wave0 = wave_begin[g];
+    auto roll = [&](int32_t t, int32_t n, int32_t k, const mil::DevExt &ext) {
+      return mil::launch_rollout(h->size_class, h->wcap, h->G, h->wpb, wave_end[g], h->dp, h->ds,
+                                 dstate, t, n, episode, act_at(k), step_slice(h, o, k), sts[g],
+                                 ext, sched);
+    };
+    auto filter = [&](int32_t t) {
+      return mil::launch_pf(h->dp, h->ds, t, episode, sts[g], pair_begin[g], pair_end[g]);
+    };
+    rc = roll(t0, 1, 0, move);
+    if (!rc) rc = filter(t0);
+    for (int32_t k = 0; k + 1 < T && !rc; ++k) {
+      rc = roll(t0 + k, 2, k, both);
+      if (!rc) rc = filter(t0 + k + 1);
+    }
+    if (!rc) rc = roll(t0 + T - 1, 1, T - 1, observe);
+  }
+  if (split) {
+    // join even after a failed launch, so that a capture can end cleanly
+    if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
+        hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
+      return -1;
+  }
   return rc;
 }
 
@@ -551,6 +600,11 @@ int env_bind(mil_env *h, void *d_workspace, int64_t bytes, void *stream) {
   d.queue = (int32_t *)(h->ws + h->off.queue);
   d.mpart = (double *)(h->ws + h->off.mpart);
   const bool pf = h->P.est_kind == 1;
+  if (pf && !h->side) {
+    HIP_CHECK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIP_CHECK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+  }
   d.pmeta = pf ? (const uint32_t *)(h->ws + h->off.pmeta) : nullptr;
   d.pfxy = pf ? F(h->off.pfxy) : nullptr;
   d.pfb = pf ? (uint8_t *)(h->ws + h->off.pfb) : nullptr;
@@ -1113,6 +1167,12 @@ int env_destroy(mil_env *h) {
   if (!h) return MIL_OK;
   if (h->gexec) hipGraphExecDestroy(h->gexec);
   if (h->graph) hipGraphDestroy(h->graph);
+  if (h->side) {
+    hipStreamSynchronize(h->side);
+    hipStreamDestroy(h->side);
+  }
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
   delete h;
   return MIL_OK;
 }

@@ -105,6 +105,9 @@ struct DevExt {
   float *win = nullptr;
   float *wsig = nullptr;
   float *meas = nullptr;
+  // static schedule only: the launch covers wavefront groups wave0 ..
+  // num_waves - 1 (a slice of the batch; the groups' envs are contiguous)
+  int32_t wave0 = 0;
 };
 
 // Kernel launchers (env_kernels.hip). All enqueue on `stream`.
@@ -131,7 +134,9 @@ int launch_get_state(const DevState &s, float *d_agent, float *d_target, void *s
 // pf_kernels.hip: one particle-filter update of every tracker for step t
 // (after the move half of step t wrote s.pfm); writes the particles, the
 // belief flags and, for trackers that hold a belief, ex / ey / ev.
-int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode, void *stream);
+// Trackers p_begin .. p_end - 1 (p_end < 0: to the last).
+int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode, void *stream,
+              int64_t p_begin = 0, int64_t p_end = -1);
 
 // est_kernels.hip
 int launch_est_exact(const float *d_win, int64_t N, int32_t W, int32_t gn_iters, float tau,

@@ -433,7 +433,7 @@ rollout_kernel(DevParams p, const DevState *sp, int32_t num_waves, int32_t t0, i
   const int span = dyn ? chunk : T;
   const int units = dyn ? num_waves * ((T + span - 1) / span) : num_waves;
   int unit = dyn ? take_unit(sp->queue, lane)
-                 : __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
+                 : ext.wave0 + __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + wib);
   while (unit < units) {
     const int cix = unit / num_waves;
     const int wave = unit - cix * num_waves;
@@ -1422,14 +1422,15 @@ static int launch_rollout_t(int waves_per_block, int num_waves, const DevParams 
   // per wavefront: target slab, then (lean form) token offsets and masks, or
   // (full form, pooled tracker) every lane's window; the pooled form runs
   // one wavefront per block to keep the block's LDS small
-  if (FULL && p.pooled) waves_per_block = 1;
+  const bool pooled_ls = FULL && p.pooled && p.est_kind == 0;
+  if (pooled_ls) waves_per_block = 1;
   constexpr int NPLT = (S + G - 1) / G;
   const size_t lds = (size_t)waves_per_block *
                      (64 * S * sizeof(float4) + (STAGE ? kStageTok<S> * (sizeof(float2) + 1) : 0) +
-                      ((FULL && p.pooled) ? 64 * WC * (2 + NPLT) * sizeof(float) : 0));
-  int blocks = (num_waves + waves_per_block - 1) / waves_per_block;
+                      (pooled_ls ? 64 * WC * (2 + NPLT) * sizeof(float) : 0));
+  int blocks = (num_waves - ext.wave0 + waves_per_block - 1) / waves_per_block;
   int32_t chunk = 0;
-  if ((sched >= 0 || sched == kSchedProbe) && hs.queue) {
+  if ((sched >= 0 || sched == kSchedProbe) && hs.queue && ext.wave0 == 0) {
     const int resident = resident_waves<S, WC, G, FULL, STAGE>(waves_per_block, lds);
     if (sched > 0) {
       chunk = sched < T ? sched : T;
@@ -1465,7 +1466,7 @@ int launch_rollout(int size_class, int wcap, int G, int waves_per_block, int num
                    int32_t T, uint32_t episode, const int32_t *actions, const DevOut &o_in,
                    void *stream, const DevExt &ext, int32_t sched) {
   hipStream_t st = (hipStream_t)stream;
-  if (num_waves <= 0 || T <= 0) return 0;
+  if (num_waves - ext.wave0 <= 0 || T <= 0) return 0;
   DevOut o = o_in;
   o.E = hs.E;
   o.A = hs.A;

@@ -93,7 +93,7 @@ struct PfArgs {
   const float4 *pfm;
   float *ex, *ey;
   uint8_t *ev;
-  int64_t P;
+  int64_t p0, P;  // trackers p0 .. P - 1
   uint32_t t, c3, key0, key1;
   float q, lik2;
 };
@@ -109,7 +109,7 @@ __device__ __forceinline__ uint32_t uniform_byte(const uint8_t *base, int64_t id
 template <bool POOLED>
 __global__ void __launch_bounds__(64 * kPfWaves) pf_kernel(PfArgs a) {
   const int lane = threadIdx.x & 63;
-  const int64_t w = (int64_t)blockIdx.x * kPfWaves +
+  const int64_t w = a.p0 + (int64_t)blockIdx.x * kPfWaves +
                     __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (w >= a.P) return;  // uniform over the wavefront
   // the particles first: their load overlaps everything up to the move
@@ -221,8 +221,11 @@ __global__ void __launch_bounds__(64 * kPfWaves) pf_kernel(PfArgs a) {
 
 }  // namespace
 
-int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode, void *stream) {
-  if (s.P <= 0) return 0;
+int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode, void *stream,
+              int64_t p_begin, int64_t p_end) {
+  if (p_end < 0 || p_end > s.P) p_end = s.P;
+  if (p_begin < 0) p_begin = 0;
+  if (p_end <= p_begin) return 0;
   if (!s.pmeta || !s.pfxy || !s.pfb || !s.pfm) return -1;
   PfArgs a{};
   a.env_id = s.env_id;
@@ -235,14 +238,15 @@ int launch_pf(const DevParams &p, const DevState &s, int32_t t, uint32_t episode
   a.ex = s.ex;
   a.ey = s.ey;
   a.ev = s.ev;
-  a.P = s.P;
+  a.p0 = p_begin;
+  a.P = p_end;
   a.t = (uint32_t)t;
   a.c3 = (episode << 4) | kPurposePf;
   a.key0 = p.key0;
   a.key1 = p.key1;
   a.q = p.pf_q;
   a.lik2 = p.pf_lik_sigma * p.pf_lik_sigma;
-  const int64_t blocks = (s.P + kPfWaves - 1) / kPfWaves;
+  const int64_t blocks = (p_end - p_begin + kPfWaves - 1) / kPfWaves;
   hipStream_t st = (hipStream_t)stream;
   if (p.pooled)
     hipLaunchKernelGGL(pf_kernel<true>, dim3((unsigned)blocks), dim3(64 * kPfWaves), 0, st, a);
