@@ -141,6 +141,8 @@ def pf_kernel_roofline(env, cfg, workload, full_size):
     log(f"[bench] pf kernel {kern_ms*1e3:.1f} us/launch, {alg/1e6:.1f} MB algorithmic, "
         f"{gbs:.0f} GB/s")
     valu = measured_valu("pf_kernel", workload) if full_size else None
+    traffic = measured_traffic("pf_kernel", workload) if full_size else None
+    hbm["traffic"] = traffic
     roof = {"kernel": "pf_kernel", "kernel_ms": kern_ms, "trackers": int(env.P),
             "particles_per_tracker": 64,
             "particle_updates_per_s": env.P * 64 / (kern_ms / 1e3)}
@@ -150,10 +152,11 @@ def pf_kernel_roofline(env, cfg, workload, full_size):
         roof.update({"bound": "alu", "achieved": ach, "peak": VALU_PEAK_CYCLES,
                      "unit": "VALU-busy SIMD cycles/s", "frac": ach / VALU_PEAK_CYCLES,
                      "valu_busy_cycles_per_launch": busy, "valu_insts_per_launch": insts,
-                     "traffic": None, "hbm_view": hbm})
+                     "traffic": traffic, "hbm_view": hbm})
     else:
         roof.update(hbm)
-        roof["traffic"] = None
+    if traffic is not None:
+        roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
     return roof
 
 
