@@ -82,9 +82,12 @@ enum {
   PURPOSE_MEASURE = 1,
   PURPOSE_RESET = 2,
   PURPOSE_CONFIG = 3,
-  PURPOSE_PF = 7 /* particle-filter draws: entity (8 agent + target) * 64 + particle */
+  PURPOSE_PF = 7,     /* particle filter: normals of particle pair h at entity
+                         (8 agent + target) * 32 + h; resampling offset at
+                         ENT_PF_OFFSET + 8 agent + target */
+  PURPOSE_PF_SEED = 8 /* particle filter: seeding angles, entity as the normals */
 };
-enum { ENT_TARGET_BLOCK = 16, ENT_RANGE_ROW = 64, ENT_ENV = 127 };
+enum { ENT_TARGET_BLOCK = 16, ENT_RANGE_ROW = 64, ENT_ENV = 127, ENT_PF_OFFSET = 2048 };
 
 static void draw(uint64_t seed, uint32_t c0, uint32_t env, uint32_t entity, uint32_t c3,
                  uint32_t out[4]) {
@@ -259,14 +262,16 @@ void orc_ls_batch(int64_t N, int W, const double *win, int gn_iters, double tau,
 /*          offset U in [0, 1), output k copies particle                      */
 /*          min{ m : C_m > (k + U) C_{n-1} / n } (the last one if none);      */
 /*   estimate: the mean of the particles.                                     */
-/* z_k, z'_k: Box-Muller of words 0 and 1 of particle k, u_k = u01(word 2),   */
-/* U = u01(word 3 of particle 0).                                             */
+/* z_k, z'_k: Box-Muller of particle k's two normal words zw[2k], zw[2k+1];   */
+/* u_k = u01(uw[k]); U = u01(uoff). How a step's words come from Philox is    */
+/* the caller's (see the tracker in env_step).                                */
 /* ------------------------------------------------------------------------ */
 #define ORC_PF_MAX 1024
 
 int orc_pf_update(int n, double *px, double *py, int init, int m, const double *ax,
                   const double *ay, const double *r, double sigma_l, double q,
-                  const uint32_t *words, double *ex, double *ey, int32_t *src) {
+                  const uint32_t *zw, const uint32_t *uw, uint32_t uoff, double *ex, double *ey,
+                  int32_t *src) {
   const double two_pi = 6.283185307179586476925286766559;
   if (n < 1 || n > ORC_PF_MAX) return 0;
   if (!init && m < 1) return 0;
@@ -274,8 +279,8 @@ int orc_pf_update(int n, double *px, double *py, int init, int m, const double *
   if (!init) {
     for (int k = 0; k < n; ++k) {
       double z0, z1;
-      orc_normal2(words[4 * k], words[4 * k + 1], &z0, &z1);
-      const double ang = two_pi * ((double)k + orc_u01(words[4 * k + 2])) / (double)n;
+      orc_normal2(zw[2 * k], zw[2 * k + 1], &z0, &z1);
+      const double ang = two_pi * ((double)k + orc_u01(uw[k])) / (double)n;
       const double rad = r[0] + sigma_l * z0;
       px[k] = ax[0] + rad * cos(ang);
       py[k] = ay[0] + rad * sin(ang);
@@ -284,7 +289,7 @@ int orc_pf_update(int n, double *px, double *py, int init, int m, const double *
   } else {
     for (int k = 0; k < n; ++k) {
       double z0, z1;
-      orc_normal2(words[4 * k], words[4 * k + 1], &z0, &z1);
+      orc_normal2(zw[2 * k], zw[2 * k + 1], &z0, &z1);
       px[k] += q * z0;
       py[k] += q * z1;
     }
@@ -307,7 +312,7 @@ int orc_pf_update(int n, double *px, double *py, int init, int m, const double *
       total += exp(lw[k] - best);
       cum[k] = total;
     }
-    const double U = orc_u01(words[3]);
+    const double U = orc_u01(uoff);
     for (int k = 0; k < n; ++k) {
       const double point = ((double)k + U) / (double)n * total;
       int j = 0;
@@ -613,6 +618,7 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
    * agents in index order; no belief and no row: no estimate (held) */
   if (p->est_kind == 1) {
     const uint32_t c3pf = (uint32_t)((episode << 4) | PURPOSE_PF);
+    const uint32_t c3seed = (uint32_t)((episode << 4) | PURPOSE_PF_SEED);
     const double sl = sqrt(E->sigma_r * E->sigma_r + p->pf_lik_sigma * p->pf_lik_sigma);
     for (int i = 0; i < E->nA; ++i) {
       for (int j = 0; j < E->nT; ++j) {
@@ -627,12 +633,27 @@ static void env_step(const orc_params *p, uint64_t seed, uint64_t episode, uint3
           wr[n] = E->hr[a][j][0];
           ++n;
         }
-        uint32_t words[4 * ORC_PF_N];
-        for (int k = 0; k < ORC_PF_N; ++k)
-          draw(seed, t, E->env_id, (uint32_t)((8 * i + j) * ORC_PF_N + k), c3pf, words + 4 * k);
+        /* the step's words: one Philox block per particle pair (2h, 2h + 1),
+         * words 0, 1 particle 2h's normals and 2, 3 particle 2h + 1's; a
+         * second block per pair (purpose 8) gives the seeding angles from
+         * words 0 and 2; the resampling offset is word 0 of the tracker's
+         * own block (entity 2048 + code) */
+        const uint32_t code = (uint32_t)(8 * i + j);
+        uint32_t zw[2 * ORC_PF_N], uw[ORC_PF_N], blk[4];
+        for (int h = 0; h < ORC_PF_N / 2; ++h) {
+          draw(seed, t, E->env_id, code * (ORC_PF_N / 2) + (uint32_t)h, c3pf, blk);
+          zw[4 * h] = blk[0];
+          zw[4 * h + 1] = blk[1];
+          zw[4 * h + 2] = blk[2];
+          zw[4 * h + 3] = blk[3];
+          draw(seed, t, E->env_id, code * (ORC_PF_N / 2) + (uint32_t)h, c3seed, blk);
+          uw[2 * h] = blk[0];
+          uw[2 * h + 1] = blk[2];
+        }
+        draw(seed, t, E->env_id, ENT_PF_OFFSET + code, c3pf, blk);
         double px, py;
         const int ok = orc_pf_update(ORC_PF_N, E->ppx[i][j], E->ppy[i][j], E->pinit[i][j], n, wx,
-                                     wy, wr, sl, p->pf_q, words, &px, &py, NULL);
+                                     wy, wr, sl, p->pf_q, zw, uw, blk[0], &px, &py, NULL);
         if (ok) {
           E->pinit[i][j] = 1;
           E->ex[i][j] = px;

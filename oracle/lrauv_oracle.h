@@ -175,18 +175,20 @@ int orc_spawn_pairwise(const orc_params *p, uint64_t seed, uint64_t episode, uin
  * likelihood and systematic resampling, is spelled out at the definition).
  * n <= 1024 particles (px, py), updated in place; init: 1 when they hold a
  * belief; m measurement rows (ax, ay, r), the first of which seeds the belief
- * when init is 0; sigma_l: likelihood std; q: move std; words [n][4]: the
- * four random words particle k draws for this step (word 3 of particle 0 is
- * the resampling offset). Returns 1 with the estimate (the particles' mean)
- * in (ex, ey) when the tracker holds a belief afterwards, 0 when it has none
- * (init 0 and no row; nothing written). src [n] (may be NULL): the index each
- * particle was copied from by the resampling, -1 when there was none. Pinned:
- * two-particle closed form of the resampling decision, offspring counts of
- * systematic resampling, ring seeding geometry, translation equivariance,
- * convergence on a static target. */
+ * when init is 0; sigma_l: likelihood std; q: move std. Random inputs:
+ * zw [n][2] the two words particle k's normals come from (Box-Muller), uw [n]
+ * the word of its seeding angle, uoff the word of the resampling offset.
+ * Returns 1 with the estimate (the particles' mean) in (ex, ey) when the
+ * tracker holds a belief afterwards, 0 when it has none (init 0 and no row;
+ * nothing written). src [n] (may be NULL): the index each particle was copied
+ * from by the resampling, -1 when there was none. Pinned: two-particle closed
+ * form of the resampling decision, offspring counts of systematic
+ * resampling, ring seeding geometry, translation equivariance, convergence
+ * on a static target. */
 int orc_pf_update(int n, double *px, double *py, int init, int m, const double *ax,
                   const double *ay, const double *r, double sigma_l, double q,
-                  const uint32_t *words, double *ex, double *ey, int32_t *src);
+                  const uint32_t *zw, const uint32_t *uw, uint32_t uoff, double *ex, double *ey,
+                  int32_t *src);
 
 /* ---- full episode(s): reset then T steps for the selected envs.
  * env_ids: global env ids (they key the RNG); counts per selected env.

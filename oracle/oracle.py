@@ -91,8 +91,8 @@ def lib():
         L.orc_rollout.restype = C.c_int
         L.orc_pf_update.argtypes = [C.c_int, P(C.c_double), P(C.c_double), C.c_int, C.c_int,
                                     P(C.c_double), P(C.c_double), P(C.c_double), C.c_double,
-                                    C.c_double, P(C.c_uint32), P(C.c_double), P(C.c_double),
-                                    P(C.c_int32)]
+                                    C.c_double, P(C.c_uint32), P(C.c_uint32), C.c_uint32,
+                                    P(C.c_double), P(C.c_double), P(C.c_int32)]
         L.orc_pf_update.restype = C.c_int
         _register_learned(L)
         _lib = L
@@ -227,21 +227,43 @@ def spawn_pairwise(cfg: dict, seed: int, episode: int, env_id: int, n_agents: in
 
 # ---------------------------------------------------------------- particle filter
 PURPOSE_PF = 7
+PURPOSE_PF_SEED = 8
+ENT_PF_OFFSET = 2048
+
+
+class PfWords:
+    """Random inputs of one filter update: zw [n][2] (normal words of each
+    particle), uw [n] (seeding-angle words), uoff (resampling-offset word)."""
+
+    def __init__(self, zw, uw, uoff):
+        self.zw = np.ascontiguousarray(zw, np.uint32).reshape(-1, 2)
+        self.uw = np.ascontiguousarray(uw, np.uint32).reshape(-1)
+        self.uoff = int(uoff)
 
 
 def pf_words(seed: int, episode: int, t: int, env_id: int, agent: int, target: int,
-             n: int = PF_N) -> np.ndarray:
-    """The random words [n][4] tracker (agent, target) of env `env_id` draws at
-    step t: Philox(t, env id, (8 agent + target) n + k, 7 | episode << 4)."""
-    ctr = np.zeros((n, 4), np.uint32)
+             n: int = PF_N) -> PfWords:
+    """The words tracker (agent, target) of env `env_id` draws at step t: one
+    Philox block per particle pair h at (t, env, (8 agent + target) n/2 + h,
+    7 | episode << 4) (words 0, 1: particle 2h's normals; 2, 3: 2h + 1's), the
+    same counter with purpose 8 for the seeding angles (words 0 and 2), and
+    word 0 of (t, env, 2048 + 8 agent + target, 7 | episode << 4) for the
+    resampling offset."""
+    code = 8 * agent + target
+    ctr = np.zeros((n // 2, 4), np.uint32)
     ctr[:, 0] = t
     ctr[:, 1] = env_id
-    ctr[:, 2] = (8 * agent + target) * n + np.arange(n)
+    ctr[:, 2] = code * (n // 2) + np.arange(n // 2)
     ctr[:, 3] = (episode << 4) | PURPOSE_PF
-    return philox(ctr, seed)
+    z = philox(ctr, seed)
+    ctr[:, 3] = (episode << 4) | PURPOSE_PF_SEED
+    s = philox(ctr, seed)
+    off = philox(np.array([[t, env_id, ENT_PF_OFFSET + code, (episode << 4) | PURPOSE_PF]],
+                          np.uint32), seed)
+    return PfWords(z.reshape(n, 2), s[:, [0, 2]].reshape(n), off[0, 0])
 
 
-def pf_update(px, py, init: bool, rows, sigma_l: float, q: float, words):
+def pf_update(px, py, init: bool, rows, sigma_l: float, q: float, words: PfWords):
     """One particle-filter update (orc_pf_update). rows [m][3] = (ax, ay, r).
     Returns (ok, px, py, (ex, ey), src) with new particle arrays."""
     px = np.array(px, np.float64)
@@ -251,12 +273,13 @@ def pf_update(px, py, init: bool, rows, sigma_l: float, q: float, words):
     ax = np.ascontiguousarray(rows[:, 0])
     ay = np.ascontiguousarray(rows[:, 1])
     r = np.ascontiguousarray(rows[:, 2])
-    w = np.ascontiguousarray(words, np.uint32).reshape(n, 4)
+    assert words.zw.shape[0] == n and words.uw.shape[0] == n
     src = np.empty(n, np.int32)
     ex, ey = C.c_double(), C.c_double()
     ok = lib().orc_pf_update(n, _p(px, C.c_double), _p(py, C.c_double), int(bool(init)),
                              rows.shape[0], _p(ax, C.c_double), _p(ay, C.c_double),
-                             _p(r, C.c_double), sigma_l, q, _p(w, C.c_uint32), C.byref(ex),
+                             _p(r, C.c_double), sigma_l, q, _p(words.zw, C.c_uint32),
+                             _p(words.uw, C.c_uint32), C.c_uint32(words.uoff), C.byref(ex),
                              C.byref(ey), _p(src, C.c_int32))
     return bool(ok), px, py, (ex.value, ey.value), src
 

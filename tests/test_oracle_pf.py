@@ -18,17 +18,15 @@ from paper_2505_08222_amd import configs
 
 
 def words_with_u(n, u3=None, seed=5):
-    """Random words [n][4]; word 3 of particle 0 set so that u01 = u3 (the
-    grid point nearest to it)."""
+    """Random inputs of one update for n particles; the resampling offset's
+    word set so that U = u3 (the grid point nearest to it)."""
     rng = np.random.default_rng(seed)
-    w = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    zw = rng.integers(0, 2**32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    uw = rng.integers(0, 2**32, size=n, dtype=np.uint64).astype(np.uint32)
+    uoff = int(rng.integers(0, 2**32, dtype=np.uint64))
     if u3 is not None:
-        w[0, 3] = np.uint32(min(int(u3 * 2**23), 2**23 - 1) << 9)
-    return w
-
-
-def u_of(word):
-    return orc.u01(int(word))
+        uoff = min(int(u3 * 2**23), 2**23 - 1) << 9
+    return orc.PfWords(zw, uw, uoff)
 
 
 @pytest.mark.parametrize("delta,sigma", [(3.0, 2.0), (1.0, 1.5), (6.0, 5.0)])
@@ -44,7 +42,7 @@ def test_two_particle_resampling_closed_form(delta, sigma):
         if abs(U - thr) < 1e-3:
             continue
         wd = words_with_u(2, U)
-        Ue = u_of(wd[0, 3])
+        Ue = orc.u01(wd.uoff)
         ok, px, py, est, src = orc.pf_update([100.0, 100.0 + delta], [0.0, 0.0], True, rows,
                                              sigma, 0.0, wd)
         assert ok
@@ -124,7 +122,7 @@ def test_seed_ring_geometry():
     k = np.arange(n)
     assert np.all(ang >= 2 * np.pi * k / n - 1e-12) and np.all(ang < 2 * np.pi * (k + 1) / n + 1e-12)
     for kk in range(n):
-        z0, _ = orc.normal2(int(wd[kk, 0]), int(wd[kk, 1]))
+        z0, _ = orc.normal2(int(wd.zw[kk, 0]), int(wd.zw[kk, 1]))
         assert math.hypot(px[kk] - a[0], py[kk] - a[1]) == pytest.approx(abs(r + sig * z0), rel=1e-12)
     # a ring's mean is near its centre
     assert math.hypot(est[0] - a[0], est[1] - a[1]) < 0.2 * r
@@ -143,7 +141,7 @@ def test_no_belief_no_row_and_predict_only():
     ok, px, py, est, src = orc.pf_update(px0, py0, True, np.zeros((0, 3)), 2.0, q, wd)
     assert ok and np.all(src == -1)
     for k in range(n):
-        z0, z1 = orc.normal2(int(wd[k, 0]), int(wd[k, 1]))
+        z0, z1 = orc.normal2(int(wd.zw[k, 0]), int(wd.zw[k, 1]))
         assert px[k] == pytest.approx(px0[k] + q * z0, abs=1e-12)
         assert py[k] == pytest.approx(py0[k] + q * z1, abs=1e-12)
     assert est == pytest.approx((px.mean(), py.mean()), abs=1e-12)
