@@ -806,6 +806,50 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
     return result
 
 
+# Table I of the paper (JaxLrauv, its particle filter, 30 s steps; one H100
+# by the paper's training setup): steps per second summed over envs, for n
+# agents and n targets, n = 1..5.
+PAPER_TABLE1_SPS = {128: [68508, 19712, 9128, 5180, 3469], 1024: [81686, 21534, 9786, 5450, 3574]}
+
+
+def table1_grid(args, steps=5, T=300):
+    """The paper's Table I grid on this build: the paper environment with the
+    particle-filter tracker over pooled ranges, n agents x n targets, 128 and
+    1024 envs; each point one captured graph of reset + T steps, replayed
+    `steps` times (HIP events). The paper's SPS beside each point is context
+    (another GPU, another filter implementation), not a target."""
+    import torch
+
+    from paper_2505_08222_amd.configs import env_config
+    from paper_2505_08222_amd.env import Env
+
+    stream = torch.cuda.current_stream()
+    points = []
+    for E in (128, 1024):
+        for n in range(1, 6):
+            cfg = env_config("paper_pf", n_agents=n, n_targets=n, ragged=0, episode_len=T)
+            env = Env(cfg, E, seed=0)
+            out, _ = env.capture_graph(T, episode=0, record=RECORD)
+            env.launch_graph()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(steps):
+                env.launch_graph()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / steps
+            sps = E * T / (ms / 1e3)
+            paper = PAPER_TABLE1_SPS[E][n - 1]
+            points.append({"envs": E, "agents": n, "targets": n, "sps": sps,
+                           "ms_per_step": ms / T, "paper_sps_h100": paper,
+                           "ratio_to_paper": sps / paper})
+            log(f"[table1] {E} envs {n}A{n}T: {sps:.3g} SPS ({ms / T * 1e3:.1f} us/step), "
+                f"paper {paper}")
+            del out, env
+    return points
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -845,9 +889,11 @@ def main():
               flush=True)
         return
     if args.workload != "all":
-        print(json.dumps(bench_env(args, args.workload, args.steps, args.warmup,
-                                   sweep=args.workload == "batched" and not args.no_sweep,
-                                   cpu_seconds=cpu_s)), flush=True)
+        res = bench_env(args, args.workload, args.steps, args.warmup,
+                        sweep=args.workload == "batched" and not args.no_sweep, cpu_seconds=cpu_s)
+        if args.workload == "paper_pf":
+            res["table1_grid"] = table1_grid(args)
+        print(json.dumps(res), flush=True)
         return
     # headline: the ragged batch, the largest single-GPU configuration
     t_start = time.perf_counter()
@@ -873,6 +919,7 @@ def main():
                                     cpu_seconds=sec_cpu)
     result["paper_pf"] = bench_env(args, "paper_pf", min(args.steps, 5), min(args.warmup, 1),
                                    cpu_seconds=sec_cpu)
+    result["paper_pf"]["table1_grid"] = table1_grid(args)
     for k in ("batched", "learned", "policy", "paper", "paper_pooled", "learned_paper",
               "ragged_pf", "paper_pf"):
         for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):

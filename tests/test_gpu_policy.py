@@ -64,11 +64,15 @@ def test_policy_init_statistics():
     assert (p[layer0:layer0 + D] == 1).all() and (p[layer0 + D:layer0 + 2 * D] == 0).all()
 
 
-@pytest.mark.parametrize("n_agents,n_targets", [(5, 5), (2, 3)])
-def test_policy_rollout_deterministic_and_graph(n_agents, n_targets):
+@pytest.mark.parametrize("n_agents,n_targets,pf", [(5, 5, False), (2, 3, False), (3, 4, True)])
+def test_policy_rollout_deterministic_and_graph(n_agents, n_targets, pf):
+    """Closed loop: graph replays equal the eager loop, and replaying its
+    actions through the environment reproduces it (pf: the particle-filter
+    tracker, pooled, inside every step)."""
     from paper_2505_08222_amd import policy
     from paper_2505_08222_amd.env import Env
-    cfg = env_config("policy", episode_len=40, n_agents=n_agents, n_targets=n_targets)
+    over = dict(est_kind=1, pf_q=1.0, pf_lik_sigma=2.0, pooled=1) if pf else {}
+    cfg = env_config("policy", episode_len=40, n_agents=n_agents, n_targets=n_targets, **over)
     E, T = 512, 40
     params = policy.init_params(0)
     rec = ("obs", "obs_mask", "reward", "done", "actions", "gstate")
@@ -95,8 +99,8 @@ def test_policy_rollout_deterministic_and_graph(n_agents, n_targets):
         np.testing.assert_array_equal(rc[k].cpu().numpy(), ra[k].cpu().numpy(), err_msg=k)
 
 
-@pytest.mark.parametrize("learned_loop", [False, True])
-def test_closed_loop_actions_follow_oracle_policy(orc, learned_loop):
+@pytest.mark.parametrize("learned_loop,pf", [(False, False), (True, False), (False, True)])
+def test_closed_loop_actions_follow_oracle_policy(orc, learned_loop, pf):
     """In the closed loop, the action of step t is the oracle's inverse-CDF
     draw from the oracle policy's logits on the loop's own observation of step
     t - 1, with u from Philox(t, env id, agent, 4 | episode << 4) keyed by the
@@ -104,7 +108,8 @@ def test_closed_loop_actions_follow_oracle_policy(orc, learned_loop):
     has u within 0.05 of a CDF boundary of the oracle's softmax."""
     from paper_2505_08222_amd import learned, policy
     from paper_2505_08222_amd.env import Env
-    cfg = env_config("policy", episode_len=24)
+    cfg = env_config("policy", episode_len=24,
+                     **(dict(est_kind=1, pf_q=1.0, pf_lik_sigma=2.0) if pf else {}))
     E, T, seed, episode = 96, 24, 3, 0
     params = policy.init_params(2)
     mlp = learned.init_params(7) if learned_loop else None
