@@ -470,6 +470,59 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
                        double *d_metrics, int32_t capture, void *d_work, int64_t work_bytes,
                        void *stream);
 
+/* ---------------------------------------------------------------------------
+ * The learner's forward half (Sec. III-B: MAPPO updates the actors with the
+ * PPO clipped surrogate objective and one centralised critic V(S) estimates
+ * the value of the global state; Sec. IV-B-1, Fig. 3: the TransformerCritic
+ * reads the full global state as entity tokens plus one embedding token whose
+ * transformed output gives V). The backward pass through the two transformers
+ * is not part of this library.
+ * ------------------------------------------------------------------------- */
+/* Workspace for critic_forward (256-byte aligned); -1 on bad sizes. */
+int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
+/* V of N global states of fixed-count envs: d_gstate [N][n_agents +
+ * n_targets][6], the rows env_rollout records in outs->gstate (x, y, z,
+ * speed, heading, is_target; one step of a batch is N = num_envs states).
+ * Each state becomes 1 + n_agents + n_targets <= 16 tokens: an all-zero token
+ * (its embedding is the embedding bias; its output carries V), then each
+ * agent and target as (x / pos_scale, y / pos_scale, v cos(heading),
+ * v sin(heading), is_agent, is_target). The network is the policy's (same
+ * parameter layout, policy_init, BF16 MFMA with FP32 accumulation) and V is
+ * the first output of its head on the first token. d_values [N] (FP32).
+ * Errors: MIL_EINVAL (sizes, pos_scale <= 0), MIL_ESHAPE, MIL_EALIGN, MIL_EHIP. */
+int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
+                   float pos_scale, const float *d_params, float *d_values, void *d_work,
+                   int64_t work_bytes, void *stream);
+/* Generalised advantage estimation (Schulman et al. 2016; the advantage
+ * estimator of MAPPO) over T steps of E envs with the env's shared reward:
+ * d_rewards [T][E], d_dones [T][E] (1: the step ends its episode, nothing is
+ * bootstrapped past it), d_values [T + 1][E] (V of the state before step t,
+ * row T the state after the last step). delta_t = r_t + gamma V_{t+1} (1 -
+ * d_t) - V_t, A_t = delta_t + gamma lambda (1 - d_t) A_{t+1}; writes d_adv
+ * [T][E] and the value targets d_ret [T][E] = A_t + V_t (FP64 recurrence,
+ * FP32 output). gamma, lambda in [0, 1]. */
+int ppo_gae(const float *d_rewards, const uint8_t *d_dones, const float *d_values, int32_t T,
+            int64_t E, float gamma, float lambda, float *d_adv, float *d_ret, void *stream);
+/* Bytes of the ppo_objective workspace (8-byte aligned). */
+int64_t ppo_workspace_bytes(void);
+/* The clipped PPO objective over T steps of A agents (agent a of env
+ * a / n_agents, sharing its env's advantage): d_logits_new / d_logits_old
+ * [T][A][8] (the first n_actions are the action logits: the policy at update
+ * time and at sampling time), d_actions [T][A], d_adv [T][E], d_values and
+ * d_returns [T][E] (critic output and targets). With rho = pi_new(a) /
+ * pi_old(a), writes d_out [4] (FP64): policy loss -mean min(rho A, clip(rho,
+ * 1 - clip_eps, 1 + clip_eps) A), value loss mean (V - R)^2, entropy mean
+ * H(pi_new), and the fraction of samples where the clipped term is strictly
+ * the smaller; d_dlogits [T][A][8] (may be NULL): d(policy loss)/d
+ * logits_new (0 where the clipped term is the minimum; columns n_actions..7
+ * are 0); d_dvalues [T][E] (may be NULL): d(value loss)/dV. Sums reduce in a
+ * fixed order: results do not depend on the launch. */
+int ppo_objective(const float *d_logits_new, const float *d_logits_old, const int32_t *d_actions,
+                  const float *d_adv, const float *d_values, const float *d_returns, int32_t T,
+                  int64_t A, int32_t n_agents, int32_t n_actions, float clip_eps, double *d_out,
+                  float *d_dlogits, float *d_dvalues, void *d_work, int64_t work_bytes,
+                  void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmilrauv.so")
 SOURCES = ["env_kernels.hip", "est_kernels.hip", "learned_kernels.hip", "policy_kernels.hip",
-           "pf_kernels.hip", "noalloc.hip", "abi.cpp", "learned_abi.cpp"]
+           "pf_kernels.hip", "ppo_kernels.hip", "noalloc.hip", "abi.cpp", "learned_abi.cpp"]
 ARCH = "gfx950"
 
 

@@ -1027,6 +1027,95 @@ int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions
   return MIL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learner's forward half: critic values, GAE, clipped PPO objective
+// ---------------------------------------------------------------------------
+static int64_t critic_logits_off(int64_t N, int nt) {
+  return align256(policy_work(N, N * nt).total);
+}
+
+int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets) {
+  if (N < 0 || n_agents < 1 || n_targets < 1 || n_agents + n_targets + 1 > mil::kPolMaxTok) return -1;
+  const int nt = n_agents + n_targets + 1;
+  return critic_logits_off(N, nt) + align256(N * mil::kPolActions * 4);
+}
+
+int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
+                   float pos_scale, const float *d_params, float *d_values, void *d_work,
+                   int64_t work_bytes, void *stream) {
+  if (N < 0 || n_agents < 1 || n_targets < 1 || n_agents + n_targets + 1 > mil::kPolMaxTok)
+    return fail(MIL_EINVAL, "need N >= 0 and 1 + n_agents + n_targets <= 16");
+  if (!(pos_scale > 0.0f)) return fail(MIL_EINVAL, "pos_scale must be > 0");
+  if (N == 0) return MIL_OK;
+  if (!d_gstate || !d_params || !d_values) return fail(MIL_EINVAL, "null argument");
+  if (!d_work || (((uintptr_t)d_work) & 255)) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (work_bytes < critic_workspace_bytes(N, n_agents, n_targets))
+    return fail(MIL_ESHAPE, "workspace too small (critic_workspace_bytes)");
+  const int M = n_agents + n_targets, nt = M + 1;
+  const PolicyWork w = policy_work(N, N * nt);
+  char *ws = (char *)d_work;
+  float *tokens = (float *)(ws + w.obs);
+  uint8_t *mask = (uint8_t *)(ws + w.mask);
+  float *logits = (float *)(ws + critic_logits_off(N, nt));
+  __bf16 *wq, *wo, *w1, *w2;
+  prepared_ptrs(ws + w.prep, &wq, &wo, &w1, &w2);
+  if (mil::launch_critic_tokens(d_gstate, N, M, pos_scale, tokens, mask, stream) ||
+      mil::launch_policy_prepare(d_params, wq, wo, w1, w2, stream))
+    return fail(MIL_EHIP, "critic set-up launch failed");
+  mil::PolicyArgs a{};
+  a.A = N;
+  a.n_tok = nt;
+  a.agents_per_tile = policy_tile(nt);
+  a.obs = tokens;
+  a.mask = mask;
+  a.params = d_params;
+  a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
+  a.logits = logits;
+  a.actions = nullptr;
+  a.n_agents = 1;
+  a.n_actions = 1;
+  a.env_ids = nullptr;
+  if (mil::launch_policy(a, num_cus_env(), stream) ||
+      mil::launch_first_column(logits, N, d_values, stream))
+    return fail(MIL_EHIP, "critic launch failed");
+  return MIL_OK;
+}
+
+int ppo_gae(const float *d_rewards, const uint8_t *d_dones, const float *d_values, int32_t T,
+            int64_t E, float gamma, float lambda, float *d_adv, float *d_ret, void *stream) {
+  if (T < 0 || E < 0) return fail(MIL_EINVAL, "need T >= 0, E >= 0");
+  if (!(gamma >= 0.0f && gamma <= 1.0f && lambda >= 0.0f && lambda <= 1.0f))
+    return fail(MIL_EINVAL, "gamma and lambda must be in [0, 1]");
+  if (T == 0 || E == 0) return MIL_OK;
+  if (!d_rewards || !d_dones || !d_values || !d_adv || !d_ret)
+    return fail(MIL_EINVAL, "null argument");
+  if (mil::launch_gae(d_rewards, d_dones, d_values, T, E, gamma, lambda, d_adv, d_ret, stream))
+    return fail(MIL_EHIP, "gae launch failed");
+  return MIL_OK;
+}
+
+int64_t ppo_workspace_bytes(void) { return (int64_t)mil::kPpoBlocks * 4 * 8; }
+
+int ppo_objective(const float *d_logits_new, const float *d_logits_old, const int32_t *d_actions,
+                  const float *d_adv, const float *d_values, const float *d_returns, int32_t T,
+                  int64_t A, int32_t n_agents, int32_t n_actions, float clip_eps, double *d_out,
+                  float *d_dlogits, float *d_dvalues, void *d_work, int64_t work_bytes,
+                  void *stream) {
+  if (T < 1 || A < 1 || n_agents < 1 || (A % n_agents) != 0 || n_actions < 1 ||
+      n_actions > mil::kPolActions)
+    return fail(MIL_EINVAL, "need T >= 1, A a positive multiple of n_agents, n_actions in 1..8");
+  if (!(clip_eps >= 0.0f && clip_eps < 1.0f)) return fail(MIL_EINVAL, "clip_eps must be in [0, 1)");
+  if (!d_logits_new || !d_logits_old || !d_actions || !d_adv || !d_values || !d_returns || !d_out)
+    return fail(MIL_EINVAL, "null argument");
+  if (!d_work || (((uintptr_t)d_work) & 7) || work_bytes < ppo_workspace_bytes())
+    return fail(MIL_ESHAPE, "workspace too small or misaligned (ppo_workspace_bytes, 8-byte aligned)");
+  if (mil::launch_ppo_objective(d_logits_new, d_logits_old, d_actions, d_adv, d_values, d_returns,
+                                T, A, n_agents, n_actions, clip_eps, d_out, d_dlogits, d_dvalues,
+                                (double *)d_work, stream))
+    return fail(MIL_EHIP, "ppo objective launch failed");
+  return MIL_OK;
+}
+
 int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned) {
   if (!h || !h->ws) return -1;
   return env_policy_work(h, learned != 0).total;

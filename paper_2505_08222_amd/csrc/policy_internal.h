@@ -66,4 +66,17 @@ int launch_policy_prepare(const float *th, __bf16 *wqkv, __bf16 *wo, __bf16 *w1,
                           void *stream);
 int launch_policy(const PolicyArgs &args, int num_cus, void *stream);
 
+// ppo_kernels.hip: the learner's forward half (critic tokens, GAE, clipped
+// PPO objective); partial sums in kPpoBlocks blocks of four doubles.
+constexpr int kPpoBlocks = 256;
+int launch_critic_tokens(const float *gstate, int64_t N, int M, float pos_scale, float *tokens,
+                         uint8_t *mask, void *stream);
+int launch_first_column(const float *logits, int64_t N, float *out, void *stream);
+int launch_gae(const float *rewards, const uint8_t *dones, const float *values, int32_t T, int64_t E,
+               float gamma, float lambda, float *adv, float *ret, void *stream);
+int launch_ppo_objective(const float *lnew, const float *lold, const int32_t *actions,
+                         const float *adv, const float *values, const float *returns, int32_t T,
+                         int64_t A, int32_t n_agents, int32_t n_actions, float clip_eps,
+                         double *out, float *dlogits, float *dvalues, double *part, void *stream);
+
 }  // namespace mil
