@@ -590,6 +590,120 @@ def policy_flops_per_agent_step(n_tok, d=64, heads=4, ffn=256, layers=2, n_out=8
     return 2 * n_tok * 6 * d + layers * per_layer + 2 * d * n_out
 
 
+def bench_ppo(args, T=32, cpu_seconds=None):
+    """The learner's forward half on the policy workload's shape (16384 envs x
+    5 agents x 5 targets), one PPO batch of T steps: critic values of the T + 1
+    global states of every env, the policy re-evaluated on every agent's T
+    observations, GAE, and the clipped objective with its gradients. Inputs are
+    synthetic tensors of the workload's shapes, resident in HBM (the learner's
+    arithmetic does not depend on their values). Dominant kernel: the attention
+    kernel (critic and policy forwards), MFMA roofline."""
+    import numpy as np
+    import torch
+
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.configs import CONFIGS
+
+    c = CONFIGS["policy"]
+    E = args.envs or c["num_envs"]
+    na = nt = 5
+    M, n_tok, A = na + nt, na + na + nt, E * na
+    g = torch.Generator(device="cuda").manual_seed(0)
+    dev = "cuda"
+    gs = torch.randn(T + 1, E * M, 6, device=dev, generator=g)
+    gs[..., 0:2] *= 1000.0
+    gs[..., 2] = 0.0
+    gs[..., 5] = (torch.arange(E * M, device=dev) % M >= na).float()
+    obs = torch.randn(T * A * n_tok, 6, device=dev, generator=g)
+    mask = (torch.rand(T * A * n_tok, device=dev, generator=g) > 0.1).to(torch.uint8)
+    actions = torch.randint(0, 5, (T, A), device=dev, dtype=torch.int32, generator=g)
+    rewards = torch.rand(T, E, device=dev, generator=g)
+    dones = torch.zeros(T, E, device=dev, dtype=torch.uint8)
+    actor = policy.init_params(c["seed"])
+    critic = policy.init_params(c["seed"] + 1)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            out = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return float(np.median(ms)), out
+
+    t_crit, values = timed(lambda: ppo.critic_forward(gs, na, nt, critic).reshape(T + 1, E))
+    t_pol, (logits, _) = timed(lambda: policy.forward(obs, mask, actor, n_tok, na))
+    logits = logits.reshape(T, A, 8)
+    logits_old = logits + 0.1 * torch.randn(logits.shape, device=dev, generator=g)
+    t_gae, (adv, ret) = timed(lambda: ppo.gae(rewards, dones, values, 0.99, 0.95))
+    t_obj, (out, _, _) = timed(lambda: ppo.objective(logits, logits_old, actions, adv,
+                                                    values[:T].contiguous(), ret, na, 5))
+    total = t_crit + t_pol + t_gae + t_obj
+    fl_crit = policy_flops_per_agent_step(M + 1) * (T + 1) * E
+    fl_pol = policy_flops_per_agent_step(n_tok) * T * A
+    ach = fl_crit / (t_crit / 1e3) / 1e12
+    log(f"[bench] ppo: critic {t_crit:.2f} ms, policy {t_pol:.2f} ms, gae {t_gae:.3f} ms, "
+        f"objective {t_obj:.3f} ms")
+    o = out.cpu().numpy()
+    res = {
+        "metric": METRIC, "value": T * A / (total / 1e3), "unit": "agent-steps/s",
+        "n_gpus": 1, "steps": 3, "dtype": "bf16 (MFMA, FP32 accumulate); FP64 GAE",
+        "data": "synthetic tensors of the workload's shapes",
+        "config": {"workload": f"PPO batch: {E} envs x {na} agents x {nt} targets x {T} steps: "
+                               "critic on T + 1 states, policy on T steps, GAE, clipped objective "
+                               "(forward half; no backward through the transformers)",
+                   "envs": E, "agents": A, "batch_steps": T},
+        "ms": {"critic": t_crit, "policy": t_pol, "gae": t_gae, "objective": t_obj, "total": total},
+        "objective": {"policy_loss": float(o[0]), "value_loss": float(o[1]),
+                      "entropy": float(o[2]), "clip_frac": float(o[3])},
+        "roofline": {"bound": "mfma", "kernel": "policy_kernel (critic tokens)", "achieved": ach,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": ach / 2500.0, "traffic": None,
+                     "flops_per_state": policy_flops_per_agent_step(M + 1), "kernel_ms": t_crit,
+                     "policy_forward_frac": fl_pol / (t_pol / 1e3) / 1e12 / 2500.0},
+    }
+    if cpu_seconds:
+        res["cpu_baseline"] = cpu_baseline_ppo(critic, actor, cpu_seconds)
+    return res
+
+
+def cpu_baseline_ppo(critic, actor, budget_s):
+    """The oracle's forward half on a bounded sample: 4 envs x 5x5 x 8 steps
+    per round (critic and policy forwards in FP64 C, one thread; GAE and the
+    objective in numpy), repeated until the budget is used; agent-steps/s."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from oracle import ppo_oracle as po
+
+    rng = np.random.default_rng(0)
+    E, T, na, nt = 4, 8, 5, 5
+    M, n_tok, A = na + nt, 2 * na + nt, E * na
+    th_c = critic.detach().cpu().numpy().astype(np.float64)
+    th_a = actor.detach().cpu().numpy().astype(np.float64)
+    rounds = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        g = rng.normal(size=((T + 1) * E, M, 6))
+        g[..., 5] = (np.arange(M) >= na)
+        tok = po.critic_tokens(g, na, nt, 1000.0)
+        v = orc.policy_forward(tok, np.ones(tok.shape[:2], np.uint8), th_c)[:, 0].reshape(T + 1, E)
+        obs = rng.normal(size=(T * A, n_tok, 6))
+        lg = orc.policy_forward(obs, np.ones((T * A, n_tok), np.uint8), th_a).reshape(T, A, 8)
+        adv, ret = po.gae(rng.random((T, E)), np.zeros((T, E)), v, 0.99, 0.95)
+        po.ppo_objective(lg, lg + 0.1, rng.integers(0, 5, (T, A)), adv, v[:T], ret, na, 5, 0.2)
+        rounds += 1
+    el = time.perf_counter() - t0
+    return {"value": rounds * T * A / el, "unit": "agent-steps/s", "cores": 1, "kind": "oracle",
+            **host_cpu(),
+            "sample": f"{rounds} rounds of {E} envs x 5x5 x {T} steps (critic and policy forwards "
+                      f"FP64 C, GAE and objective numpy), {el:.1f} s"}
+
+
 def bench_policy(args, steps, warmup, mlp="train", cpu_seconds=None):
     """Full rollout with the attention policy: 16384 envs x 5 agents x 5
     targets x 1000 steps, each step = policy forward on every agent's
@@ -857,7 +971,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "plain", "batched", "ragged", "learned", "policy", "paper",
-                             "paper_pooled", "learned_paper", "ragged_pf", "paper_pf"])
+                             "paper_pooled", "learned_paper", "ragged_pf", "paper_pf", "ppo"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -884,6 +998,9 @@ def main():
         print(json.dumps(bench_learned(args, args.steps, cpu_seconds=cpu_s, variant=variant)),
               flush=True)
         return
+    if args.workload == "ppo":
+        print(json.dumps(bench_ppo(args, cpu_seconds=cpu_s)), flush=True)
+        return
     if args.workload == "policy":
         print(json.dumps(bench_policy(args, args.steps, args.warmup, cpu_seconds=cpu_s)),
               flush=True)
@@ -907,6 +1024,7 @@ def main():
     result["learned"] = bench_learned(args, args.steps, cpu_seconds=sec_cpu, trained=(mlp, train_info))
     result["policy"] = bench_policy(args, min(args.steps, 3), min(args.warmup, 1), mlp=mlp,
                                     cpu_seconds=sec_cpu)
+    result["ppo"] = bench_ppo(args, cpu_seconds=None if sec_cpu is None else 4.0)
     # the paper's own environment (30 s steps, rudder, follow reward, 450 m
     # detection, pairwise spawn) and the learned estimator on its windows
     result["paper"] = bench_env(args, "paper", args.steps, args.warmup, cpu_seconds=sec_cpu)
@@ -920,7 +1038,7 @@ def main():
     result["paper_pf"] = bench_env(args, "paper_pf", min(args.steps, 5), min(args.warmup, 1),
                                    cpu_seconds=sec_cpu)
     result["paper_pf"]["table1_grid"] = table1_grid(args)
-    for k in ("batched", "learned", "policy", "paper", "paper_pooled", "learned_paper",
+    for k in ("batched", "learned", "policy", "ppo", "paper", "paper_pooled", "learned_paper",
               "ragged_pf", "paper_pf"):
         for key in ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "data"):
             result[k].pop(key, None)
