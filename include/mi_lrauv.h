@@ -446,6 +446,14 @@ int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions
                    const uint8_t *d_mask, const float *d_params, float *d_logits,
                    int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
                    int64_t work_bytes, void *stream);
+/* policy_forward that also writes d_feat [A][64] (may be NULL): the head's
+ * input of each agent, the final LayerNorm of its self token, for the head's
+ * gradient (head_grad). */
+int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
+                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
+                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
+                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
+                        void *stream);
 /* Workspace for env_policy_rollout on this bound batch (256-byte aligned):
  * the policy's, plus (learned != 0) every tracker's window, sigma, estimate
  * and flag and the learned estimator's own workspace. -1 on a bad handle. */
@@ -475,8 +483,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
  * PPO clipped surrogate objective and one centralised critic V(S) estimates
  * the value of the global state; Sec. IV-B-1, Fig. 3: the TransformerCritic
  * reads the full global state as entity tokens plus one embedding token whose
- * transformed output gives V). The backward pass through the two transformers
- * is not part of this library.
+ * transformed output gives V), and the gradient of the two output heads. The
+ * backward pass through the transformers below the heads is not part of this
+ * library.
  * ------------------------------------------------------------------------- */
 /* Workspace for critic_forward (256-byte aligned); -1 on bad sizes. */
 int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
@@ -488,11 +497,12 @@ int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
  * agent and target as (x / pos_scale, y / pos_scale, v cos(heading),
  * v sin(heading), is_agent, is_target). The network is the policy's (same
  * parameter layout, policy_init, BF16 MFMA with FP32 accumulation) and V is
- * the first output of its head on the first token. d_values [N] (FP32).
+ * the first output of its head on the first token. d_values [N] (FP32);
+ * d_feat [N][64] (may be NULL): the head's input of each state.
  * Errors: MIL_EINVAL (sizes, pos_scale <= 0), MIL_ESHAPE, MIL_EALIGN, MIL_EHIP. */
 int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
-                   float pos_scale, const float *d_params, float *d_values, void *d_work,
-                   int64_t work_bytes, void *stream);
+                   float pos_scale, const float *d_params, float *d_values, float *d_feat,
+                   void *d_work, int64_t work_bytes, void *stream);
 /* Generalised advantage estimation (Schulman et al. 2016; the advantage
  * estimator of MAPPO) over T steps of E envs with the env's shared reward:
  * d_rewards [T][E], d_dones [T][E] (1: the step ends its episode, nothing is
@@ -503,8 +513,20 @@ int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n
  * FP32 output). gamma, lambda in [0, 1]. */
 int ppo_gae(const float *d_rewards, const uint8_t *d_dones, const float *d_values, int32_t T,
             int64_t E, float gamma, float lambda, float *d_adv, float *d_ret, void *stream);
-/* Bytes of the ppo_objective workspace (8-byte aligned). */
+/* Bytes of the ppo_objective and head_grad workspace (8-byte aligned). */
 int64_t ppo_workspace_bytes(void);
+/* Gradient of the output head (the last linear layer of the policy or of the
+ * critic) from the gradients at its outputs: d_feat [N][64] the head's inputs
+ * (policy_forward_feat, critic_forward), d_dout [N][ld] the gradients at the
+ * first n_out outputs (d_dlogits of ppo_objective with ld 8; d_dvalues with ld
+ * 1, n_out 1). d_grad [8 * 64 + 8] in the head's parameter layout (Wh then
+ * bh, the last 520 floats of the parameter vector): rows n_out..7 are 0, so
+ * mlp_adam_step over those 520 floats updates the head. FP64 sums in a fixed
+ * order; N = 0 gives a zero gradient (d_feat and d_dout may then be
+ * NULL). The layers below the head are not differentiated here. Errors: MIL_EINVAL (N < 0, n_out outside 1..8,
+ * ld < n_out, null pointer), MIL_ESHAPE (workspace), MIL_EHIP. */
+int head_grad(int64_t N, const float *d_feat, const float *d_dout, int32_t ld, int32_t n_out,
+              float *d_grad, void *d_work, int64_t work_bytes, void *stream);
 /* The clipped PPO objective over T steps of A agents (agent a of env
  * a / n_agents, sharing its env's advantage): d_logits_new / d_logits_old
  * [T][A][8] (the first n_actions are the action logits: the policy at update

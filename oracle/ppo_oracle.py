@@ -1,5 +1,6 @@
 """FP64 CPU oracle of the learner's forward half: the centralised critic's
-inputs, generalised advantage estimation and the clipped PPO objective.
+inputs, generalised advantage estimation, the clipped PPO objective and the
+gradient of a network's output head.
 
 TEST INFRASTRUCTURE ONLY: plain numpy loops, written for reading against the
 definitions; only the tests, the package's smoke check and the benchmark's
@@ -111,3 +112,18 @@ def ppo_objective(logits_new, logits_old, actions, adv, values, returns, n_agent
         "dlogits": dlog,
         "dvalues": 2.0 * (v - R) / v.size,
     }
+
+
+def head_grad(feat, dout, n_out: int, rows: int = 8):
+    """Gradient of the linear output head y = W f + b (W [rows][64], b [rows])
+    from the gradients at its outputs: feat [N][64] the head's inputs,
+    dout [N][>= n_out] d loss / d y for the first n_out outputs (the others
+    take no gradient). Returns (dW [rows][64], db [rows]) with
+    dW[k][d] = sum_n dout[n][k] f[n][d], db[k] = sum_n dout[n][k]."""
+    f = np.asarray(feat, np.float64)
+    g = np.asarray(dout, np.float64).reshape(f.shape[0], -1)[:, :n_out]
+    dW = np.zeros((rows, f.shape[1]))
+    db = np.zeros(rows)
+    dW[:n_out] = g.T @ f
+    db[:n_out] = g.sum(0)
+    return dW, db

@@ -989,10 +989,25 @@ int policy_init(float *d_params, uint64_t seed, void *stream) {
   return MIL_OK;
 }
 
+int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
+                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
+                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
+                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
+                        void *stream);
+
 int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions, const float *d_obs,
                    const uint8_t *d_mask, const float *d_params, float *d_logits,
                    int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
                    int64_t work_bytes, void *stream) {
+  return policy_forward_feat(A, n_tok, n_agents, n_actions, d_obs, d_mask, d_params, d_logits,
+                             d_actions, nullptr, seed, t, episode, d_work, work_bytes, stream);
+}
+
+int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
+                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
+                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
+                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
+                        void *stream) {
   if (A < 0 || n_tok < 1 || n_tok > mil::kPolMaxTok || n_agents < 1 || n_actions < 1 ||
       n_actions > mil::kPolActions || (A % n_agents) != 0)
     return fail(MIL_EINVAL, "need n_tok in 1..16, n_actions in 1..8, A a multiple of n_agents");
@@ -1016,6 +1031,7 @@ int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions
   a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
   a.logits = d_logits;
   a.actions = d_actions;
+  a.feat = d_feat;
   a.n_agents = n_agents;
   a.n_actions = n_actions;
   a.t = t;
@@ -1041,8 +1057,8 @@ int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets) {
 }
 
 int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
-                   float pos_scale, const float *d_params, float *d_values, void *d_work,
-                   int64_t work_bytes, void *stream) {
+                   float pos_scale, const float *d_params, float *d_values, float *d_feat,
+                   void *d_work, int64_t work_bytes, void *stream) {
   if (N < 0 || n_agents < 1 || n_targets < 1 || n_agents + n_targets + 1 > mil::kPolMaxTok)
     return fail(MIL_EINVAL, "need N >= 0 and 1 + n_agents + n_targets <= 16");
   if (!(pos_scale > 0.0f)) return fail(MIL_EINVAL, "pos_scale must be > 0");
@@ -1072,6 +1088,7 @@ int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n
   a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
   a.logits = logits;
   a.actions = nullptr;
+  a.feat = d_feat;
   a.n_agents = 1;
   a.n_actions = 1;
   a.env_ids = nullptr;
@@ -1094,7 +1111,22 @@ int ppo_gae(const float *d_rewards, const uint8_t *d_dones, const float *d_value
   return MIL_OK;
 }
 
-int64_t ppo_workspace_bytes(void) { return (int64_t)mil::kPpoBlocks * 4 * 8; }
+int64_t ppo_workspace_bytes(void) {
+  // the objective's partials, or the head gradient's (n_out <= 8)
+  return (int64_t)mil::kPpoBlocks * mil::kPolActions * (mil::kPolD + 1) * 8;
+}
+
+int head_grad(int64_t N, const float *d_feat, const float *d_dout, int32_t ld, int32_t n_out,
+              float *d_grad, void *d_work, int64_t work_bytes, void *stream) {
+  if (N < 0 || n_out < 1 || n_out > mil::kPolActions || ld < n_out)
+    return fail(MIL_EINVAL, "need N >= 0, n_out in 1..8, ld >= n_out");
+  if (!d_grad || (N > 0 && (!d_feat || !d_dout))) return fail(MIL_EINVAL, "null argument");
+  if (!d_work || (((uintptr_t)d_work) & 7) || work_bytes < ppo_workspace_bytes())
+    return fail(MIL_ESHAPE, "workspace too small or misaligned (ppo_workspace_bytes, 8-byte aligned)");
+  if (mil::launch_head_grad(d_feat, d_dout, N, ld, n_out, d_grad, (double *)d_work, stream))
+    return fail(MIL_EHIP, "head gradient launch failed");
+  return MIL_OK;
+}
 
 int ppo_objective(const float *d_logits_new, const float *d_logits_old, const int32_t *d_actions,
                   const float *d_adv, const float *d_values, const float *d_returns, int32_t T,

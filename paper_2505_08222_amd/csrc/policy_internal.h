@@ -54,6 +54,7 @@ struct PolicyArgs {
   const float *params;       // FP32 master parameters
   const __bf16 *wqkv, *wo, *w1, *w2;
   float *logits;             // [A][8] or null
+  float *feat;               // [A][64] or null: the head's input (final LN of the self token)
   int32_t *actions;          // [A] or null
   int64_t n_agents;          // agents per env
   int32_t n_actions;
@@ -74,6 +75,11 @@ int launch_critic_tokens(const float *gstate, int64_t N, int M, float pos_scale,
 int launch_first_column(const float *logits, int64_t N, float *out, void *stream);
 int launch_gae(const float *rewards, const uint8_t *dones, const float *values, int32_t T, int64_t E,
                float gamma, float lambda, float *adv, float *ret, void *stream);
+// Linear-head gradient in the head's layout (weights [8][64], biases [8]):
+// grad[o][i] = sum_n dout[n * ld + o] feat[n][i], bias o = sum_n dout[n * ld + o]
+// for o < n_out, 0 for the other rows; fixed-order sums.
+int launch_head_grad(const float *feat, const float *dout, int64_t N, int ld, int n_out,
+                     float *grad, double *part, void *stream);
 int launch_ppo_objective(const float *lnew, const float *lold, const int32_t *actions,
                          const float *adv, const float *values, const float *returns, int32_t T,
                          int64_t A, int32_t n_agents, int32_t n_actions, float clip_eps,

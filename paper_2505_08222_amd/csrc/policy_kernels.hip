@@ -445,6 +445,12 @@ policy_kernel(PolicyArgs a) {
               fmaf((x[c] - mean) * inv, fp[kPolLnfG + 16 * q + c], fp[kPolLnfB + 16 * q + c]);
       }
       __syncthreads();
+      if (a.feat) {  // the head's input features of each agent, for its gradient
+        for (int e = tid; e < nag * kPolD; e += nthr) {
+          const int al = e / kPolD, d = e - al * kPolD;
+          a.feat[(ag0 + al) * kPolD + d] = sv[al][d];
+        }
+      }
       for (int e = tid >> 2; e < at * kPolActions; e += nthr >> 2) {
         const int al = e / kPolActions, k = e % kPolActions;
         const float4 *w = reinterpret_cast<const float4 *>(fp + kPolWh + k * kPolD + 16 * q);

@@ -212,6 +212,44 @@ __global__ void ppo_final_kernel(const double *__restrict__ part, int nb, double
   out[3] = s[2] * inv_s;
 }
 
+// Head gradient partials: block b sums samples [b * per, (b + 1) * per) for
+// every (output, input) pair; thread j owns pairs j, j + 256, ... of the
+// n_out * 65 entries (64 weights and the bias of each output).
+__global__ void __launch_bounds__(kPpoThreads)
+head_grad_partial_kernel(const float *__restrict__ feat, const float *__restrict__ dout, int64_t N,
+                         int ld, int n_out, int64_t per, double *__restrict__ part) {
+  const int64_t n0 = (int64_t)blockIdx.x * per;
+  const int64_t n1 = n0 + per < N ? n0 + per : N;
+  const int ne = n_out * (kPolD + 1);
+  for (int j = threadIdx.x; j < ne; j += blockDim.x) {
+    const int o = j / (kPolD + 1), i = j - o * (kPolD + 1);
+    double acc = 0.0;
+    for (int64_t n = n0; n < n1; ++n) {
+      const float g = dout[n * ld + o];
+      acc += (double)(i < kPolD ? g * feat[n * kPolD + i] : g);
+    }
+    part[(int64_t)blockIdx.x * ne + j] = acc;
+  }
+}
+
+// Partials in block order -> grad in the head's parameter layout: weights
+// [8][64], then biases [8]; rows n_out..7 are 0.
+__global__ void __launch_bounds__(kPpoThreads)
+head_grad_final_kernel(const double *__restrict__ part, int nb, int n_out,
+                       float *__restrict__ grad) {
+  const int ne = n_out * (kPolD + 1);
+  for (int j = threadIdx.x; j < kPolActions * (kPolD + 1); j += blockDim.x) {
+    const int o = j / (kPolD + 1), i = j - o * (kPolD + 1);
+    double s = 0.0;
+    if (j < ne)
+      for (int b = 0; b < nb; ++b) s += part[(int64_t)b * ne + j];
+    if (i < kPolD)
+      grad[o * kPolD + i] = (float)s;
+    else
+      grad[kPolActions * kPolD + o] = (float)s;
+  }
+}
+
 int check() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 }  // namespace
@@ -230,6 +268,21 @@ int launch_first_column(const float *logits, int64_t N, float *out, void *stream
   if (N == 0) return 0;
   hipLaunchKernelGGL(first_column_kernel, dim3((unsigned)((N + kPpoThreads - 1) / kPpoThreads)),
                      dim3(kPpoThreads), 0, (hipStream_t)stream, logits, N, out);
+  return check();
+}
+
+int launch_head_grad(const float *feat, const float *dout, int64_t N, int ld, int n_out,
+                     float *grad, double *part, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  if (N > 0) {
+    const int64_t per = (N + kPpoBlocks - 1) / kPpoBlocks;
+    hipLaunchKernelGGL(head_grad_partial_kernel, dim3(kPpoBlocks), dim3(kPpoThreads), 0, st, feat,
+                       dout, N, ld, n_out, per, part);
+    if (check()) return -1;
+  }
+  // no samples: no partials, a zero gradient
+  hipLaunchKernelGGL(head_grad_final_kernel, dim3(1), dim3(kPpoThreads), 0, st, part,
+                     N > 0 ? kPpoBlocks : 0, n_out, grad);
   return check();
 }
 

@@ -1,7 +1,8 @@
-"""The learner's forward half (argument marshalling only): critic values of
-global states, generalised advantage estimation and the clipped PPO
-objective (MAPPO, Sec. III-B; TransformerCritic, Sec. IV-B-1). Every step
-runs in the HIP library."""
+"""The learner (argument marshalling only): critic values of global states,
+generalised advantage estimation, the clipped PPO objective, and the
+gradient and Adam update of the policy's and critic's output heads (MAPPO,
+Sec. III-B; TransformerCritic, Sec. IV-B-1). Every step runs in the HIP
+library; the transformers below the heads are not trained here."""
 import ctypes as C
 
 import torch
@@ -15,7 +16,7 @@ def _l():
         V, I32, I64, F = C.c_void_p, C.c_int32, C.c_int64, C.c_float
         L.critic_workspace_bytes.argtypes = [I64, I32, I32]
         L.critic_workspace_bytes.restype = I64
-        L.critic_forward.argtypes = [V, I64, I32, I32, F, V, V, V, I64, V]
+        L.critic_forward.argtypes = [V, I64, I32, I32, F, V, V, V, V, I64, V]
         L.critic_forward.restype = C.c_int
         L.ppo_gae.argtypes = [V, V, V, I32, I64, F, F, V, V, V]
         L.ppo_gae.restype = C.c_int
@@ -23,6 +24,11 @@ def _l():
         L.ppo_workspace_bytes.restype = I64
         L.ppo_objective.argtypes = [V, V, V, V, V, V, I32, I64, I32, I32, F, V, V, V, V, I64, V]
         L.ppo_objective.restype = C.c_int
+        L.head_grad.argtypes = [I64, V, V, I32, I32, V, V, I64, V]
+        L.head_grad.restype = C.c_int
+        L.policy_forward_feat.argtypes = [I64, I32, I32, I32, V, V, V, V, V, V, C.c_uint64,
+                                          C.c_uint32, C.c_uint32, V, I64, V]
+        L.policy_forward_feat.restype = C.c_int
         L._ppo_registered = True
     return L
 
@@ -31,9 +37,13 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def critic_forward(gstate, n_agents: int, n_targets: int, params, pos_scale: float = 1000.0):
+HEAD_PARAMS = 8 * 64 + 8  # the head: the last floats of the parameter vector
+
+
+def critic_forward(gstate, n_agents: int, n_targets: int, params, pos_scale: float = 1000.0,
+                   features: bool = False):
     """gstate [N, n_agents + n_targets, 6] (or the rollout's [T, E*M, 6]) ->
-    values [N]."""
+    values [N] (and the head's input features [N, 64] with features=True)."""
     M = n_agents + n_targets
     g = gstate.reshape(-1, M, 6).contiguous()
     N = g.shape[0]
@@ -42,9 +52,37 @@ def critic_forward(gstate, n_agents: int, n_targets: int, params, pos_scale: flo
     buf = torch.empty(n + 256, dtype=torch.uint8, device=g.device)
     w = (buf.data_ptr() + 255) & ~255
     out = torch.empty(N, dtype=torch.float32, device=g.device)
+    feat = torch.empty((N, 64), dtype=torch.float32, device=g.device) if features else None
     check(L.critic_forward(ptr(g), N, n_agents, n_targets, pos_scale, ptr(params), ptr(out),
-                           C.c_void_p(w), n, _stream()))
-    return out
+                           ptr(feat), C.c_void_p(w), n, _stream()))
+    return (out, feat) if features else out
+
+
+def policy_features(obs, mask, params, n_tok: int, n_agents: int, n_actions: int = 5):
+    """obs [A * n_tok, 6], mask [A * n_tok] -> (logits [A, 8], features [A, 64])."""
+    from .policy import _work
+    A = obs.shape[0] // n_tok
+    logits = torch.empty((A, 8), dtype=torch.float32, device=obs.device)
+    feat = torch.empty((A, 64), dtype=torch.float32, device=obs.device)
+    buf, w, n = _work(A, A * n_tok, obs.device)
+    check(_l().policy_forward_feat(A, n_tok, n_agents, n_actions, ptr(obs.contiguous()),
+                                   ptr(mask.contiguous()), ptr(params), ptr(logits), None,
+                                   ptr(feat), C.c_uint64(0), 0, 0, w, n, _stream()))
+    del buf
+    return logits, feat
+
+
+def head_grad(feat, dout, n_out: int):
+    """feat [N, 64], dout [N, ld] (or [N] for one output) -> the head's
+    gradient [520] (Wh [8, 64], bh [8])."""
+    N = feat.shape[0]
+    d = (dout.reshape(N, 1) if dout.dim() == 1 else dout.reshape(N, dout.shape[-1])).contiguous()
+    L = _l()
+    work = torch.empty(L.ppo_workspace_bytes(), dtype=torch.uint8, device=feat.device)
+    g = torch.empty(HEAD_PARAMS, dtype=torch.float32, device=feat.device)
+    check(L.head_grad(N, ptr(feat.contiguous()), ptr(d), d.shape[1], n_out, ptr(g), ptr(work),
+                      work.numel(), _stream()))
+    return g
 
 
 def gae(rewards, dones, values, gamma: float, lam: float):
@@ -73,3 +111,21 @@ def objective(logits_new, logits_old, actions, adv, values, returns, n_agents: i
                           ptr(returns.contiguous()), T, A, n_agents, n_actions, clip_eps, ptr(out),
                           ptr(dl), ptr(dv), ptr(work), work.numel(), _stream()))
     return out, dl, dv
+
+
+class HeadAdam:
+    """Adam state of one network's output head (the last HEAD_PARAMS floats
+    of its parameter vector); step() updates them in place on the device."""
+
+    def __init__(self, params, lr=3e-4, betas=(0.9, 0.999), eps=1e-8):
+        self.params = params
+        self.head = params[params.numel() - HEAD_PARAMS:]
+        self.m = torch.zeros_like(self.head)
+        self.v = torch.zeros_like(self.head)
+        self.lr, (self.b1, self.b2), self.eps = float(lr), betas, float(eps)
+        self.step_count = 0
+
+    def step(self, grad):
+        self.step_count += 1
+        check(lib().mlp_adam_step(HEAD_PARAMS, ptr(self.head), ptr(grad), ptr(self.m), ptr(self.v),
+                                  self.lr, self.b1, self.b2, self.eps, self.step_count, _stream()))

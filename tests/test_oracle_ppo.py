@@ -1,7 +1,8 @@
 """Pins of the learner oracle (oracle/ppo_oracle.py): GAE special cases with
 closed forms, done handling, the clipped surrogate's values and its
-gradient against torch's float64 autograd, entropy limits, and the critic's
-token layout."""
+gradient against torch's float64 autograd, entropy limits, the critic's
+token layout, and the head gradient against finite differences of the
+loss it feeds."""
 import math
 
 import numpy as np
@@ -113,3 +114,54 @@ def test_critic_token_layout():
     np.testing.assert_allclose(tok[0, 0], 0.0)
     np.testing.assert_allclose(tok[0, 1], [0.1, -0.05, 0.0, 1.0, 1.0, 0.0], atol=1e-15)
     np.testing.assert_allclose(tok[0, 2], [0.3, 0.02, 0.5, 0.0, 0.0, 1.0], atol=1e-15)
+
+
+def test_head_grad_matches_finite_differences():
+    # a loss through the head: the PPO surrogate of logits W f + b; central
+    # differences in each weight and bias against the analytic gradient
+    rng = np.random.default_rng(7)
+    T, A, na, n_agents = 2, 6, 5, 3
+    feat = rng.normal(size=(T * A, 64))
+    W = rng.normal(scale=0.2, size=(8, 64))
+    b = rng.normal(scale=0.1, size=8)
+    lo = rng.normal(size=(T, A, 8))
+    act = rng.integers(0, na, size=(T, A))
+    adv = rng.normal(size=(T, A // n_agents))
+    v = R = np.zeros((T, A // n_agents))
+
+    def loss(W_, b_):
+        z = (feat @ W_.T + b_).reshape(T, A, 8)
+        return po.ppo_objective(z, lo, act, adv, v, R, n_agents, na, 10.0)["policy_loss"]
+
+    z = (feat @ W.T + b).reshape(T, A, 8)
+    dl = po.ppo_objective(z, lo, act, adv, v, R, n_agents, na, 10.0)["dlogits"]
+    dW, db = po.head_grad(feat, dl.reshape(T * A, na), na)
+    assert (dW[na:] == 0).all() and (db[na:] == 0).all()
+    h = 1e-6
+    for k, d in ((0, 0), (2, 17), (4, 63), (1, 40)):
+        Wp, Wm = W.copy(), W.copy()
+        Wp[k, d] += h
+        Wm[k, d] -= h
+        assert dW[k, d] == pytest.approx((loss(Wp, b) - loss(Wm, b)) / (2 * h), abs=1e-8)
+    for k in range(na):
+        bp, bm = b.copy(), b.copy()
+        bp[k] += h
+        bm[k] -= h
+        assert db[k] == pytest.approx((loss(W, bp) - loss(W, bm)) / (2 * h), abs=1e-8)
+    # the head's rows past the actions carry no loss
+    Wp = W.copy()
+    Wp[6] += 1.0
+    assert loss(Wp, b) == loss(W, b)
+
+
+def test_head_grad_of_value_head():
+    # value loss mean (w . f + c - R)^2: gradient 2 / N sum (V - R) f
+    rng = np.random.default_rng(2)
+    f = rng.normal(size=(9, 64))
+    w = rng.normal(size=64)
+    R = rng.normal(size=9)
+    V = f @ w + 0.3
+    dW, db = po.head_grad(f, (2.0 * (V - R) / 9)[:, None], 1)
+    np.testing.assert_allclose(dW[0], 2.0 / 9 * ((V - R)[:, None] * f).sum(0), atol=1e-12)
+    assert db[0] == pytest.approx(2.0 / 9 * (V - R).sum())
+    assert not dW[1:].any() and not db[1:].any()
