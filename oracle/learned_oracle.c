@@ -288,95 +288,132 @@ static void layer_norm(const double *x, const double *g, const double *b, double
   for (int i = 0; i < PD; ++i) y[i] = (x[i] - m) * inv * g[i] + b[i];
 }
 
-/* tokens [A][n_tok][6], mask [A][n_tok] -> logits [A][PA] */
-void orc_policy_forward(int64_t A, int n_tok, const double *tokens, const uint8_t *mask,
-                        const double *th, double *logits) {
-  enum { MAXT = 32 };
-  double h[MAXT][PD], a[MAXT][PD], q[MAXT][3 * PD], o[MAXT][PD], f[PF];
-  for (int64_t ag = 0; ag < A; ++ag) {
-    const double *x = tokens + ag * n_tok * 6;
-    const uint8_t *mk = mask + ag * n_tok;
-    const double *p = th;
-    const double *E = p; p += PD * 6;
-    const double *e = p; p += PD;
+enum { P_MAXT = 32 };
+
+/* The trunk and head on rows already in the residual stream: h[0..n_tok-1]
+ * (modified in place), key mask mk; logits = Wh LN_f(h_0) + bh, and
+ * feat = LN_f(h_0) when feat is not NULL. th points at the first layer's
+ * parameters. */
+static void policy_trunk(int n_tok, double h[][PD], const uint8_t *mk, const double *th,
+                         double *logits, double *feat) {
+  double a[P_MAXT][PD], q[P_MAXT][3 * PD], o[P_MAXT][PD], f[PF];
+  const double *p = th;
+  for (int l = 0; l < PL; ++l) {
+    const double *g1 = p; p += PD;
+    const double *b1n = p; p += PD;
+    const double *Wqkv = p; p += 3 * PD * PD;
+    const double *bqkv = p; p += 3 * PD;
+    const double *Wo = p; p += PD * PD;
+    const double *bo = p; p += PD;
+    const double *g2 = p; p += PD;
+    const double *b2n = p; p += PD;
+    const double *W1 = p; p += PF * PD;
+    const double *b1 = p; p += PF;
+    const double *W2 = p; p += PD * PF;
+    const double *b2 = p; p += PD;
+    for (int t = 0; t < n_tok; ++t) layer_norm(h[t], g1, b1n, a[t]);
+    for (int t = 0; t < n_tok; ++t)
+      for (int r = 0; r < 3 * PD; ++r) {
+        double acc = bqkv[r];
+        for (int i = 0; i < PD; ++i) acc += Wqkv[r * PD + i] * a[t][i];
+        q[t][r] = acc;
+      }
+    for (int hd = 0; hd < PH; ++hd)
+      for (int t = 0; t < n_tok; ++t) {
+        double s[P_MAXT], mx = -INFINITY;
+        for (int u = 0; u < n_tok; ++u) {
+          if (!mk[u]) { s[u] = -INFINITY; continue; }
+          double acc = 0.0;
+          for (int c = 0; c < PDH; ++c) acc += q[t][hd * PDH + c] * q[u][PD + hd * PDH + c];
+          s[u] = acc / 4.0; /* sqrt(16) */
+          if (s[u] > mx) mx = s[u];
+        }
+        double z = 0.0;
+        for (int u = 0; u < n_tok; ++u) {
+          s[u] = mk[u] ? exp(s[u] - mx) : 0.0;
+          z += s[u];
+        }
+        for (int c = 0; c < PDH; ++c) {
+          double acc = 0.0;
+          for (int u = 0; u < n_tok; ++u) acc += s[u] * q[u][2 * PD + hd * PDH + c];
+          o[t][hd * PDH + c] = acc / z;
+        }
+      }
     for (int t = 0; t < n_tok; ++t)
       for (int d = 0; d < PD; ++d) {
-        double acc = e[d];
-        for (int c = 0; c < 6; ++c) acc += E[d * 6 + c] * x[t * 6 + c];
-        h[t][d] = acc;
+        double acc = bo[d];
+        for (int i = 0; i < PD; ++i) acc += Wo[d * PD + i] * o[t][i];
+        h[t][d] += acc;
       }
-    for (int l = 0; l < PL; ++l) {
-      const double *g1 = p; p += PD;
-      const double *b1n = p; p += PD;
-      const double *Wqkv = p; p += 3 * PD * PD;
-      const double *bqkv = p; p += 3 * PD;
-      const double *Wo = p; p += PD * PD;
-      const double *bo = p; p += PD;
-      const double *g2 = p; p += PD;
-      const double *b2n = p; p += PD;
-      const double *W1 = p; p += PF * PD;
-      const double *b1 = p; p += PF;
-      const double *W2 = p; p += PD * PF;
-      const double *b2 = p; p += PD;
-      for (int t = 0; t < n_tok; ++t) layer_norm(h[t], g1, b1n, a[t]);
-      for (int t = 0; t < n_tok; ++t)
-        for (int r = 0; r < 3 * PD; ++r) {
-          double acc = bqkv[r];
-          for (int i = 0; i < PD; ++i) acc += Wqkv[r * PD + i] * a[t][i];
-          q[t][r] = acc;
-        }
-      for (int hd = 0; hd < PH; ++hd)
-        for (int t = 0; t < n_tok; ++t) {
-          double s[MAXT], mx = -INFINITY;
-          for (int u = 0; u < n_tok; ++u) {
-            if (!mk[u]) { s[u] = -INFINITY; continue; }
-            double acc = 0.0;
-            for (int c = 0; c < PDH; ++c) acc += q[t][hd * PDH + c] * q[u][PD + hd * PDH + c];
-            s[u] = acc / 4.0; /* sqrt(16) */
-            if (s[u] > mx) mx = s[u];
-          }
-          double z = 0.0;
-          for (int u = 0; u < n_tok; ++u) {
-            s[u] = mk[u] ? exp(s[u] - mx) : 0.0;
-            z += s[u];
-          }
-          for (int c = 0; c < PDH; ++c) {
-            double acc = 0.0;
-            for (int u = 0; u < n_tok; ++u) acc += s[u] * q[u][2 * PD + hd * PDH + c];
-            o[t][hd * PDH + c] = acc / z;
-          }
-        }
-      for (int t = 0; t < n_tok; ++t)
-        for (int d = 0; d < PD; ++d) {
-          double acc = bo[d];
-          for (int i = 0; i < PD; ++i) acc += Wo[d * PD + i] * o[t][i];
-          h[t][d] += acc;
-        }
-      for (int t = 0; t < n_tok; ++t) {
-        layer_norm(h[t], g2, b2n, a[t]);
-        for (int r = 0; r < PF; ++r) {
-          double acc = b1[r];
-          for (int i = 0; i < PD; ++i) acc += W1[r * PD + i] * a[t][i];
-          f[r] = gelu(acc);
-        }
-        for (int d = 0; d < PD; ++d) {
-          double acc = b2[d];
-          for (int r = 0; r < PF; ++r) acc += W2[d * PF + r] * f[r];
-          h[t][d] += acc;
-        }
+    for (int t = 0; t < n_tok; ++t) {
+      layer_norm(h[t], g2, b2n, a[t]);
+      for (int r = 0; r < PF; ++r) {
+        double acc = b1[r];
+        for (int i = 0; i < PD; ++i) acc += W1[r * PD + i] * a[t][i];
+        f[r] = gelu(acc);
+      }
+      for (int d = 0; d < PD; ++d) {
+        double acc = b2[d];
+        for (int r = 0; r < PF; ++r) acc += W2[d * PF + r] * f[r];
+        h[t][d] += acc;
       }
     }
-    const double *gf = p; p += PD;
-    const double *bf = p; p += PD;
-    const double *Wh = p; p += PA * PD;
-    const double *bh = p; p += PA;
-    double s0[PD];
-    layer_norm(h[0], gf, bf, s0);
-    for (int k = 0; k < PA; ++k) {
-      double acc = bh[k];
-      for (int i = 0; i < PD; ++i) acc += Wh[k * PD + i] * s0[i];
-      logits[ag * PA + k] = acc;
+  }
+  const double *gf = p; p += PD;
+  const double *bf = p; p += PD;
+  const double *Wh = p; p += PA * PD;
+  const double *bh = p; p += PA;
+  double s0[PD];
+  layer_norm(h[0], gf, bf, s0);
+  for (int k = 0; k < PA; ++k) {
+    double acc = bh[k];
+    for (int i = 0; i < PD; ++i) acc += Wh[k * PD + i] * s0[i];
+    logits[k] = acc;
+  }
+  if (feat)
+    for (int i = 0; i < PD; ++i) feat[i] = s0[i];
+}
+
+/* Embedding of one token: E x + e. */
+static void policy_embed(const double *th, const double *x, double *h) {
+  const double *E = th, *e = th + PD * 6;
+  for (int d = 0; d < PD; ++d) {
+    double acc = e[d];
+    for (int c = 0; c < 6; ++c) acc += E[d * 6 + c] * x[c];
+    h[d] = acc;
+  }
+}
+
+/* tokens [A][n_tok][6], mask [A][n_tok] -> logits [A][PA]; the head reads
+ * the first token. */
+void orc_policy_forward(int64_t A, int n_tok, const double *tokens, const uint8_t *mask,
+                        const double *th, double *logits) {
+  double h[P_MAXT][PD];
+  for (int64_t ag = 0; ag < A; ++ag) {
+    for (int t = 0; t < n_tok; ++t) policy_embed(th, tokens + (ag * n_tok + t) * 6, h[t]);
+    policy_trunk(n_tok, h, mask + ag * n_tok, th + PD * 6 + PD, logits + ag * PA, NULL);
+  }
+}
+
+/* The recurrent form (TransfMAPPO, Fig. 3): a carried 64-wide state enters
+ * the residual stream as an extra first row, ahead of the n_obs embedded
+ * tokens, and is never masked; the head reads that row, and its final
+ * LayerNorm is the next state. tokens [A][n_obs][6], mask [A][n_obs],
+ * hidden_in [A][64] (NULL: zeros, the start of an episode) -> logits [A][PA],
+ * hidden_out [A][64] (may alias hidden_in). */
+void orc_policy_forward_rec(int64_t A, int n_obs, const double *tokens, const uint8_t *mask,
+                            const double *hidden_in, const double *th, double *logits,
+                            double *hidden_out) {
+  double h[P_MAXT][PD];
+  uint8_t mk[P_MAXT];
+  for (int64_t ag = 0; ag < A; ++ag) {
+    for (int d = 0; d < PD; ++d) h[0][d] = hidden_in ? hidden_in[ag * PD + d] : 0.0;
+    mk[0] = 1;
+    for (int t = 0; t < n_obs; ++t) {
+      policy_embed(th, tokens + (ag * n_obs + t) * 6, h[1 + t]);
+      mk[1 + t] = mask[ag * n_obs + t];
     }
+    policy_trunk(1 + n_obs, h, mk, th + PD * 6 + PD, logits + ag * PA, hidden_out + ag * PD);
   }
 }
 

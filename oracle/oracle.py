@@ -116,6 +116,8 @@ def _register_learned(L):
     if hasattr(L, "orc_policy_forward"):
         L.orc_policy_num_params.restype = I64
         L.orc_policy_forward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D)]
+        L.orc_policy_forward_rec.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D),
+                                             P(D)]
         L.orc_policy_sample.argtypes = [P(D), C.c_int, D]
         L.orc_policy_sample.restype = C.c_int
 
@@ -439,6 +441,23 @@ def policy_forward(tokens, mask, params):
     lib().orc_policy_forward(A, n_tok, _p(tokens, C.c_double), _p(mask, C.c_uint8),
                              _p(params, C.c_double), _p(out, C.c_double))
     return out
+
+
+def policy_forward_rec(tokens, mask, hidden, params):
+    """The recurrent form: tokens [A, n_obs, 6], mask [A, n_obs], hidden
+    [A, 64] or None (zeros) -> (logits [A, 8], next hidden [A, 64])."""
+    tokens = np.ascontiguousarray(tokens, np.float64)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    params = np.ascontiguousarray(params, np.float64)
+    A, n_obs, _ = tokens.shape
+    hin = None if hidden is None else np.ascontiguousarray(hidden, np.float64)
+    out = np.zeros((A, 8))
+    hout = np.zeros((A, 64))
+    lib().orc_policy_forward_rec(A, n_obs, _p(tokens, C.c_double), _p(mask, C.c_uint8),
+                                 None if hin is None else _p(hin, C.c_double),
+                                 _p(params, C.c_double), _p(out, C.c_double),
+                                 _p(hout, C.c_double))
+    return out, hout
 
 
 def policy_sample(logits, n, u) -> int:

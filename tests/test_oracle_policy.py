@@ -1,7 +1,10 @@
 """Pins of the attention-policy oracle (CPU only): the forward pass against
 torch's float64 layers (layer_norm, linear, softmax attention with key
 masking, tanh GELU), permutation invariance over the non-self tokens (the
-property Sec. IV-B-1 builds on), and the inverse-CDF sampler."""
+property Sec. IV-B-1 builds on), the inverse-CDF sampler, and the recurrent
+form of Fig. 3 (a carried state as an extra first row): against torch, its
+reduction to the plain form when the state is an embedded token, the head
+on the returned state, and invariance to any order of the tokens."""
 import numpy as np
 import pytest
 
@@ -16,7 +19,7 @@ def _params(orc, seed=0):
     return p
 
 
-def _torch_policy(tokens, mask, th):
+def _torch_policy(tokens, mask, th, hidden=None):
     t = torch.from_numpy(th)
     o = 0
 
@@ -30,7 +33,10 @@ def _torch_policy(tokens, mask, th):
     x = torch.from_numpy(tokens)
     m = torch.from_numpy(mask.astype(bool))
     h = x @ E.T + e
-    A, T = x.shape[0], x.shape[1]
+    if hidden is not None:  # the recurrent row ahead of the embedded tokens, never masked
+        h = torch.cat([torch.from_numpy(hidden)[:, None], h], 1)
+        m = torch.cat([torch.ones_like(m[:, :1]), m], 1)
+    A, T = h.shape[0], h.shape[1]
     for _ in range(L):
         g1, b1n = take(D), take(D)
         Wqkv, bqkv = take(3 * D, D), take(3 * D)
@@ -114,3 +120,57 @@ def test_sampler_inverse_cdf(orc):
     rng = np.random.default_rng(0)
     draws = [orc.policy_sample(lg, 5, u) for u in rng.random(20000)]
     assert stats.chisquare(np.bincount(draws, minlength=5), 20000 * p).pvalue > 1e-3
+
+
+def test_recurrent_form_matches_torch(orc):
+    th = _params(orc, 5)
+    x, mask = _tokens(7, 3, 2, seed=8)
+    rng = np.random.default_rng(3)
+    hid = rng.normal(0, 1.0, (7, D))
+    lg, hout = orc.policy_forward_rec(x, mask, hid, th)
+    np.testing.assert_allclose(lg, _torch_policy(x, mask, th, hid), atol=1e-10)
+    # no state: zeros
+    lz, _ = orc.policy_forward_rec(x, mask, None, th)
+    np.testing.assert_allclose(lz, _torch_policy(x, mask, th, np.zeros((7, D))), atol=1e-10)
+
+
+def test_recurrent_form_reduces_to_plain_form(orc):
+    # a carried state equal to the embedding of a token x0 is that token put first
+    th = _params(orc, 6)
+    x, mask = _tokens(5, 2, 3, seed=9)
+    x0 = np.random.default_rng(4).normal(0, 1.0, (5, 6))
+    E, e = th[:D * 6].reshape(D, 6), th[D * 6:D * 7]
+    lg, _ = orc.policy_forward_rec(x, mask, x0 @ E.T + e, th)
+    full = np.concatenate([x0[:, None], x], 1)
+    fm = np.concatenate([np.ones((5, 1), np.uint8), mask], 1)
+    np.testing.assert_allclose(lg, orc.policy_forward(full, fm, th), atol=1e-12)
+
+
+def test_recurrent_state_is_the_heads_input(orc):
+    th = _params(orc, 7)
+    x, mask = _tokens(4, 2, 2, seed=10)
+    hid = np.random.default_rng(5).normal(0, 1.0, (4, D))
+    lg, hout = orc.policy_forward_rec(x, mask, hid, th)
+    n = th.size
+    Wh, bh = th[n - NA * D - NA:n - NA].reshape(NA, D), th[n - NA:]
+    np.testing.assert_allclose(lg, hout @ Wh.T + bh, atol=1e-12)
+    # the state is a final LayerNorm output: (s - beta) / gamma has mean 0, variance ~1
+    gf, bf = th[n - NA * D - NA - 2 * D:n - NA * D - NA - D], th[n - NA * D - NA - D:n - NA * D - NA]
+    z = (hout - bf) / gf
+    np.testing.assert_allclose(z.mean(1), 0.0, atol=1e-10)
+    assert np.all(np.abs(z.var(1) - 1.0) < 1e-3)
+    # two steps: the second sees the first's state
+    lg2, h2 = orc.policy_forward_rec(x, mask, hout, th)
+    np.testing.assert_allclose(lg2, _torch_policy(x, mask, th, hout), atol=1e-10)
+    assert np.abs(h2 - hout).max() > 1e-3
+
+
+def test_recurrent_form_ignores_token_order(orc):
+    th = _params(orc, 8)
+    x, mask = _tokens(3, 3, 3, seed=11)
+    hid = np.random.default_rng(6).normal(0, 1.0, (3, D))
+    lg, hout = orc.policy_forward_rec(x, mask, hid, th)
+    perm = np.random.default_rng(7).permutation(x.shape[1])
+    lp, hp = orc.policy_forward_rec(x[:, perm], mask[:, perm], hid, th)
+    np.testing.assert_allclose(lp, lg, atol=1e-12)
+    np.testing.assert_allclose(hp, hout, atol=1e-12)
