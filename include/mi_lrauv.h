@@ -454,6 +454,22 @@ int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_ac
                         float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
                         uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
                         void *stream);
+/* The recurrent form of the actor (TransfMAPPO, Fig. 3: an extra recurrent
+ * embedding is transformed with the entity tokens and the action head reads
+ * its output). A carried state d_hidden_in [A][64] (NULL: zeros, an
+ * episode's start) enters each agent's residual stream as an unmasked first
+ * row, not embedded, ahead of its n_obs <= 15 tokens (d_obs [A * n_obs][6],
+ * d_mask [A * n_obs]); the head reads that row's final LayerNorm, which is
+ * also written to d_hidden_out [A][64], the next step's state (may equal
+ * d_hidden_in: each agent's row is read before it is written). Logits,
+ * actions, draws, parameters and workspace as for policy_forward with
+ * n_tok = n_obs + 1. Errors: MIL_EINVAL (sizes, null d_hidden_out),
+ * MIL_ESHAPE, MIL_EALIGN, MIL_EHIP. */
+int policy_forward_rec(int64_t A, int32_t n_obs, int32_t n_agents, int32_t n_actions,
+                       const float *d_obs, const uint8_t *d_mask, const float *d_hidden_in,
+                       const float *d_params, float *d_logits, int32_t *d_actions,
+                       float *d_hidden_out, uint64_t seed, uint32_t t, uint32_t episode,
+                       void *d_work, int64_t work_bytes, void *stream);
 /* Workspace for env_policy_rollout on this bound batch (256-byte aligned):
  * the policy's, plus (learned != 0) every tracker's window, sigma, estimate
  * and flag and the learned estimator's own workspace. -1 on a bad handle. */
@@ -470,22 +486,26 @@ int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned);
  * exact fallback); then the step
  * takes those estimates (for trackers whose window is full; shorter windows keep
  * the exact estimator) and computes reward and observation. Needs window <= 21.
+ * d_hidden [A][64] (may be NULL): when given, the actor runs in its recurrent
+ * form (policy_forward_rec) with the carried state kept there: zeros at the
+ * reset, each step's state written over the last (the final one is left
+ * there); n_agents + n_targets + 1 <= 16.
  * Errors: MIL_EINVAL (ragged batch, too many tokens or actions, bad T/episode,
  * window too long for the learned estimator), MIL_ESHAPE (workspace smaller
  * than env_policy_workspace_bytes), MIL_EALIGN, MIL_EHIP. */
 int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
-                       const float *d_mlp_params, float k_sigma, const mil_env_outputs *outs,
-                       double *d_metrics, int32_t capture, void *d_work, int64_t work_bytes,
-                       void *stream);
+                       const float *d_mlp_params, float k_sigma, float *d_hidden,
+                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
+                       void *d_work, int64_t work_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * The learner's forward half (Sec. III-B: MAPPO updates the actors with the
  * PPO clipped surrogate objective and one centralised critic V(S) estimates
  * the value of the global state; Sec. IV-B-1, Fig. 3: the TransformerCritic
  * reads the full global state as entity tokens plus one embedding token whose
- * transformed output gives V), and the gradient of the two output heads. The
- * backward pass through the transformers below the heads is not part of this
- * library.
+ * transformed output gives V; plain, or with that token recurrent), and the
+ * gradient of the two output heads. The backward pass through the
+ * transformers below the heads is not part of this library.
  * ------------------------------------------------------------------------- */
 /* Workspace for critic_forward (256-byte aligned); -1 on bad sizes. */
 int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
@@ -503,6 +523,21 @@ int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
 int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
                    float pos_scale, const float *d_params, float *d_values, float *d_feat,
                    void *d_work, int64_t work_bytes, void *stream);
+/* The recurrent critic (Fig. 3: the TransformerCritic keeps a recurrent
+ * embedding from which V is read) over T steps of N envs in order: at step t
+ * the state carried from step t - 1 (d_hidden_in [N][64] at t = 0, NULL:
+ * zeros) is the unmasked first row ahead of the n_agents + n_targets entity
+ * tokens of d_gstate[t] ([T][N][n_agents + n_targets][6], tokens as for
+ * critic_forward, no all-zero token); V_t = d_values[t] ([T][N]) is the
+ * head's first output on that row's final LayerNorm, which is the next
+ * state: d_hidden_seq [T][N][64] receives every step's (the head's inputs
+ * for head_grad; the last is the state after the last step). Workspace
+ * critic_workspace_bytes(N, ...) (one step's tokens). Errors as for
+ * critic_forward. */
+int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_agents,
+                       int32_t n_targets, float pos_scale, const float *d_params,
+                       const float *d_hidden_in, float *d_values, float *d_hidden_seq,
+                       void *d_work, int64_t work_bytes, void *stream);
 /* Generalised advantage estimation (Schulman et al. 2016; the advantage
  * estimator of MAPPO) over T steps of E envs with the env's shared reward:
  * d_rewards [T][E], d_dones [T][E] (1: the step ends its episode, nothing is

@@ -989,28 +989,17 @@ int policy_init(float *d_params, uint64_t seed, void *stream) {
   return MIL_OK;
 }
 
-int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
-                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
-                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
-                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
-                        void *stream);
-
-int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions, const float *d_obs,
-                   const uint8_t *d_mask, const float *d_params, float *d_logits,
-                   int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
-                   int64_t work_bytes, void *stream) {
-  return policy_forward_feat(A, n_tok, n_agents, n_actions, d_obs, d_mask, d_params, d_logits,
-                             d_actions, nullptr, seed, t, episode, d_work, work_bytes, stream);
-}
-
-int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
-                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
-                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
-                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
-                        void *stream) {
-  if (A < 0 || n_tok < 1 || n_tok > mil::kPolMaxTok || n_agents < 1 || n_actions < 1 ||
+// One policy launch on caller tokens: n_tok rows per agent, the first the
+// carried state when rec = 1 (then obs holds n_tok - 1 tokens per agent).
+static int policy_run(int64_t A, int32_t n_tok, int rec, int32_t n_agents, int32_t n_actions,
+                      const float *d_obs, const uint8_t *d_mask, const float *d_hidden_in,
+                      const float *d_params, float *d_logits, int32_t *d_actions, float *d_feat,
+                      uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
+                      int64_t work_bytes, void *stream) {
+  if (A < 0 || n_tok < 1 + rec || n_tok > mil::kPolMaxTok || n_agents < 1 || n_actions < 1 ||
       n_actions > mil::kPolActions || (A % n_agents) != 0)
-    return fail(MIL_EINVAL, "need n_tok in 1..16, n_actions in 1..8, A a multiple of n_agents");
+    return fail(MIL_EINVAL, rec ? "need n_obs in 1..15, n_actions in 1..8, A a multiple of n_agents"
+                                : "need n_tok in 1..16, n_actions in 1..8, A a multiple of n_agents");
   if (A == 0) return MIL_OK;
   if (!d_obs || !d_mask || !d_params) return fail(MIL_EINVAL, "null argument");
   const PolicyWork w = policy_work(A, A * n_tok);
@@ -1032,6 +1021,8 @@ int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_ac
   a.logits = d_logits;
   a.actions = d_actions;
   a.feat = d_feat;
+  a.hidden_in = d_hidden_in;
+  a.rec = rec;
   a.n_agents = n_agents;
   a.n_actions = n_actions;
   a.t = t;
@@ -1041,6 +1032,36 @@ int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_ac
   a.env_ids = nullptr;
   if (mil::launch_policy(a, num_cus_env(), stream)) return fail(MIL_EHIP, "policy launch failed");
   return MIL_OK;
+}
+
+int policy_forward(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions, const float *d_obs,
+                   const uint8_t *d_mask, const float *d_params, float *d_logits,
+                   int32_t *d_actions, uint64_t seed, uint32_t t, uint32_t episode, void *d_work,
+                   int64_t work_bytes, void *stream) {
+  return policy_run(A, n_tok, 0, n_agents, n_actions, d_obs, d_mask, nullptr, d_params, d_logits,
+                    d_actions, nullptr, seed, t, episode, d_work, work_bytes, stream);
+}
+
+int policy_forward_feat(int64_t A, int32_t n_tok, int32_t n_agents, int32_t n_actions,
+                        const float *d_obs, const uint8_t *d_mask, const float *d_params,
+                        float *d_logits, int32_t *d_actions, float *d_feat, uint64_t seed,
+                        uint32_t t, uint32_t episode, void *d_work, int64_t work_bytes,
+                        void *stream) {
+  return policy_run(A, n_tok, 0, n_agents, n_actions, d_obs, d_mask, nullptr, d_params, d_logits,
+                    d_actions, d_feat, seed, t, episode, d_work, work_bytes, stream);
+}
+
+int policy_forward_rec(int64_t A, int32_t n_obs, int32_t n_agents, int32_t n_actions,
+                       const float *d_obs, const uint8_t *d_mask, const float *d_hidden_in,
+                       const float *d_params, float *d_logits, int32_t *d_actions,
+                       float *d_hidden_out, uint64_t seed, uint32_t t, uint32_t episode,
+                       void *d_work, int64_t work_bytes, void *stream) {
+  if (A > 0 && !d_hidden_out) return fail(MIL_EINVAL, "null argument");
+  if (n_obs < 1 || n_obs > mil::kPolMaxTok - 1)
+    return fail(MIL_EINVAL, "need n_obs in 1..15 (the carried state takes one more row)");
+  return policy_run(A, n_obs + 1, 1, n_agents, n_actions, d_obs, d_mask, d_hidden_in, d_params,
+                    d_logits, d_actions, d_hidden_out, seed, t, episode, d_work, work_bytes,
+                    stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,7 +1096,7 @@ int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n
   float *logits = (float *)(ws + critic_logits_off(N, nt));
   __bf16 *wq, *wo, *w1, *w2;
   prepared_ptrs(ws + w.prep, &wq, &wo, &w1, &w2);
-  if (mil::launch_critic_tokens(d_gstate, N, M, pos_scale, tokens, mask, stream) ||
+  if (mil::launch_critic_tokens(d_gstate, N, M, 1, pos_scale, tokens, mask, stream) ||
       mil::launch_policy_prepare(d_params, wq, wo, w1, w2, stream))
     return fail(MIL_EHIP, "critic set-up launch failed");
   mil::PolicyArgs a{};
@@ -1095,6 +1116,53 @@ int critic_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n
   if (mil::launch_policy(a, num_cus_env(), stream) ||
       mil::launch_first_column(logits, N, d_values, stream))
     return fail(MIL_EHIP, "critic launch failed");
+  return MIL_OK;
+}
+
+int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_agents,
+                       int32_t n_targets, float pos_scale, const float *d_params,
+                       const float *d_hidden_in, float *d_values, float *d_hidden_seq,
+                       void *d_work, int64_t work_bytes, void *stream) {
+  if (T < 0 || N < 0 || n_agents < 1 || n_targets < 1 || n_agents + n_targets + 1 > mil::kPolMaxTok)
+    return fail(MIL_EINVAL, "need T >= 0, N >= 0 and 1 + n_agents + n_targets <= 16");
+  if (!(pos_scale > 0.0f)) return fail(MIL_EINVAL, "pos_scale must be > 0");
+  if (N == 0 || T == 0) return MIL_OK;
+  if (!d_gstate || !d_params || !d_values || !d_hidden_seq) return fail(MIL_EINVAL, "null argument");
+  if (!d_work || (((uintptr_t)d_work) & 255)) return fail(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (work_bytes < critic_workspace_bytes(N, n_agents, n_targets))
+    return fail(MIL_ESHAPE, "workspace too small (critic_workspace_bytes)");
+  const int M = n_agents + n_targets, nt = M + 1;
+  const PolicyWork w = policy_work(N, N * nt);
+  char *ws = (char *)d_work;
+  float *tokens = (float *)(ws + w.obs);
+  uint8_t *mask = (uint8_t *)(ws + w.mask);
+  float *logits = (float *)(ws + critic_logits_off(N, nt));
+  __bf16 *wq, *wo, *w1, *w2;
+  prepared_ptrs(ws + w.prep, &wq, &wo, &w1, &w2);
+  if (mil::launch_policy_prepare(d_params, wq, wo, w1, w2, stream))
+    return fail(MIL_EHIP, "critic set-up launch failed");
+  // the steps in order: step t reads the state step t - 1 wrote
+  for (int32_t t = 0; t < T; ++t) {
+    mil::PolicyArgs a{};
+    a.A = N;
+    a.n_tok = nt;
+    a.agents_per_tile = policy_tile(nt);
+    a.obs = tokens;
+    a.mask = mask;
+    a.params = d_params;
+    a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
+    a.logits = logits;
+    a.feat = d_hidden_seq + (int64_t)t * N * mil::kPolD;
+    a.hidden_in = t == 0 ? d_hidden_in : d_hidden_seq + (int64_t)(t - 1) * N * mil::kPolD;
+    a.rec = 1;
+    a.n_agents = 1;
+    a.n_actions = 1;
+    if (mil::launch_critic_tokens(d_gstate + (int64_t)t * N * M * 6, N, M, 0, pos_scale, tokens,
+                                  mask, stream) ||
+        mil::launch_policy(a, num_cus_env(), stream) ||
+        mil::launch_first_column(logits, N, d_values + (int64_t)t * N, stream))
+      return fail(MIL_EHIP, "critic launch failed");
+  }
   return MIL_OK;
 }
 
@@ -1154,15 +1222,17 @@ int64_t env_policy_workspace_bytes(const mil_env *h, int32_t learned) {
 }
 
 int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_params,
-                       const float *d_mlp_params, float k_sigma, const mil_env_outputs *outs,
-                       double *d_metrics, int32_t capture, void *d_work, int64_t work_bytes,
-                       void *stream) {
+                       const float *d_mlp_params, float k_sigma, float *d_hidden,
+                       const mil_env_outputs *outs, double *d_metrics, int32_t capture,
+                       void *d_work, int64_t work_bytes, void *stream) {
   if (!h || !d_params) return fail(MIL_EINVAL, "null argument");
   if (!h->ws) return fail(MIL_ESTATE, "env_bind has not been called");
   if (h->P.ragged) return fail(MIL_EINVAL, "the policy needs a batch with fixed counts");
-  const int na = h->P.n_agents, n_tok = h->P.n_agents + h->P.n_targets;
+  const int rec = d_hidden != nullptr;  // the recurrent form carries d_hidden across steps
+  const int na = h->P.n_agents, n_tok = h->P.n_agents + h->P.n_targets + rec;
   if (n_tok > mil::kPolMaxTok || h->P.n_actions > mil::kPolActions)
-    return fail(MIL_EINVAL, "the policy supports at most 16 tokens per agent and 8 actions");
+    return fail(MIL_EINVAL, "the policy supports at most 16 rows per agent (tokens and the "
+                            "carried state) and 8 actions");
   if (T < 1 || T > h->P.episode_len) return fail(MIL_EINVAL, "T must be in 1..episode_len");
   if (episode >= (1ull << 28)) return fail(MIL_EINVAL, "episode must be < 2^28");
   int rc = check_outputs(outs);
@@ -1216,6 +1286,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
     a.params = d_params;
     a.wqkv = wq; a.wo = wo; a.w1 = w1; a.w2 = w2;
     a.actions = wact;
+    a.feat = d_hidden;  // this step's state, read back by the next (zeros at the reset)
+    a.hidden_in = t == 0 ? nullptr : d_hidden;
+    a.rec = rec;
     a.n_agents = na;
     a.n_actions = h->P.n_actions;
     a.t = (uint32_t)t;

@@ -54,7 +54,12 @@ struct PolicyArgs {
   const float *params;       // FP32 master parameters
   const __bf16 *wqkv, *wo, *w1, *w2;
   float *logits;             // [A][8] or null
-  float *feat;               // [A][64] or null: the head's input (final LN of the self token)
+  float *feat;               // [A][64] or null: the head's input (final LN of the first row)
+  // recurrent form: rec = 1 puts a carried state ahead of each agent's
+  // n_tok - 1 observed tokens as an unmasked first row (hidden_in [A][64], or
+  // zeros when null; feat may alias it); rec = 0: n_tok observed tokens
+  const float *hidden_in;
+  int32_t rec;
   int32_t *actions;          // [A] or null
   int64_t n_agents;          // agents per env
   int32_t n_actions;
@@ -70,8 +75,8 @@ int launch_policy(const PolicyArgs &args, int num_cus, void *stream);
 // ppo_kernels.hip: the learner's forward half (critic tokens, GAE, clipped
 // PPO objective); partial sums in kPpoBlocks blocks of four doubles.
 constexpr int kPpoBlocks = 256;
-int launch_critic_tokens(const float *gstate, int64_t N, int M, float pos_scale, float *tokens,
-                         uint8_t *mask, void *stream);
+int launch_critic_tokens(const float *gstate, int64_t N, int M, int lead, float pos_scale,
+                         float *tokens, uint8_t *mask, void *stream);
 int launch_first_column(const float *logits, int64_t N, float *out, void *stream);
 int launch_gae(const float *rewards, const uint8_t *dones, const float *values, int32_t T, int64_t E,
                float gamma, float lambda, float *adv, float *ret, void *stream);

@@ -1,6 +1,8 @@
 // Attention policy of the full-rollout workload on gfx950: the per-agent
 // transformer actor of arXiv 2505.08222, Sec. IV-B-1 (TransfMAPPO, entity
-// tokens, LayerNorm throughout), without its recurrent token; forward only.
+// tokens, LayerNorm throughout), plain or with its recurrent token (Fig. 3: a
+// carried 64-wide state as an unmasked first row, not embedded, whose final
+// LayerNorm is the head's input and the next state); forward only.
 //
 // A persistent block (two per CU) takes tiles of agents (at most 80 token
 // rows); the small FP32 parameters (embedding, LayerNorms, biases, head) are
@@ -9,8 +11,9 @@
 // accumulation over the tile's stacked token rows, and attention (n_tok <= 16
 // keys per agent, 4 heads of 16) runs as two 16x16x16 MFMA products per
 // (agent, head) with keys whose observation mask is 0 excluded. The residual
-// stream stays in LDS in FP32. The self token's final LayerNorm feeds the
-// action head; the action is an inverse-CDF draw from Philox (purpose 4).
+// stream stays in LDS in FP32. The first row's final LayerNorm (the self
+// token, or the recurrent row) feeds the action head; the action is an
+// inverse-CDF draw from Philox (purpose 4).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <math.h>
@@ -181,17 +184,23 @@ policy_kernel(PolicyArgs a) {
   float tok[kTokRegs];
   uint8_t msk = 0;
   uint32_t eid_next = 0;
+  const int ot = nt - a.rec;  // observed tokens per agent (the recurrent row is not in obs)
   auto fetch = [&](int64_t tile) {
     const int64_t ag0 = tile * at;
     const int64_t nag = (a.A - ag0) < at ? (a.A - ag0) : at;
     const int nrow = (int)nag * nt;
-    const float *src = a.obs + ag0 * nt * 6;
+    const float *src = a.obs + ag0 * ot * 6;
 #pragma unroll
     for (int q = 0; q < kTokRegs; ++q) {
       const int e = tid + q * nthr;
-      tok[q] = (tile < ntiles && e < nrow * 6) ? src[e] : 0.0f;
+      tok[q] = (tile < ntiles && e < (int)nag * ot * 6) ? src[e] : 0.0f;
     }
-    msk = (tile < ntiles && tid < nrow) ? a.mask[ag0 * nt + tid] : 0;
+    if (a.rec) {  // row k of agent al: the carried state (never masked) or token k - 1
+      const int al = tid / nt, k = tid - al * nt;
+      msk = (tile < ntiles && tid < nrow) ? (k == 0 ? 1 : a.mask[(ag0 + al) * ot + k - 1]) : 0;
+    } else {
+      msk = (tile < ntiles && tid < nrow) ? a.mask[ag0 * nt + tid] : 0;
+    }
     // the global env id of agent tid of the tile, for its action draw
     const int64_t env = (ag0 + tid) / a.n_agents;
     eid_next = (tile < ntiles && tid < nag) ? (a.env_ids ? a.env_ids[env] : (uint32_t)env) : 0u;
@@ -223,8 +232,17 @@ policy_kernel(PolicyArgs a) {
       for (int c = 0; c < 6; ++c) wv[c] = L.prm[kSmEmbW + d * 6 + c];
       const float bd = L.prm[kSmEmbB + d];
       for (int r = tid >> 6; r < rows; r += nthr >> 6) {
+        // the staged row of row r: r itself, or with the recurrent row first,
+        // token k - 1 of agent al (row-uniform across the wavefront)
+        int xrow = r;
+        bool carried = false;
+        if (a.rec) {
+          const int al = r / nt, k = r - al * nt;
+          carried = k == 0;
+          xrow = al * ot + (carried ? 0 : k - 1);
+        }
         // the row's six inputs as three 8-byte reads (rows start 24 bytes apart)
-        const float2 *xr = reinterpret_cast<const float2 *>(x_raw + r * 6);
+        const float2 *xr = reinterpret_cast<const float2 *>(x_raw + xrow * 6);
         const float2 x01 = xr[0], x23 = xr[1], x45 = xr[2];
         float acc = bd;
         acc = fmaf(wv[0], x01.x, acc);
@@ -233,6 +251,8 @@ policy_kernel(PolicyArgs a) {
         acc = fmaf(wv[3], x23.y, acc);
         acc = fmaf(wv[4], x45.x, acc);
         acc = fmaf(wv[5], x45.y, acc);
+        if (carried)  // (rows past the tile's last agent stay zero)
+          acc = (a.hidden_in && r < nrow) ? a.hidden_in[(ag0 + r / nt) * kPolD + d] : 0.0f;
         L.h[r][d] = r < nrow ? acc : 0.0f;
       }
       if (tid < at) {

@@ -15,21 +15,24 @@ namespace {
 
 constexpr int kPpoThreads = 256;
 
-// One thread per (state, token): token 0 is the critic's own embedding token
-// (all-zero features: its embedding is the embedding bias), tokens 1.. the
-// state's agents and targets: (x / s, y / s, v cos psi, v sin psi, is_agent,
-// is_target) from the global-state rows (x, y, z, speed, heading, is_target).
+// One thread per (state, token): with lead = 1, token 0 is the critic's own
+// value token (all-zero features: its embedding is the embedding bias) and
+// tokens 1.. the state's agents and targets; with lead = 0 (the recurrent
+// critic, whose carried state takes the first row inside the attention
+// kernel) only the entities. An entity token is (x / s, y / s, v cos psi,
+// v sin psi, is_agent, is_target) from the global-state row (x, y, z, speed,
+// heading, is_target).
 __global__ void __launch_bounds__(kPpoThreads)
-critic_tokens_kernel(const float *__restrict__ gstate, int64_t N, int M, float inv_scale,
-                     float *__restrict__ tokens, uint8_t *__restrict__ mask) {
+critic_tokens_kernel(const float *__restrict__ gstate, int64_t N, int M, int lead,
+                     float inv_scale, float *__restrict__ tokens, uint8_t *__restrict__ mask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nt = M + 1;
+  const int nt = M + lead;
   if (i >= N * nt) return;
   const int64_t n = i / nt;
-  const int k = (int)(i - n * nt);
+  const int k = (int)(i - n * nt) - lead;  // entity, or -1 for the value token
   float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (k > 0) {
-    const float *g = gstate + (n * M + (k - 1)) * 6;
+  if (k >= 0) {
+    const float *g = gstate + (n * M + k) * 6;
     const float x = g[0], y = g[1], v = g[3], psi = g[4], is_t = g[5];
     // hardware sin / cos take revolutions
     const float rev = psi * 0.15915494309189535f;
@@ -254,13 +257,13 @@ int check() { return hipGetLastError() == hipSuccess ? 0 : -1; }
 
 }  // namespace
 
-int launch_critic_tokens(const float *gstate, int64_t N, int M, float pos_scale, float *tokens,
-                         uint8_t *mask, void *stream) {
-  const int64_t n = N * (M + 1);
+int launch_critic_tokens(const float *gstate, int64_t N, int M, int lead, float pos_scale,
+                         float *tokens, uint8_t *mask, void *stream) {
+  const int64_t n = N * (M + lead);
   if (n == 0) return 0;
   hipLaunchKernelGGL(critic_tokens_kernel, dim3((unsigned)((n + kPpoThreads - 1) / kPpoThreads)),
-                     dim3(kPpoThreads), 0, (hipStream_t)stream, gstate, N, M, 1.0f / pos_scale,
-                     tokens, mask);
+                     dim3(kPpoThreads), 0, (hipStream_t)stream, gstate, N, M, lead,
+                     1.0f / pos_scale, tokens, mask);
   return check();
 }
 

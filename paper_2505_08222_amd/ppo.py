@@ -29,6 +29,8 @@ def _l():
         L.policy_forward_feat.argtypes = [I64, I32, I32, I32, V, V, V, V, V, V, C.c_uint64,
                                           C.c_uint32, C.c_uint32, V, I64, V]
         L.policy_forward_feat.restype = C.c_int
+        L.critic_forward_rec.argtypes = [V, I32, I64, I32, I32, F, V, V, V, V, V, I64, V]
+        L.critic_forward_rec.restype = C.c_int
         L._ppo_registered = True
     return L
 
@@ -56,6 +58,27 @@ def critic_forward(gstate, n_agents: int, n_targets: int, params, pos_scale: flo
     check(L.critic_forward(ptr(g), N, n_agents, n_targets, pos_scale, ptr(params), ptr(out),
                            ptr(feat), C.c_void_p(w), n, _stream()))
     return (out, feat) if features else out
+
+
+def critic_forward_rec(gstate, n_agents: int, n_targets: int, params, hidden=None,
+                       pos_scale: float = 1000.0):
+    """The recurrent critic over a trajectory: gstate [T, N, n_agents +
+    n_targets, 6] (or the rollout's [T, N * M, 6]), hidden [N, 64] or None
+    (zeros) -> (values [T, N], states [T, N, 64]; states[t] is the head's
+    input at step t and the state carried into step t + 1)."""
+    M = n_agents + n_targets
+    T = gstate.shape[0]
+    g = gstate.reshape(T, -1, M, 6).contiguous()
+    N = g.shape[1]
+    L = _l()
+    n = L.critic_workspace_bytes(N, n_agents, n_targets)
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=g.device)
+    w = (buf.data_ptr() + 255) & ~255
+    values = torch.empty((T, N), dtype=torch.float32, device=g.device)
+    states = torch.empty((T, N, 64), dtype=torch.float32, device=g.device)
+    check(L.critic_forward_rec(ptr(g), T, N, n_agents, n_targets, pos_scale, ptr(params),
+                               ptr(hidden), ptr(values), ptr(states), C.c_void_p(w), n, _stream()))
+    return values, states
 
 
 def policy_features(obs, mask, params, n_tok: int, n_agents: int, n_actions: int = 5):
