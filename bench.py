@@ -636,29 +636,37 @@ def bench_ppo(args, T=32, cpu_seconds=None):
             ms.append(a.elapsed_time(b))
         return float(np.median(ms)), out
 
-    t_crit, values = timed(lambda: ppo.critic_forward(gs, na, nt, critic).reshape(T + 1, E))
-    t_pol, (logits, _) = timed(lambda: policy.forward(obs, mask, actor, n_tok, na))
+    t_crit, (values, cfeat) = timed(lambda: ppo.critic_forward(gs, na, nt, critic, features=True))
+    values = values.reshape(T + 1, E)
+    t_pol, (logits, pfeat) = timed(lambda: ppo.policy_features(obs, mask, actor, n_tok, na))
     logits = logits.reshape(T, A, 8)
     logits_old = logits + 0.1 * torch.randn(logits.shape, device=dev, generator=g)
     t_gae, (adv, ret) = timed(lambda: ppo.gae(rewards, dones, values, 0.99, 0.95))
-    t_obj, (out, _, _) = timed(lambda: ppo.objective(logits, logits_old, actions, adv,
-                                                    values[:T].contiguous(), ret, na, 5))
-    total = t_crit + t_pol + t_gae + t_obj
+    t_obj, (out, dl, dv) = timed(lambda: ppo.objective(logits, logits_old, actions, adv,
+                                                      values[:T].contiguous(), ret, na, 5))
+    # the heads' gradients and Adam steps (the layers below them are not trained)
+    t_hg, (ga, gc) = timed(lambda: (ppo.head_grad(pfeat, dl.reshape(T * A, 8), 5),
+                                    ppo.head_grad(cfeat[:T * E], dv.reshape(-1), 1)))
+    oa, oc = ppo.HeadAdam(actor), ppo.HeadAdam(critic)
+    t_adam, _ = timed(lambda: (oa.step(ga), oc.step(gc)))
+    total = t_crit + t_pol + t_gae + t_obj + t_hg + t_adam
     fl_crit = policy_flops_per_agent_step(M + 1) * (T + 1) * E
     fl_pol = policy_flops_per_agent_step(n_tok) * T * A
     ach = fl_crit / (t_crit / 1e3) / 1e12
     log(f"[bench] ppo: critic {t_crit:.2f} ms, policy {t_pol:.2f} ms, gae {t_gae:.3f} ms, "
-        f"objective {t_obj:.3f} ms")
+        f"objective {t_obj:.3f} ms, head gradients {t_hg:.3f} ms, Adam {t_adam:.3f} ms")
     o = out.cpu().numpy()
     res = {
         "metric": METRIC, "value": T * A / (total / 1e3), "unit": "agent-steps/s",
         "n_gpus": 1, "steps": 3, "dtype": "bf16 (MFMA, FP32 accumulate); FP64 GAE",
         "data": "synthetic tensors of the workload's shapes",
         "config": {"workload": f"PPO batch: {E} envs x {na} agents x {nt} targets x {T} steps: "
-                               "critic on T + 1 states, policy on T steps, GAE, clipped objective "
-                               "(forward half; no backward through the transformers)",
+                               "critic on T + 1 states, policy on T steps (with the heads' "
+                               "inputs), GAE, clipped objective, head gradients and Adam (no "
+                               "backward through the transformers below the heads)",
                    "envs": E, "agents": A, "batch_steps": T},
-        "ms": {"critic": t_crit, "policy": t_pol, "gae": t_gae, "objective": t_obj, "total": total},
+        "ms": {"critic": t_crit, "policy": t_pol, "gae": t_gae, "objective": t_obj,
+               "head_grad": t_hg, "adam": t_adam, "total": total},
         "objective": {"policy_loss": float(o[0]), "value_loss": float(o[1]),
                       "entropy": float(o[2]), "clip_frac": float(o[3])},
         "roofline": {"bound": "mfma", "kernel": "policy_kernel (critic tokens)", "achieved": ach,

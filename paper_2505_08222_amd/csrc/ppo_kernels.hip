@@ -215,23 +215,70 @@ __global__ void ppo_final_kernel(const double *__restrict__ part, int nb, double
   out[3] = s[2] * inv_s;
 }
 
-// Head gradient partials: block b sums samples [b * per, (b + 1) * per) for
-// every (output, input) pair; thread j owns pairs j, j + 256, ... of the
-// n_out * 65 entries (64 weights and the bias of each output).
-__global__ void __launch_bounds__(kPpoThreads)
+// Head gradient partials: block b sums samples [b * per, (b + 1) * per).
+// Wavefront w of the block takes rows w, w + 16, ... of its range, lane d
+// feature d of each row (coalesced 256-byte row reads; the row's output
+// gradients are wavefront-uniform, scalar loads); each lane keeps FP64 sums
+// for every output, its rows in increasing order, four rows in flight. The
+// 16 wavefronts' sums are then added in a fixed order through LDS.
+constexpr int kHgThreads = 1024, kHgGroups = kHgThreads / kPolD;
+__global__ void __launch_bounds__(kHgThreads)
 head_grad_partial_kernel(const float *__restrict__ feat, const float *__restrict__ dout, int64_t N,
                          int ld, int n_out, int64_t per, double *__restrict__ part) {
+  __shared__ double red[kHgGroups / 2][kPolActions][kPolD + 1];
+  const int d = threadIdx.x & (kPolD - 1);
+  const int rg = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t n0 = (int64_t)blockIdx.x * per;
   const int64_t n1 = n0 + per < N ? n0 + per : N;
+  double acc[kPolActions], accb[kPolActions];
+#pragma unroll
+  for (int o = 0; o < kPolActions; ++o) acc[o] = accb[o] = 0.0;
+  auto add_row = [&](int64_t n, float f) {
+    const float *g = dout + n * ld;
+#pragma unroll
+    for (int o = 0; o < kPolActions; ++o)
+      if (o < n_out) {
+        const float go = g[o];
+        acc[o] += (double)(go * f);
+        accb[o] += (double)go;
+      }
+  };
+  int64_t n = n0 + rg;
+  for (; n + 3 * kHgGroups < n1; n += 4 * kHgGroups) {
+    const float f0 = feat[n * kPolD + d];
+    const float f1 = feat[(n + kHgGroups) * kPolD + d];
+    const float f2 = feat[(n + 2 * kHgGroups) * kPolD + d];
+    const float f3 = feat[(n + 3 * kHgGroups) * kPolD + d];
+    add_row(n, f0);
+    add_row(n + kHgGroups, f1);
+    add_row(n + 2 * kHgGroups, f2);
+    add_row(n + 3 * kHgGroups, f3);
+  }
+  for (; n < n1; n += kHgGroups) add_row(n, feat[n * kPolD + d]);
+  // wavefronts 8..15 store, 0..7 add theirs (fixed pairs), then eight in order
+  const int half = kHgGroups / 2;
+  if (rg >= half) {
+#pragma unroll
+    for (int o = 0; o < kPolActions; ++o) {
+      red[rg - half][o][d] = acc[o];
+      if (d == 0) red[rg - half][o][kPolD] = accb[o];
+    }
+  }
+  __syncthreads();
+  if (rg < half) {
+#pragma unroll
+    for (int o = 0; o < kPolActions; ++o) {
+      red[rg][o][d] += acc[o];
+      if (d == 0) red[rg][o][kPolD] += accb[o];
+    }
+  }
+  __syncthreads();
   const int ne = n_out * (kPolD + 1);
   for (int j = threadIdx.x; j < ne; j += blockDim.x) {
     const int o = j / (kPolD + 1), i = j - o * (kPolD + 1);
-    double acc = 0.0;
-    for (int64_t n = n0; n < n1; ++n) {
-      const float g = dout[n * ld + o];
-      acc += (double)(i < kPolD ? g * feat[n * kPolD + i] : g);
-    }
-    part[(int64_t)blockIdx.x * ne + j] = acc;
+    double s = 0.0;
+    for (int r = 0; r < half; ++r) s += red[r][o][i];
+    part[(int64_t)blockIdx.x * ne + j] = s;
   }
 }
 
@@ -279,7 +326,7 @@ int launch_head_grad(const float *feat, const float *dout, int64_t N, int ld, in
   hipStream_t st = (hipStream_t)stream;
   if (N > 0) {
     const int64_t per = (N + kPpoBlocks - 1) / kPpoBlocks;
-    hipLaunchKernelGGL(head_grad_partial_kernel, dim3(kPpoBlocks), dim3(kPpoThreads), 0, st, feat,
+    hipLaunchKernelGGL(head_grad_partial_kernel, dim3(kPpoBlocks), dim3(kHgThreads), 0, st, feat,
                        dout, N, ld, n_out, per, part);
     if (check()) return -1;
   }
