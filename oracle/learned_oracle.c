@@ -417,6 +417,298 @@ void orc_policy_forward_rec(int64_t A, int n_obs, const double *tokens, const ui
   }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Gradient of the attention network (the learner's backward pass, MAPPO's  */
+/* gradient step of Sec. III-B through the TransfMAPPO networks of Fig. 3).  */
+/* For a loss whose gradient at each agent's logits is dlogits, the exact   */
+/* gradient in every parameter, summed over agents: the forward pass is     */
+/* taken again with every intermediate kept, then each operation is         */
+/* differentiated in reverse order (layer norm, attention with its softmax  */
+/* and key mask, tanh GELU, the residual adds, the embedding). In the       */
+/* recurrent form the carried state is an input: its gradient is returned   */
+/* (dhidden, may be NULL) but not followed into earlier steps.              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  double hin[PL][P_MAXT][PD], a1[PL][P_MAXT][PD], q[PL][P_MAXT][3 * PD];
+  double pr[PL][PH][P_MAXT][P_MAXT], o[PL][P_MAXT][PD], hmid[PL][P_MAXT][PD];
+  double a2[PL][P_MAXT][PD], z[PL][P_MAXT][PF], hout[P_MAXT][PD];
+} policy_tape;
+
+static void ln_backward(const double *x, const double *g, const double *dy, double *dx,
+                        double *dg, double *db) {
+  double m = 0.0, v = 0.0;
+  for (int i = 0; i < PD; ++i) m += x[i];
+  m /= PD;
+  for (int i = 0; i < PD; ++i) v += (x[i] - m) * (x[i] - m);
+  v /= PD;
+  const double r = 1.0 / sqrt(v + 1e-5);
+  double xh[PD], dxh[PD], s1 = 0.0, s2 = 0.0;
+  for (int i = 0; i < PD; ++i) {
+    xh[i] = (x[i] - m) * r;
+    dxh[i] = dy[i] * g[i];
+    dg[i] += dy[i] * xh[i];
+    db[i] += dy[i];
+    s1 += dxh[i];
+    s2 += dxh[i] * xh[i];
+  }
+  for (int i = 0; i < PD; ++i) dx[i] = r * (dxh[i] - s1 / PD - xh[i] * s2 / PD);
+}
+
+/* One agent: rows h[0..n_tok-1] already in the residual stream (embedded, or
+ * the carried state first); the trunk's forward pass recorded on the tape. */
+static void policy_trunk_taped(int n_tok, double h[][PD], const uint8_t *mk, const double *th,
+                               policy_tape *tp) {
+  double f[PF];
+  const double *p = th;
+  for (int l = 0; l < PL; ++l) {
+    const double *g1 = p; p += PD;
+    const double *b1n = p; p += PD;
+    const double *Wqkv = p; p += 3 * PD * PD;
+    const double *bqkv = p; p += 3 * PD;
+    const double *Wo = p; p += PD * PD;
+    const double *bo = p; p += PD;
+    const double *g2 = p; p += PD;
+    const double *b2n = p; p += PD;
+    const double *W1 = p; p += PF * PD;
+    const double *b1 = p; p += PF;
+    const double *W2 = p; p += PD * PF;
+    const double *b2 = p; p += PD;
+    for (int t = 0; t < n_tok; ++t) {
+      memcpy(tp->hin[l][t], h[t], sizeof(double) * PD);
+      layer_norm(h[t], g1, b1n, tp->a1[l][t]);
+      for (int r = 0; r < 3 * PD; ++r) {
+        double acc = bqkv[r];
+        for (int i = 0; i < PD; ++i) acc += Wqkv[r * PD + i] * tp->a1[l][t][i];
+        tp->q[l][t][r] = acc;
+      }
+    }
+    for (int hd = 0; hd < PH; ++hd)
+      for (int t = 0; t < n_tok; ++t) {
+        double *s = tp->pr[l][hd][t], mx = -INFINITY, zs = 0.0;
+        for (int u = 0; u < n_tok; ++u) {
+          s[u] = -INFINITY;
+          if (!mk[u]) continue;
+          double acc = 0.0;
+          for (int c = 0; c < PDH; ++c)
+            acc += tp->q[l][t][hd * PDH + c] * tp->q[l][u][PD + hd * PDH + c];
+          s[u] = acc / 4.0;
+          if (s[u] > mx) mx = s[u];
+        }
+        for (int u = 0; u < n_tok; ++u) {
+          s[u] = mk[u] ? exp(s[u] - mx) : 0.0;
+          zs += s[u];
+        }
+        for (int u = 0; u < n_tok; ++u) s[u] /= zs;
+        for (int c = 0; c < PDH; ++c) {
+          double acc = 0.0;
+          for (int u = 0; u < n_tok; ++u) acc += s[u] * tp->q[l][u][2 * PD + hd * PDH + c];
+          tp->o[l][t][hd * PDH + c] = acc;
+        }
+      }
+    for (int t = 0; t < n_tok; ++t) {
+      for (int d = 0; d < PD; ++d) {
+        double acc = bo[d];
+        for (int i = 0; i < PD; ++i) acc += Wo[d * PD + i] * tp->o[l][t][i];
+        h[t][d] += acc;
+      }
+      memcpy(tp->hmid[l][t], h[t], sizeof(double) * PD);
+      layer_norm(h[t], g2, b2n, tp->a2[l][t]);
+      for (int r = 0; r < PF; ++r) {
+        double acc = b1[r];
+        for (int i = 0; i < PD; ++i) acc += W1[r * PD + i] * tp->a2[l][t][i];
+        tp->z[l][t][r] = acc;
+        f[r] = gelu(acc);
+      }
+      for (int d = 0; d < PD; ++d) {
+        double acc = b2[d];
+        for (int r = 0; r < PF; ++r) acc += W2[d * PF + r] * f[r];
+        h[t][d] += acc;
+      }
+    }
+  }
+  for (int t = 0; t < n_tok; ++t) memcpy(tp->hout[t], h[t], sizeof(double) * PD);
+}
+
+/* Reverse pass of one agent: dlogits [PA] -> parameter gradient added to
+ * gr (layer parameters from gl, embedding from ge, final LN and head from
+ * gf), dh [n_tok][PD] the gradient at the rows entering the trunk. */
+static void policy_trunk_backward(int n_tok, const uint8_t *mk, const double *th,
+                                  const policy_tape *tp, const double *dlogits, double *gl,
+                                  double dh[][PD]) {
+  const double *p = th;
+  const double *lay[PL];
+  double *glay[PL];
+  for (int l = 0; l < PL; ++l) {
+    lay[l] = p + l * P_LAYER;
+    glay[l] = gl + l * P_LAYER;
+  }
+  /* final LN and head (row 0) */
+  const double *gf = p + PL * P_LAYER, *Wh = gf + 2 * PD;
+  double *dgf = gl + PL * P_LAYER, *dbf = dgf + PD, *dWh = dgf + 2 * PD, *dbh = dWh + PA * PD;
+  double s0[PD], ds0[PD];
+  layer_norm(tp->hout[0], gf, gf + PD, s0);
+  for (int i = 0; i < PD; ++i) ds0[i] = 0.0;
+  for (int k = 0; k < PA; ++k) {
+    dbh[k] += dlogits[k];
+    for (int i = 0; i < PD; ++i) {
+      dWh[k * PD + i] += dlogits[k] * s0[i];
+      ds0[i] += dlogits[k] * Wh[k * PD + i];
+    }
+  }
+  for (int t = 0; t < n_tok; ++t)
+    for (int d = 0; d < PD; ++d) dh[t][d] = 0.0;
+  ln_backward(tp->hout[0], gf, ds0, dh[0], dgf, dbf);
+  double dz[PF], df[PF], da[PD], dx[PD];
+  double dq[P_MAXT][3 * PD], dov[P_MAXT][PD];
+  for (int l = PL - 1; l >= 0; --l) {
+    const double *q = lay[l];
+    const double *g1 = q; q += PD;
+    q += PD; /* ln1 offset */
+    const double *Wqkv = q; q += 3 * PD * PD;
+    q += 3 * PD;
+    const double *Wo = q; q += PD * PD;
+    q += PD;
+    const double *g2 = q; q += PD;
+    q += PD;
+    const double *W1 = q; q += PF * PD;
+    q += PF;
+    const double *W2 = q;
+    double *w = glay[l];
+    double *dg1 = w; w += PD;
+    double *db1n = w; w += PD;
+    double *dWqkv = w; w += 3 * PD * PD;
+    double *dbqkv = w; w += 3 * PD;
+    double *dWo = w; w += PD * PD;
+    double *dbo = w; w += PD;
+    double *dg2 = w; w += PD;
+    double *db2n = w; w += PD;
+    double *dW1 = w; w += PF * PD;
+    double *db1 = w; w += PF;
+    double *dW2 = w; w += PD * PF;
+    double *db2 = w;
+    /* feed-forward block: h = hmid + W2 gelu(z) + b2 */
+    for (int t = 0; t < n_tok; ++t) {
+      for (int r = 0; r < PF; ++r) df[r] = 0.0;
+      for (int d = 0; d < PD; ++d) {
+        db2[d] += dh[t][d];
+        for (int r = 0; r < PF; ++r) {
+          dW2[d * PF + r] += dh[t][d] * gelu(tp->z[l][t][r]);
+          df[r] += W2[d * PF + r] * dh[t][d];
+        }
+      }
+      for (int r = 0; r < PF; ++r) {
+        dz[r] = df[r] * gelu_grad(tp->z[l][t][r]);
+        db1[r] += dz[r];
+      }
+      for (int i = 0; i < PD; ++i) da[i] = 0.0;
+      for (int r = 0; r < PF; ++r)
+        for (int i = 0; i < PD; ++i) {
+          dW1[r * PD + i] += dz[r] * tp->a2[l][t][i];
+          da[i] += W1[r * PD + i] * dz[r];
+        }
+      ln_backward(tp->hmid[l][t], g2, da, dx, dg2, db2n);
+      for (int d = 0; d < PD; ++d) dh[t][d] += dx[d];
+    }
+    /* attention block: hmid = hin + Wo o + bo */
+    for (int t = 0; t < n_tok; ++t) {
+      for (int i = 0; i < PD; ++i) dov[t][i] = 0.0;
+      for (int d = 0; d < PD; ++d) {
+        dbo[d] += dh[t][d];
+        for (int i = 0; i < PD; ++i) {
+          dWo[d * PD + i] += dh[t][d] * tp->o[l][t][i];
+          dov[t][i] += Wo[d * PD + i] * dh[t][d];
+        }
+      }
+      for (int r = 0; r < 3 * PD; ++r) dq[t][r] = 0.0;
+    }
+    for (int hd = 0; hd < PH; ++hd)
+      for (int t = 0; t < n_tok; ++t) {
+        const double *P = tp->pr[l][hd][t];
+        double dP[P_MAXT], dot = 0.0;
+        for (int u = 0; u < n_tok; ++u) {
+          dP[u] = 0.0;
+          for (int c = 0; c < PDH; ++c) {
+            dP[u] += dov[t][hd * PDH + c] * tp->q[l][u][2 * PD + hd * PDH + c];
+            dq[u][2 * PD + hd * PDH + c] += P[u] * dov[t][hd * PDH + c];
+          }
+          dot += P[u] * dP[u];
+        }
+        for (int u = 0; u < n_tok; ++u) {
+          const double ds = P[u] * (dP[u] - dot) / 4.0; /* through s = q.k / sqrt(16) */
+          if (!mk[u]) continue;
+          for (int c = 0; c < PDH; ++c) {
+            dq[t][hd * PDH + c] += ds * tp->q[l][u][PD + hd * PDH + c];
+            dq[u][PD + hd * PDH + c] += ds * tp->q[l][t][hd * PDH + c];
+          }
+        }
+      }
+    for (int t = 0; t < n_tok; ++t) {
+      for (int i = 0; i < PD; ++i) da[i] = 0.0;
+      for (int r = 0; r < 3 * PD; ++r) {
+        dbqkv[r] += dq[t][r];
+        for (int i = 0; i < PD; ++i) {
+          dWqkv[r * PD + i] += dq[t][r] * tp->a1[l][t][i];
+          da[i] += Wqkv[r * PD + i] * dq[t][r];
+        }
+      }
+      ln_backward(tp->hin[l][t], g1, da, dx, dg1, db1n);
+      for (int d = 0; d < PD; ++d) dh[t][d] += dx[d];
+    }
+  }
+}
+
+/* grad [P] += the gradient of sum_a dlogits[a] . logits[a] (plain form:
+ * tokens [A][n_tok][6], the head on the first token). */
+void orc_policy_backward(int64_t A, int n_tok, const double *tokens, const uint8_t *mask,
+                         const double *th, const double *dlogits, double *grad) {
+  policy_tape *tp = (policy_tape *)malloc(sizeof(policy_tape));
+  double h[P_MAXT][PD], dh[P_MAXT][PD];
+  const double *tl = th + PD * 6 + PD;
+  for (int64_t ag = 0; ag < A; ++ag) {
+    const double *x = tokens + ag * n_tok * 6;
+    for (int t = 0; t < n_tok; ++t) policy_embed(th, x + t * 6, h[t]);
+    policy_trunk_taped(n_tok, h, mask + ag * n_tok, tl, tp);
+    policy_trunk_backward(n_tok, mask + ag * n_tok, tl, tp, dlogits + ag * PA,
+                          grad + PD * 6 + PD, dh);
+    for (int t = 0; t < n_tok; ++t)
+      for (int d = 0; d < PD; ++d) {
+        grad[PD * 6 + d] += dh[t][d];
+        for (int c = 0; c < 6; ++c) grad[d * 6 + c] += dh[t][d] * x[t * 6 + c];
+      }
+  }
+  free(tp);
+}
+
+/* The recurrent form: the carried state hidden_in [A][64] (NULL: zeros) is
+ * row 0; dhidden [A][64] (may be NULL) receives the gradient at it. */
+void orc_policy_backward_rec(int64_t A, int n_obs, const double *tokens, const uint8_t *mask,
+                             const double *hidden_in, const double *th, const double *dlogits,
+                             double *grad, double *dhidden) {
+  policy_tape *tp = (policy_tape *)malloc(sizeof(policy_tape));
+  double h[P_MAXT][PD], dh[P_MAXT][PD];
+  uint8_t mk[P_MAXT];
+  const double *tl = th + PD * 6 + PD;
+  for (int64_t ag = 0; ag < A; ++ag) {
+    const double *x = tokens + ag * n_obs * 6;
+    for (int d = 0; d < PD; ++d) h[0][d] = hidden_in ? hidden_in[ag * PD + d] : 0.0;
+    mk[0] = 1;
+    for (int t = 0; t < n_obs; ++t) {
+      policy_embed(th, x + t * 6, h[1 + t]);
+      mk[1 + t] = mask[ag * n_obs + t];
+    }
+    policy_trunk_taped(1 + n_obs, h, mk, tl, tp);
+    policy_trunk_backward(1 + n_obs, mk, tl, tp, dlogits + ag * PA, grad + PD * 6 + PD, dh);
+    if (dhidden)
+      for (int d = 0; d < PD; ++d) dhidden[ag * PD + d] = dh[0][d];
+    for (int t = 0; t < n_obs; ++t)
+      for (int d = 0; d < PD; ++d) {
+        grad[PD * 6 + d] += dh[1 + t][d];
+        for (int c = 0; c < 6; ++c) grad[d * 6 + c] += dh[1 + t][d] * x[t * 6 + c];
+      }
+  }
+  free(tp);
+}
+
 /* Inverse-CDF draw from softmax(logits[0..n-1]) with uniform u in (0,1):
  * the smallest k whose cumulative probability exceeds u. */
 int orc_policy_sample(const double *logits, int n, double u) {

@@ -118,6 +118,9 @@ def _register_learned(L):
         L.orc_policy_forward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D)]
         L.orc_policy_forward_rec.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D),
                                              P(D)]
+        L.orc_policy_backward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D)]
+        L.orc_policy_backward_rec.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D),
+                                              P(D), P(D)]
         L.orc_policy_sample.argtypes = [P(D), C.c_int, D]
         L.orc_policy_sample.restype = C.c_int
 
@@ -458,6 +461,38 @@ def policy_forward_rec(tokens, mask, hidden, params):
                                  _p(params, C.c_double), _p(out, C.c_double),
                                  _p(hout, C.c_double))
     return out, hout
+
+
+def policy_backward(tokens, mask, params, dlogits):
+    """Gradient of sum_a dlogits[a] . logits[a] in every parameter (plain
+    form) -> [P]."""
+    tokens = np.ascontiguousarray(tokens, np.float64)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    params = np.ascontiguousarray(params, np.float64)
+    dl = np.ascontiguousarray(dlogits, np.float64).reshape(tokens.shape[0], 8)
+    g = np.zeros(params.size)
+    lib().orc_policy_backward(tokens.shape[0], tokens.shape[1], _p(tokens, C.c_double),
+                              _p(mask, C.c_uint8), _p(params, C.c_double), _p(dl, C.c_double),
+                              _p(g, C.c_double))
+    return g
+
+
+def policy_backward_rec(tokens, mask, hidden, params, dlogits):
+    """The recurrent form -> (parameter gradient [P], gradient at the carried
+    state [A, 64])."""
+    tokens = np.ascontiguousarray(tokens, np.float64)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    params = np.ascontiguousarray(params, np.float64)
+    A, n_obs, _ = tokens.shape
+    dl = np.ascontiguousarray(dlogits, np.float64).reshape(A, 8)
+    hin = None if hidden is None else np.ascontiguousarray(hidden, np.float64)
+    g = np.zeros(params.size)
+    dh = np.zeros((A, 64))
+    lib().orc_policy_backward_rec(A, n_obs, _p(tokens, C.c_double), _p(mask, C.c_uint8),
+                                  None if hin is None else _p(hin, C.c_double),
+                                  _p(params, C.c_double), _p(dl, C.c_double), _p(g, C.c_double),
+                                  _p(dh, C.c_double))
+    return g, dh
 
 
 def policy_sample(logits, n, u) -> int:

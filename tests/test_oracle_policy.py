@@ -4,7 +4,10 @@ masking, tanh GELU), permutation invariance over the non-self tokens (the
 property Sec. IV-B-1 builds on), the inverse-CDF sampler, and the recurrent
 form of Fig. 3 (a carried state as an extra first row): against torch, its
 reduction to the plain form when the state is an embedded token, the head
-on the returned state, and invariance to any order of the tokens."""
+on the returned state, and invariance to any order of the tokens. The
+backward pass: central differences of the forward pass in sampled entries of
+every parameter group, and the whole gradient against torch's float64
+autograd of the torch network (plain and recurrent forms, masked keys)."""
 import numpy as np
 import pytest
 
@@ -20,7 +23,7 @@ def _params(orc, seed=0):
 
 
 def _torch_policy(tokens, mask, th, hidden=None):
-    t = torch.from_numpy(th)
+    t = th if isinstance(th, torch.Tensor) else torch.from_numpy(th)
     o = 0
 
     def take(*shape):
@@ -34,7 +37,8 @@ def _torch_policy(tokens, mask, th, hidden=None):
     m = torch.from_numpy(mask.astype(bool))
     h = x @ E.T + e
     if hidden is not None:  # the recurrent row ahead of the embedded tokens, never masked
-        h = torch.cat([torch.from_numpy(hidden)[:, None], h], 1)
+        hid = hidden if isinstance(hidden, torch.Tensor) else torch.from_numpy(hidden)
+        h = torch.cat([hid[:, None], h], 1)
         m = torch.cat([torch.ones_like(m[:, :1]), m], 1)
     A, T = h.shape[0], h.shape[1]
     for _ in range(L):
@@ -60,7 +64,8 @@ def _torch_policy(tokens, mask, th, hidden=None):
     gf, bf = take(D), take(D)
     Wh, bh = take(NA, D), take(NA)
     s0 = torch.nn.functional.layer_norm(h[:, 0], (D,), gf, bf, eps=1e-5)
-    return (s0 @ Wh.T + bh).numpy()
+    out = s0 @ Wh.T + bh
+    return out if isinstance(th, torch.Tensor) else out.numpy()
 
 
 def _tokens(A, n_agents, n_targets, seed, p_missing=0.2):
@@ -174,3 +179,57 @@ def test_recurrent_form_ignores_token_order(orc):
     lp, hp = orc.policy_forward_rec(x[:, perm], mask[:, perm], hid, th)
     np.testing.assert_allclose(lp, lg, atol=1e-12)
     np.testing.assert_allclose(hp, hout, atol=1e-12)
+
+
+PER_LAYER = 2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D
+GROUPS = [("E", D * 6), ("e", D)] + [
+    (f"{n}{l}", s) for l in range(L) for n, s in (
+        ("ln1g", D), ("ln1b", D), ("Wq", D * D), ("Wk", D * D), ("Wv", D * D), ("bqkv", 3 * D),
+        ("Wo", D * D), ("bo", D), ("ln2g", D), ("ln2b", D), ("W1", F * D), ("b1", F),
+        ("W2", D * F), ("b2", D))] + [("lnfg", D), ("lnfb", D), ("Wh", NA * D), ("bh", NA)]
+
+
+def test_backward_matches_central_differences(orc):
+    th = _params(orc, 11)
+    x, mask = _tokens(3, 2, 3, seed=12)
+    dl = np.random.default_rng(13).normal(size=(3, NA))
+    g = orc.policy_backward(x, mask, th, dl)
+    assert sum(s for _, s in GROUPS) == th.size
+    rng = np.random.default_rng(14)
+    off, h = 0, 1e-5
+    for name, size in GROUPS:
+        for i in off + rng.choice(size, min(size, 4), replace=False):
+            tp, tm = th.copy(), th.copy()
+            tp[i] += h
+            tm[i] -= h
+            fd = ((orc.policy_forward(x, mask, tp) - orc.policy_forward(x, mask, tm)) * dl).sum()
+            assert g[i] == pytest.approx(fd / (2 * h), abs=1e-8 * max(1.0, np.abs(g).max())), name
+        off += size
+
+
+def test_backward_matches_autograd(orc):
+    th = _params(orc, 15)
+    x, mask = _tokens(4, 3, 2, seed=16)
+    dl = np.random.default_rng(17).normal(size=(4, NA))
+    t = torch.tensor(th, requires_grad=True)
+    (_torch_policy(x, mask, t) * torch.from_numpy(dl)).sum().backward()
+    np.testing.assert_allclose(orc.policy_backward(x, mask, th, dl), t.grad.numpy(), rtol=0,
+                               atol=1e-11 * np.abs(t.grad.numpy()).max())
+
+
+def test_recurrent_backward_matches_autograd(orc):
+    th = _params(orc, 18)
+    x, mask = _tokens(3, 2, 2, seed=19)
+    rng = np.random.default_rng(20)
+    hid = rng.normal(0, 1.0, (3, D))
+    dl = rng.normal(size=(3, NA))
+    t = torch.tensor(th, requires_grad=True)
+    hv = torch.tensor(hid, requires_grad=True)
+    (_torch_policy(x, mask, t, hv) * torch.from_numpy(dl)).sum().backward()
+    g, dh = orc.policy_backward_rec(x, mask, hid, th, dl)
+    np.testing.assert_allclose(g, t.grad.numpy(), rtol=0, atol=1e-11 * np.abs(g).max())
+    np.testing.assert_allclose(dh, hv.grad.numpy(), rtol=0, atol=1e-11 * np.abs(dh).max())
+    # no state: zeros, and the embedding takes no gradient from the state row
+    g0, _ = orc.policy_backward_rec(x, mask, None, th, dl)
+    g1, _ = orc.policy_backward_rec(x, mask, np.zeros((3, D)), th, dl)
+    np.testing.assert_array_equal(g0, g1)
