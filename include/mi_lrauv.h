@@ -503,9 +503,9 @@ int env_policy_rollout(mil_env *h, uint64_t episode, int32_t T, const float *d_p
  * PPO clipped surrogate objective and one centralised critic V(S) estimates
  * the value of the global state; Sec. IV-B-1, Fig. 3: the TransformerCritic
  * reads the full global state as entity tokens plus one embedding token whose
- * transformed output gives V; plain, or with that token recurrent), and the
- * gradient of the two output heads. The backward pass through the
- * transformers below the heads is not part of this library.
+ * transformed output gives V; plain, or with that token recurrent), the
+ * gradient of the two output heads, and the networks' training form (the
+ * gradient of every parameter).
  * ------------------------------------------------------------------------- */
 /* Workspace for critic_forward (256-byte aligned); -1 on bad sizes. */
 int64_t critic_workspace_bytes(int64_t N, int32_t n_agents, int32_t n_targets);
@@ -538,6 +538,45 @@ int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_ag
                        int32_t n_targets, float pos_scale, const float *d_params,
                        const float *d_hidden_in, float *d_values, float *d_hidden_seq,
                        void *d_work, int64_t work_bytes, void *stream);
+/* Training form of the networks (the gradient step of MAPPO, Sec. III-B,
+ * through the TransfMAPPO actor and critic of Fig. 3): an FP32 forward pass
+ * that records every intermediate in the workspace (the tape), then its
+ * exact reverse pass into the gradient of every parameter. The per-row work
+ * (embedding, LayerNorms, attention with its softmax and key mask, tanh
+ * GELU, head) runs in the library's kernels, the dense products in rocBLAS
+ * FP32 GEMMs. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
+ * the recurrent form of policy_forward_rec (n_tok - 1 observed tokens per
+ * agent after the carried state). The carried state is an input of the
+ * step: its gradient is returned, not followed into earlier steps. */
+/* Workspace of the training form for A agents of n_tok rows (256-byte
+ * aligned; about 11 KB per row); -1 on bad sizes. */
+int64_t policy_train_workspace_bytes(int64_t A, int32_t n_tok);
+/* Forward pass: d_obs [A * (n_tok - rec)][6], d_mask, d_hidden_in [A][64]
+ * (rec = 1; NULL: zeros) -> d_logits [A][8] (may be NULL), d_feat [A][64]
+ * (the head's inputs, may be NULL); the tape stays in d_work for
+ * policy_train_backward. Errors: MIL_EINVAL (sizes, A < 1, null inputs),
+ * MIL_ESHAPE, MIL_EALIGN, MIL_EHIP. */
+int policy_train_forward(int64_t A, int32_t n_tok, int32_t rec, const float *d_obs,
+                         const uint8_t *d_mask, const float *d_hidden_in, const float *d_params,
+                         float *d_logits, float *d_feat, void *d_work, int64_t work_bytes,
+                         void *stream);
+/* The critic's forward pass on N global states (tokens as critic_forward;
+ * rec = 1: the recurrent critic's step, entity tokens after the carried state
+ * d_hidden_in) -> d_values [N], d_feat [N][64] (may be NULL); the tape is
+ * that of policy_train_forward with A = N, n_tok = n_agents + n_targets + 1. */
+int critic_train_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
+                         float pos_scale, int32_t rec, const float *d_hidden_in,
+                         const float *d_params, float *d_values, float *d_feat, void *d_work,
+                         int64_t work_bytes, void *stream);
+/* Reverse pass of the last forward pass recorded in d_work (same A, n_tok,
+ * rec, parameters): d_dout [A][ld] the loss gradient at the first n_out
+ * outputs (ppo_objective's d_dlogits with ld 8; the critic's d_dvalues with
+ * ld 1, n_out 1) -> d_grad [policy_num_params()] (overwritten; layout of the
+ * parameters), d_dhidden [A][64] (rec = 1, may be NULL) the gradient at the
+ * carried state. Errors as for policy_train_forward. */
+int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_params,
+                          const float *d_dout, int32_t ld, int32_t n_out, float *d_grad,
+                          float *d_dhidden, void *d_work, int64_t work_bytes, void *stream);
 /* Generalised advantage estimation (Schulman et al. 2016; the advantage
  * estimator of MAPPO) over T steps of E envs with the env's shared reward:
  * d_rewards [T][E], d_dones [T][E] (1: the step ends its episode, nothing is

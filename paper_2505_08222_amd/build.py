@@ -11,7 +11,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmilrauv.so")
 SOURCES = ["env_kernels.hip", "est_kernels.hip", "learned_kernels.hip", "policy_kernels.hip",
-           "pf_kernels.hip", "ppo_kernels.hip", "noalloc.hip", "abi.cpp", "learned_abi.cpp"]
+           "pf_kernels.hip", "ppo_kernels.hip", "train_kernels.hip", "noalloc.hip", "abi.cpp",
+           "learned_abi.cpp", "train_abi.cpp"]
 ARCH = "gfx950"
 
 
@@ -56,7 +57,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    # rocBLAS serves the plain FP32 GEMMs of the networks' training form
+    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

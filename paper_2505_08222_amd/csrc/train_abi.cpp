@@ -1,0 +1,274 @@
+// C ABI of the attention networks' training form (declared in
+// include/mi_lrauv.h, "learner"): the FP32 forward pass that records its
+// tape in the caller's workspace, the reverse pass into the parameter
+// gradient, and the critic's variant on global states. Per-row work runs in
+// train_kernels.hip; the dense products are plain FP32 GEMMs and column sums
+// in rocBLAS (atomics off: results do not depend on the run).
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+
+#include "mi_lrauv.h"
+#include "policy_internal.h"
+#include "train_internal.h"
+
+extern "C" int mil_set_error(int code, const char *msg);  // abi.cpp
+
+namespace {
+
+constexpr int D = mil::kPolD, F = mil::kPolF, L = mil::kPolLayers, NA = mil::kPolActions;
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// Workspace: the tape (per layer the inputs of every operation) and the
+// reverse pass's scratch, all [rows][...] FP32 unless stated.
+struct TrainWork {
+  int64_t tok, tmask, xaug, mrow, ones, h[L + 1], a1[L], qkv[L], P[L], o[L], hmid[L], a2[L], z[L],
+      f[L], feat, dh, t64, dyx, dqkv, dz, dl8, gfa, bfa, gaug, total;
+};
+
+TrainWork train_work(int64_t A, int nt) {
+  const int64_t R = A * nt;
+  TrainWork w{};
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  w.tok = take(R * 6 * 4);
+  w.tmask = take(R);
+  w.xaug = take(R * 8 * 4);
+  w.mrow = take(R);
+  w.ones = take((R > A ? R : A) * 4);
+  for (int l = 0; l <= L; ++l) w.h[l] = take(R * D * 4);
+  for (int l = 0; l < L; ++l) {
+    w.a1[l] = take(R * D * 4);
+    w.qkv[l] = take(R * 3 * D * 4);
+    w.P[l] = take(A * mil::kPolHeads * nt * nt * 4);
+    w.o[l] = take(R * D * 4);
+    w.hmid[l] = take(R * D * 4);
+    w.a2[l] = take(R * D * 4);
+    w.z[l] = take(R * F * 4);
+    w.f[l] = take(R * F * 4);
+  }
+  w.feat = take(A * D * 4);
+  w.dh = take(R * D * 4);
+  w.t64 = take(R * D * 4);
+  w.dyx = take(R * D * 4);
+  w.dqkv = take(R * 3 * D * 4);
+  w.dz = take(R * F * 4);
+  w.dl8 = take(A * NA * 4);
+  w.gfa = take(A * D * 4);
+  w.bfa = take(A * D * 4);
+  w.gaug = take(D * 8 * 4);
+  w.total = o;
+  return w;
+}
+
+// One rocBLAS handle per device, made on first use (pointer mode host,
+// atomics off so that every sum is taken in one order).
+rocblas_handle blas_for_current_device() {
+  static rocblas_handle handles[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  if (!handles[dev]) {
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
+    rocblas_set_pointer_mode(h, rocblas_pointer_mode_host);
+    rocblas_set_atomics_mode(h, rocblas_atomics_not_allowed);
+    handles[dev] = h;
+  }
+  return handles[dev];
+}
+
+struct Ctx {
+  rocblas_handle h;
+  void *stream;
+  bool ok = true;
+  // Y [R][N] = X [R][K] W^T (W [N][K] row-major), added to Y when beta = 1
+  void xwt(const float *X, const float *W, float *Y, int64_t R, int N, int K, float beta) {
+    const float one = 1.0f;
+    ok = ok && rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, N, (int)R, K,
+                             &one, W, K, X, K, &beta, Y, N) == rocblas_status_success;
+  }
+  // dX [R][K] = dY [R][N] W [N][K] (+ dX when beta = 1)
+  void xw(const float *dY, const float *W, float *dX, int64_t R, int N, int K, float beta) {
+    const float one = 1.0f;
+    ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, K, (int)R, N, &one,
+                             W, K, dY, N, &beta, dX, K) == rocblas_status_success;
+  }
+  // dW [N][K] = dY^T X summed over the R rows
+  void dw(const float *dY, const float *X, float *dW, int64_t R, int N, int K) {
+    const float one = 1.0f, zero = 0.0f;
+    ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)R,
+                             &one, X, K, dY, N, &zero, dW, K) == rocblas_status_success;
+  }
+  // out [N] = column sums of Y [R][N]
+  void colsum(const float *Y, const float *ones, float *out, int64_t R, int N) {
+    const float one = 1.0f, zero = 0.0f;
+    ok = ok && rocblas_sgemv(h, rocblas_operation_none, N, (int)R, &one, Y, N, ones, 1, &zero, out,
+                             1) == rocblas_status_success;
+  }
+  void k(int rc) { ok = ok && rc == 0; }
+};
+
+int check_args(int64_t A, int32_t n_tok, int32_t rec, void *d_work, int64_t work_bytes) {
+  if (A < 1 || rec < 0 || rec > 1 || n_tok < 1 + rec || n_tok > mil::kPolMaxTok ||
+      A * n_tok > INT32_MAX / (3 * D))
+    return mil_set_error(MIL_EINVAL, "need A >= 1, rec in {0, 1}, n_tok in 1 + rec..16");
+  if (!d_work || (((uintptr_t)d_work) & 255))
+    return mil_set_error(MIL_EALIGN, "workspace must be 256-byte aligned");
+  if (work_bytes < train_work(A, n_tok).total)
+    return mil_set_error(MIL_ESHAPE, "workspace too small (policy_train_workspace_bytes)");
+  return MIL_OK;
+}
+
+int train_forward(int64_t A, int nt, int rec, const float *obs, const uint8_t *mask,
+                  const float *hidden, const float *prm, float *logits, float *feat_out,
+                  char *ws, void *stream) {
+  rocblas_handle bh = blas_for_current_device();
+  if (!bh || rocblas_set_stream(bh, (hipStream_t)stream) != rocblas_status_success)
+    return mil_set_error(MIL_EHIP, "rocBLAS handle unavailable");
+  const TrainWork w = train_work(A, nt);
+  const int64_t R = A * nt;
+  auto fp = [&](int64_t off) { return (float *)(ws + off); };
+  Ctx c{bh, stream};
+  uint8_t *mrow = (uint8_t *)(ws + w.mrow);
+  c.k(mil::tr_fill(fp(w.ones), 1.0f, R > A ? R : A, stream));
+  c.k(mil::tr_embed(obs, mask, R, nt, rec, hidden, prm, fp(w.h[0]), fp(w.xaug), mrow, stream));
+  for (int l = 0; l < L && c.ok; ++l) {
+    const float *lp = prm + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
+    c.k(mil::tr_layernorm(fp(w.h[l]), lp + mil::kPolLn1G, lp + mil::kPolLn1B, fp(w.a1[l]), R,
+                          stream));
+    c.k(mil::tr_bias_rows(nullptr, lp + mil::kPolBqkv, R, 3 * D, fp(w.qkv[l]), stream));
+    c.xwt(fp(w.a1[l]), lp + mil::kPolWqkv, fp(w.qkv[l]), R, 3 * D, D, 1.0f);
+    c.k(mil::tr_attention(fp(w.qkv[l]), mrow, A, nt, fp(w.P[l]), fp(w.o[l]), stream));
+    c.k(mil::tr_bias_rows(fp(w.h[l]), lp + mil::kPolBo, R, D, fp(w.hmid[l]), stream));
+    c.xwt(fp(w.o[l]), lp + mil::kPolWo, fp(w.hmid[l]), R, D, D, 1.0f);
+    c.k(mil::tr_layernorm(fp(w.hmid[l]), lp + mil::kPolLn2G, lp + mil::kPolLn2B, fp(w.a2[l]), R,
+                          stream));
+    c.k(mil::tr_bias_rows(nullptr, lp + mil::kPolB1, R, F, fp(w.z[l]), stream));
+    c.xwt(fp(w.a2[l]), lp + mil::kPolW1, fp(w.z[l]), R, F, D, 1.0f);
+    c.k(mil::tr_gelu(fp(w.z[l]), fp(w.f[l]), R * F, stream));
+    c.k(mil::tr_bias_rows(fp(w.hmid[l]), lp + mil::kPolB2, R, D, fp(w.h[l + 1]), stream));
+    c.xwt(fp(w.f[l]), lp + mil::kPolW2, fp(w.h[l + 1]), R, D, F, 1.0f);
+  }
+  c.k(mil::tr_head(fp(w.h[L]), A, nt, prm, logits, fp(w.feat), stream));
+  if (feat_out && c.ok)
+    c.ok = hipMemcpyAsync(feat_out, fp(w.feat), A * D * 4, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream) == hipSuccess;
+  return c.ok ? MIL_OK : mil_set_error(MIL_EHIP, "training forward launch failed");
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t policy_train_workspace_bytes(int64_t A, int32_t n_tok) {
+  if (A < 1 || n_tok < 1 || n_tok > mil::kPolMaxTok) return -1;
+  return train_work(A, n_tok).total;
+}
+
+int policy_train_forward(int64_t A, int32_t n_tok, int32_t rec, const float *d_obs,
+                         const uint8_t *d_mask, const float *d_hidden_in, const float *d_params,
+                         float *d_logits, float *d_feat, void *d_work, int64_t work_bytes,
+                         void *stream) {
+  int rc = check_args(A, n_tok, rec, d_work, work_bytes);
+  if (rc) return rc;
+  if (!d_obs || !d_mask || !d_params) return mil_set_error(MIL_EINVAL, "null argument");
+  return train_forward(A, n_tok, rec, d_obs, d_mask, d_hidden_in, d_params, d_logits, d_feat,
+                       (char *)d_work, stream);
+}
+
+int critic_train_forward(const float *d_gstate, int64_t N, int32_t n_agents, int32_t n_targets,
+                         float pos_scale, int32_t rec, const float *d_hidden_in,
+                         const float *d_params, float *d_values, float *d_feat, void *d_work,
+                         int64_t work_bytes, void *stream) {
+  if (n_agents < 1 || n_targets < 1 || n_agents + n_targets + 1 > mil::kPolMaxTok)
+    return mil_set_error(MIL_EINVAL, "need 1 + n_agents + n_targets <= 16");
+  if (!(pos_scale > 0.0f)) return mil_set_error(MIL_EINVAL, "pos_scale must be > 0");
+  const int M = n_agents + n_targets, nt = M + 1;
+  int rc = check_args(N, nt, rec, d_work, work_bytes);
+  if (rc) return rc;
+  if (!d_gstate || !d_params || !d_values) return mil_set_error(MIL_EINVAL, "null argument");
+  char *ws = (char *)d_work;
+  const TrainWork w = train_work(N, nt);
+  float *tok = (float *)(ws + w.tok);
+  uint8_t *tmask = (uint8_t *)(ws + w.tmask);
+  // plain: the all-zero value token then the entities; recurrent: the
+  // entities (the carried state takes the first row)
+  if (mil::launch_critic_tokens(d_gstate, N, M, 1 - rec, pos_scale, tok, tmask, stream))
+    return mil_set_error(MIL_EHIP, "critic token launch failed");
+  float *logits = (float *)(ws + w.dz);  // free until the reverse pass
+  rc = train_forward(N, nt, rec, tok, tmask, d_hidden_in, d_params, logits, d_feat, ws, stream);
+  if (rc) return rc;
+  if (mil::launch_first_column(logits, N, d_values, stream))
+    return mil_set_error(MIL_EHIP, "critic value launch failed");
+  return MIL_OK;
+}
+
+int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_params,
+                          const float *d_dout, int32_t ld, int32_t n_out, float *d_grad,
+                          float *d_dhidden, void *d_work, int64_t work_bytes, void *stream) {
+  int rc = check_args(A, n_tok, rec, d_work, work_bytes);
+  if (rc) return rc;
+  if (n_out < 1 || n_out > NA || ld < n_out)
+    return mil_set_error(MIL_EINVAL, "need n_out in 1..8 and ld >= n_out");
+  if (!d_params || !d_dout || !d_grad) return mil_set_error(MIL_EINVAL, "null argument");
+  rocblas_handle bh = blas_for_current_device();
+  if (!bh || rocblas_set_stream(bh, (hipStream_t)stream) != rocblas_status_success)
+    return mil_set_error(MIL_EHIP, "rocBLAS handle unavailable");
+  char *ws = (char *)d_work;
+  const int nt = n_tok;
+  const TrainWork w = train_work(A, nt);
+  const int64_t R = A * nt;
+  auto fp = [&](int64_t off) { return (float *)(ws + off); };
+  const uint8_t *mrow = (const uint8_t *)(ws + w.mrow);
+  const float *ones = fp(w.ones);
+  float *dh = fp(w.dh), *t64 = fp(w.t64), *dyx = fp(w.dyx);
+  Ctx c{bh, stream};
+  float *gfin = d_grad + mil::kPolOffFinal;
+  // head and final LayerNorm (each agent's first row)
+  c.k(mil::tr_fill(dh, 0.0f, R * D, stream));
+  c.k(mil::tr_head_back(fp(w.h[L]), A, nt, d_params, d_dout, ld, n_out, fp(w.dl8), dh, fp(w.gfa),
+                        fp(w.bfa), stream));
+  c.dw(fp(w.dl8), fp(w.feat), gfin + mil::kPolWh, A, NA, D);
+  c.colsum(fp(w.dl8), ones, gfin + mil::kPolBh, A, NA);
+  c.colsum(fp(w.gfa), ones, gfin + mil::kPolLnfG, A, D);
+  c.colsum(fp(w.bfa), ones, gfin + mil::kPolLnfB, A, D);
+  for (int l = L - 1; l >= 0 && c.ok; --l) {
+    const float *lp = d_params + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
+    float *gp = d_grad + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
+    // feed-forward block: h[l + 1] = hmid + W2 gelu(z) + b2
+    c.colsum(dh, ones, gp + mil::kPolB2, R, D);
+    c.dw(dh, fp(w.f[l]), gp + mil::kPolW2, R, D, F);
+    c.xw(dh, lp + mil::kPolW2, fp(w.dz), R, D, F, 0.0f);
+    c.k(mil::tr_gelu_back(fp(w.dz), fp(w.z[l]), R * F, stream));
+    c.colsum(fp(w.dz), ones, gp + mil::kPolB1, R, F);
+    c.dw(fp(w.dz), fp(w.a2[l]), gp + mil::kPolW1, R, F, D);
+    c.xw(fp(w.dz), lp + mil::kPolW1, t64, R, F, D, 0.0f);
+    c.k(mil::tr_layernorm_back(fp(w.hmid[l]), lp + mil::kPolLn2G, t64, dh, dyx, R, stream));
+    c.colsum(dyx, ones, gp + mil::kPolLn2G, R, D);
+    c.colsum(t64, ones, gp + mil::kPolLn2B, R, D);
+    // attention block: hmid = h[l] + Wo attention(LN1(h[l])) + bo
+    c.colsum(dh, ones, gp + mil::kPolBo, R, D);
+    c.dw(dh, fp(w.o[l]), gp + mil::kPolWo, R, D, D);
+    c.xw(dh, lp + mil::kPolWo, t64, R, D, D, 0.0f);
+    c.k(mil::tr_attention_back(fp(w.qkv[l]), fp(w.P[l]), mrow, t64, A, nt, fp(w.dqkv), stream));
+    c.colsum(fp(w.dqkv), ones, gp + mil::kPolBqkv, R, 3 * D);
+    c.dw(fp(w.dqkv), fp(w.a1[l]), gp + mil::kPolWqkv, R, 3 * D, D);
+    c.xw(fp(w.dqkv), lp + mil::kPolWqkv, t64, R, 3 * D, D, 0.0f);
+    c.k(mil::tr_layernorm_back(fp(w.h[l]), lp + mil::kPolLn1G, t64, dh, dyx, R, stream));
+    c.colsum(dyx, ones, gp + mil::kPolLn1G, R, D);
+    c.colsum(t64, ones, gp + mil::kPolLn1B, R, D);
+  }
+  // embedding (observed rows; a carried row's augmented input is zero)
+  c.dw(dh, fp(w.xaug), fp(w.gaug), R, D, 8);
+  c.k(mil::tr_embed_grad_scatter(fp(w.gaug), d_grad, stream));
+  if (d_dhidden && rec) c.k(mil::tr_first_rows(dh, A, nt, d_dhidden, stream));
+  return c.ok ? MIL_OK : mil_set_error(MIL_EHIP, "training backward launch failed");
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Launchers of train_kernels.hip: the per-row and per-(agent, head) parts of
+// the attention networks' FP32 training forward pass (with its tape) and of
+// its reverse pass. Row-major arrays; an agent's n_tok rows are consecutive.
+#pragma once
+#include <stdint.h>
+
+namespace mil {
+
+// h [R][64] = embedding of each observed row, or the carried state (rec = 1,
+// the first row of each agent; NULL hidden: zeros); xaug [R][8] = (x, 1, 0)
+// or zeros for a carried row; mrow [R] = key mask (1 for a carried row).
+int tr_embed(const float *obs, const uint8_t *mask, int64_t R, int nt, int rec,
+             const float *hidden, const float *prm, float *h, float *xaug, uint8_t *mrow,
+             void *stream);
+int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64_t R, void *stream);
+// out [R][N] = base (NULL: 0) + bias broadcast over rows
+int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *out, void *stream);
+int tr_gelu(const float *z, float *f, int64_t n, void *stream);
+int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream);
+// qkv [R][192] -> P [A][4][nt][nt] (softmax over unmasked keys), o [R][64]
+int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float *P, float *o,
+                 void *stream);
+// dout [R][64] (gradient at o) -> dqkv [R][192]
+int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, const float *dout,
+                      int64_t A, int nt, float *dqkv, void *stream);
+// dxacc += LayerNorm input gradient; dyxhat = dy * xhat
+int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dxacc, float *dyxhat,
+                      int64_t R, void *stream);
+// final LayerNorm of each agent's first row -> feat [A][64], logits [A][8] (may be NULL)
+int tr_head(const float *h, int64_t A, int nt, const float *prm, float *logits, float *feat,
+            void *stream);
+int tr_head_back(const float *h, int64_t A, int nt, const float *prm, const float *dout, int ld,
+                 int n_out, float *dl8, float *dh, float *gfa, float *bfa, void *stream);
+int tr_embed_grad_scatter(const float *gaug, float *grad, void *stream);
+int tr_first_rows(const float *dh, int64_t A, int nt, float *out, void *stream);
+int tr_fill(float *p, float v, int64_t n, void *stream);
+
+}  // namespace mil

@@ -1,0 +1,413 @@
+// Training form of the attention networks (the learner's update: MAPPO's
+// gradient step, Sec. III-B, through the TransfMAPPO actor and critic of
+// Fig. 3): the per-row and per-(agent, head) parts of an FP32 forward pass
+// that keeps every intermediate on a tape, and of its exact reverse pass.
+// The dense products between them (each layer's projections, their input
+// gradients and the weight gradients summed over all rows) are plain FP32
+// GEMMs issued by the host side (train_abi.cpp).
+//
+// Rows: an agent's n_tok rows are consecutive ([A][n_tok][64] residual
+// stream); in the recurrent form its first row is the carried state and its
+// n_tok - 1 observed tokens follow.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "policy_internal.h"
+#include "train_internal.h"
+
+namespace mil {
+namespace {
+
+constexpr int kTrThreads = 256;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ float gelu_tanh(float x) {
+  const float c = 0.7978845608028654f;  // sqrt(2 / pi)
+  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+
+__device__ __forceinline__ float gelu_tanh_grad(float x) {
+  const float c = 0.7978845608028654f;
+  const float t = tanhf(c * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+// Thread (row r, feature d): the row's embedding E x + e (or the carried
+// state), its augmented input (x, 1) for the embedding gradient (zeros for
+// the carried row) and its key mask.
+__global__ void __launch_bounds__(kTrThreads)
+embed_kernel(const float *__restrict__ obs, const uint8_t *__restrict__ mask, int64_t R, int nt,
+             int rec, const float *__restrict__ hidden, const float *__restrict__ prm,
+             float *__restrict__ h, float *__restrict__ xaug, uint8_t *__restrict__ mrow) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * kPolD) return;
+  const int64_t r = i / kPolD;
+  const int d = (int)(i - r * kPolD);
+  const int64_t a = r / nt;
+  const int k = (int)(r - a * nt);
+  const float *E = prm + kPolOffEmbW, *e = prm + kPolOffEmbB;
+  if (rec && k == 0) {
+    h[i] = hidden ? hidden[a * kPolD + d] : 0.0f;
+    if (d < 8) xaug[r * 8 + d] = 0.0f;
+    if (d == 0) mrow[r] = 1;
+    return;
+  }
+  const int64_t orow = rec ? a * (nt - 1) + (k - 1) : r;
+  const float *x = obs + orow * 6;
+  float acc = e[d];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) acc = fmaf(E[d * 6 + c], x[c], acc);
+  h[i] = acc;
+  if (d < 6) xaug[r * 8 + d] = x[d];
+  if (d == 6) xaug[r * 8 + 6] = 1.0f;
+  if (d == 7) xaug[r * 8 + 7] = 0.0f;
+  if (d == 0) mrow[r] = mask[orow];
+}
+
+// One wavefront per row, lane d = feature d.
+__global__ void __launch_bounds__(kTrThreads)
+layernorm_kernel(const float *__restrict__ x, const float *__restrict__ g,
+                 const float *__restrict__ b, float *__restrict__ y, int64_t R) {
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int d = threadIdx.x & 63;
+  if (r >= R) return;
+  const float v = x[r * kPolD + d];
+  const float m = wave_sum(v) * (1.0f / kPolD);
+  const float c = v - m;
+  const float rs = rsqrtf(wave_sum(c * c) * (1.0f / kPolD) + 1e-5f);
+  y[r * kPolD + d] = fmaf(c * rs, g[d], b[d]);
+}
+
+// out[r][n] = base[r][n] (or 0) + bias[n]: a GEMM then adds its product.
+__global__ void __launch_bounds__(kTrThreads)
+bias_rows_kernel(const float *__restrict__ base, const float *__restrict__ bias, int64_t R, int N,
+                 float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * N) return;
+  const int n = (int)(i % N);
+  out[i] = (base ? base[i] : 0.0f) + bias[n];
+}
+
+__global__ void __launch_bounds__(kTrThreads)
+gelu_kernel(const float *__restrict__ z, float *__restrict__ f, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = gelu_tanh(z[i]);
+}
+
+__global__ void __launch_bounds__(kTrThreads)
+gelu_back_kernel(float *__restrict__ dz, const float *__restrict__ z, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dz[i] *= gelu_tanh_grad(z[i]);
+}
+
+// Thread (agent, head, query t): scores q.k / 4 over the agent's unmasked
+// keys, softmax (kept), and the head's output o = P V.
+__global__ void __launch_bounds__(kTrThreads)
+attention_kernel(const float *__restrict__ qkv, const uint8_t *__restrict__ mrow, int64_t A,
+                 int nt, float *__restrict__ P, float *__restrict__ o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A * kPolHeads * nt) return;
+  const int t = (int)(i % nt);
+  const int64_t ah = i / nt;
+  const int hd = (int)(ah % kPolHeads);
+  const int64_t a = ah / kPolHeads;
+  const int64_t r0 = a * nt;
+  const float *q = qkv + (r0 + t) * 3 * kPolD + hd * kPolDh;
+  float s[kPolMaxTok];
+  float mx = -INFINITY;
+  for (int u = 0; u < nt; ++u) {
+    s[u] = -INFINITY;
+    if (!mrow[r0 + u]) continue;
+    const float *k = qkv + (r0 + u) * 3 * kPolD + kPolD + hd * kPolDh;
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kPolDh; ++c) acc = fmaf(q[c], k[c], acc);
+    s[u] = acc * 0.25f;
+    mx = fmaxf(mx, s[u]);
+  }
+  float z = 0.0f;
+  for (int u = 0; u < nt; ++u) {
+    s[u] = mrow[r0 + u] ? expf(s[u] - mx) : 0.0f;
+    z += s[u];
+  }
+  const float iz = 1.0f / z;
+  float *pr = P + i * nt;
+  float acc[kPolDh];
+#pragma unroll
+  for (int c = 0; c < kPolDh; ++c) acc[c] = 0.0f;
+  for (int u = 0; u < nt; ++u) {
+    const float p = s[u] * iz;
+    pr[u] = p;
+    const float *v = qkv + (r0 + u) * 3 * kPolD + 2 * kPolD + hd * kPolDh;
+#pragma unroll
+    for (int c = 0; c < kPolDh; ++c) acc[c] = fmaf(p, v[c], acc[c]);
+  }
+  float *out = o + (r0 + t) * kPolD + hd * kPolDh;
+#pragma unroll
+  for (int c = 0; c < kPolDh; ++c) out[c] = acc[c];
+}
+
+// Thread (agent, head): the reverse of attention_kernel for all the agent's
+// queries and keys: dP = dO V^T, dS = P (dP - sum P dP) / 4, dQ = dS K,
+// dK = dS^T Q, dV = P^T dO, written into dqkv (this head's columns).
+__global__ void __launch_bounds__(kTrThreads)
+attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P,
+                      const uint8_t *__restrict__ mrow, const float *__restrict__ dout, int64_t A,
+                      int nt, float *__restrict__ dqkv) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A * kPolHeads) return;
+  const int hd = (int)(i % kPolHeads);
+  const int64_t a = i / kPolHeads;
+  const int64_t r0 = a * nt;
+  const int qo = hd * kPolDh, ko = kPolD + hd * kPolDh, vo = 2 * kPolD + hd * kPolDh;
+  for (int u = 0; u < nt; ++u)
+#pragma unroll
+    for (int c = 0; c < kPolDh; ++c) {
+      float *row = dqkv + (r0 + u) * 3 * kPolD;
+      row[qo + c] = 0.0f;
+      row[ko + c] = 0.0f;
+      row[vo + c] = 0.0f;
+    }
+  for (int t = 0; t < nt; ++t) {
+    const float *pr = P + (i * nt + t) * nt;
+    const float *dot_ = dout + (r0 + t) * kPolD + qo;
+    float dP[kPolMaxTok];
+    float dsum = 0.0f;
+    for (int u = 0; u < nt; ++u) {
+      const float *v = qkv + (r0 + u) * 3 * kPolD + vo;
+      float *dv = dqkv + (r0 + u) * 3 * kPolD + vo;
+      float acc = 0.0f;
+#pragma unroll
+      for (int c = 0; c < kPolDh; ++c) {
+        acc = fmaf(dot_[c], v[c], acc);
+        dv[c] = fmaf(pr[u], dot_[c], dv[c]);
+      }
+      dP[u] = acc;
+      dsum = fmaf(pr[u], acc, dsum);
+    }
+    const float *q = qkv + (r0 + t) * 3 * kPolD + qo;
+    float *dq = dqkv + (r0 + t) * 3 * kPolD + qo;
+    for (int u = 0; u < nt; ++u) {
+      if (!mrow[r0 + u]) continue;
+      const float ds = pr[u] * (dP[u] - dsum) * 0.25f;
+      const float *k = qkv + (r0 + u) * 3 * kPolD + ko;
+      float *dk = dqkv + (r0 + u) * 3 * kPolD + ko;
+#pragma unroll
+      for (int c = 0; c < kPolDh; ++c) {
+        dq[c] = fmaf(ds, k[c], dq[c]);
+        dk[c] = fmaf(ds, q[c], dk[c]);
+      }
+    }
+  }
+}
+
+// One wavefront per row: LayerNorm's reverse pass. dx is added to dxacc;
+// dyxhat = dy * xhat (its column sums are the gain's gradient).
+__global__ void __launch_bounds__(kTrThreads)
+layernorm_back_kernel(const float *__restrict__ x, const float *__restrict__ g,
+                      const float *__restrict__ dy, float *__restrict__ dxacc,
+                      float *__restrict__ dyxhat, int64_t R) {
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int d = threadIdx.x & 63;
+  if (r >= R) return;
+  const int64_t i = r * kPolD + d;
+  const float v = x[i];
+  const float m = wave_sum(v) * (1.0f / kPolD);
+  const float c = v - m;
+  const float rs = rsqrtf(wave_sum(c * c) * (1.0f / kPolD) + 1e-5f);
+  const float xh = c * rs, gy = dy[i];
+  const float dxh = gy * g[d];
+  const float s1 = wave_sum(dxh) * (1.0f / kPolD), s2 = wave_sum(dxh * xh) * (1.0f / kPolD);
+  dxacc[i] += rs * (dxh - s1 - xh * s2);
+  dyxhat[i] = gy * xh;
+}
+
+// One wavefront per agent: final LayerNorm of its first row and the head.
+__global__ void __launch_bounds__(kTrThreads)
+head_kernel(const float *__restrict__ h, int64_t A, int nt, const float *__restrict__ prm,
+            float *__restrict__ logits, float *__restrict__ feat) {
+  const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int d = threadIdx.x & 63;
+  if (a >= A) return;
+  const float *fp = prm + kPolOffFinal;
+  const float v = h[a * nt * kPolD + d];
+  const float m = wave_sum(v) * (1.0f / kPolD);
+  const float c = v - m;
+  const float rs = rsqrtf(wave_sum(c * c) * (1.0f / kPolD) + 1e-5f);
+  const float s = fmaf(c * rs, fp[kPolLnfG + d], fp[kPolLnfB + d]);
+  feat[a * kPolD + d] = s;
+#pragma unroll
+  for (int k = 0; k < kPolActions; ++k) {
+    const float y = wave_sum(fp[kPolWh + k * kPolD + d] * s);
+    if (d == 0 && logits) logits[a * kPolActions + k] = y + fp[kPolBh + k];
+  }
+}
+
+// One wavefront per agent: the head's and the final LayerNorm's reverse
+// pass. dl8 [A][8] = the output gradients padded with zeros (for the head's
+// weight gradient), dh row 0 of the agent = the LayerNorm's input gradient
+// (dh zero elsewhere beforehand), gfa / bfa [A][64] the per-agent terms of
+// the final LayerNorm's gain and offset gradients.
+__global__ void __launch_bounds__(kTrThreads)
+head_back_kernel(const float *__restrict__ h, int64_t A, int nt, const float *__restrict__ prm,
+                 const float *__restrict__ dout, int ld, int n_out, float *__restrict__ dl8,
+                 float *__restrict__ dh, float *__restrict__ gfa, float *__restrict__ bfa) {
+  const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int d = threadIdx.x & 63;
+  if (a >= A) return;
+  const float *fp = prm + kPolOffFinal;
+  float ds = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kPolActions; ++k) {
+    const float gk = k < n_out ? dout[a * ld + k] : 0.0f;
+    if (d == k) dl8[a * kPolActions + k] = gk;
+    ds = fmaf(gk, fp[kPolWh + k * kPolD + d], ds);
+  }
+  const int64_t i = a * nt * kPolD + d;
+  const float v = h[i];
+  const float m = wave_sum(v) * (1.0f / kPolD);
+  const float c = v - m;
+  const float rs = rsqrtf(wave_sum(c * c) * (1.0f / kPolD) + 1e-5f);
+  const float xh = c * rs;
+  const float dxh = ds * fp[kPolLnfG + d];
+  const float s1 = wave_sum(dxh) * (1.0f / kPolD), s2 = wave_sum(dxh * xh) * (1.0f / kPolD);
+  dh[i] = rs * (dxh - s1 - xh * s2);
+  gfa[a * kPolD + d] = ds * xh;
+  bfa[a * kPolD + d] = ds;
+}
+
+// Embedding gradient [64][8] (E's six columns, e, padding) into the
+// parameter layout.
+__global__ void embed_grad_scatter_kernel(const float *__restrict__ gaug,
+                                          float *__restrict__ grad) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i >= kPolD * 7) return;
+  const int d = i / 7, c = i - d * 7;
+  if (c < 6)
+    grad[kPolOffEmbW + d * 6 + c] = gaug[d * 8 + c];
+  else
+    grad[kPolOffEmbB + d] = gaug[d * 8 + 6];
+}
+
+// The gradient at each agent's carried state (its first row).
+__global__ void __launch_bounds__(kTrThreads)
+first_rows_kernel(const float *__restrict__ dh, int64_t A, int nt, float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A * kPolD) return;
+  const int64_t a = i / kPolD;
+  out[i] = dh[a * nt * kPolD + (i - a * kPolD)];
+}
+
+__global__ void __launch_bounds__(kTrThreads)
+fill_kernel(float *__restrict__ p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+int check() { return hipGetLastError() == hipSuccess ? 0 : -1; }
+
+dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kTrThreads - 1) / kTrThreads)); }
+
+}  // namespace
+
+int tr_embed(const float *obs, const uint8_t *mask, int64_t R, int nt, int rec,
+             const float *hidden, const float *prm, float *h, float *xaug, uint8_t *mrow,
+             void *stream) {
+  if (R == 0) return 0;
+  hipLaunchKernelGGL(embed_kernel, grid_for(R * kPolD), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     obs, mask, R, nt, rec, hidden, prm, h, xaug, mrow);
+  return check();
+}
+
+int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64_t R, void *stream) {
+  if (R == 0) return 0;
+  hipLaunchKernelGGL(layernorm_kernel, grid_for(R * 64), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     x, g, b, y, R);
+  return check();
+}
+
+int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *out, void *stream) {
+  if (R == 0) return 0;
+  hipLaunchKernelGGL(bias_rows_kernel, grid_for(R * N), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     base, bias, R, N, out);
+  return check();
+}
+
+int tr_gelu(const float *z, float *f, int64_t n, void *stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(gelu_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, z, f, n);
+  return check();
+}
+
+int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(gelu_back_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, dz,
+                     z, n);
+  return check();
+}
+
+int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float *P, float *o,
+                 void *stream) {
+  if (A == 0) return 0;
+  hipLaunchKernelGGL(attention_kernel, grid_for(A * kPolHeads * nt), dim3(kTrThreads), 0,
+                     (hipStream_t)stream, qkv, mrow, A, nt, P, o);
+  return check();
+}
+
+int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, const float *dout,
+                      int64_t A, int nt, float *dqkv, void *stream) {
+  if (A == 0) return 0;
+  hipLaunchKernelGGL(attention_back_kernel, grid_for(A * kPolHeads), dim3(kTrThreads), 0,
+                     (hipStream_t)stream, qkv, P, mrow, dout, A, nt, dqkv);
+  return check();
+}
+
+int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dxacc, float *dyxhat,
+                      int64_t R, void *stream) {
+  if (R == 0) return 0;
+  hipLaunchKernelGGL(layernorm_back_kernel, grid_for(R * 64), dim3(kTrThreads), 0,
+                     (hipStream_t)stream, x, g, dy, dxacc, dyxhat, R);
+  return check();
+}
+
+int tr_head(const float *h, int64_t A, int nt, const float *prm, float *logits, float *feat,
+            void *stream) {
+  if (A == 0) return 0;
+  hipLaunchKernelGGL(head_kernel, grid_for(A * 64), dim3(kTrThreads), 0, (hipStream_t)stream, h, A,
+                     nt, prm, logits, feat);
+  return check();
+}
+
+int tr_head_back(const float *h, int64_t A, int nt, const float *prm, const float *dout, int ld,
+                 int n_out, float *dl8, float *dh, float *gfa, float *bfa, void *stream) {
+  if (A == 0) return 0;
+  hipLaunchKernelGGL(head_back_kernel, grid_for(A * 64), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     h, A, nt, prm, dout, ld, n_out, dl8, dh, gfa, bfa);
+  return check();
+}
+
+int tr_embed_grad_scatter(const float *gaug, float *grad, void *stream) {
+  hipLaunchKernelGGL(embed_grad_scatter_kernel, dim3(2), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     gaug, grad);
+  return check();
+}
+
+int tr_first_rows(const float *dh, int64_t A, int nt, float *out, void *stream) {
+  if (A == 0) return 0;
+  hipLaunchKernelGGL(first_rows_kernel, grid_for(A * kPolD), dim3(kTrThreads), 0,
+                     (hipStream_t)stream, dh, A, nt, out);
+  return check();
+}
+
+int tr_fill(float *p, float v, int64_t n, void *stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(fill_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, p, v, n);
+  return check();
+}
+
+}  // namespace mil

@@ -1,8 +1,9 @@
 """The learner (argument marshalling only): critic values of global states,
-generalised advantage estimation, the clipped PPO objective, and the
-gradient and Adam update of the policy's and critic's output heads (MAPPO,
-Sec. III-B; TransformerCritic, Sec. IV-B-1). Every step runs in the HIP
-library; the transformers below the heads are not trained here."""
+generalised advantage estimation, the clipped PPO objective, the gradient
+and Adam update of the output heads, and the networks' training form (an
+FP32 forward pass with its tape and the exact reverse pass into every
+parameter) for the full update (MAPPO, Sec. III-B; TransfMAPPO, Sec. IV-B-1,
+Fig. 3). Every step runs in the HIP library."""
 import ctypes as C
 
 import torch
@@ -31,6 +32,14 @@ def _l():
         L.policy_forward_feat.restype = C.c_int
         L.critic_forward_rec.argtypes = [V, I32, I64, I32, I32, F, V, V, V, V, V, I64, V]
         L.critic_forward_rec.restype = C.c_int
+        L.policy_train_workspace_bytes.argtypes = [I64, I32]
+        L.policy_train_workspace_bytes.restype = I64
+        L.policy_train_forward.argtypes = [I64, I32, I32, V, V, V, V, V, V, V, I64, V]
+        L.policy_train_forward.restype = C.c_int
+        L.critic_train_forward.argtypes = [V, I64, I32, I32, F, I32, V, V, V, V, V, I64, V]
+        L.critic_train_forward.restype = C.c_int
+        L.policy_train_backward.argtypes = [I64, I32, I32, V, V, I32, I32, V, V, V, I64, V]
+        L.policy_train_backward.restype = C.c_int
         L._ppo_registered = True
     return L
 
@@ -152,3 +161,54 @@ class HeadAdam:
         self.step_count += 1
         check(lib().mlp_adam_step(HEAD_PARAMS, ptr(self.head), ptr(grad), ptr(self.m), ptr(self.v),
                                   self.lr, self.b1, self.b2, self.eps, self.step_count, _stream()))
+
+
+class TrainPass:
+    """Workspace and calls of the training form for batches of A agents (or
+    critic states) with n_tok rows each (rec = 1: the recurrent form, the
+    carried state first). forward() records the tape that backward() reads."""
+
+    def __init__(self, A: int, n_tok: int, rec: int = 0, device="cuda"):
+        L = _l()
+        self.A, self.n_tok, self.rec = int(A), int(n_tok), int(rec)
+        n = int(L.policy_train_workspace_bytes(self.A, self.n_tok))
+        assert n > 0, "bad sizes"
+        self._buf = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        off = (-self._buf.data_ptr()) % 256
+        self._w, self._n = C.c_void_p(self._buf.data_ptr() + off), n
+        self.device = device
+
+    def forward(self, obs, mask, params, hidden=None):
+        """obs [A * (n_tok - rec), 6], mask -> (logits [A, 8], features [A, 64])."""
+        logits = torch.empty((self.A, 8), dtype=torch.float32, device=self.device)
+        feat = torch.empty((self.A, 64), dtype=torch.float32, device=self.device)
+        check(_l().policy_train_forward(self.A, self.n_tok, self.rec, ptr(obs.contiguous()),
+                                        ptr(mask.contiguous()), ptr(hidden), ptr(params),
+                                        ptr(logits), ptr(feat), self._w, self._n, _stream()))
+        return logits, feat
+
+    def critic_forward(self, gstate, n_agents: int, n_targets: int, params, hidden=None,
+                       pos_scale: float = 1000.0):
+        """gstate [A, n_agents + n_targets, 6] -> (values [A], features [A, 64])."""
+        assert self.n_tok == n_agents + n_targets + 1
+        g = gstate.reshape(self.A, n_agents + n_targets, 6).contiguous()
+        values = torch.empty(self.A, dtype=torch.float32, device=self.device)
+        feat = torch.empty((self.A, 64), dtype=torch.float32, device=self.device)
+        check(_l().critic_train_forward(ptr(g), self.A, n_agents, n_targets, pos_scale, self.rec,
+                                        ptr(hidden), ptr(params), ptr(values), ptr(feat), self._w,
+                                        self._n, _stream()))
+        return values, feat
+
+    def backward(self, params, dout, n_out: int, grad=None):
+        """dout [A, ld] (or [A]) -> (gradient [P], gradient at the carried
+        state [A, 64] or None)."""
+        d = (dout.reshape(self.A, 1) if dout.dim() == 1
+             else dout.reshape(self.A, dout.shape[-1])).contiguous()
+        if grad is None:
+            grad = torch.empty_like(params)
+        dh = (torch.empty((self.A, 64), dtype=torch.float32, device=self.device)
+              if self.rec else None)
+        check(_l().policy_train_backward(self.A, self.n_tok, self.rec, ptr(params), ptr(d),
+                                         d.shape[1], n_out, ptr(grad), ptr(dh), self._w, self._n,
+                                         _stream()))
+        return grad, dh

@@ -1,0 +1,172 @@
+"""GPU checks of the networks' training form (FP32 forward pass with its
+tape, exact reverse pass) against the FP64 oracle (orc.policy_backward,
+orc.policy_backward_rec, the forwards).
+
+* Forward: logits (or values) within 1e-4 of max(1, max |logit|) of the
+  oracle's (FP32 throughout: no BF16 operands here).
+* Gradient: every parameter group (embedding, per layer the LayerNorms, the
+  Q/K/V projection, attention output, feed-forward, and the final LayerNorm
+  and head) within 2e-4 of that group's largest oracle entry; the carried
+  state's gradient likewise. FP32 sums over up to a few thousand rows against
+  FP64 give errors of order 1e-6 of the scale.
+* Full updates (policy and critic, every parameter, Adam at a small step)
+  lower the surrogate and the value loss at every step.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2505_08222_amd.configs import env_config  # noqa: E402
+from paper_2505_08222_amd.synth import policy_params, policy_tokens  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+D, F, L, NA = 64, 256, 2, 8
+PER_LAYER = 2 * D + 3 * D * D + 3 * D + D * D + D + 2 * D + F * D + F + D * F + D
+GROUPS = [("E", D * 6), ("e", D)] + [
+    (f"{n}{l}", s) for l in range(L) for n, s in (
+        ("ln1g", D), ("ln1b", D), ("Wqkv", 3 * D * D), ("bqkv", 3 * D), ("Wo", D * D),
+        ("bo", D), ("ln2g", D), ("ln2b", D), ("W1", F * D), ("b1", F), ("W2", D * F),
+        ("b2", D))] + [("lnfg", D), ("lnfb", D), ("Wh", NA * D), ("bh", NA)]
+
+
+def _check_grad(got, want, tol=2e-4):
+    off = 0
+    worst = 0.0
+    for name, size in GROUPS:
+        g, w = got[off:off + size], want[off:off + size]
+        scale = max(np.abs(w).max(), 1e-30)
+        err = np.abs(g - w).max() / scale
+        worst = max(worst, err)
+        assert err <= tol or np.abs(w).max() < 1e-12, (name, err, scale)
+        off += size
+    assert off == got.size
+    return worst
+
+
+@pytest.mark.parametrize("n_agents,n_targets,n_envs", [(5, 5, 41), (2, 3, 29), (1, 1, 17),
+                                                       (7, 8, 9)])
+def test_policy_gradient_matches_oracle(orc, n_agents, n_targets, n_envs):
+    from paper_2505_08222_amd import ppo
+    A = n_envs * n_agents
+    n_tok = n_agents + n_targets
+    x, mask = policy_tokens(A, n_agents, n_targets, seed=2 * n_agents + n_targets)
+    th = policy_params(orc.policy_num_params(), seed=8)
+    dl = np.random.default_rng(A).normal(size=(A, 8)).astype(np.float32)
+    dl[:, 5:] = 0.0
+    tp = ppo.TrainPass(A, n_tok)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    logits, feat = tp.forward(dev(x.reshape(-1, 6)), dev(mask.reshape(-1)), dev(th))
+    want = orc.policy_forward(x.astype(np.float64), mask, th.astype(np.float64))
+    err = np.abs(logits.cpu().numpy() - want).max()
+    assert err <= 1e-4 * max(1.0, np.abs(want).max()), err
+    grad, _ = tp.backward(dev(th), dev(dl), 5)
+    gw = orc.policy_backward(x.astype(np.float64), mask, th.astype(np.float64),
+                             dl.astype(np.float64))
+    worst = _check_grad(grad.cpu().numpy(), gw)
+    print(f"train {n_agents}x{n_targets}: {A} agents, logit err {err:.1e}, grad err {worst:.1e}")
+
+
+def test_recurrent_gradient_matches_oracle(orc):
+    from paper_2505_08222_amd import ppo
+    na, nt, E = 3, 4, 23
+    A = E * na
+    n_obs = na + nt
+    x, mask = policy_tokens(A, na, nt, seed=31)
+    th = policy_params(orc.policy_num_params(), seed=9)
+    rng = np.random.default_rng(3)
+    hid = rng.normal(size=(A, D)).astype(np.float32)
+    dl = rng.normal(size=(A, 8)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    tp = ppo.TrainPass(A, n_obs + 1, rec=1)
+    logits, feat = tp.forward(dev(x.reshape(-1, 6)), dev(mask.reshape(-1)), dev(th), dev(hid))
+    wl, wh = orc.policy_forward_rec(x.astype(np.float64), mask, hid.astype(np.float64),
+                                    th.astype(np.float64))
+    assert np.abs(logits.cpu().numpy() - wl).max() <= 1e-4 * max(1.0, np.abs(wl).max())
+    assert np.abs(feat.cpu().numpy() - wh).max() <= 1e-4 * max(1.0, np.abs(wh).max())
+    grad, dh = tp.backward(dev(th), dev(dl), 8)
+    gw, dhw = orc.policy_backward_rec(x.astype(np.float64), mask, hid.astype(np.float64),
+                                      th.astype(np.float64), dl.astype(np.float64))
+    _check_grad(grad.cpu().numpy(), gw)
+    assert np.abs(dh.cpu().numpy() - dhw).max() <= 2e-4 * np.abs(dhw).max()
+    # no carried state: zeros
+    tp.forward(dev(x.reshape(-1, 6)), dev(mask.reshape(-1)), dev(th), None)
+    g0, _ = tp.backward(dev(th), dev(dl), 8)
+    gz, _ = orc.policy_backward_rec(x.astype(np.float64), mask, None, th.astype(np.float64),
+                                    dl.astype(np.float64))
+    _check_grad(g0.cpu().numpy(), gz)
+
+
+@pytest.mark.parametrize("rec", [0, 1])
+def test_critic_gradient_matches_oracle(orc, rec):
+    from oracle import ppo_oracle as po
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.env import Env
+    na, nt, E, T = 3, 2, 37, 2
+    cfg = env_config("batched", n_agents=na, n_targets=nt, episode_len=T)
+    env = Env(cfg, E, seed=6)
+    env.reset(0)
+    gs = env.rollout(T, record=("gstate",))["gstate"][T - 1]
+    params = policy.init_params(14)
+    th = params.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(4)
+    hid = torch.tensor(rng.normal(size=(E, D)).astype(np.float32), device="cuda") if rec else None
+    dv = torch.tensor(rng.normal(size=E).astype(np.float32), device="cuda")
+    tp = ppo.TrainPass(E, na + nt + 1, rec=rec)
+    v, feat = tp.critic_forward(gs, na, nt, params, hidden=hid)
+    tok = po.critic_tokens(gs.cpu().numpy().astype(np.float64).reshape(E, na + nt, 6), na, nt,
+                           1000.0)
+    dl = np.zeros((E, 8))
+    dl[:, 0] = dv.cpu().numpy()
+    if rec:
+        tok = tok[:, 1:]
+        h64 = hid.cpu().numpy().astype(np.float64)
+        wl, _ = orc.policy_forward_rec(tok, np.ones(tok.shape[:2], np.uint8), h64, th)
+        gw, _ = orc.policy_backward_rec(tok, np.ones(tok.shape[:2], np.uint8), h64, th, dl)
+    else:
+        wl = orc.policy_forward(tok, np.ones(tok.shape[:2], np.uint8), th)
+        gw = orc.policy_backward(tok, np.ones(tok.shape[:2], np.uint8), th, dl)
+    assert np.abs(v.cpu().numpy() - wl[:, 0]).max() <= 1e-4 * max(1.0, np.abs(wl[:, 0]).max())
+    grad, _ = tp.backward(params, dv, 1)
+    _check_grad(grad.cpu().numpy(), gw)
+    env.close()
+
+
+def test_full_update_lowers_losses(orc):
+    # one PPO update of every parameter of the actor and the critic: the
+    # surrogate at the new logits and the value loss at the new values fall
+    from paper_2505_08222_amd import learned, policy, ppo
+    na, nt, E = 3, 3, 96
+    A, n_tok = E * na, na + nt
+    x, mask = policy_tokens(A, na, nt, seed=5)
+    obs = torch.from_numpy(x.reshape(-1, 6)).cuda()
+    msk = torch.from_numpy(mask.reshape(-1)).cuda()
+    actor = policy.init_params(30)
+    critic = policy.init_params(31)
+    rng = np.random.default_rng(8)
+    act = torch.tensor(rng.integers(0, 5, size=(1, A)).astype(np.int32), device="cuda")
+    adv = torch.tensor(rng.normal(size=(1, E)).astype(np.float32), device="cuda")
+    ret = torch.tensor(rng.normal(size=(1, E)).astype(np.float32), device="cuda")
+    gs = torch.randn(E, na + nt, 6, device="cuda")
+    gs[..., 5] = (torch.arange(na + nt, device="cuda") >= na).float()
+    ta, tc = ppo.TrainPass(A, n_tok), ppo.TrainPass(E, na + nt + 1)
+    # Adam's first steps move every one of the ~1e5 parameters by about lr
+    # together: lr small enough for the first-order decrease to dominate
+    oa, oc = learned.Adam(actor, lr=1e-5), learned.Adam(critic, lr=1e-5)
+    lo, _ = ta.forward(obs, msk, actor)
+    lo = lo.reshape(1, A, 8).clone()
+    losses = []
+    for it in range(3):
+        ln, _ = ta.forward(obs, msk, actor)
+        v, _ = tc.critic_forward(gs, na, nt, critic)
+        out, dl, dv = ppo.objective(ln.reshape(1, A, 8), lo, act, adv, v.reshape(1, E), ret, na, 5)
+        losses.append((out[0].item(), out[1].item()))
+        ga, _ = ta.backward(actor, dl.reshape(A, 8), 5)
+        gc, _ = tc.backward(critic, dv.reshape(E), 1)
+        assert torch.isfinite(ga).all() and torch.isfinite(gc).all()
+        oa.step(ga)
+        oc.step(gc)
+    print("update losses", losses)
+    for k in range(1, len(losses)):
+        assert losses[k][0] < losses[k - 1][0] and losses[k][1] < losses[k - 1][1], losses
