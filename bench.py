@@ -591,13 +591,16 @@ def policy_flops_per_agent_step(n_tok, d=64, heads=4, ffn=256, layers=2, n_out=8
 
 
 def bench_ppo(args, T=32, cpu_seconds=None):
-    """The learner's forward half on the policy workload's shape (16384 envs x
-    5 agents x 5 targets), one PPO batch of T steps: critic values of the T + 1
-    global states of every env, the policy re-evaluated on every agent's T
-    observations, GAE, and the clipped objective with its gradients. Inputs are
-    synthetic tensors of the workload's shapes, resident in HBM (the learner's
-    arithmetic does not depend on their values). Dominant kernel: the attention
-    kernel (critic and policy forwards), MFMA roofline."""
+    """The learner on the policy workload's shape (16384 envs x 5 agents x 5
+    targets), one PPO batch of T steps: critic values of the T + 1 global
+    states of every env, the policy re-evaluated on every agent's T
+    observations, GAE, the clipped objective with its gradients, the heads'
+    gradients and Adam steps; then the full update of every parameter (the
+    training form's forward and reverse passes of actor and critic, Adam) on
+    one minibatch. Inputs are synthetic tensors of the workload's shapes,
+    resident in HBM (the learner's arithmetic does not depend on their
+    values). Dominant kernel: the attention kernel (critic and policy
+    forwards), MFMA roofline."""
     import numpy as np
     import torch
 
@@ -650,11 +653,36 @@ def bench_ppo(args, T=32, cpu_seconds=None):
     oa, oc = ppo.HeadAdam(actor), ppo.HeadAdam(critic)
     t_adam, _ = timed(lambda: (oa.step(ga), oc.step(gc)))
     total = t_crit + t_pol + t_gae + t_obj + t_hg + t_adam
+    # the full update of every parameter on one minibatch: the training form
+    # (FP32 forward with its tape, reverse pass) of the actor on mb_agents
+    # agents and of the critic on their envs' states, then Adam on both
+    from paper_2505_08222_amd import learned
+    mb_envs = min(E, 8192)
+    mb_agents = mb_envs * na
+    ta, tc = ppo.TrainPass(mb_agents, n_tok), ppo.TrainPass(mb_envs, M + 1)
+    mobs, mmask = obs[:mb_agents * n_tok], mask[:mb_agents * n_tok]
+    mgs = gs[0, :mb_envs * M]
+    dlm = dl.reshape(T * A, 8)[:mb_agents].contiguous()
+    dvm = dv.reshape(-1)[:mb_envs].contiguous()
+    fa, fc = learned.Adam(actor.clone(), lr=1e-5), learned.Adam(critic.clone(), lr=1e-5)
+
+    def full_update():
+        ta.forward(mobs, mmask, fa.params)
+        g1, _ = ta.backward(fa.params, dlm, 5)
+        tc.critic_forward(mgs, na, nt, fc.params)
+        g2, _ = tc.backward(fc.params, dvm, 1)
+        fa.step(g1)
+        fc.step(g2)
+        return g1, g2
+    t_full, _ = timed(full_update)
+    fl_full = 3 * (policy_flops_per_agent_step(n_tok) * mb_agents
+                   + policy_flops_per_agent_step(M + 1) * mb_envs)
     fl_crit = policy_flops_per_agent_step(M + 1) * (T + 1) * E
     fl_pol = policy_flops_per_agent_step(n_tok) * T * A
     ach = fl_crit / (t_crit / 1e3) / 1e12
     log(f"[bench] ppo: critic {t_crit:.2f} ms, policy {t_pol:.2f} ms, gae {t_gae:.3f} ms, "
-        f"objective {t_obj:.3f} ms, head gradients {t_hg:.3f} ms, Adam {t_adam:.3f} ms")
+        f"objective {t_obj:.3f} ms, head gradients {t_hg:.3f} ms, Adam {t_adam:.3f} ms; "
+        f"full update of {mb_agents} agents + {mb_envs} states {t_full:.2f} ms")
     o = out.cpu().numpy()
     res = {
         "metric": METRIC, "value": T * A / (total / 1e3), "unit": "agent-steps/s",
@@ -667,6 +695,12 @@ def bench_ppo(args, T=32, cpu_seconds=None):
                    "envs": E, "agents": A, "batch_steps": T},
         "ms": {"critic": t_crit, "policy": t_pol, "gae": t_gae, "objective": t_obj,
                "head_grad": t_hg, "adam": t_adam, "total": total},
+        "full_update": {"minibatch_agents": mb_agents, "minibatch_states": mb_envs,
+                        "ms": t_full, "agent_samples_per_s": mb_agents / (t_full / 1e3),
+                        "tflops": fl_full / (t_full / 1e3) / 1e12,
+                        "note": "FP32 training form (forward with tape, exact backward, rocBLAS "
+                                "FP32 GEMMs) of actor and critic plus Adam on every parameter; "
+                                "flops counted as 3x the forward's"},
         "objective": {"policy_loss": float(o[0]), "value_loss": float(o[1]),
                       "entropy": float(o[2]), "clip_frac": float(o[3])},
         "roofline": {"bound": "mfma", "kernel": "policy_kernel (critic tokens)", "achieved": ach,
@@ -676,7 +710,27 @@ def bench_ppo(args, T=32, cpu_seconds=None):
     }
     if cpu_seconds:
         res["cpu_baseline"] = cpu_baseline_ppo(critic, actor, cpu_seconds)
+        res["full_update"]["cpu_oracle"] = cpu_oracle_gradient(actor, 2.0)
     return res
+
+
+def cpu_oracle_gradient(actor, budget_s):
+    """The oracle's gradient of the actor (FP64 C, one thread) on batches of
+    20 agents of 5x5 envs until the budget is used; agent-samples/s."""
+    import numpy as np
+
+    from oracle import oracle as orc
+
+    rng = np.random.default_rng(1)
+    th = actor.detach().cpu().numpy().astype(np.float64)
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        x = rng.normal(size=(20, 10, 6))
+        orc.policy_backward(x, np.ones((20, 10), np.uint8), th, rng.normal(size=(20, 8)))
+        n += 20
+    el = time.perf_counter() - t0
+    return {"value": n / el, "unit": "agent-samples/s", "cores": 1,
+            "sample": f"{n} agents of 10 tokens, {el:.1f} s"}
 
 
 def cpu_baseline_ppo(critic, actor, budget_s):

@@ -18,14 +18,15 @@ extern "C" int mil_set_error(int code, const char *msg);  // abi.cpp
 namespace {
 
 constexpr int D = mil::kPolD, F = mil::kPolF, L = mil::kPolLayers, NA = mil::kPolActions;
+constexpr int kMaxSplit = 64;  // row chunks of a weight gradient's sum
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 // Workspace: the tape (per layer the inputs of every operation) and the
 // reverse pass's scratch, all [rows][...] FP32 unless stated.
 struct TrainWork {
-  int64_t tok, tmask, xaug, mrow, ones, h[L + 1], a1[L], qkv[L], P[L], o[L], hmid[L], a2[L], z[L],
-      f[L], feat, dh, t64, dyx, dqkv, dz, dl8, gfa, bfa, gaug, total;
+  int64_t tok, tmask, xaug, mrow, h[L + 1], a1[L], qkv[L], P[L], o[L], hmid[L], a2[L], z[L], f[L],
+      feat, dh, t64, dyx, dqkv, dz, dl8, gfa, bfa, gaug, csum, wpart, total;
 };
 
 TrainWork train_work(int64_t A, int nt) {
@@ -41,7 +42,6 @@ TrainWork train_work(int64_t A, int nt) {
   w.tmask = take(R);
   w.xaug = take(R * 8 * 4);
   w.mrow = take(R);
-  w.ones = take((R > A ? R : A) * 4);
   for (int l = 0; l <= L; ++l) w.h[l] = take(R * D * 4);
   for (int l = 0; l < L; ++l) {
     w.a1[l] = take(R * D * 4);
@@ -63,6 +63,8 @@ TrainWork train_work(int64_t A, int nt) {
   w.gfa = take(A * D * 4);
   w.bfa = take(A * D * 4);
   w.gaug = take(D * 8 * 4);
+  w.csum = take(mil::tr_colsum_scratch_doubles() * 8);
+  w.wpart = take((int64_t)(kMaxSplit + 1) * F * D * 4);  // the largest weight: 256 x 64
   w.total = o;
   return w;
 }
@@ -86,6 +88,8 @@ rocblas_handle blas_for_current_device() {
 struct Ctx {
   rocblas_handle h;
   void *stream;
+  double *csum;  // column-sum scratch
+  float *wpart;  // weight-gradient partials [kMaxSplit + 1][N * K]
   bool ok = true;
   // Y [R][N] = X [R][K] W^T (W [N][K] row-major), added to Y when beta = 1
   void xwt(const float *X, const float *W, float *Y, int64_t R, int N, int K, float beta) {
@@ -99,17 +103,31 @@ struct Ctx {
     ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, K, (int)R, N, &one,
                              W, K, dY, N, &beta, dX, K) == rocblas_status_success;
   }
-  // dW [N][K] = dY^T X summed over the R rows
+  // dW [N][K] = dY^T X summed over the R rows: the rows split into up to
+  // kMaxSplit equal chunks (one batched GEMM, one product per chunk, plus the
+  // remainder), the chunks' products then added in order
   void dw(const float *dY, const float *X, float *dW, int64_t R, int N, int K) {
     const float one = 1.0f, zero = 0.0f;
-    ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)R,
-                             &one, X, K, dY, N, &zero, dW, K) == rocblas_status_success;
+    const int64_t nb = R / 4096 < kMaxSplit ? R / 4096 : kMaxSplit;
+    if (nb <= 1) {
+      ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)R,
+                               &one, X, K, dY, N, &zero, dW, K) == rocblas_status_success;
+      return;
+    }
+    const int64_t chunk = R / nb, rem = R - nb * chunk, nk = (int64_t)N * K;
+    ok = ok && rocblas_sgemm_strided_batched(
+                   h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)chunk, &one,
+                   X, K, chunk * K, dY, N, chunk * N, &zero, wpart, K, nk, (int)nb) ==
+                   rocblas_status_success;
+    if (rem > 0)
+      ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N,
+                               (int)rem, &one, X + nb * chunk * K, K, dY + nb * chunk * N, N,
+                               &zero, wpart + nb * nk, K) == rocblas_status_success;
+    k(mil::tr_sum_partials(wpart, (int)(nb + (rem > 0)), nk, dW, stream));
   }
   // out [N] = column sums of Y [R][N]
-  void colsum(const float *Y, const float *ones, float *out, int64_t R, int N) {
-    const float one = 1.0f, zero = 0.0f;
-    ok = ok && rocblas_sgemv(h, rocblas_operation_none, N, (int)R, &one, Y, N, ones, 1, &zero, out,
-                             1) == rocblas_status_success;
+  void colsum(const float *Y, float *out, int64_t R, int N) {
+    k(mil::tr_colsum(Y, R, N, csum, out, stream));
   }
   void k(int rc) { ok = ok && rc == 0; }
 };
@@ -134,9 +152,8 @@ int train_forward(int64_t A, int nt, int rec, const float *obs, const uint8_t *m
   const TrainWork w = train_work(A, nt);
   const int64_t R = A * nt;
   auto fp = [&](int64_t off) { return (float *)(ws + off); };
-  Ctx c{bh, stream};
+  Ctx c{bh, stream, (double *)(ws + w.csum), fp(w.wpart)};
   uint8_t *mrow = (uint8_t *)(ws + w.mrow);
-  c.k(mil::tr_fill(fp(w.ones), 1.0f, R > A ? R : A, stream));
   c.k(mil::tr_embed(obs, mask, R, nt, rec, hidden, prm, fp(w.h[0]), fp(w.xaug), mrow, stream));
   for (int l = 0; l < L && c.ok; ++l) {
     const float *lp = prm + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
@@ -226,43 +243,42 @@ int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_
   const int64_t R = A * nt;
   auto fp = [&](int64_t off) { return (float *)(ws + off); };
   const uint8_t *mrow = (const uint8_t *)(ws + w.mrow);
-  const float *ones = fp(w.ones);
   float *dh = fp(w.dh), *t64 = fp(w.t64), *dyx = fp(w.dyx);
-  Ctx c{bh, stream};
+  Ctx c{bh, stream, (double *)(ws + w.csum), fp(w.wpart)};
   float *gfin = d_grad + mil::kPolOffFinal;
   // head and final LayerNorm (each agent's first row)
   c.k(mil::tr_fill(dh, 0.0f, R * D, stream));
   c.k(mil::tr_head_back(fp(w.h[L]), A, nt, d_params, d_dout, ld, n_out, fp(w.dl8), dh, fp(w.gfa),
                         fp(w.bfa), stream));
   c.dw(fp(w.dl8), fp(w.feat), gfin + mil::kPolWh, A, NA, D);
-  c.colsum(fp(w.dl8), ones, gfin + mil::kPolBh, A, NA);
-  c.colsum(fp(w.gfa), ones, gfin + mil::kPolLnfG, A, D);
-  c.colsum(fp(w.bfa), ones, gfin + mil::kPolLnfB, A, D);
+  c.colsum(fp(w.dl8), gfin + mil::kPolBh, A, NA);
+  c.colsum(fp(w.gfa), gfin + mil::kPolLnfG, A, D);
+  c.colsum(fp(w.bfa), gfin + mil::kPolLnfB, A, D);
   for (int l = L - 1; l >= 0 && c.ok; --l) {
     const float *lp = d_params + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
     float *gp = d_grad + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
     // feed-forward block: h[l + 1] = hmid + W2 gelu(z) + b2
-    c.colsum(dh, ones, gp + mil::kPolB2, R, D);
+    c.colsum(dh, gp + mil::kPolB2, R, D);
     c.dw(dh, fp(w.f[l]), gp + mil::kPolW2, R, D, F);
     c.xw(dh, lp + mil::kPolW2, fp(w.dz), R, D, F, 0.0f);
     c.k(mil::tr_gelu_back(fp(w.dz), fp(w.z[l]), R * F, stream));
-    c.colsum(fp(w.dz), ones, gp + mil::kPolB1, R, F);
+    c.colsum(fp(w.dz), gp + mil::kPolB1, R, F);
     c.dw(fp(w.dz), fp(w.a2[l]), gp + mil::kPolW1, R, F, D);
     c.xw(fp(w.dz), lp + mil::kPolW1, t64, R, F, D, 0.0f);
     c.k(mil::tr_layernorm_back(fp(w.hmid[l]), lp + mil::kPolLn2G, t64, dh, dyx, R, stream));
-    c.colsum(dyx, ones, gp + mil::kPolLn2G, R, D);
-    c.colsum(t64, ones, gp + mil::kPolLn2B, R, D);
+    c.colsum(dyx, gp + mil::kPolLn2G, R, D);
+    c.colsum(t64, gp + mil::kPolLn2B, R, D);
     // attention block: hmid = h[l] + Wo attention(LN1(h[l])) + bo
-    c.colsum(dh, ones, gp + mil::kPolBo, R, D);
+    c.colsum(dh, gp + mil::kPolBo, R, D);
     c.dw(dh, fp(w.o[l]), gp + mil::kPolWo, R, D, D);
     c.xw(dh, lp + mil::kPolWo, t64, R, D, D, 0.0f);
     c.k(mil::tr_attention_back(fp(w.qkv[l]), fp(w.P[l]), mrow, t64, A, nt, fp(w.dqkv), stream));
-    c.colsum(fp(w.dqkv), ones, gp + mil::kPolBqkv, R, 3 * D);
+    c.colsum(fp(w.dqkv), gp + mil::kPolBqkv, R, 3 * D);
     c.dw(fp(w.dqkv), fp(w.a1[l]), gp + mil::kPolWqkv, R, 3 * D, D);
     c.xw(fp(w.dqkv), lp + mil::kPolWqkv, t64, R, 3 * D, D, 0.0f);
     c.k(mil::tr_layernorm_back(fp(w.h[l]), lp + mil::kPolLn1G, t64, dh, dyx, R, stream));
-    c.colsum(dyx, ones, gp + mil::kPolLn1G, R, D);
-    c.colsum(t64, ones, gp + mil::kPolLn1B, R, D);
+    c.colsum(dyx, gp + mil::kPolLn1G, R, D);
+    c.colsum(t64, gp + mil::kPolLn1B, R, D);
   }
   // embedding (observed rows; a carried row's augmented input is zero)
   c.dw(dh, fp(w.xaug), fp(w.gaug), R, D, 8);

@@ -34,5 +34,11 @@ int tr_head_back(const float *h, int64_t A, int nt, const float *prm, const floa
 int tr_embed_grad_scatter(const float *gaug, float *grad, void *stream);
 int tr_first_rows(const float *dh, int64_t A, int nt, float *out, void *stream);
 int tr_fill(float *p, float v, int64_t n, void *stream);
+// out [N] = column sums of Y [R][N] (N <= 256), FP64 in a fixed order;
+// scratch holds tr_colsum_scratch_doubles() doubles
+int64_t tr_colsum_scratch_doubles();
+int tr_colsum(const float *Y, int64_t R, int N, double *scratch, float *out, void *stream);
+// out [n] = sum over b < nb of part[b][n], in order (FP64 sums)
+int tr_sum_partials(const float *part, int nb, int64_t n, float *out, void *stream);
 
 }  // namespace mil

@@ -152,58 +152,125 @@ attention_kernel(const float *__restrict__ qkv, const uint8_t *__restrict__ mrow
   for (int c = 0; c < kPolDh; ++c) out[c] = acc[c];
 }
 
-// Thread (agent, head): the reverse of attention_kernel for all the agent's
-// queries and keys: dP = dO V^T, dS = P (dP - sum P dP) / 4, dQ = dS K,
-// dK = dS^T Q, dV = P^T dO, written into dqkv (this head's columns).
-__global__ void __launch_bounds__(kTrThreads)
+// One block per agent: the reverse of attention_kernel for all its heads,
+// queries and keys, staged through LDS (the agent's Q/K/V rows, softmax
+// probabilities and output gradients read once, coalesced):
+// dP = dO V^T, dS = P (dP - sum_u P dP) / 4, dQ = dS K, dK = dS^T Q,
+// dV = P^T dO, written to dqkv row by row.
+constexpr int kAbThreads = 256;
+__global__ void __launch_bounds__(kAbThreads)
 attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P,
                       const uint8_t *__restrict__ mrow, const float *__restrict__ dout, int64_t A,
                       int nt, float *__restrict__ dqkv) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A * kPolHeads) return;
-  const int hd = (int)(i % kPolHeads);
-  const int64_t a = i / kPolHeads;
-  const int64_t r0 = a * nt;
-  const int qo = hd * kPolDh, ko = kPolD + hd * kPolDh, vo = 2 * kPolD + hd * kPolDh;
-  for (int u = 0; u < nt; ++u)
-#pragma unroll
-    for (int c = 0; c < kPolDh; ++c) {
-      float *row = dqkv + (r0 + u) * 3 * kPolD;
-      row[qo + c] = 0.0f;
-      row[ko + c] = 0.0f;
-      row[vo + c] = 0.0f;
+  __shared__ float sq[kPolMaxTok][3 * kPolD];
+  __shared__ float so[kPolMaxTok][kPolD];
+  __shared__ float sp[kPolHeads][kPolMaxTok][kPolMaxTok];
+  __shared__ float sd[kPolHeads][kPolMaxTok][kPolMaxTok];
+  __shared__ float ssum[kPolHeads][kPolMaxTok];
+  const int tid = threadIdx.x;
+  for (int64_t a = blockIdx.x; a < A; a += gridDim.x) {
+    const int64_t r0 = a * nt;
+    for (int e = tid; e < nt * 3 * kPolD; e += kAbThreads)
+      sq[e / (3 * kPolD)][e % (3 * kPolD)] = qkv[r0 * 3 * kPolD + e];
+    for (int e = tid; e < nt * kPolD; e += kAbThreads) so[e / kPolD][e % kPolD] = dout[r0 * kPolD + e];
+    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
+      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
+      sp[h][t][u] = P[a * kPolHeads * nt * nt + e];
     }
-  for (int t = 0; t < nt; ++t) {
-    const float *pr = P + (i * nt + t) * nt;
-    const float *dot_ = dout + (r0 + t) * kPolD + qo;
-    float dP[kPolMaxTok];
-    float dsum = 0.0f;
-    for (int u = 0; u < nt; ++u) {
-      const float *v = qkv + (r0 + u) * 3 * kPolD + vo;
-      float *dv = dqkv + (r0 + u) * 3 * kPolD + vo;
+    __syncthreads();
+    // dP[h][t][u] = dO[t] . V[u] over the head's 16 dimensions
+    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
+      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
       float acc = 0.0f;
 #pragma unroll
-      for (int c = 0; c < kPolDh; ++c) {
-        acc = fmaf(dot_[c], v[c], acc);
-        dv[c] = fmaf(pr[u], dot_[c], dv[c]);
-      }
-      dP[u] = acc;
-      dsum = fmaf(pr[u], acc, dsum);
+      for (int c = 0; c < kPolDh; ++c)
+        acc = fmaf(so[t][h * kPolDh + c], sq[u][2 * kPolD + h * kPolDh + c], acc);
+      sd[h][t][u] = acc;
     }
-    const float *q = qkv + (r0 + t) * 3 * kPolD + qo;
-    float *dq = dqkv + (r0 + t) * 3 * kPolD + qo;
-    for (int u = 0; u < nt; ++u) {
-      if (!mrow[r0 + u]) continue;
-      const float ds = pr[u] * (dP[u] - dsum) * 0.25f;
-      const float *k = qkv + (r0 + u) * 3 * kPolD + ko;
-      float *dk = dqkv + (r0 + u) * 3 * kPolD + ko;
-#pragma unroll
-      for (int c = 0; c < kPolDh; ++c) {
-        dq[c] = fmaf(ds, k[c], dq[c]);
-        dk[c] = fmaf(ds, q[c], dk[c]);
-      }
+    __syncthreads();
+    for (int e = tid; e < kPolHeads * nt; e += kAbThreads) {
+      const int h = e / nt, t = e % nt;
+      float acc = 0.0f;
+      for (int u = 0; u < nt; ++u) acc = fmaf(sp[h][t][u], sd[h][t][u], acc);
+      ssum[h][t] = acc;
     }
+    __syncthreads();
+    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
+      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
+      // a masked key has probability 0 and takes no gradient
+      sd[h][t][u] = mrow[r0 + u] ? sp[h][t][u] * (sd[h][t][u] - ssum[h][t]) * 0.25f : 0.0f;
+    }
+    __syncthreads();
+    // outputs: row x, column j of dQ / dK / dV (head h = column / 16)
+    for (int e = tid; e < nt * 3 * kPolD; e += kAbThreads) {
+      const int x = e / (3 * kPolD), j = e % (3 * kPolD);
+      const int part = j / kPolD, col = j % kPolD, h = col / kPolDh;
+      float acc = 0.0f;
+      if (part == 0) {  // dQ[x] = sum_u dS[x][u] K[u]
+        for (int u = 0; u < nt; ++u) acc = fmaf(sd[h][x][u], sq[u][kPolD + col], acc);
+      } else if (part == 1) {  // dK[x] = sum_t dS[t][x] Q[t]
+        for (int t = 0; t < nt; ++t) acc = fmaf(sd[h][t][x], sq[t][col], acc);
+      } else {  // dV[x] = sum_t P[t][x] dO[t]
+        for (int t = 0; t < nt; ++t) acc = fmaf(sp[h][t][x], so[t][col], acc);
+      }
+      dqkv[r0 * 3 * kPolD + e] = acc;
+    }
+    __syncthreads();  // before the next agent's rows overwrite the stage
   }
+}
+
+// Column sums of Y [R][N] (N <= 256) in two fixed-order passes: block b adds
+// rows [b * per, (b + 1) * per) in FP64 (thread (group, column) with four
+// running sums over its rows, groups combined in order), then one wavefront
+// per column adds the blocks' partials (lane j: partials j, j + 64, ...;
+// then a fixed butterfly).
+constexpr int kCsBlocks = 256;
+__global__ void __launch_bounds__(256)
+colsum_partial_kernel(const float *__restrict__ Y, int64_t R, int N, int64_t per,
+                      double *__restrict__ part) {
+  __shared__ double red[256];
+  const int groups = 256 / N;
+  const int g = threadIdx.x / N, col = threadIdx.x - g * N;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (g < groups) {
+    int64_t r = r0 + g;
+    for (; r + 3 * groups < r1; r += 4 * groups) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += (double)Y[(r + q * groups) * N + col];
+    }
+    for (; r < r1; r += groups) acc[0] += (double)Y[r * N + col];
+  }
+  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+    for (int q = 0; q < groups; ++q) s += red[q * N + threadIdx.x];
+    part[(int64_t)blockIdx.x * N + threadIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+colsum_final_kernel(const double *__restrict__ part, int nb, int N, float *__restrict__ out) {
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (col >= N) return;  // wavefront-uniform
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += part[(int64_t)b * N + col];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  if (lane == 0) out[col] = (float)s;
+}
+
+// Sum of nb partial matrices of n floats each, in order.
+__global__ void __launch_bounds__(256)
+sum_partials_kernel(const float *__restrict__ part, int nb, int64_t n, float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * n + i];
+  out[i] = (float)s;
 }
 
 // One wavefront per row: LayerNorm's reverse pass. dx is added to dxacc;
@@ -362,8 +429,30 @@ int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float
 int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, const float *dout,
                       int64_t A, int nt, float *dqkv, void *stream) {
   if (A == 0) return 0;
-  hipLaunchKernelGGL(attention_back_kernel, grid_for(A * kPolHeads), dim3(kTrThreads), 0,
+  const int64_t blocks = A < 8192 ? A : 8192;
+  hipLaunchKernelGGL(attention_back_kernel, dim3((unsigned)blocks), dim3(kAbThreads), 0,
                      (hipStream_t)stream, qkv, P, mrow, dout, A, nt, dqkv);
+  return check();
+}
+
+int64_t tr_colsum_scratch_doubles() { return (int64_t)kCsBlocks * 256; }
+
+int tr_colsum(const float *Y, int64_t R, int N, double *scratch, float *out, void *stream) {
+  if (N < 1 || N > 256) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t per = R > 0 ? (R + kCsBlocks - 1) / kCsBlocks : 1;
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3(kCsBlocks), dim3(256), 0, st, Y, R, N, per,
+                     scratch);
+  if (check()) return -1;
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, scratch,
+                     kCsBlocks, N, out);
+  return check();
+}
+
+int tr_sum_partials(const float *part, int nb, int64_t n, float *out, void *stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(sum_partials_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream,
+                     part, nb, n, out);
   return check();
 }
 
