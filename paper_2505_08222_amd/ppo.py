@@ -212,3 +212,82 @@ class TrainPass:
                                          d.shape[1], n_out, ptr(grad), ptr(dh), self._w, self._n,
                                          _stream()))
         return grad, dh
+
+
+class Learner:
+    """The learner's loop over one batch of closed-loop experience (MAPPO,
+    Sec. III-B, with the TransfMAPPO networks): critic values of every
+    state, GAE, then `epochs` passes over `minibatches` groups of whole steps,
+    each a training-form forward and reverse pass of the actor (clipped
+    surrogate) and the critic (squared error to the GAE returns) and an Adam
+    step on every parameter of both. Orchestration only: every step of it is
+    one of the library's entry points."""
+
+    def __init__(self, actor, critic, n_agents: int, n_targets: int, n_actions: int = 5,
+                 lr: float = 3e-4, clip_eps: float = 0.2, gamma: float = 0.99, lam: float = 0.95,
+                 pos_scale: float = 1000.0):
+        from .learned import Adam
+        self.actor, self.critic = actor, critic
+        self.na, self.nt, self.n_actions = n_agents, n_targets, n_actions
+        self.opt_a, self.opt_c = Adam(actor, lr=lr), Adam(critic, lr=lr)
+        self.clip_eps, self.gamma, self.lam, self.pos_scale = clip_eps, gamma, lam, pos_scale
+        self._passes = {}
+
+    def _pass(self, A, n_tok):
+        key = (A, n_tok)
+        if key not in self._passes:
+            self._passes[key] = TrainPass(A, n_tok, device=self.actor.device)
+        return self._passes[key]
+
+    def values(self, gstate):
+        """V of states gstate [S, E, M, 6] -> [S, E] (training form, FP32)."""
+        S = gstate.shape[0]
+        E = gstate.reshape(S, -1, self.na + self.nt, 6).shape[1]
+        tp = self._pass(E, self.na + self.nt + 1)
+        return torch.stack([tp.critic_forward(gstate[s], self.na, self.nt, self.critic,
+                                              pos_scale=self.pos_scale)[0].clone()
+                            for s in range(S)])
+
+    def logits(self, obs, mask):
+        """Actor logits of obs [T, A * n_tok, 6] -> [T, A, 8] (training form)."""
+        T = obs.shape[0]
+        n_tok = self.na + self.nt
+        A = obs.shape[1] // n_tok
+        tp = self._pass(A, n_tok)
+        return torch.stack([tp.forward(obs[t], mask[t], self.actor)[0].clone() for t in range(T)])
+
+    def update(self, obs, mask, actions, gstate, rewards, dones, epochs: int = 2,
+               minibatches: int = 2):
+        """obs / mask [T, A * n_tok, ...]: the observation each step's action
+        was taken on; actions [T, A]; gstate [T + 1, E * M, 6]: the states
+        before each step and after the last; rewards / dones [T, E].
+        Returns the objective's outputs [4] of every minibatch step."""
+        T, A = actions.shape
+        E = A // self.na
+        n_tok = self.na + self.nt
+        M = self.na + self.nt
+        values = self.values(gstate.reshape(T + 1, E, M, 6))
+        adv, ret = gae(rewards, dones, values, self.gamma, self.lam)
+        logits_old = self.logits(obs, mask)
+        assert T % minibatches == 0, "minibatches must divide the batch's steps"
+        k = T // minibatches
+        ta = self._pass(k * A, n_tok)
+        tc = self._pass(k * E, M + 1)
+        gs = gstate.reshape(T + 1, E, M, 6)
+        history = []
+        for _ in range(epochs):
+            for mb in range(minibatches):
+                s = slice(mb * k, (mb + 1) * k)
+                ln, _ = ta.forward(obs[s].reshape(-1, 6), mask[s].reshape(-1), self.actor)
+                v, _ = tc.critic_forward(gs[s].reshape(k * E, M, 6), self.na, self.nt,
+                                         self.critic, pos_scale=self.pos_scale)
+                out, dl, dv = objective(ln.reshape(k, A, 8), logits_old[s].contiguous(),
+                                        actions[s].contiguous(), adv[s].contiguous(),
+                                        v.reshape(k, E), ret[s].contiguous(), self.na,
+                                        self.n_actions, self.clip_eps)
+                ga, _ = ta.backward(self.actor, dl.reshape(k * A, 8), self.n_actions)
+                gc, _ = tc.backward(self.critic, dv.reshape(k * E), 1)
+                self.opt_a.step(ga)
+                self.opt_c.step(gc)
+                history.append(out)
+        return torch.stack(history)
