@@ -1039,7 +1039,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the env-count sweep of the batched workload")
+                    help="skip the env-count sweeps (the batched workload's; the Table I grid of "
+                         "the paper_pf workload)")
     ap.add_argument("--no-learned-loop", action="store_true",
                     help="policy workload: keep the exact estimator in the loop")
     ap.add_argument("--copy-probe", action="store_true",
@@ -1070,7 +1071,7 @@ def main():
     if args.workload != "all":
         res = bench_env(args, args.workload, args.steps, args.warmup,
                         sweep=args.workload == "batched" and not args.no_sweep, cpu_seconds=cpu_s)
-        if args.workload == "paper_pf":
+        if args.workload == "paper_pf" and not args.no_sweep:
             res["table1_grid"] = table1_grid(args)
         print(json.dumps(res), flush=True)
         return
