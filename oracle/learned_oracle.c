@@ -529,12 +529,13 @@ static void policy_trunk_taped(int n_tok, double h[][PD], const uint8_t *mk, con
   for (int t = 0; t < n_tok; ++t) memcpy(tp->hout[t], h[t], sizeof(double) * PD);
 }
 
-/* Reverse pass of one agent: dlogits [PA] -> parameter gradient added to
- * gr (layer parameters from gl, embedding from ge, final LN and head from
- * gf), dh [n_tok][PD] the gradient at the rows entering the trunk. */
+/* Reverse pass of one agent: dlogits [PA] and dfeat [PD] (may be NULL) the
+ * loss gradients at the logits and at the head's input LN_f(h_0) -> the
+ * parameter gradient added to gl (layers, final LN and head), dh [n_tok][PD]
+ * the gradient at the rows entering the trunk. */
 static void policy_trunk_backward(int n_tok, const uint8_t *mk, const double *th,
-                                  const policy_tape *tp, const double *dlogits, double *gl,
-                                  double dh[][PD]) {
+                                  const policy_tape *tp, const double *dlogits, const double *dfeat,
+                                  double *gl, double dh[][PD]) {
   const double *p = th;
   const double *lay[PL];
   double *glay[PL];
@@ -547,7 +548,7 @@ static void policy_trunk_backward(int n_tok, const uint8_t *mk, const double *th
   double *dgf = gl + PL * P_LAYER, *dbf = dgf + PD, *dWh = dgf + 2 * PD, *dbh = dWh + PA * PD;
   double s0[PD], ds0[PD];
   layer_norm(tp->hout[0], gf, gf + PD, s0);
-  for (int i = 0; i < PD; ++i) ds0[i] = 0.0;
+  for (int i = 0; i < PD; ++i) ds0[i] = dfeat ? dfeat[i] : 0.0;
   for (int k = 0; k < PA; ++k) {
     dbh[k] += dlogits[k];
     for (int i = 0; i < PD; ++i) {
@@ -668,7 +669,7 @@ void orc_policy_backward(int64_t A, int n_tok, const double *tokens, const uint8
     const double *x = tokens + ag * n_tok * 6;
     for (int t = 0; t < n_tok; ++t) policy_embed(th, x + t * 6, h[t]);
     policy_trunk_taped(n_tok, h, mask + ag * n_tok, tl, tp);
-    policy_trunk_backward(n_tok, mask + ag * n_tok, tl, tp, dlogits + ag * PA,
+    policy_trunk_backward(n_tok, mask + ag * n_tok, tl, tp, dlogits + ag * PA, NULL,
                           grad + PD * 6 + PD, dh);
     for (int t = 0; t < n_tok; ++t)
       for (int d = 0; d < PD; ++d) {
@@ -680,10 +681,14 @@ void orc_policy_backward(int64_t A, int n_tok, const double *tokens, const uint8
 }
 
 /* The recurrent form: the carried state hidden_in [A][64] (NULL: zeros) is
- * row 0; dhidden [A][64] (may be NULL) receives the gradient at it. */
+ * row 0; dnext [A][64] (may be NULL) is the loss gradient at the state this
+ * step passes on (its head input, which the next step reads), so that a
+ * sequence is differentiated by calling the steps in reverse order with
+ * dnext = the following step's dhidden; dhidden [A][64] (may be NULL)
+ * receives the gradient at hidden_in. */
 void orc_policy_backward_rec(int64_t A, int n_obs, const double *tokens, const uint8_t *mask,
                              const double *hidden_in, const double *th, const double *dlogits,
-                             double *grad, double *dhidden) {
+                             const double *dnext, double *grad, double *dhidden) {
   policy_tape *tp = (policy_tape *)malloc(sizeof(policy_tape));
   double h[P_MAXT][PD], dh[P_MAXT][PD];
   uint8_t mk[P_MAXT];
@@ -697,7 +702,8 @@ void orc_policy_backward_rec(int64_t A, int n_obs, const double *tokens, const u
       mk[1 + t] = mask[ag * n_obs + t];
     }
     policy_trunk_taped(1 + n_obs, h, mk, tl, tp);
-    policy_trunk_backward(1 + n_obs, mk, tl, tp, dlogits + ag * PA, grad + PD * 6 + PD, dh);
+    policy_trunk_backward(1 + n_obs, mk, tl, tp, dlogits + ag * PA, dnext ? dnext + ag * PD : NULL,
+                          grad + PD * 6 + PD, dh);
     if (dhidden)
       for (int d = 0; d < PD; ++d) dhidden[ag * PD + d] = dh[0][d];
     for (int t = 0; t < n_obs; ++t)

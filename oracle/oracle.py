@@ -120,7 +120,7 @@ def _register_learned(L):
                                              P(D)]
         L.orc_policy_backward.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D)]
         L.orc_policy_backward_rec.argtypes = [I64, C.c_int, P(D), P(C.c_uint8), P(D), P(D), P(D),
-                                              P(D), P(D)]
+                                              P(D), P(D), P(D)]
         L.orc_policy_sample.argtypes = [P(D), C.c_int, D]
         L.orc_policy_sample.restype = C.c_int
 
@@ -477,22 +477,47 @@ def policy_backward(tokens, mask, params, dlogits):
     return g
 
 
-def policy_backward_rec(tokens, mask, hidden, params, dlogits):
+def policy_backward_rec(tokens, mask, hidden, params, dlogits, dnext=None):
     """The recurrent form -> (parameter gradient [P], gradient at the carried
-    state [A, 64])."""
+    state [A, 64]); dnext [A, 64] (or None) is the loss gradient at the state
+    this step passes on."""
     tokens = np.ascontiguousarray(tokens, np.float64)
     mask = np.ascontiguousarray(mask, np.uint8)
     params = np.ascontiguousarray(params, np.float64)
     A, n_obs, _ = tokens.shape
     dl = np.ascontiguousarray(dlogits, np.float64).reshape(A, 8)
     hin = None if hidden is None else np.ascontiguousarray(hidden, np.float64)
+    dn = None if dnext is None else np.ascontiguousarray(dnext, np.float64).reshape(A, 64)
     g = np.zeros(params.size)
     dh = np.zeros((A, 64))
     lib().orc_policy_backward_rec(A, n_obs, _p(tokens, C.c_double), _p(mask, C.c_uint8),
                                   None if hin is None else _p(hin, C.c_double),
-                                  _p(params, C.c_double), _p(dl, C.c_double), _p(g, C.c_double),
+                                  _p(params, C.c_double), _p(dl, C.c_double),
+                                  None if dn is None else _p(dn, C.c_double), _p(g, C.c_double),
                                   _p(dh, C.c_double))
     return g, dh
+
+
+def policy_bptt(tokens_seq, masks_seq, params, dlogits_seq):
+    """Gradient of sum_t dlogits_seq[t] . logits_t over a sequence of T steps
+    of the recurrent form started from zeros (logits_t from the state the
+    previous step passed on): the forward chain, then the steps' reverse
+    passes in reverse order, each handing the gradient at its input state to
+    the step before. tokens_seq [T][A][n_obs][6], masks_seq [T][A][n_obs],
+    dlogits_seq [T][A][8] -> gradient [P]."""
+    T = len(tokens_seq)
+    states = [None]
+    for t in range(T):
+        _, h = policy_forward_rec(tokens_seq[t], masks_seq[t], states[-1], params)
+        states.append(h)
+    grad = np.zeros(np.asarray(params).size)
+    dnext = None
+    for t in range(T - 1, -1, -1):
+        g, dh = policy_backward_rec(tokens_seq[t], masks_seq[t], states[t], params,
+                                    dlogits_seq[t], dnext)
+        grad += g
+        dnext = dh
+    return grad
 
 
 def policy_sample(logits, n, u) -> int:

@@ -233,3 +233,98 @@ def test_recurrent_backward_matches_autograd(orc):
     g0, _ = orc.policy_backward_rec(x, mask, None, th, dl)
     g1, _ = orc.policy_backward_rec(x, mask, np.zeros((3, D)), th, dl)
     np.testing.assert_array_equal(g0, g1)
+
+
+def _chain_loss_torch(xs, ms, t, dls):
+    h = torch.zeros(xs[0].shape[0], D, dtype=torch.float64)
+    loss = 0.0
+    for x, m, dl in zip(xs, ms, dls):
+        out, h = _torch_policy_rec(x, m, t, h)
+        loss = loss + (out * torch.from_numpy(dl)).sum()
+    return loss
+
+
+def _torch_policy_rec(x, m, t, h):
+    """Torch form of one recurrent step: (logits, next state)."""
+    return _torch_policy(x, m, t, h), _torch_state(x, m, t, h)
+
+
+def _torch_state(x, m, t, h):
+    """LN_f of the carried row after the trunk (the next state), torch float64."""
+    o = 0
+
+    def take(*shape):
+        nonlocal o
+        k = int(np.prod(shape))
+        v = t[o:o + k].view(*shape)
+        o += k
+        return v
+    E, e = take(D, 6), take(D)
+    xx = torch.from_numpy(x)
+    mm = torch.from_numpy(m.astype(bool))
+    hh = torch.cat([h[:, None], xx @ E.T + e], 1)
+    mm = torch.cat([torch.ones_like(mm[:, :1]), mm], 1)
+    A_, T_ = hh.shape[0], hh.shape[1]
+    for _ in range(L):
+        g1, b1n = take(D), take(D)
+        Wqkv, bqkv = take(3 * D, D), take(3 * D)
+        Wo, bo = take(D, D), take(D)
+        g2, b2n = take(D), take(D)
+        W1, b1 = take(F, D), take(F)
+        W2, b2 = take(D, F), take(D)
+        a = torch.nn.functional.layer_norm(hh, (D,), g1, b1n, eps=1e-5)
+        qkv = a @ Wqkv.T + bqkv
+        q, k, v = qkv[..., :D], qkv[..., D:2 * D], qkv[..., 2 * D:]
+        q = q.view(A_, T_, H, DH).transpose(1, 2)
+        k = k.view(A_, T_, H, DH).transpose(1, 2)
+        v = v.view(A_, T_, H, DH).transpose(1, 2)
+        s = (q @ k.transpose(-1, -2)) / np.sqrt(DH)
+        s = s.masked_fill(~mm[:, None, None, :], float("-inf"))
+        o_ = (torch.softmax(s, -1) @ v).transpose(1, 2).reshape(A_, T_, D)
+        hh = hh + o_ @ Wo.T + bo
+        b = torch.nn.functional.layer_norm(hh, (D,), g2, b2n, eps=1e-5)
+        hh = hh + torch.nn.functional.gelu(b @ W1.T + b1, approximate="tanh") @ W2.T + b2
+    gf, bf = take(D), take(D)
+    return torch.nn.functional.layer_norm(hh[:, 0], (D,), gf, bf, eps=1e-5)
+
+
+def test_bptt_matches_autograd_through_the_sequence(orc):
+    # three recurrent steps from zeros: the chained oracle gradient against
+    # torch float64 autograd through the whole sequence
+    th = _params(orc, 21)
+    rng = np.random.default_rng(22)
+    T_, A_ = 3, 4
+    xs, ms = zip(*[_tokens(A_, 2, 2, seed=30 + s) for s in range(T_)])
+    dls = [rng.normal(size=(A_, NA)) for _ in range(T_)]
+    t = torch.tensor(th, requires_grad=True)
+    _chain_loss_torch(xs, ms, t, dls).backward()
+    g = orc.policy_bptt(np.stack(xs), np.stack(ms), th, np.stack(dls))
+    np.testing.assert_allclose(g, t.grad.numpy(), rtol=0, atol=1e-10 * np.abs(g).max())
+    # one-step gradients (each step's state taken as a constant input) miss the
+    # later steps' dependence on the state
+    states, h = [], None
+    for s in range(T_):
+        states.append(h)
+        h = orc.policy_forward_rec(xs[s], ms[s], h, th)[1]
+    g1 = sum(orc.policy_backward_rec(xs[s], ms[s], states[s], th, dls[s])[0] for s in range(T_))
+    assert np.abs(g1 - g).max() > 1e-3 * np.abs(g).max()
+
+
+def test_bptt_matches_central_differences(orc):
+    th = _params(orc, 23)
+    rng = np.random.default_rng(24)
+    xs, ms = zip(*[_tokens(2, 2, 1, seed=40 + s) for s in range(3)])
+    dls = np.stack([rng.normal(size=(2, NA)) for _ in range(3)])
+
+    def loss(p):
+        h, tot = None, 0.0
+        for s in range(3):
+            lg, h = orc.policy_forward_rec(xs[s], ms[s], h, p)
+            tot += (lg * dls[s]).sum()
+        return tot
+    g = orc.policy_bptt(np.stack(xs), np.stack(ms), th, dls)
+    for i in rng.choice(th.size, 12, replace=False):
+        tp, tm = th.copy(), th.copy()
+        tp[i] += 1e-5
+        tm[i] -= 1e-5
+        assert g[i] == pytest.approx((loss(tp) - loss(tm)) / 2e-5, abs=1e-8 * max(1.0, np.abs(g).max()))
