@@ -546,8 +546,9 @@ int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_ag
  * GELU, head) runs in the library's kernels, the dense products in rocBLAS
  * FP32 GEMMs. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
  * the recurrent form of policy_forward_rec (n_tok - 1 observed tokens per
- * agent after the carried state). The carried state is an input of the
- * step: its gradient is returned, not followed into earlier steps. */
+ * agent after the carried state). Within one call the carried state is an
+ * input: its gradient is returned; a sequence is differentiated through the
+ * state by chaining the calls (policy_train_backward). */
 /* Workspace of the training form for A agents of n_tok rows (256-byte
  * aligned; about 11 KB per row); -1 on bad sizes. */
 int64_t policy_train_workspace_bytes(int64_t A, int32_t n_tok);
@@ -571,12 +572,18 @@ int critic_train_forward(const float *d_gstate, int64_t N, int32_t n_agents, int
 /* Reverse pass of the last forward pass recorded in d_work (same A, n_tok,
  * rec, parameters): d_dout [A][ld] the loss gradient at the first n_out
  * outputs (ppo_objective's d_dlogits with ld 8; the critic's d_dvalues with
- * ld 1, n_out 1) -> d_grad [policy_num_params()] (overwritten; layout of the
- * parameters), d_dhidden [A][64] (rec = 1, may be NULL) the gradient at the
- * carried state. Errors as for policy_train_forward. */
+ * ld 1, n_out 1); d_dnext [A][64] (may be NULL) the loss gradient at the
+ * head's input, which in the recurrent form is the state passed on to the
+ * next step -> d_grad [policy_num_params()] (layout of the parameters;
+ * overwritten, or added to with accumulate = 1), d_dhidden [A][64] (rec = 1,
+ * may be NULL) the gradient at the carried state. Back-propagation through
+ * time: the steps in reverse order, each forward pass taken again from its
+ * input state, d_dnext = the following step's d_dhidden, accumulate = 1 after
+ * the first. Errors as for policy_train_forward. */
 int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_params,
-                          const float *d_dout, int32_t ld, int32_t n_out, float *d_grad,
-                          float *d_dhidden, void *d_work, int64_t work_bytes, void *stream);
+                          const float *d_dout, int32_t ld, int32_t n_out, const float *d_dnext,
+                          int32_t accumulate, float *d_grad, float *d_dhidden, void *d_work,
+                          int64_t work_bytes, void *stream);
 /* Generalised advantage estimation (Schulman et al. 2016; the advantage
  * estimator of MAPPO) over T steps of E envs with the env's shared reward:
  * d_rewards [T][E], d_dones [T][E] (1: the step ends its episode, nothing is

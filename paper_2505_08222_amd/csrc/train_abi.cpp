@@ -90,6 +90,7 @@ struct Ctx {
   void *stream;
   double *csum;  // column-sum scratch
   float *wpart;  // weight-gradient partials [kMaxSplit + 1][N * K]
+  int acc = 0;   // parameter gradients: add into the output instead of writing
   bool ok = true;
   // Y [R][N] = X [R][K] W^T (W [N][K] row-major), added to Y when beta = 1
   void xwt(const float *X, const float *W, float *Y, int64_t R, int N, int K, float beta) {
@@ -107,11 +108,11 @@ struct Ctx {
   // kMaxSplit equal chunks (one batched GEMM, one product per chunk, plus the
   // remainder), the chunks' products then added in order
   void dw(const float *dY, const float *X, float *dW, int64_t R, int N, int K) {
-    const float one = 1.0f, zero = 0.0f;
+    const float one = 1.0f, zero = 0.0f, beta = acc ? 1.0f : 0.0f;
     const int64_t nb = R / 4096 < kMaxSplit ? R / 4096 : kMaxSplit;
     if (nb <= 1) {
       ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)R,
-                               &one, X, K, dY, N, &zero, dW, K) == rocblas_status_success;
+                               &one, X, K, dY, N, &beta, dW, K) == rocblas_status_success;
       return;
     }
     const int64_t chunk = R / nb, rem = R - nb * chunk, nk = (int64_t)N * K;
@@ -123,11 +124,11 @@ struct Ctx {
       ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N,
                                (int)rem, &one, X + nb * chunk * K, K, dY + nb * chunk * N, N,
                                &zero, wpart + nb * nk, K) == rocblas_status_success;
-    k(mil::tr_sum_partials(wpart, (int)(nb + (rem > 0)), nk, dW, stream));
+    k(mil::tr_sum_partials(wpart, (int)(nb + (rem > 0)), nk, acc, dW, stream));
   }
   // out [N] = column sums of Y [R][N]
   void colsum(const float *Y, float *out, int64_t R, int N) {
-    k(mil::tr_colsum(Y, R, N, csum, out, stream));
+    k(mil::tr_colsum(Y, R, N, csum, acc, out, stream));
   }
   void k(int rc) { ok = ok && rc == 0; }
 };
@@ -227,8 +228,9 @@ int critic_train_forward(const float *d_gstate, int64_t N, int32_t n_agents, int
 }
 
 int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_params,
-                          const float *d_dout, int32_t ld, int32_t n_out, float *d_grad,
-                          float *d_dhidden, void *d_work, int64_t work_bytes, void *stream) {
+                          const float *d_dout, int32_t ld, int32_t n_out, const float *d_dnext,
+                          int32_t accumulate, float *d_grad, float *d_dhidden, void *d_work,
+                          int64_t work_bytes, void *stream) {
   int rc = check_args(A, n_tok, rec, d_work, work_bytes);
   if (rc) return rc;
   if (n_out < 1 || n_out > NA || ld < n_out)
@@ -244,12 +246,12 @@ int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_
   auto fp = [&](int64_t off) { return (float *)(ws + off); };
   const uint8_t *mrow = (const uint8_t *)(ws + w.mrow);
   float *dh = fp(w.dh), *t64 = fp(w.t64), *dyx = fp(w.dyx);
-  Ctx c{bh, stream, (double *)(ws + w.csum), fp(w.wpart)};
+  Ctx c{bh, stream, (double *)(ws + w.csum), fp(w.wpart), accumulate ? 1 : 0};
   float *gfin = d_grad + mil::kPolOffFinal;
   // head and final LayerNorm (each agent's first row)
   c.k(mil::tr_fill(dh, 0.0f, R * D, stream));
-  c.k(mil::tr_head_back(fp(w.h[L]), A, nt, d_params, d_dout, ld, n_out, fp(w.dl8), dh, fp(w.gfa),
-                        fp(w.bfa), stream));
+  c.k(mil::tr_head_back(fp(w.h[L]), A, nt, d_params, d_dout, ld, n_out, d_dnext, fp(w.dl8), dh,
+                        fp(w.gfa), fp(w.bfa), stream));
   c.dw(fp(w.dl8), fp(w.feat), gfin + mil::kPolWh, A, NA, D);
   c.colsum(fp(w.dl8), gfin + mil::kPolBh, A, NA);
   c.colsum(fp(w.gfa), gfin + mil::kPolLnfG, A, D);
@@ -281,8 +283,11 @@ int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_
     c.colsum(t64, gp + mil::kPolLn1B, R, D);
   }
   // embedding (observed rows; a carried row's augmented input is zero)
+  const int acc = c.acc;
+  c.acc = 0;  // into the scratch matrix; the scatter then writes or adds
   c.dw(dh, fp(w.xaug), fp(w.gaug), R, D, 8);
-  c.k(mil::tr_embed_grad_scatter(fp(w.gaug), d_grad, stream));
+  c.acc = acc;
+  c.k(mil::tr_embed_grad_scatter(fp(w.gaug), c.acc, d_grad, stream));
   if (d_dhidden && rec) c.k(mil::tr_first_rows(dh, A, nt, d_dhidden, stream));
   return c.ok ? MIL_OK : mil_set_error(MIL_EHIP, "training backward launch failed");
 }

@@ -29,16 +29,20 @@ int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dx
 // final LayerNorm of each agent's first row -> feat [A][64], logits [A][8] (may be NULL)
 int tr_head(const float *h, int64_t A, int nt, const float *prm, float *logits, float *feat,
             void *stream);
+// dnext [A][64] (may be NULL): an extra gradient at the head's input
 int tr_head_back(const float *h, int64_t A, int nt, const float *prm, const float *dout, int ld,
-                 int n_out, float *dl8, float *dh, float *gfa, float *bfa, void *stream);
-int tr_embed_grad_scatter(const float *gaug, float *grad, void *stream);
+                 int n_out, const float *dnext, float *dl8, float *dh, float *gfa, float *bfa,
+                 void *stream);
+// acc = 1: add into grad instead of writing (likewise for the two below)
+int tr_embed_grad_scatter(const float *gaug, int acc, float *grad, void *stream);
 int tr_first_rows(const float *dh, int64_t A, int nt, float *out, void *stream);
 int tr_fill(float *p, float v, int64_t n, void *stream);
 // out [N] = column sums of Y [R][N] (N <= 256), FP64 in a fixed order;
 // scratch holds tr_colsum_scratch_doubles() doubles
 int64_t tr_colsum_scratch_doubles();
-int tr_colsum(const float *Y, int64_t R, int N, double *scratch, float *out, void *stream);
-// out [n] = sum over b < nb of part[b][n], in order (FP64 sums)
-int tr_sum_partials(const float *part, int nb, int64_t n, float *out, void *stream);
+int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float *out,
+              void *stream);
+// out [n] (+)= sum over b < nb of part[b][n], in order (FP64 sums)
+int tr_sum_partials(const float *part, int nb, int64_t n, int acc, float *out, void *stream);
 
 }  // namespace mil

@@ -252,7 +252,8 @@ colsum_partial_kernel(const float *__restrict__ Y, int64_t R, int N, int64_t per
 }
 
 __global__ void __launch_bounds__(256)
-colsum_final_kernel(const double *__restrict__ part, int nb, int N, float *__restrict__ out) {
+colsum_final_kernel(const double *__restrict__ part, int nb, int N, int acc,
+                    float *__restrict__ out) {
   const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (col >= N) return;  // wavefront-uniform
@@ -260,17 +261,18 @@ colsum_final_kernel(const double *__restrict__ part, int nb, int N, float *__res
   for (int b = lane; b < nb; b += 64) s += part[(int64_t)b * N + col];
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
-  if (lane == 0) out[col] = (float)s;
+  if (lane == 0) out[col] = acc ? out[col] + (float)s : (float)s;
 }
 
 // Sum of nb partial matrices of n floats each, in order.
 __global__ void __launch_bounds__(256)
-sum_partials_kernel(const float *__restrict__ part, int nb, int64_t n, float *__restrict__ out) {
+sum_partials_kernel(const float *__restrict__ part, int nb, int64_t n, int acc,
+                    float *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * n + i];
-  out[i] = (float)s;
+  out[i] = acc ? out[i] + (float)s : (float)s;
 }
 
 // One wavefront per row: LayerNorm's reverse pass. dx is added to dxacc;
@@ -319,16 +321,20 @@ head_kernel(const float *__restrict__ h, int64_t A, int nt, const float *__restr
 // pass. dl8 [A][8] = the output gradients padded with zeros (for the head's
 // weight gradient), dh row 0 of the agent = the LayerNorm's input gradient
 // (dh zero elsewhere beforehand), gfa / bfa [A][64] the per-agent terms of
-// the final LayerNorm's gain and offset gradients.
+// the final LayerNorm's gain and offset gradients. dnext [A][64] (may be
+// null): an extra gradient at the LayerNorm's output.
 __global__ void __launch_bounds__(kTrThreads)
 head_back_kernel(const float *__restrict__ h, int64_t A, int nt, const float *__restrict__ prm,
-                 const float *__restrict__ dout, int ld, int n_out, float *__restrict__ dl8,
-                 float *__restrict__ dh, float *__restrict__ gfa, float *__restrict__ bfa) {
+                 const float *__restrict__ dout, int ld, int n_out, const float *__restrict__ dnext,
+                 float *__restrict__ dl8, float *__restrict__ dh, float *__restrict__ gfa,
+                 float *__restrict__ bfa) {
   const int64_t a = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int d = threadIdx.x & 63;
   if (a >= A) return;
   const float *fp = prm + kPolOffFinal;
-  float ds = 0.0f;
+  // the gradient at the head's input: from the outputs, plus (recurrent form)
+  // the loss gradient at the state passed on to the next step
+  float ds = dnext ? dnext[a * kPolD + d] : 0.0f;
 #pragma unroll
   for (int k = 0; k < kPolActions; ++k) {
     const float gk = k < n_out ? dout[a * ld + k] : 0.0f;
@@ -350,15 +356,14 @@ head_back_kernel(const float *__restrict__ h, int64_t A, int nt, const float *__
 
 // Embedding gradient [64][8] (E's six columns, e, padding) into the
 // parameter layout.
-__global__ void embed_grad_scatter_kernel(const float *__restrict__ gaug,
+__global__ void embed_grad_scatter_kernel(const float *__restrict__ gaug, int acc,
                                           float *__restrict__ grad) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
   if (i >= kPolD * 7) return;
   const int d = i / 7, c = i - d * 7;
-  if (c < 6)
-    grad[kPolOffEmbW + d * 6 + c] = gaug[d * 8 + c];
-  else
-    grad[kPolOffEmbB + d] = gaug[d * 8 + 6];
+  float *dst = c < 6 ? grad + kPolOffEmbW + d * 6 + c : grad + kPolOffEmbB + d;
+  const float v = gaug[d * 8 + c];
+  *dst = acc ? *dst + v : v;
 }
 
 // The gradient at each agent's carried state (its first row).
@@ -437,7 +442,8 @@ int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, con
 
 int64_t tr_colsum_scratch_doubles() { return (int64_t)kCsBlocks * 256; }
 
-int tr_colsum(const float *Y, int64_t R, int N, double *scratch, float *out, void *stream) {
+int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float *out,
+              void *stream) {
   if (N < 1 || N > 256) return -1;
   hipStream_t st = (hipStream_t)stream;
   const int64_t per = R > 0 ? (R + kCsBlocks - 1) / kCsBlocks : 1;
@@ -445,14 +451,14 @@ int tr_colsum(const float *Y, int64_t R, int N, double *scratch, float *out, voi
                      scratch);
   if (check()) return -1;
   hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, scratch,
-                     kCsBlocks, N, out);
+                     kCsBlocks, N, acc, out);
   return check();
 }
 
-int tr_sum_partials(const float *part, int nb, int64_t n, float *out, void *stream) {
+int tr_sum_partials(const float *part, int nb, int64_t n, int acc, float *out, void *stream) {
   if (n == 0) return 0;
   hipLaunchKernelGGL(sum_partials_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream,
-                     part, nb, n, out);
+                     part, nb, n, acc, out);
   return check();
 }
 
@@ -473,16 +479,17 @@ int tr_head(const float *h, int64_t A, int nt, const float *prm, float *logits, 
 }
 
 int tr_head_back(const float *h, int64_t A, int nt, const float *prm, const float *dout, int ld,
-                 int n_out, float *dl8, float *dh, float *gfa, float *bfa, void *stream) {
+                 int n_out, const float *dnext, float *dl8, float *dh, float *gfa, float *bfa,
+                 void *stream) {
   if (A == 0) return 0;
   hipLaunchKernelGGL(head_back_kernel, grid_for(A * 64), dim3(kTrThreads), 0, (hipStream_t)stream,
-                     h, A, nt, prm, dout, ld, n_out, dl8, dh, gfa, bfa);
+                     h, A, nt, prm, dout, ld, n_out, dnext, dl8, dh, gfa, bfa);
   return check();
 }
 
-int tr_embed_grad_scatter(const float *gaug, float *grad, void *stream) {
+int tr_embed_grad_scatter(const float *gaug, int acc, float *grad, void *stream) {
   hipLaunchKernelGGL(embed_grad_scatter_kernel, dim3(2), dim3(kTrThreads), 0, (hipStream_t)stream,
-                     gaug, grad);
+                     gaug, acc, grad);
   return check();
 }
 

@@ -38,7 +38,8 @@ def _l():
         L.policy_train_forward.restype = C.c_int
         L.critic_train_forward.argtypes = [V, I64, I32, I32, F, I32, V, V, V, V, V, I64, V]
         L.critic_train_forward.restype = C.c_int
-        L.policy_train_backward.argtypes = [I64, I32, I32, V, V, I32, I32, V, V, V, I64, V]
+        L.policy_train_backward.argtypes = [I64, I32, I32, V, V, I32, I32, V, I32, V, V, V, I64,
+                                            V]
         L.policy_train_backward.restype = C.c_int
         L._ppo_registered = True
     return L
@@ -199,19 +200,47 @@ class TrainPass:
                                         self._n, _stream()))
         return values, feat
 
-    def backward(self, params, dout, n_out: int, grad=None):
-        """dout [A, ld] (or [A]) -> (gradient [P], gradient at the carried
-        state [A, 64] or None)."""
+    def backward(self, params, dout, n_out: int, grad=None, dnext=None, accumulate=False):
+        """dout [A, ld] (or [A]), dnext [A, 64] (the gradient at the state
+        passed on, or None) -> (gradient [P] (added to `grad` with
+        accumulate), gradient at the carried state [A, 64] or None)."""
         d = (dout.reshape(self.A, 1) if dout.dim() == 1
              else dout.reshape(self.A, dout.shape[-1])).contiguous()
         if grad is None:
             grad = torch.empty_like(params)
+            accumulate = False
         dh = (torch.empty((self.A, 64), dtype=torch.float32, device=self.device)
               if self.rec else None)
+        dn = None if dnext is None else dnext.contiguous()
         check(_l().policy_train_backward(self.A, self.n_tok, self.rec, ptr(params), ptr(d),
-                                         d.shape[1], n_out, ptr(grad), ptr(dh), self._w, self._n,
-                                         _stream()))
+                                         d.shape[1], n_out, ptr(dn), int(bool(accumulate)),
+                                         ptr(grad), ptr(dh), self._w, self._n, _stream()))
         return grad, dh
+
+
+def bptt(tp: TrainPass, forward, douts, params, n_out: int, grad=None):
+    """Back-propagation through time over T steps of the recurrent form,
+    started from zeros. forward(t, hidden) runs step t's training-form
+    forward pass on `tp` (tp.forward or tp.critic_forward with the step's
+    inputs) and returns its outputs, the second being the state it passes on;
+    douts[t] the loss gradient at step t's outputs. The forward chain runs
+    once to record the states, then the steps in reverse order: each forward
+    pass again from its input state, its reverse pass with the following
+    step's state gradient, the parameter gradients summed. Returns (gradient
+    [P], the states [T, A, 64])."""
+    assert tp.rec == 1
+    T = len(douts)
+    states = []
+    h = None
+    for t in range(T):
+        h = forward(t, h)[1].clone()
+        states.append(h)
+    dnext = None
+    for t in range(T - 1, -1, -1):
+        forward(t, states[t - 1] if t > 0 else None)
+        grad, dnext = tp.backward(params, douts[t], n_out, grad=grad, dnext=dnext,
+                                  accumulate=t < T - 1)
+    return grad, torch.stack(states)
 
 
 class Learner:

@@ -206,3 +206,59 @@ def test_learner_iteration_on_closed_loop_experience():
           "surrogate", o0[0].item(), "->", o1[0].item())
     assert o1[0].item() < o0[0].item()
     env.close()
+
+
+def test_bptt_matches_oracle(orc):
+    # three recurrent steps from zeros, differentiated through the carried
+    # state: the GPU's chain against the oracle's (policy_bptt)
+    from paper_2505_08222_amd import ppo
+    na, nt, E, T = 2, 3, 21, 3
+    A, n_obs = E * na, na + nt
+    th = policy_params(orc.policy_num_params(), seed=12)
+    seq = [policy_tokens(A, na, nt, seed=50 + t) for t in range(T)]
+    rng = np.random.default_rng(5)
+    dls = rng.normal(size=(T, A, 8)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    params = dev(th)
+    tp = ppo.TrainPass(A, n_obs + 1, rec=1)
+    obs = [dev(x.reshape(-1, 6)) for x, _ in seq]
+    msk = [dev(m.reshape(-1)) for _, m in seq]
+    grad, states = ppo.bptt(tp, lambda t, h: tp.forward(obs[t], msk[t], params, h),
+                            [dev(d) for d in dls], params, 8)
+    want = orc.policy_bptt(np.stack([x.astype(np.float64) for x, _ in seq]),
+                           np.stack([m for _, m in seq]), th.astype(np.float64),
+                           dls.astype(np.float64))
+    worst = _check_grad(grad.cpu().numpy(), want, tol=5e-4)
+    print(f"bptt {T} steps x {A} agents: grad err {worst:.1e}")
+    # accumulate: a second reverse pass of the last step adds its gradient
+    tp.forward(obs[T - 1], msk[T - 1], params, states[T - 2])
+    g_last, _ = tp.backward(params, dev(dls[T - 1]), 8)
+    tp.forward(obs[T - 1], msk[T - 1], params, states[T - 2])
+    g2, _ = tp.backward(params, dev(dls[T - 1]), 8, grad=g_last.clone(), accumulate=True)
+    np.testing.assert_allclose(g2.cpu().numpy(), 2 * g_last.cpu().numpy(), rtol=1e-6,
+                               atol=1e-6 * float(g_last.abs().max()))
+
+
+def test_critic_bptt_matches_oracle(orc):
+    from oracle import ppo_oracle as po
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.env import Env
+    na, nt, E, T = 2, 2, 29, 3
+    cfg = env_config("batched", n_agents=na, n_targets=nt, episode_len=T)
+    env = Env(cfg, E, seed=8)
+    env.reset(0)
+    gs = env.rollout(T, record=("gstate",))["gstate"]
+    params = policy.init_params(15)
+    rng = np.random.default_rng(6)
+    dv = rng.normal(size=(T, E)).astype(np.float32)
+    tc = ppo.TrainPass(E, na + nt + 1, rec=1)
+    grad, _ = ppo.bptt(tc, lambda t, h: tc.critic_forward(gs[t], na, nt, params, hidden=h),
+                       [torch.tensor(dv[t], device="cuda") for t in range(T)], params, 1)
+    g = gs.cpu().numpy().astype(np.float64).reshape(T, E, na + nt, 6)
+    tok = np.stack([po.critic_tokens(g[t], na, nt, 1000.0)[:, 1:] for t in range(T)])
+    dl = np.zeros((T, E, 8))
+    dl[..., 0] = dv
+    want = orc.policy_bptt(tok, np.ones(tok.shape[:3], np.uint8),
+                           params.cpu().numpy().astype(np.float64), dl)
+    _check_grad(grad.cpu().numpy(), want, tol=5e-4)
+    env.close()
