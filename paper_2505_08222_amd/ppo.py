@@ -218,70 +218,105 @@ class TrainPass:
         return grad, dh
 
 
-def bptt(tp: TrainPass, forward, douts, params, n_out: int, grad=None):
-    """Back-propagation through time over T steps of the recurrent form,
-    started from zeros. forward(t, hidden) runs step t's training-form
-    forward pass on `tp` (tp.forward or tp.critic_forward with the step's
-    inputs) and returns its outputs, the second being the state it passes on;
-    douts[t] the loss gradient at step t's outputs. The forward chain runs
-    once to record the states, then the steps in reverse order: each forward
-    pass again from its input state, its reverse pass with the following
-    step's state gradient, the parameter gradients summed. Returns (gradient
-    [P], the states [T, A, 64])."""
+def chain_forward(tp: TrainPass, forward, T: int):
+    """The forward chain of T steps of the recurrent form from zeros:
+    forward(t, hidden) runs step t's training-form forward pass on `tp`
+    (tp.forward or tp.critic_forward with the step's inputs) and returns its
+    outputs, the second being the state it passes on. Returns (first outputs
+    [T, ...], states [T, A, 64])."""
     assert tp.rec == 1
-    T = len(douts)
-    states = []
+    outs, states = [], []
     h = None
     for t in range(T):
-        h = forward(t, h)[1].clone()
+        o = forward(t, h)
+        outs.append(o[0].clone())
+        h = o[1].clone()
         states.append(h)
+    return torch.stack(outs), torch.stack(states)
+
+
+def chain_backward(tp: TrainPass, forward, states, douts, params, n_out: int, grad=None):
+    """The reverse pass of a chain recorded by chain_forward: the steps in
+    reverse order, each forward pass taken again from its input state and
+    reversed with the following step's state gradient, the parameter
+    gradients summed. douts[t]: the loss gradient at step t's outputs."""
+    T = len(douts)
     dnext = None
     for t in range(T - 1, -1, -1):
         forward(t, states[t - 1] if t > 0 else None)
         grad, dnext = tp.backward(params, douts[t], n_out, grad=grad, dnext=dnext,
                                   accumulate=t < T - 1)
-    return grad, torch.stack(states)
+    return grad
+
+
+def bptt(tp: TrainPass, forward, douts, params, n_out: int, grad=None):
+    """Back-propagation through time over T = len(douts) steps of the
+    recurrent form started from zeros (chain_forward, then chain_backward).
+    Returns (gradient [P], the states [T, A, 64])."""
+    _, states = chain_forward(tp, forward, len(douts))
+    return chain_backward(tp, forward, states, douts, params, n_out, grad), states
 
 
 class Learner:
     """The learner's loop over one batch of closed-loop experience (MAPPO,
     Sec. III-B, with the TransfMAPPO networks): critic values of every
-    state, GAE, then `epochs` passes over `minibatches` groups of whole steps,
-    each a training-form forward and reverse pass of the actor (clipped
-    surrogate) and the critic (squared error to the GAE returns) and an Adam
-    step on every parameter of both. Orchestration only: every step of it is
-    one of the library's entry points."""
+    state, GAE, then `epochs` passes over `minibatches` groups, each a
+    training-form forward and reverse pass of the actor (clipped surrogate)
+    and the critic (squared error to the GAE returns) and an Adam step on
+    every parameter of both. Plain form: minibatches of whole steps.
+    Recurrent form (recurrent=True, both networks with their carried
+    state, started from zeros at the batch's first step, an episode start):
+    minibatches of whole envs over all steps, differentiated through time.
+    Orchestration only: every step of it is one of the library's entry
+    points."""
 
     def __init__(self, actor, critic, n_agents: int, n_targets: int, n_actions: int = 5,
                  lr: float = 3e-4, clip_eps: float = 0.2, gamma: float = 0.99, lam: float = 0.95,
-                 pos_scale: float = 1000.0):
+                 pos_scale: float = 1000.0, recurrent: bool = False):
         from .learned import Adam
+        self.recurrent = bool(recurrent)
         self.actor, self.critic = actor, critic
         self.na, self.nt, self.n_actions = n_agents, n_targets, n_actions
         self.opt_a, self.opt_c = Adam(actor, lr=lr), Adam(critic, lr=lr)
         self.clip_eps, self.gamma, self.lam, self.pos_scale = clip_eps, gamma, lam, pos_scale
         self._passes = {}
 
-    def _pass(self, A, n_tok):
-        key = (A, n_tok)
+    def _pass(self, A, n_tok, rec=0):
+        key = (A, n_tok, rec)
         if key not in self._passes:
-            self._passes[key] = TrainPass(A, n_tok, device=self.actor.device)
+            self._passes[key] = TrainPass(A, n_tok, rec, device=self.actor.device)
         return self._passes[key]
 
+    def _critic_fn(self, tp, gs):
+        return lambda t, h: tp.critic_forward(gs[t], self.na, self.nt, self.critic, hidden=h,
+                                              pos_scale=self.pos_scale)
+
+    def _actor_fn(self, tp, obs, mask):
+        return lambda t, h: tp.forward(obs[t], mask[t], self.actor, h)
+
     def values(self, gstate):
-        """V of states gstate [S, E, M, 6] -> [S, E] (training form, FP32)."""
+        """V of states gstate [S, E, M, 6] -> [S, E] (training form, FP32;
+        the recurrent critic runs them in order from zeros)."""
         S = gstate.shape[0]
-        E = gstate.reshape(S, -1, self.na + self.nt, 6).shape[1]
-        tp = self._pass(E, self.na + self.nt + 1)
-        return torch.stack([tp.critic_forward(gstate[s], self.na, self.nt, self.critic,
+        M = self.na + self.nt
+        gs = gstate.reshape(S, -1, M, 6)
+        E = gs.shape[1]
+        tp = self._pass(E, M + 1, int(self.recurrent))
+        if self.recurrent:
+            return chain_forward(tp, self._critic_fn(tp, gs), S)[0]
+        return torch.stack([tp.critic_forward(gs[s], self.na, self.nt, self.critic,
                                               pos_scale=self.pos_scale)[0].clone()
                             for s in range(S)])
 
     def logits(self, obs, mask):
-        """Actor logits of obs [T, A * n_tok, 6] -> [T, A, 8] (training form)."""
+        """Actor logits of obs [T, A * n_tok, 6] -> [T, A, 8] (training form;
+        the recurrent actor runs the steps in order from zeros)."""
         T = obs.shape[0]
         n_tok = self.na + self.nt
         A = obs.shape[1] // n_tok
+        if self.recurrent:
+            tp = self._pass(A, n_tok + 1, 1)
+            return chain_forward(tp, self._actor_fn(tp, obs, mask), T)[0]
         tp = self._pass(A, n_tok)
         return torch.stack([tp.forward(obs[t], mask[t], self.actor)[0].clone() for t in range(T)])
 
@@ -298,6 +333,9 @@ class Learner:
         values = self.values(gstate.reshape(T + 1, E, M, 6))
         adv, ret = gae(rewards, dones, values, self.gamma, self.lam)
         logits_old = self.logits(obs, mask)
+        if self.recurrent:
+            return self._update_rec(obs, mask, actions, gstate.reshape(T + 1, E, M, 6), adv, ret,
+                                    logits_old, epochs, minibatches)
         assert T % minibatches == 0, "minibatches must divide the batch's steps"
         k = T // minibatches
         ta = self._pass(k * A, n_tok)
@@ -316,6 +354,38 @@ class Learner:
                                         self.n_actions, self.clip_eps)
                 ga, _ = ta.backward(self.actor, dl.reshape(k * A, 8), self.n_actions)
                 gc, _ = tc.backward(self.critic, dv.reshape(k * E), 1)
+                self.opt_a.step(ga)
+                self.opt_c.step(gc)
+                history.append(out)
+        return torch.stack(history)
+
+    def _update_rec(self, obs, mask, actions, gs, adv, ret, logits_old, epochs, minibatches):
+        T, A = actions.shape
+        E = A // self.na
+        n_tok, M = self.na + self.nt, self.na + self.nt
+        assert E % minibatches == 0, "minibatches must divide the batch's envs"
+        Em = E // minibatches
+        Am = Em * self.na
+        ta = self._pass(Am, n_tok + 1, 1)
+        tc = self._pass(Em, M + 1, 1)
+        history = []
+        for _ in range(epochs):
+            for mb in range(minibatches):
+                e0, e1 = mb * Em, (mb + 1) * Em
+                a0, a1 = e0 * self.na, e1 * self.na
+                o = obs[:, a0 * n_tok:a1 * n_tok].contiguous()
+                m = mask[:, a0 * n_tok:a1 * n_tok].contiguous()
+                g = gs[:T, e0:e1].contiguous()
+                fa, fc = self._actor_fn(ta, o, m), self._critic_fn(tc, g)
+                ln, sa = chain_forward(ta, fa, T)
+                v, sc = chain_forward(tc, fc, T)
+                out, dl, dv = objective(ln, logits_old[:, a0:a1].contiguous(),
+                                        actions[:, a0:a1].contiguous(), adv[:, e0:e1].contiguous(),
+                                        v, ret[:, e0:e1].contiguous(), self.na, self.n_actions,
+                                        self.clip_eps)
+                ga = chain_backward(ta, fa, sa, [dl[t] for t in range(T)], self.actor,
+                                    self.n_actions)
+                gc = chain_backward(tc, fc, sc, [dv[t] for t in range(T)], self.critic, 1)
                 self.opt_a.step(ga)
                 self.opt_c.step(gc)
                 history.append(out)

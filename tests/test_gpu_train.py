@@ -192,13 +192,14 @@ def test_learner_iteration_on_closed_loop_experience():
     a0, c0 = actor.clone(), critic.clone()
     lr = ppo.Learner(actor, critic, na, nt, lr=1e-4)
     before = lr.logits(obs, mask)
+    # the advantages the update itself uses (the critic before the update)
+    vals = lr.values(gs.reshape(T + 1, E, na + nt, 6))
+    adv, ret = ppo.gae(out["reward"], out["done"], vals, 0.99, 0.95)
     hist = lr.update(obs, mask, out["actions"], gs, out["reward"], out["done"], epochs=2,
                      minibatches=2)
     assert torch.isfinite(hist).all()
     assert not torch.equal(actor, a0) and not torch.equal(critic, c0)
     # the surrogate of the whole batch at the new logits against the old ones
-    vals = lr.values(gs.reshape(T + 1, E, na + nt, 6))
-    adv, ret = ppo.gae(out["reward"], out["done"], vals, 0.99, 0.95)
     after = lr.logits(obs, mask)
     o0, _, _ = ppo.objective(before, before, out["actions"], adv, vals[:T].contiguous(), ret, na, 5)
     o1, _, _ = ppo.objective(after, before, out["actions"], adv, vals[:T].contiguous(), ret, na, 5)
@@ -261,4 +262,40 @@ def test_critic_bptt_matches_oracle(orc):
     want = orc.policy_bptt(tok, np.ones(tok.shape[:3], np.uint8),
                            params.cpu().numpy().astype(np.float64), dl)
     _check_grad(grad.cpu().numpy(), want, tol=5e-4)
+    env.close()
+
+
+def test_recurrent_learner_on_closed_loop_experience():
+    # the recurrent closed loop's experience through the recurrent learner
+    # (both networks differentiated through time over the batch's 12 steps,
+    # minibatches of whole envs): finite losses, both networks changed, the
+    # batch's surrogate lower afterwards
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.env import Env
+    na, nt, E, T, ep = 2, 2, 48, 12, 0
+    cfg = env_config("policy", episode_len=T, n_agents=na, n_targets=nt)
+    env = Env(cfg, E, seed=12)
+    actor, critic = policy.init_params(42), policy.init_params(43)
+    r0 = env.reset(ep, record=("obs", "obs_mask", "gstate"))
+    out, _ = policy.PolicyRollout(env, actor, recurrent=True).run(
+        T, episode=ep, record=("obs", "obs_mask", "actions", "gstate", "reward", "done"))
+    obs = torch.cat([r0["obs"][None], out["obs"][:T - 1]])
+    mask = torch.cat([r0["obs_mask"][None], out["obs_mask"][:T - 1]])
+    gs = torch.cat([r0["gstate"][None], out["gstate"]])
+    a0, c0 = actor.clone(), critic.clone()
+    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4, recurrent=True)
+    before = lr.logits(obs, mask)
+    # the advantages the update itself uses (the critic before the update)
+    vals = lr.values(gs.reshape(T + 1, E, na + nt, 6))
+    adv, ret = ppo.gae(out["reward"], out["done"], vals, 0.99, 0.95)
+    hist = lr.update(obs, mask, out["actions"], gs, out["reward"], out["done"], epochs=2,
+                     minibatches=2)
+    assert torch.isfinite(hist).all()
+    assert not torch.equal(actor, a0) and not torch.equal(critic, c0)
+    after = lr.logits(obs, mask)
+    o0, _, _ = ppo.objective(before, before, out["actions"], adv, vals[:T].contiguous(), ret, na, 5)
+    o1, _, _ = ppo.objective(after, before, out["actions"], adv, vals[:T].contiguous(), ret, na, 5)
+    print("recurrent learner: minibatch losses", hist[:, :2].cpu().numpy().round(4).tolist(),
+          "surrogate", o0[0].item(), "->", o1[0].item())
+    assert o1[0].item() < o0[0].item()
     env.close()
