@@ -45,8 +45,10 @@ def _check_grad(got, want, tol=2e-4):
     return worst
 
 
+# the last case has 1001 agents x 9 tokens = 9009 rows: the weight gradients
+# take the split-K path (row chunks summed in order, with a remainder chunk)
 @pytest.mark.parametrize("n_agents,n_targets,n_envs", [(5, 5, 41), (2, 3, 29), (1, 1, 17),
-                                                       (7, 8, 9)])
+                                                       (7, 8, 9), (7, 2, 143)])
 def test_policy_gradient_matches_oracle(orc, n_agents, n_targets, n_envs):
     from paper_2505_08222_amd import ppo
     A = n_envs * n_agents
@@ -299,3 +301,31 @@ def test_recurrent_learner_on_closed_loop_experience():
           "surrogate", o0[0].item(), "->", o1[0].item())
     assert o1[0].item() < o0[0].item()
     env.close()
+
+
+def test_accumulate_on_the_split_k_path(orc):
+    # 1001 agents x 9 rows (the recurrent form: 8 tokens + the state): the
+    # weight gradients take the split-K path with a remainder chunk; adding a
+    # second reverse pass of the same step gives twice the first, and the
+    # first matches the oracle
+    from paper_2505_08222_amd import ppo
+    A = 1001
+    x, m = policy_tokens(A, 1, 7, seed=19)
+    th = policy_params(orc.policy_num_params(), seed=13)
+    rng = np.random.default_rng(9)
+    hid = rng.normal(size=(A, D)).astype(np.float32)
+    dl = rng.normal(size=(A, 8)).astype(np.float32)
+    dn = rng.normal(size=(A, D)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    params = dev(th)
+    tp = ppo.TrainPass(A, 9, rec=1)
+    tp.forward(dev(x.reshape(-1, 6)), dev(m.reshape(-1)), params, dev(hid))
+    g1, dh = tp.backward(params, dev(dl), 8, dnext=dev(dn))
+    g2, _ = tp.backward(params, dev(dl), 8, dnext=dev(dn), grad=g1.clone(), accumulate=True)
+    np.testing.assert_allclose(g2.cpu().numpy(), 2 * g1.cpu().numpy(), rtol=1e-6,
+                               atol=1e-6 * float(g1.abs().max()))
+    gw, dhw = orc.policy_backward_rec(x.astype(np.float64), m, hid.astype(np.float64),
+                                      th.astype(np.float64), dl.astype(np.float64),
+                                      dn.astype(np.float64))
+    _check_grad(g1.cpu().numpy(), gw)
+    assert np.abs(dh.cpu().numpy() - dhw).max() <= 2e-4 * np.abs(dhw).max()
