@@ -546,7 +546,9 @@ int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_ag
  * GELU, head) runs in the library's kernels, the dense products in rocBLAS
  * FP32 GEMMs. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
  * the recurrent form of policy_forward_rec (n_tok - 1 observed tokens per
- * agent after the carried state). Within one call the carried state is an
+ * agent after the carried state). The library keeps one rocBLAS handle per
+ * device for these calls: calls on one device must not overlap from several
+ * host threads. Within one call the carried state is an
  * input: its gradient is returned; a sequence is differentiated through the
  * state by chaining the calls (policy_train_backward). */
 /* Workspace of the training form for A agents of n_tok rows (256-byte

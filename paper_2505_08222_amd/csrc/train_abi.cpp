@@ -8,6 +8,7 @@
 #include <rocblas/rocblas.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "mi_lrauv.h"
 #include "policy_internal.h"
@@ -70,11 +71,15 @@ TrainWork train_work(int64_t A, int nt) {
 }
 
 // One rocBLAS handle per device, made on first use (pointer mode host,
-// atomics off so that every sum is taken in one order).
+// atomics off so that every sum is taken in one order). The handle carries
+// the stream of the call in progress: training-form calls on one device must
+// not overlap from several host threads.
 rocblas_handle blas_for_current_device() {
   static rocblas_handle handles[64] = {};
+  static std::mutex made;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(made);
   if (!handles[dev]) {
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) return nullptr;
