@@ -983,13 +983,30 @@ infer_kernel(const float *__restrict__ win, int64_t N, int32_t W, const float *_
   load_bfrag(f2, w2g, kLdH);
   const int64_t ntiles = (N + 63) / 64;
   const int wlen = W * 3;
+  // the tile's windows (contiguous) are held in registers a tile ahead: each
+  // thread's share of the next tile is in flight while this one computes
+  constexpr int kPre = (64 * kMaxW * 3 + 255) / 256;
+  float pre[kPre];
+  auto fetch = [&](int64_t tile) {
+    const int64_t t0 = tile * 64;
+    const int nwt = tile < ntiles ? ((N - t0) < 64 ? (int)(N - t0) : 64) : 0;
+    const float *src = win + t0 * wlen;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = tid + q * 256;
+      pre[q] = e < nwt * wlen ? src[e] : 0.0f;
+    }
+  };
+  fetch(blockIdx.x);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t s0 = tile * 64;
     const int nw = (N - s0) < 64 ? (int)(N - s0) : 64;  // windows in this tile
-    {
-      const float *src = win + s0 * wlen;
-      for (int e = tid; e < nw * wlen; e += blockDim.x) L.win[e] = src[e];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = tid + q * 256;
+      if (e < nw * wlen) L.win[e] = pre[q];
     }
+    fetch(tile + gridDim.x);
     __syncthreads();
     // features (the same quantities as window_features): four threads per
     // window, each taking entries part, part + 4, ...; the window's sums are
