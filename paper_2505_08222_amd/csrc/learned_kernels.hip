@@ -932,6 +932,120 @@ forward_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict
   }
 }
 
+// BF16 forward pass, persistent: the same layers as forward_kernel<bf16> with
+// the structure of the inference kernel below (both hidden layers' weight
+// fragments in registers for every tile, the next tile's features in
+// registers while this one computes, the output layer fused into the second
+// layer's epilogue: each lane's four BF16-rounded activations, then the four
+// lanes of a row and the four wavefronts in a fixed order).
+struct FwdBfLds {
+  float w3[2][kHidden];
+  float b1[kHidden], b2[kHidden], b3[4];
+  __bf16 x[64][kIn + 8];
+  __bf16 h1[64][kHidden + 8];
+  float ypart[64][4][2];
+};
+static_assert(offsetof(FwdBfLds, x) % 16 == 0 && offsetof(FwdBfLds, h1) % 16 == 0 &&
+                  offsetof(FwdBfLds, b1) % 16 == 0 && offsetof(FwdBfLds, b2) % 16 == 0,
+              "MFMA operands and float4 parameter reads need 16-byte alignment");
+
+__global__ void __launch_bounds__(256)
+forward_bf16_kernel(int64_t N, const float *__restrict__ xin, const float *__restrict__ th,
+                    const __bf16 *__restrict__ w1g, const __bf16 *__restrict__ w2g,
+                    float *__restrict__ y) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FwdBfLds &L = *reinterpret_cast<FwdBfLds *>(smem);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 2 * kHidden; e += blockDim.x) (&L.w3[0][0])[e] = th[kOffW3 + e];
+  for (int e = tid; e < kHidden; e += blockDim.x) {
+    L.b1[e] = th[kOffB1 + e];
+    L.b2[e] = th[kOffB2 + e];
+  }
+  if (tid < 2) L.b3[tid] = th[kOffB3 + tid];
+  BFrag<kIn, kHidden> f1;
+  BFrag<kHidden, kHidden> f2;
+  load_bfrag(f1, w1g, kLdIn);
+  load_bfrag(f2, w2g, kLdH);
+  const int64_t ntiles = (N + 63) / 64;
+  constexpr int kPre = 64 * kIn / 256;
+  float pre[kPre];
+  auto fetch = [&](int64_t tile) {
+    const int64_t t0 = tile * 64;
+    const int nst = tile < ntiles ? ((N - t0) < 64 ? (int)(N - t0) : 64) : 0;
+    const float *src = xin + t0 * kIn;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = tid + q * 256;
+      pre[q] = e < nst * kIn ? src[e] : 0.0f;
+    }
+  };
+  fetch(blockIdx.x);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t s0 = tile * 64;
+    const int ns = (N - s0) < 64 ? (int)(N - s0) : 64;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = tid + q * 256;  // samples past the end stay zero
+      L.x[e / kIn][e % kIn] = __float2bfloat16(pre[q]);
+    }
+    fetch(tile + gridDim.x);
+    __syncthreads();
+    gemm_rs_bf16_tf<kIn, kHidden>(&L.x[0][0], kIn + 8, f1, 64,
+                                  [&](int m, int n, const floatx4 &v) {
+                                    const float4 b = *reinterpret_cast<const float4 *>(&L.b1[n]);
+                                    const bf16x4 h = {__float2bfloat16(gelu_tanh_fast(v[0] + b.x)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[1] + b.y)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[2] + b.z)),
+                                                      __float2bfloat16(gelu_tanh_fast(v[3] + b.w))};
+                                    *reinterpret_cast<bf16x4 *>(&L.h1[m][n]) = h;
+                                  });
+    __syncthreads();
+    {
+      const int wave = tid >> 6, lane = tid & 63, row = lane & 15, kg = lane >> 4;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        bf16x8 a[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+          a[ks] = *reinterpret_cast<const bf16x8 *>(&L.h1[16 * mt + row][ks * 32 + 8 * kg]);
+        float y0 = 0.0f, y1 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int ks = 0; ks < 4; ++ks)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f2.v[c][ks], a[ks], acc, 0, 0, 0);
+          const int n = ((wave + 4 * c) << 4) + 4 * kg;
+          const float4 b = *reinterpret_cast<const float4 *>(&L.b2[n]);
+          const float4 u0 = *reinterpret_cast<const float4 *>(&L.w3[0][n]);
+          const float4 u1 = *reinterpret_cast<const float4 *>(&L.w3[1][n]);
+          const float bb[4] = {b.x, b.y, b.z, b.w}, w0[4] = {u0.x, u0.y, u0.z, u0.w},
+                      w1[4] = {u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float h = __bfloat162float(__float2bfloat16(gelu_tanh_fast(acc[j] + bb[j])));
+            y0 = fmaf(w0[j], h, y0);
+            y1 = fmaf(w1[j], h, y1);
+          }
+        }
+        y0 = col_sum4(y0);
+        y1 = col_sum4(y1);
+        if (kg == 0) {
+          L.ypart[16 * mt + row][wave][0] = y0;
+          L.ypart[16 * mt + row][wave][1] = y1;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 2 * ns) {
+      const int s = tid >> 1, o = tid & 1;
+      y[(s0 + s) * 2 + o] = L.b3[o] + ((L.ypart[s][0][o] + L.ypart[s][1][o]) +
+                                       (L.ypart[s][2][o] + L.ypart[s][3][o]));
+    }
+    __syncthreads();  // before the next tile's features overwrite the stage
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Inference: persistent blocks (as many as fit a CU) loop over tiles of 64 windows.
 // The tile's windows (contiguous in memory) are staged in LDS with coalesced
@@ -1304,9 +1418,22 @@ int launch_forward(int64_t N, const float *x, const float *th, int precision, co
   const unsigned blocks = (unsigned)((N + 63) / 64);
   if (precision == 0) {
     const __bf16 *w1 = (const __bf16 *)prep, *w2 = w1 + kHidden * kLdIn;
-    if (allow_lds((const void *)forward_kernel<__bf16>, sizeof(FwdLds<__bf16>))) return -1;
-    hipLaunchKernelGGL(forward_kernel<__bf16>, dim3(blocks), dim3(256), sizeof(FwdLds<__bf16>),
-                       st, N, x, th, w1, w2, y);
+    // persistent: as many blocks as fit the CUs, each looping over tiles
+    static int per_cu = 0;  // resident blocks per CU (registers and LDS decide)
+    if (per_cu == 0 &&
+        (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)forward_bf16_kernel,
+                                                      256, sizeof(FwdBfLds)) != hipSuccess ||
+         per_cu < 1))
+      per_cu = 1;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    const int64_t slots = (int64_t)per_cu * cus;
+    const unsigned grid = (unsigned)((int64_t)blocks < slots ? blocks : slots);
+    hipLaunchKernelGGL(forward_bf16_kernel, dim3(grid), dim3(256), sizeof(FwdBfLds), st, N, x, th,
+                       w1, w2, y);
   } else {
     const float *w1 = (const float *)prep, *w2 = w1 + kHidden * kLdIn;
     if (allow_lds((const void *)forward_kernel<float>, sizeof(FwdLds<float>))) return -1;
