@@ -139,9 +139,10 @@ struct Ctx {
 };
 
 int check_args(int64_t A, int32_t n_tok, int32_t rec, void *d_work, int64_t work_bytes) {
-  if (A < 1 || rec < 0 || rec > 1 || n_tok < 1 + rec || n_tok > mil::kPolMaxTok ||
-      A * n_tok > INT32_MAX / (3 * D))
+  if (A < 1 || rec < 0 || rec > 1 || n_tok < 1 + rec || n_tok > mil::kPolMaxTok)
     return mil_set_error(MIL_EINVAL, "need A >= 1, rec in {0, 1}, n_tok in 1 + rec..16");
+  if (A * n_tok > INT32_MAX / (3 * D))
+    return mil_set_error(MIL_EINVAL, "A * n_tok too large for one pass (split the batch)");
   if (!d_work || (((uintptr_t)d_work) & 255))
     return mil_set_error(MIL_EALIGN, "workspace must be 256-byte aligned");
   if (work_bytes < train_work(A, n_tok).total)
