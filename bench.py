@@ -690,8 +690,8 @@ def bench_ppo(args, T=32, cpu_seconds=None):
         "data": "synthetic tensors of the workload's shapes",
         "config": {"workload": f"PPO batch: {E} envs x {na} agents x {nt} targets x {T} steps: "
                                "critic on T + 1 states, policy on T steps (with the heads' "
-                               "inputs), GAE, clipped objective, head gradients and Adam (no "
-                               "backward through the transformers below the heads)",
+                               "inputs), GAE, clipped objective, head gradients and Adam; the "
+                               "full update of every parameter is timed under full_update",
                    "envs": E, "agents": A, "batch_steps": T},
         "ms": {"critic": t_crit, "policy": t_pol, "gae": t_gae, "objective": t_obj,
                "head_grad": t_hg, "adam": t_adam, "total": total},

@@ -420,8 +420,9 @@ int env_pf_update(mil_env *h, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Attention policy: the per-agent transformer actor of Sec. IV-B-1
- * (TransfMAPPO) without its recurrent token, forward only, BF16 MFMA with FP32
- * accumulation. Each agent's tokens (its observation, [self, agents, targets],
+ * (TransfMAPPO), inference form (BF16 MFMA with FP32 accumulation), plain or
+ * with its recurrent token (policy_forward_rec); the training form is with the
+ * learner below. Each agent's tokens (its observation, [self, agents, targets],
  * n_tok = n_agents + n_targets <= 16) are embedded 6 -> 64, pass 2 pre-LN
  * layers of 4-head self-attention (keys with mask 0 excluded) and a 256-wide
  * GELU feed-forward block, and the self token's final LayerNorm gives 8

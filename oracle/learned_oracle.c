@@ -256,8 +256,8 @@ void orc_range_refine(int64_t N, int W, const double *win, const double *centre,
 }
 
 /* ------------------------------------------------------------------------ */
-/* Attention policy (the TransfMAPPO actor of Sec. IV-B-1, without its        */
-/* recurrent token; random initialisation, forward only). Tokens of one      */
+/* Attention policy (the TransfMAPPO actor of Sec. IV-B-1; the plain form   */
+/* here, the recurrent form and the gradient further down). Tokens of one    */
 /* agent: [self, other agents, targets], each (dx, dy, dz, one-hot type).    */
 /* Pre-LN transformer: h = E x + e; for each layer: h += Wo MHA(LN1(h)) + bo,*/
 /* h += W2 gelu(W1 LN2(h) + b1) + b2; logits = Wh LN_f(h_self) + bh.         */
