@@ -157,6 +157,7 @@ def pf_kernel_roofline(env, cfg, workload, full_size):
         roof.update(hbm)
     if traffic is not None:
         roof["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
+        roof["traffic_gbps"] = traffic / (kern_ms / 1e3) / 1e9
     return roof
 
 
@@ -971,6 +972,9 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
     }
     if result["roofline"]["traffic"] is not None:
         result["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
+        # the measured DRAM bytes over the live launch time, beside the algorithmic rate
+        result["roofline"]["traffic_gbps"] = (result["roofline"]["traffic"] /
+                                              (result["roofline"]["kernel_ms"] / 1e3) / 1e9)
     if sweep and E == c["num_envs"]:
         del out, gout
         torch.cuda.empty_cache()
