@@ -699,6 +699,10 @@ def bench_ppo(args, T=32, cpu_seconds=None):
         "full_update": {"minibatch_agents": mb_agents, "minibatch_states": mb_envs,
                         "ms": t_full, "agent_samples_per_s": mb_agents / (t_full / 1e3),
                         "tflops": fl_full / (t_full / 1e3) / 1e12,
+                        # its dense products are FP32 GEMMs: the FP32 matrix peak bounds it
+                        "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": 157.3,
+                                     "achieved": fl_full / (t_full / 1e3) / 1e12,
+                                     "frac": fl_full / (t_full / 1e3) / 1e12 / 157.3},
                         "note": "FP32 training form (forward with tape, exact backward, rocBLAS "
                                 "FP32 GEMMs) of actor and critic plus Adam on every parameter; "
                                 "flops counted as 3x the forward's"},
