@@ -1056,8 +1056,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(environments are independent: a multi-GPU run would shard env ranges, "
-              "see DESIGN.md)", file=sys.stderr)
+              "(environments are independent: a multi-GPU run would shard env ranges)",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.copy_probe:

@@ -3,9 +3,8 @@
  * policy. TEST INFRASTRUCTURE ONLY (see lrauv_oracle.h).
  *
  * The learned estimator is not in the paper: it stands in for the per-target
- * range-only estimator of Sec. III-A. Its readings (features, output
- * parameterisation, loss) are listed in the design doc; this file writes them out
- * plainly in FP64.
+ * range-only estimator of Sec. III-A. Its definitions (features, output
+ * parameterisation, loss) are written out below, plainly, in FP64.
  *
  *   features of a window of W entries (a_k, r_k), all present:
  *     abar = mean a_k, rbar = mean r_k; theta = direction of a_0 - a_{W-1}

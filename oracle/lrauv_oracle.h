@@ -19,7 +19,7 @@
  *   - partial observability limits (450 m detection, 1500 m comms): Sec.
  *     IV-A-2, "Why is UTracking a difficult environment?".
  * Where the paper is silent (RNG assignment, estimator guards, the multi-agent
- * tracking error) the oracle follows the readings listed in the design doc.
+ * tracking error) the oracle follows the readings stated at each function.
  *
  * Parity status per function is stated next to each declaration.
  */

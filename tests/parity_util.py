@@ -1,6 +1,6 @@
 """Comparison of GPU rollouts with the FP64 oracle.
 
-Tolerances ("parity"): states, ranges and rewards must agree to
+Tolerances: states, ranges and rewards must agree to
 1e-5 relative with scale s = area/2 for lengths and pi for headings. The
 range-only estimate amplifies any difference of its inputs by the window's
 geometry, so each estimate is checked against
