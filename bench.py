@@ -738,6 +738,71 @@ def cpu_oracle_gradient(actor, budget_s):
             "sample": f"{n} agents of 10 tokens, {el:.1f} s"}
 
 
+def bench_train_loop(args, T=32, epochs=1, minibatches=16):
+    """End-to-end training on the policy workload's shape (16384 envs x 5 x 5):
+    one PPO iteration is a closed-loop batch of T steps from an episode start
+    (the attention policy driving the environment, exact estimator in the
+    loop), then the learner over it (critic values of the T + 1 states, GAE,
+    the old logits, and `epochs` passes over `minibatches` groups of whole
+    steps: training-form forward and reverse passes of actor and critic, Adam
+    on every parameter). Reported: env-steps/s of training = T x envs over the
+    iteration's time; the paper's own figure (1e10 single-agent timesteps of
+    pre-training in 1.5 days on one H100, Sec. IV-B-2) is context only (another
+    GPU, model and batch). One untimed iteration first."""
+    import numpy as np
+    import torch
+
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.configs import CONFIGS, env_config
+    from paper_2505_08222_amd.env import Env
+
+    c = CONFIGS["policy"]
+    E = args.envs or c["num_envs"]
+    cfg = env_config("policy")
+    na, nt = cfg["n_agents"], cfg["n_targets"]
+    env = Env(cfg, E, seed=c["seed"])
+    actor, critic = policy.init_params(c["seed"]), policy.init_params(c["seed"] + 1)
+    learner = ppo.Learner(actor, critic, na, nt, lr=3e-4)
+    roll = policy.PolicyRollout(env, actor)
+    rec = ("obs", "obs_mask", "actions", "gstate", "reward", "done")
+
+    def iteration(ep):
+        t0 = time.perf_counter()
+        r0 = env.reset(ep, record=("obs", "obs_mask", "gstate"))
+        out, _ = roll.run(T, episode=ep, record=rec, metrics=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        obs = torch.cat([r0["obs"][None], out["obs"][:T - 1]])
+        mask = torch.cat([r0["obs_mask"][None], out["obs_mask"][:T - 1]])
+        gs = torch.cat([r0["gstate"][None], out["gstate"]])
+        hist = learner.update(obs, mask, out["actions"], gs, out["reward"], out["done"],
+                              epochs=epochs, minibatches=minibatches)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, hist
+
+    iteration(0)
+    t_roll, t_learn, hist = iteration(1)
+    total = t_roll + t_learn
+    h = hist.cpu().numpy()
+    log(f"[bench] train loop: rollout {t_roll * 1e3:.1f} ms, learner {t_learn * 1e3:.1f} ms, "
+        f"{T * E / total:.3g} env-steps/s of training")
+    paper = 1e10 / (1.5 * 86400.0)
+    return {
+        "metric": METRIC, "value": T * E / total, "unit": "env-steps/s of PPO training",
+        "n_gpus": 1, "steps": 1, "dtype": "bf16 rollout policy; fp32 learner",
+        "data": "closed-loop experience from random-init networks",
+        "config": {"workload": f"train loop: {E} envs x {na} agents x {nt} targets, batches of {T} "
+                               f"steps from an episode start, {epochs} epoch(s) of {minibatches} "
+                               "minibatches, every parameter of actor and critic updated",
+                   "envs": E, "batch_steps": T, "epochs": epochs, "minibatches": minibatches},
+        "agent_steps_per_s": T * E * na / total,
+        "ms": {"rollout": t_roll * 1e3, "learner": t_learn * 1e3, "total": total * 1e3},
+        "losses_first_last": [h[0].tolist(), h[-1].tolist()],
+        "paper_pretraining_steps_per_s_context": paper,
+    }
+
+
 def cpu_baseline_ppo(critic, actor, budget_s):
     """The oracle's forward half on a bounded sample: 4 envs x 5x5 x 8 steps
     per round (critic and policy forwards in FP64 C, one thread; GAE and the
@@ -1041,7 +1106,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all",
                     choices=["all", "plain", "batched", "ragged", "learned", "policy", "paper",
-                             "paper_pooled", "learned_paper", "ragged_pf", "paper_pf", "ppo"])
+                             "paper_pooled", "learned_paper", "ragged_pf", "paper_pf", "ppo",
+                             "train_loop"])
     ap.add_argument("--envs", type=int, default=None, help="override the number of envs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -1072,6 +1138,9 @@ def main():
     if args.workload == "ppo":
         print(json.dumps(bench_ppo(args, cpu_seconds=cpu_s)), flush=True)
         return
+    if args.workload == "train_loop":
+        print(json.dumps(bench_train_loop(args)), flush=True)
+        return
     if args.workload == "policy":
         print(json.dumps(bench_policy(args, args.steps, args.warmup, cpu_seconds=cpu_s)),
               flush=True)
@@ -1096,6 +1165,7 @@ def main():
     result["policy"] = bench_policy(args, min(args.steps, 3), min(args.warmup, 1), mlp=mlp,
                                     cpu_seconds=sec_cpu)
     result["ppo"] = bench_ppo(args, cpu_seconds=None if sec_cpu is None else 4.0)
+    result["train_loop"] = bench_train_loop(args)
     # the paper's own environment (30 s steps, rudder, follow reward, 450 m
     # detection, pairwise spawn) and the learned estimator on its windows
     result["paper"] = bench_env(args, "paper", args.steps, args.warmup, cpu_seconds=sec_cpu)
