@@ -742,10 +742,10 @@ def bench_train_loop(args, T=32, epochs=1, minibatches=16):
     """End-to-end training on the policy workload's shape (16384 envs x 5 x 5):
     one PPO iteration is a closed-loop batch of T steps from an episode start
     (the attention policy driving the environment, exact estimator in the
-    loop), then the learner over it (critic values of the T + 1 states, GAE,
-    the old logits, and `epochs` passes over `minibatches` groups of whole
-    steps: training-form forward and reverse passes of actor and critic, Adam
-    on every parameter). Reported: env-steps/s of training = T x envs over the
+    loop), then the learner over it (the critic's values of the T + 1 states
+    and the behaviour policy's logits from the inference kernels, GAE, and
+    `epochs` passes over `minibatches` groups of whole steps: training-form
+    forward and reverse passes of actor and critic, Adam on every parameter). Reported: env-steps/s of training = T x envs over the
     iteration's time; the paper's own figure (1e10 single-agent timesteps of
     pre-training in 1.5 days on one H100, Sec. IV-B-2) is context only (another
     GPU, model and batch). One untimed iteration first."""

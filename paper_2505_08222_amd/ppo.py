@@ -272,9 +272,15 @@ class Learner:
 
     def __init__(self, actor, critic, n_agents: int, n_targets: int, n_actions: int = 5,
                  lr: float = 3e-4, clip_eps: float = 0.2, gamma: float = 0.99, lam: float = 0.95,
-                 pos_scale: float = 1000.0, recurrent: bool = False):
+                 pos_scale: float = 1000.0, recurrent: bool = False, behaviour: str = "inference"):
         from .learned import Adam
         self.recurrent = bool(recurrent)
+        # the old policy's logits and the values for GAE: "inference" takes the
+        # inference kernels (BF16; the old logits are then exactly those of the
+        # policy that sampled the closed loop's actions), "training" the FP32
+        # training form (then the first ratio is exactly 1)
+        assert behaviour in ("inference", "training")
+        self.behaviour = behaviour
         self.actor, self.critic = actor, critic
         self.na, self.nt, self.n_actions = n_agents, n_targets, n_actions
         self.opt_a, self.opt_c = Adam(actor, lr=lr), Adam(critic, lr=lr)
@@ -320,6 +326,31 @@ class Learner:
         tp = self._pass(A, n_tok)
         return torch.stack([tp.forward(obs[t], mask[t], self.actor)[0].clone() for t in range(T)])
 
+    def _behaviour(self, obs, mask, gs):
+        """Values [T + 1, E] and old logits [T, A, 8] from the inference
+        kernels: the critic over every state in one call (in order through
+        its carried state when recurrent), the actor step by step."""
+        from . import policy
+        S, E = gs.shape[0], gs.shape[1]
+        T = obs.shape[0]
+        n_tok = self.na + self.nt
+        A = obs.shape[1] // n_tok
+        if self.recurrent:
+            values = critic_forward_rec(gs, self.na, self.nt, self.critic,
+                                        pos_scale=self.pos_scale)[0]
+            h = None
+            logits = []
+            for t in range(T):
+                lg, _, h = policy.forward_rec(obs[t], mask[t], h, self.actor, n_tok, self.na,
+                                              self.n_actions)
+                logits.append(lg)
+            return values, torch.stack(logits)
+        values = critic_forward(gs.reshape(S * E, self.na + self.nt, 6), self.na, self.nt,
+                                self.critic, pos_scale=self.pos_scale).reshape(S, E)
+        logits = torch.stack([policy.forward(obs[t], mask[t], self.actor, n_tok, self.na,
+                                             self.n_actions)[0] for t in range(T)])
+        return values, logits.reshape(T, A, 8)
+
     def update(self, obs, mask, actions, gstate, rewards, dones, epochs: int = 2,
                minibatches: int = 2):
         """obs / mask [T, A * n_tok, ...]: the observation each step's action
@@ -330,9 +361,12 @@ class Learner:
         E = A // self.na
         n_tok = self.na + self.nt
         M = self.na + self.nt
-        values = self.values(gstate.reshape(T + 1, E, M, 6))
+        if self.behaviour == "inference":
+            values, logits_old = self._behaviour(obs, mask, gstate.reshape(T + 1, E, M, 6))
+        else:
+            values = self.values(gstate.reshape(T + 1, E, M, 6))
+            logits_old = self.logits(obs, mask)
         adv, ret = gae(rewards, dones, values, self.gamma, self.lam)
-        logits_old = self.logits(obs, mask)
         if self.recurrent:
             return self._update_rec(obs, mask, actions, gstate.reshape(T + 1, E, M, 6), adv, ret,
                                     logits_old, epochs, minibatches)

@@ -192,7 +192,7 @@ def test_learner_iteration_on_closed_loop_experience():
     mask = torch.cat([r0["obs_mask"][None], out["obs_mask"][:T - 1]])
     gs = torch.cat([r0["gstate"][None], out["gstate"]])
     a0, c0 = actor.clone(), critic.clone()
-    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4)
+    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4, behaviour="training")
     before = lr.logits(obs, mask)
     # the advantages the update itself uses (the critic before the update)
     vals = lr.values(gs.reshape(T + 1, E, na + nt, 6))
@@ -285,7 +285,7 @@ def test_recurrent_learner_on_closed_loop_experience():
     mask = torch.cat([r0["obs_mask"][None], out["obs_mask"][:T - 1]])
     gs = torch.cat([r0["gstate"][None], out["gstate"]])
     a0, c0 = actor.clone(), critic.clone()
-    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4, recurrent=True)
+    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4, recurrent=True, behaviour="training")
     before = lr.logits(obs, mask)
     # the advantages the update itself uses (the critic before the update)
     vals = lr.values(gs.reshape(T + 1, E, na + nt, 6))
@@ -329,3 +329,47 @@ def test_accumulate_on_the_split_k_path(orc):
                                       dn.astype(np.float64))
     _check_grad(g1.cpu().numpy(), gw)
     assert np.abs(dh.cpu().numpy() - dhw).max() <= 2e-4 * np.abs(dhw).max()
+
+
+
+@pytest.mark.parametrize("recurrent", [False, True])
+def test_learner_behaviour_from_the_inference_kernels(recurrent):
+    # the old logits are those of the policy that sampled the loop's actions
+    # (the inference kernel on the loop's own observations, the recurrent
+    # chain from zeros), the values the inference critic's, and an update
+    # from them changes both networks with finite losses
+    from paper_2505_08222_amd import policy, ppo
+    from paper_2505_08222_amd.env import Env
+    na, nt, E, T = 2, 2, 32, 8
+    cfg = env_config("policy", episode_len=T, n_agents=na, n_targets=nt)
+    env = Env(cfg, E, seed=13)
+    actor, critic = policy.init_params(44), policy.init_params(45)
+    r0 = env.reset(0, record=("obs", "obs_mask", "gstate"))
+    out, _ = policy.PolicyRollout(env, actor, recurrent=recurrent).run(
+        T, record=("obs", "obs_mask", "actions", "gstate", "reward", "done"))
+    obs = torch.cat([r0["obs"][None], out["obs"][:T - 1]])
+    mask = torch.cat([r0["obs_mask"][None], out["obs_mask"][:T - 1]])
+    gs = torch.cat([r0["gstate"][None], out["gstate"]])
+    lr = ppo.Learner(actor, critic, na, nt, lr=1e-4, recurrent=recurrent)
+    vals, lo = lr._behaviour(obs, mask, gs.reshape(T + 1, E, na + nt, 6))
+    A, n_tok = E * na, na + nt
+    if recurrent:
+        h = None
+        for t in range(T):
+            lg, _, h = policy.forward_rec(obs[t], mask[t], h, actor, n_tok, na)
+            assert torch.equal(lg, lo[t])
+        v_want = ppo.critic_forward_rec(gs, na, nt, critic)[0]
+    else:
+        for t in range(T):
+            assert torch.equal(policy.forward(obs[t], mask[t], actor, n_tok, na)[0], lo[t])
+        v_want = ppo.critic_forward(gs, na, nt, critic).reshape(T + 1, E)
+    assert torch.equal(vals, v_want)
+    # the training form's values and logits agree with them to the BF16 bound
+    vt = lr.values(gs.reshape(T + 1, E, na + nt, 6))
+    assert float((vt - vals).abs().max()) <= 3e-2 * max(1.0, float(vt.abs().max()))
+    a0, c0 = actor.clone(), critic.clone()
+    hist = lr.update(obs, mask, out["actions"], gs, out["reward"], out["done"], epochs=1,
+                     minibatches=2)
+    assert torch.isfinite(hist).all()
+    assert not torch.equal(actor, a0) and not torch.equal(critic, c0)
+    env.close()
