@@ -373,3 +373,30 @@ def test_learner_behaviour_from_the_inference_kernels(recurrent):
     assert torch.isfinite(hist).all()
     assert not torch.equal(actor, a0) and not torch.equal(critic, c0)
     env.close()
+
+
+def test_large_batch_gradient_is_reproducible_and_splits(orc):
+    # 16384 agents x 10 tokens (the policy workload's minibatch scale): two
+    # reverse passes give identical bits, and the gradient equals the sum of
+    # the two halves' gradients (other row counts, so other GEMM shapes and
+    # split-K chunkings) to FP32 rounding
+    from paper_2505_08222_amd import ppo
+    A, H = 16384, 8192
+    x, m = policy_tokens(A, 5, 5, seed=23)
+    th = policy_params(orc.policy_num_params(), seed=29)
+    rng = np.random.default_rng(31)
+    dl = rng.normal(size=(A, 8)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    params = dev(th)
+    xs, ms, dls = dev(x.reshape(A, 10, 6)), dev(m.reshape(A, 10)), dev(dl)
+    tp = ppo.TrainPass(A, 10)
+    tp.forward(xs.reshape(-1, 6), ms.reshape(-1), params)
+    g1, _ = tp.backward(params, dls, 8)
+    g2, _ = tp.backward(params, dls, 8)
+    assert torch.equal(g1, g2)
+    th_ = ppo.TrainPass(H, 10)
+    th_.forward(xs[:H].reshape(-1, 6), ms[:H].reshape(-1), params)
+    gh, _ = th_.backward(params, dls[:H], 8)
+    th_.forward(xs[H:].reshape(-1, 6), ms[H:].reshape(-1), params)
+    gh, _ = th_.backward(params, dls[H:], 8, grad=gh, accumulate=True)
+    _check_grad(gh.cpu().numpy(), g1.cpu().numpy().astype(np.float64), tol=1e-5)
