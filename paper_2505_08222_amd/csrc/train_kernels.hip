@@ -223,8 +223,56 @@ attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P
 // rows [b * per, (b + 1) * per) in FP64 (thread (group, column) with four
 // running sums over its rows, groups combined in order), then one wavefront
 // per column adds the blocks' partials (lane j: partials j, j + 64, ...;
-// then a fixed butterfly).
-constexpr int kCsBlocks = 256;
+// then a fixed butterfly). With N a multiple of 4 and Y 16-byte aligned the
+// first pass reads float4s instead (thread (group, column quad), one running
+// sum per column, four row loads in flight), which keeps enough bytes in
+// flight to stream Y at close to HBM rate.
+constexpr int kCsBlocks = 1024;
+
+__global__ void __launch_bounds__(256)
+colsum_partial4_kernel(const float4 *__restrict__ Y, int64_t R, int N, int64_t per,
+                       double *__restrict__ part) {
+  __shared__ double red[1024];
+  const int nq = N >> 2;
+  const int groups = 256 / nq;
+  const int g = threadIdx.x / nq, q = threadIdx.x - g * nq;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  if (g < groups) {
+    int64_t r = r0 + g;
+    for (; r + 3 * groups < r1; r += 4 * groups) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = Y[(r + u * groups) * nq + q];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        s0 += (double)v[u].x;
+        s1 += (double)v[u].y;
+        s2 += (double)v[u].z;
+        s3 += (double)v[u].w;
+      }
+    }
+    for (; r < r1; r += groups) {
+      const float4 v = Y[r * nq + q];
+      s0 += (double)v.x;
+      s1 += (double)v.y;
+      s2 += (double)v.z;
+      s3 += (double)v.w;
+    }
+    double *o = red + g * N + 4 * q;  // groups * N <= 1024
+    o[0] = s0;
+    o[1] = s1;
+    o[2] = s2;
+    o[3] = s3;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+    for (int k = 0; k < groups; ++k) s += red[k * N + threadIdx.x];
+    part[(int64_t)blockIdx.x * N + threadIdx.x] = s;
+  }
+}
 __global__ void __launch_bounds__(256)
 colsum_partial_kernel(const float *__restrict__ Y, int64_t R, int N, int64_t per,
                       double *__restrict__ part) {
@@ -447,8 +495,12 @@ int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float 
   if (N < 1 || N > 256) return -1;
   hipStream_t st = (hipStream_t)stream;
   const int64_t per = R > 0 ? (R + kCsBlocks - 1) / kCsBlocks : 1;
-  hipLaunchKernelGGL(colsum_partial_kernel, dim3(kCsBlocks), dim3(256), 0, st, Y, R, N, per,
-                     scratch);
+  if (N % 4 == 0 && ((uintptr_t)Y & 15) == 0)
+    hipLaunchKernelGGL(colsum_partial4_kernel, dim3(kCsBlocks), dim3(256), 0, st,
+                       reinterpret_cast<const float4 *>(Y), R, N, per, scratch);
+  else
+    hipLaunchKernelGGL(colsum_partial_kernel, dim3(kCsBlocks), dim3(256), 0, st, Y, R, N, per,
+                       scratch);
   if (check()) return -1;
   hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, scratch,
                      kCsBlocks, N, acc, out);
