@@ -105,118 +105,183 @@ gelu_back_kernel(float *__restrict__ dz, const float *__restrict__ z, int64_t n)
   if (i < n) dz[i] *= gelu_tanh_grad(z[i]);
 }
 
-// Thread (agent, head, query t): scores q.k / 4 over the agent's unmasked
-// keys, softmax (kept), and the head's output o = P V.
-__global__ void __launch_bounds__(kTrThreads)
-attention_kernel(const float *__restrict__ qkv, const uint8_t *__restrict__ mrow, int64_t A,
-                 int nt, float *__restrict__ P, float *__restrict__ o) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A * kPolHeads * nt) return;
-  const int t = (int)(i % nt);
-  const int64_t ah = i / nt;
-  const int hd = (int)(ah % kPolHeads);
-  const int64_t a = ah / kPolHeads;
+// Attention of one agent per wavefront (a block of 64 threads): the agent's
+// rows are staged in LDS with coalesced float4 loads, then lane (head h,
+// query t) = (lane / 16, lane % 16) does that query's work; lanes t >= nt
+// only help with the staging. Rows of Q/K/V hold [Q | K | V], 64 each, head h
+// in columns 16h..16h+15.
+constexpr int kAtThreads = 64;
+
+__device__ __forceinline__ void lds_row16(const float *src, float (&v)[kPolDh]) {
+#pragma unroll
+  for (int c4 = 0; c4 < kPolDh / 4; ++c4) {
+    const float4 x = reinterpret_cast<const float4 *>(src)[c4];
+    v[4 * c4] = x.x;
+    v[4 * c4 + 1] = x.y;
+    v[4 * c4 + 2] = x.z;
+    v[4 * c4 + 3] = x.w;
+  }
+}
+
+__device__ __forceinline__ void store_row16(float *dst, const float (&v)[kPolDh]) {
+#pragma unroll
+  for (int c4 = 0; c4 < kPolDh / 4; ++c4)
+    reinterpret_cast<float4 *>(dst)[c4] =
+        make_float4(v[4 * c4], v[4 * c4 + 1], v[4 * c4 + 2], v[4 * c4 + 3]);
+}
+
+// Forward: scores q.k / 4 over the agent's unmasked keys, softmax (kept in
+// P [agent][head][query][key]), and the head's output o = P V.
+__global__ void __launch_bounds__(kAtThreads)
+attention_kernel(const float *__restrict__ qkv, const uint8_t *__restrict__ mrow, int nt,
+                 float *__restrict__ P, float *__restrict__ o) {
+  extern __shared__ float4 at_lds[];  // [nt][48]: the agent's Q/K/V rows
+  const int64_t a = blockIdx.x;
   const int64_t r0 = a * nt;
-  const float *q = qkv + (r0 + t) * 3 * kPolD + hd * kPolDh;
+  const int lane = threadIdx.x;
+  const float4 *src = reinterpret_cast<const float4 *>(qkv + r0 * 3 * kPolD);
+  for (int e = lane; e < nt * 3 * kPolD / 4; e += kAtThreads) at_lds[e] = src[e];
+  __syncthreads();
+  const int hd = lane >> 4, t = lane & 15;
+  if (t >= nt) return;  // no barrier follows
+  const float *sq = reinterpret_cast<const float *>(at_lds);
+  float q[kPolDh];
+  lds_row16(sq + t * 3 * kPolD + hd * kPolDh, q);
   float s[kPolMaxTok];
   float mx = -INFINITY;
-  for (int u = 0; u < nt; ++u) {
-    s[u] = -INFINITY;
-    if (!mrow[r0 + u]) continue;
-    const float *k = qkv + (r0 + u) * 3 * kPolD + kPolD + hd * kPolDh;
-    float acc = 0.0f;
 #pragma unroll
-    for (int c = 0; c < kPolDh; ++c) acc = fmaf(q[c], k[c], acc);
-    s[u] = acc * 0.25f;
-    mx = fmaxf(mx, s[u]);
+  for (int u = 0; u < kPolMaxTok; ++u) {
+    s[u] = -INFINITY;
+    if (u < nt && mrow[r0 + u]) {
+      float k[kPolDh];
+      lds_row16(sq + u * 3 * kPolD + kPolD + hd * kPolDh, k);
+      float acc = 0.0f;
+#pragma unroll
+      for (int c = 0; c < kPolDh; ++c) acc = fmaf(q[c], k[c], acc);
+      s[u] = acc * 0.25f;
+      mx = fmaxf(mx, s[u]);
+    }
   }
   float z = 0.0f;
-  for (int u = 0; u < nt; ++u) {
-    s[u] = mrow[r0 + u] ? expf(s[u] - mx) : 0.0f;
-    z += s[u];
+#pragma unroll
+  for (int u = 0; u < kPolMaxTok; ++u) {
+    if (u < nt) {
+      s[u] = mrow[r0 + u] ? expf(s[u] - mx) : 0.0f;
+      z += s[u];
+    }
   }
   const float iz = 1.0f / z;
-  float *pr = P + i * nt;
+  float *pr = P + ((a * kPolHeads + hd) * nt + t) * nt;
   float acc[kPolDh];
 #pragma unroll
   for (int c = 0; c < kPolDh; ++c) acc[c] = 0.0f;
-  for (int u = 0; u < nt; ++u) {
-    const float p = s[u] * iz;
-    pr[u] = p;
-    const float *v = qkv + (r0 + u) * 3 * kPolD + 2 * kPolD + hd * kPolDh;
 #pragma unroll
-    for (int c = 0; c < kPolDh; ++c) acc[c] = fmaf(p, v[c], acc[c]);
+  for (int u = 0; u < kPolMaxTok; ++u) {
+    if (u < nt) {
+      const float p = s[u] * iz;
+      pr[u] = p;
+      float v[kPolDh];
+      lds_row16(sq + u * 3 * kPolD + 2 * kPolD + hd * kPolDh, v);
+#pragma unroll
+      for (int c = 0; c < kPolDh; ++c) acc[c] = fmaf(p, v[c], acc[c]);
+    }
   }
-  float *out = o + (r0 + t) * kPolD + hd * kPolDh;
-#pragma unroll
-  for (int c = 0; c < kPolDh; ++c) out[c] = acc[c];
+  store_row16(o + (r0 + t) * kPolD + hd * kPolDh, acc);
 }
 
-// One block per agent: the reverse of attention_kernel for all its heads,
-// queries and keys, staged through LDS (the agent's Q/K/V rows, softmax
-// probabilities and output gradients read once, coalesced):
-// dP = dO V^T, dS = P (dP - sum_u P dP) / 4, dQ = dS K, dK = dS^T Q,
-// dV = P^T dO, written to dqkv row by row.
-constexpr int kAbThreads = 256;
-__global__ void __launch_bounds__(kAbThreads)
+// Reverse pass of attention_kernel, same layout (LDS: the agent's Q/K/V
+// rows, output gradients dO, probabilities P and score gradients dS).
+// Lane (h, t): dP[u] = dO[t] . V[u], dS[t][u] = P (dP - sum_u P dP) / 4,
+// dQ[t] = dS[t] K; after the block's barrier, as lane (h, x) with x = t:
+// dK[x] = sum_t dS[t][x] Q[t], dV[x] = sum_t P[t][x] dO[t].
+__global__ void __launch_bounds__(kAtThreads)
 attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P,
-                      const uint8_t *__restrict__ mrow, const float *__restrict__ dout, int64_t A,
-                      int nt, float *__restrict__ dqkv) {
-  __shared__ float sq[kPolMaxTok][3 * kPolD];
-  __shared__ float so[kPolMaxTok][kPolD];
-  __shared__ float sp[kPolHeads][kPolMaxTok][kPolMaxTok];
-  __shared__ float sd[kPolHeads][kPolMaxTok][kPolMaxTok];
-  __shared__ float ssum[kPolHeads][kPolMaxTok];
-  const int tid = threadIdx.x;
-  for (int64_t a = blockIdx.x; a < A; a += gridDim.x) {
-    const int64_t r0 = a * nt;
-    for (int e = tid; e < nt * 3 * kPolD; e += kAbThreads)
-      sq[e / (3 * kPolD)][e % (3 * kPolD)] = qkv[r0 * 3 * kPolD + e];
-    for (int e = tid; e < nt * kPolD; e += kAbThreads) so[e / kPolD][e % kPolD] = dout[r0 * kPolD + e];
-    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
-      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
-      sp[h][t][u] = P[a * kPolHeads * nt * nt + e];
-    }
-    __syncthreads();
-    // dP[h][t][u] = dO[t] . V[u] over the head's 16 dimensions
-    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
-      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
-      float acc = 0.0f;
-#pragma unroll
-      for (int c = 0; c < kPolDh; ++c)
-        acc = fmaf(so[t][h * kPolDh + c], sq[u][2 * kPolD + h * kPolDh + c], acc);
-      sd[h][t][u] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kPolHeads * nt; e += kAbThreads) {
-      const int h = e / nt, t = e % nt;
-      float acc = 0.0f;
-      for (int u = 0; u < nt; ++u) acc = fmaf(sp[h][t][u], sd[h][t][u], acc);
-      ssum[h][t] = acc;
-    }
-    __syncthreads();
-    for (int e = tid; e < kPolHeads * nt * nt; e += kAbThreads) {
-      const int h = e / (nt * nt), t = (e / nt) % nt, u = e % nt;
-      // a masked key has probability 0 and takes no gradient
-      sd[h][t][u] = mrow[r0 + u] ? sp[h][t][u] * (sd[h][t][u] - ssum[h][t]) * 0.25f : 0.0f;
-    }
-    __syncthreads();
-    // outputs: row x, column j of dQ / dK / dV (head h = column / 16)
-    for (int e = tid; e < nt * 3 * kPolD; e += kAbThreads) {
-      const int x = e / (3 * kPolD), j = e % (3 * kPolD);
-      const int part = j / kPolD, col = j % kPolD, h = col / kPolDh;
-      float acc = 0.0f;
-      if (part == 0) {  // dQ[x] = sum_u dS[x][u] K[u]
-        for (int u = 0; u < nt; ++u) acc = fmaf(sd[h][x][u], sq[u][kPolD + col], acc);
-      } else if (part == 1) {  // dK[x] = sum_t dS[t][x] Q[t]
-        for (int t = 0; t < nt; ++t) acc = fmaf(sd[h][t][x], sq[t][col], acc);
-      } else {  // dV[x] = sum_t P[t][x] dO[t]
-        for (int t = 0; t < nt; ++t) acc = fmaf(sp[h][t][x], so[t][col], acc);
-      }
-      dqkv[r0 * 3 * kPolD + e] = acc;
-    }
-    __syncthreads();  // before the next agent's rows overwrite the stage
+                      const uint8_t *__restrict__ mrow, const float *__restrict__ dout, int nt,
+                      float *__restrict__ dqkv) {
+  extern __shared__ float4 ab_lds[];  // [nt][48] Q/K/V | [nt][16] dO | [4 nt nt / 4] P | dS
+  const int64_t a = blockIdx.x;
+  const int64_t r0 = a * nt;
+  const int lane = threadIdx.x;
+  const int nqkv = nt * 3 * kPolD / 4, ndo = nt * kPolD / 4, np = kPolHeads * nt * nt / 4;
+  {
+    const float4 *s1 = reinterpret_cast<const float4 *>(qkv + r0 * 3 * kPolD);
+    const float4 *s2 = reinterpret_cast<const float4 *>(dout + r0 * kPolD);
+    const float4 *s3 = reinterpret_cast<const float4 *>(P + a * kPolHeads * nt * nt);
+    for (int e = lane; e < nqkv; e += kAtThreads) ab_lds[e] = s1[e];
+    for (int e = lane; e < ndo; e += kAtThreads) ab_lds[nqkv + e] = s2[e];
+    for (int e = lane; e < np; e += kAtThreads) ab_lds[nqkv + ndo + e] = s3[e];
   }
+  __syncthreads();
+  float *const base = reinterpret_cast<float *>(ab_lds);
+  const float *sq = base, *so = base + 4 * nqkv, *sp = so + 4 * ndo;
+  float *sd = base + 4 * (nqkv + ndo + np);
+  const int hd = lane >> 4, t = lane & 15;
+  const bool live = t < nt;
+  float dq[kPolDh];
+#pragma unroll
+  for (int c = 0; c < kPolDh; ++c) dq[c] = 0.0f;
+  if (live) {
+    float dot[kPolDh];
+    lds_row16(so + t * kPolD + hd * kPolDh, dot);
+    const float *prow = sp + (hd * nt + t) * nt;
+    float dp[kPolMaxTok];
+    float ssum = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kPolMaxTok; ++u) {
+      dp[u] = 0.0f;
+      if (u < nt) {
+        float v[kPolDh];
+        lds_row16(sq + u * 3 * kPolD + 2 * kPolD + hd * kPolDh, v);
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < kPolDh; ++c) acc = fmaf(dot[c], v[c], acc);
+        dp[u] = acc;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kPolMaxTok; ++u)
+      if (u < nt) ssum = fmaf(prow[u], dp[u], ssum);
+    float *drow = sd + (hd * nt + t) * nt;
+#pragma unroll
+    for (int u = 0; u < kPolMaxTok; ++u) {
+      if (u < nt) {
+        // a masked key has probability 0 and takes no gradient
+        const float ds = mrow[r0 + u] ? prow[u] * (dp[u] - ssum) * 0.25f : 0.0f;
+        drow[u] = ds;
+        float k[kPolDh];
+        lds_row16(sq + u * 3 * kPolD + kPolD + hd * kPolDh, k);
+#pragma unroll
+        for (int c = 0; c < kPolDh; ++c) dq[c] = fmaf(ds, k[c], dq[c]);
+      }
+    }
+  }
+  __syncthreads();  // every lane's dS row is in LDS
+  if (!live) return;
+  const int x = t;
+  float dk[kPolDh], dv[kPolDh];
+#pragma unroll
+  for (int c = 0; c < kPolDh; ++c) {
+    dk[c] = 0.0f;
+    dv[c] = 0.0f;
+  }
+#pragma unroll
+  for (int tq = 0; tq < kPolMaxTok; ++tq) {
+    if (tq < nt) {
+      const float ds = sd[(hd * nt + tq) * nt + x], p = sp[(hd * nt + tq) * nt + x];
+      float qv[kPolDh], ov[kPolDh];
+      lds_row16(sq + tq * 3 * kPolD + hd * kPolDh, qv);
+      lds_row16(so + tq * kPolD + hd * kPolDh, ov);
+#pragma unroll
+      for (int c = 0; c < kPolDh; ++c) {
+        dk[c] = fmaf(ds, qv[c], dk[c]);
+        dv[c] = fmaf(p, ov[c], dv[c]);
+      }
+    }
+  }
+  float *row = dqkv + (r0 + x) * 3 * kPolD + hd * kPolDh;
+  store_row16(row, dq);
+  store_row16(row + kPolD, dk);
+  store_row16(row + 2 * kPolD, dv);
 }
 
 // Column sums of Y [R][N] (N <= 256) in two fixed-order passes: block b adds
@@ -471,20 +536,27 @@ int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream) {
   return check();
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float *P, float *o,
                  void *stream) {
   if (A == 0) return 0;
-  hipLaunchKernelGGL(attention_kernel, grid_for(A * kPolHeads * nt), dim3(kTrThreads), 0,
-                     (hipStream_t)stream, qkv, mrow, A, nt, P, o);
+  if (nt < 1 || nt > kPolMaxTok || A > INT32_MAX || !aligned16(qkv) || !aligned16(o)) return -1;
+  const size_t lds = (size_t)nt * 3 * kPolD * 4;
+  hipLaunchKernelGGL(attention_kernel, dim3((unsigned)A), dim3(kAtThreads), lds,
+                     (hipStream_t)stream, qkv, mrow, nt, P, o);
   return check();
 }
 
 int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, const float *dout,
                       int64_t A, int nt, float *dqkv, void *stream) {
   if (A == 0) return 0;
-  const int64_t blocks = A < 8192 ? A : 8192;
-  hipLaunchKernelGGL(attention_back_kernel, dim3((unsigned)blocks), dim3(kAbThreads), 0,
-                     (hipStream_t)stream, qkv, P, mrow, dout, A, nt, dqkv);
+  if (nt < 1 || nt > kPolMaxTok || A > INT32_MAX || !aligned16(qkv) || !aligned16(P) ||
+      !aligned16(dout) || !aligned16(dqkv))
+    return -1;
+  const size_t lds = ((size_t)nt * 3 * kPolD + (size_t)nt * kPolD + 2 * kPolHeads * nt * nt) * 4;
+  hipLaunchKernelGGL(attention_back_kernel, dim3((unsigned)A), dim3(kAtThreads), lds,
+                     (hipStream_t)stream, qkv, P, mrow, dout, nt, dqkv);
   return check();
 }
 
