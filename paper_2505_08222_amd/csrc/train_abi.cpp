@@ -95,11 +95,12 @@ rocblas_handle blas_for_current_device() {
 }
 
 // hipBLASLt, per device: a handle and the plans (descriptors and algorithm)
-// of the column-major products D [m][n] = A [m][k] B [k][n] (+ D) seen so far,
-// made on first use. Same threading rule as the rocBLAS handle.
+// of the column-major products D [m][n] = op(A) B [k][n] (+ C) (+ bias [m]
+// broadcast over columns) seen so far, made on first use; op(A) = A [m][k],
+// or A^T for A [k][m] when trans. Same threading rule as the rocBLAS handle.
 struct LtPlan {
   int64_t m, n, k;
-  bool add;
+  bool add, trans, bias;
   bool ok;  // the heuristic offered an algorithm that needs no workspace
   hipblasLtMatmulDesc_t desc = nullptr;
   hipblasLtMatrixLayout_t la = nullptr, lb = nullptr, lc = nullptr;
@@ -118,9 +119,10 @@ void lt_drop(LtPlan &p) {
   if (p.desc) hipblasLtMatmulDescDestroy(p.desc);
 }
 
-// The plan for (m, n, k, add) on the current device; NULL if hipBLASLt is
-// unavailable or offers no algorithm without workspace for it.
-const LtPlan *lt_plan(int64_t m, int64_t n, int64_t k, bool add, hipblasLtHandle_t *handle) {
+// The plan for (m, n, k, add, trans, bias) on the current device; NULL if
+// hipBLASLt is unavailable or offers no algorithm without workspace for it.
+const LtPlan *lt_plan(int64_t m, int64_t n, int64_t k, bool add, bool trans, bool bias,
+                      hipblasLtHandle_t *handle) {
   constexpr int kMaxPlans = 64;
   static LtDevice devs[64];
   static std::mutex made;
@@ -134,22 +136,42 @@ const LtPlan *lt_plan(int64_t m, int64_t n, int64_t k, bool add, hipblasLtHandle
   }
   *handle = d.h;
   for (const LtPlan &p : d.plans)
-    if (p.m == m && p.n == n && p.k == k && p.add == add) return p.ok ? &p : nullptr;
+    if (p.m == m && p.n == n && p.k == k && p.add == add && p.trans == trans && p.bias == bias)
+      return p.ok ? &p : nullptr;
   if ((int)d.plans.size() >= kMaxPlans) {  // many distinct batch sizes: start over
     for (LtPlan &p : d.plans) lt_drop(p);
     d.plans.clear();
   }
   d.plans.reserve(kMaxPlans);  // plans never move while in use
-  LtPlan p{m, n, k, add, false};
+  LtPlan p{m, n, k, add, trans, bias, false};
   if (hipblasLtMatmulDescCreate(&p.desc, HIPBLAS_COMPUTE_32F, HIP_R_32F) != HIPBLAS_STATUS_SUCCESS)
     p.desc = nullptr;
-  if (hipblasLtMatrixLayoutCreate(&p.la, HIP_R_32F, m, k, m) != HIPBLAS_STATUS_SUCCESS)
+  if (hipblasLtMatrixLayoutCreate(&p.la, HIP_R_32F, trans ? k : m, trans ? m : k, trans ? k : m) !=
+      HIPBLAS_STATUS_SUCCESS)
     p.la = nullptr;
   if (hipblasLtMatrixLayoutCreate(&p.lb, HIP_R_32F, k, n, k) != HIPBLAS_STATUS_SUCCESS)
     p.lb = nullptr;
   if (hipblasLtMatrixLayoutCreate(&p.lc, HIP_R_32F, m, n, m) != HIPBLAS_STATUS_SUCCESS)
     p.lc = nullptr;
   if (!p.desc || !p.la || !p.lb || !p.lc) {  // out of host memory: rocBLAS serves this call
+    lt_drop(p);
+    return nullptr;
+  }
+  bool set = true;
+  if (trans) {
+    const int32_t op = HIPBLAS_OP_T;
+    set = hipblasLtMatmulDescSetAttribute(p.desc, HIPBLASLT_MATMUL_DESC_TRANSA, &op, sizeof(op)) ==
+          HIPBLAS_STATUS_SUCCESS;
+  }
+  if (bias && set) {
+    const uint32_t epi = HIPBLASLT_EPILOGUE_BIAS;
+    const int32_t bt = HIP_R_32F;
+    set = hipblasLtMatmulDescSetAttribute(p.desc, HIPBLASLT_MATMUL_DESC_EPILOGUE, &epi,
+                                          sizeof(epi)) == HIPBLAS_STATUS_SUCCESS &&
+          hipblasLtMatmulDescSetAttribute(p.desc, HIPBLASLT_MATMUL_DESC_BIAS_DATA_TYPE, &bt,
+                                          sizeof(bt)) == HIPBLAS_STATUS_SUCCESS;
+  }
+  if (!set) {
     lt_drop(p);
     return nullptr;
   }
@@ -185,13 +207,33 @@ struct Ctx {
     ok = ok && rocblas_sgemm(h, rocblas_operation_transpose, rocblas_operation_none, N, (int)R, K,
                              &one, W, K, X, K, &beta, Y, N) == rocblas_status_success;
   }
+  // Y [R][N] = X [R][K] W^T + b (+ res [R][N], may be NULL): in hipBLASLt with
+  // its bias epilogue (one pass over Y), else the bias rows then rocBLAS
+  void linear(const float *X, const float *W, const float *b, const float *res, float *Y,
+              int64_t R, int N, int K) {
+    const float one = 1.0f, beta = res ? 1.0f : 0.0f;
+    if (!ok) return;
+    hipblasLtHandle_t lh = nullptr;
+    const LtPlan *p = lt_plan(N, R, K, res != nullptr, true, true, &lh);
+    if (p) {
+      const void *bp = b;
+      ok = hipblasLtMatmulDescSetAttribute(p->desc, HIPBLASLT_MATMUL_DESC_BIAS_POINTER, &bp,
+                                           sizeof(bp)) == HIPBLAS_STATUS_SUCCESS &&
+           hipblasLtMatmul(lh, p->desc, &one, W, p->la, X, p->lb, &beta, res ? res : Y, p->lc, Y,
+                           p->lc, &p->algo, nullptr, 0, (hipStream_t)stream) ==
+               HIPBLAS_STATUS_SUCCESS;
+      return;
+    }
+    k(mil::tr_bias_rows(res, b, R, N, Y, stream));
+    xwt(X, W, Y, R, N, K, 1.0f);
+  }
   // dX [R][K] = dY [R][N] W [N][K] (+ dX when beta = 1); 64-wide outputs in
   // hipBLASLt (2.5-3x faster than rocBLAS on these shapes), others in rocBLAS
   void xw(const float *dY, const float *W, float *dX, int64_t R, int N, int K, float beta) {
     const float one = 1.0f;
     if (!ok) return;
     hipblasLtHandle_t lh = nullptr;
-    const LtPlan *p = K == D ? lt_plan(K, R, N, beta != 0.0f, &lh) : nullptr;
+    const LtPlan *p = K == D ? lt_plan(K, R, N, beta != 0.0f, false, false, &lh) : nullptr;
     if (p) {
       ok = hipblasLtMatmul(lh, p->desc, &one, W, p->la, dY, p->lb, &beta, dX, p->lc, dX, p->lc,
                            &p->algo, nullptr, 0, (hipStream_t)stream) == HIPBLAS_STATUS_SUCCESS;
@@ -257,18 +299,16 @@ int train_forward(int64_t A, int nt, int rec, const float *obs, const uint8_t *m
     const float *lp = prm + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
     c.k(mil::tr_layernorm(fp(w.h[l]), lp + mil::kPolLn1G, lp + mil::kPolLn1B, fp(w.a1[l]), R,
                           stream));
-    c.k(mil::tr_bias_rows(nullptr, lp + mil::kPolBqkv, R, 3 * D, fp(w.qkv[l]), stream));
-    c.xwt(fp(w.a1[l]), lp + mil::kPolWqkv, fp(w.qkv[l]), R, 3 * D, D, 1.0f);
+    c.linear(fp(w.a1[l]), lp + mil::kPolWqkv, lp + mil::kPolBqkv, nullptr, fp(w.qkv[l]), R, 3 * D,
+             D);
     c.k(mil::tr_attention(fp(w.qkv[l]), mrow, A, nt, fp(w.P[l]), fp(w.o[l]), stream));
-    c.k(mil::tr_bias_rows(fp(w.h[l]), lp + mil::kPolBo, R, D, fp(w.hmid[l]), stream));
-    c.xwt(fp(w.o[l]), lp + mil::kPolWo, fp(w.hmid[l]), R, D, D, 1.0f);
+    c.linear(fp(w.o[l]), lp + mil::kPolWo, lp + mil::kPolBo, fp(w.h[l]), fp(w.hmid[l]), R, D, D);
     c.k(mil::tr_layernorm(fp(w.hmid[l]), lp + mil::kPolLn2G, lp + mil::kPolLn2B, fp(w.a2[l]), R,
                           stream));
-    c.k(mil::tr_bias_rows(nullptr, lp + mil::kPolB1, R, F, fp(w.z[l]), stream));
-    c.xwt(fp(w.a2[l]), lp + mil::kPolW1, fp(w.z[l]), R, F, D, 1.0f);
+    c.linear(fp(w.a2[l]), lp + mil::kPolW1, lp + mil::kPolB1, nullptr, fp(w.z[l]), R, F, D);
     c.k(mil::tr_gelu(fp(w.z[l]), fp(w.f[l]), R * F, stream));
-    c.k(mil::tr_bias_rows(fp(w.hmid[l]), lp + mil::kPolB2, R, D, fp(w.h[l + 1]), stream));
-    c.xwt(fp(w.f[l]), lp + mil::kPolW2, fp(w.h[l + 1]), R, D, F, 1.0f);
+    c.linear(fp(w.f[l]), lp + mil::kPolW2, lp + mil::kPolB2, fp(w.hmid[l]), fp(w.h[l + 1]), R, D,
+             F);
   }
   c.k(mil::tr_head(fp(w.h[L]), A, nt, prm, logits, fp(w.feat), stream));
   if (feat_out && c.ok)
