@@ -2,10 +2,12 @@
 // include/mi_lrauv.h, "learner"): the FP32 forward pass that records its
 // tape in the caller's workspace, the reverse pass into the parameter
 // gradient, and the critic's variant on global states. Per-row work runs in
-// train_kernels.hip; the dense products are plain FP32 GEMMs in rocBLAS
-// (atomics off: results do not depend on the run) and, for the input
-// gradients into 64-wide rows, in hipBLASLt (no workspace, the heuristic's
-// first algorithm per shape); column sums are the library's own kernels.
+// train_kernels.hip, and so do the layers' weight gradients (FP32 matrix
+// cores, fixed-order partial sums) and the column sums; the other dense
+// products are plain FP32 GEMMs: the forward ones in hipBLASLt with its bias
+// epilogue, the input gradients into 64-wide rows in hipBLASLt, the rest in
+// rocBLAS (atomics off). hipBLASLt runs without workspace, with the
+// heuristic's first algorithm per shape, so results do not depend on the run.
 #include <hip/hip_runtime.h>
 #include <hipblaslt/hipblaslt.h>
 #include <rocblas/rocblas.h>
@@ -69,7 +71,9 @@ TrainWork train_work(int64_t A, int nt) {
   w.bfa = take(A * D * 4);
   w.gaug = take(D * 8 * 4);
   w.csum = take(mil::tr_colsum_scratch_doubles() * 8);
-  w.wpart = take((int64_t)(kMaxSplit + 1) * F * D * 4);  // the largest weight: 256 x 64
+  // weight-gradient partials; the largest weight is 256 x 64
+  w.wpart = take((int64_t)(kMaxSplit + 1 > mil::kWgMaxBlocks ? kMaxSplit + 1 : mil::kWgMaxBlocks) *
+                 F * D * 4);
   w.total = o;
   return w;
 }
@@ -242,11 +246,18 @@ struct Ctx {
     ok = rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, K, (int)R, N, &one, W,
                        K, dY, N, &beta, dX, K) == rocblas_status_success;
   }
-  // dW [N][K] = dY^T X summed over the R rows: the rows split into up to
+  // dW [N][K] = dY^T X summed over the R rows: on the matrix cores
+  // (tr_wgrad) for the layers' shapes; otherwise the rows split into up to
   // kMaxSplit equal chunks (one batched GEMM, one product per chunk, plus the
   // remainder), the chunks' products then added in order
   void dw(const float *dY, const float *X, float *dW, int64_t R, int N, int K) {
     const float one = 1.0f, zero = 0.0f, beta = acc ? 1.0f : 0.0f;
+    if (!ok) return;
+    const int rc = mil::tr_wgrad(dY, X, R, N, K, wpart, acc, dW, stream);
+    if (rc != -2) {  // the matrix-core kernel took it
+      ok = rc == 0;
+      return;
+    }
     const int64_t nb = R / 4096 < kMaxSplit ? R / 4096 : kMaxSplit;
     if (nb <= 1) {
       ok = ok && rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_transpose, K, N, (int)R,

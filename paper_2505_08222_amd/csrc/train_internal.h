@@ -42,6 +42,14 @@ int tr_fill(float *p, float v, int64_t n, void *stream);
 int64_t tr_colsum_scratch_doubles();
 int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float *out,
               void *stream);
+// dW [N][K] (+)= dY^T X over the R rows (dY [R][N], X [R][K]) on the FP32
+// matrix cores, in up to kWgMaxBlocks row blocks whose partials (part holds
+// kWgMaxBlocks * N * K floats) are then added in a fixed order. Shapes
+// (N, K) in {(64, 64), (64, 256), (192, 64), (256, 64)}; -2 for any other
+// (the caller uses a library GEMM), -1 if a launch failed.
+constexpr int kWgMaxBlocks = 512;
+int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *part, int acc,
+             float *out, void *stream);
 // out [n] (+)= sum over b < nb of part[b][n], in order (FP64 sums)
 int tr_sum_partials(const float *part, int nb, int64_t n, int acc, float *out, void *stream);
 

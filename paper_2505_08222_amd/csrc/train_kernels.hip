@@ -284,6 +284,94 @@ attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P
   store_row16(row + 2 * kPolD, dv);
 }
 
+// Weight-gradient partials on the FP32 matrix cores: dW [N][K] = sum over
+// rows r of dY[r][n] X[r][k], as v_mfma_f32_16x16x4f32 products with
+// A = dY^T (16 n x 4 rows) and B = X (4 rows x 16 k), four rows of the sum
+// per instruction. Block b (four wavefronts) takes rows [b per, (b+1) per)
+// and writes its sums to part[b]; wavefront w holds the n-blocks
+// [w NBW, (w+1) NBW) against every k-block. Lane l supplies A[l%16][l/16]
+// and B[l/16][l%16] and receives D[4(l/16)+v][l%16] in accumulator v. Rows
+// past the block's end are read as 0. Each block's sum runs over its rows in
+// order, so the result does not depend on the run.
+typedef float wg_floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kWgThreads = 256;
+
+template <int NBW, int KB>
+__global__ void __launch_bounds__(kWgThreads)
+wgrad_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t R, int64_t per,
+             float *__restrict__ part) {
+  constexpr int N = NBW * 64, K = KB * 16;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rl = lane >> 4, cl = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  wg_floatx4 acc[NBW][KB];
+#pragma unroll
+  for (int i = 0; i < NBW; ++i)
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[i][j] = wg_floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  const float *ya = dY + w * NBW * 16 + cl;
+  const float *xb = X + cl;
+  for (int64_t r = r0; r < r1; r += 16) {
+    float a[4][NBW], b[4][KB];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t row = r + 4 * s + rl;
+      const bool in = row < r1;
+#pragma unroll
+      for (int i = 0; i < NBW; ++i) a[s][i] = in ? ya[row * N + i * 16] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < KB; ++j) b[s][j] = in ? xb[row * K + j * 16] : 0.0f;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < NBW; ++i)
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][i], b[s][j], acc[i][j], 0, 0, 0);
+  }
+  float *pb = part + (int64_t)blockIdx.x * N * K;
+#pragma unroll
+  for (int i = 0; i < NBW; ++i)
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        pb[((w * NBW + i) * 16 + 4 * rl + v) * K + j * 16 + cl] = acc[i][j][v];
+}
+
+// out [n] (+)= sum over b < nb of part[b][n]: block = 64 outputs, wavefront
+// w adds partials [w q, (w+1) q) in order (FP64), then the four sums are
+// added in order.
+__global__ void __launch_bounds__(kWgThreads)
+wgrad_sum_kernel(const float *__restrict__ part, int nb, int64_t n, int acc,
+                 float *__restrict__ out) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+  const int q = (nb + 3) / 4;
+  const int b0 = w * q, b1 = b0 + q < nb ? b0 + q : nb;
+  double s = 0.0;
+  if (i < n) {
+    int b = b0;
+    for (; b + 7 < b1; b += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; b < b1; ++b) s += (double)part[(int64_t)b * n + i];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && i < n) {
+    const double t = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    out[i] = acc ? out[i] + (float)t : (float)t;
+  }
+}
+
 // Column sums of Y [R][N] (N <= 256) in two fixed-order passes: block b adds
 // rows [b * per, (b + 1) * per) in FP64 (thread (group, column) with four
 // running sums over its rows, groups combined in order), then one wavefront
@@ -576,6 +664,31 @@ int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float 
   if (check()) return -1;
   hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 3) / 4)), dim3(256), 0, st, scratch,
                      kCsBlocks, N, acc, out);
+  return check();
+}
+
+int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *part, int acc,
+             float *out, void *stream) {
+  if (R < 1) return -2;
+  int64_t per = (R + kWgMaxBlocks - 1) / kWgMaxBlocks;
+  per = (per + 15) / 16 * 16;
+  const int64_t nb = (R + per - 1) / per;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 g((unsigned)nb), b(kWgThreads);
+  if (N == 64 && K == 64)
+    hipLaunchKernelGGL((wgrad_kernel<1, 4>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 64 && K == 256)
+    hipLaunchKernelGGL((wgrad_kernel<1, 16>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 192 && K == 64)
+    hipLaunchKernelGGL((wgrad_kernel<3, 4>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 256 && K == 64)
+    hipLaunchKernelGGL((wgrad_kernel<4, 4>), g, b, 0, st, dY, X, R, per, part);
+  else
+    return -2;
+  if (check()) return -1;
+  const int64_t n = (int64_t)N * K;
+  hipLaunchKernelGGL(wgrad_sum_kernel, dim3((unsigned)((n + 63) / 64)), b, 0, st, part, (int)nb,
+                     n, acc, out);
   return check();
 }
 
