@@ -45,7 +45,7 @@ int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float 
 // dW [N][K] (+)= dY^T X over the R rows (dY [R][N], X [R][K]) on the FP32
 // matrix cores, in up to kWgMaxBlocks row blocks whose partials (part holds
 // kWgMaxBlocks * N * K floats) are then added in a fixed order. Shapes
-// (N, K) in {(64, 64), (64, 256), (192, 64), (256, 64)}; -2 for any other
+// (N, K) in {(64, 64), (64, 256), (192, 64), (256, 64), (64, 8)}; -2 for any other
 // (the caller uses a library GEMM), -1 if a launch failed.
 constexpr int kWgMaxBlocks = 512;
 int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *part, int acc,

@@ -105,6 +105,91 @@ gelu_back_kernel(float *__restrict__ dz, const float *__restrict__ z, int64_t n)
   if (i < n) dz[i] *= gelu_tanh_grad(z[i]);
 }
 
+// The same on float4s (n a multiple of 4, 16-byte aligned arrays).
+__global__ void __launch_bounds__(kTrThreads)
+gelu4_kernel(const float4 *__restrict__ z, float4 *__restrict__ f, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const float4 v = z[i];
+  f[i] = make_float4(gelu_tanh(v.x), gelu_tanh(v.y), gelu_tanh(v.z), gelu_tanh(v.w));
+}
+
+__global__ void __launch_bounds__(kTrThreads)
+gelu_back4_kernel(float4 *__restrict__ dz, const float4 *__restrict__ z, int64_t n4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n4) return;
+  const float4 v = z[i];
+  float4 d = dz[i];
+  d.x *= gelu_tanh_grad(v.x);
+  d.y *= gelu_tanh_grad(v.y);
+  d.z *= gelu_tanh_grad(v.z);
+  d.w *= gelu_tanh_grad(v.w);
+  dz[i] = d;
+}
+
+// LayerNorm on float4s: 16 lanes per row (lane q: features 4q..4q+3), four
+// rows per wavefront; row sums over the 16 lanes by a fixed butterfly.
+__device__ __forceinline__ float row16_sum(float v) {
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 16);
+  return v;
+}
+
+__global__ void __launch_bounds__(kTrThreads)
+layernorm4_kernel(const float4 *__restrict__ x, const float *__restrict__ g,
+                  const float *__restrict__ b, float4 *__restrict__ y, int64_t R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = t >> 4;
+  const int q = (int)(t & 15);
+  if (r >= R) return;  // whole 16-lane groups leave together
+  const float4 v = x[r * (kPolD / 4) + q];
+  const float m = row16_sum((v.x + v.y) + (v.z + v.w)) * (1.0f / kPolD);
+  const float c0 = v.x - m, c1 = v.y - m, c2 = v.z - m, c3 = v.w - m;
+  const float var = row16_sum((c0 * c0 + c1 * c1) + (c2 * c2 + c3 * c3)) * (1.0f / kPolD);
+  const float rs = rsqrtf(var + 1e-5f);
+  const int d = 4 * q;
+  y[r * (kPolD / 4) + q] = make_float4(fmaf(c0 * rs, g[d], b[d]), fmaf(c1 * rs, g[d + 1], b[d + 1]),
+                                       fmaf(c2 * rs, g[d + 2], b[d + 2]),
+                                       fmaf(c3 * rs, g[d + 3], b[d + 3]));
+}
+
+// Reverse pass on float4s, same layout: dx is added to dxacc; dyxhat = dy * xhat.
+__global__ void __launch_bounds__(kTrThreads)
+layernorm_back4_kernel(const float4 *__restrict__ x, const float *__restrict__ g,
+                       const float4 *__restrict__ dy, float4 *__restrict__ dxacc,
+                       float4 *__restrict__ dyxhat, int64_t R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = t >> 4;
+  const int q = (int)(t & 15);
+  if (r >= R) return;
+  const int64_t i = r * (kPolD / 4) + q;
+  const float4 v = x[i];
+  const float m = row16_sum((v.x + v.y) + (v.z + v.w)) * (1.0f / kPolD);
+  const float c[4] = {v.x - m, v.y - m, v.z - m, v.w - m};
+  const float var = row16_sum((c[0] * c[0] + c[1] * c[1]) + (c[2] * c[2] + c[3] * c[3])) *
+                    (1.0f / kPolD);
+  const float rs = rsqrtf(var + 1e-5f);
+  const float4 gy4 = dy[i];
+  const float gy[4] = {gy4.x, gy4.y, gy4.z, gy4.w};
+  float xh[4], dxh[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    xh[k] = c[k] * rs;
+    dxh[k] = gy[k] * g[4 * q + k];
+  }
+  const float s1 = row16_sum((dxh[0] + dxh[1]) + (dxh[2] + dxh[3])) * (1.0f / kPolD);
+  const float s2 =
+      row16_sum((dxh[0] * xh[0] + dxh[1] * xh[1]) + (dxh[2] * xh[2] + dxh[3] * xh[3])) *
+      (1.0f / kPolD);
+  float4 a = dxacc[i];
+  a.x += rs * (dxh[0] - s1 - xh[0] * s2);
+  a.y += rs * (dxh[1] - s1 - xh[1] * s2);
+  a.z += rs * (dxh[2] - s1 - xh[2] * s2);
+  a.w += rs * (dxh[3] - s1 - xh[3] * s2);
+  dxacc[i] = a;
+  dyxhat[i] = make_float4(gy[0] * xh[0], gy[1] * xh[1], gy[2] * xh[2], gy[3] * xh[3]);
+}
+
 // Attention of one agent per wavefront (a block of 64 threads): the agent's
 // rows are staged in LDS with coalesced float4 loads, then lane (head h,
 // query t) = (lane / 16, lane % 16) does that query's work; lanes t >= nt
@@ -289,18 +374,18 @@ attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P
 // A = dY^T (16 n x 4 rows) and B = X (4 rows x 16 k), four rows of the sum
 // per instruction. Block b (four wavefronts) takes rows [b per, (b+1) per)
 // and writes its sums to part[b]; wavefront w holds the n-blocks
-// [w NBW, (w+1) NBW) against every k-block. Lane l supplies A[l%16][l/16]
+// [w NBW, (w+1) NBW) against every 16-wide k-block. Lane l supplies A[l%16][l/16]
 // and B[l/16][l%16] and receives D[4(l/16)+v][l%16] in accumulator v. Rows
 // past the block's end are read as 0. Each block's sum runs over its rows in
 // order, so the result does not depend on the run.
 typedef float wg_floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kWgThreads = 256;
 
-template <int NBW, int KB>
+template <int NBW, int K>
 __global__ void __launch_bounds__(kWgThreads)
 wgrad_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t R, int64_t per,
              float *__restrict__ part) {
-  constexpr int N = NBW * 64, K = KB * 16;
+  constexpr int N = NBW * 64, KB = (K + 15) / 16;  // K < 16: lanes past K read 0, write nothing
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int rl = lane >> 4, cl = lane & 15;
   const int64_t r0 = (int64_t)blockIdx.x * per;
@@ -321,7 +406,7 @@ wgrad_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t 
 #pragma unroll
       for (int i = 0; i < NBW; ++i) a[s][i] = in ? ya[row * N + i * 16] : 0.0f;
 #pragma unroll
-      for (int j = 0; j < KB; ++j) b[s][j] = in ? xb[row * K + j * 16] : 0.0f;
+      for (int j = 0; j < KB; ++j) b[s][j] = (in && j * 16 + cl < K) ? xb[row * K + j * 16] : 0.0f;
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -338,7 +423,7 @@ wgrad_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t 
     for (int j = 0; j < KB; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        pb[((w * NBW + i) * 16 + 4 * rl + v) * K + j * 16 + cl] = acc[i][j][v];
+        if (j * 16 + cl < K) pb[((w * NBW + i) * 16 + 4 * rl + v) * K + j * 16 + cl] = acc[i][j][v];
 }
 
 // out [n] (+)= sum over b < nb of part[b][n]: block = 64 outputs, wavefront
@@ -597,10 +682,17 @@ int tr_embed(const float *obs, const uint8_t *mask, int64_t R, int nt, int rec,
   return check();
 }
 
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
 int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64_t R, void *stream) {
   if (R == 0) return 0;
-  hipLaunchKernelGGL(layernorm_kernel, grid_for(R * 64), dim3(kTrThreads), 0, (hipStream_t)stream,
-                     x, g, b, y, R);
+  if (aligned16(x) && aligned16(y))
+    hipLaunchKernelGGL(layernorm4_kernel, grid_for(R * 16), dim3(kTrThreads), 0,
+                       (hipStream_t)stream, reinterpret_cast<const float4 *>(x), g, b,
+                       reinterpret_cast<float4 *>(y), R);
+  else
+    hipLaunchKernelGGL(layernorm_kernel, grid_for(R * 64), dim3(kTrThreads), 0,
+                       (hipStream_t)stream, x, g, b, y, R);
   return check();
 }
 
@@ -613,18 +705,26 @@ int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *
 
 int tr_gelu(const float *z, float *f, int64_t n, void *stream) {
   if (n == 0) return 0;
-  hipLaunchKernelGGL(gelu_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, z, f, n);
+  if (n % 4 == 0 && aligned16(z) && aligned16(f))
+    hipLaunchKernelGGL(gelu4_kernel, grid_for(n / 4), dim3(kTrThreads), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float4 *>(z), reinterpret_cast<float4 *>(f), n / 4);
+  else
+    hipLaunchKernelGGL(gelu_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, z, f,
+                       n);
   return check();
 }
 
 int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream) {
   if (n == 0) return 0;
-  hipLaunchKernelGGL(gelu_back_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, dz,
-                     z, n);
+  if (n % 4 == 0 && aligned16(z) && aligned16(dz))
+    hipLaunchKernelGGL(gelu_back4_kernel, grid_for(n / 4), dim3(kTrThreads), 0,
+                       (hipStream_t)stream, reinterpret_cast<float4 *>(dz),
+                       reinterpret_cast<const float4 *>(z), n / 4);
+  else
+    hipLaunchKernelGGL(gelu_back_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream,
+                       dz, z, n);
   return check();
 }
-
-static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
 int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float *P, float *o,
                  void *stream) {
@@ -676,13 +776,15 @@ int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *pa
   hipStream_t st = (hipStream_t)stream;
   const dim3 g((unsigned)nb), b(kWgThreads);
   if (N == 64 && K == 64)
-    hipLaunchKernelGGL((wgrad_kernel<1, 4>), g, b, 0, st, dY, X, R, per, part);
+    hipLaunchKernelGGL((wgrad_kernel<1, 64>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 64 && K == 256)
-    hipLaunchKernelGGL((wgrad_kernel<1, 16>), g, b, 0, st, dY, X, R, per, part);
+    hipLaunchKernelGGL((wgrad_kernel<1, 256>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 192 && K == 64)
-    hipLaunchKernelGGL((wgrad_kernel<3, 4>), g, b, 0, st, dY, X, R, per, part);
+    hipLaunchKernelGGL((wgrad_kernel<3, 64>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 256 && K == 64)
-    hipLaunchKernelGGL((wgrad_kernel<4, 4>), g, b, 0, st, dY, X, R, per, part);
+    hipLaunchKernelGGL((wgrad_kernel<4, 64>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 64 && K == 8)
+    hipLaunchKernelGGL((wgrad_kernel<1, 8>), g, b, 0, st, dY, X, R, per, part);
   else
     return -2;
   if (check()) return -1;
@@ -702,8 +804,14 @@ int tr_sum_partials(const float *part, int nb, int64_t n, int acc, float *out, v
 int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dxacc, float *dyxhat,
                       int64_t R, void *stream) {
   if (R == 0) return 0;
-  hipLaunchKernelGGL(layernorm_back_kernel, grid_for(R * 64), dim3(kTrThreads), 0,
-                     (hipStream_t)stream, x, g, dy, dxacc, dyxhat, R);
+  if (aligned16(x) && aligned16(dy) && aligned16(dxacc) && aligned16(dyxhat))
+    hipLaunchKernelGGL(layernorm_back4_kernel, grid_for(R * 16), dim3(kTrThreads), 0,
+                       (hipStream_t)stream, reinterpret_cast<const float4 *>(x), g,
+                       reinterpret_cast<const float4 *>(dy), reinterpret_cast<float4 *>(dxacc),
+                       reinterpret_cast<float4 *>(dyxhat), R);
+  else
+    hipLaunchKernelGGL(layernorm_back_kernel, grid_for(R * 64), dim3(kTrThreads), 0,
+                       (hipStream_t)stream, x, g, dy, dxacc, dyxhat, R);
   return check();
 }
 
