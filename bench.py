@@ -703,9 +703,10 @@ def bench_ppo(args, T=32, cpu_seconds=None):
                         "roofline": {"bound": "mfma", "unit": "TFLOP/s", "peak": 157.3,
                                      "achieved": fl_full / (t_full / 1e3) / 1e12,
                                      "frac": fl_full / (t_full / 1e3) / 1e12 / 157.3},
-                        "note": "FP32 training form (forward with tape, exact backward, rocBLAS "
-                                "FP32 GEMMs) of actor and critic plus Adam on every parameter; "
-                                "flops counted as 3x the forward's"},
+                        "note": "FP32 training form (forward with tape, exact backward; weight "
+                                "gradients on the FP32 matrix cores, other products in "
+                                "hipBLASLt/rocBLAS FP32 GEMMs) of actor and critic plus Adam on "
+                                "every parameter; flops counted as 3x the forward's"},
         "objective": {"policy_loss": float(o[0]), "value_loss": float(o[1]),
                       "entropy": float(o[2]), "clip_frac": float(o[3])},
         "roofline": {"bound": "mfma", "kernel": "policy_kernel (critic tokens)", "achieved": ach,

@@ -544,16 +544,18 @@ int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_ag
  * that records every intermediate in the workspace (the tape), then its
  * exact reverse pass into the gradient of every parameter. The per-row work
  * (embedding, LayerNorms, attention with its softmax and key mask, tanh
- * GELU, head) runs in the library's kernels, the dense products in rocBLAS
- * FP32 GEMMs. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
+ * GELU, head) and the weight gradients (FP32 matrix cores) run in the
+ * library's kernels, the other dense products in hipBLASLt and rocBLAS FP32
+ * GEMMs; every sum is taken in a fixed order, so results do not depend on
+ * the run. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
  * the recurrent form of policy_forward_rec (n_tok - 1 observed tokens per
- * agent after the carried state). The library keeps one rocBLAS handle per
- * device for these calls: calls on one device must not overlap from several
- * host threads. Within one call the carried state is an
+ * agent after the carried state). The library keeps one rocBLAS and one
+ * hipBLASLt handle per device for these calls (made on the first call):
+ * calls on one device must not overlap from several host threads. Within one call the carried state is an
  * input: its gradient is returned; a sequence is differentiated through the
  * state by chaining the calls (policy_train_backward). */
 /* Workspace of the training form for A agents of n_tok rows (256-byte
- * aligned; about 11 KB per row); -1 on bad sizes. */
+ * aligned; about 11 KB per row plus 36 MB of partial sums); -1 on bad sizes. */
 int64_t policy_train_workspace_bytes(int64_t A, int32_t n_tok);
 /* Forward pass: d_obs [A * (n_tok - rec)][6], d_mask, d_hidden_in [A][64]
  * (rec = 1; NULL: zeros) -> d_logits [A][8] (may be NULL), d_feat [A][64]
