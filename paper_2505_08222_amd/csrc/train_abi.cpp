@@ -33,7 +33,7 @@ int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 // reverse pass's scratch, all [rows][...] FP32 unless stated.
 struct TrainWork {
   int64_t tok, tmask, xaug, mrow, h[L + 1], a1[L], qkv[L], P[L], o[L], hmid[L], a2[L], z[L], f[L],
-      feat, dh, t64, dyx, dqkv, dz, dl8, gfa, bfa, gaug, csum, wpart, total;
+      feat, dh, t64, dqkv, dz, dl8, gfa, bfa, gaug, csum, wpart, total;
 };
 
 TrainWork train_work(int64_t A, int nt) {
@@ -63,7 +63,6 @@ TrainWork train_work(int64_t A, int nt) {
   w.feat = take(A * D * 4);
   w.dh = take(R * D * 4);
   w.t64 = take(R * D * 4);
-  w.dyx = take(R * D * 4);
   w.dqkv = take(R * 3 * D * 4);
   w.dz = take(R * F * 4);
   w.dl8 = take(A * NA * 4);
@@ -393,7 +392,7 @@ int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_
   const int64_t R = A * nt;
   auto fp = [&](int64_t off) { return (float *)(ws + off); };
   const uint8_t *mrow = (const uint8_t *)(ws + w.mrow);
-  float *dh = fp(w.dh), *t64 = fp(w.t64), *dyx = fp(w.dyx);
+  float *dh = fp(w.dh), *t64 = fp(w.t64);
   Ctx c{bh, stream, (double *)(ws + w.csum), fp(w.wpart), accumulate ? 1 : 0};
   float *gfin = d_grad + mil::kPolOffFinal;
   // head and final LayerNorm (each agent's first row)
@@ -407,28 +406,29 @@ int policy_train_backward(int64_t A, int32_t n_tok, int32_t rec, const float *d_
   for (int l = L - 1; l >= 0 && c.ok; --l) {
     const float *lp = d_params + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
     float *gp = d_grad + mil::kPolOffLayer0 + (int64_t)l * mil::kPolLayerParams;
+    // the bias b2 below this layer's output: summed by the LayerNorm pass of
+    // the layer above, except for the last layer
+    float *gprev = l > 0 ? gp - mil::kPolLayerParams : nullptr;
     // feed-forward block: h[l + 1] = hmid + W2 gelu(z) + b2
-    c.colsum(dh, gp + mil::kPolB2, R, D);
+    if (l == L - 1) c.colsum(dh, gp + mil::kPolB2, R, D);
     c.dw(dh, fp(w.f[l]), gp + mil::kPolW2, R, D, F);
     c.xw(dh, lp + mil::kPolW2, fp(w.dz), R, D, F, 0.0f);
-    c.k(mil::tr_gelu_back(fp(w.dz), fp(w.z[l]), R * F, stream));
-    c.colsum(fp(w.dz), gp + mil::kPolB1, R, F);
+    c.k(mil::tr_gelu_back_sums(fp(w.dz), fp(w.z[l]), R, c.csum, c.acc, gp + mil::kPolB1, stream));
     c.dw(fp(w.dz), fp(w.a2[l]), gp + mil::kPolW1, R, F, D);
     c.xw(fp(w.dz), lp + mil::kPolW1, t64, R, F, D, 0.0f);
-    c.k(mil::tr_layernorm_back(fp(w.hmid[l]), lp + mil::kPolLn2G, t64, dh, dyx, R, stream));
-    c.colsum(dyx, gp + mil::kPolLn2G, R, D);
-    c.colsum(t64, gp + mil::kPolLn2B, R, D);
+    c.k(mil::tr_layernorm_back_sums(fp(w.hmid[l]), lp + mil::kPolLn2G, t64, dh, R, c.csum, c.acc,
+                                    gp + mil::kPolLn2G, gp + mil::kPolLn2B, gp + mil::kPolBo,
+                                    stream));
     // attention block: hmid = h[l] + Wo attention(LN1(h[l])) + bo
-    c.colsum(dh, gp + mil::kPolBo, R, D);
     c.dw(dh, fp(w.o[l]), gp + mil::kPolWo, R, D, D);
     c.xw(dh, lp + mil::kPolWo, t64, R, D, D, 0.0f);
     c.k(mil::tr_attention_back(fp(w.qkv[l]), fp(w.P[l]), mrow, t64, A, nt, fp(w.dqkv), stream));
     c.colsum(fp(w.dqkv), gp + mil::kPolBqkv, R, 3 * D);
     c.dw(fp(w.dqkv), fp(w.a1[l]), gp + mil::kPolWqkv, R, 3 * D, D);
     c.xw(fp(w.dqkv), lp + mil::kPolWqkv, t64, R, 3 * D, D, 0.0f);
-    c.k(mil::tr_layernorm_back(fp(w.h[l]), lp + mil::kPolLn1G, t64, dh, dyx, R, stream));
-    c.colsum(dyx, gp + mil::kPolLn1G, R, D);
-    c.colsum(t64, gp + mil::kPolLn1B, R, D);
+    c.k(mil::tr_layernorm_back_sums(fp(w.h[l]), lp + mil::kPolLn1G, t64, dh, R, c.csum, c.acc,
+                                    gp + mil::kPolLn1G, gp + mil::kPolLn1B,
+                                    gprev ? gprev + mil::kPolB2 : nullptr, stream));
   }
   // embedding (observed rows; a carried row's augmented input is zero)
   const int acc = c.acc;

@@ -16,16 +16,22 @@ int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64
 // out [R][N] = base (NULL: 0) + bias broadcast over rows
 int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *out, void *stream);
 int tr_gelu(const float *z, float *f, int64_t n, void *stream);
-int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream);
+// dz [R][256] *= GELU'(z) in place; bias_grad [256] (+)= its column sums
+// (scratch: tr_colsum_scratch_doubles() doubles; 16-byte aligned arrays)
+int tr_gelu_back_sums(float *dz, const float *z, int64_t R, double *scratch, int acc,
+                      float *bias_grad, void *stream);
 // qkv [R][192] -> P [A][4][nt][nt] (softmax over unmasked keys), o [R][64]
 int tr_attention(const float *qkv, const uint8_t *mrow, int64_t A, int nt, float *P, float *o,
                  void *stream);
 // dout [R][64] (gradient at o) -> dqkv [R][192]
 int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, const float *dout,
                       int64_t A, int nt, float *dqkv, void *stream);
-// dxacc += LayerNorm input gradient; dyxhat = dy * xhat
-int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dxacc, float *dyxhat,
-                      int64_t R, void *stream);
+// dxacc += LayerNorm input gradient; then gain_grad (+)= column sums of
+// dy * xhat, bias_grad (+)= those of dy and next_grad (may be NULL) (+)= those
+// of the updated dxacc (scratch as for tr_colsum; 16-byte aligned arrays)
+int tr_layernorm_back_sums(const float *x, const float *g, const float *dy, float *dxacc,
+                           int64_t R, double *scratch, int acc, float *gain_grad,
+                           float *bias_grad, float *next_grad, void *stream);
 // final LayerNorm of each agent's first row -> feat [A][64], logits [A][8] (may be NULL)
 int tr_head(const float *h, int64_t A, int nt, const float *prm, float *logits, float *feat,
             void *stream);

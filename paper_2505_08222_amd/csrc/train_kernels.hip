@@ -99,32 +99,13 @@ gelu_kernel(const float *__restrict__ z, float *__restrict__ f, int64_t n) {
   if (i < n) f[i] = gelu_tanh(z[i]);
 }
 
-__global__ void __launch_bounds__(kTrThreads)
-gelu_back_kernel(float *__restrict__ dz, const float *__restrict__ z, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dz[i] *= gelu_tanh_grad(z[i]);
-}
-
-// The same on float4s (n a multiple of 4, 16-byte aligned arrays).
+// GELU on float4s (n a multiple of 4, 16-byte aligned arrays).
 __global__ void __launch_bounds__(kTrThreads)
 gelu4_kernel(const float4 *__restrict__ z, float4 *__restrict__ f, int64_t n4) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n4) return;
   const float4 v = z[i];
   f[i] = make_float4(gelu_tanh(v.x), gelu_tanh(v.y), gelu_tanh(v.z), gelu_tanh(v.w));
-}
-
-__global__ void __launch_bounds__(kTrThreads)
-gelu_back4_kernel(float4 *__restrict__ dz, const float4 *__restrict__ z, int64_t n4) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n4) return;
-  const float4 v = z[i];
-  float4 d = dz[i];
-  d.x *= gelu_tanh_grad(v.x);
-  d.y *= gelu_tanh_grad(v.y);
-  d.z *= gelu_tanh_grad(v.z);
-  d.w *= gelu_tanh_grad(v.w);
-  dz[i] = d;
 }
 
 // LayerNorm on float4s: 16 lanes per row (lane q: features 4q..4q+3), four
@@ -153,41 +134,148 @@ layernorm4_kernel(const float4 *__restrict__ x, const float *__restrict__ g,
                                        fmaf(c3 * rs, g[d + 3], b[d + 3]));
 }
 
-// Reverse pass on float4s, same layout: dx is added to dxacc; dyxhat = dy * xhat.
-__global__ void __launch_bounds__(kTrThreads)
-layernorm_back4_kernel(const float4 *__restrict__ x, const float *__restrict__ g,
-                       const float4 *__restrict__ dy, float4 *__restrict__ dxacc,
-                       float4 *__restrict__ dyxhat, int64_t R) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = t >> 4;
-  const int q = (int)(t & 15);
-  if (r >= R) return;
-  const int64_t i = r * (kPolD / 4) + q;
-  const float4 v = x[i];
-  const float m = row16_sum((v.x + v.y) + (v.z + v.w)) * (1.0f / kPolD);
-  const float c[4] = {v.x - m, v.y - m, v.z - m, v.w - m};
-  const float var = row16_sum((c[0] * c[0] + c[1] * c[1]) + (c[2] * c[2] + c[3] * c[3])) *
-                    (1.0f / kPolD);
-  const float rs = rsqrtf(var + 1e-5f);
-  const float4 gy4 = dy[i];
-  const float gy[4] = {gy4.x, gy4.y, gy4.z, gy4.w};
-  float xh[4], dxh[4];
+// Reverse passes fused with the column sums of what they produce (bias and
+// LayerNorm gradients), so that the tape is not read again for those: rows
+// split into kCsBlocks blocks of `per` rows, each block's FP64 sums combined
+// in a fixed order into part[block], the partials then added by
+// colsum_final_kernel / sums3_final_kernel.
+constexpr int kCsBlocks = 1024;
+
+// dz *= GELU'(z) in place (rows of F = 256), and the column sums of the
+// result (the first feed-forward bias's gradient). Thread (row slot s,
+// quad q) = (tid / 64, tid % 64): four row slots, two rows in flight each.
+__global__ void __launch_bounds__(256)
+gelu_back_sums_kernel(float4 *__restrict__ dz, const float4 *__restrict__ z, int64_t R,
+                      int64_t per, double *__restrict__ part) {
+  __shared__ double red[4][kPolF];
+  const int s = threadIdx.x >> 6, q = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t r = r0 + s;
+  for (; r + 4 < r1; r += 8) {
+    const int64_t i0 = r * (kPolF / 4) + q, i1 = (r + 4) * (kPolF / 4) + q;
+    const float4 v0 = z[i0], v1 = z[i1];
+    float4 d0 = dz[i0], d1 = dz[i1];
+    d0.x *= gelu_tanh_grad(v0.x);
+    d0.y *= gelu_tanh_grad(v0.y);
+    d0.z *= gelu_tanh_grad(v0.z);
+    d0.w *= gelu_tanh_grad(v0.w);
+    d1.x *= gelu_tanh_grad(v1.x);
+    d1.y *= gelu_tanh_grad(v1.y);
+    d1.z *= gelu_tanh_grad(v1.z);
+    d1.w *= gelu_tanh_grad(v1.w);
+    dz[i0] = d0;
+    dz[i1] = d1;
+    a[0] += (double)d0.x;
+    a[1] += (double)d0.y;
+    a[2] += (double)d0.z;
+    a[3] += (double)d0.w;
+    a[0] += (double)d1.x;
+    a[1] += (double)d1.y;
+    a[2] += (double)d1.z;
+    a[3] += (double)d1.w;
+  }
+  if (r < r1) {
+    const int64_t i0 = r * (kPolF / 4) + q;
+    const float4 v0 = z[i0];
+    float4 d0 = dz[i0];
+    d0.x *= gelu_tanh_grad(v0.x);
+    d0.y *= gelu_tanh_grad(v0.y);
+    d0.z *= gelu_tanh_grad(v0.z);
+    d0.w *= gelu_tanh_grad(v0.w);
+    dz[i0] = d0;
+    a[0] += (double)d0.x;
+    a[1] += (double)d0.y;
+    a[2] += (double)d0.z;
+    a[3] += (double)d0.w;
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[s][4 * q + k] = a[k];
+  __syncthreads();
+  const int col = threadIdx.x;  // 256 threads = 256 columns
+  part[(int64_t)blockIdx.x * kPolF + col] =
+      ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+}
+
+// LayerNorm's reverse pass on float4s (16 lanes per row as in the forward;
+// dx added to dxacc) and the column sums of dy * xhat (the gain's gradient),
+// dy (the bias's) and the updated dxacc (the gradient of the bias whose sum
+// this LayerNorm normalised). Thread (row slot s, quad q) = (tid / 16,
+// tid % 16): 16 row slots.
+__global__ void __launch_bounds__(256)
+layernorm_back_sums_kernel(const float4 *__restrict__ x, const float *__restrict__ g,
+                           const float4 *__restrict__ dy, float4 *__restrict__ dxacc, int64_t R,
+                           int64_t per, double *__restrict__ part) {
+  __shared__ double red[16][3 * kPolD];
+  const int s = threadIdx.x >> 4, q = threadIdx.x & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  float gq[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gq[k] = g[4 * q + k];
+  double sg[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0}, sh[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = r0 + s; r < r1; r += 16) {  // a row's 16 lanes share every trip
+    const int64_t i = r * (kPolD / 4) + q;
+    const float4 v = x[i];
+    const float m = row16_sum((v.x + v.y) + (v.z + v.w)) * (1.0f / kPolD);
+    const float c[4] = {v.x - m, v.y - m, v.z - m, v.w - m};
+    const float var = row16_sum((c[0] * c[0] + c[1] * c[1]) + (c[2] * c[2] + c[3] * c[3])) *
+                      (1.0f / kPolD);
+    const float rs = rsqrtf(var + 1e-5f);
+    const float4 gy4 = dy[i];
+    const float gy[4] = {gy4.x, gy4.y, gy4.z, gy4.w};
+    float xh[4], dxh[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      xh[k] = c[k] * rs;
+      dxh[k] = gy[k] * gq[k];
+    }
+    const float s1 = row16_sum((dxh[0] + dxh[1]) + (dxh[2] + dxh[3])) * (1.0f / kPolD);
+    const float s2 =
+        row16_sum((dxh[0] * xh[0] + dxh[1] * xh[1]) + (dxh[2] * xh[2] + dxh[3] * xh[3])) *
+        (1.0f / kPolD);
+    const float4 a0 = dxacc[i];
+    const float a[4] = {a0.x + rs * (dxh[0] - s1 - xh[0] * s2), a0.y + rs * (dxh[1] - s1 - xh[1] * s2),
+                        a0.z + rs * (dxh[2] - s1 - xh[2] * s2), a0.w + rs * (dxh[3] - s1 - xh[3] * s2)};
+    dxacc[i] = make_float4(a[0], a[1], a[2], a[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sg[k] += (double)(gy[k] * xh[k]);
+      sb[k] += (double)gy[k];
+      sh[k] += (double)a[k];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    xh[k] = c[k] * rs;
-    dxh[k] = gy[k] * g[4 * q + k];
+    red[s][4 * q + k] = sg[k];
+    red[s][kPolD + 4 * q + k] = sb[k];
+    red[s][2 * kPolD + 4 * q + k] = sh[k];
   }
-  const float s1 = row16_sum((dxh[0] + dxh[1]) + (dxh[2] + dxh[3])) * (1.0f / kPolD);
-  const float s2 =
-      row16_sum((dxh[0] * xh[0] + dxh[1] * xh[1]) + (dxh[2] * xh[2] + dxh[3] * xh[3])) *
-      (1.0f / kPolD);
-  float4 a = dxacc[i];
-  a.x += rs * (dxh[0] - s1 - xh[0] * s2);
-  a.y += rs * (dxh[1] - s1 - xh[1] * s2);
-  a.z += rs * (dxh[2] - s1 - xh[2] * s2);
-  a.w += rs * (dxh[3] - s1 - xh[3] * s2);
-  dxacc[i] = a;
-  dyxhat[i] = make_float4(gy[0] * xh[0], gy[1] * xh[1], gy[2] * xh[2], gy[3] * xh[3]);
+  __syncthreads();
+  if (threadIdx.x < 3 * kPolD) {
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    part[(int64_t)blockIdx.x * 3 * kPolD + threadIdx.x] = t;
+  }
+}
+
+// Partials [nb][192] of layernorm_back_sums_kernel -> three 64-wide outputs
+// (out2 may be NULL), one wavefront per column as in colsum_final_kernel.
+__global__ void __launch_bounds__(256)
+sums3_final_kernel(const double *__restrict__ part, int nb, int acc, float *__restrict__ out0,
+                   float *__restrict__ out1, float *__restrict__ out2) {
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  float *out = col < kPolD ? out0 : (col < 2 * kPolD ? out1 : out2);
+  if (col >= 3 * kPolD || !out) return;  // wavefront-uniform
+  double s = 0.0;
+  for (int b = lane; b < nb; b += 64) s += part[(int64_t)b * 3 * kPolD + col];
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+  const int d = col % kPolD;
+  if (lane == 0) out[d] = acc ? out[d] + (float)s : (float)s;
 }
 
 // Attention of one agent per wavefront (a block of 64 threads): the agent's
@@ -465,7 +553,6 @@ wgrad_sum_kernel(const float *__restrict__ part, int nb, int64_t n, int acc,
 // first pass reads float4s instead (thread (group, column quad), one running
 // sum per column, four row loads in flight), which keeps enough bytes in
 // flight to stream Y at close to HBM rate.
-constexpr int kCsBlocks = 1024;
 
 __global__ void __launch_bounds__(256)
 colsum_partial4_kernel(const float4 *__restrict__ Y, int64_t R, int N, int64_t per,
@@ -714,15 +801,19 @@ int tr_gelu(const float *z, float *f, int64_t n, void *stream) {
   return check();
 }
 
-int tr_gelu_back(float *dz, const float *z, int64_t n, void *stream) {
-  if (n == 0) return 0;
-  if (n % 4 == 0 && aligned16(z) && aligned16(dz))
-    hipLaunchKernelGGL(gelu_back4_kernel, grid_for(n / 4), dim3(kTrThreads), 0,
-                       (hipStream_t)stream, reinterpret_cast<float4 *>(dz),
-                       reinterpret_cast<const float4 *>(z), n / 4);
-  else
-    hipLaunchKernelGGL(gelu_back_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream,
-                       dz, z, n);
+int tr_gelu_back_sums(float *dz, const float *z, int64_t R, double *scratch, int acc,
+                      float *bias_grad, void *stream) {
+  if (R == 0) return 0;
+  if (!aligned16(dz) || !aligned16(z)) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t per = (R + kCsBlocks - 1) / kCsBlocks;
+  const int64_t nb = (R + per - 1) / per;
+  hipLaunchKernelGGL(gelu_back_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st,
+                     reinterpret_cast<float4 *>(dz), reinterpret_cast<const float4 *>(z), R, per,
+                     scratch);
+  if (check()) return -1;
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(kPolF / 4), dim3(256), 0, st, scratch, (int)nb,
+                     kPolF, acc, bias_grad);
   return check();
 }
 
@@ -801,17 +892,20 @@ int tr_sum_partials(const float *part, int nb, int64_t n, int acc, float *out, v
   return check();
 }
 
-int tr_layernorm_back(const float *x, const float *g, const float *dy, float *dxacc, float *dyxhat,
-                      int64_t R, void *stream) {
+int tr_layernorm_back_sums(const float *x, const float *g, const float *dy, float *dxacc,
+                           int64_t R, double *scratch, int acc, float *gain_grad,
+                           float *bias_grad, float *next_grad, void *stream) {
   if (R == 0) return 0;
-  if (aligned16(x) && aligned16(dy) && aligned16(dxacc) && aligned16(dyxhat))
-    hipLaunchKernelGGL(layernorm_back4_kernel, grid_for(R * 16), dim3(kTrThreads), 0,
-                       (hipStream_t)stream, reinterpret_cast<const float4 *>(x), g,
-                       reinterpret_cast<const float4 *>(dy), reinterpret_cast<float4 *>(dxacc),
-                       reinterpret_cast<float4 *>(dyxhat), R);
-  else
-    hipLaunchKernelGGL(layernorm_back_kernel, grid_for(R * 64), dim3(kTrThreads), 0,
-                       (hipStream_t)stream, x, g, dy, dxacc, dyxhat, R);
+  if (!aligned16(x) || !aligned16(dy) || !aligned16(dxacc)) return -1;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t per = (R + kCsBlocks - 1) / kCsBlocks;
+  const int64_t nb = (R + per - 1) / per;
+  hipLaunchKernelGGL(layernorm_back_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st,
+                     reinterpret_cast<const float4 *>(x), g, reinterpret_cast<const float4 *>(dy),
+                     reinterpret_cast<float4 *>(dxacc), R, per, scratch);
+  if (check()) return -1;
+  hipLaunchKernelGGL(sums3_final_kernel, dim3(3 * kPolD / 4), dim3(256), 0, st, scratch, (int)nb,
+                     acc, gain_grad, bias_grad, next_grad);
   return check();
 }
 
