@@ -296,6 +296,28 @@ __device__ __forceinline__ void lds_row16(const float *src, float (&v)[kPolDh]) 
   }
 }
 
+// Copy n 16-byte words (1 <= n <= 64 * MAXV) from global memory to LDS,
+// every load of the lane issued before its first LDS write (lanes past the
+// end re-read word n - 1 and write nothing).
+typedef float at_f32x4 __attribute__((ext_vector_type(4)));
+template <int MAXV>
+__device__ __forceinline__ void stage_lds(void *dst, const void *__restrict__ src, int n,
+                                          int lane) {
+  const at_f32x4 *s = reinterpret_cast<const at_f32x4 *>(src);
+  at_f32x4 *d = reinterpret_cast<at_f32x4 *>(dst);
+  at_f32x4 v[MAXV];
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k) {
+    const int e = lane + k * kAtThreads;
+    v[k] = s[e < n ? e : n - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k) {
+    const int e = lane + k * kAtThreads;
+    if (e < n) d[e] = v[k];
+  }
+}
+
 __device__ __forceinline__ void store_row16(float *dst, const float (&v)[kPolDh]) {
 #pragma unroll
   for (int c4 = 0; c4 < kPolDh / 4; ++c4)
@@ -312,8 +334,8 @@ attention_kernel(const float *__restrict__ qkv, const uint8_t *__restrict__ mrow
   const int64_t a = blockIdx.x;
   const int64_t r0 = a * nt;
   const int lane = threadIdx.x;
-  const float4 *src = reinterpret_cast<const float4 *>(qkv + r0 * 3 * kPolD);
-  for (int e = lane; e < nt * 3 * kPolD / 4; e += kAtThreads) at_lds[e] = src[e];
+  constexpr int kQkv4 = kPolMaxTok * 3 * kPolD / 4 / kAtThreads;  // float4s per lane, at most
+  stage_lds<kQkv4>(at_lds, qkv + r0 * 3 * kPolD, nt * 3 * kPolD / 4, lane);
   __syncthreads();
   const int hd = lane >> 4, t = lane & 15;
   if (t >= nt) return;  // no barrier follows
@@ -377,12 +399,23 @@ attention_back_kernel(const float *__restrict__ qkv, const float *__restrict__ P
   const int lane = threadIdx.x;
   const int nqkv = nt * 3 * kPolD / 4, ndo = nt * kPolD / 4, np = kPolHeads * nt * nt / 4;
   {
-    const float4 *s1 = reinterpret_cast<const float4 *>(qkv + r0 * 3 * kPolD);
-    const float4 *s2 = reinterpret_cast<const float4 *>(dout + r0 * kPolD);
-    const float4 *s3 = reinterpret_cast<const float4 *>(P + a * kPolHeads * nt * nt);
-    for (int e = lane; e < nqkv; e += kAtThreads) ab_lds[e] = s1[e];
-    for (int e = lane; e < ndo; e += kAtThreads) ab_lds[nqkv + e] = s2[e];
-    for (int e = lane; e < np; e += kAtThreads) ab_lds[nqkv + ndo + e] = s3[e];
+    // all three copies as one: every load in flight before the first LDS write
+    constexpr int kAll4 = (kPolMaxTok * 3 * kPolD / 4 + kPolMaxTok * kPolD / 4 +
+                           kPolHeads * kPolMaxTok * kPolMaxTok / 4) / kAtThreads;
+    const at_f32x4 *s1 = reinterpret_cast<const at_f32x4 *>(qkv + r0 * 3 * kPolD);
+    const at_f32x4 *s2 = reinterpret_cast<const at_f32x4 *>(dout + r0 * kPolD);
+    const at_f32x4 *s3 = reinterpret_cast<const at_f32x4 *>(P + a * kPolHeads * nt * nt);
+    at_f32x4 *d = reinterpret_cast<at_f32x4 *>(ab_lds);
+    const int n = nqkv + ndo + np;
+    at_f32x4 v[kAll4];
+#pragma unroll
+    for (int k = 0; k < kAll4; ++k) {
+      const int e0 = lane + k * kAtThreads, e = e0 < n ? e0 : n - 1;
+      v[k] = e < nqkv ? s1[e] : (e < nqkv + ndo ? s2[e - nqkv] : s3[e - nqkv - ndo]);
+    }
+#pragma unroll
+    for (int k = 0; k < kAll4; ++k)
+      if (lane + k * kAtThreads < n) d[lane + k * kAtThreads] = v[k];
   }
   __syncthreads();
   float *const base = reinterpret_cast<float *>(ab_lds);
