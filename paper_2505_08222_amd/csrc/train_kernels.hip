@@ -547,6 +547,61 @@ wgrad_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t 
         if (j * 16 + cl < K) pb[((w * NBW + i) * 16 + 4 * rl + v) * K + j * 16 + cl] = acc[i][j][v];
 }
 
+// The same sums with float4 loads, one 64 x 64 output tile per wavefront
+// (block = TN x TK wavefronts, wavefront w the tile (w / TK, w % TK)): lane l
+// reads columns 4(l%16)..4(l%16)+3 of the tile's 64 in row l/16 of a 4-row
+// slab, for dY and for X, and component i of each is the fragment of
+// virtual 16-column block i. So virtual block i of the tile holds columns
+// 4c + i (c = 0..15), and D_ij[m][c] is dW[tile n0 + 4m + i][tile k0 + 4c + j];
+// lane l, accumulator v holds m = 4(l/16) + v, so its four j values are
+// four consecutive k and leave as one float4.
+typedef float wg4_f32x4 __attribute__((ext_vector_type(4)));
+template <int TN, int TK>
+__global__ void __launch_bounds__(64 * TN * TK)
+wgrad4_kernel(const float *__restrict__ dY, const float *__restrict__ X, int64_t R, int64_t per,
+              float *__restrict__ part) {
+  constexpr int N = TN * 64, K = TK * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tn = w / TK, tk = w - tn * TK;
+  const int rl = lane >> 4, cl = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < R ? r0 + per : R;
+  wg4_f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = wg4_f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const wg4_f32x4 *ya = reinterpret_cast<const wg4_f32x4 *>(dY + tn * 64) + cl;
+  const wg4_f32x4 *xb = reinterpret_cast<const wg4_f32x4 *>(X + tk * 64) + cl;
+  const wg4_f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t r = r0; r < r1; r += 16) {
+    wg4_f32x4 a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t row = r + 4 * s + rl;
+      const bool in = row < r1;
+      a[s] = in ? ya[row * (N / 4)] : zero4;
+      b[s] = in ? xb[row * (K / 4)] : zero4;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s][i], b[s][j], acc[i][j], 0, 0, 0);
+  }
+  float *pb = part + (int64_t)blockIdx.x * N * K;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = tn * 64 + 4 * (4 * rl + v) + i;
+      *reinterpret_cast<wg4_f32x4 *>(pb + (int64_t)n * K + tk * 64 + 4 * cl) =
+          wg4_f32x4{acc[i][0][v], acc[i][1][v], acc[i][2][v], acc[i][3][v]};
+    }
+}
+
 // out [n] (+)= sum over b < nb of part[b][n]: block = 64 outputs, wavefront
 // w adds partials [w q, (w+1) q) in order (FP64), then the four sums are
 // added in order.
@@ -899,12 +954,19 @@ int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *pa
   const int64_t nb = (R + per - 1) / per;
   hipStream_t st = (hipStream_t)stream;
   const dim3 g((unsigned)nb), b(kWgThreads);
+  const bool vec = aligned16(dY) && aligned16(X);
   if (N == 64 && K == 64)
     hipLaunchKernelGGL((wgrad_kernel<1, 64>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 64 && K == 256 && vec)
+    hipLaunchKernelGGL((wgrad4_kernel<1, 4>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 64 && K == 256)
     hipLaunchKernelGGL((wgrad_kernel<1, 256>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 192 && K == 64 && vec)
+    hipLaunchKernelGGL((wgrad4_kernel<3, 1>), g, dim3(192), 0, st, dY, X, R, per, part);
   else if (N == 192 && K == 64)
     hipLaunchKernelGGL((wgrad_kernel<3, 64>), g, b, 0, st, dY, X, R, per, part);
+  else if (N == 256 && K == 64 && vec)
+    hipLaunchKernelGGL((wgrad4_kernel<4, 1>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 256 && K == 64)
     hipLaunchKernelGGL((wgrad_kernel<4, 64>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 64 && K == 8)
