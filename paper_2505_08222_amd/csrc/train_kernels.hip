@@ -143,7 +143,9 @@ constexpr int kCsBlocks = 1024;
 
 // dz *= GELU'(z) in place (rows of F = 256), and the column sums of the
 // result (the first feed-forward bias's gradient). Thread (row slot s,
-// quad q) = (tid / 64, tid % 64): four row slots, two rows in flight each.
+// quad q) = (tid / 64, tid % 64): four row slots, four rows in flight each;
+// kGbBlocks blocks.
+constexpr int kGbBlocks = 2048;
 __global__ void __launch_bounds__(256)
 gelu_back_sums_kernel(float4 *__restrict__ dz, const float4 *__restrict__ z, int64_t R,
                       int64_t per, double *__restrict__ part) {
@@ -152,43 +154,28 @@ gelu_back_sums_kernel(float4 *__restrict__ dz, const float4 *__restrict__ z, int
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = r0 + per < R ? r0 + per : R;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
-  int64_t r = r0 + s;
-  for (; r + 4 < r1; r += 8) {
-    const int64_t i0 = r * (kPolF / 4) + q, i1 = (r + 4) * (kPolF / 4) + q;
-    const float4 v0 = z[i0], v1 = z[i1];
-    float4 d0 = dz[i0], d1 = dz[i1];
-    d0.x *= gelu_tanh_grad(v0.x);
-    d0.y *= gelu_tanh_grad(v0.y);
-    d0.z *= gelu_tanh_grad(v0.z);
-    d0.w *= gelu_tanh_grad(v0.w);
-    d1.x *= gelu_tanh_grad(v1.x);
-    d1.y *= gelu_tanh_grad(v1.y);
-    d1.z *= gelu_tanh_grad(v1.z);
-    d1.w *= gelu_tanh_grad(v1.w);
-    dz[i0] = d0;
-    dz[i1] = d1;
-    a[0] += (double)d0.x;
-    a[1] += (double)d0.y;
-    a[2] += (double)d0.z;
-    a[3] += (double)d0.w;
-    a[0] += (double)d1.x;
-    a[1] += (double)d1.y;
-    a[2] += (double)d1.z;
-    a[3] += (double)d1.w;
-  }
-  if (r < r1) {
-    const int64_t i0 = r * (kPolF / 4) + q;
-    const float4 v0 = z[i0];
-    float4 d0 = dz[i0];
-    d0.x *= gelu_tanh_grad(v0.x);
-    d0.y *= gelu_tanh_grad(v0.y);
-    d0.z *= gelu_tanh_grad(v0.z);
-    d0.w *= gelu_tanh_grad(v0.w);
-    dz[i0] = d0;
-    a[0] += (double)d0.x;
-    a[1] += (double)d0.y;
-    a[2] += (double)d0.z;
-    a[3] += (double)d0.w;
+  for (int64_t r = r0 + s; r < r1; r += 16) {  // rows r, r + 4, r + 8, r + 12 in flight
+    float4 v[4], d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t ru = r + 4 * u < r1 ? r + 4 * u : r;  // past the end: reread row r
+      v[u] = z[ru * (kPolF / 4) + q];
+      d[u] = dz[ru * (kPolF / 4) + q];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (r + 4 * u < r1) {
+        d[u].x *= gelu_tanh_grad(v[u].x);
+        d[u].y *= gelu_tanh_grad(v[u].y);
+        d[u].z *= gelu_tanh_grad(v[u].z);
+        d[u].w *= gelu_tanh_grad(v[u].w);
+        dz[(r + 4 * u) * (kPolF / 4) + q] = d[u];
+        a[0] += (double)d[u].x;
+        a[1] += (double)d[u].y;
+        a[2] += (double)d[u].z;
+        a[3] += (double)d[u].w;
+      }
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) red[s][4 * q + k] = a[k];
@@ -894,7 +881,7 @@ int tr_gelu_back_sums(float *dz, const float *z, int64_t R, double *scratch, int
   if (R == 0) return 0;
   if (!aligned16(dz) || !aligned16(z)) return -1;
   hipStream_t st = (hipStream_t)stream;
-  const int64_t per = (R + kCsBlocks - 1) / kCsBlocks;
+  const int64_t per = (R + kGbBlocks - 1) / kGbBlocks;
   const int64_t nb = (R + per - 1) / per;
   hipLaunchKernelGGL(gelu_back_sums_kernel, dim3((unsigned)nb), dim3(256), 0, st,
                      reinterpret_cast<float4 *>(dz), reinterpret_cast<const float4 *>(z), R, per,
@@ -927,7 +914,9 @@ int tr_attention_back(const float *qkv, const float *P, const uint8_t *mrow, con
   return check();
 }
 
-int64_t tr_colsum_scratch_doubles() { return (int64_t)kCsBlocks * 256; }
+int64_t tr_colsum_scratch_doubles() {
+  return (int64_t)(kCsBlocks > kGbBlocks ? kCsBlocks : kGbBlocks) * 256;
+}
 
 int tr_colsum(const float *Y, int64_t R, int N, double *scratch, int acc, float *out,
               void *stream) {
@@ -961,9 +950,7 @@ int tr_wgrad(const float *dY, const float *X, int64_t R, int N, int K, float *pa
     hipLaunchKernelGGL((wgrad4_kernel<1, 4>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 64 && K == 256)
     hipLaunchKernelGGL((wgrad_kernel<1, 256>), g, b, 0, st, dY, X, R, per, part);
-  else if (N == 192 && K == 64 && vec)
-    hipLaunchKernelGGL((wgrad4_kernel<3, 1>), g, dim3(192), 0, st, dY, X, R, per, part);
-  else if (N == 192 && K == 64)
+  else if (N == 192 && K == 64)  // three-wavefront float4 blocks measured slower here
     hipLaunchKernelGGL((wgrad_kernel<3, 64>), g, b, 0, st, dY, X, R, per, part);
   else if (N == 256 && K == 64 && vec)
     hipLaunchKernelGGL((wgrad4_kernel<4, 1>), g, b, 0, st, dY, X, R, per, part);
