@@ -1,10 +1,11 @@
 // Training form of the attention networks (the learner's update: MAPPO's
 // gradient step, Sec. III-B, through the TransfMAPPO actor and critic of
 // Fig. 3): the per-row and per-(agent, head) parts of an FP32 forward pass
-// that keeps every intermediate on a tape, and of its exact reverse pass.
-// The dense products between them (each layer's projections, their input
-// gradients and the weight gradients summed over all rows) are plain FP32
-// GEMMs issued by the host side (train_abi.cpp).
+// that keeps every intermediate on a tape, and of its exact reverse pass,
+// plus the weight gradients summed over all rows (FP32 matrix cores) and
+// the bias / LayerNorm column sums. The other dense products (each layer's
+// projections and their input gradients) are plain FP32 GEMMs issued by the
+// host side (train_abi.cpp).
 //
 // Rows: an agent's n_tok rows are consecutive ([A][n_tok][64] residual
 // stream); in the recurrent form its first row is the carried state and its
@@ -721,27 +722,6 @@ sum_partials_kernel(const float *__restrict__ part, int nb, int64_t n, int acc,
   double s = 0.0;
   for (int b = 0; b < nb; ++b) s += (double)part[(int64_t)b * n + i];
   out[i] = acc ? out[i] + (float)s : (float)s;
-}
-
-// One wavefront per row: LayerNorm's reverse pass. dx is added to dxacc;
-// dyxhat = dy * xhat (its column sums are the gain's gradient).
-__global__ void __launch_bounds__(kTrThreads)
-layernorm_back_kernel(const float *__restrict__ x, const float *__restrict__ g,
-                      const float *__restrict__ dy, float *__restrict__ dxacc,
-                      float *__restrict__ dyxhat, int64_t R) {
-  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int d = threadIdx.x & 63;
-  if (r >= R) return;
-  const int64_t i = r * kPolD + d;
-  const float v = x[i];
-  const float m = wave_sum(v) * (1.0f / kPolD);
-  const float c = v - m;
-  const float rs = rsqrtf(wave_sum(c * c) * (1.0f / kPolD) + 1e-5f);
-  const float xh = c * rs, gy = dy[i];
-  const float dxh = gy * g[d];
-  const float s1 = wave_sum(dxh) * (1.0f / kPolD), s2 = wave_sum(dxh * xh) * (1.0f / kPolD);
-  dxacc[i] += rs * (dxh - s1 - xh * s2);
-  dyxhat[i] = gy * xh;
 }
 
 // One wavefront per agent: final LayerNorm of its first row and the head.
