@@ -100,6 +100,40 @@ def test_recurrent_gradient_matches_oracle(orc):
     _check_grad(g0.cpu().numpy(), gz)
 
 
+# the token-count limits: 16 rows per agent (recurrent, 15 observed tokens:
+# every lane of the attention kernels busy, the largest LDS stage) and a
+# single-token agent (one key, probability 1)
+@pytest.mark.parametrize("na,nt,rec,E", [(7, 8, 1, 11), (1, 0, 0, 301)])
+def test_gradient_at_token_count_limits(orc, na, nt, rec, E):
+    from paper_2505_08222_amd import ppo
+    A = E * na
+    n_obs = na + nt
+    x, mask = policy_tokens(A, na, nt, seed=41 + nt)
+    th = policy_params(orc.policy_num_params(), seed=12)
+    rng = np.random.default_rng(17)
+    hid = rng.normal(size=(A, D)).astype(np.float32)
+    dl = rng.normal(size=(A, 8)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    tp = ppo.TrainPass(A, n_obs + rec, rec=rec)
+    if rec:
+        logits, _ = tp.forward(dev(x.reshape(-1, 6)), dev(mask.reshape(-1)), dev(th), dev(hid))
+        want, _ = orc.policy_forward_rec(x.astype(np.float64), mask, hid.astype(np.float64),
+                                         th.astype(np.float64))
+        grad, dh = tp.backward(dev(th), dev(dl), 8)
+        gw, dhw = orc.policy_backward_rec(x.astype(np.float64), mask, hid.astype(np.float64),
+                                          th.astype(np.float64), dl.astype(np.float64))
+        assert np.abs(dh.cpu().numpy() - dhw).max() <= 2e-4 * np.abs(dhw).max()
+    else:
+        logits, _ = tp.forward(dev(x.reshape(-1, 6)), dev(mask.reshape(-1)), dev(th))
+        want = orc.policy_forward(x.astype(np.float64), mask, th.astype(np.float64))
+        grad, _ = tp.backward(dev(th), dev(dl), 8)
+        gw = orc.policy_backward(x.astype(np.float64), mask, th.astype(np.float64),
+                                 dl.astype(np.float64))
+    assert np.abs(logits.cpu().numpy() - want).max() <= 1e-4 * max(1.0, np.abs(want).max())
+    worst = _check_grad(grad.cpu().numpy(), gw)
+    print(f"train limits {n_obs + rec} rows: grad err {worst:.1e}")
+
+
 @pytest.mark.parametrize("rec", [0, 1])
 def test_critic_gradient_matches_oracle(orc, rec):
     from oracle import ppo_oracle as po
