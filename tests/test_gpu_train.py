@@ -46,7 +46,7 @@ def _check_grad(got, want, tol=2e-4):
 
 
 # the last case has 1001 agents x 9 tokens = 9009 rows: the weight gradients
-# take the split-K path (row chunks summed in order, with a remainder chunk)
+# are summed over several row blocks in order, the last one ragged
 @pytest.mark.parametrize("n_agents,n_targets,n_envs", [(5, 5, 41), (2, 3, 29), (1, 1, 17),
                                                        (7, 8, 9), (7, 2, 143)])
 def test_policy_gradient_matches_oracle(orc, n_agents, n_targets, n_envs):
@@ -337,11 +337,11 @@ def test_recurrent_learner_on_closed_loop_experience():
     env.close()
 
 
-def test_accumulate_on_the_split_k_path(orc):
+def test_accumulate_on_the_row_block_path(orc):
     # 1001 agents x 9 rows (the recurrent form: 8 tokens + the state): the
-    # weight gradients take the split-K path with a remainder chunk; adding a
-    # second reverse pass of the same step gives twice the first, and the
-    # first matches the oracle
+    # weight gradients are summed over several row blocks, the last one
+    # ragged; adding a second reverse pass of the same step gives twice the
+    # first, and the first matches the oracle
     from paper_2505_08222_amd import ppo
     A = 1001
     x, m = policy_tokens(A, 1, 7, seed=19)
@@ -413,7 +413,7 @@ def test_large_batch_gradient_is_reproducible_and_splits(orc):
     # 16384 agents x 10 tokens (the policy workload's minibatch scale): two
     # reverse passes give identical bits, and the gradient equals the sum of
     # the two halves' gradients (other row counts, so other GEMM shapes and
-    # split-K chunkings) to FP32 rounding
+    # row-block partitions) to FP32 rounding
     from paper_2505_08222_amd import ppo
     A, H = 16384, 8192
     x, m = policy_tokens(A, 5, 5, seed=23)
