@@ -315,8 +315,8 @@ int train_forward(int64_t A, int nt, int rec, const float *obs, const uint8_t *m
     c.linear(fp(w.o[l]), lp + mil::kPolWo, lp + mil::kPolBo, fp(w.h[l]), fp(w.hmid[l]), R, D, D);
     c.k(mil::tr_layernorm(fp(w.hmid[l]), lp + mil::kPolLn2G, lp + mil::kPolLn2B, fp(w.a2[l]), R,
                           stream));
-    c.linear(fp(w.a2[l]), lp + mil::kPolW1, lp + mil::kPolB1, nullptr, fp(w.z[l]), R, F, D);
-    c.k(mil::tr_gelu(fp(w.z[l]), fp(w.f[l]), R * F, stream));
+    c.k(mil::tr_ffn_up(fp(w.a2[l]), lp + mil::kPolW1, lp + mil::kPolB1, fp(w.z[l]), fp(w.f[l]), R,
+                       stream));
     c.linear(fp(w.f[l]), lp + mil::kPolW2, lp + mil::kPolB2, fp(w.hmid[l]), fp(w.h[l + 1]), R, D,
              F);
   }

@@ -16,6 +16,10 @@ int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64
 // out [R][N] = base (NULL: 0) + bias broadcast over rows
 int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *out, void *stream);
 int tr_gelu(const float *z, float *f, int64_t n, void *stream);
+// z [R][256] = x [R][64] W1^T + b1 (W1 [256][64]) and f = GELU(z), on the FP32
+// matrix cores (x 16-byte aligned)
+int tr_ffn_up(const float *x, const float *w1, const float *b1, float *z, float *f, int64_t R,
+              void *stream);
 // dz [R][256] *= GELU'(z) in place; bias_grad [256] (+)= its column sums
 // (scratch: tr_colsum_scratch_doubles() doubles; 16-byte aligned arrays)
 int tr_gelu_back_sums(float *dz, const float *z, int64_t R, double *scratch, int acc,

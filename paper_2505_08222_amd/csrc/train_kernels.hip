@@ -109,6 +109,75 @@ gelu4_kernel(const float4 *__restrict__ z, float4 *__restrict__ f, int64_t n4) {
   f[i] = make_float4(gelu_tanh(v.x), gelu_tanh(v.y), gelu_tanh(v.z), gelu_tanh(v.w));
 }
 
+// Feed-forward up-projection fused with its bias and GELU: z = X W1^T + b1
+// and f = GELU(z) for X [R][64], W1 [256][64], both written (the tape keeps
+// z for the derivative and f for W2's weight gradient). FP32 matrix cores,
+// v_mfma_f32_16x16x4f32 on the transposed product z^T = W1 X^T; persistent
+// blocks of eight wavefronts share W1 (rows padded to 68 floats) and b1 in
+// LDS, each wavefront takes 16-row tiles across all 256 outputs (16 n-blocks).
+// Lane l = (m, kk) = (l%16, l/16) holds row m's inputs 16kk..16kk+15 as four
+// float4s; virtual k-step (g, c) pairs A[i][kk] = W1[i][16kk + 4g + c] with
+// B[kk][m] = X[m][16kk + 4g + c], so the 16 steps sum over all 64 inputs.
+// Lane l receives D[4(l/16)+v][l%16] = z[row m][column 4kk + v of the
+// n-block]: four consecutive outputs of one row, stored as a float4.
+constexpr int kFfnThreads = 512, kFfnLd = kPolD + 4;
+typedef float ffn_f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kFfnThreads, 4)  // 4 waves per SIMD: two blocks per CU
+ffn_up_kernel(const float *__restrict__ X, const float *__restrict__ W1,
+              const float *__restrict__ b1, float *__restrict__ z, float *__restrict__ f,
+              int64_t R) {
+  extern __shared__ float ffn_w[];  // [256][kFfnLd], then b1 [256]
+  float *ffn_b = ffn_w + kPolF * kFfnLd;
+  for (int e = threadIdx.x; e < kPolF * kPolD; e += kFfnThreads)
+    ffn_w[(e / kPolD) * kFfnLd + (e % kPolD)] = W1[e];
+  for (int e = threadIdx.x; e < kPolF; e += kFfnThreads) ffn_b[e] = b1[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kk = lane >> 4;
+  const int64_t tiles = (R + 15) / 16;
+  const int64_t nw = (int64_t)gridDim.x * (kFfnThreads / 64);
+  const ffn_f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int64_t tile = (int64_t)blockIdx.x * (kFfnThreads / 64) + (threadIdx.x >> 6); tile < tiles;
+       tile += nw) {
+    const int64_t row = tile * 16 + m;
+    const bool in = row < R;
+    ffn_f32x4 xa[4];
+    const ffn_f32x4 *xr = reinterpret_cast<const ffn_f32x4 *>(X + row * kPolD + 16 * kk);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) xa[g] = in ? xr[g] : zero4;
+    // two n-blocks at a time (independent accumulator chains), each finished
+    // and stored before the next pair, so few accumulators are live
+#pragma unroll 1
+    for (int nb = 0; nb < kPolF / 16; nb += 2) {
+      ffn_f32x4 acc0 = zero4, acc1 = zero4;
+      const float *wr0 = ffn_w + (nb * 16 + m) * kFfnLd + 16 * kk;  // lane (i = m, kk)
+      const float *wr1 = wr0 + 16 * kFfnLd;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const ffn_f32x4 wa0 = *reinterpret_cast<const ffn_f32x4 *>(wr0 + 4 * g);
+        const ffn_f32x4 wa1 = *reinterpret_cast<const ffn_f32x4 *>(wr1 + 4 * g);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa0[cc], xa[g][cc], acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(wa1[cc], xa[g][cc], acc1, 0, 0, 0);
+        }
+      }
+      if (in) {
+        const int n0 = nb * 16 + 4 * kk;
+        const ffn_f32x4 z0 = acc0 + *reinterpret_cast<const ffn_f32x4 *>(ffn_b + n0);
+        const ffn_f32x4 z1 = acc1 + *reinterpret_cast<const ffn_f32x4 *>(ffn_b + n0 + 16);
+        *reinterpret_cast<ffn_f32x4 *>(z + row * kPolF + n0) = z0;
+        *reinterpret_cast<ffn_f32x4 *>(z + row * kPolF + n0 + 16) = z1;
+        *reinterpret_cast<ffn_f32x4 *>(f + row * kPolF + n0) =
+            ffn_f32x4{gelu_tanh(z0[0]), gelu_tanh(z0[1]), gelu_tanh(z0[2]), gelu_tanh(z0[3])};
+        *reinterpret_cast<ffn_f32x4 *>(f + row * kPolF + n0 + 16) =
+            ffn_f32x4{gelu_tanh(z1[0]), gelu_tanh(z1[1]), gelu_tanh(z1[2]), gelu_tanh(z1[3])};
+      }
+    }
+  }
+}
+
 // LayerNorm on float4s: 16 lanes per row (lane q: features 4q..4q+3), four
 // rows per wavefront; row sums over the 16 lanes by a fixed butterfly.
 __device__ __forceinline__ float row16_sum(float v) {
@@ -842,6 +911,31 @@ int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *
   if (R == 0) return 0;
   hipLaunchKernelGGL(bias_rows_kernel, grid_for(R * N), dim3(kTrThreads), 0, (hipStream_t)stream,
                      base, bias, R, N, out);
+  return check();
+}
+
+int tr_ffn_up(const float *x, const float *w1, const float *b1, float *z, float *f, int64_t R,
+              void *stream) {
+  if (R == 0) return 0;
+  if (!aligned16(x) || !aligned16(z) || !aligned16(f)) return -1;
+  static int blocks[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  const size_t lds = (size_t)kPolF * (kFfnLd + 1) * sizeof(float);  // 69 KB: above the 64 KB default
+  if (!blocks[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0 ||
+        hipFuncSetAttribute((const void *)ffn_up_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      return -1;
+    blocks[dev] = 2 * cus;  // two blocks of W1 per CU
+  }
+  const int64_t tiles = (R + 15) / 16, waves = tiles < INT32_MAX ? tiles : INT32_MAX;
+  const int64_t need = (waves + kFfnThreads / 64 - 1) / (kFfnThreads / 64);
+  const unsigned nb = (unsigned)(need < blocks[dev] ? need : blocks[dev]);
+  hipLaunchKernelGGL(ffn_up_kernel, dim3(nb), dim3(kFfnThreads), lds, (hipStream_t)stream, x, w1,
+                     b1, z, f, R);
   return check();
 }
 
