@@ -544,8 +544,8 @@ int critic_forward_rec(const float *d_gstate, int32_t T, int64_t N, int32_t n_ag
  * that records every intermediate in the workspace (the tape), then its
  * exact reverse pass into the gradient of every parameter. The per-row work
  * (embedding, LayerNorms, attention with its softmax and key mask, tanh
- * GELU, head) and the weight gradients (FP32 matrix cores) run in the
- * library's kernels, the other dense products in hipBLASLt and rocBLAS FP32
+ * GELU, head), the weight gradients and the feed-forward up-projection
+ * (FP32 matrix cores) run in the library's kernels, the other dense products in hipBLASLt and rocBLAS FP32
  * GEMMs; every sum is taken in a fixed order, so results do not depend on
  * the run. Rows as for policy_forward (n_tok per agent) or, with rec = 1,
  * the recurrent form of policy_forward_rec (n_tok - 1 observed tokens per

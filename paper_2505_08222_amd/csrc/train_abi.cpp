@@ -3,9 +3,10 @@
 // tape in the caller's workspace, the reverse pass into the parameter
 // gradient, and the critic's variant on global states. Per-row work runs in
 // train_kernels.hip, and so do the layers' weight gradients (FP32 matrix
-// cores, fixed-order partial sums) and the column sums; the other dense
-// products are plain FP32 GEMMs: the forward ones in hipBLASLt with its bias
-// epilogue, the input gradients into 64-wide rows in hipBLASLt, the rest in
+// cores, fixed-order partial sums), the feed-forward up-projection with its
+// bias and GELU (FP32 matrix cores) and the column sums; the other dense
+// products are plain FP32 GEMMs: the other forward ones in hipBLASLt with its
+// bias epilogue, the input gradients into 64-wide rows in hipBLASLt, the rest in
 // rocBLAS (atomics off). hipBLASLt runs without workspace, with the
 // heuristic's first algorithm per shape, so results do not depend on the run.
 #include <hip/hip_runtime.h>
