@@ -15,7 +15,6 @@ int tr_embed(const float *obs, const uint8_t *mask, int64_t R, int nt, int rec,
 int tr_layernorm(const float *x, const float *g, const float *b, float *y, int64_t R, void *stream);
 // out [R][N] = base (NULL: 0) + bias broadcast over rows
 int tr_bias_rows(const float *base, const float *bias, int64_t R, int N, float *out, void *stream);
-int tr_gelu(const float *z, float *f, int64_t n, void *stream);
 // z [R][256] = x [R][64] W1^T + b1 (W1 [256][64]) and f = GELU(z), on the FP32
 // matrix cores (x 16-byte aligned)
 int tr_ffn_up(const float *x, const float *w1, const float *b1, float *z, float *f, int64_t R,

@@ -94,21 +94,6 @@ bias_rows_kernel(const float *__restrict__ base, const float *__restrict__ bias,
   out[i] = (base ? base[i] : 0.0f) + bias[n];
 }
 
-__global__ void __launch_bounds__(kTrThreads)
-gelu_kernel(const float *__restrict__ z, float *__restrict__ f, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) f[i] = gelu_tanh(z[i]);
-}
-
-// GELU on float4s (n a multiple of 4, 16-byte aligned arrays).
-__global__ void __launch_bounds__(kTrThreads)
-gelu4_kernel(const float4 *__restrict__ z, float4 *__restrict__ f, int64_t n4) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n4) return;
-  const float4 v = z[i];
-  f[i] = make_float4(gelu_tanh(v.x), gelu_tanh(v.y), gelu_tanh(v.z), gelu_tanh(v.w));
-}
-
 // Feed-forward up-projection fused with its bias and GELU: z = X W1^T + b1
 // and f = GELU(z) for X [R][64], W1 [256][64], both written (the tape keeps
 // z for the derivative and f for W2's weight gradient). FP32 matrix cores,
@@ -936,17 +921,6 @@ int tr_ffn_up(const float *x, const float *w1, const float *b1, float *z, float 
   const unsigned nb = (unsigned)(need < blocks[dev] ? need : blocks[dev]);
   hipLaunchKernelGGL(ffn_up_kernel, dim3(nb), dim3(kFfnThreads), lds, (hipStream_t)stream, x, w1,
                      b1, z, f, R);
-  return check();
-}
-
-int tr_gelu(const float *z, float *f, int64_t n, void *stream) {
-  if (n == 0) return 0;
-  if (n % 4 == 0 && aligned16(z) && aligned16(f))
-    hipLaunchKernelGGL(gelu4_kernel, grid_for(n / 4), dim3(kTrThreads), 0, (hipStream_t)stream,
-                       reinterpret_cast<const float4 *>(z), reinterpret_cast<float4 *>(f), n / 4);
-  else
-    hipLaunchKernelGGL(gelu_kernel, grid_for(n), dim3(kTrThreads), 0, (hipStream_t)stream, z, f,
-                       n);
   return check();
 }
 
