@@ -48,7 +48,8 @@ KERNEL_SOURCES = {
     "pf_kernel": ["pf_kernels.hip", "env_internal.h", "rng.h"],
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_counters.md")
-VALU_FILE = os.path.join(ROOT, "profiles", "pf_kernel_valu_counters.md")
+VALU_FILES = [os.path.join(ROOT, "profiles", n) for n in
+              ("pf_kernel_valu_counters.md", "rollout_kernel_paper_valu_counters.md")]
 # VALU issue capacity of the chip: 256 CUs x 4 SIMDs, each SIMD's vector unit
 # busy for one cycle per cycle at 2.4 GHz (a full-rate wave64 instruction
 # occupies it 4 cycles, a quarter-rate one 16)
@@ -87,15 +88,16 @@ def measured_valu(kernel, workload):
     the chip) and VALU instructions per launch from the committed counter
     summary, or None when there is none or the kernel changed since."""
     import re
-    if not os.path.exists(VALU_FILE):
-        return None
     ver = kernel_version(kernel)
     pat = re.compile(r"^valu\s+(\S+)\s+(\S+)\s+(\S+)\s+(\d+)\s+(\d+)\s*$")
-    with open(VALU_FILE) as f:
-        for line in f:
-            m = pat.match(line.strip())
-            if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == ver:
-                return int(m.group(4)), int(m.group(5))
+    for path in VALU_FILES:
+        if not os.path.exists(path):
+            continue
+        with open(path) as f:
+            for line in f:
+                m = pat.match(line.strip())
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(3) == ver:
+                    return int(m.group(4)), int(m.group(5))
     return None
 
 
@@ -1040,6 +1042,16 @@ def bench_env(args, workload, steps, warmup, sweep=False, cpu_seconds=None):
             "crash_steps": float(m[4]), "lost_targets": float(m[5]),
         },
     }
+    valu = measured_valu("rollout_kernel", workload) if not pf and E == c["num_envs"] else None
+    if valu is not None:
+        # the VALU view from the committed counters (paper environment: too few
+        # wavefronts to fill the chip, so neither HBM nor VALU issue bounds it)
+        busy, insts = valu
+        ach = busy / (kern_ms / 1e3)
+        result["roofline"]["alu_view"] = {
+            "bound": "alu", "achieved": ach, "peak": VALU_PEAK_CYCLES,
+            "unit": "VALU-busy SIMD cycles/s", "frac": ach / VALU_PEAK_CYCLES,
+            "valu_busy_cycles_per_launch": busy, "valu_insts_per_launch": insts}
     if result["roofline"]["traffic"] is not None:
         result["roofline"]["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)"
         # the measured DRAM bytes over the live launch time, beside the algorithmic rate
